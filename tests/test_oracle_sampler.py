@@ -1,0 +1,67 @@
+"""Pins of the oracle's basis sampler (Sec. Subspace of the ground state;
+variant-1 acceptance with a single random hop, Sec. Other sampling methods)."""
+import numpy as np
+import pytest
+from scipy import stats
+
+import workloads as W
+from oracle import fock, sampler
+
+
+def test_c_and_python_chains_agree_bit_for_bit():
+    c = W.config_c1()
+    m = c["model"]
+    a, sa = sampler.chain_c(m, W.neel_start(m), c["seed"], c["n_f"], c["burn_in"], c["max_steps"])
+    b, sb = sampler.chain_python(m, W.neel_start(m), c["seed"], c["n_f"], c["burn_in"],
+                                 c["max_steps"])
+    assert sa == sb and np.array_equal(a, b) and len(a) == c["n_f"]
+    fock.check_sector(a, m)
+
+
+def test_impurity_chain_agrees():
+    m = W.impurity_plaquette_bath(7)
+    st = W.neel_start(m)
+    a, sa = sampler.chain_c(m, st, 9, 3000, 500, 10**6)
+    b, sb = sampler.chain_python(m, st, 9, 3000, 500, 10**6)
+    assert sa == sb and np.array_equal(a, b)
+    fock.check_sector(a, m)
+
+
+def test_neel_start_states():
+    m = W.config_c1()["model"]
+    k = W.neel_start(m)
+    up, dn = k >> 32, k & 0xFFFFFFFF
+    assert bin(up).count("1") == 4 and bin(dn).count("1") == 4 and up & dn == 0
+    m2 = W.config_c2()["model"]
+    k2 = W.neel_start(m2)
+    assert bin(k2 >> 32).count("1") == 7 and bin(k2 & 0xFFFFFFFF).count("1") == 7
+
+
+@pytest.mark.parametrize("model", [W.chain(4, U=8.0, mu=4.0, pbc=True),
+                                   W.square(3, 2, U=4.0, tp=-0.3, pbc=False, n_up=2, n_dn=2)])
+def test_stationary_distribution(model):
+    """Symmetric proposal + Metropolis ratio: visit frequencies -> exp(-b E)/Z."""
+    beta = 0.5
+    k = fock.sector_keys(model.n_orb, model.n_up, model.n_dn)
+    E = fock.diagonal(k, model)
+    p = np.exp(-beta * (E - E.min()))
+    p /= p.sum()
+    steps = 4_000_000
+    counts = sampler.chain_histogram(model, W.neel_start(model), 123, 10_000, steps, k, beta)
+    # thin by the autocorrelation: compare with a generous effective sample size
+    n_eff = steps / 50
+    f = counts / steps
+    chi2 = n_eff * np.sum((f - p) ** 2 / p)
+    dof = len(k) - 1
+    assert chi2 < stats.chi2.ppf(0.999, dof), (chi2, dof)
+    # a chain that ignored the acceptance would be uniform: that must fail
+    u = np.full(len(k), 1.0 / len(k))
+    assert n_eff * np.sum((f - u) ** 2 / u) > stats.chi2.ppf(0.999, dof)
+
+
+def test_chain_stops_at_n_f_and_respects_cap():
+    m = W.config_c1()["model"]
+    a, s = sampler.chain_c(m, W.neel_start(m), 4, 100, 10, 10**6)
+    assert len(a) == 100
+    b, s2 = sampler.chain_c(m, W.neel_start(m), 4, 4900, 10, 2000)
+    assert s2 == 2000 and len(b) < 4900
