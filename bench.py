@@ -1,0 +1,166 @@
+"""Benchmark of the MCD hot path on one MI355X.
+
+Workload: 4x4 periodic Hubbard cluster (t = 1, t' = -0.3, U = 8, N_up = N_dn = 7),
+truncated basis of 4,000,000 distinct Fock states drawn by the seeded
+Metropolis chain (weight exp(-0.5 E_diag), seed 2, burn-in 1e6), float64.
+One step = one Lanczos ground-state solve of 200 iterations (200 products
+H~ v plus the recurrence, then the ground state rebuilt from the stored
+Krylov vectors).  Basis sampling, index and CSR build are set-up, reported
+separately and not timed.
+
+The metric is the effective HBM bandwidth of H~ v: compulsory bytes of the
+packed-CSR representation per product (8(n+1) row pointers + 4 nnz packed
+column/sign/class words + 8n diagonal + 8n x + 8n y) times the products per
+step, over the step time.  `roofline` reports the product kernel alone,
+timed with HIP events on the stream it runs on.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0
+ITERS = 200
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(HERE, "paper_2509_22975_amd", "csrc", "mcd_op.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profile(alg_bytes):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source; else None."""
+    p = os.path.join(HERE, "profiles", "spmv_stream_c2_pmc.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(model, keys_np, x_np, nnz_per_row):
+    """Oracle H~ x (element definition) on a bounded row sample, one thread."""
+    import numpy as np
+    from oracle import hamiltonian as ham
+    n = len(keys_np)
+    rows = np.arange(0, min(n, 400_000), dtype=np.int64)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        ham.apply_rows(keys_np, rows, model, x_np)
+        reps += 1
+        if time.perf_counter() - t0 > 10.0 or reps >= 3:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    bytes_rows = len(rows) * (32.0 + 4.0 * nnz_per_row)
+    return {"value": round(bytes_rows / dt / 1e9, 4), "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"oracle.hamiltonian.apply_rows on rows 0..{len(rows)} of the same basis "
+                      f"(x float64), {reps} reps, {dt:.2f} s each; bytes counted as for the GPU"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--storage", default="csr")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU layout is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2509_22975_amd as mcd
+    import workloads as W
+
+    mcd.lib()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    c = W.config_c2()
+    m = c["model"]
+    t0 = time.perf_counter()
+    keys, steps = mcd.basis_build(m, "chain", start_key=W.neel_start(m), seed=c["seed"],
+                                  beta_s=c["beta_s"], burn_in=c["burn_in"],
+                                  max_steps=c["max_steps"], n_f=c["n_f"])
+    torch.cuda.synchronize()
+    basis_s = time.perf_counter() - t0
+    op = mcd.Operator(m, keys, storage=args.storage)
+    info = op.info()
+    n, nnz = info["n"], info["nnz"]
+    alg_bytes = 8.0 * (n + 1) + 4.0 * nnz + 24.0 * n
+
+    def step():
+        return mcd.lanczos_ground(op, max_iter=ITERS, tol=0.0, seed=11, check_every=50,
+                                  store_vectors=True, min_iter=ITERS)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = None
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    e0, _, _, _, si = res
+    value = alg_bytes * si.n_apply / dt / 1e9
+
+    # Product kernel alone: HIP events on the stream the kernel is launched on.
+    x = torch.from_numpy(W.random_vector(n, 21)).to(dev)
+    y = torch.empty_like(x)
+    s = torch.cuda.current_stream()
+    for _ in range(5):
+        op.apply(x, out=y)
+    e_a, e_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 200
+    e_a.record(s)
+    for _ in range(reps):
+        op.apply(x, out=y)
+    e_b.record(s)
+    e_b.synchronize()
+    k_ms = e_a.elapsed_time(e_b) / reps
+    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": "H~v effective HBM bandwidth (GB/s), float64 Lanczos step on the 4M-state basis",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "4x4 periodic Hubbard t=1 t'=-0.3 U=8 (7,7), 4M Metropolis-chain "
+                               "states, FP64 Lanczos 200 iterations + ground state",
+                   "n_states": n, "nnz_offdiag": nnz, "storage": info["storage"],
+                   "rows_per_block": info["rows_per_block"], "lanczos_iters": si.n_apply,
+                   "e0": e0, "hbm_frac_step": round(value / HBM_PEAK_GBS, 4),
+                   "basis_build_s": round(basis_s, 3), "chain_steps": steps,
+                   "op_build_ms": round(info["build_ms"], 2),
+                   "bytes_per_apply": alg_bytes},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profile(alg_bytes),
+                     "kernel": "k_spmv_stream<double,256>", "kernel_ms": round(k_ms, 5)},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(m, mcd.keys_to_numpy(keys), x.cpu().numpy(),
+                                           nnz / n)
+    op.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

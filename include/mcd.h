@@ -1,0 +1,268 @@
+/* mcd.h -- C ABI of the MI355X (gfx950) Monte Carlo diagonalization library.
+ *
+ * Monte Carlo diagonalization (MCD) solves the Hubbard model in a truncated
+ * Fock basis F~ of "important" states (Sec. Subspace of the ground state):
+ * the Hamiltonian is restricted to F~ (Eq. h_matrix_projected), the ground
+ * state is found with Lanczos (App. Lanczos), and the Green function with
+ * band Lanczos on the excited subspaces F~+- (Eq. excited_subspace,
+ * App. Band Lanczos, Eqs. green_qmatrix / q_matrix).  Every step applies H~
+ * to vectors; states that H sends outside the basis are discarded (App.
+ * Lanczos, last paragraph).  This library runs that product and the solvers
+ * around it on one GPU.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Model.  H = sum_b sum_s t_b (c+_{i_b s} c_{j_b s} + h.c.)
+ *           + sum_i U_i n_{i up} n_{i dn} + sum_{i s} eps_i n_{i s}
+ *   (Eq. hubbard_model with -t on nearest-neighbour bonds and eps_i = -mu on
+ *   lattice sites; per-orbital U_i and eps_i cover impurity + bath models).
+ *   Bonds listed twice add up.  n_orb <= 32, n_bonds <= MCD_MAX_BONDS.
+ * Fock state.  A uint64 key (up << 32) | down, orbital i <-> bit i of each
+ *   spin string.  A basis is an array of keys sorted ascending and unique;
+ *   the row/column index of a state is its position in that array.
+ * Fermion signs.  Orbital order "all up orbitals, then all down": a hop
+ *   c+_{i s} c_{j s} carries (-1)^(number of s-electrons strictly between i
+ *   and j); c+_{i s} or c_{i s} carries (-1)^(electrons in orbitals ordered
+ *   before (i, s)).
+ * Memory.  Pointers named *_dev are device pointers on the current HIP
+ *   device; all others are host pointers.  Device inputs and outputs belong
+ *   to the caller; an operator handle owns the device memory it allocates
+ *   (its copy of the keys, index, CSR, scratch) until mcd_op_destroy.
+ * Streams.  `stream` is a hipStream_t (NULL = default stream).  Work is
+ *   enqueued on it; calls that return host values synchronise it first and
+ *   say so.  Calls on one operator from several host threads or streams at
+ *   once race on its scratch buffers.
+ * Errors.  Every call returns MCD_OK (0), a positive warning (the result is
+ *   still written) or a negative error code; mcd_last_error() gives a
+ *   message for the calling thread.  Nothing aborts or throws across the ABI.
+ */
+#ifndef MCD_H
+#define MCD_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCD_MAX_ORB 32
+#define MCD_MAX_BONDS 512
+
+enum {
+    MCD_OK = 0,
+    MCD_NOCONV = 1,          /* warning: iteration cap reached before tol */
+    MCD_E_INVALID = -1,      /* bad argument (null pointer, size, range) */
+    MCD_E_SECTOR = -2,       /* key outside the sector, unsorted or duplicate */
+    MCD_E_HIP = -3,          /* a HIP runtime call failed */
+    MCD_E_CAPACITY = -4,     /* output buffer or format limit too small */
+};
+
+enum { MCD_STORAGE_AUTO = 0, MCD_STORAGE_ON_THE_FLY = 1, MCD_STORAGE_CSR = 2 };
+enum { MCD_F64 = 0, MCD_F32 = 1 };
+enum { MCD_BASIS_FULL = 0, MCD_BASIS_CHAIN = 1 };
+
+typedef struct mcd_model {
+    int32_t n_orb;            /* orbitals (sites), 1..32 */
+    int32_t n_bonds;          /* 0..MCD_MAX_BONDS */
+    const int32_t *bond_i;    /* [n_bonds] host */
+    const int32_t *bond_j;    /* [n_bonds] host, bond_i != bond_j */
+    const double *bond_t;     /* [n_bonds] host, amplitude t_ij */
+    const double *U;          /* [n_orb] host, on-site repulsion */
+    const double *eps;        /* [n_orb] host, orbital energy (includes -mu) */
+} mcd_model;
+
+typedef struct mcd_op mcd_op;
+
+const char *mcd_last_error(void);
+int mcd_version(void);
+
+/* ---------------------------------------------------------------------------
+ * mcd_basis_build -- the truncated basis F~ (Sec. Subspace of the ground
+ * state; Sec. Other sampling methods).
+ *
+ * mode MCD_BASIS_FULL: every state of the (n_up, n_dn) sector, sorted
+ *   (the f = 1 case, Sec. Exact diagonalization); n_out = C(n,n_up)C(n,n_dn).
+ * mode MCD_BASIS_CHAIN: the distinct states visited by a Metropolis chain
+ *   that proposes one random hop per step (variant 2) and accepts it with the
+ *   ratio of Boltzmann factors of the diagonal energy (variant 1, Eq.
+ *   boltzmann_factor2) at inverse temperature beta_s.  Draws come from
+ *   splitmix64(seed), two per step: r0 picks m = (hi32(r0) * 4 n_bonds) >> 32
+ *   (bond m >> 2, spin (m >> 1) & 1 with 0 = up, direction m & 1 with 0 =
+ *   i -> j); an impossible hop is a rejected step; dE = (eps[dst]-eps[src])
+ *   + (U[dst] o[dst] - U[src] o[src]) (o = other-spin occupation) and the
+ *   hop is taken iff dE <= 0 or (r1 >> 11) 2^-53 < exp(-beta_s dE).  After
+ *   burn_in steps the state after every step is recorded; the basis is the
+ *   first n_f distinct recorded states (or all of them if max_steps ends the
+ *   chain first), sorted.  steps_out = steps the chain ran.
+ *   The chain itself is sequential and runs on the host; recording,
+ *   de-duplication, first-visit selection and sorting run on the GPU.
+ * keys_dev: [cap] device output.  Returns MCD_E_CAPACITY if cap is too
+ * small, MCD_E_SECTOR if start_key is not in the sector.  Synchronises.
+ * ------------------------------------------------------------------------- */
+typedef struct mcd_basis_cfg {
+    int32_t mode;             /* MCD_BASIS_FULL or MCD_BASIS_CHAIN */
+    int32_t n_up, n_dn;
+    uint64_t start_key;       /* chain start state (in the sector) */
+    uint64_t seed;
+    double beta_s;            /* weight exp(-beta_s * E_diag) */
+    int64_t burn_in;
+    int64_t max_steps;        /* total steps, burn-in included */
+    int64_t n_f;              /* target number of distinct states */
+} mcd_basis_cfg;
+
+int mcd_basis_build(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t *keys_dev,
+                    int64_t cap, int64_t *n_out, int64_t *steps_out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * mcd_op_create -- the operator H~ = P H P on a basis (Eq.
+ * h_matrix_projected; App. Lanczos, discarding out-of-basis states).
+ *
+ * keys_dev: [n] sorted unique keys of one or several (N_up, N_dn) sectors
+ *   (a union of sectors is block diagonal).  Copied; the caller may free it.
+ * storage: MCD_STORAGE_ON_THE_FLY recomputes every element at each apply
+ *   (hop enumeration, popcount signs, hash lookup of the image state);
+ *   MCD_STORAGE_CSR stores the matrix once as a packed CSR (one 32-bit word
+ *   per nonzero: column, sign, amplitude class); MCD_STORAGE_AUTO picks CSR
+ *   when it fits the format (n < 2^26, <= 32 distinct |t|) and the memory
+ *   budget (free HBM / 2), else on-the-fly.
+ * validate != 0 checks on the GPU that the keys are sorted, unique and within
+ *   n_orb bits (MCD_E_SECTOR otherwise).  Synchronises.
+ * ------------------------------------------------------------------------- */
+int mcd_op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32_t storage,
+                  int32_t validate, void *stream, mcd_op **out);
+void mcd_op_destroy(mcd_op *op);
+
+typedef struct mcd_op_info_t {
+    int64_t n;                /* basis size */
+    int64_t nnz;              /* off-diagonal nonzeros (CSR), else -1 */
+    int32_t storage;          /* resolved storage */
+    int32_t n_classes;        /* distinct |t| amplitudes */
+    int32_t rows_per_block;   /* CSR stream kernel row block */
+    int32_t reserved;
+    int64_t device_bytes;     /* device memory held by the operator */
+    double build_ms;          /* time of index + CSR build */
+} mcd_op_info_t;
+
+int mcd_op_info(const mcd_op *op, mcd_op_info_t *info);
+
+/* ---------------------------------------------------------------------------
+ * mcd_hamiltonian_apply -- y = H~ x (the product every Lanczos step repeats,
+ * Eq. next_vector; App. Lanczos).
+ *
+ * x_dev, y_dev: [n][nvec] row-major (vector k of row r at r*nvec + k), of
+ *   type double (dtype MCD_F64) or float (MCD_F32, float accumulation).
+ *   nvec in {1, 2, 4, 8, 16}.  x and y must not overlap.
+ * Row r of y = d_r x_r + sum over kept hops, with d_r the diagonal energy.
+ * Asynchronous on `stream`.
+ * ------------------------------------------------------------------------- */
+int mcd_hamiltonian_apply(const mcd_op *op, int32_t dtype, int32_t nvec, const void *x_dev,
+                          void *y_dev, void *stream);
+
+/* Diagonal <x_r|H|x_r> into diag_dev [n] (double).  Asynchronous. */
+int mcd_hamiltonian_diagonal(const mcd_op *op, double *diag_dev, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * mcd_hamiltonian_connectivity -- the off-diagonal elements of rows
+ * [row0, row1) as (row, col, value) triples, in the order the operator
+ * enumerates them (bond order, up before down), for checking connectivity and
+ * signs exactly.  rows_dev, cols_dev: int64 [cap]; vals_dev: double [cap].
+ * count_out (host) = number of triples; MCD_E_CAPACITY if cap is too small.
+ * Synchronises.
+ * ------------------------------------------------------------------------- */
+int mcd_hamiltonian_connectivity(const mcd_op *op, int64_t row0, int64_t row1, int64_t *rows_dev,
+                                 int64_t *cols_dev, double *vals_dev, int64_t cap,
+                                 int64_t *count_out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * mcd_lanczos_ground -- lowest eigenpair of H~ by Lanczos (App. Lanczos,
+ * Eqs. next_vector / an_bn; ground state rebuilt by Eq. change_basis).
+ *
+ * Orthonormal recurrence v_{k+1} b_{k+1} = H v_k - a_k v_k - b_k v_{k-1} in
+ * float64 with deterministic grid reductions; the tridiagonal H_eff is solved
+ * on the host (Sturm bisection + inverse iteration) every check_every steps.
+ * Stops when the Ritz residual b_{k+1} |s_k| <= tol max(1, |E0|), on
+ * breakdown, or at max_iter (MCD_NOCONV, result still written).
+ * phi0_dev: [n] start vector or NULL; NULL draws phi0[r] = 2u - 1 with u the
+ *   top 53 bits of the first splitmix64 output of the state (seed XOR key_r).
+ * psi0_dev: [n] output ground state (unit norm), or NULL.  With
+ *   store_vectors != 0 the Krylov vectors are kept in HBM (n * iters * 8 B)
+ *   and psi0 is one weighted sum; otherwise the recurrence is run a second
+ *   time (Eq. change_basis without storage).
+ * alpha_out / beta_out: optional host arrays [max_iter] receiving a_k, b_{k+1}.
+ * Synchronises.
+ * ------------------------------------------------------------------------- */
+typedef struct mcd_lanczos_cfg {
+    int32_t max_iter;
+    int32_t check_every;      /* convergence test period (>= 1) */
+    double tol;
+    uint64_t seed;
+    int32_t store_vectors;
+    int32_t min_iter;         /* run at least this many steps */
+} mcd_lanczos_cfg;
+
+typedef struct mcd_solve_info {
+    int32_t iters;            /* Lanczos steps (or block steps) taken */
+    int32_t converged;
+    double e0;
+    double residual;
+    double solve_ms;          /* wall time of the call */
+    double apply_ms;          /* time spent in H~ applies (events) */
+    int32_t n_apply;
+    int32_t krylov_dim;       /* band: number of Krylov vectors */
+    int64_t n_plus, n_minus;  /* band: sizes of F~+ and F~- */
+    int64_t n_truncated;      /* band: states kept by the w_t cut */
+} mcd_solve_info;
+
+int mcd_lanczos_ground(const mcd_op *op, const mcd_lanczos_cfg *cfg, const double *phi0_dev,
+                       double *e0, double *psi0_dev, double *alpha_out, double *beta_out,
+                       mcd_solve_info *info, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * mcd_band_lanczos_green -- Green function of the truncated ground state on
+ * Matsubara frequencies (Sec. Subspace of the Green function, Sec. Further
+ * truncation, App. Band Lanczos).
+ *
+ * Steps: keep the most important states of psi0 up to weight w_t (order
+ * |c|^2 descending, ties by key ascending; shortest prefix with cumulative
+ * weight >= w_t; renormalise); build F~+ = union c+_mu F~ and F~- = union
+ * c_mu F~ over the selected (orb[k], spin[k]) (Eq. excited_subspace); start
+ * blocks c+_mu|psi0> and c_mu|psi0>; block Lanczos with block width
+ * p = n_sel (the block Krylov space K_r^L of App. Band Lanczos), full
+ * reorthogonalisation against every stored block and rank-revealing
+ * deflation of directions with norm <= dtol max_k ||start_k||; then
+ * G+_{mu nu}(i w) = [R^T (z - T)^-1 R]_{mu nu} at z = i w + E0 and
+ * G-_{mu nu}(i w) = -[R^T (z - T)^-1 R] at z = E0 - i w (the resolvent form
+ * of Eqs. green_qmatrix; R = start block in the Lanczos basis), evaluated by
+ * a block continued fraction in complex128 on the host.
+ *
+ * keys_dev [n], psi0_dev [n]: ground-state basis and vector (double).
+ * orb, spin: [n_sel] host; spin 0 = up, 1 = down; n_sel <= 32.
+ * omega: [n_freq] host Matsubara frequencies w_n.
+ * G_out, Gp_out, Gm_out: host complex128 interleaved [n_freq][n_sel][n_sel]
+ *   (G = G+ + G-); Gp_out / Gm_out may be NULL.
+ * precision MCD_F64: float64 Krylov blocks.  MCD_F32: float32 blocks and
+ *   SpMM with float accumulation; Gram matrices, recurrence, deflation and
+ *   the continued fraction stay float64.
+ * max_blocks: block steps per run (Krylov dim <= max_blocks * p).
+ * Synchronises.
+ * ------------------------------------------------------------------------- */
+typedef struct mcd_band_cfg {
+    int32_t max_blocks;
+    int32_t precision;        /* MCD_F64 or MCD_F32 */
+    double w_t;               /* target weight in (0, 1] */
+    double dtol;              /* relative deflation tolerance (1e-10) */
+    int32_t storage;          /* operator storage for F~+- */
+    int32_t reorth;           /* 1 = full reorthogonalisation, 0 = none */
+} mcd_band_cfg;
+
+int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                           const double *psi0_dev, double e0, int32_t n_sel, const int32_t *orb,
+                           const int32_t *spin, int32_t n_freq, const double *omega,
+                           const mcd_band_cfg *cfg, double *G_out, double *Gp_out,
+                           double *Gm_out, mcd_solve_info *info, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCD_H */

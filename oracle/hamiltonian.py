@@ -60,6 +60,49 @@ def hop_terms(keys: np.ndarray, model):
     return z, z, np.zeros(0)
 
 
+def hop_terms_rows(keys: np.ndarray, rows: np.ndarray, model):
+    """Off-diagonal elements (row m, col n, value) of H~ for the given rows m.
+
+    Same definition as ``hop_terms`` (H~ is symmetric, so the elements of
+    row m are the hops applied to x_m), restricted to a subset of rows so
+    that single rows of a large basis can be checked.
+    """
+    keys = np.asarray(keys, dtype=np.uint64)
+    rows = np.asarray(rows, dtype=np.int64)
+    sub = keys[rows]
+    up, dn = fock.split(sub)
+    out_r, out_c, out_v = [], [], []
+    for (a, b, t) in model.bonds:
+        i, j = (a, b) if a < b else (b, a)
+        mask = np.uint64((1 << i) | (1 << j))
+        between = np.uint64(((1 << j) - 1) & ~((1 << (i + 1)) - 1))
+        for shift, s in ((np.uint64(32), up), (np.uint64(0), dn)):
+            movable = np.bitwise_count(s & mask) == 1
+            tgt = sub[movable] ^ (mask << shift)
+            sign = 1.0 - 2.0 * (np.bitwise_count(s[movable] & between) & 1)
+            pos = np.minimum(np.searchsorted(keys, tgt), len(keys) - 1)
+            found = keys[pos] == tgt
+            out_r.append(rows[movable][found])
+            out_c.append(pos[found])
+            out_v.append(t * sign[found])
+    if not out_r:
+        z = np.zeros(0, dtype=np.int64)
+        return z, z, np.zeros(0)
+    return np.concatenate(out_r), np.concatenate(out_c), np.concatenate(out_v)
+
+
+def apply_rows(keys: np.ndarray, rows: np.ndarray, model, x: np.ndarray) -> np.ndarray:
+    """(H~ x)[rows] from the element definition (x of shape (n,) or (n, k))."""
+    r, c, v = hop_terms_rows(keys, rows, model)
+    d = fock.diagonal(np.asarray(keys, dtype=np.uint64)[rows], model)
+    y = d[:, None] * (x[rows] if x.ndim == 2 else x[rows][:, None])
+    loc = np.searchsorted(rows, r) if np.all(np.diff(rows) > 0) else None
+    assert loc is not None, "rows must be sorted and unique"
+    xc = x[c] if x.ndim == 2 else x[c][:, None]
+    np.add.at(y, loc, v[:, None] * xc)
+    return y if x.ndim == 2 else y[:, 0]
+
+
 def build_csr(keys: np.ndarray, model) -> sp.csr_matrix:
     """H~ on the basis `keys` (sorted unique) as a float64 CSR matrix."""
     n = len(keys)

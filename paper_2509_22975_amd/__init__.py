@@ -1,0 +1,328 @@
+"""MI355X-native Monte Carlo diagonalization hot path (Python binding).
+
+Thin ctypes marshalling over ``libmcd.so`` (C ABI in ``include/mcd.h``).
+Every step of the path runs in the library's HIP kernels; PyTorch only
+provides device memory (tensors) and the current HIP stream.  The library
+must be built (``python -m paper_2509_22975_amd.build``); importing this
+package without it raises, there is no fallback.
+
+Keys are passed as torch.int64 tensors holding the uint64 bit pattern
+(up << 32) | down.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmcd.so")
+
+MCD_OK, MCD_NOCONV = 0, 1
+STORAGE = {"auto": 0, "on_the_fly": 1, "otf": 1, "csr": 2}
+STORAGE_NAME = {0: "auto", 1: "on_the_fly", 2: "csr"}
+DTYPE = {"f64": 0, "f32": 1}
+
+P = ctypes.POINTER
+c_i32, c_i64, c_u64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
+
+
+class McdModel(ctypes.Structure):
+    _fields_ = [("n_orb", c_i32), ("n_bonds", c_i32), ("bond_i", P(c_i32)), ("bond_j", P(c_i32)),
+                ("bond_t", P(c_dbl)), ("U", P(c_dbl)), ("eps", P(c_dbl))]
+
+
+class McdBasisCfg(ctypes.Structure):
+    _fields_ = [("mode", c_i32), ("n_up", c_i32), ("n_dn", c_i32), ("start_key", c_u64),
+                ("seed", c_u64), ("beta_s", c_dbl), ("burn_in", c_i64), ("max_steps", c_i64),
+                ("n_f", c_i64)]
+
+
+class McdOpInfo(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("nnz", c_i64), ("storage", c_i32), ("n_classes", c_i32),
+                ("rows_per_block", c_i32), ("reserved", c_i32), ("device_bytes", c_i64),
+                ("build_ms", c_dbl)]
+
+
+class McdLanczosCfg(ctypes.Structure):
+    _fields_ = [("max_iter", c_i32), ("check_every", c_i32), ("tol", c_dbl), ("seed", c_u64),
+                ("store_vectors", c_i32), ("min_iter", c_i32)]
+
+
+class McdSolveInfo(ctypes.Structure):
+    _fields_ = [("iters", c_i32), ("converged", c_i32), ("e0", c_dbl), ("residual", c_dbl),
+                ("solve_ms", c_dbl), ("apply_ms", c_dbl), ("n_apply", c_i32),
+                ("krylov_dim", c_i32), ("n_plus", c_i64), ("n_minus", c_i64),
+                ("n_truncated", c_i64)]
+
+
+class McdBandCfg(ctypes.Structure):
+    _fields_ = [("max_blocks", c_i32), ("precision", c_i32), ("w_t", c_dbl), ("dtol", c_dbl),
+                ("storage", c_i32), ("reorth", c_i32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libmcd.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2509_22975_amd.build` (no fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.mcd_last_error.restype = ctypes.c_char_p
+    L.mcd_version.restype = ctypes.c_int
+    L.mcd_basis_build.argtypes = [P(McdModel), P(McdBasisCfg), c_vp, c_i64, P(c_i64), P(c_i64), c_vp]
+    L.mcd_op_create.argtypes = [P(McdModel), c_vp, c_i64, c_i32, c_i32, c_vp, P(c_vp)]
+    L.mcd_op_destroy.argtypes = [c_vp]
+    L.mcd_op_destroy.restype = None
+    L.mcd_op_info.argtypes = [c_vp, P(McdOpInfo)]
+    L.mcd_hamiltonian_apply.argtypes = [c_vp, c_i32, c_i32, c_vp, c_vp, c_vp]
+    L.mcd_hamiltonian_diagonal.argtypes = [c_vp, c_vp, c_vp]
+    L.mcd_hamiltonian_connectivity.argtypes = [c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_i64,
+                                               P(c_i64), c_vp]
+    L.mcd_lanczos_ground.argtypes = [c_vp, P(McdLanczosCfg), c_vp, P(c_dbl), c_vp, P(c_dbl),
+                                     P(c_dbl), P(McdSolveInfo), c_vp]
+    if hasattr(L, "mcd_band_lanczos_green"):
+        L.mcd_band_lanczos_green.argtypes = [P(McdModel), c_vp, c_i64, c_vp, c_dbl, c_i32,
+                                             P(c_i32), P(c_i32), c_i32, P(c_dbl), P(McdBandCfg),
+                                             P(c_dbl), P(c_dbl), P(c_dbl), P(McdSolveInfo), c_vp]
+    for name in ("mcd_basis_build", "mcd_op_create", "mcd_op_info", "mcd_hamiltonian_apply",
+                 "mcd_hamiltonian_diagonal", "mcd_hamiltonian_connectivity", "mcd_lanczos_ground",
+                 "mcd_band_lanczos_green"):
+        if hasattr(L, name):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+class McdError(RuntimeError):
+    def __init__(self, code, where):
+        msg = lib().mcd_last_error().decode(errors="replace")
+        super().__init__(f"{where}: status {code}: {msg}")
+        self.code = code
+
+
+def _check(code, where, allow_noconv=True):
+    if code < 0 or (code > 0 and not allow_noconv):
+        raise McdError(code, where)
+    return code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class _ModelBuf:
+    """Keeps the host arrays of an mcd_model alive while the struct is used."""
+
+    def __init__(self, model):
+        bonds = list(model.bonds)
+        self.bi = np.ascontiguousarray([b[0] for b in bonds], dtype=np.int32)
+        self.bj = np.ascontiguousarray([b[1] for b in bonds], dtype=np.int32)
+        self.bt = np.ascontiguousarray([b[2] for b in bonds], dtype=np.float64)
+        self.U = np.ascontiguousarray(model.U, dtype=np.float64)
+        self.eps = np.ascontiguousarray(model.eps, dtype=np.float64)
+        self.s = McdModel(int(model.n_orb), len(bonds),
+                          self.bi.ctypes.data_as(P(c_i32)), self.bj.ctypes.data_as(P(c_i32)),
+                          self.bt.ctypes.data_as(P(c_dbl)), self.U.ctypes.data_as(P(c_dbl)),
+                          self.eps.ctypes.data_as(P(c_dbl)))
+
+
+def keys_to_numpy(keys) -> np.ndarray:
+    return keys.detach().cpu().numpy().view(np.uint64)
+
+
+def keys_from_numpy(keys: np.ndarray, device="cuda"):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(keys, dtype=np.uint64).view(np.int64)).to(device)
+
+
+def basis_build(model, mode="full", n_up=None, n_dn=None, start_key=0, seed=0, beta_s=0.5,
+                burn_in=0, max_steps=0, n_f=0, cap=None, device="cuda"):
+    """Basis keys (torch.int64 on device) and the number of chain steps."""
+    torch = _torch()
+    n_up = model.n_up if n_up is None else n_up
+    n_dn = model.n_dn if n_dn is None else n_dn
+    mb = _ModelBuf(model)
+    m = 0 if mode == "full" else 1
+    if cap is None:
+        import math
+        cap = math.comb(model.n_orb, n_up) * math.comb(model.n_orb, n_dn) if m == 0 else int(n_f)
+    cfg = McdBasisCfg(m, n_up, n_dn, int(start_key), int(seed), float(beta_s), int(burn_in),
+                      int(max_steps), int(n_f))
+    out = torch.empty(max(int(cap), 1), dtype=torch.int64, device=device)
+    n_out, steps = c_i64(0), c_i64(0)
+    _check(lib().mcd_basis_build(ctypes.byref(mb.s), ctypes.byref(cfg), c_vp(out.data_ptr()),
+                                 int(cap), ctypes.byref(n_out), ctypes.byref(steps), _stream()),
+           "mcd_basis_build")
+    return out[: n_out.value], steps.value
+
+
+class Operator:
+    """H~ on a basis (mcd_op_create / mcd_hamiltonian_apply)."""
+
+    def __init__(self, model, keys, storage="auto", validate=True):
+        torch = _torch()
+        assert keys.dtype == torch.int64 and keys.is_cuda
+        self.model = model
+        self._mb = _ModelBuf(model)
+        self.keys = keys.contiguous()
+        self.n = int(keys.numel())
+        self.device = keys.device
+        h = c_vp(0)
+        _check(lib().mcd_op_create(ctypes.byref(self._mb.s), c_vp(self.keys.data_ptr()), self.n,
+                                   STORAGE[storage], 1 if validate else 0, _stream(),
+                                   ctypes.byref(h)), "mcd_op_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("operator is closed")
+        return self._h
+
+    def info(self) -> dict:
+        i = McdOpInfo()
+        _check(lib().mcd_op_info(self.handle, ctypes.byref(i)), "mcd_op_info")
+        return dict(n=i.n, nnz=i.nnz, storage=STORAGE_NAME[i.storage], n_classes=i.n_classes,
+                    rows_per_block=i.rows_per_block, device_bytes=i.device_bytes,
+                    build_ms=i.build_ms)
+
+    def apply(self, x, out=None):
+        """y = H~ x; x is (n,) or (n, nvec) float64/float32 on the device."""
+        torch = _torch()
+        x = x.contiguous()
+        nvec = 1 if x.dim() == 1 else x.shape[1]
+        dt = {torch.float64: 0, torch.float32: 1}[x.dtype]
+        y = torch.empty_like(x) if out is None else out
+        _check(lib().mcd_hamiltonian_apply(self.handle, dt, nvec, c_vp(x.data_ptr()),
+                                           c_vp(y.data_ptr()), _stream()), "mcd_hamiltonian_apply")
+        return y
+
+    def apply_raw(self, dtype_code: int, nvec: int, x_ptr: int, y_ptr: int, stream=None):
+        return lib().mcd_hamiltonian_apply(self.handle, dtype_code, nvec, c_vp(x_ptr), c_vp(y_ptr),
+                                           _stream() if stream is None else stream)
+
+    def diagonal(self):
+        torch = _torch()
+        d = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(lib().mcd_hamiltonian_diagonal(self.handle, c_vp(d.data_ptr()), _stream()),
+               "mcd_hamiltonian_diagonal")
+        return d
+
+    def connectivity(self, row0=0, row1=None):
+        """(rows, cols, vals) numpy arrays of the off-diagonal elements."""
+        torch = _torch()
+        row1 = self.n if row1 is None else row1
+        cnt = c_i64(0)
+        code = lib().mcd_hamiltonian_connectivity(self.handle, row0, row1, None, None, None, 0,
+                                                  ctypes.byref(cnt), _stream())
+        if code not in (0, -4):
+            _check(code, "mcd_hamiltonian_connectivity")
+        m = max(cnt.value, 1)
+        r = torch.empty(m, dtype=torch.int64, device=self.device)
+        c = torch.empty(m, dtype=torch.int64, device=self.device)
+        v = torch.empty(m, dtype=torch.float64, device=self.device)
+        _check(lib().mcd_hamiltonian_connectivity(self.handle, row0, row1, c_vp(r.data_ptr()),
+                                                  c_vp(c.data_ptr()), c_vp(v.data_ptr()), m,
+                                                  ctypes.byref(cnt), _stream()),
+               "mcd_hamiltonian_connectivity")
+        k = cnt.value
+        return r[:k].cpu().numpy(), c[:k].cpu().numpy(), v[:k].cpu().numpy()
+
+    def close(self):
+        if self._h:
+            lib().mcd_op_destroy(self._h)
+            self._h = c_vp(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+@dataclass
+class SolveInfo:
+    iters: int
+    converged: bool
+    e0: float
+    residual: float
+    solve_ms: float
+    apply_ms: float
+    n_apply: int
+    krylov_dim: int
+    n_plus: int
+    n_minus: int
+    n_truncated: int
+
+    @staticmethod
+    def of(i: McdSolveInfo) -> "SolveInfo":
+        return SolveInfo(i.iters, bool(i.converged), i.e0, i.residual, i.solve_ms, i.apply_ms,
+                         i.n_apply, i.krylov_dim, i.n_plus, i.n_minus, i.n_truncated)
+
+
+def lanczos_ground(op: Operator, max_iter=300, tol=1e-12, seed=0, check_every=10,
+                   store_vectors=True, min_iter=1, phi0=None, want_psi=True):
+    """(E0, psi0 tensor or None, alpha, beta, SolveInfo) via mcd_lanczos_ground."""
+    torch = _torch()
+    cfg = McdLanczosCfg(int(max_iter), int(check_every), float(tol), int(seed),
+                        1 if store_vectors else 0, int(min_iter))
+    psi = torch.empty(op.n, dtype=torch.float64, device=op.device) if want_psi else None
+    e0 = c_dbl(0)
+    a = np.zeros(max_iter)
+    b = np.zeros(max_iter)
+    info = McdSolveInfo()
+    code = lib().mcd_lanczos_ground(op.handle, ctypes.byref(cfg),
+                                    c_vp(phi0.data_ptr()) if phi0 is not None else None,
+                                    ctypes.byref(e0), c_vp(psi.data_ptr()) if want_psi else None,
+                                    a.ctypes.data_as(P(c_dbl)), b.ctypes.data_as(P(c_dbl)),
+                                    ctypes.byref(info), _stream())
+    _check(code, "mcd_lanczos_ground")
+    si = SolveInfo.of(info)
+    return e0.value, psi, a[: si.iters], b[: si.iters], si
+
+
+def band_lanczos_green(model, keys, psi0, e0, orbitals, spins, omega, max_blocks=50,
+                       precision="f64", w_t=1.0, dtol=1e-10, storage="auto", reorth=True,
+                       parts=False):
+    """G(i w_n) [n_freq, n_sel, n_sel] complex128 via mcd_band_lanczos_green."""
+    mb = _ModelBuf(model)
+    orb = np.ascontiguousarray(orbitals, dtype=np.int32)
+    sp = np.ascontiguousarray(spins, dtype=np.int32)
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    ns, nf = len(orb), len(om)
+    G = np.zeros((nf, ns, ns), dtype=np.complex128)
+    Gp = np.zeros_like(G)
+    Gm = np.zeros_like(G)
+    cfg = McdBandCfg(int(max_blocks), DTYPE[precision], float(w_t), float(dtol), STORAGE[storage],
+                     1 if reorth else 0)
+    info = McdSolveInfo()
+    dp = lambda a: a.view(np.float64).ctypes.data_as(P(c_dbl))
+    code = lib().mcd_band_lanczos_green(ctypes.byref(mb.s), c_vp(keys.data_ptr()), int(keys.numel()),
+                                        c_vp(psi0.data_ptr()), float(e0), ns,
+                                        orb.ctypes.data_as(P(c_i32)), sp.ctypes.data_as(P(c_i32)),
+                                        nf, om.ctypes.data_as(P(c_dbl)), ctypes.byref(cfg), dp(G),
+                                        dp(Gp), dp(Gm), ctypes.byref(info), _stream())
+    _check(code, "mcd_band_lanczos_green")
+    if parts:
+        return G, Gp, Gm, SolveInfo.of(info)
+    return G, SolveInfo.of(info)

@@ -1,0 +1,774 @@
+// Green function of the truncated ground state by block (band) Lanczos on
+// the excited subspaces (Sec. Subspace of the Green function, Sec. Further
+// truncation, App. Band Lanczos, Eqs. green_qmatrix / q_matrix).
+//
+// Pipeline (all vector work on the GPU, p x p algebra on the host):
+//  1. target-weight cut of |Omega>: radix sort of |c_n|^2 (descending,
+//     stable so ties stay in key order), cumulative weight on the host,
+//     kept rows re-sorted by key and renormalised;
+//  2. F~+ / F~-: images c+_mu x / c_mu x of every kept state for the selected
+//     (orbital, spin) pairs, radix sort + unique (Eq. excited_subspace);
+//  3. start block c+_mu|Omega> (c_mu|Omega>) scattered into F~+- through the
+//     operator's hash, Jordan-Wigner sign of the ordering "up orbitals, then
+//     down orbitals";
+//  4. block Lanczos with block width P (the selected p padded to a power of
+//     two; zero columns deflate at once): W = H Q_j (block SpMM), A_j = Q_j^T W,
+//     W -= Q_j A_j + Q_{j-1} B_j^T, optional full reorthogonalisation against
+//     every stored block (two passes), W = Q_{j+1} B_{j+1} by a twice-applied
+//     Gram eigen-decomposition that drops directions of norm <= dtol (the
+//     band method's deflation) -- this spans the block Krylov space K_r^L;
+//  5. G(z) = R^T [(z - T)^-1]_{00} R by a block continued fraction over the
+//     block tridiagonal T (complex128, host), z = i w + E0 for G+ and
+//     G- = -R^T [(E0 - i w) - T]^-1 R; this is the resolvent that the Lehmann
+//     sums of Eqs. green_qmatrix write through the eigenpairs of T.
+#include <hipcub/hipcub.hpp>
+#include <math.h>
+
+#include <algorithm>
+#include <chrono>
+#include <complex>
+#include <vector>
+
+#include "mcd_hash.h"
+#include "mcd_internal.h"
+#include "mcd_reduce.h"
+
+namespace mcd {
+
+using cplx = std::complex<double>;
+static constexpr int BS = 256;
+
+static inline unsigned gridn(int64_t n, int bs) {
+    return (unsigned)std::max<int64_t>(1, (n + bs - 1) / bs);
+}
+
+__global__ void k_weights(int64_t n, const double *__restrict__ psi, double *__restrict__ w,
+                          uint32_t *__restrict__ idx) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    w[r] = psi[r] * psi[r];
+    idx[r] = (uint32_t)r;
+}
+
+__global__ void k_gather_kept(int64_t m, const uint32_t *__restrict__ rows,
+                              const uint64_t *__restrict__ keys, const double *__restrict__ psi,
+                              uint64_t *__restrict__ keys_t, double *__restrict__ psi_t) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint32_t r = rows[i];
+    keys_t[i] = keys[r];
+    psi_t[i] = psi[r];
+}
+
+__global__ __launch_bounds__(BS) void k_norm2(int64_t n, const double *__restrict__ v,
+                                              double *__restrict__ partials,
+                                              unsigned int *counter, double *__restrict__ out) {
+    double acc = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < n; r += (int64_t)gridDim.x * BS)
+        acc += v[r] * v[r];
+    grid_sum_last<BS>(block_sum<BS>(acc), gridDim.x, partials, counter, out);
+}
+
+__global__ void k_scale_by(int64_t n, double *__restrict__ v, const double *__restrict__ nrm2) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    v[r] *= scale_from(nrm2, 1);
+}
+
+struct SelOps {
+    int n;
+    int orb[32];
+    int spin[32];
+};
+
+// Jordan-Wigner sign of c+_{i s} / c_{i s} on (up, dn): electrons in the
+// orbitals ordered before (i, s) with all up orbitals first.
+__device__ __forceinline__ double jw_sign(uint32_t up, uint32_t dn, int i, int spin) {
+    const uint32_t below = (1u << i) - 1u;
+    const int par = spin == 0 ? __popc(up & below) : __popc(up) + __popc(dn & below);
+    return (par & 1) ? -1.0 : 1.0;
+}
+
+__device__ __forceinline__ bool image(uint64_t key, int i, int spin, bool create, uint64_t *out) {
+    const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
+    const uint32_t s = spin == 0 ? up : dn;
+    const bool occ = (s >> i) & 1u;
+    if (occ == create) return false;
+    *out = key ^ ((uint64_t)(1u << i) << (spin == 0 ? 32 : 0));
+    return true;
+}
+
+__global__ void k_images(int64_t m, const uint64_t *__restrict__ keys, SelOps sel, int create,
+                         uint64_t *__restrict__ out) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const uint64_t k = keys[r];
+    for (int q = 0; q < sel.n; q++) {
+        uint64_t t;
+        out[r * sel.n + q] = image(k, sel.orb[q], sel.spin[q], create != 0, &t) ? t : kEmpty;
+    }
+}
+
+template <typename T>
+__global__ void k_start_block(int64_t m, const uint64_t *__restrict__ keys,
+                              const double *__restrict__ psi, SelOps sel, int create,
+                              const HashSlot *__restrict__ h, uint64_t hmask, int P,
+                              T *__restrict__ phi) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const uint64_t k = keys[r];
+    const uint32_t up = (uint32_t)(k >> 32), dn = (uint32_t)k;
+    for (int q = 0; q < sel.n; q++) {
+        uint64_t t;
+        if (!image(k, sel.orb[q], sel.spin[q], create != 0, &t)) continue;
+        const int64_t row = hash_find(h, hmask, t);
+        if (row >= 0) phi[row * P + q] = (T)(jw_sign(up, dn, sel.orb[q], sel.spin[q]) * psi[r]);
+    }
+}
+
+// Partial Gram matrices: partial[(m * nch + chunk)][a][b] = sum over the
+// chunk's rows of Q_m[r][a] X[r][b] (float64 accumulation, fixed order).
+template <typename T, int P>
+__global__ __launch_bounds__(BS) void k_gram(int64_t n, int64_t chunk_rows, int nch,
+                                             const T *__restrict__ Q0, int64_t qstride,
+                                             const T *__restrict__ X, double *__restrict__ part) {
+    constexpr int PP = P * P;
+    constexpr int S = BS / PP;
+    constexpr int TR = 32;
+    __shared__ double sQ[TR][P];
+    __shared__ double sX[TR][P];
+    __shared__ double red[BS];
+    const int chunk = blockIdx.x, m = blockIdx.y;
+    const T *__restrict__ Q = Q0 + (int64_t)m * qstride;
+    const int t = threadIdx.x;
+    const int pair = t % PP, slice = t / PP;
+    const int a = pair / P, b = pair % P;
+    const int64_t r0 = (int64_t)chunk * chunk_rows;
+    const int64_t r1 = min(r0 + chunk_rows, n);
+    double acc = 0.0;
+    for (int64_t base = r0; base < r1; base += TR) {
+        const int rows = (int)min((int64_t)TR, r1 - base);
+        for (int e = t; e < TR * P; e += BS) {
+            const int rr = e / P, cc = e % P;
+            const bool ok = rr < rows;
+            sQ[rr][cc] = ok ? (double)Q[(base + rr) * P + cc] : 0.0;
+            sX[rr][cc] = ok ? (double)X[(base + rr) * P + cc] : 0.0;
+        }
+        __syncthreads();
+        for (int rr = slice; rr < TR; rr += S) acc += sQ[rr][a] * sX[rr][b];
+        __syncthreads();
+    }
+    red[t] = acc;
+    __syncthreads();
+    if (t < PP) {
+        double s = 0.0;
+        for (int q = 0; q < S; q++) s += red[t + q * PP];
+        part[((int64_t)m * nch + chunk) * PP + t] = s;
+    }
+}
+
+__global__ void k_gram_reduce(int nm, int nch, int PP, const double *__restrict__ part,
+                              double *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nm * PP) return;
+    const int m = i / PP, e = i % PP;
+    double s = 0.0;
+    for (int c = 0; c < nch; c++) s += part[((int64_t)m * nch + c) * PP + e];
+    out[i] = s;
+}
+
+// W -= sum_{m < nm} Q_m C_m  (sub != 0)   or   W = Q_0 C_0  (sub == 0, nm == 1).
+// C: nm float64 P x P matrices (row a, column b), kept in LDS.
+template <typename T, int P>
+__global__ __launch_bounds__(BS) void k_block_apply(int64_t n, int nm, const T *__restrict__ Q0,
+                                                    int64_t qstride, const double *__restrict__ C,
+                                                    T *__restrict__ W, int sub) {
+    constexpr int RPB = BS / P;
+    extern __shared__ double sC[];
+    for (int e = threadIdx.x; e < nm * P * P; e += BS) sC[e] = C[e];
+    __syncthreads();
+    const int b = threadIdx.x % P;
+    for (int64_t tile = blockIdx.x; tile * RPB < n; tile += gridDim.x) {
+        const int64_t r = tile * RPB + threadIdx.x / P;
+        if (r >= n) continue;
+        double acc = 0.0;
+        for (int m = 0; m < nm; m++) {
+            const T *__restrict__ q = Q0 + (int64_t)m * qstride + r * P;
+            const double *__restrict__ c = sC + m * P * P;
+#pragma unroll
+            for (int a = 0; a < P; a++) acc += (double)q[a] * c[a * P + b];
+        }
+        if (sub)
+            W[r * P + b] = (T)((double)W[r * P + b] - acc);
+        else
+            W[r * P + b] = (T)acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host small linear algebra (float64 / complex128, P <= 16).
+// Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (row-major):
+// A = V diag(w) V^T, columns of V are eigenvectors.
+static void jacobi_eig(int n, std::vector<double> A, std::vector<double> &w,
+                       std::vector<double> &V) {
+    V.assign(n * n, 0.0);
+    for (int i = 0; i < n; i++) V[i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; sweep++) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < n; i++)
+            for (int j = 0; j < n; j++)
+                (i == j ? diag : off) += A[i * n + j] * A[i * n + j];
+        if (off <= 1e-30 * std::max(diag, 1e-300)) break;
+        for (int p = 0; p < n; p++)
+            for (int q = p + 1; q < n; q++) {
+                const double apq = A[p * n + q];
+                if (fabs(apq) < 1e-300) continue;
+                // rotation angle that zeroes A[p][q]
+                const double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+                const double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(tt * tt + 1.0), s = tt * c;
+                for (int k = 0; k < n; k++) {   // columns p, q
+                    const double akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = c * akp - s * akq;
+                    A[k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; k++) {   // rows p, q
+                    const double apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = c * apk - s * aqk;
+                    A[q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; k++) {
+                    const double vkp = V[k * n + p], vkq = V[k * n + q];
+                    V[k * n + p] = c * vkp - s * vkq;
+                    V[k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; i++) w[i] = A[i * n + i];
+}
+
+// Solve S X = B (S n x n, B n x k, complex, row-major) by Gaussian
+// elimination with partial pivoting; S and B are overwritten, X returned in B.
+static void csolve(int n, int k, std::vector<cplx> &S, std::vector<cplx> &B) {
+    for (int c = 0; c < n; c++) {
+        int piv = c;
+        for (int r = c + 1; r < n; r++)
+            if (std::abs(S[r * n + c]) > std::abs(S[piv * n + c])) piv = r;
+        if (piv != c) {
+            for (int j = 0; j < n; j++) std::swap(S[c * n + j], S[piv * n + j]);
+            for (int j = 0; j < k; j++) std::swap(B[c * k + j], B[piv * k + j]);
+        }
+        const cplx d = S[c * n + c];
+        for (int r = c + 1; r < n; r++) {
+            const cplx f = S[r * n + c] / d;
+            if (f == cplx(0.0)) continue;
+            for (int j = c; j < n; j++) S[r * n + j] -= f * S[c * n + j];
+            for (int j = 0; j < k; j++) B[r * k + j] -= f * B[c * k + j];
+        }
+    }
+    for (int c = n - 1; c >= 0; c--) {
+        for (int j = 0; j < k; j++) {
+            cplx s = B[c * k + j];
+            for (int q = c + 1; q < n; q++) s -= S[c * n + q] * B[q * k + j];
+            B[c * k + j] = s / S[c * n + c];
+        }
+    }
+}
+
+struct BandResult {
+    std::vector<std::vector<double>> A;   // A_j, P x P
+    std::vector<std::vector<double>> B;   // B_j (j >= 1), P x P; B[0] unused
+    std::vector<double> R0;               // P x P: start block = Q_0 R0
+    int P = 0;
+    int m = 0;                            // number of blocks in T
+    int krylov = 0;                       // nonzero Lanczos directions
+};
+
+// G_sub(z) = R0^T [(z - T)^-1]_00 R0 for one z; out p x p (first p columns).
+static void block_cf(const BandResult &br, cplx z, int p, cplx *out) {
+    const int P = br.P;
+    std::vector<cplx> S(P * P), X;
+    auto zA = [&](int j) {
+        for (int a = 0; a < P; a++)
+            for (int b = 0; b < P; b++)
+                S[a * P + b] = (a == b ? z : cplx(0.0)) - br.A[j][a * P + b];
+    };
+    zA(br.m - 1);
+    for (int j = br.m - 2; j >= 0; j--) {
+        // X = S^-1 B_{j+1};  S_j = z - A_j - B_{j+1}^T X
+        X.assign(P * P, cplx(0.0));
+        for (int e = 0; e < P * P; e++) X[e] = br.B[j + 1][e];
+        std::vector<cplx> Sc = S;
+        csolve(P, P, Sc, X);
+        zA(j);
+        for (int a = 0; a < P; a++)
+            for (int b = 0; b < P; b++) {
+                cplx s = 0.0;
+                for (int q = 0; q < P; q++) s += br.B[j + 1][q * P + a] * X[q * P + b];
+                S[a * P + b] -= s;
+            }
+    }
+    std::vector<cplx> Y(P * P);
+    for (int e = 0; e < P * P; e++) Y[e] = br.R0[e];
+    csolve(P, P, S, Y);
+    for (int a = 0; a < p; a++)
+        for (int b = 0; b < p; b++) {
+            cplx s = 0.0;
+            for (int q = 0; q < P; q++) s += br.R0[q * P + a] * Y[q * P + b];
+            out[a * p + b] = s;
+        }
+}
+
+template <typename T>
+struct BandRun {
+    const mcd_op *op;
+    int P;
+    int64_t n;
+    hipStream_t s;
+    T *Qs = nullptr;          // [nstore][n][P]
+    T *W = nullptr;           // [n][P]
+    double *part = nullptr;   // Gram partials
+    double *dC = nullptr;     // device coefficient matrices
+    double *dG = nullptr;     // reduced Gram matrices
+    int nstore = 0;
+    int64_t part_cap = 0;
+    int64_t coef_cap = 0;
+
+    T *blk(int j) { return Qs + (int64_t)(nstore == 3 ? j % 3 : j) * n * P; }
+
+    int gram(const T *Q0, int nm, const T *X, std::vector<double> &out) {
+        const int PP = P * P;
+        int nch = (int)std::min<int64_t>(gridn(n, 256), std::max<int64_t>(1, 65536 / nm));
+        nch = std::max(1, nch);
+        const int64_t chunk_rows = (n + nch - 1) / nch;
+        nch = (int)((n + chunk_rows - 1) / chunk_rows);
+        MCD_REQUIRE((int64_t)nm * nch * PP <= part_cap, MCD_E_CAPACITY, "gram scratch too small");
+        dim3 grid(nch, nm);
+#define GR(PV)                                                                           \
+    case PV:                                                                             \
+        hipLaunchKernelGGL((k_gram<T, PV>), grid, dim3(BS), 0, s, n, chunk_rows, nch, Q0, \
+                           (int64_t)n * P, X, part);                                     \
+        break;
+        switch (P) {
+            GR(1) GR(2) GR(4) GR(8) GR(16)
+        }
+#undef GR
+        MCD_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_gram_reduce, dim3(gridn((int64_t)nm * PP, 256)), dim3(256), 0, s, nm,
+                           nch, PP, part, dG);
+        MCD_HIP(hipGetLastError());
+        out.resize((size_t)nm * PP);
+        MCD_HIP(hipMemcpyAsync(out.data(), dG, (size_t)nm * PP * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        MCD_HIP(hipStreamSynchronize(s));
+        return MCD_OK;
+    }
+
+    // W (-)= sum_m Q_m C_m with C given on the host ([nm][P][P]).
+    int block_apply(const T *Q0, int nm, const std::vector<double> &C, T *Wout, bool sub) {
+        const int PP = P * P;
+        const int group = std::max(1, (48 * 1024) / (PP * 8));
+        for (int g0 = 0; g0 < nm; g0 += group) {
+            const int g = std::min(group, nm - g0);
+            MCD_HIP(hipMemcpyAsync(dC, C.data() + (size_t)g0 * PP, (size_t)g * PP * sizeof(double),
+                                   hipMemcpyHostToDevice, s));
+            const unsigned nb = (unsigned)std::min<int64_t>(gridn(n, BS / P), 4096);
+            const T *q = Q0 + (int64_t)g0 * n * P;
+#define BA(PV)                                                                               \
+    case PV:                                                                                 \
+        hipLaunchKernelGGL((k_block_apply<T, PV>), dim3(nb), dim3(BS), g * PP * sizeof(double), \
+                           s, n, g, q, (int64_t)n * P, dC, Wout, sub ? 1 : 0);               \
+        break;
+            switch (P) {
+                BA(1) BA(2) BA(4) BA(8) BA(16)
+            }
+#undef BA
+            MCD_HIP(hipGetLastError());
+            if (!sub && g0 + g < nm) {
+                set_error("assigning block product must use one block");
+                return MCD_E_INVALID;
+            }
+        }
+        return MCD_OK;
+    }
+
+    // Orthonormalise X (n x P) into dst: X = dst Bout; drops directions with
+    // Gram eigenvalue <= thr2 (first pass) and repeats once for accuracy.
+    int qr(T *X, T *dst, double thr2, std::vector<double> &Bout, int *rank) {
+        const int PP = P * P;
+        std::vector<double> Bacc(PP, 0.0);
+        for (int i = 0; i < P; i++) Bacc[i * P + i] = 1.0;
+        T *src = X;
+        for (int pass = 0; pass < 2; pass++) {
+            std::vector<double> M, w, V;
+            MCD_TRY(gram(src, 1, src, M));
+            jacobi_eig(P, M, w, V);
+            std::vector<double> Xm(PP, 0.0), Bm(PP, 0.0);
+            double wmax = 0.0;
+            for (int i = 0; i < P; i++) wmax = std::max(wmax, w[i]);
+            const double th = pass == 0 ? thr2 : 1e-2 * std::max(wmax, 1e-300);
+            int rk = 0;
+            for (int i = 0; i < P; i++) {
+                if (w[i] <= th || w[i] <= 0.0) continue;
+                rk++;
+                const double sq = sqrt(w[i]);
+                for (int a = 0; a < P; a++) {
+                    Xm[a * P + i] = V[a * P + i] / sq;   // column i of U L^-1/2
+                    Bm[i * P + a] = sq * V[a * P + i];   // row i of L^1/2 U^T
+                }
+            }
+            *rank = rk;
+            // dst = src Xm  (when src == dst go through W)
+            T *out = (src == dst) ? W : dst;
+            MCD_TRY(block_apply(src, 1, Xm, out, false));
+            if (out != dst)
+                MCD_HIP(hipMemcpyAsync(dst, out, (size_t)n * P * sizeof(T), hipMemcpyDeviceToDevice,
+                                       s));
+            // Bacc = Bm Bacc
+            std::vector<double> nb(PP, 0.0);
+            for (int i = 0; i < P; i++)
+                for (int j = 0; j < P; j++) {
+                    double acc = 0.0;
+                    for (int q = 0; q < P; q++) acc += Bm[i * P + q] * Bacc[q * P + j];
+                    nb[i * P + j] = acc;
+                }
+            Bacc = nb;
+            src = dst;
+            if (rk == 0) break;
+        }
+        Bout = Bacc;
+        return MCD_OK;
+    }
+
+    int run(T *phi, int max_blocks, double dtol_abs, bool reorth, BandResult &br) {
+        const int PP = P * P;
+        br.P = P;
+        br.A.clear();
+        br.B.assign(1, std::vector<double>());
+        int rk = 0;
+        std::vector<double> R0;
+        MCD_TRY(qr(phi, blk(0), dtol_abs * dtol_abs, R0, &rk));
+        br.R0 = R0;
+        br.krylov = rk;
+        if (rk == 0) {
+            br.m = 0;
+            return MCD_OK;
+        }
+        std::vector<double> G, C;
+        for (int j = 0; j < max_blocks; j++) {
+            MCD_TRY(apply_any(op, sizeof(T) == 8 ? MCD_F64 : MCD_F32, P, blk(j), W, s));
+            MCD_TRY(gram(blk(j), 1, W, G));
+            std::vector<double> Aj(PP);
+            for (int a = 0; a < P; a++)        // symmetrise the projected block
+                for (int b = 0; b < P; b++) Aj[a * P + b] = 0.5 * (G[a * P + b] + G[b * P + a]);
+            br.A.push_back(Aj);
+            // W -= Q_j A_j + Q_{j-1} B_j^T
+            MCD_TRY(block_apply(blk(j), 1, Aj, W, true));
+            if (j > 0) {
+                std::vector<double> Bt(PP);
+                for (int a = 0; a < P; a++)
+                    for (int b = 0; b < P; b++) Bt[a * P + b] = br.B[j][b * P + a];
+                MCD_TRY(block_apply(blk(j - 1), 1, Bt, W, true));
+            }
+            if (reorth) {
+                for (int pass = 0; pass < 2; pass++) {
+                    MCD_TRY(gram(blk(0), j + 1, W, C));
+                    MCD_TRY(block_apply(blk(0), j + 1, C, W, true));
+                }
+            }
+            if (j + 1 == max_blocks) break;
+            std::vector<double> Bn;
+            MCD_TRY(qr(W, blk(j + 1), dtol_abs * dtol_abs, Bn, &rk));
+            br.B.push_back(Bn);
+            if (rk == 0) break;
+            br.krylov += rk;
+        }
+        br.m = (int)br.A.size();
+        return MCD_OK;
+    }
+};
+
+static double wall_ms() {
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// One excited sector run (create = particle / G+, else hole / G-).
+template <typename T>
+static int excited_run(const mcd_model *model, const uint64_t *keys_t, const double *psi_t,
+                       int64_t nt, const SelOps &sel, bool create, const mcd_band_cfg *cfg,
+                       double dtol_scale, int P, BandResult &br, int64_t *n_x, hipStream_t s) {
+    uint64_t *img = nullptr, *srt = nullptr, *uniq = nullptr;
+    int64_t *d_nu = nullptr;
+    void *tmp = nullptr;
+    mcd_op *op = nullptr;
+    BandRun<T> run;
+    auto cleanup = [&]() {
+        for (void *p : {(void *)img, (void *)srt, (void *)uniq, (void *)d_nu, tmp, (void *)run.Qs,
+                        (void *)run.W, (void *)run.part, (void *)run.dC, (void *)run.dG})
+            if (p) (void)hipFree(p);
+        if (op) mcd_op_destroy(op);
+    };
+#define CK(expr)                                                              \
+    do {                                                                      \
+        hipError_t e_ = (expr);                                               \
+        if (e_ != hipSuccess) {                                               \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));         \
+            cleanup();                                                        \
+            return MCD_E_HIP;                                                 \
+        }                                                                     \
+    } while (0)
+#define TRY(expr)          \
+    do {                   \
+        int rc_ = (expr);  \
+        if (rc_ < 0) {     \
+            cleanup();     \
+            return rc_;    \
+        }                  \
+    } while (0)
+    const int64_t ni = nt * sel.n;
+    CK(hipMalloc(&img, std::max<int64_t>(ni, 1) * sizeof(uint64_t)));
+    CK(hipMalloc(&srt, std::max<int64_t>(ni, 1) * sizeof(uint64_t)));
+    CK(hipMalloc(&uniq, std::max<int64_t>(ni, 1) * sizeof(uint64_t)));
+    CK(hipMalloc(&d_nu, sizeof(int64_t)));
+    hipLaunchKernelGGL(k_images, dim3(gridn(nt, 256)), dim3(256), 0, s, nt, keys_t, sel,
+                       create ? 1 : 0, img);
+    CK(hipGetLastError());
+    size_t b1 = 0, b2 = 0;
+    CK(hipcub::DeviceRadixSort::SortKeys(nullptr, b1, img, srt, (int)ni, 0, 64, s));
+    CK(hipcub::DeviceSelect::Unique(nullptr, b2, srt, uniq, d_nu, (int)ni, s));
+    CK(hipMalloc(&tmp, std::max(b1, b2)));
+    size_t t1 = std::max(b1, b2), t2 = t1;
+    CK(hipcub::DeviceRadixSort::SortKeys(tmp, t1, img, srt, (int)ni, 0, 64, s));
+    CK(hipcub::DeviceSelect::Unique(tmp, t2, srt, uniq, d_nu, (int)ni, s));
+    int64_t nu = 0;
+    CK(hipMemcpyAsync(&nu, d_nu, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    uint64_t lastk = 0;
+    if (nu > 0) {
+        CK(hipMemcpyAsync(&lastk, uniq + nu - 1, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        if (lastk == kEmpty) nu--;
+    }
+    *n_x = nu;
+    if (nu == 0) {
+        br = BandResult();
+        br.P = P;
+        cleanup();
+        return MCD_OK;
+    }
+    TRY(mcd_op_create(model, uniq, nu, cfg->storage, 0, s, &op));
+    // Storage for the Krylov blocks.
+    const bool reorth = cfg->reorth != 0;
+    run.op = op;
+    run.P = P;
+    run.n = nu;
+    run.s = s;
+    run.nstore = reorth ? cfg->max_blocks + 1 : 3;
+    size_t fr = 0, tot = 0;
+    CK(hipMemGetInfo(&fr, &tot));
+    const double need = (double)run.nstore * nu * P * sizeof(T);
+    if (need > 0.8 * (double)fr) {
+        cleanup();
+        set_error("Krylov store needs %.1f GB, %.1f GB free (lower max_blocks or reorth=0)",
+                  need / 1e9, fr / 1e9);
+        return MCD_E_CAPACITY;
+    }
+    CK(hipMalloc(&run.Qs, (size_t)run.nstore * nu * P * sizeof(T)));
+    CK(hipMalloc(&run.W, (size_t)nu * P * sizeof(T)));
+    run.part_cap = (int64_t)65536 * P * P + (int64_t)(cfg->max_blocks + 1) * P * P;
+    CK(hipMalloc(&run.part, run.part_cap * sizeof(double)));
+    run.coef_cap = (int64_t)(cfg->max_blocks + 1) * P * P;
+    CK(hipMalloc(&run.dC, run.coef_cap * sizeof(double)));
+    CK(hipMalloc(&run.dG, run.coef_cap * sizeof(double)));
+    // start block (into W, then orthonormalised into Q_0)
+    CK(hipMemsetAsync(run.W, 0, (size_t)nu * P * sizeof(T), s));
+    hipLaunchKernelGGL((k_start_block<T>), dim3(gridn(nt, 256)), dim3(256), 0, s, nt, keys_t,
+                       psi_t, sel, create ? 1 : 0, op->d_hash, op->hash_mask, P, run.W);
+    CK(hipGetLastError());
+    // the start block lives in W; qr() reads W and writes Q_0 (W is reused as
+    // scratch only when source and destination coincide, not here)
+    T *phi = nullptr;
+    CK(hipMalloc(&phi, (size_t)nu * P * sizeof(T)));
+    CK(hipMemcpyAsync(phi, run.W, (size_t)nu * P * sizeof(T), hipMemcpyDeviceToDevice, s));
+    const double dtol_abs = cfg->dtol * dtol_scale;
+    int rc = run.run(phi, cfg->max_blocks, dtol_abs, reorth, br);
+    (void)hipFree(phi);
+    if (rc < 0) {
+        cleanup();
+        return rc;
+    }
+    CK(hipStreamSynchronize(s));
+    cleanup();
+#undef CK
+#undef TRY
+    return MCD_OK;
+}
+
+template <typename T>
+static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                      const double *psi0_dev, double e0, const SelOps &sel, int n_freq,
+                      const double *omega, const mcd_band_cfg *cfg, double *G_out, double *Gp_out,
+                      double *Gm_out, mcd_solve_info *info, hipStream_t s) {
+    const double t0 = wall_ms();
+    double *w = nullptr, *w2 = nullptr, *psi_t = nullptr, *scr = nullptr;
+    uint32_t *idx = nullptr, *idx2 = nullptr, *kept = nullptr;
+    uint64_t *keys_t = nullptr;
+    unsigned int *cnt = nullptr;
+    void *tmp = nullptr;
+    auto cleanup = [&]() {
+        for (void *p : {(void *)w, (void *)w2, (void *)psi_t, (void *)scr, (void *)idx,
+                        (void *)idx2, (void *)kept, (void *)keys_t, (void *)cnt, tmp})
+            if (p) (void)hipFree(p);
+    };
+#define CK(expr)                                                              \
+    do {                                                                      \
+        hipError_t e_ = (expr);                                               \
+        if (e_ != hipSuccess) {                                               \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));         \
+            cleanup();                                                        \
+            return MCD_E_HIP;                                                 \
+        }                                                                     \
+    } while (0)
+    MCD_REQUIRE(n < (int64_t(1) << 31), MCD_E_CAPACITY, "basis too large for the w_t sort");
+    CK(hipMalloc(&w, n * sizeof(double)));
+    CK(hipMalloc(&w2, n * sizeof(double)));
+    CK(hipMalloc(&idx, n * sizeof(uint32_t)));
+    CK(hipMalloc(&idx2, n * sizeof(uint32_t)));
+    CK(hipMalloc(&kept, n * sizeof(uint32_t)));
+    CK(hipMalloc(&keys_t, n * sizeof(uint64_t)));
+    CK(hipMalloc(&psi_t, n * sizeof(double)));
+    CK(hipMalloc(&scr, (4096 + 8) * sizeof(double)));
+    CK(hipMalloc(&cnt, 8 * sizeof(unsigned int)));
+    CK(hipMemsetAsync(cnt, 0, 8 * sizeof(unsigned int), s));
+    hipLaunchKernelGGL(k_weights, dim3(gridn(n, 256)), dim3(256), 0, s, n, psi0_dev, w, idx);
+    CK(hipGetLastError());
+    int64_t n_keep = n;
+    if (cfg->w_t < 1.0) {
+        size_t b1 = 0;
+        CK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, b1, w, w2, idx, idx2, (int)n, 0,
+                                                        64, s));
+        size_t b2 = 0;
+        CK(hipcub::DeviceRadixSort::SortKeys(nullptr, b2, idx2, kept, (int)n, 0, 32, s));
+        CK(hipMalloc(&tmp, std::max(b1, b2)));
+        size_t t1 = std::max(b1, b2);
+        CK(hipcub::DeviceRadixSort::SortPairsDescending(tmp, t1, w, w2, idx, idx2, (int)n, 0, 64,
+                                                        s));
+        std::vector<double> hw(n);
+        CK(hipMemcpyAsync(hw.data(), w2, n * sizeof(double), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        double total = 0.0;
+        for (int64_t i = 0; i < n; i++) total += hw[i];
+        double cum = 0.0;
+        n_keep = n;
+        for (int64_t i = 0; i < n; i++) {
+            cum += hw[i] / total;
+            if (cum >= cfg->w_t) {
+                n_keep = i + 1;
+                break;
+            }
+        }
+        size_t t2 = std::max(b1, b2);
+        CK(hipcub::DeviceRadixSort::SortKeys(tmp, t2, idx2, kept, (int)n_keep, 0, 32, s));
+    } else {
+        CK(hipMemcpyAsync(kept, idx, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    }
+    hipLaunchKernelGGL(k_gather_kept, dim3(gridn(n_keep, 256)), dim3(256), 0, s, n_keep, kept,
+                       keys_dev, psi0_dev, keys_t, psi_t);
+    hipLaunchKernelGGL(k_norm2, dim3(std::min<unsigned>(gridn(n_keep, BS), 2048)), dim3(BS), 0, s,
+                       n_keep, psi_t, scr, cnt, scr + 4096);
+    hipLaunchKernelGGL(k_scale_by, dim3(gridn(n_keep, 256)), dim3(256), 0, s, n_keep, psi_t,
+                       scr + 4096);
+    CK(hipGetLastError());
+    CK(hipStreamSynchronize(s));
+
+    int P = 1;
+    while (P < sel.n) P <<= 1;
+    const int p = sel.n;
+    BandResult brp, brm;
+    int64_t np = 0, nm = 0;
+    int rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, true, cfg, 1.0, P, brp, &np, s);
+    if (rc >= 0)
+        rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, false, cfg, 1.0, P, brm, &nm, s);
+    if (rc < 0) {
+        cleanup();
+        return rc;
+    }
+    std::vector<cplx> g(p * p);
+    for (int f = 0; f < n_freq; f++) {
+        cplx *Gf = (cplx *)G_out + (size_t)f * p * p;
+        for (int e = 0; e < p * p; e++) Gf[e] = 0.0;
+        if (brp.m > 0) {
+            block_cf(brp, cplx(e0, omega[f]), p, g.data());
+            for (int e = 0; e < p * p; e++) {
+                Gf[e] += g[e];
+                if (Gp_out) ((cplx *)Gp_out)[(size_t)f * p * p + e] = g[e];
+            }
+        } else if (Gp_out) {
+            for (int e = 0; e < p * p; e++) ((cplx *)Gp_out)[(size_t)f * p * p + e] = 0.0;
+        }
+        if (brm.m > 0) {
+            block_cf(brm, cplx(e0, -omega[f]), p, g.data());
+            for (int e = 0; e < p * p; e++) {
+                Gf[e] -= g[e];
+                if (Gm_out) ((cplx *)Gm_out)[(size_t)f * p * p + e] = -g[e];
+            }
+        } else if (Gm_out) {
+            for (int e = 0; e < p * p; e++) ((cplx *)Gm_out)[(size_t)f * p * p + e] = 0.0;
+        }
+    }
+    cleanup();
+#undef CK
+    if (info) {
+        memset(info, 0, sizeof(*info));
+        info->iters = std::max(brp.m, brm.m);
+        info->converged = 1;
+        info->e0 = e0;
+        info->solve_ms = wall_ms() - t0;
+        info->krylov_dim = brp.krylov + brm.krylov;
+        info->n_plus = np;
+        info->n_minus = nm;
+        info->n_truncated = n_keep;
+    }
+    return MCD_OK;
+}
+
+}  // namespace mcd
+
+using namespace mcd;
+
+extern "C" int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                                      const double *psi0_dev, double e0, int32_t n_sel,
+                                      const int32_t *orb, const int32_t *spin, int32_t n_freq,
+                                      const double *omega, const mcd_band_cfg *cfg,
+                                      double *G_out, double *Gp_out, double *Gm_out,
+                                      mcd_solve_info *info, void *stream) {
+    MCD_REQUIRE(model && cfg && keys_dev && psi0_dev && orb && spin && G_out, MCD_E_INVALID,
+                "a required pointer is NULL");
+    MCD_REQUIRE(n >= 1, MCD_E_INVALID, "empty basis");
+    MCD_REQUIRE(n_sel >= 1 && n_sel <= 16, MCD_E_INVALID, "n_sel = %d outside 1..16", n_sel);
+    MCD_REQUIRE(n_freq >= 0 && (n_freq == 0 || omega), MCD_E_INVALID, "bad frequencies");
+    MCD_REQUIRE(cfg->w_t > 0.0 && cfg->w_t <= 1.0, MCD_E_INVALID, "w_t must be in (0, 1]");
+    MCD_REQUIRE(cfg->max_blocks >= 1, MCD_E_INVALID, "max_blocks must be >= 1");
+    MCD_REQUIRE(cfg->precision == MCD_F64 || cfg->precision == MCD_F32, MCD_E_INVALID,
+                "precision must be MCD_F64 or MCD_F32");
+    HostModel hm;
+    MCD_TRY(prepare_model(model, &hm));
+    SelOps sel;
+    memset(&sel, 0, sizeof(sel));
+    sel.n = n_sel;
+    for (int q = 0; q < n_sel; q++) {
+        MCD_REQUIRE(orb[q] >= 0 && orb[q] < model->n_orb && (spin[q] == 0 || spin[q] == 1),
+                    MCD_E_INVALID, "selection %d = (%d, %d) invalid", q, orb[q], spin[q]);
+        sel.orb[q] = orb[q];
+        sel.spin[q] = spin[q];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (cfg->precision == MCD_F64)
+        return band_green<double>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg,
+                                  G_out, Gp_out, Gm_out, info, s);
+    return band_green<float>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg, G_out,
+                             Gp_out, Gm_out, info, s);
+}

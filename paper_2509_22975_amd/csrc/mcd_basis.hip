@@ -1,0 +1,316 @@
+// The truncated basis F~ (Sec. Subspace of the ground state; Sec. Other
+// sampling methods).
+//
+// Full sector: every key of (n_up, n_dn), produced in sorted order on the GPU
+// by unranking combinations (combinatorial number system, up string major).
+//
+// Chain: a Metropolis chain over the sector, one random hop per step,
+// accepted with the Boltzmann ratio of the diagonal energy.  A Markov chain
+// is sequential, so the host walks it; it only emits the steps at which the
+// state changes (plus the first recorded step).  The GPU does the rest: a
+// hash table keeps, for every distinct state, the earliest step it was
+// recorded at (atomicMin); the first n_f distinct states in order of first
+// visit are exactly the states a sequential "stop at n_f" run would hold;
+// they are selected by sorting first-visit steps and then sorted by key.
+#include <hipcub/hipcub.hpp>
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "mcd_internal.h"
+
+namespace mcd {
+
+struct Binom {
+    uint64_t c[MCD_MAX_ORB + 1][MCD_MAX_ORB + 1];
+};
+
+static void fill_binom(Binom &b) {
+    memset(&b, 0, sizeof(b));
+    for (int n = 0; n <= MCD_MAX_ORB; n++) {
+        b.c[n][0] = 1;
+        for (int k = 1; k <= n; k++) b.c[n][k] = b.c[n - 1][k - 1] + (k <= n - 1 ? b.c[n - 1][k] : 0);
+    }
+}
+
+// The r-th smallest n-bit string with k ones (r counted from 0).
+__device__ __forceinline__ uint32_t unrank(uint64_t r, int n, int k, const Binom *__restrict__ B) {
+    uint32_t s = 0;
+    for (int i = n - 1; i >= 0 && k > 0; i--) {
+        const uint64_t below = B->c[i][k];   // strings using only bits < i
+        if (r >= below) {
+            s |= 1u << i;
+            r -= below;
+            k--;
+        }
+    }
+    return s;
+}
+
+__global__ void k_enumerate(uint64_t total, uint64_t n_dn_states, int n, int nu, int nd,
+                            const Binom *__restrict__ B, uint64_t *__restrict__ keys) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const uint64_t ru = q / n_dn_states, rd = q % n_dn_states;
+    keys[q] = ((uint64_t)unrank(ru, n, nu, B) << 32) | unrank(rd, n, nd, B);
+}
+
+struct VisitSlot {
+    unsigned long long key;
+    unsigned long long step;
+};
+
+__device__ __forceinline__ uint64_t vmix(uint64_t k) {
+    k ^= k >> 31;
+    k *= 0x7fb5d329728ea185ull;
+    k ^= k >> 27;
+    k *= 0x81dadef4bc2dd44dull;
+    k ^= k >> 33;
+    return k;
+}
+
+__global__ void k_visit_insert(int64_t m, const uint64_t *__restrict__ ev_key,
+                               const uint64_t *__restrict__ ev_step, VisitSlot *tab, uint64_t mask,
+                               unsigned long long *distinct) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint64_t key = ev_key[i];
+    uint64_t p = vmix(key) & mask;
+    for (;;) {
+        const unsigned long long prev = atomicCAS(&tab[p].key, (unsigned long long)kEmpty,
+                                                  (unsigned long long)key);
+        if (prev == kEmpty) atomicAdd(distinct, 1ull);
+        if (prev == kEmpty || prev == key) {
+            atomicMin(&tab[p].step, (unsigned long long)ev_step[i]);
+            return;
+        }
+        p = (p + 1) & mask;
+    }
+}
+
+__global__ void k_visit_compact(uint64_t cap, const VisitSlot *__restrict__ tab,
+                                uint64_t *__restrict__ steps, uint64_t *__restrict__ keys,
+                                unsigned long long *cnt) {
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= cap) return;
+    const VisitSlot v = tab[p];
+    if (v.key == kEmpty) return;
+    const unsigned long long at = atomicAdd(cnt, 1ull);
+    steps[at] = v.step;
+    keys[at] = v.key;
+}
+
+// splitmix64 (Vigna): the chain's random stream.
+struct SplitMix {
+    uint64_t s;
+    uint64_t next() {
+        s += 0x9E3779B97F4A7C15ull;
+        uint64_t z = s;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+};
+
+// Host walker of the chain: advances `nsteps` steps and appends (step, key)
+// whenever a recorded step holds a state different from the previous record.
+struct ChainWalker {
+    const mcd_model *m;
+    std::vector<int> lo, hi;
+    uint64_t up, dn;
+    SplitMix rng;
+    double beta;
+    int64_t step = 0, burn_in;
+    bool have_record = false;
+
+    void run(int64_t nsteps, std::vector<uint64_t> &ek, std::vector<uint64_t> &es) {
+        const uint64_t M = 4ull * (uint64_t)lo.size();
+        for (int64_t it = 0; it < nsteps; it++) {
+            const uint64_t r0 = rng.next(), r1 = rng.next();
+            const uint64_t pick = ((r0 >> 32) * M) >> 32;
+            const int b = (int)(pick >> 2);
+            const bool spin_dn = ((pick >> 1) & 1ull) != 0;
+            const bool rev = (pick & 1ull) != 0;
+            const int src = rev ? hi[b] : lo[b], dst = rev ? lo[b] : hi[b];
+            uint64_t &mine = spin_dn ? dn : up;
+            const uint64_t other = spin_dn ? up : dn;
+            bool moved = false;
+            if (((mine >> src) & 1ull) != 0 && ((mine >> dst) & 1ull) == 0) {
+                const double od = (double)((other >> dst) & 1ull);
+                const double os = (double)((other >> src) & 1ull);
+                const double dE = (m->eps[dst] - m->eps[src]) + (m->U[dst] * od - m->U[src] * os);
+                const double u = (double)(r1 >> 11) * (1.0 / 9007199254740992.0);
+                if (dE <= 0.0 || u < exp(-beta * dE)) {
+                    mine ^= (1ull << src) | (1ull << dst);
+                    moved = true;
+                }
+            }
+            step++;
+            if (step > burn_in && (moved || !have_record)) {
+                ek.push_back((up << 32) | dn);
+                es.push_back((uint64_t)step);
+                have_record = true;
+            }
+        }
+    }
+};
+
+static int build_full(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t *keys_dev,
+                      int64_t cap, int64_t *n_out, hipStream_t s) {
+    Binom hb;
+    fill_binom(hb);
+    const int n = model->n_orb;
+    const uint64_t nd_states = hb.c[n][cfg->n_dn];
+    const uint64_t total = hb.c[n][cfg->n_up] * nd_states;
+    *n_out = (int64_t)total;
+    MCD_REQUIRE((int64_t)total <= cap, MCD_E_CAPACITY, "sector has %llu states, cap is %lld",
+                (unsigned long long)total, (long long)cap);
+    Binom *db = nullptr;
+    MCD_HIP(hipMalloc(&db, sizeof(Binom)));
+    MCD_HIP(hipMemcpyAsync(db, &hb, sizeof(Binom), hipMemcpyHostToDevice, s));
+    if (total)
+        hipLaunchKernelGGL(k_enumerate, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                           total, nd_states, n, cfg->n_up, cfg->n_dn, db, keys_dev);
+    MCD_HIP(hipGetLastError());
+    MCD_HIP(hipStreamSynchronize(s));
+    MCD_HIP(hipFree(db));
+    return MCD_OK;
+}
+
+static int build_chain(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t *keys_dev,
+                       int64_t cap, int64_t *n_out, int64_t *steps_out, hipStream_t s) {
+    const uint64_t lim = model->n_orb >= 32 ? 0xffffffffull : ((1ull << model->n_orb) - 1ull);
+    const uint64_t su = cfg->start_key >> 32, sd = cfg->start_key & 0xffffffffull;
+    MCD_REQUIRE((su & ~lim) == 0 && (sd & ~lim) == 0 && __builtin_popcountll(su) == cfg->n_up &&
+                    __builtin_popcountll(sd) == cfg->n_dn,
+                MCD_E_SECTOR, "start key is not in the (%d, %d) sector", cfg->n_up, cfg->n_dn);
+    MCD_REQUIRE(cfg->n_f >= 0 && cfg->burn_in >= 0 && cfg->max_steps >= 0, MCD_E_INVALID,
+                "negative n_f, burn_in or max_steps");
+    MCD_REQUIRE(model->n_bonds >= 1, MCD_E_INVALID, "a chain needs at least one bond");
+    ChainWalker w;
+    w.m = model;
+    for (int b = 0; b < model->n_bonds; b++) {
+        w.lo.push_back(std::min(model->bond_i[b], model->bond_j[b]));
+        w.hi.push_back(std::max(model->bond_i[b], model->bond_j[b]));
+    }
+    w.up = su;
+    w.dn = sd;
+    w.rng.s = cfg->seed;
+    w.beta = cfg->beta_s;
+    w.burn_in = cfg->burn_in;
+
+    const int64_t chunk = int64_t(1) << 24;
+    uint64_t tcap = 1024;
+    while (tcap < (uint64_t)(2 * (cfg->n_f + chunk))) tcap <<= 1;
+    VisitSlot *tab = nullptr;
+    uint64_t *d_ek = nullptr, *d_es = nullptr;
+    unsigned long long *d_cnt = nullptr;
+    uint64_t *d_steps = nullptr, *d_keys = nullptr, *d_steps2 = nullptr, *d_keys2 = nullptr;
+    void *tmp = nullptr;
+    auto cleanup = [&]() {
+        for (void *p : {(void *)tab, (void *)d_ek, (void *)d_es, (void *)d_cnt, (void *)d_steps,
+                        (void *)d_keys, (void *)d_steps2, (void *)d_keys2, tmp})
+            if (p) (void)hipFree(p);
+    };
+#define CK(expr)                                                                    \
+    do {                                                                            \
+        hipError_t e_ = (expr);                                                     \
+        if (e_ != hipSuccess) {                                                     \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));               \
+            cleanup();                                                              \
+            return MCD_E_HIP;                                                       \
+        }                                                                           \
+    } while (0)
+    CK(hipMalloc(&tab, tcap * sizeof(VisitSlot)));
+    CK(hipMemsetAsync(tab, 0xff, tcap * sizeof(VisitSlot), s));
+    CK(hipMalloc(&d_ek, chunk * sizeof(uint64_t)));
+    CK(hipMalloc(&d_es, chunk * sizeof(uint64_t)));
+    CK(hipMalloc(&d_cnt, 2 * sizeof(unsigned long long)));
+    CK(hipMemsetAsync(d_cnt, 0, 2 * sizeof(unsigned long long), s));
+    std::vector<uint64_t> ek, es;
+    ek.reserve(chunk);
+    es.reserve(chunk);
+    unsigned long long distinct = 0;
+    while (w.step < cfg->max_steps && (int64_t)distinct < cfg->n_f) {
+        ek.clear();
+        es.clear();
+        w.run(std::min<int64_t>(chunk, cfg->max_steps - w.step), ek, es);
+        const int64_t m = (int64_t)ek.size();
+        if (m) {
+            CK(hipMemcpyAsync(d_ek, ek.data(), m * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+            CK(hipMemcpyAsync(d_es, es.data(), m * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_visit_insert, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+                               m, d_ek, d_es, tab, tcap - 1, d_cnt);
+            CK(hipGetLastError());
+        }
+        CK(hipMemcpyAsync(&distinct, d_cnt, sizeof(distinct), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+    }
+    const int64_t D = (int64_t)distinct;
+    const int64_t nf = std::min<int64_t>(D, cfg->n_f);
+    *n_out = nf;
+    if (nf > cap) {
+        cleanup();
+        set_error("chain basis has %lld states, cap is %lld", (long long)nf, (long long)cap);
+        return MCD_E_CAPACITY;
+    }
+    int64_t steps_done = w.step;
+    if (D > 0) {
+        CK(hipMalloc(&d_steps, D * sizeof(uint64_t)));
+        CK(hipMalloc(&d_keys, D * sizeof(uint64_t)));
+        CK(hipMalloc(&d_steps2, D * sizeof(uint64_t)));
+        CK(hipMalloc(&d_keys2, D * sizeof(uint64_t)));
+        hipLaunchKernelGGL(k_visit_compact, dim3((unsigned)((tcap + 255) / 256)), dim3(256), 0, s,
+                           tcap, tab, d_steps, d_keys, d_cnt + 1);
+        CK(hipGetLastError());
+        size_t tb1 = 0, tb2 = 0;
+        CK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb1, d_steps, d_steps2, d_keys, d_keys2,
+                                              (int)D, 0, 64, s));
+        CK(hipcub::DeviceRadixSort::SortKeys(nullptr, tb2, d_keys2, keys_dev, (int)nf, 0, 64, s));
+        const size_t tb = std::max(tb1, tb2);
+        CK(hipMalloc(&tmp, tb));
+        size_t t1 = tb;
+        CK(hipcub::DeviceRadixSort::SortPairs(tmp, t1, d_steps, d_steps2, d_keys, d_keys2, (int)D,
+                                              0, 64, s));
+        if ((int64_t)distinct >= cfg->n_f && nf > 0) {
+            uint64_t last = 0;
+            CK(hipMemcpyAsync(&last, d_steps2 + (nf - 1), sizeof(uint64_t), hipMemcpyDeviceToHost,
+                              s));
+            CK(hipStreamSynchronize(s));
+            steps_done = (int64_t)last;
+        }
+        size_t t2 = tb;
+        if (nf > 0)
+            CK(hipcub::DeviceRadixSort::SortKeys(tmp, t2, d_keys2, keys_dev, (int)nf, 0, 64, s));
+        CK(hipStreamSynchronize(s));
+    }
+    if (steps_out) *steps_out = steps_done;
+    cleanup();
+#undef CK
+    return MCD_OK;
+}
+
+}  // namespace mcd
+
+using namespace mcd;
+
+extern "C" int mcd_basis_build(const mcd_model *model, const mcd_basis_cfg *cfg,
+                               uint64_t *keys_dev, int64_t cap, int64_t *n_out,
+                               int64_t *steps_out, void *stream) {
+    MCD_REQUIRE(model && cfg && n_out, MCD_E_INVALID, "model, cfg or n_out is NULL");
+    HostModel hm;
+    MCD_TRY(prepare_model(model, &hm));
+    MCD_REQUIRE(cfg->n_up >= 0 && cfg->n_dn >= 0 && cfg->n_up <= model->n_orb &&
+                    cfg->n_dn <= model->n_orb,
+                MCD_E_SECTOR, "sector (%d, %d) impossible with %d orbitals", cfg->n_up, cfg->n_dn,
+                model->n_orb);
+    MCD_REQUIRE(cap == 0 || keys_dev != nullptr, MCD_E_INVALID, "keys_dev is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (steps_out) *steps_out = 0;
+    if (cfg->mode == MCD_BASIS_FULL) return build_full(model, cfg, keys_dev, cap, n_out, s);
+    if (cfg->mode == MCD_BASIS_CHAIN)
+        return build_chain(model, cfg, keys_dev, cap, n_out, steps_out, s);
+    set_error("basis mode %d unknown", cfg->mode);
+    return MCD_E_INVALID;
+}

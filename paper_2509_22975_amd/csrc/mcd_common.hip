@@ -1,0 +1,93 @@
+// Error reporting and model preparation shared by the library.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <utility>
+
+#include "mcd_internal.h"
+
+namespace mcd {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+// Validate the model, merge bonds that join the same pair (their amplitudes
+// add, as two listed terms of Eq. hubbard_model would) and assign each
+// distinct |t| a class index for the packed CSR.
+int prepare_model(const mcd_model *m, HostModel *hm) {
+    MCD_REQUIRE(m != nullptr, MCD_E_INVALID, "model is NULL");
+    MCD_REQUIRE(m->n_orb >= 1 && m->n_orb <= MCD_MAX_ORB, MCD_E_INVALID,
+                "n_orb = %d outside 1..%d", m->n_orb, MCD_MAX_ORB);
+    MCD_REQUIRE(m->n_bonds >= 0 && m->n_bonds <= MCD_MAX_BONDS, MCD_E_INVALID,
+                "n_bonds = %d outside 0..%d", m->n_bonds, MCD_MAX_BONDS);
+    MCD_REQUIRE(m->U && m->eps, MCD_E_INVALID, "U or eps is NULL");
+    MCD_REQUIRE(m->n_bonds == 0 || (m->bond_i && m->bond_j && m->bond_t), MCD_E_INVALID,
+                "bond arrays are NULL");
+    DevModel &d = hm->dm;
+    memset(&d, 0, sizeof(d));
+    d.n_orb = m->n_orb;
+    for (int i = 0; i < m->n_orb; i++) {
+        d.U[i] = m->U[i];
+        d.eps[i] = m->eps[i];
+    }
+    std::vector<std::pair<std::pair<int, int>, double>> merged;
+    std::map<std::pair<int, int>, size_t> where;
+    for (int b = 0; b < m->n_bonds; b++) {
+        int i = m->bond_i[b], j = m->bond_j[b];
+        MCD_REQUIRE(i >= 0 && j >= 0 && i < m->n_orb && j < m->n_orb && i != j, MCD_E_INVALID,
+                    "bond %d joins (%d, %d): orbitals must differ and be < n_orb", b, i, j);
+        std::pair<int, int> key(std::min(i, j), std::max(i, j));
+        auto it = where.find(key);
+        if (it == where.end()) {
+            where[key] = merged.size();
+            merged.push_back({key, m->bond_t[b]});
+        } else {
+            merged[it->second].second += m->bond_t[b];
+        }
+    }
+    std::vector<double> classes;
+    int nb = 0;
+    hm->ok_classes = true;
+    for (auto &e : merged) {
+        double t = e.second;
+        if (t == 0.0) continue;
+        int i = e.first.first, j = e.first.second;
+        DevBond &b = d.bonds[nb++];
+        b.mask = (1u << i) | (1u << j);
+        b.between = (uint32_t)(((1ull << j) - 1ull) & ~((1ull << (i + 1)) - 1ull));
+        b.t = t;
+        b.neg = t < 0.0 ? 1u : 0u;
+        double a = fabs(t);
+        int c = -1;
+        for (size_t k = 0; k < classes.size(); k++)
+            if (classes[k] == a) c = (int)k;
+        if (c < 0) {
+            c = (int)classes.size();
+            classes.push_back(a);
+        }
+        if (c >= kMaxClasses) {
+            hm->ok_classes = false;
+            c = 0;
+        }
+        b.cls = (uint32_t)c;
+    }
+    d.n_bonds = nb;
+    d.n_classes = (int)std::min<size_t>(classes.size(), kMaxClasses);
+    for (int k = 0; k < d.n_classes; k++) d.vtab[k] = classes[k];
+    return MCD_OK;
+}
+
+}  // namespace mcd
+
+extern "C" const char *mcd_last_error(void) { return mcd::g_err; }
+extern "C" int mcd_version(void) { return 10000; }

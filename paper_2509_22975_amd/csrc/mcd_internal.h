@@ -1,0 +1,129 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include <string.h>
+
+#include "mcd.h"
+
+namespace mcd {
+
+void set_error(const char *fmt, ...);
+
+#define MCD_HIP(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            ::mcd::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                             __FILE__, __LINE__);                                      \
+            return MCD_E_HIP;                                                          \
+        }                                                                              \
+    } while (0)
+
+#define MCD_TRY(expr)                    \
+    do {                                 \
+        int rc_ = (expr);                \
+        if (rc_ < 0) return rc_;         \
+    } while (0)
+
+#define MCD_REQUIRE(cond, code, ...)           \
+    do {                                       \
+        if (!(cond)) {                         \
+            ::mcd::set_error(__VA_ARGS__);     \
+            return (code);                     \
+        }                                      \
+    } while (0)
+
+constexpr uint64_t kEmpty = ~0ull;           // hash sentinel, never a valid key
+constexpr uint32_t kColBits = 26;            // packed CSR: column bits
+constexpr uint32_t kColMask = (1u << kColBits) - 1u;
+constexpr int kMaxClasses = 32;              // packed CSR: distinct |t| values
+constexpr int kStreamNnzMax = 4096;          // LDS products per stream block
+
+// One hopping bond with i < j, prepared for bit arithmetic.
+struct DevBond {
+    uint32_t mask;      // (1 << i) | (1 << j)
+    uint32_t between;   // bits strictly between i and j
+    double t;           // amplitude t_ij (duplicates merged)
+    uint32_t cls;       // index of |t| in vtab
+    uint32_t neg;       // 1 if t < 0
+};
+
+// Model in device memory (read-only in kernels).
+struct DevModel {
+    int n_orb;
+    int n_bonds;
+    int n_classes;
+    int pad;
+    double U[MCD_MAX_ORB];
+    double eps[MCD_MAX_ORB];
+    double vtab[kMaxClasses];   // |t| per class
+    DevBond bonds[MCD_MAX_BONDS];
+};
+
+struct HashSlot {
+    uint64_t key;
+    int64_t val;
+};
+
+// Host mirror of the model: bonds merged (same unordered pair -> summed t).
+struct HostModel {
+    DevModel dm;
+    bool ok_classes;     // <= kMaxClasses distinct |t|
+};
+
+int prepare_model(const mcd_model *m, HostModel *hm);
+
+}  // namespace mcd
+
+struct mcd_op {
+    int device;
+    int64_t n;
+    int32_t storage;
+    int32_t rows_per_block;
+    int64_t nnz;
+    int64_t device_bytes;
+    double build_ms;
+    mcd::HostModel hm;
+    mcd::DevModel *d_model;
+    uint64_t *d_keys;
+    double *d_diag;
+    mcd::HashSlot *d_hash;
+    uint64_t hash_mask;
+    int64_t *d_rowptr;
+    uint32_t *d_colw;
+    // scratch for grid reductions
+    double *d_partials;        // [max blocks]
+    unsigned int *d_counter;   // last-block counters [8]
+    double *d_scalars;         // [64]
+    int64_t max_partials;
+};
+
+namespace mcd {
+
+// Launch geometry of the stream SpMV for an operator.
+inline int64_t stream_blocks(const mcd_op *op) {
+    return (op->n + op->rows_per_block - 1) / op->rows_per_block;
+}
+
+// Operator internals used by the solvers (defined in mcd_op.hip).
+// y = sx * H (x) for one double vector, sx read on the device (sx_mode 0:
+// *sx_dev, 1: 1/sqrt(*sx_dev), sx_dev == nullptr: 1); when dot_out !=
+// nullptr the scalar sum_r (sx x_r) y_r is written to *dot_out (device).
+int apply_f64_fused(const mcd_op *op, const double *x, double *y, const double *sx_dev,
+                    int sx_mode, double *dot_out, hipStream_t s);
+// y *= sx and optional dot as above (used after an on-the-fly apply).
+int scale_dot(const mcd_op *op, double *y, const double *x, const double *sx_dev, int sx_mode,
+              double *dot_out, hipStream_t s);
+int apply_any(const mcd_op *op, int dtype, int nvec, const void *x, void *y, hipStream_t s);
+
+// Deterministic dot product a . b into *out_dev (mcd_lanczos.hip).
+int dev_dot(const mcd_op *op, const double *a, const double *b, int64_t n, double *out_dev,
+            hipStream_t s);
+
+}  // namespace mcd

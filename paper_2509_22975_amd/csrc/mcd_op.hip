@@ -1,0 +1,561 @@
+// The operator H~ = P H P on a truncated basis (Eq. h_matrix_projected):
+// device index of the basis, diagonal, packed CSR build, and the applies.
+//
+// Kernels
+//   k_validate      keys sorted, unique, within n_orb bits
+//   k_diag          d_r = sum_i U_i n_iu n_id + sum_is eps_i n_is
+//   k_hash_insert   open-addressing hash key -> row (load <= 1/4)
+//   k_csr_count     kept hops per row (hop enumeration + lookup)
+//   k_csr_fill      packed words: column | class << 26 | sign << 31
+//   k_spmv_stream   one vector: a workgroup streams the nonzeros of a row
+//                   block into LDS products, then each row sums its run
+//   k_apply_group   nvec vectors (row-major): nvec lanes per row, each lane
+//                   one column of the block; CSR or on-the-fly elements
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <chrono>
+
+#include "mcd_hash.h"
+#include "mcd_internal.h"
+#include "mcd_reduce.h"
+
+namespace mcd {
+
+__global__ void k_validate(int64_t n, const uint64_t *__restrict__ keys, int n_orb,
+                           int *__restrict__ bad) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint64_t k = keys[r];
+    const uint64_t lim = (n_orb >= 32) ? 0xffffffffull : ((1ull << n_orb) - 1ull);
+    bool ok = ((k >> 32) & ~lim) == 0 && ((k & 0xffffffffull) & ~lim) == 0;
+    if (r + 1 < n) ok = ok && keys[r + 1] > k;
+    if (!ok) atomicOr(bad, 1);
+}
+
+__global__ void k_diag(int64_t n, const uint64_t *__restrict__ keys,
+                       const DevModel *__restrict__ m, double *__restrict__ diag) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint64_t k = keys[r];
+    const uint32_t up = (uint32_t)(k >> 32), dn = (uint32_t)k;
+    double d = 0.0;
+    for (int i = 0; i < m->n_orb; i++) {
+        const double nu = (double)((up >> i) & 1u), nd = (double)((dn >> i) & 1u);
+        d += m->U[i] * (nu * nd);
+        d += m->eps[i] * (nu + nd);
+    }
+    diag[r] = d;
+}
+
+__global__ void k_hash_insert(int64_t n, const uint64_t *__restrict__ keys, HashSlot *h,
+                              uint64_t mask) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint64_t key = keys[r];
+    uint64_t p = mix64(key) & mask;
+    for (;;) {
+        unsigned long long prev = atomicCAS((unsigned long long *)&h[p].key,
+                                            (unsigned long long)kEmpty, (unsigned long long)key);
+        if (prev == kEmpty || prev == key) {
+            h[p].val = r;
+            return;
+        }
+        p = (p + 1) & mask;
+    }
+}
+
+// Visit every kept hop of the state `key` in canonical order (bond order, up
+// spin before down).  f(col, bond) is called for each image found in the
+// basis; `neg` = element sign bit = JW parity XOR sign of t.
+template <typename F>
+__device__ __forceinline__ void for_each_hop(uint64_t key, const DevModel *__restrict__ m,
+                                             const HashSlot *__restrict__ h, uint64_t hmask,
+                                             F &&f) {
+    const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
+    const int nb = m->n_bonds;
+    for (int b = 0; b < nb; b++) {
+        const uint32_t mask = m->bonds[b].mask;
+        const uint32_t between = m->bonds[b].between;
+        if (__popc(up & mask) == 1) {
+            const int64_t c = hash_find(h, hmask, key ^ ((uint64_t)mask << 32));
+            if (c >= 0) f(c, b, (uint32_t)(__popc(up & between) & 1));
+        }
+        if (__popc(dn & mask) == 1) {
+            const int64_t c = hash_find(h, hmask, key ^ (uint64_t)mask);
+            if (c >= 0) f(c, b, (uint32_t)(__popc(dn & between) & 1));
+        }
+    }
+}
+
+__global__ void k_csr_count(int64_t n, const uint64_t *__restrict__ keys,
+                            const DevModel *__restrict__ m, const HashSlot *__restrict__ h,
+                            uint64_t hmask, int64_t *__restrict__ cnt) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > n) return;
+    if (r == n) {
+        cnt[n] = 0;
+        return;
+    }
+    int64_t c = 0;
+    for_each_hop(keys[r], m, h, hmask, [&](int64_t, int, uint32_t) { c++; });
+    cnt[r] = c;
+}
+
+__global__ void k_csr_fill(int64_t n, const uint64_t *__restrict__ keys,
+                           const DevModel *__restrict__ m, const HashSlot *__restrict__ h,
+                           uint64_t hmask, const int64_t *__restrict__ rowptr,
+                           uint32_t *__restrict__ colw) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int64_t e = rowptr[r];
+    for_each_hop(keys[r], m, h, hmask, [&](int64_t c, int b, uint32_t par) {
+        const uint32_t neg = par ^ m->bonds[b].neg;
+        colw[e++] = (uint32_t)c | (m->bonds[b].cls << kColBits) | (neg << 31);
+    });
+}
+
+__global__ void k_block_max(int64_t n, int R, const int64_t *__restrict__ rowptr,
+                            unsigned long long *out) {
+    const int64_t nb = (n + R - 1) / R;
+    unsigned long long best = 0;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r0 = b * R, r1 = min(r0 + (int64_t)R, n);
+        best = max(best, (unsigned long long)(rowptr[r1] - rowptr[r0]));
+    }
+    atomicMax(out, best);
+}
+
+// ---------------------------------------------------------------------------
+// One-vector CSR product.  A workgroup owns rows [r0, r0 + R); its nonzeros
+// are contiguous, so phase 1 reads them fully coalesced (4 words per thread
+// in flight), gathers x and writes the signed products to LDS; phase 2 adds
+// each row's run in entry order after d_r x_r.  Optional fused dot product
+// sum_r (sx x_r) y_r reduced by the last workgroup.
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_spmv_stream(
+    int64_t n, int R, const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ colw,
+    const DevModel *__restrict__ m, const double *__restrict__ diag, const T *__restrict__ x,
+    T *__restrict__ y, const double *__restrict__ sx_dev, int sx_mode,
+    double *__restrict__ partials, unsigned int *counter, double *__restrict__ dot_out) {
+    __shared__ T prod[kStreamNnzMax];
+    const double sx = scale_from(sx_dev, sx_mode);
+    __shared__ T vtab[kMaxClasses];
+    if (threadIdx.x < kMaxClasses) vtab[threadIdx.x] = (T)m->vtab[threadIdx.x];
+    const int64_t r0 = (int64_t)blockIdx.x * R;
+    const int64_t r1 = min(r0 + (int64_t)R, n);
+    const int64_t e0 = rowptr[r0], e1 = rowptr[r1];
+    const int cnt = (int)(e1 - e0);
+    __syncthreads();
+    const uint32_t *__restrict__ cw = colw + e0;
+    int e = threadIdx.x;
+    for (; e + 3 * BS < cnt; e += 4 * BS) {
+        const uint32_t w0 = cw[e], w1 = cw[e + BS], w2 = cw[e + 2 * BS], w3 = cw[e + 3 * BS];
+        const T x0 = x[w0 & kColMask], x1 = x[w1 & kColMask];
+        const T x2 = x[w2 & kColMask], x3 = x[w3 & kColMask];
+        const T v0 = vtab[(w0 >> kColBits) & 31], v1 = vtab[(w1 >> kColBits) & 31];
+        const T v2 = vtab[(w2 >> kColBits) & 31], v3 = vtab[(w3 >> kColBits) & 31];
+        prod[e] = (w0 >> 31) ? -(v0 * x0) : v0 * x0;
+        prod[e + BS] = (w1 >> 31) ? -(v1 * x1) : v1 * x1;
+        prod[e + 2 * BS] = (w2 >> 31) ? -(v2 * x2) : v2 * x2;
+        prod[e + 3 * BS] = (w3 >> 31) ? -(v3 * x3) : v3 * x3;
+    }
+    for (; e < cnt; e += BS) {
+        const uint32_t w = cw[e];
+        const T xv = x[w & kColMask];
+        const T v = vtab[(w >> kColBits) & 31];
+        prod[e] = (w >> 31) ? -(v * xv) : v * xv;
+    }
+    __syncthreads();
+    double dot = 0.0;
+    for (int i = threadIdx.x; i < R; i += BS) {
+        const int64_t r = r0 + i;
+        if (r < r1) {
+            const int s = (int)(rowptr[r] - e0), t = (int)(rowptr[r + 1] - e0);
+            const T xr = x[r];
+            T acc = (T)diag[r] * xr;
+            for (int k = s; k < t; k++) acc += prod[k];
+            acc = acc * (T)sx;
+            y[r] = acc;
+            dot += (double)xr * sx * (double)acc;
+        }
+    }
+    if (dot_out != nullptr) {
+        const double bsum = block_sum<BS>(dot);
+        grid_sum_last<BS>(bsum, gridDim.x, partials, counter, dot_out);
+    }
+}
+
+// nvec lanes per row: lane k accumulates column k of the block.  CSR words
+// are read once per group (same address for the group's lanes).
+template <typename T, int NV, int BS, bool OTF>
+__global__ __launch_bounds__(BS) void k_apply_group(
+    int64_t n, const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ colw,
+    const DevModel *__restrict__ m, const uint64_t *__restrict__ keys,
+    const HashSlot *__restrict__ h, uint64_t hmask, const double *__restrict__ diag,
+    const T *__restrict__ x, T *__restrict__ y) {
+    __shared__ T vtab[kMaxClasses];
+    if (threadIdx.x < kMaxClasses) vtab[threadIdx.x] = (T)m->vtab[threadIdx.x];
+    __syncthreads();
+    constexpr int RPB = BS / NV;
+    const int64_t r = (int64_t)blockIdx.x * RPB + threadIdx.x / NV;
+    const int lane = threadIdx.x % NV;
+    if (r >= n) return;
+    T acc = (T)diag[r] * x[r * NV + lane];
+    if constexpr (!OTF) {
+        const int64_t e1 = rowptr[r + 1];
+        for (int64_t e = rowptr[r]; e < e1; e++) {
+            const uint32_t w = colw[e];
+            const T v = vtab[(w >> kColBits) & 31];
+            const T xv = x[(int64_t)(w & kColMask) * NV + lane];
+            acc += (w >> 31) ? -(v * xv) : v * xv;
+        }
+    } else {
+        for_each_hop(keys[r], m, h, hmask, [&](int64_t c, int b, uint32_t par) {
+            const T v = (T)m->bonds[b].t;
+            const T xv = x[c * NV + lane];
+            acc += par ? -(v * xv) : v * xv;
+        });
+    }
+    y[r * NV + lane] = acc;
+}
+
+__global__ void k_conn_count(int64_t row0, int64_t row1, const uint64_t *__restrict__ keys,
+                             const DevModel *__restrict__ m, const HashSlot *__restrict__ h,
+                             uint64_t hmask, int64_t *__restrict__ cnt) {
+    const int64_t r = row0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= row1) return;
+    int64_t c = 0;
+    for_each_hop(keys[r], m, h, hmask, [&](int64_t, int, uint32_t) { c++; });
+    cnt[r - row0] = c;
+}
+
+__global__ void k_conn_fill(int64_t row0, int64_t row1, const uint64_t *__restrict__ keys,
+                            const DevModel *__restrict__ m, const HashSlot *__restrict__ h,
+                            uint64_t hmask, const int64_t *__restrict__ off,
+                            int64_t *__restrict__ rows, int64_t *__restrict__ cols,
+                            double *__restrict__ vals) {
+    const int64_t r = row0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= row1) return;
+    int64_t e = off[r - row0];
+    for_each_hop(keys[r], m, h, hmask, [&](int64_t c, int b, uint32_t par) {
+        rows[e] = r;
+        cols[e] = c;
+        vals[e] = par ? -m->bonds[b].t : m->bonds[b].t;
+        e++;
+    });
+}
+
+static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+static int build_csr(mcd_op *op, hipStream_t s) {
+    const int64_t n = op->n;
+    int64_t *cnt = nullptr;
+    MCD_HIP(hipMalloc(&op->d_rowptr, (n + 1) * sizeof(int64_t)));
+    MCD_HIP(hipMalloc(&cnt, (n + 1) * sizeof(int64_t)));
+    op->device_bytes += (n + 1) * sizeof(int64_t);
+    hipLaunchKernelGGL(k_csr_count, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, n, op->d_keys,
+                       op->d_model, op->d_hash, op->hash_mask, cnt);
+    MCD_HIP(hipGetLastError());
+    size_t tmp_bytes = 0;
+    MCD_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, op->d_rowptr, n + 1, s));
+    void *tmp = nullptr;
+    MCD_HIP(hipMalloc(&tmp, tmp_bytes));
+    MCD_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, op->d_rowptr, n + 1, s));
+    int64_t nnz = 0;
+    MCD_HIP(hipMemcpyAsync(&nnz, op->d_rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MCD_HIP(hipStreamSynchronize(s));
+    MCD_HIP(hipFree(tmp));
+    MCD_HIP(hipFree(cnt));
+    op->nnz = nnz;
+    MCD_HIP(hipMalloc(&op->d_colw, std::max<int64_t>(nnz, 1) * sizeof(uint32_t)));
+    op->device_bytes += nnz * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
+                       op->d_model, op->d_hash, op->hash_mask, op->d_rowptr, op->d_colw);
+    MCD_HIP(hipGetLastError());
+    // Largest power-of-two row block whose nonzeros fit the LDS product buffer.
+    unsigned long long *d_max = nullptr;
+    MCD_HIP(hipMalloc(&d_max, sizeof(unsigned long long)));
+    op->rows_per_block = 1;
+    for (int R = 256; R >= 1; R >>= 1) {
+        MCD_HIP(hipMemsetAsync(d_max, 0, sizeof(unsigned long long), s));
+        hipLaunchKernelGGL(k_block_max, dim3(512), dim3(256), 0, s, n, R, op->d_rowptr, d_max);
+        unsigned long long mx = 0;
+        MCD_HIP(hipMemcpyAsync(&mx, d_max, sizeof(mx), hipMemcpyDeviceToHost, s));
+        MCD_HIP(hipStreamSynchronize(s));
+        if (mx <= (unsigned long long)kStreamNnzMax) {
+            op->rows_per_block = R;
+            break;
+        }
+    }
+    MCD_HIP(hipFree(d_max));
+    return MCD_OK;
+}
+
+template <typename T>
+static int launch_apply(const mcd_op *op, int nvec, const T *x, T *y, hipStream_t s) {
+    const bool otf = op->storage == MCD_STORAGE_ON_THE_FLY;
+    const int64_t n = op->n;
+    if (n == 0) return MCD_OK;
+    if (!otf && nvec == 1) {
+        hipLaunchKernelGGL((k_spmv_stream<T, 256>), dim3((unsigned)stream_blocks(op)), dim3(256),
+                           0, s, n, op->rows_per_block, op->d_rowptr, op->d_colw, op->d_model,
+                           op->d_diag, x, y, (const double *)nullptr, 0, (double *)nullptr,
+                           (unsigned int *)nullptr, (double *)nullptr);
+        MCD_HIP(hipGetLastError());
+        return MCD_OK;
+    }
+#define MCD_GROUP(NV)                                                                          \
+    case NV:                                                                                   \
+        if (otf)                                                                               \
+            hipLaunchKernelGGL((k_apply_group<T, NV, 256, true>), dim3(grid_for(n, 256 / NV)), \
+                               dim3(256), 0, s, n, op->d_rowptr, op->d_colw, op->d_model,      \
+                               op->d_keys, op->d_hash, op->hash_mask, op->d_diag, x, y);       \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_apply_group<T, NV, 256, false>),                             \
+                               dim3(grid_for(n, 256 / NV)), dim3(256), 0, s, n, op->d_rowptr,  \
+                               op->d_colw, op->d_model, op->d_keys, op->d_hash, op->hash_mask, \
+                               op->d_diag, x, y);                                              \
+        break;
+    switch (nvec) {
+        MCD_GROUP(1)
+        MCD_GROUP(2)
+        MCD_GROUP(4)
+        MCD_GROUP(8)
+        MCD_GROUP(16)
+        default:
+            set_error("nvec = %d not in {1, 2, 4, 8, 16}", nvec);
+            return MCD_E_INVALID;
+    }
+#undef MCD_GROUP
+    MCD_HIP(hipGetLastError());
+    return MCD_OK;
+}
+
+int apply_any(const mcd_op *op, int dtype, int nvec, const void *x, void *y, hipStream_t s) {
+    if (dtype == MCD_F64) return launch_apply<double>(op, nvec, (const double *)x, (double *)y, s);
+    if (dtype == MCD_F32) return launch_apply<float>(op, nvec, (const float *)x, (float *)y, s);
+    set_error("dtype %d is neither MCD_F64 nor MCD_F32", dtype);
+    return MCD_E_INVALID;
+}
+
+int apply_f64_fused(const mcd_op *op, const double *x, double *y, const double *sx_dev,
+                    int sx_mode, double *dot_out, hipStream_t s) {
+    const int64_t n = op->n;
+    if (op->storage == MCD_STORAGE_CSR) {
+        const int64_t nb = stream_blocks(op);
+        MCD_REQUIRE(dot_out == nullptr || nb <= op->max_partials, MCD_E_CAPACITY,
+                    "too many blocks for the reduction scratch");
+        hipLaunchKernelGGL((k_spmv_stream<double, 256>), dim3((unsigned)nb), dim3(256), 0, s, n,
+                           op->rows_per_block, op->d_rowptr, op->d_colw, op->d_model, op->d_diag,
+                           x, y, sx_dev, sx_mode, op->d_partials, op->d_counter, dot_out);
+        MCD_HIP(hipGetLastError());
+        return MCD_OK;
+    }
+    // On-the-fly: product, then a separate fused scale + dot.
+    MCD_TRY(launch_apply<double>(op, 1, x, y, s));
+    if (sx_dev != nullptr || dot_out != nullptr)
+        MCD_TRY(scale_dot(op, y, x, sx_dev, sx_mode, dot_out, s));
+    return MCD_OK;
+}
+
+}  // namespace mcd
+
+using namespace mcd;
+
+extern "C" int mcd_op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                             int32_t storage, int32_t validate, void *stream, mcd_op **out) {
+    MCD_REQUIRE(out != nullptr, MCD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    MCD_REQUIRE(n >= 0 && (n == 0 || keys_dev != nullptr), MCD_E_INVALID, "bad keys/n");
+    MCD_REQUIRE(storage >= MCD_STORAGE_AUTO && storage <= MCD_STORAGE_CSR, MCD_E_INVALID,
+                "storage %d unknown", storage);
+    hipStream_t s = (hipStream_t)stream;
+    const double t0 = now_ms();
+    mcd_op *op = new mcd_op();
+    memset(op, 0, sizeof(*op));
+    auto fail = [&](int rc) {
+        mcd_op_destroy(op);
+        return rc;
+    };
+    int rc = prepare_model(model, &op->hm);
+    if (rc < 0) return fail(rc);
+    if (hipGetDevice(&op->device) != hipSuccess) return fail(MCD_E_HIP);
+    op->n = n;
+    op->nnz = -1;
+#define CK(expr)                                                                             \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));                        \
+            return fail(MCD_E_HIP);                                                          \
+        }                                                                                    \
+    } while (0)
+    const int64_t nn = std::max<int64_t>(n, 1);
+    CK(hipMalloc(&op->d_model, sizeof(DevModel)));
+    CK(hipMemcpyAsync(op->d_model, &op->hm.dm, sizeof(DevModel), hipMemcpyHostToDevice, s));
+    CK(hipMalloc(&op->d_keys, nn * sizeof(uint64_t)));
+    if (n) CK(hipMemcpyAsync(op->d_keys, keys_dev, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    CK(hipMalloc(&op->d_diag, nn * sizeof(double)));
+    op->device_bytes = sizeof(DevModel) + nn * 16;
+    if (validate && n) {
+        int *bad = nullptr, hbad = 0;
+        CK(hipMalloc(&bad, sizeof(int)));
+        CK(hipMemsetAsync(bad, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_validate, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
+                           op->hm.dm.n_orb, bad);
+        CK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        CK(hipFree(bad));
+        if (hbad) {
+            set_error("keys are not sorted/unique or exceed n_orb bits");
+            return fail(MCD_E_SECTOR);
+        }
+    }
+    if (n) {
+        hipLaunchKernelGGL(k_diag, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
+                           op->d_model, op->d_diag);
+        CK(hipGetLastError());
+    }
+    // Hash index, load factor <= 1/4.
+    uint64_t cap = 16;
+    while (cap < (uint64_t)(4 * nn)) cap <<= 1;
+    op->hash_mask = cap - 1;
+    CK(hipMalloc(&op->d_hash, cap * sizeof(HashSlot)));
+    CK(hipMemsetAsync(op->d_hash, 0xff, cap * sizeof(HashSlot), s));
+    op->device_bytes += cap * sizeof(HashSlot);
+    if (n) {
+        hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
+                           op->d_hash, op->hash_mask);
+        CK(hipGetLastError());
+    }
+    // Reduction scratch.
+    op->max_partials = std::max<int64_t>(grid_for(n, 1) + 1024, 4096);
+    CK(hipMalloc(&op->d_partials, op->max_partials * sizeof(double)));
+    CK(hipMalloc(&op->d_counter, 8 * sizeof(unsigned int)));
+    CK(hipMemsetAsync(op->d_counter, 0, 8 * sizeof(unsigned int), s));
+    CK(hipMalloc(&op->d_scalars, 64 * sizeof(double)));
+    op->device_bytes += op->max_partials * sizeof(double);
+    // Storage choice.
+    const bool fmt_ok = n < (int64_t(1) << kColBits) && op->hm.ok_classes;
+    int st = storage;
+    if (st == MCD_STORAGE_CSR && !fmt_ok) {
+        set_error("packed CSR needs n < 2^26 and <= 32 distinct |t| (n = %lld)", (long long)n);
+        return fail(MCD_E_CAPACITY);
+    }
+    if (st == MCD_STORAGE_AUTO) {
+        size_t fr = 0, tot = 0;
+        CK(hipMemGetInfo(&fr, &tot));
+        // Upper bound of the CSR: every candidate hop kept.
+        const double est = (double)n * (8.0 + 4.0 * 2.0 * op->hm.dm.n_bonds);
+        st = (fmt_ok && est < 0.5 * (double)fr) ? MCD_STORAGE_CSR : MCD_STORAGE_ON_THE_FLY;
+    }
+    op->storage = st;
+    op->rows_per_block = 256;
+    if (st == MCD_STORAGE_CSR) {
+        rc = build_csr(op, s);
+        if (rc < 0) return fail(rc);
+    }
+    CK(hipStreamSynchronize(s));
+#undef CK
+    op->build_ms = now_ms() - t0;
+    *out = op;
+    return MCD_OK;
+}
+
+extern "C" void mcd_op_destroy(mcd_op *op) {
+    if (!op) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(op->device);
+    (void)hipDeviceSynchronize();
+    if (op->d_model) (void)hipFree(op->d_model);
+    if (op->d_keys) (void)hipFree(op->d_keys);
+    if (op->d_diag) (void)hipFree(op->d_diag);
+    if (op->d_hash) (void)hipFree(op->d_hash);
+    if (op->d_rowptr) (void)hipFree(op->d_rowptr);
+    if (op->d_colw) (void)hipFree(op->d_colw);
+    if (op->d_partials) (void)hipFree(op->d_partials);
+    if (op->d_counter) (void)hipFree(op->d_counter);
+    if (op->d_scalars) (void)hipFree(op->d_scalars);
+    (void)hipSetDevice(cur);
+    delete op;
+}
+
+extern "C" int mcd_op_info(const mcd_op *op, mcd_op_info_t *info) {
+    MCD_REQUIRE(op && info, MCD_E_INVALID, "op or info is NULL");
+    info->n = op->n;
+    info->nnz = op->storage == MCD_STORAGE_CSR ? op->nnz : -1;
+    info->storage = op->storage;
+    info->n_classes = op->hm.dm.n_classes;
+    info->rows_per_block = op->rows_per_block;
+    info->reserved = 0;
+    info->device_bytes = op->device_bytes;
+    info->build_ms = op->build_ms;
+    return MCD_OK;
+}
+
+extern "C" int mcd_hamiltonian_apply(const mcd_op *op, int32_t dtype, int32_t nvec,
+                                     const void *x_dev, void *y_dev, void *stream) {
+    MCD_REQUIRE(op != nullptr, MCD_E_INVALID, "op is NULL");
+    MCD_REQUIRE(op->n == 0 || (x_dev && y_dev), MCD_E_INVALID, "x or y is NULL");
+    MCD_REQUIRE(x_dev != y_dev || op->n == 0, MCD_E_INVALID, "x and y must not alias");
+    return apply_any(op, dtype, nvec, x_dev, y_dev, (hipStream_t)stream);
+}
+
+extern "C" int mcd_hamiltonian_diagonal(const mcd_op *op, double *diag_dev, void *stream) {
+    MCD_REQUIRE(op && (diag_dev || op->n == 0), MCD_E_INVALID, "op or diag is NULL");
+    if (op->n)
+        MCD_HIP(hipMemcpyAsync(diag_dev, op->d_diag, op->n * sizeof(double),
+                               hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return MCD_OK;
+}
+
+extern "C" int mcd_hamiltonian_connectivity(const mcd_op *op, int64_t row0, int64_t row1,
+                                            int64_t *rows_dev, int64_t *cols_dev,
+                                            double *vals_dev, int64_t cap, int64_t *count_out,
+                                            void *stream) {
+    MCD_REQUIRE(op && count_out, MCD_E_INVALID, "op or count_out is NULL");
+    MCD_REQUIRE(0 <= row0 && row0 <= row1 && row1 <= op->n, MCD_E_INVALID,
+                "row range [%lld, %lld) outside [0, %lld)", (long long)row0, (long long)row1,
+                (long long)op->n);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t m = row1 - row0;
+    *count_out = 0;
+    if (m == 0) return MCD_OK;
+    int64_t *cnt = nullptr;
+    MCD_HIP(hipMalloc(&cnt, m * sizeof(int64_t)));
+    hipLaunchKernelGGL(k_conn_count, dim3(grid_for(m, 256)), dim3(256), 0, s, row0, row1,
+                       op->d_keys, op->d_model, op->d_hash, op->hash_mask, cnt);
+    std::vector<int64_t> h(m);
+    MCD_HIP(hipMemcpyAsync(h.data(), cnt, m * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MCD_HIP(hipStreamSynchronize(s));
+    int64_t tot = 0;
+    for (int64_t i = 0; i < m; i++) {
+        const int64_t c = h[i];
+        h[i] = tot;
+        tot += c;
+    }
+    *count_out = tot;
+    if (tot > cap) {
+        (void)hipFree(cnt);
+        set_error("connectivity needs %lld entries, cap is %lld", (long long)tot, (long long)cap);
+        return MCD_E_CAPACITY;
+    }
+    MCD_REQUIRE(tot == 0 || (rows_dev && cols_dev && vals_dev), MCD_E_INVALID, "outputs NULL");
+    MCD_HIP(hipMemcpyAsync(cnt, h.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_conn_fill, dim3(grid_for(m, 256)), dim3(256), 0, s, row0, row1,
+                       op->d_keys, op->d_model, op->d_hash, op->hash_mask, cnt, rows_dev,
+                       cols_dev, vals_dev);
+    MCD_HIP(hipGetLastError());
+    MCD_HIP(hipStreamSynchronize(s));
+    MCD_HIP(hipFree(cnt));
+    return MCD_OK;
+}

@@ -1,0 +1,44 @@
+"""The C-ABI library loads and exports every entry point include/mcd.h declares
+(no GPU work: only calls that return before touching the device)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mcd.h")
+LIB = os.path.join(ROOT, "paper_2509_22975_amd", "libmcd.so")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcd_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared()
+    for n in ("mcd_basis_build", "mcd_op_create", "mcd_hamiltonian_apply", "mcd_lanczos_ground",
+              "mcd_band_lanczos_green", "mcd_last_error", "mcd_op_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.fail("libmcd.so not built: run python -m paper_2509_22975_amd.build")
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_argument_errors_without_device_work():
+    import paper_2509_22975_amd as mcd
+    L = mcd.lib()
+    assert L.mcd_version() >= 10000
+    # NULL output handle is rejected before any HIP call
+    rc = L.mcd_op_create(None, None, 0, 0, 0, None, None)
+    assert rc == -1
+    assert b"NULL" in L.mcd_last_error()
+    rc = L.mcd_lanczos_ground(None, None, None, None, None, None, None, None, None)
+    assert rc == -1

@@ -1,0 +1,147 @@
+"""GPU parity of mcd_band_lanczos_green (w_t cut, F~+-, start blocks, block
+Lanczos, resolvent) against the oracle's band Lanczos + Lehmann sums.
+
+Same Krylov space on both sides: the GPU's block step adds P = padded p
+directions, the oracle's band method one at a time, so max_dim = p * blocks
+per spin sector gives the same projected resolvent.  Float64 tolerance:
+1e-9 max |G| (both sides reorthogonalise fully; the resolvent at Matsubara
+frequencies is well conditioned, |z - E| >= pi/beta).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fock, green as gr, hamiltonian as ham, lanczos as lz, sampler
+from tests.gpu_common import log_case, require_gpu
+
+pytestmark = pytest.mark.gpu
+OM = W.matsubara(64, 50.0)
+
+
+def _gs(m, keys):
+    H = ham.build_csr(keys, m)
+    r = lz.lanczos_ground(H, lz.start_vector(keys, 11), tol=1e-13)
+    return r["e0"], r["psi0"]
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _oracle_G(keys, m, psi, e0, orbs, spins, blocks, w_t=1.0):
+    """Oracle G for a selection that may mix spins: per-spin band runs."""
+    p = len(orbs)
+    G = np.zeros((len(OM), p, p), complex)
+    for s in (0, 1):
+        sel = [q for q in range(p) if spins[q] == s]
+        if not sel:
+            continue
+        o = [orbs[q] for q in sel]
+        Gs = gr.green_mcd(keys, m, psi, e0, o, s, OM, max_dim=len(o) * blocks, w_t=w_t)
+        for i, qi in enumerate(sel):
+            for j, qj in enumerate(sel):
+                G[:, qi, qj] = Gs[:, i, j]
+    return G
+
+
+def _c1_chain():
+    c = W.config_c1()
+    m = c["model"]
+    k, _ = sampler.chain_c(m, W.neel_start(m), c["seed"], c["n_f"], c["burn_in"], c["max_steps"])
+    return m, k
+
+
+@pytest.mark.parametrize("sel", ["up4", "mixed8", "ragged3"])
+def test_green_c1_chain_vs_oracle(sel):
+    torch, mcd = require_gpu()
+    m, keys = _c1_chain()
+    orbs, spins = {"up4": ([0, 1, 2, 3], [0] * 4), "mixed8": ([0, 1, 2, 3] * 2, [0] * 4 + [1] * 4),
+                   "ragged3": ([1, 5, 6], [1, 0, 1])}[sel]
+    log_case("green_c1", sel=sel)
+    e0, psi = _gs(m, keys)
+    blocks = 30
+    Go = _oracle_G(keys, m, psi, e0, orbs, spins, blocks)
+    G, info = mcd.band_lanczos_green(m, mcd.keys_from_numpy(keys), torch.from_numpy(psi).cuda(),
+                                     e0, orbs, spins, OM, max_blocks=blocks)
+    assert _rel(G, Go) <= 1e-9
+
+
+def test_green_exhausted_equals_dense_definition():
+    """Small space run to exhaustion: G equals the dense Lehmann sum over the
+    truncated H~+- (the definition, Eqs. green_plus / green_minus)."""
+    torch, mcd = require_gpu()
+    m = W.chain(6, U=6.0, mu=3.0, pbc=True, n_up=3, n_dn=3)
+    keys = fock.sector_keys(6, 3, 3)
+    e0, psi = _gs(m, keys)
+    orbs, spins = [0, 1, 2, 4], [0, 0, 0, 0]
+    Gd = gr.green_dense(m, keys, psi[:, None], e0, orbs, 0, 1j * OM)
+    G, info = mcd.band_lanczos_green(m, mcd.keys_from_numpy(keys), torch.from_numpy(psi).cuda(),
+                                     e0, orbs, spins, OM, max_blocks=200)
+    assert _rel(G, Gd) <= 1e-9
+
+
+def test_green_free_fermions_closed_form():
+    torch, mcd = require_gpu()
+    m = W.chain(6, U=0.0, pbc=True, n_up=3, n_dn=3)
+    keys = fock.sector_keys(6, 3, 3)
+    e0, psi = _gs(m, keys)
+    h = np.zeros((6, 6))
+    for i, j, t in m.bonds:
+        h[i, j] += t
+        h[j, i] += t
+    G0 = np.array([np.linalg.inv(1j * w * np.eye(6) - h) for w in OM])
+    G, _ = mcd.band_lanczos_green(m, mcd.keys_from_numpy(keys), torch.from_numpy(psi).cuda(),
+                                  e0, list(range(6)), [1] * 6, OM, max_blocks=100)
+    assert np.max(np.abs(G - G0)) <= 1e-10
+
+
+def test_green_wt_truncation_vs_oracle():
+    torch, mcd = require_gpu()
+    m = W.config_c1()["model"]
+    keys = fock.sector_keys(8, 4, 4)
+    e0, psi = _gs(m, keys)
+    orbs, spins = [0, 2, 5], [0, 0, 0]
+    for wt in (0.9, 0.99):
+        log_case("green_wt", w_t=wt)
+        k2, _ = gr.truncate_wt(keys, psi, wt)
+        Go = _oracle_G(keys, m, psi, e0, orbs, spins, 25, w_t=wt)
+        G, info = mcd.band_lanczos_green(m, mcd.keys_from_numpy(keys),
+                                         torch.from_numpy(psi).cuda(), e0, orbs, spins, OM,
+                                         max_blocks=25, w_t=wt)
+        assert info.n_truncated == len(k2)
+        assert _rel(G, Go) <= 1e-9
+
+
+def test_green_impurity_p8_and_sum_rule():
+    """C3-shaped impurity model (2x2 + 8 baths, U = 8), chain basis, p = 8."""
+    torch, mcd = require_gpu()
+    m = W.impurity_plaquette_bath(3)
+    keys, _ = sampler.chain_c(m, W.neel_start(m), 9, 20000, 1000, 10**7)
+    e0, psi = _gs(m, keys)
+    orbs, spins = [0, 1, 2, 3] * 2, [0] * 4 + [1] * 4
+    blocks = 20
+    Go = _oracle_G(keys, m, psi, e0, orbs, spins, blocks)
+    G, info = mcd.band_lanczos_green(m, mcd.keys_from_numpy(keys), torch.from_numpy(psi).cuda(),
+                                     e0, orbs, spins, OM, max_blocks=blocks)
+    assert _rel(G, Go) <= 1e-9
+    # tail: i w G(i w) -> identity
+    Gt, _ = mcd.band_lanczos_green(m, mcd.keys_from_numpy(keys), torch.from_numpy(psi).cuda(),
+                                   e0, orbs, spins, np.array([1e7]), max_blocks=blocks)
+    assert np.max(np.abs(1j * 1e7 * Gt[0] - np.eye(8))) < 1e-5
+    # float32 Krylov blocks, float64 recurrence
+    G32, _ = mcd.band_lanczos_green(m, mcd.keys_from_numpy(keys), torch.from_numpy(psi).cuda(),
+                                    e0, orbs, spins, OM, max_blocks=blocks, precision="f32")
+    err = _rel(G32, Go)
+    print("[green] f32 rel err", err, flush=True)
+    assert err <= 1e-4
+
+
+def test_green_deflation_duplicate_selection():
+    torch, mcd = require_gpu()
+    m, keys = _c1_chain()
+    e0, psi = _gs(m, keys)
+    G, _ = mcd.band_lanczos_green(m, mcd.keys_from_numpy(keys), torch.from_numpy(psi).cuda(), e0,
+                                  [0, 0, 3], [0, 0, 0], OM, max_blocks=20)
+    Go = _oracle_G(keys, m, psi, e0, [0, 3], [0, 0], 20)
+    assert _rel(G[:, 0, 0], G[:, 1, 1]) < 1e-10
+    assert _rel(G[:, 0, 2], Go[:, 0, 1]) < 1e-8

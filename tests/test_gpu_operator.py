@@ -1,0 +1,209 @@
+"""GPU parity of the basis and of H~ x (C ABI) against the CPU oracle.
+
+Bit-exact: basis keys, chain step counts, connectivity (row, col) and signed
+elements.  Float64 products: max |y - y_ref| <= 1e-12 max |y_ref| (the
+summation order differs; each element is a sum of <= 2 n_bonds + 1 terms of
+magnitude |t| |x| or |d| |x|, so the rounding difference is a few ulp).
+Float32 products: 2e-6 relative (float accumulation of <= 257 terms).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fock, hamiltonian as ham, sampler
+from tests.gpu_common import log_case, random_model, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+MODELS = {
+    "c1": W.config_c1()["model"],
+    "ring8_mu4": W.chain(8, U=8.0, mu=4.0, pbc=True),
+    "sq3x2_tp": W.square(3, 2, tp=-0.3, U=8.0, pbc=True, n_up=3, n_dn=2),
+    "sq2x2_doubled": W.square(2, 2, U=8.0, pbc=True),
+    "rand_dup": random_model(7, dup=True),
+    "imp": W.impurity_plaquette_bath(3),
+}
+
+
+@pytest.mark.parametrize("name", ["c1", "ring8_mu4", "sq3x2_tp", "rand_dup"])
+def test_full_sector_keys(name):
+    torch, mcd = require_gpu()
+    m = MODELS[name]
+    log_case("full_sector_keys", model=name)
+    k, _ = mcd.basis_build(m, "full")
+    assert np.array_equal(mcd.keys_to_numpy(k), fock.sector_keys(m.n_orb, m.n_up, m.n_dn))
+
+
+def test_full_sector_keys_edges():
+    torch, mcd = require_gpu()
+    m = W.chain(12, U=8.0, mu=4.0)
+    for nu, nd in ((0, 0), (0, 3), (12, 5), (6, 6)):
+        log_case("full_sector_edges", n_up=nu, n_dn=nd)
+        k, _ = mcd.basis_build(m, "full", n_up=nu, n_dn=nd)
+        assert np.array_equal(mcd.keys_to_numpy(k), fock.sector_keys(12, nu, nd))
+
+
+def _chain_case(mcd, m, seed, n_f, burn, steps):
+    st = W.neel_start(m)
+    ko, so = sampler.chain_c(m, st, seed, n_f, burn, steps)
+    kg, sg = mcd.basis_build(m, "chain", start_key=st, seed=seed, beta_s=0.5, burn_in=burn,
+                             max_steps=steps, n_f=n_f)
+    return ko, so, mcd.keys_to_numpy(kg), sg
+
+
+@pytest.mark.parametrize("case", ["c1", "imp", "c1_short"])
+def test_chain_basis_bit_exact(case):
+    torch, mcd = require_gpu()
+    log_case("chain_basis", case=case)
+    if case == "c1":
+        c = W.config_c1()
+        ko, so, kg, sg = _chain_case(mcd, c["model"], c["seed"], c["n_f"], c["burn_in"],
+                                     c["max_steps"])
+    elif case == "imp":
+        ko, so, kg, sg = _chain_case(mcd, MODELS["imp"], 9, 30000, 1000, 10**7)
+    else:   # step cap reached before n_f
+        ko, so, kg, sg = _chain_case(mcd, MODELS["c1"], 4, 4900, 10, 2000)
+    assert so == sg
+    assert np.array_equal(ko, kg)
+
+
+def test_chain_basis_c2_full_size():
+    torch, mcd = require_gpu()
+    c = W.config_c2()
+    log_case("chain_basis_c2", n_f=c["n_f"])
+    ko, so, kg, sg = _chain_case(mcd, c["model"], c["seed"], c["n_f"], c["burn_in"],
+                                 c["max_steps"])
+    assert len(kg) == c["n_f"] and so == sg and np.array_equal(ko, kg)
+
+
+def _basis(name, mcd):
+    m = MODELS[name]
+    if name == "imp":
+        keys, _ = sampler.chain_c(m, W.neel_start(m), 9, 20000, 1000, 10**7)
+    elif name == "c1":
+        c = W.config_c1()
+        keys, _ = sampler.chain_c(m, W.neel_start(m), c["seed"], c["n_f"], c["burn_in"],
+                                  c["max_steps"])
+    else:
+        keys = fock.sector_keys(m.n_orb, m.n_up, m.n_dn)
+    return m, keys
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+@pytest.mark.parametrize("storage", ["csr", "otf"])
+def test_connectivity_bit_exact(name, storage):
+    torch, mcd = require_gpu()
+    m, keys = _basis(name, mcd)
+    log_case("connectivity", model=name, storage=storage, n=len(keys))
+    op = mcd.Operator(m, mcd.keys_from_numpy(keys), storage=storage)
+    r, c, v = op.connectivity()
+    order = np.lexsort((c, r))
+    ro, co, vo = ham.offdiag_pattern(keys, m)
+    assert np.array_equal(r[order], ro) and np.array_equal(c[order], co)
+    assert np.array_equal(v[order], vo)
+    # diagonal
+    d = op.diagonal().cpu().numpy()
+    assert np.max(np.abs(d - fock.diagonal(keys, m))) <= 1e-13 * max(1.0, np.abs(d).max())
+    op.close()
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+@pytest.mark.parametrize("storage", ["csr", "otf"])
+@pytest.mark.parametrize("nvec", [1, 2, 4, 8, 16])
+def test_apply_f64(name, storage, nvec):
+    torch, mcd = require_gpu()
+    m, keys = _basis(name, mcd)
+    log_case("apply_f64", model=name, storage=storage, nvec=nvec, n=len(keys))
+    H = ham.build_csr(keys, m)
+    x = W.random_vector(len(keys), 100 + nvec, nvec)
+    op = mcd.Operator(m, mcd.keys_from_numpy(keys), storage=storage)
+    y = op.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert _rel(y, H @ x) <= 1e-12
+    op.close()
+
+
+@pytest.mark.parametrize("storage", ["csr", "otf"])
+@pytest.mark.parametrize("nvec", [1, 8, 16])
+def test_apply_f32(storage, nvec):
+    torch, mcd = require_gpu()
+    m, keys = _basis("imp", mcd)
+    log_case("apply_f32", storage=storage, nvec=nvec)
+    H = ham.build_csr(keys, m)
+    x = W.random_vector(len(keys), 7, nvec).astype(np.float32)
+    op = mcd.Operator(m, mcd.keys_from_numpy(keys), storage=storage)
+    y = op.apply(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
+    assert _rel(y, H @ x.astype(np.float64)) <= 2e-6
+
+
+def test_apply_edges():
+    """Ragged and degenerate bases: 1 state, 2 states, no kept hops, sizes that
+    end mid-block, and a basis mixing two sectors (block diagonal)."""
+    torch, mcd = require_gpu()
+    m = MODELS["sq3x2_tp"]
+    full = fock.sector_keys(6, 3, 2)
+    rng = np.random.default_rng(3)
+    other = fock.sector_keys(6, 2, 2)
+    cases = {
+        "one": full[:1], "two": full[[0, -1]],
+        "ragged": np.sort(rng.choice(full, 257, replace=False)),
+        "ragged2": np.sort(rng.choice(full, 131, replace=False)),
+        "two_sectors": np.union1d(full[::2], other[::3]),
+    }
+    for name, keys in cases.items():
+        for storage in ("csr", "otf"):
+            log_case("apply_edges", case=name, storage=storage, n=len(keys))
+            H = ham.build_csr(keys, m)
+            x = W.random_vector(len(keys), 1)
+            op = mcd.Operator(m, mcd.keys_from_numpy(keys), storage=storage)
+            y = op.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+            assert _rel(y, H @ x) <= 1e-12, name
+            op.close()
+
+
+def test_invalid_keys_rejected():
+    torch, mcd = require_gpu()
+    m = MODELS["sq3x2_tp"]
+    full = fock.sector_keys(6, 3, 2)
+    bad = full[::-1].copy()
+    with pytest.raises(mcd.McdError):
+        mcd.Operator(m, mcd.keys_from_numpy(bad))
+    dup = np.concatenate([full[:5], full[4:6]])
+    with pytest.raises(mcd.McdError):
+        mcd.Operator(m, mcd.keys_from_numpy(dup))
+
+
+def test_apply_c2_full_size_sampled_rows():
+    """C2 at its full size (4x4 t-t', 4M chain states): every row of the GPU
+    product is produced by the timed kernel; 3000 seeded rows are checked
+    against the oracle's element definition, plus H = H^T via <x|Hy> = <Hx|y>."""
+    torch, mcd = require_gpu()
+    c = W.config_c2()
+    m = c["model"]
+    keys, _ = sampler.chain_c(m, W.neel_start(m), c["seed"], c["n_f"], c["burn_in"],
+                              c["max_steps"])
+    log_case("apply_c2", n=len(keys))
+    x = W.random_vector(len(keys), 21)
+    rows = np.sort(np.random.default_rng(5).choice(len(keys), 3000, replace=False))
+    ref = ham.apply_rows(keys, rows, m, x)
+    kd = mcd.keys_from_numpy(keys)
+    for storage in ("csr", "otf"):
+        op = mcd.Operator(m, kd, storage=storage)
+        xt = torch.from_numpy(x).cuda()
+        y = op.apply(xt)
+        assert _rel(y.cpu().numpy()[rows], ref) <= 1e-12
+        x2 = torch.from_numpy(W.random_vector(len(keys), 22)).cuda()
+        y2 = op.apply(x2)
+        a, b = float(torch.dot(x2, y)), float(torch.dot(xt, y2))
+        assert abs(a - b) <= 1e-11 * max(abs(a), 1.0)
+        if storage == "csr":
+            info = op.info()
+            assert info["nnz"] > 0
+            print("[c2] nnz", info["nnz"], "rows/block", info["rows_per_block"], flush=True)
+        op.close()
