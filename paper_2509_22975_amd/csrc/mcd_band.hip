@@ -61,12 +61,11 @@ __global__ void k_gather_kept(int64_t m, const uint32_t *__restrict__ rows,
 }
 
 __global__ __launch_bounds__(BS) void k_norm2(int64_t n, const double *__restrict__ v,
-                                              double *__restrict__ partials,
-                                              unsigned int *counter, double *__restrict__ out) {
+                                              double *__restrict__ partials) {
     double acc = 0.0;
     for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < n; r += (int64_t)gridDim.x * BS)
         acc += v[r] * v[r];
-    grid_sum_last<BS>(block_sum<BS>(acc), gridDim.x, partials, counter, out);
+    store_partial<BS>(block_sum<BS>(acc), partials);
 }
 
 __global__ void k_scale_by(int64_t n, double *__restrict__ v, const double *__restrict__ nrm2) {
@@ -677,8 +676,9 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
     }
     hipLaunchKernelGGL(k_gather_kept, dim3(gridn(n_keep, 256)), dim3(256), 0, s, n_keep, kept,
                        keys_dev, psi0_dev, keys_t, psi_t);
-    hipLaunchKernelGGL(k_norm2, dim3(std::min<unsigned>(gridn(n_keep, BS), 2048)), dim3(BS), 0, s,
-                       n_keep, psi_t, scr, cnt, scr + 4096);
+    const unsigned nbn = std::min<unsigned>(gridn(n_keep, BS), 2048);
+    hipLaunchKernelGGL(k_norm2, dim3(nbn), dim3(BS), 0, s, n_keep, psi_t, scr);
+    hipLaunchKernelGGL((k_finalize_sum<BS>), dim3(1), dim3(BS), 0, s, (int)nbn, scr, scr + 4096);
     hipLaunchKernelGGL(k_scale_by, dim3(gridn(n_keep, 256)), dim3(256), 0, s, n_keep, psi_t,
                        scr + 4096);
     CK(hipGetLastError());

@@ -102,6 +102,9 @@ struct mcd_op {
     unsigned int *d_counter;   // last-block counters [8]
     double *d_scalars;         // [64]
     int64_t max_partials;
+    // grow-only solver workspace (Krylov store etc.), freed with the operator
+    void *ws;
+    size_t ws_bytes;
 };
 
 namespace mcd {
@@ -121,6 +124,10 @@ int apply_f64_fused(const mcd_op *op, const double *x, double *y, const double *
 int scale_dot(const mcd_op *op, double *y, const double *x, const double *sx_dev, int sx_mode,
               double *dot_out, hipStream_t s);
 int apply_any(const mcd_op *op, int dtype, int nvec, const void *x, void *y, hipStream_t s);
+
+// Solver workspace of at least `bytes` held by the operator (reallocated
+// only when it grows).  Not thread-safe per operator.
+int op_workspace(const mcd_op *op, size_t bytes, void **ptr);
 
 // Deterministic dot product a . b into *out_dev (mcd_lanczos.hip).
 int dev_dot(const mcd_op *op, const double *a, const double *b, int64_t n, double *out_dev,

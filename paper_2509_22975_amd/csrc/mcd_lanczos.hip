@@ -49,19 +49,17 @@ __global__ void k_start_vector(int64_t n, const uint64_t *__restrict__ keys, uin
 
 __global__ __launch_bounds__(BS) void k_dot(int64_t n, const double *__restrict__ a,
                                             const double *__restrict__ b,
-                                            double *__restrict__ partials, unsigned int *counter,
-                                            double *__restrict__ out) {
+                                            double *__restrict__ partials) {
     double acc = 0.0;
     for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < n; r += (int64_t)gridDim.x * BS)
         acc += a[r] * b[r];
-    grid_sum_last<BS>(block_sum<BS>(acc), gridDim.x, partials, counter, out);
+    store_partial<BS>(block_sum<BS>(acc), partials);
 }
 
 __global__ __launch_bounds__(BS) void k_scale_dot(int64_t n, double *__restrict__ y,
                                                   const double *__restrict__ x,
                                                   const double *__restrict__ sx_dev, int sx_mode,
-                                                  double *__restrict__ partials,
-                                                  unsigned int *counter, double *__restrict__ out) {
+                                                  double *__restrict__ partials) {
     const double sx = scale_from(sx_dev, sx_mode);
     double acc = 0.0;
     for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < n;
@@ -70,7 +68,7 @@ __global__ __launch_bounds__(BS) void k_scale_dot(int64_t n, double *__restrict_
         y[r] = v;
         acc += x[r] * sx * v;
     }
-    if (out != nullptr) grid_sum_last<BS>(block_sum<BS>(acc), gridDim.x, partials, counter, out);
+    if (partials != nullptr) store_partial<BS>(block_sum<BS>(acc), partials);
 }
 
 // u_next = y - (a_k / ||u_k||) u_k - (||u_k|| / ||u_{k-1}||) u_{k-1};
@@ -78,7 +76,7 @@ __global__ __launch_bounds__(BS) void k_scale_dot(int64_t n, double *__restrict_
 __global__ __launch_bounds__(BS) void k_lanczos_update(
     int64_t n, int k, const double *__restrict__ y, const double *__restrict__ uk,
     const double *__restrict__ ukm1, double *__restrict__ unext, const double *__restrict__ alpha,
-    double *__restrict__ nrm2, double *__restrict__ partials, unsigned int *counter) {
+    const double *__restrict__ nrm2, double *__restrict__ partials) {
     const double ik = scale_from(&nrm2[k], 1);
     const double c1 = alpha[k] * ik;
     const double c2 = (k > 0) ? sqrt(nrm2[k]) * scale_from(&nrm2[k - 1], 1) : 0.0;
@@ -90,7 +88,7 @@ __global__ __launch_bounds__(BS) void k_lanczos_update(
         unext[r] = w;
         acc += w * w;
     }
-    grid_sum_last<BS>(block_sum<BS>(acc), gridDim.x, partials, counter, &nrm2[k + 1]);
+    store_partial<BS>(block_sum<BS>(acc), partials);
 }
 
 // psi[r] = sum_k c_k U[k][r] (c_k = s_k / ||u_k||), one pass over the store.
@@ -124,8 +122,9 @@ __global__ __launch_bounds__(BS) void k_scale(int64_t n, double *__restrict__ v,
 
 int dev_dot(const mcd_op *op, const double *a, const double *b, int64_t n, double *out_dev,
             hipStream_t s) {
-    hipLaunchKernelGGL(k_dot, dim3(nblk(n)), dim3(BS), 0, s, n, a, b, op->d_partials,
-                       op->d_counter + 1, out_dev);
+    hipLaunchKernelGGL(k_dot, dim3(nblk(n)), dim3(BS), 0, s, n, a, b, op->d_partials);
+    hipLaunchKernelGGL((k_finalize_sum<BS>), dim3(1), dim3(BS), 0, s, (int)nblk(n),
+                       op->d_partials, out_dev);
     MCD_HIP(hipGetLastError());
     return MCD_OK;
 }
@@ -133,7 +132,10 @@ int dev_dot(const mcd_op *op, const double *a, const double *b, int64_t n, doubl
 int scale_dot(const mcd_op *op, double *y, const double *x, const double *sx_dev, int sx_mode,
               double *dot_out, hipStream_t s) {
     hipLaunchKernelGGL(k_scale_dot, dim3(nblk(op->n)), dim3(BS), 0, s, op->n, y, x, sx_dev,
-                       sx_mode, op->d_partials, op->d_counter + 1, dot_out);
+                       sx_mode, dot_out ? op->d_partials : nullptr);
+    if (dot_out)
+        hipLaunchKernelGGL((k_finalize_sum<BS>), dim3(1), dim3(BS), 0, s, (int)nblk(op->n),
+                           op->d_partials, dot_out);
     MCD_HIP(hipGetLastError());
     return MCD_OK;
 }
@@ -144,7 +146,9 @@ static int lanczos_step(const mcd_op *op, int k, const double *uk, const double 
                         hipStream_t s) {
     MCD_TRY(apply_f64_fused(op, uk, y, &d_nrm2[k], 1, &d_alpha[k], s));
     hipLaunchKernelGGL(k_lanczos_update, dim3(nblk(op->n)), dim3(BS), 0, s, op->n, k, y, uk,
-                       ukm1, unext, d_alpha, d_nrm2, op->d_partials, op->d_counter + 2);
+                       ukm1, unext, d_alpha, d_nrm2, op->d_partials);
+    hipLaunchKernelGGL((k_finalize_sum<BS>), dim3(1), dim3(BS), 0, s, (int)nblk(op->n),
+                       op->d_partials, &d_nrm2[k + 1]);
     MCD_HIP(hipGetLastError());
     return MCD_OK;
 }
@@ -173,18 +177,22 @@ extern "C" int mcd_lanczos_ground(const mcd_op *op, const mcd_lanczos_cfg *cfg,
     const int maxit = (int)std::min<int64_t>(cfg->max_iter, n);
     const int every = std::max(1, cfg->check_every);
 
-    // Vector storage: the whole Krylov store if it fits half the free HBM.
+    // Vector storage: the whole Krylov store if it fits half the free HBM
+    // (the operator's workspace is reused between calls).
     size_t fr = 0, tot = 0;
     MCD_HIP(hipMemGetInfo(&fr, &tot));
-    bool store = cfg->store_vectors != 0 &&
-                 (double)(maxit + 1) * (double)n * 8.0 < 0.5 * (double)fr;
-    double *U = nullptr, *y = nullptr, *d_sc = nullptr;
+    const size_t have = op->ws_bytes;
+    const size_t sc_bytes = (3 * (size_t)maxit + 4) * sizeof(double);
+    const size_t need_store = ((size_t)(maxit + 2) * n) * sizeof(double) + sc_bytes;
+    bool store = cfg->store_vectors != 0 && (double)need_store < 0.5 * ((double)fr + have);
     const int64_t nvecs = store ? (maxit + 1) : 3;
-    auto cleanup = [&]() {
-        if (U) (void)hipFree(U);
-        if (y) (void)hipFree(y);
-        if (d_sc) (void)hipFree(d_sc);
-    };
+    const size_t need = ((size_t)(nvecs + 1) * n) * sizeof(double) + sc_bytes;
+    void *wsp = nullptr;
+    MCD_TRY(op_workspace(op, need, &wsp));
+    double *U = (double *)wsp;
+    double *y = U + nvecs * n;
+    double *d_sc = y + n;
+    auto cleanup = [&]() {};
 #define CK(expr)                                                                   \
     do {                                                                           \
         hipError_t e_ = (expr);                                                    \
@@ -202,10 +210,6 @@ extern "C" int mcd_lanczos_ground(const mcd_op *op, const mcd_lanczos_cfg *cfg,
             return rc_;        \
         }                      \
     } while (0)
-    CK(hipMalloc(&U, nvecs * n * sizeof(double)));
-    CK(hipMalloc(&y, n * sizeof(double)));
-    // d_sc: alpha[maxit], nrm2[maxit + 1], coefficients[maxit], psi norm^2
-    CK(hipMalloc(&d_sc, (3 * (size_t)maxit + 4) * sizeof(double)));
     double *d_alpha = d_sc, *d_nrm2 = d_sc + maxit, *d_coef = d_sc + 2 * maxit + 1;
     double *d_pn = d_sc + 3 * maxit + 2;
     auto vec = [&](int k) -> double * { return U + (store ? (int64_t)k : (int64_t)(k % 3)) * n; };

@@ -128,63 +128,73 @@ __global__ void k_block_max(int64_t n, int R, const int64_t *__restrict__ rowptr
 }
 
 // ---------------------------------------------------------------------------
-// One-vector CSR product.  A workgroup owns rows [r0, r0 + R); its nonzeros
-// are contiguous, so phase 1 reads them fully coalesced (4 words per thread
-// in flight), gathers x and writes the signed products to LDS; phase 2 adds
-// each row's run in entry order after d_r x_r.  Optional fused dot product
-// sum_r (sx x_r) y_r reduced by the last workgroup.
+// One-vector CSR product.  A workgroup owns rows [r0, r0 + R) whose nonzeros
+// (<= kStreamNnzMax) are contiguous.  The kernel is latency bound, so every
+// thread first issues all its loads: its rows' pointers, diagonal and x_r,
+// then up to DEPTH packed words (coalesced), then the DEPTH gathers of x;
+// the signed products go to LDS and each row adds its run in entry order
+// after d_r x_r.  Optional partial of sum_r (sx x_r) y_r per workgroup.
 template <typename T, int BS>
 __global__ __launch_bounds__(BS) void k_spmv_stream(
     int64_t n, int R, const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ colw,
     const DevModel *__restrict__ m, const double *__restrict__ diag, const T *__restrict__ x,
     T *__restrict__ y, const double *__restrict__ sx_dev, int sx_mode,
-    double *__restrict__ partials, unsigned int *counter, double *__restrict__ dot_out) {
+    double *__restrict__ partials) {
+    constexpr int DEPTH = kStreamNnzMax / BS;
     __shared__ T prod[kStreamNnzMax];
-    const double sx = scale_from(sx_dev, sx_mode);
     __shared__ T vtab[kMaxClasses];
-    if (threadIdx.x < kMaxClasses) vtab[threadIdx.x] = (T)m->vtab[threadIdx.x];
+    const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * R;
     const int64_t r1 = min(r0 + (int64_t)R, n);
-    const int64_t e0 = rowptr[r0], e1 = rowptr[r1];
-    const int cnt = (int)(e1 - e0);
-    __syncthreads();
+    const int64_t r = r0 + tid;
+    const bool own = tid < R && r < r1;
+    int64_t rs = 0, re = 0;
+    double dr = 0.0;
+    T xr = (T)0;
+    if (own) {
+        rs = rowptr[r];
+        re = rowptr[r + 1];
+        dr = diag[r];
+        xr = x[r];
+    }
+    if (tid < kMaxClasses) vtab[tid] = (T)m->vtab[tid];
+    const int64_t e0 = rowptr[r0];
+    const int cnt = (int)(rowptr[r1] - e0);
     const uint32_t *__restrict__ cw = colw + e0;
-    int e = threadIdx.x;
-    for (; e + 3 * BS < cnt; e += 4 * BS) {
-        const uint32_t w0 = cw[e], w1 = cw[e + BS], w2 = cw[e + 2 * BS], w3 = cw[e + 3 * BS];
-        const T x0 = x[w0 & kColMask], x1 = x[w1 & kColMask];
-        const T x2 = x[w2 & kColMask], x3 = x[w3 & kColMask];
-        const T v0 = vtab[(w0 >> kColBits) & 31], v1 = vtab[(w1 >> kColBits) & 31];
-        const T v2 = vtab[(w2 >> kColBits) & 31], v3 = vtab[(w3 >> kColBits) & 31];
-        prod[e] = (w0 >> 31) ? -(v0 * x0) : v0 * x0;
-        prod[e + BS] = (w1 >> 31) ? -(v1 * x1) : v1 * x1;
-        prod[e + 2 * BS] = (w2 >> 31) ? -(v2 * x2) : v2 * x2;
-        prod[e + 3 * BS] = (w3 >> 31) ? -(v3 * x3) : v3 * x3;
+    uint32_t w[DEPTH];
+    T xv[DEPTH];
+#pragma unroll
+    for (int j = 0; j < DEPTH; j++) {
+        const int e = tid + j * BS;
+        w[j] = (e < cnt) ? cw[e] : 0u;
     }
-    for (; e < cnt; e += BS) {
-        const uint32_t w = cw[e];
-        const T xv = x[w & kColMask];
-        const T v = vtab[(w >> kColBits) & 31];
-        prod[e] = (w >> 31) ? -(v * xv) : v * xv;
+#pragma unroll
+    for (int j = 0; j < DEPTH; j++) {
+        const int e = tid + j * BS;
+        xv[j] = (e < cnt) ? x[w[j] & kColMask] : (T)0;
     }
     __syncthreads();
-    double dot = 0.0;
-    for (int i = threadIdx.x; i < R; i += BS) {
-        const int64_t r = r0 + i;
-        if (r < r1) {
-            const int s = (int)(rowptr[r] - e0), t = (int)(rowptr[r + 1] - e0);
-            const T xr = x[r];
-            T acc = (T)diag[r] * xr;
-            for (int k = s; k < t; k++) acc += prod[k];
-            acc = acc * (T)sx;
-            y[r] = acc;
-            dot += (double)xr * sx * (double)acc;
+#pragma unroll
+    for (int j = 0; j < DEPTH; j++) {
+        const int e = tid + j * BS;
+        if (e < cnt) {
+            const T v = vtab[(w[j] >> kColBits) & 31];
+            prod[e] = (w[j] >> 31) ? -(v * xv[j]) : v * xv[j];
         }
     }
-    if (dot_out != nullptr) {
-        const double bsum = block_sum<BS>(dot);
-        grid_sum_last<BS>(bsum, gridDim.x, partials, counter, dot_out);
+    __syncthreads();
+    const double sx = scale_from(sx_dev, sx_mode);
+    double dot = 0.0;
+    if (own) {
+        const int s0 = (int)(rs - e0), s1 = (int)(re - e0);
+        T acc = (T)dr * xr;
+#pragma unroll 4
+        for (int k = s0; k < s1; k++) acc += prod[k];
+        acc = acc * (T)sx;
+        y[r] = acc;
+        dot = (double)xr * sx * (double)acc;
     }
+    if (partials != nullptr) store_partial<BS>(block_sum<BS>(dot), partials);
 }
 
 // nvec lanes per row: lane k accumulates column k of the block.  CSR words
@@ -307,8 +317,7 @@ static int launch_apply(const mcd_op *op, int nvec, const T *x, T *y, hipStream_
     if (!otf && nvec == 1) {
         hipLaunchKernelGGL((k_spmv_stream<T, 256>), dim3((unsigned)stream_blocks(op)), dim3(256),
                            0, s, n, op->rows_per_block, op->d_rowptr, op->d_colw, op->d_model,
-                           op->d_diag, x, y, (const double *)nullptr, 0, (double *)nullptr,
-                           (unsigned int *)nullptr, (double *)nullptr);
+                           op->d_diag, x, y, (const double *)nullptr, 0, (double *)nullptr);
         MCD_HIP(hipGetLastError());
         return MCD_OK;
     }
@@ -339,6 +348,19 @@ static int launch_apply(const mcd_op *op, int nvec, const T *x, T *y, hipStream_
     return MCD_OK;
 }
 
+int op_workspace(const mcd_op *op_c, size_t bytes, void **ptr) {
+    mcd_op *op = const_cast<mcd_op *>(op_c);
+    if (op->ws_bytes < bytes) {
+        if (op->ws) MCD_HIP(hipFree(op->ws));
+        op->ws = nullptr;
+        op->ws_bytes = 0;
+        MCD_HIP(hipMalloc(&op->ws, bytes));
+        op->ws_bytes = bytes;
+    }
+    *ptr = op->ws;
+    return MCD_OK;
+}
+
 int apply_any(const mcd_op *op, int dtype, int nvec, const void *x, void *y, hipStream_t s) {
     if (dtype == MCD_F64) return launch_apply<double>(op, nvec, (const double *)x, (double *)y, s);
     if (dtype == MCD_F32) return launch_apply<float>(op, nvec, (const float *)x, (float *)y, s);
@@ -355,8 +377,13 @@ int apply_f64_fused(const mcd_op *op, const double *x, double *y, const double *
                     "too many blocks for the reduction scratch");
         hipLaunchKernelGGL((k_spmv_stream<double, 256>), dim3((unsigned)nb), dim3(256), 0, s, n,
                            op->rows_per_block, op->d_rowptr, op->d_colw, op->d_model, op->d_diag,
-                           x, y, sx_dev, sx_mode, op->d_partials, op->d_counter, dot_out);
+                           x, y, sx_dev, sx_mode, dot_out ? op->d_partials : nullptr);
         MCD_HIP(hipGetLastError());
+        if (dot_out) {
+            hipLaunchKernelGGL((k_finalize_sum<1024>), dim3(1), dim3(1024), 0, s, (int)nb,
+                               op->d_partials, dot_out);
+            MCD_HIP(hipGetLastError());
+        }
         return MCD_OK;
     }
     // On-the-fly: product, then a separate fused scale + dot.
@@ -485,6 +512,7 @@ extern "C" void mcd_op_destroy(mcd_op *op) {
     if (op->d_partials) (void)hipFree(op->d_partials);
     if (op->d_counter) (void)hipFree(op->d_counter);
     if (op->d_scalars) (void)hipFree(op->d_scalars);
+    if (op->ws) (void)hipFree(op->ws);
     (void)hipSetDevice(cur);
     delete op;
 }

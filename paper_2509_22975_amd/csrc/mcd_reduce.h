@@ -40,33 +40,33 @@ __device__ __forceinline__ double block_sum(double v) {
     return r;
 }
 
-// Grid-wide sum by the "last block finishes" pattern: every block deposits
-// its partial, the block that arrives last adds all partials in index order
-// and writes *out.  Deterministic for a fixed grid.  `counter` must be zero
-// on entry and is zero again on exit.  Every thread of every block calls it
-// with its block's value in thread 0.
+// Grid-wide sums are two-phase: every workgroup stores its partial (thread 0)
+// and a one-workgroup kernel adds the partials in index order.  The kernel
+// boundary orders the stores; no fences or atomics, deterministic for a fixed
+// grid.  (A "last workgroup finishes" scheme needs an agent-scope release
+// fence per workgroup, which on CDNA writes back the L2 and costs far more
+// than the extra launch.)
 template <int BS>
-__device__ __forceinline__ void grid_sum_last(double block_val, int nblocks, double *partials,
-                                              unsigned int *counter, double *out) {
-    __shared__ int is_last;
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x] = block_val;
-        __threadfence();
-        unsigned int prev = atomicAdd(counter, 1u);
-        is_last = (prev == (unsigned int)nblocks - 1u);
+__device__ __forceinline__ void store_partial(double block_val, double *partials) {
+    if (threadIdx.x == 0) partials[blockIdx.x] = block_val;
+}
+
+// out[0] = sum_i partials[i]: one workgroup, four independent accumulators
+// per thread so the loads overlap; fixed order.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_finalize_sum(int n, const double *__restrict__ partials,
+                                                     double *__restrict__ out) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = threadIdx.x;
+    for (; i + 3 * BS < n; i += 4 * BS) {
+        s0 += partials[i];
+        s1 += partials[i + BS];
+        s2 += partials[i + 2 * BS];
+        s3 += partials[i + 3 * BS];
     }
-    __syncthreads();
-    if (is_last) {
-        __threadfence();
-        double s = 0.0;
-        for (int i = threadIdx.x; i < nblocks; i += BS)
-            s += __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s = block_sum<BS>(s);
-        if (threadIdx.x == 0) {
-            *out = s;
-            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    for (; i < n; i += BS) s0 += partials[i];
+    const double s = block_sum<BS>((s0 + s1) + (s2 + s3));
+    if (threadIdx.x == 0) *out = s;
 }
 
 }  // namespace mcd
