@@ -139,12 +139,21 @@ typedef struct mcd_op_info_t {
     int32_t storage;          /* resolved storage */
     int32_t n_classes;        /* distinct |t| amplitudes */
     int32_t rows_per_block;   /* CSR stream kernel row block */
-    int32_t reserved;
+    int32_t kernel;           /* one-vector CSR kernel: 1 stream, 2 merge-path */
     int64_t device_bytes;     /* device memory held by the operator */
     double build_ms;          /* time of index + CSR build */
 } mcd_op_info_t;
 
 int mcd_op_info(const mcd_op *op, mcd_op_info_t *info);
+
+/* Select the kernel of one-vector CSR products (y = H~ x with nvec = 1):
+ *   1 = stream: one row block per workgroup, nonzeros staged through LDS;
+ *   2 = merge-path: persistent workgroups over chunks of (nonzeros + rows),
+ *       next chunk prefetched while the current one is reduced.
+ * Both give the same result up to summation order.  At creation a CSR
+ * operator times both on its own matrix and keeps the faster one.
+ * MCD_E_INVALID for other values or an on-the-fly operator. */
+int mcd_op_set_kernel(mcd_op *op, int32_t kernel);
 
 /* ---------------------------------------------------------------------------
  * mcd_hamiltonian_apply -- y = H~ x (the product every Lanczos step repeats,

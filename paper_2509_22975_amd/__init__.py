@@ -24,6 +24,7 @@ MCD_OK, MCD_NOCONV = 0, 1
 STORAGE = {"auto": 0, "on_the_fly": 1, "otf": 1, "csr": 2}
 STORAGE_NAME = {0: "auto", 1: "on_the_fly", 2: "csr"}
 DTYPE = {"f64": 0, "f32": 1}
+KERNEL_NAME = {1: "stream", 2: "merge"}
 
 P = ctypes.POINTER
 c_i32, c_i64, c_u64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
@@ -42,7 +43,7 @@ class McdBasisCfg(ctypes.Structure):
 
 class McdOpInfo(ctypes.Structure):
     _fields_ = [("n", c_i64), ("nnz", c_i64), ("storage", c_i32), ("n_classes", c_i32),
-                ("rows_per_block", c_i32), ("reserved", c_i32), ("device_bytes", c_i64),
+                ("rows_per_block", c_i32), ("kernel", c_i32), ("device_bytes", c_i64),
                 ("build_ms", c_dbl)]
 
 
@@ -82,6 +83,7 @@ def lib():
     L.mcd_op_destroy.argtypes = [c_vp]
     L.mcd_op_destroy.restype = None
     L.mcd_op_info.argtypes = [c_vp, P(McdOpInfo)]
+    L.mcd_op_set_kernel.argtypes = [c_vp, c_i32]
     L.mcd_hamiltonian_apply.argtypes = [c_vp, c_i32, c_i32, c_vp, c_vp, c_vp]
     L.mcd_hamiltonian_diagonal.argtypes = [c_vp, c_vp, c_vp]
     L.mcd_hamiltonian_connectivity.argtypes = [c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_i64,
@@ -92,7 +94,7 @@ def lib():
         L.mcd_band_lanczos_green.argtypes = [P(McdModel), c_vp, c_i64, c_vp, c_dbl, c_i32,
                                              P(c_i32), P(c_i32), c_i32, P(c_dbl), P(McdBandCfg),
                                              P(c_dbl), P(c_dbl), P(c_dbl), P(McdSolveInfo), c_vp]
-    for name in ("mcd_basis_build", "mcd_op_create", "mcd_op_info", "mcd_hamiltonian_apply",
+    for name in ("mcd_basis_build", "mcd_op_create", "mcd_op_info", "mcd_op_set_kernel", "mcd_hamiltonian_apply",
                  "mcd_hamiltonian_diagonal", "mcd_hamiltonian_connectivity", "mcd_lanczos_ground",
                  "mcd_band_lanczos_green"):
         if hasattr(L, name):
@@ -197,8 +199,13 @@ class Operator:
         i = McdOpInfo()
         _check(lib().mcd_op_info(self.handle, ctypes.byref(i)), "mcd_op_info")
         return dict(n=i.n, nnz=i.nnz, storage=STORAGE_NAME[i.storage], n_classes=i.n_classes,
-                    rows_per_block=i.rows_per_block, device_bytes=i.device_bytes,
-                    build_ms=i.build_ms)
+                    rows_per_block=i.rows_per_block, kernel=KERNEL_NAME.get(i.kernel, "none"),
+                    device_bytes=i.device_bytes, build_ms=i.build_ms)
+
+    def set_kernel(self, name: str):
+        """Force the one-vector CSR kernel: 'stream' or 'merge'."""
+        _check(lib().mcd_op_set_kernel(self.handle, {"stream": 1, "merge": 2}[name]),
+               "mcd_op_set_kernel")
 
     def apply(self, x, out=None):
         """y = H~ x; x is (n,) or (n, nvec) float64/float32 on the device."""

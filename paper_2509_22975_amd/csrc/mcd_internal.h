@@ -44,6 +44,12 @@ constexpr uint32_t kColBits = 26;            // packed CSR: column bits
 constexpr uint32_t kColMask = (1u << kColBits) - 1u;
 constexpr int kMaxClasses = 32;              // packed CSR: distinct |t| values
 constexpr int kStreamNnzMax = 4096;          // LDS products per stream block
+constexpr int kMergeBS = 256;                // merge-path SpMV: threads per workgroup
+constexpr int kMergeDepth = 8;               // nonzeros per thread per chunk
+constexpr int kMergeK = kMergeBS * kMergeDepth;  // path items (nonzeros + 9 per row) per chunk
+constexpr int kMergeRowCost = 9;             // so a chunk ends < kMergeBS rows
+
+enum { KERNEL_STREAM = 1, KERNEL_MERGE = 2 };
 
 // One hopping bond with i < j, prepared for bit arithmetic.
 struct DevBond {
@@ -105,6 +111,14 @@ struct mcd_op {
     // grow-only solver workspace (Krylov store etc.), freed with the operator
     void *ws;
     size_t ws_bytes;
+    // merge-path SpMV: chunk split points and carries
+    int32_t kernel;            // KERNEL_STREAM or KERNEL_MERGE (one-vector CSR)
+    int32_t merge_grid;        // persistent workgroups
+    int64_t nchunks;
+    int64_t *d_split_i, *d_split_j;   // [nchunks + 1]
+    double *d_carry;                  // [nchunks]
+    int64_t *d_carry_row;             // [nchunks]
+    double tune_ms[3];                // measured per-apply time per kernel
 };
 
 namespace mcd {

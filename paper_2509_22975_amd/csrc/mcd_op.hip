@@ -197,6 +197,168 @@ __global__ __launch_bounds__(BS) void k_spmv_stream(
     if (partials != nullptr) store_partial<BS>(block_sum<BS>(dot), partials);
 }
 
+// ---------------------------------------------------------------------------
+// One-vector CSR product, merge-path form.  The "path" of the matrix is the
+// sequence (nonzeros of row 0, end of row 0, nonzeros of row 1, ...), a row
+// end costing kMergeRowCost items; chunk c owns the items [c K, (c+1) K), so a
+// chunk holds <= K nonzeros and ends < kMergeBS rows whatever the row lengths.
+// Split points (rows ended, nonzeros consumed) are found once at build time.
+// A persistent grid walks the chunks; while the products of chunk c are
+// reduced, the packed words and row data of chunk c + grid are already in
+// flight (their addresses do not depend on chunk c), which hides the load
+// latency that bounds a one-chunk-per-workgroup kernel.  A row split across
+// two chunks is finished by the first chunk that ends it; the other chunk's
+// partial (its "carry") is added by k_merge_fixup, so every y_r is a fixed-
+// order sum.  Row lengths must stay below K - kMergeRowCost (they are at
+// most 2 n_bonds <= 1024 here).
+__global__ void k_merge_splits(int64_t n, int64_t nch, const int64_t *__restrict__ rowptr,
+                               int64_t *__restrict__ si, int64_t *__restrict__ sj) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > nch) return;
+    const int64_t nnz = rowptr[n];
+    if (c == nch) {
+        si[c] = n;
+        sj[c] = nnz;
+        return;
+    }
+    const int64_t d = c * (int64_t)kMergeK;
+    // largest i in [0, n] with cost(i) = R i + rowptr[i] <= d
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if ((int64_t)kMergeRowCost * mid + rowptr[mid] <= d)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    si[c] = lo;
+    sj[c] = (lo == n) ? nnz : min(d - (int64_t)kMergeRowCost * lo, rowptr[lo + 1]);
+}
+
+template <typename T>
+struct MergeChunk {
+    int64_t i0, i1, j0, j1;
+    uint32_t w[kMergeDepth];
+    int64_t rs, re;
+    double d;
+    T xr;
+};
+
+template <typename T>
+__device__ __forceinline__ void merge_load(int64_t c, int64_t n, const int64_t *__restrict__ si,
+                                           const int64_t *__restrict__ sj,
+                                           const int64_t *__restrict__ rowptr,
+                                           const uint32_t *__restrict__ colw,
+                                           const double *__restrict__ diag,
+                                           const T *__restrict__ x, MergeChunk<T> &q) {
+    const int tid = threadIdx.x;
+    q.i0 = si[c];
+    q.i1 = si[c + 1];
+    q.j0 = sj[c];
+    q.j1 = sj[c + 1];
+#pragma unroll
+    for (int k = 0; k < kMergeDepth; k++) {
+        const int64_t e = q.j0 + tid + k * kMergeBS;
+        q.w[k] = (e < q.j1) ? colw[e] : 0u;
+    }
+    const int64_t r = q.i0 + tid;
+    q.rs = 0;
+    q.re = 0;
+    q.d = 0.0;
+    q.xr = (T)0;
+    if (r <= q.i1 && r < n) {
+        q.rs = rowptr[r];
+        q.re = rowptr[r + 1];
+    }
+    if (r < q.i1) {
+        q.d = diag[r];
+        q.xr = x[r];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMergeBS) void k_spmv_merge(
+    int64_t n, int64_t nch, const int64_t *__restrict__ si, const int64_t *__restrict__ sj,
+    const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ colw,
+    const DevModel *__restrict__ m, const double *__restrict__ diag, const T *__restrict__ x,
+    T *__restrict__ y, double *__restrict__ carry, int64_t *__restrict__ carry_row,
+    const double *__restrict__ sx_dev, int sx_mode, double *__restrict__ partials) {
+    __shared__ T prod[kMergeK];
+    __shared__ T vtab[kMaxClasses];
+    const int tid = threadIdx.x;
+    if (tid < kMaxClasses) vtab[tid] = (T)m->vtab[tid];
+    const double sx = scale_from(sx_dev, sx_mode);
+    double dot = 0.0;
+    int64_t c = blockIdx.x;
+    MergeChunk<T> cur, nxt;
+    if (c < nch) merge_load(c, n, si, sj, rowptr, colw, diag, x, cur);
+    __syncthreads();
+    while (c < nch) {
+        const int64_t cn = c + gridDim.x;
+        T xv[kMergeDepth];
+#pragma unroll
+        for (int k = 0; k < kMergeDepth; k++) {
+            const int64_t e = cur.j0 + tid + k * kMergeBS;
+            xv[k] = (e < cur.j1) ? x[cur.w[k] & kColMask] : (T)0;
+        }
+        if (cn < nch) merge_load(cn, n, si, sj, rowptr, colw, diag, x, nxt);
+#pragma unroll
+        for (int k = 0; k < kMergeDepth; k++) {
+            const int64_t e = cur.j0 + tid + k * kMergeBS;
+            if (e < cur.j1) {
+                const uint32_t w = cur.w[k];
+                const T v = vtab[(w >> kColBits) & 31];
+                prod[e - cur.j0] = (w >> 31) ? -(v * xv[k]) : v * xv[k];
+            }
+        }
+        __syncthreads();
+        const int64_t r = cur.i0 + tid;
+        if (r <= cur.i1) {
+            if (r < n) {
+                const int64_t a = max(cur.rs, cur.j0), b = min(cur.re, cur.j1);
+                T acc = (T)0;
+                for (int64_t e = a; e < b; e++) acc += prod[e - cur.j0];
+                if (r < cur.i1) {
+                    const T v = ((T)cur.d * cur.xr + acc) * (T)sx;
+                    y[r] = v;
+                    dot += (double)cur.xr * sx * (double)v;
+                } else {
+                    carry[c] = (double)(acc * (T)sx);
+                    carry_row[c] = r;
+                }
+            } else {
+                carry[c] = 0.0;
+                carry_row[c] = n;
+            }
+        }
+        __syncthreads();
+        c = cn;
+        cur = nxt;
+    }
+    if (partials != nullptr) store_partial<kMergeBS>(block_sum<kMergeBS>(dot), partials);
+}
+
+// y[carry_row[c]] += carry[c]; partial of sum (sx x_r) carry for the dot.
+template <typename T>
+__global__ __launch_bounds__(256) void k_merge_fixup(int64_t n, int64_t nch,
+                                                     const double *__restrict__ carry,
+                                                     const int64_t *__restrict__ carry_row,
+                                                     const T *__restrict__ x, T *__restrict__ y,
+                                                     const double *__restrict__ sx_dev,
+                                                     int sx_mode, double *__restrict__ partials) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double dot = 0.0;
+    if (c < nch) {
+        const int64_t r = carry_row[c];
+        if (r < n) {
+            const double v = carry[c];
+            y[r] = (T)((double)y[r] + v);
+            dot = (double)x[r] * scale_from(sx_dev, sx_mode) * v;
+        }
+    }
+    if (partials != nullptr) store_partial<256>(block_sum<256>(dot), partials);
+}
+
 // nvec lanes per row: lane k accumulates column k of the block.  CSR words
 // are read once per group (same address for the group's lanes).
 template <typename T, int NV, int BS, bool OTF>
@@ -306,6 +468,98 @@ static int build_csr(mcd_op *op, hipStream_t s) {
         }
     }
     MCD_HIP(hipFree(d_max));
+    // merge-path split points
+    op->nchunks = (kMergeRowCost * n + nnz + kMergeK - 1) / kMergeK;
+    if (op->nchunks < 1) op->nchunks = 1;
+    MCD_HIP(hipMalloc(&op->d_split_i, (op->nchunks + 1) * sizeof(int64_t)));
+    MCD_HIP(hipMalloc(&op->d_split_j, (op->nchunks + 1) * sizeof(int64_t)));
+    MCD_HIP(hipMalloc(&op->d_carry, op->nchunks * sizeof(double)));
+    MCD_HIP(hipMalloc(&op->d_carry_row, op->nchunks * sizeof(int64_t)));
+    op->device_bytes += op->nchunks * 32;
+    hipLaunchKernelGGL(k_merge_splits, dim3(grid_for(op->nchunks + 1, 256)), dim3(256), 0, s, n,
+                       op->nchunks, op->d_rowptr, op->d_split_i, op->d_split_j);
+    MCD_HIP(hipGetLastError());
+    int dev = 0, cus = 256;
+    MCD_HIP(hipGetDevice(&dev));
+    MCD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    op->merge_grid = (int)std::min<int64_t>(op->nchunks, (int64_t)cus * 8);
+    return MCD_OK;
+}
+
+// One-vector CSR product with the operator's selected kernel.
+template <typename T>
+static int csr_one(const mcd_op *op, const T *x, T *y, const double *sx_dev, int sx_mode,
+                   double *dot_out, hipStream_t s) {
+    const int64_t n = op->n;
+    if (op->kernel == KERNEL_MERGE) {
+        const int G = op->merge_grid;
+        const int64_t nfix = (op->nchunks + 255) / 256;
+        MCD_REQUIRE(!dot_out || G + nfix <= op->max_partials, MCD_E_CAPACITY,
+                    "reduction scratch too small");
+        hipLaunchKernelGGL((k_spmv_merge<T>), dim3(G), dim3(kMergeBS), 0, s, n, op->nchunks,
+                           op->d_split_i, op->d_split_j, op->d_rowptr, op->d_colw, op->d_model,
+                           op->d_diag, x, y, op->d_carry, op->d_carry_row, sx_dev, sx_mode,
+                           dot_out ? op->d_partials : nullptr);
+        hipLaunchKernelGGL((k_merge_fixup<T>), dim3((unsigned)nfix), dim3(256), 0, s, n,
+                           op->nchunks, op->d_carry, op->d_carry_row, x, y, sx_dev, sx_mode,
+                           dot_out ? op->d_partials + G : nullptr);
+        MCD_HIP(hipGetLastError());
+        if (dot_out) {
+            hipLaunchKernelGGL((k_finalize_sum<1024>), dim3(1), dim3(1024), 0, s,
+                               (int)(G + nfix), op->d_partials, dot_out);
+            MCD_HIP(hipGetLastError());
+        }
+        return MCD_OK;
+    }
+    const int64_t nb = stream_blocks(op);
+    MCD_REQUIRE(!dot_out || nb <= op->max_partials, MCD_E_CAPACITY,
+                "reduction scratch too small");
+    hipLaunchKernelGGL((k_spmv_stream<T, 256>), dim3((unsigned)nb), dim3(256), 0, s, n,
+                       op->rows_per_block, op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x,
+                       y, sx_dev, sx_mode, dot_out ? op->d_partials : nullptr);
+    MCD_HIP(hipGetLastError());
+    if (dot_out) {
+        hipLaunchKernelGGL((k_finalize_sum<1024>), dim3(1), dim3(1024), 0, s, (int)nb,
+                           op->d_partials, dot_out);
+        MCD_HIP(hipGetLastError());
+    }
+    return MCD_OK;
+}
+
+// Time both one-vector kernels on this matrix and keep the faster (a
+// per-operator autotune; a few applies of the diagonal as the vector).
+static int tune_kernel(mcd_op *op, hipStream_t s) {
+    if (op->n == 0) return MCD_OK;
+    double *x = nullptr, *y = nullptr;
+    MCD_HIP(hipMalloc(&x, op->n * sizeof(double)));
+    MCD_HIP(hipMalloc(&y, op->n * sizeof(double)));
+    MCD_HIP(hipMemcpyAsync(x, op->d_diag, op->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    hipEvent_t a, b;
+    MCD_HIP(hipEventCreate(&a));
+    MCD_HIP(hipEventCreate(&b));
+    double best = 1e300;
+    int pick = KERNEL_STREAM;
+    for (int k : {KERNEL_STREAM, KERNEL_MERGE}) {
+        op->kernel = k;
+        MCD_TRY(csr_one<double>(op, x, y, nullptr, 0, nullptr, s));
+        MCD_HIP(hipEventRecord(a, s));
+        const int reps = 5;
+        for (int i = 0; i < reps; i++) MCD_TRY(csr_one<double>(op, x, y, nullptr, 0, nullptr, s));
+        MCD_HIP(hipEventRecord(b, s));
+        MCD_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        MCD_HIP(hipEventElapsedTime(&ms, a, b));
+        op->tune_ms[k] = ms / reps;
+        if (ms < best) {
+            best = ms;
+            pick = k;
+        }
+    }
+    op->kernel = pick;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    MCD_HIP(hipFree(x));
+    MCD_HIP(hipFree(y));
     return MCD_OK;
 }
 
@@ -314,13 +568,7 @@ static int launch_apply(const mcd_op *op, int nvec, const T *x, T *y, hipStream_
     const bool otf = op->storage == MCD_STORAGE_ON_THE_FLY;
     const int64_t n = op->n;
     if (n == 0) return MCD_OK;
-    if (!otf && nvec == 1) {
-        hipLaunchKernelGGL((k_spmv_stream<T, 256>), dim3((unsigned)stream_blocks(op)), dim3(256),
-                           0, s, n, op->rows_per_block, op->d_rowptr, op->d_colw, op->d_model,
-                           op->d_diag, x, y, (const double *)nullptr, 0, (double *)nullptr);
-        MCD_HIP(hipGetLastError());
-        return MCD_OK;
-    }
+    if (!otf && nvec == 1) return csr_one<T>(op, x, y, nullptr, 0, nullptr, s);
 #define MCD_GROUP(NV)                                                                          \
     case NV:                                                                                   \
         if (otf)                                                                               \
@@ -370,22 +618,7 @@ int apply_any(const mcd_op *op, int dtype, int nvec, const void *x, void *y, hip
 
 int apply_f64_fused(const mcd_op *op, const double *x, double *y, const double *sx_dev,
                     int sx_mode, double *dot_out, hipStream_t s) {
-    const int64_t n = op->n;
-    if (op->storage == MCD_STORAGE_CSR) {
-        const int64_t nb = stream_blocks(op);
-        MCD_REQUIRE(dot_out == nullptr || nb <= op->max_partials, MCD_E_CAPACITY,
-                    "too many blocks for the reduction scratch");
-        hipLaunchKernelGGL((k_spmv_stream<double, 256>), dim3((unsigned)nb), dim3(256), 0, s, n,
-                           op->rows_per_block, op->d_rowptr, op->d_colw, op->d_model, op->d_diag,
-                           x, y, sx_dev, sx_mode, dot_out ? op->d_partials : nullptr);
-        MCD_HIP(hipGetLastError());
-        if (dot_out) {
-            hipLaunchKernelGGL((k_finalize_sum<1024>), dim3(1), dim3(1024), 0, s, (int)nb,
-                               op->d_partials, dot_out);
-            MCD_HIP(hipGetLastError());
-        }
-        return MCD_OK;
-    }
+    if (op->storage == MCD_STORAGE_CSR) return csr_one<double>(op, x, y, sx_dev, sx_mode, dot_out, s);
     // On-the-fly: product, then a separate fused scale + dot.
     MCD_TRY(launch_apply<double>(op, 1, x, y, s));
     if (sx_dev != nullptr || dot_out != nullptr)
@@ -489,6 +722,8 @@ extern "C" int mcd_op_create(const mcd_model *model, const uint64_t *keys_dev, i
     if (st == MCD_STORAGE_CSR) {
         rc = build_csr(op, s);
         if (rc < 0) return fail(rc);
+        rc = tune_kernel(op, s);
+        if (rc < 0) return fail(rc);
     }
     CK(hipStreamSynchronize(s));
 #undef CK
@@ -513,6 +748,9 @@ extern "C" void mcd_op_destroy(mcd_op *op) {
     if (op->d_counter) (void)hipFree(op->d_counter);
     if (op->d_scalars) (void)hipFree(op->d_scalars);
     if (op->ws) (void)hipFree(op->ws);
+    for (void *p : {(void *)op->d_split_i, (void *)op->d_split_j, (void *)op->d_carry,
+                    (void *)op->d_carry_row})
+        if (p) (void)hipFree(p);
     (void)hipSetDevice(cur);
     delete op;
 }
@@ -524,9 +762,18 @@ extern "C" int mcd_op_info(const mcd_op *op, mcd_op_info_t *info) {
     info->storage = op->storage;
     info->n_classes = op->hm.dm.n_classes;
     info->rows_per_block = op->rows_per_block;
-    info->reserved = 0;
+    info->kernel = op->kernel;
     info->device_bytes = op->device_bytes;
     info->build_ms = op->build_ms;
+    return MCD_OK;
+}
+
+extern "C" int mcd_op_set_kernel(mcd_op *op, int32_t kernel) {
+    MCD_REQUIRE(op != nullptr, MCD_E_INVALID, "op is NULL");
+    MCD_REQUIRE(op->storage == MCD_STORAGE_CSR, MCD_E_INVALID, "operator has no CSR");
+    MCD_REQUIRE(kernel == KERNEL_STREAM || kernel == KERNEL_MERGE, MCD_E_INVALID,
+                "kernel %d unknown", kernel);
+    op->kernel = kernel;
     return MCD_OK;
 }
 

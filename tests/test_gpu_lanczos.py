@@ -40,13 +40,16 @@ CASES = _cases()
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("storage,store", [("csr", True), ("otf", False), ("csr", False)])
-def test_e0_and_ground_state(name, storage, store):
+@pytest.mark.parametrize("storage,store,kern", [("csr", True, "stream"), ("otf", False, None),
+                                                ("csr", False, "merge"), ("csr", True, "merge")])
+def test_e0_and_ground_state(name, storage, store, kern):
     torch, mcd = require_gpu()
     m, keys = CASES[name]
-    log_case("lanczos", case=name, storage=storage, store=store, n=len(keys))
+    log_case("lanczos", case=name, storage=storage, store=store, kernel=kern, n=len(keys))
     H, ro = _oracle(keys, m)
     op = mcd.Operator(m, mcd.keys_from_numpy(keys), storage=storage)
+    if kern:
+        op.set_kernel(kern)
     e0, psi, a, b, info = mcd.lanczos_ground(op, max_iter=400, tol=1e-12, seed=11,
                                               store_vectors=store)
     assert abs(e0 - ro["e0"]) <= 1e-10 * abs(ro["e0"])

@@ -114,6 +114,10 @@ def test_connectivity_bit_exact(name, storage):
     op.close()
 
 
+def _kernels(op, storage):
+    return ["stream", "merge"] if storage == "csr" else [None]
+
+
 @pytest.mark.parametrize("name", list(MODELS))
 @pytest.mark.parametrize("storage", ["csr", "otf"])
 @pytest.mark.parametrize("nvec", [1, 2, 4, 8, 16])
@@ -124,9 +128,38 @@ def test_apply_f64(name, storage, nvec):
     H = ham.build_csr(keys, m)
     x = W.random_vector(len(keys), 100 + nvec, nvec)
     op = mcd.Operator(m, mcd.keys_from_numpy(keys), storage=storage)
-    y = op.apply(torch.from_numpy(x).cuda()).cpu().numpy()
-    assert _rel(y, H @ x) <= 1e-12
+    for kern in _kernels(op, storage) if nvec == 1 else [None]:
+        if kern:
+            op.set_kernel(kern)
+        y = op.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+        assert _rel(y, H @ x) <= 1e-12, kern
     op.close()
+
+
+def test_merge_path_long_and_empty_rows():
+    """Merge-path chunking with rows of ~130 nonzeros (fully connected 12-orbital
+    model) and with rows that keep no hop at all (sparse subset of a sector)."""
+    torch, mcd = require_gpu()
+    rng = np.random.default_rng(11)
+    amps = [-1.0, -0.5, 0.3, 0.7]          # packed CSR holds <= 32 distinct |t|
+    bonds = [(i, j, float(rng.choice(amps))) for i in range(12) for j in range(i + 1, 12)]
+    dense = W.Model(12, bonds, rng.uniform(0, 4, 12), rng.uniform(-1, 1, 12), 6, 6, "dense")
+    full = fock.sector_keys(12, 6, 6)
+    cases = {"dense_full": (dense, full[:60000]),
+             "sparse_subset": (W.chain(12, U=8.0, mu=4.0), np.sort(rng.choice(full, 30000, replace=False))),
+             "mixed": (dense, np.sort(np.concatenate([full[:3000], rng.choice(full[3000:], 20000, replace=False)])))}
+    for name, (m, keys) in cases.items():
+        log_case("merge_rows", case=name, n=len(keys))
+        H = ham.build_csr(keys, m)
+        x = W.random_vector(len(keys), 3)
+        op = mcd.Operator(m, mcd.keys_from_numpy(keys), storage="csr")
+        for kern in ("stream", "merge"):
+            op.set_kernel(kern)
+            y = op.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+            assert _rel(y, H @ x) <= 1e-12, (name, kern)
+            y32 = op.apply(torch.from_numpy(x.astype(np.float32)).cuda()).cpu().numpy()
+            assert _rel(y32.astype(np.float64), H @ x) <= 2e-6, (name, kern)
+        op.close()
 
 
 @pytest.mark.parametrize("storage", ["csr", "otf"])
@@ -162,8 +195,11 @@ def test_apply_edges():
             H = ham.build_csr(keys, m)
             x = W.random_vector(len(keys), 1)
             op = mcd.Operator(m, mcd.keys_from_numpy(keys), storage=storage)
-            y = op.apply(torch.from_numpy(x).cuda()).cpu().numpy()
-            assert _rel(y, H @ x) <= 1e-12, name
+            for kern in _kernels(op, storage):
+                if kern:
+                    op.set_kernel(kern)
+                y = op.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+                assert _rel(y, H @ x) <= 1e-12, (name, kern)
             op.close()
 
 
@@ -193,8 +229,10 @@ def test_apply_c2_full_size_sampled_rows():
     rows = np.sort(np.random.default_rng(5).choice(len(keys), 3000, replace=False))
     ref = ham.apply_rows(keys, rows, m, x)
     kd = mcd.keys_from_numpy(keys)
-    for storage in ("csr", "otf"):
+    for storage, kern in (("csr", "stream"), ("csr", "merge"), ("otf", None)):
         op = mcd.Operator(m, kd, storage=storage)
+        if kern:
+            op.set_kernel(kern)
         xt = torch.from_numpy(x).cuda()
         y = op.apply(xt)
         assert _rel(y.cpu().numpy()[rows], ref) <= 1e-12
