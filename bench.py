@@ -141,13 +141,35 @@ def main():
     chosen = info["kernel"]
     per_kernel = {}
     if info["storage"] == "csr":
-        for kname in ("stream", "merge"):
+        for kname in ("stream", "stream_xcd", "merge", "rowchunk"):
             op.set_kernel(kname)
             per_kernel[kname] = round(time_apply(50), 5)
         op.set_kernel(chosen)
     k_ms = time_apply()
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+
+    # Block products (the batched form): ms per apply and per vector.
+    spmm = {}
+    for tdt, tname in ((torch.float32, "f32"), (torch.float64, "f64")):
+        for b in (8, 16):
+            X = torch.from_numpy(W.random_vector(n, 31, b)).to(dev).to(tdt)
+            Y = torch.empty_like(X)
+            for _ in range(3):
+                op.apply(X, out=Y)
+            e_a, e_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e_a.record(s)
+            for _ in range(20):
+                op.apply(X, out=Y)
+            e_b.record(s)
+            e_b.synchronize()
+            ms = e_a.elapsed_time(e_b) / 20
+            byts = 8.0 * (n + 1) + 4.0 * nnz + 8.0 * n + 2.0 * n * b * X.element_size()
+            spmm[f"{tname}_b{b}"] = {"ms": round(ms, 4), "ms_per_vector": round(ms / b, 5),
+                                     "GBs": round(byts / ms / 1e6, 1)}
+            del X, Y
     kernel_names = {"stream": "k_spmv_stream<double,256>",
+                    "stream_xcd": "k_spmv_stream<double,256> (XCD-major order)",
+                    "rowchunk": "k_apply_group<double,1,256,false> (row-chunk)",
                     "merge": "k_spmv_merge<double> + k_merge_fixup<double>"}
 
     out = {
@@ -169,6 +191,7 @@ def main():
                      "kernel": kernel_names.get(chosen, "k_apply_group (on-the-fly)"),
                      "kernel_ms": round(k_ms, 5), "ms_per_kernel_variant": per_kernel},
         "cpu_baseline": None,
+        "block_spmm": spmm,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(m, mcd.keys_to_numpy(keys), x.cpu().numpy(),

@@ -139,7 +139,8 @@ typedef struct mcd_op_info_t {
     int32_t storage;          /* resolved storage */
     int32_t n_classes;        /* distinct |t| amplitudes */
     int32_t rows_per_block;   /* CSR stream kernel row block */
-    int32_t kernel;           /* one-vector CSR kernel: 1 stream, 2 merge-path */
+    int32_t kernel;           /* one-vector CSR kernel: 1 stream, 2 merge-path, 3 stream XCD,
+                                 4 row-chunk */
     int64_t device_bytes;     /* device memory held by the operator */
     double build_ms;          /* time of index + CSR build */
 } mcd_op_info_t;
@@ -149,7 +150,12 @@ int mcd_op_info(const mcd_op *op, mcd_op_info_t *info);
 /* Select the kernel of one-vector CSR products (y = H~ x with nvec = 1):
  *   1 = stream: one row block per workgroup, nonzeros staged through LDS;
  *   2 = merge-path: persistent workgroups over chunks of (nonzeros + rows),
- *       next chunk prefetched while the current one is reduced.
+ *       next chunk prefetched while the current one is reduced;
+ *   3 = stream with an XCD-major workgroup order: each of the 8 XCDs walks
+ *       one contiguous slice of rows, so its L2 serves mostly its own slice
+ *       of x;
+ *   4 = row-chunk: one thread per row, 16 column words then 16 gathers in
+ *       flight per thread, no LDS staging (XCD-major row tiles).
  * Both give the same result up to summation order.  At creation a CSR
  * operator times both on its own matrix and keeps the faster one.
  * MCD_E_INVALID for other values or an on-the-fly operator. */

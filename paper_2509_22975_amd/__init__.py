@@ -24,7 +24,7 @@ MCD_OK, MCD_NOCONV = 0, 1
 STORAGE = {"auto": 0, "on_the_fly": 1, "otf": 1, "csr": 2}
 STORAGE_NAME = {0: "auto", 1: "on_the_fly", 2: "csr"}
 DTYPE = {"f64": 0, "f32": 1}
-KERNEL_NAME = {1: "stream", 2: "merge"}
+KERNEL_NAME = {1: "stream", 2: "merge", 3: "stream_xcd", 4: "rowchunk"}
 
 P = ctypes.POINTER
 c_i32, c_i64, c_u64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
@@ -203,8 +203,8 @@ class Operator:
                     device_bytes=i.device_bytes, build_ms=i.build_ms)
 
     def set_kernel(self, name: str):
-        """Force the one-vector CSR kernel: 'stream' or 'merge'."""
-        _check(lib().mcd_op_set_kernel(self.handle, {"stream": 1, "merge": 2}[name]),
+        """Force the one-vector CSR kernel: 'stream', 'merge', 'stream_xcd' or 'rowchunk'."""
+        _check(lib().mcd_op_set_kernel(self.handle, {v: k for k, v in KERNEL_NAME.items()}[name]),
                "mcd_op_set_kernel")
 
     def apply(self, x, out=None):

@@ -49,7 +49,8 @@ constexpr int kMergeDepth = 8;               // nonzeros per thread per chunk
 constexpr int kMergeK = kMergeBS * kMergeDepth;  // path items (nonzeros + 9 per row) per chunk
 constexpr int kMergeRowCost = 9;             // so a chunk ends < kMergeBS rows
 
-enum { KERNEL_STREAM = 1, KERNEL_MERGE = 2 };
+enum { KERNEL_STREAM = 1, KERNEL_MERGE = 2, KERNEL_STREAM_XCD = 3, KERNEL_ROWCHUNK = 4 };
+constexpr int kNumXcd = 8;                   // gfx950: workgroups are dealt round-robin to 8 XCDs
 
 // One hopping bond with i < j, prepared for bit arithmetic.
 struct DevBond {
@@ -118,7 +119,7 @@ struct mcd_op {
     int64_t *d_split_i, *d_split_j;   // [nchunks + 1]
     double *d_carry;                  // [nchunks]
     int64_t *d_carry_row;             // [nchunks]
-    double tune_ms[3];                // measured per-apply time per kernel
+    double tune_ms[5];                // measured per-apply time per kernel
 };
 
 namespace mcd {

@@ -139,12 +139,24 @@ __global__ __launch_bounds__(BS) void k_spmv_stream(
     int64_t n, int R, const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ colw,
     const DevModel *__restrict__ m, const double *__restrict__ diag, const T *__restrict__ x,
     T *__restrict__ y, const double *__restrict__ sx_dev, int sx_mode,
-    double *__restrict__ partials) {
+    double *__restrict__ partials, int64_t nblocks, int xcd_major) {
     constexpr int DEPTH = kStreamNnzMax / BS;
     __shared__ T prod[kStreamNnzMax];
     __shared__ T vtab[kMaxClasses];
     const int tid = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * R;
+    // XCD-major mapping: workgroup b runs on XCD b % 8, so giving XCD k the
+    // contiguous row blocks [k per, (k + 1) per) keeps each L2 on one slice of
+    // the matrix (its gathers stay mostly in its own slice of x).
+    int64_t blk = blockIdx.x;
+    if (xcd_major) {
+        const int64_t per = (nblocks + kNumXcd - 1) / kNumXcd;
+        blk = (int64_t)(blockIdx.x % kNumXcd) * per + blockIdx.x / kNumXcd;
+    }
+    if (blk >= nblocks) {   // padding workgroup of the XCD-major grid
+        if (partials != nullptr && tid == 0) partials[blockIdx.x] = 0.0;
+        return;
+    }
+    const int64_t r0 = blk * R;
     const int64_t r1 = min(r0 + (int64_t)R, n);
     const int64_t r = r0 + tid;
     const bool own = tid < R && r < r1;
@@ -360,37 +372,80 @@ __global__ __launch_bounds__(256) void k_merge_fixup(int64_t n, int64_t nch,
 }
 
 // nvec lanes per row: lane k accumulates column k of the block.  CSR words
-// are read once per group (same address for the group's lanes).
+// are read once per group (same address for the group's lanes).  Each
+// workgroup owns RT consecutive rows, walked RPB at a time, and the row tiles
+// are dealt XCD-major (XCD k gets one contiguous slice of rows), so the
+// gathered rows of X -- mostly inside the same up-string segment for
+// down-spin hops -- are reused from that XCD's L2.
 template <typename T, int NV, int BS, bool OTF>
 __global__ __launch_bounds__(BS) void k_apply_group(
     int64_t n, const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ colw,
     const DevModel *__restrict__ m, const uint64_t *__restrict__ keys,
     const HashSlot *__restrict__ h, uint64_t hmask, const double *__restrict__ diag,
-    const T *__restrict__ x, T *__restrict__ y) {
+    const T *__restrict__ x, T *__restrict__ y, int64_t ntiles, int rows_per_tile,
+    const double *__restrict__ sx_dev = nullptr, int sx_mode = 0,
+    double *__restrict__ partials = nullptr) {
     __shared__ T vtab[kMaxClasses];
     if (threadIdx.x < kMaxClasses) vtab[threadIdx.x] = (T)m->vtab[threadIdx.x];
     __syncthreads();
     constexpr int RPB = BS / NV;
-    const int64_t r = (int64_t)blockIdx.x * RPB + threadIdx.x / NV;
-    const int lane = threadIdx.x % NV;
-    if (r >= n) return;
-    T acc = (T)diag[r] * x[r * NV + lane];
-    if constexpr (!OTF) {
-        const int64_t e1 = rowptr[r + 1];
-        for (int64_t e = rowptr[r]; e < e1; e++) {
-            const uint32_t w = colw[e];
-            const T v = vtab[(w >> kColBits) & 31];
-            const T xv = x[(int64_t)(w & kColMask) * NV + lane];
-            acc += (w >> 31) ? -(v * xv) : v * xv;
-        }
-    } else {
-        for_each_hop(keys[r], m, h, hmask, [&](int64_t c, int b, uint32_t par) {
-            const T v = (T)m->bonds[b].t;
-            const T xv = x[c * NV + lane];
-            acc += par ? -(v * xv) : v * xv;
-        });
+    const int64_t per = (ntiles + kNumXcd - 1) / kNumXcd;
+    const int64_t tile = (int64_t)(blockIdx.x % kNumXcd) * per + blockIdx.x / kNumXcd;
+    // optional scale sx and, for NV == 1, the partial of sum_r (sx x_r) y_r
+    const double sx = scale_from(sx_dev, sx_mode);
+    double dot = 0.0;
+    if (tile >= ntiles) {
+        if (partials != nullptr && threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+        return;
     }
-    y[r * NV + lane] = acc;
+    const int lane = threadIdx.x % NV;
+    const int64_t rbeg = tile * rows_per_tile;
+    const int64_t rend = min(rbeg + (int64_t)rows_per_tile, n);
+    for (int64_t r = rbeg + threadIdx.x / NV; r < rend; r += RPB) {
+        T acc = (T)diag[r] * x[r * NV + lane];
+        if constexpr (!OTF) {
+            // Chunks of CH nonzeros: the group loads the chunk's words with one
+            // coalesced access (CH / NV words per lane), broadcasts word j with
+            // a lane shuffle and issues all CH gathers before the first FMA, so
+            // a row costs ~2 dependent memory round trips per chunk instead of
+            // one per nonzero.  Accumulation stays in entry order.
+            constexpr int CH = 16;
+            constexpr int WPL = (CH + NV - 1) / NV;
+            const int64_t e1 = rowptr[r + 1];
+            for (int64_t base = rowptr[r]; base < e1; base += CH) {
+                uint32_t mw[WPL];
+#pragma unroll
+                for (int q = 0; q < WPL; q++) {
+                    const int64_t e = base + q * NV + lane;
+                    mw[q] = (q * NV + lane < CH && e < e1) ? colw[e] : 0u;
+                }
+                uint32_t wj[CH];
+                T xv[CH];
+#pragma unroll
+                for (int j = 0; j < CH; j++) {
+                    wj[j] = (uint32_t)__shfl((int)mw[j / NV], j % NV, NV);
+                    xv[j] = (base + j < e1) ? x[(int64_t)(wj[j] & kColMask) * NV + lane] : (T)0;
+                }
+#pragma unroll
+                for (int j = 0; j < CH; j++) {
+                    if (base + j < e1) {
+                        const T v = vtab[(wj[j] >> kColBits) & 31];
+                        acc += (wj[j] >> 31) ? -(v * xv[j]) : v * xv[j];
+                    }
+                }
+            }
+        } else {
+            for_each_hop(keys[r], m, h, hmask, [&](int64_t c, int b, uint32_t par) {
+                const T v = (T)m->bonds[b].t;
+                const T xv = x[c * NV + lane];
+                acc += par ? -(v * xv) : v * xv;
+            });
+        }
+        if (sx_dev != nullptr) acc = acc * (T)sx;
+        y[r * NV + lane] = acc;
+        if (partials != nullptr) dot += (double)x[r * NV + lane] * sx * (double)acc;
+    }
+    if (partials != nullptr) store_partial<BS>(block_sum<BS>(dot), partials);
 }
 
 __global__ void k_conn_count(int64_t row0, int64_t row1, const uint64_t *__restrict__ keys,
@@ -511,15 +566,35 @@ static int csr_one(const mcd_op *op, const T *x, T *y, const double *sx_dev, int
         }
         return MCD_OK;
     }
+    if (op->kernel == KERNEL_ROWCHUNK) {
+        const int rpt = 1024;
+        const int64_t ntiles = (n + rpt - 1) / rpt;
+        const int64_t grid = kNumXcd * ((ntiles + kNumXcd - 1) / kNumXcd);
+        MCD_REQUIRE(!dot_out || grid <= op->max_partials, MCD_E_CAPACITY,
+                    "reduction scratch too small");
+        hipLaunchKernelGGL((k_apply_group<T, 1, 256, false>), dim3((unsigned)grid), dim3(256), 0,
+                           s, n, op->d_rowptr, op->d_colw, op->d_model, op->d_keys, op->d_hash,
+                           op->hash_mask, op->d_diag, x, y, ntiles, rpt, sx_dev, sx_mode,
+                           dot_out ? op->d_partials : nullptr);
+        MCD_HIP(hipGetLastError());
+        if (dot_out) {
+            hipLaunchKernelGGL((k_finalize_sum<1024>), dim3(1), dim3(1024), 0, s, (int)grid,
+                               op->d_partials, dot_out);
+            MCD_HIP(hipGetLastError());
+        }
+        return MCD_OK;
+    }
     const int64_t nb = stream_blocks(op);
-    MCD_REQUIRE(!dot_out || nb <= op->max_partials, MCD_E_CAPACITY,
+    const bool xcd = op->kernel == KERNEL_STREAM_XCD;
+    const int64_t grid = xcd ? kNumXcd * ((nb + kNumXcd - 1) / kNumXcd) : nb;
+    MCD_REQUIRE(!dot_out || grid <= op->max_partials, MCD_E_CAPACITY,
                 "reduction scratch too small");
-    hipLaunchKernelGGL((k_spmv_stream<T, 256>), dim3((unsigned)nb), dim3(256), 0, s, n,
+    hipLaunchKernelGGL((k_spmv_stream<T, 256>), dim3((unsigned)grid), dim3(256), 0, s, n,
                        op->rows_per_block, op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x,
-                       y, sx_dev, sx_mode, dot_out ? op->d_partials : nullptr);
+                       y, sx_dev, sx_mode, dot_out ? op->d_partials : nullptr, nb, xcd ? 1 : 0);
     MCD_HIP(hipGetLastError());
     if (dot_out) {
-        hipLaunchKernelGGL((k_finalize_sum<1024>), dim3(1), dim3(1024), 0, s, (int)nb,
+        hipLaunchKernelGGL((k_finalize_sum<1024>), dim3(1), dim3(1024), 0, s, (int)grid,
                            op->d_partials, dot_out);
         MCD_HIP(hipGetLastError());
     }
@@ -539,7 +614,7 @@ static int tune_kernel(mcd_op *op, hipStream_t s) {
     MCD_HIP(hipEventCreate(&b));
     double best = 1e300;
     int pick = KERNEL_STREAM;
-    for (int k : {KERNEL_STREAM, KERNEL_MERGE}) {
+    for (int k : {KERNEL_STREAM, KERNEL_STREAM_XCD, KERNEL_MERGE, KERNEL_ROWCHUNK}) {
         op->kernel = k;
         MCD_TRY(csr_one<double>(op, x, y, nullptr, 0, nullptr, s));
         MCD_HIP(hipEventRecord(a, s));
@@ -569,18 +644,22 @@ static int launch_apply(const mcd_op *op, int nvec, const T *x, T *y, hipStream_
     const int64_t n = op->n;
     if (n == 0) return MCD_OK;
     if (!otf && nvec == 1) return csr_one<T>(op, x, y, nullptr, 0, nullptr, s);
+    // row tile per workgroup: 4 passes of 256/NV rows (>= 64 rows)
 #define MCD_GROUP(NV)                                                                          \
-    case NV:                                                                                   \
+    case NV: {                                                                                 \
+        const int rpt = std::max(64, 4 * (256 / NV));                                          \
+        const int64_t ntiles = (n + rpt - 1) / rpt;                                            \
+        const unsigned grid = (unsigned)(kNumXcd * ((ntiles + kNumXcd - 1) / kNumXcd));        \
         if (otf)                                                                               \
-            hipLaunchKernelGGL((k_apply_group<T, NV, 256, true>), dim3(grid_for(n, 256 / NV)), \
-                               dim3(256), 0, s, n, op->d_rowptr, op->d_colw, op->d_model,      \
-                               op->d_keys, op->d_hash, op->hash_mask, op->d_diag, x, y);       \
+            hipLaunchKernelGGL((k_apply_group<T, NV, 256, true>), dim3(grid), dim3(256), 0, s, \
+                               n, op->d_rowptr, op->d_colw, op->d_model, op->d_keys,           \
+                               op->d_hash, op->hash_mask, op->d_diag, x, y, ntiles, rpt);      \
         else                                                                                   \
-            hipLaunchKernelGGL((k_apply_group<T, NV, 256, false>),                             \
-                               dim3(grid_for(n, 256 / NV)), dim3(256), 0, s, n, op->d_rowptr,  \
-                               op->d_colw, op->d_model, op->d_keys, op->d_hash, op->hash_mask, \
-                               op->d_diag, x, y);                                              \
-        break;
+            hipLaunchKernelGGL((k_apply_group<T, NV, 256, false>), dim3(grid), dim3(256), 0,   \
+                               s, n, op->d_rowptr, op->d_colw, op->d_model, op->d_keys,        \
+                               op->d_hash, op->hash_mask, op->d_diag, x, y, ntiles, rpt);      \
+        break;                                                                                 \
+    }
     switch (nvec) {
         MCD_GROUP(1)
         MCD_GROUP(2)
@@ -771,7 +850,7 @@ extern "C" int mcd_op_info(const mcd_op *op, mcd_op_info_t *info) {
 extern "C" int mcd_op_set_kernel(mcd_op *op, int32_t kernel) {
     MCD_REQUIRE(op != nullptr, MCD_E_INVALID, "op is NULL");
     MCD_REQUIRE(op->storage == MCD_STORAGE_CSR, MCD_E_INVALID, "operator has no CSR");
-    MCD_REQUIRE(kernel == KERNEL_STREAM || kernel == KERNEL_MERGE, MCD_E_INVALID,
+    MCD_REQUIRE(kernel >= KERNEL_STREAM && kernel <= KERNEL_ROWCHUNK, MCD_E_INVALID,
                 "kernel %d unknown", kernel);
     op->kernel = kernel;
     return MCD_OK;

@@ -41,7 +41,8 @@ CASES = _cases()
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("storage,store,kern", [("csr", True, "stream"), ("otf", False, None),
-                                                ("csr", False, "merge"), ("csr", True, "merge")])
+                                                ("csr", True, "rowchunk"),
+                                                ("csr", False, "merge"), ("csr", True, "stream_xcd")])
 def test_e0_and_ground_state(name, storage, store, kern):
     torch, mcd = require_gpu()
     m, keys = CASES[name]
