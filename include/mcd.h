@@ -124,7 +124,8 @@ int mcd_basis_build(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t *
  *   (hop enumeration, popcount signs, hash lookup of the image state);
  *   MCD_STORAGE_CSR stores the matrix once as a packed CSR (one 32-bit word
  *   per nonzero: column, sign, amplitude class); MCD_STORAGE_AUTO picks CSR
- *   when it fits the format (n < 2^26, <= 32 distinct |t|) and the memory
+ *   when it fits the format (n <= 2^(31 - ceil(log2 #classes)), <= 32 distinct
+ *   |t|) and the memory
  *   budget (free HBM / 2), else on-the-fly.
  * validate != 0 checks on the GPU that the keys are sorted, unique and within
  *   n_orb bits (MCD_E_SECTOR otherwise).  Synchronises.

@@ -83,6 +83,10 @@ int prepare_model(const mcd_model *m, HostModel *hm) {
     }
     d.n_bonds = nb;
     d.n_classes = (int)std::min<size_t>(classes.size(), kMaxClasses);
+    uint32_t cls_bits = 0;
+    while ((1 << cls_bits) < d.n_classes) cls_bits++;
+    d.col_bits = 31u - cls_bits;
+    d.col_mask = (d.col_bits >= 32) ? 0xffffffffu : ((1u << d.col_bits) - 1u);
     for (int k = 0; k < d.n_classes; k++) d.vtab[k] = classes[k];
     return MCD_OK;
 }

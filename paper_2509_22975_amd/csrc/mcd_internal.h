@@ -40,8 +40,9 @@ void set_error(const char *fmt, ...);
     } while (0)
 
 constexpr uint64_t kEmpty = ~0ull;           // hash sentinel, never a valid key
-constexpr uint32_t kColBits = 26;            // packed CSR: column bits
-constexpr uint32_t kColMask = (1u << kColBits) - 1u;
+// Packed CSR word: column (col_bits) | amplitude class (31 - col_bits bits)
+// | sign (bit 31).  col_bits = 31 - ceil(log2(classes)) is chosen per model,
+// so one |t| allows 2^31 rows, two 2^30, ..., 32 classes 2^26.
 constexpr int kMaxClasses = 32;              // packed CSR: distinct |t| values
 constexpr int kStreamNnzMax = 4096;          // LDS products per stream block
 constexpr int kMergeBS = 256;                // merge-path SpMV: threads per workgroup
@@ -66,7 +67,8 @@ struct DevModel {
     int n_orb;
     int n_bonds;
     int n_classes;
-    int pad;
+    uint32_t col_bits;          // packed CSR column bits
+    uint32_t col_mask;          // (1 << col_bits) - 1
     double U[MCD_MAX_ORB];
     double eps[MCD_MAX_ORB];
     double vtab[kMaxClasses];   // |t| per class

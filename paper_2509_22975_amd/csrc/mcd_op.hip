@@ -111,7 +111,7 @@ __global__ void k_csr_fill(int64_t n, const uint64_t *__restrict__ keys,
     int64_t e = rowptr[r];
     for_each_hop(keys[r], m, h, hmask, [&](int64_t c, int b, uint32_t par) {
         const uint32_t neg = par ^ m->bonds[b].neg;
-        colw[e++] = (uint32_t)c | (m->bonds[b].cls << kColBits) | (neg << 31);
+        colw[e++] = (uint32_t)c | (m->bonds[b].cls << m->col_bits) | (neg << 31);
     });
 }
 
@@ -170,6 +170,7 @@ __global__ __launch_bounds__(BS) void k_spmv_stream(
         xr = x[r];
     }
     if (tid < kMaxClasses) vtab[tid] = (T)m->vtab[tid];
+    const uint32_t cmask = m->col_mask, cbits = m->col_bits;
     const int64_t e0 = rowptr[r0];
     const int cnt = (int)(rowptr[r1] - e0);
     const uint32_t *__restrict__ cw = colw + e0;
@@ -183,14 +184,14 @@ __global__ __launch_bounds__(BS) void k_spmv_stream(
 #pragma unroll
     for (int j = 0; j < DEPTH; j++) {
         const int e = tid + j * BS;
-        xv[j] = (e < cnt) ? x[w[j] & kColMask] : (T)0;
+        xv[j] = (e < cnt) ? x[w[j] & cmask] : (T)0;
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < DEPTH; j++) {
         const int e = tid + j * BS;
         if (e < cnt) {
-            const T v = vtab[(w[j] >> kColBits) & 31];
+            const T v = vtab[(w[j] & 0x7fffffffu) >> cbits];
             prod[e] = (w[j] >> 31) ? -(v * xv[j]) : v * xv[j];
         }
     }
@@ -299,6 +300,7 @@ __global__ __launch_bounds__(kMergeBS) void k_spmv_merge(
     __shared__ T vtab[kMaxClasses];
     const int tid = threadIdx.x;
     if (tid < kMaxClasses) vtab[tid] = (T)m->vtab[tid];
+    const uint32_t cmask = m->col_mask, cbits = m->col_bits;
     const double sx = scale_from(sx_dev, sx_mode);
     double dot = 0.0;
     int64_t c = blockIdx.x;
@@ -311,7 +313,7 @@ __global__ __launch_bounds__(kMergeBS) void k_spmv_merge(
 #pragma unroll
         for (int k = 0; k < kMergeDepth; k++) {
             const int64_t e = cur.j0 + tid + k * kMergeBS;
-            xv[k] = (e < cur.j1) ? x[cur.w[k] & kColMask] : (T)0;
+            xv[k] = (e < cur.j1) ? x[cur.w[k] & cmask] : (T)0;
         }
         if (cn < nch) merge_load(cn, n, si, sj, rowptr, colw, diag, x, nxt);
 #pragma unroll
@@ -319,7 +321,7 @@ __global__ __launch_bounds__(kMergeBS) void k_spmv_merge(
             const int64_t e = cur.j0 + tid + k * kMergeBS;
             if (e < cur.j1) {
                 const uint32_t w = cur.w[k];
-                const T v = vtab[(w >> kColBits) & 31];
+                const T v = vtab[(w & 0x7fffffffu) >> cbits];
                 prod[e - cur.j0] = (w >> 31) ? -(v * xv[k]) : v * xv[k];
             }
         }
@@ -388,6 +390,7 @@ __global__ __launch_bounds__(BS) void k_apply_group(
     __shared__ T vtab[kMaxClasses];
     if (threadIdx.x < kMaxClasses) vtab[threadIdx.x] = (T)m->vtab[threadIdx.x];
     __syncthreads();
+    const uint32_t cmask = m->col_mask, cbits = m->col_bits;
     constexpr int RPB = BS / NV;
     const int64_t per = (ntiles + kNumXcd - 1) / kNumXcd;
     const int64_t tile = (int64_t)(blockIdx.x % kNumXcd) * per + blockIdx.x / kNumXcd;
@@ -424,12 +427,12 @@ __global__ __launch_bounds__(BS) void k_apply_group(
 #pragma unroll
                 for (int j = 0; j < CH; j++) {
                     wj[j] = (uint32_t)__shfl((int)mw[j / NV], j % NV, NV);
-                    xv[j] = (base + j < e1) ? x[(int64_t)(wj[j] & kColMask) * NV + lane] : (T)0;
+                    xv[j] = (base + j < e1) ? x[(int64_t)(wj[j] & cmask) * NV + lane] : (T)0;
                 }
 #pragma unroll
                 for (int j = 0; j < CH; j++) {
                     if (base + j < e1) {
-                        const T v = vtab[(wj[j] >> kColBits) & 31];
+                        const T v = vtab[(wj[j] & 0x7fffffffu) >> cbits];
                         acc += (wj[j] >> 31) ? -(v * xv[j]) : v * xv[j];
                     }
                 }
@@ -783,10 +786,11 @@ extern "C" int mcd_op_create(const mcd_model *model, const uint64_t *keys_dev, i
     CK(hipMalloc(&op->d_scalars, 64 * sizeof(double)));
     op->device_bytes += op->max_partials * sizeof(double);
     // Storage choice.
-    const bool fmt_ok = n < (int64_t(1) << kColBits) && op->hm.ok_classes;
+    const bool fmt_ok = n <= (int64_t(1) << op->hm.dm.col_bits) && op->hm.ok_classes;
     int st = storage;
     if (st == MCD_STORAGE_CSR && !fmt_ok) {
-        set_error("packed CSR needs n < 2^26 and <= 32 distinct |t| (n = %lld)", (long long)n);
+        set_error("packed CSR needs n <= 2^%u (%d amplitude classes) and <= 32 distinct |t| "
+                  "(n = %lld)", op->hm.dm.col_bits, op->hm.dm.n_classes, (long long)n);
         return fail(MCD_E_CAPACITY);
     }
     if (st == MCD_STORAGE_AUTO) {
