@@ -70,6 +70,61 @@ def cpu_baseline(model, keys_np, x_np, nnz_per_row):
                       f"(x float64), {reps} reps, {dt:.2f} s each; bytes counted as for the GPU"}
 
 
+def pipeline_c3(mcd, W, torch, blocks=40):
+    """E0 + G(i w_n) on one impurity instance (2x2 + 8 baths, 0.5M chain states,
+    p = 8 = 4 sites x 2 spins, 64 Matsubara frequencies at beta = 50).
+
+    plain:      float64 Lanczos, then float64 band Lanczos with one single-vector
+                product per block column and full (two-pass) reorthogonalisation;
+    f64_block:  float64 block products, three-term block recurrence only;
+    chosen:     float32 block products (float64 Gram, recurrence, deflation and
+                resolvent), three-term block recurrence only.
+    Both stop Lanczos at a Ritz residual of 1e-6 |E0|; errors are against a
+    1e-12-residual float64 solve and the float64 band result.
+    """
+    import numpy as np
+    c = W.config_c3()
+    m = c["model"]
+    keys, _ = mcd.basis_build(m, "chain", start_key=W.neel_start(m), seed=c["seed"],
+                              beta_s=c["beta_s"], burn_in=c["burn_in"], max_steps=c["max_steps"],
+                              n_f=c["n_f"])
+    op = mcd.Operator(m, keys)
+    orbs, spins = [0, 1, 2, 3] * 2, [0] * 4 + [1] * 4
+    om = W.matsubara(64, 50.0)
+    e_ref, _, _, _, _ = mcd.lanczos_ground(op, max_iter=3000, tol=1e-12, seed=11, want_psi=False)
+    out = {"workload": "2x2 plaquette + 8 baths, U=8, half filling, 0.5M chain states, p=8, "
+                       "64 Matsubara frequencies (beta=50), 40 block steps",
+           "n_states": int(keys.numel())}
+    res = {}
+    for form, prec, percol, reo in (("plain", "f64", True, 2), ("f64_block", "f64", False, 0),
+                                    ("chosen", "f32", False, 0)):
+        for rep in range(2):          # second repetition is timed
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0, psi, _, _, si = mcd.lanczos_ground(op, max_iter=3000, tol=1e-6, seed=11,
+                                                   check_every=10)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            G, gi = mcd.band_lanczos_green(m, keys, psi, e0, orbs, spins, om, max_blocks=blocks,
+                                           precision=prec, per_column=percol, reorth=reo)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        res[form] = G
+        out[form] = {"e0_s": round(t1 - t0, 4), "green_s": round(t2 - t1, 4),
+                     "total_s": round(t2 - t0, 4), "lanczos_iters": si.iters,
+                     "e0_rel_err": abs(e0 - e_ref) / abs(e_ref), "n_plus": gi.n_plus,
+                     "n_minus": gi.n_minus, "krylov_dim": gi.krylov_dim}
+    for f in ("f64_block", "chosen"):
+        out[f]["G_rel_err_vs_plain"] = float(np.max(np.abs(res[f] - res["plain"]))
+                                             / np.max(np.abs(res["plain"])))
+        out[f]["reorth_passes"] = 0
+    out["plain"]["reorth_passes"] = 2
+    out["speedup_total"] = round(out["plain"]["total_s"] / out["chosen"]["total_s"], 3)
+    out["speedup_green"] = round(out["plain"]["green_s"] / out["chosen"]["green_s"], 3)
+    op.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +132,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--storage", default="csr")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="skip the plain-vs-chosen E0 + G comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for PMC byte counters)")
     args = ap.parse_args()
@@ -196,6 +253,8 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(m, mcd.keys_to_numpy(keys), x.cpu().numpy(),
                                            nnz / n)
+    if not args.no_pipeline:
+        out["pipeline_e0_green"] = pipeline_c3(mcd, W, torch)
     if args.copy_probe:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)

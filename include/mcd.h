@@ -244,8 +244,8 @@ int mcd_lanczos_ground(const mcd_op *op, const mcd_lanczos_cfg *cfg, const doubl
  * weight >= w_t; renormalise); build F~+ = union c+_mu F~ and F~- = union
  * c_mu F~ over the selected (orb[k], spin[k]) (Eq. excited_subspace); start
  * blocks c+_mu|psi0> and c_mu|psi0>; block Lanczos with block width
- * p = n_sel (the block Krylov space K_r^L of App. Band Lanczos), full
- * reorthogonalisation against every stored block and rank-revealing
+ * p = n_sel (the block Krylov space K_r^L of App. Band Lanczos),
+ * reorthogonalisation against every stored block (cfg->reorth passes) and rank-revealing
  * deflation of directions with norm <= dtol max_k ||start_k||; then
  * G+_{mu nu}(i w) = [R^T (z - T)^-1 R]_{mu nu} at z = i w + E0 and
  * G-_{mu nu}(i w) = -[R^T (z - T)^-1 R] at z = E0 - i w (the resolvent form
@@ -269,7 +269,11 @@ typedef struct mcd_band_cfg {
     double w_t;               /* target weight in (0, 1] */
     double dtol;              /* relative deflation tolerance (1e-10) */
     int32_t storage;          /* operator storage for F~+- */
-    int32_t reorth;           /* 1 = full reorthogonalisation, 0 = none */
+    int32_t reorth;           /* passes of reorthogonalisation against every stored
+                                 block: 2 (full, twice), 1 (once), 0 (none: only
+                                 the three-term recurrence; 3 blocks kept) */
+    int32_t per_column;       /* 1 = one single-vector product per block column
+                                 (the unbatched reference form), 0 = block SpMM */
 } mcd_band_cfg;
 
 int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int64_t n,

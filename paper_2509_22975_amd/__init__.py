@@ -61,7 +61,7 @@ class McdSolveInfo(ctypes.Structure):
 
 class McdBandCfg(ctypes.Structure):
     _fields_ = [("max_blocks", c_i32), ("precision", c_i32), ("w_t", c_dbl), ("dtol", c_dbl),
-                ("storage", c_i32), ("reorth", c_i32)]
+                ("storage", c_i32), ("reorth", c_i32), ("per_column", c_i32)]
 
 
 _lib = None
@@ -309,8 +309,8 @@ def lanczos_ground(op: Operator, max_iter=300, tol=1e-12, seed=0, check_every=10
 
 
 def band_lanczos_green(model, keys, psi0, e0, orbitals, spins, omega, max_blocks=50,
-                       precision="f64", w_t=1.0, dtol=1e-10, storage="auto", reorth=True,
-                       parts=False):
+                       precision="f64", w_t=1.0, dtol=1e-10, storage="auto", reorth=2,
+                       parts=False, per_column=False):
     """G(i w_n) [n_freq, n_sel, n_sel] complex128 via mcd_band_lanczos_green."""
     mb = _ModelBuf(model)
     orb = np.ascontiguousarray(orbitals, dtype=np.int32)
@@ -321,7 +321,7 @@ def band_lanczos_green(model, keys, psi0, e0, orbitals, spins, omega, max_blocks
     Gp = np.zeros_like(G)
     Gm = np.zeros_like(G)
     cfg = McdBandCfg(int(max_blocks), DTYPE[precision], float(w_t), float(dtol), STORAGE[storage],
-                     1 if reorth else 0)
+                     (2 if reorth is True else int(reorth)), 1 if per_column else 0)
     info = McdSolveInfo()
     dp = lambda a: a.view(np.float64).ctypes.data_as(P(c_dbl))
     code = lib().mcd_band_lanczos_green(ctypes.byref(mb.s), c_vp(keys.data_ptr()), int(keys.numel()),

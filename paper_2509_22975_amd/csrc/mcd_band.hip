@@ -125,6 +125,18 @@ __global__ void k_start_block(int64_t m, const uint64_t *__restrict__ keys,
     }
 }
 
+// Column k of a row-major [n][P] block to / from a contiguous vector
+// (dir 0: v = B[:, k]; dir 1: B[:, k] = v).
+template <typename T>
+__global__ void k_column(int64_t n, int P, int k, T *__restrict__ B, T *__restrict__ v, int dir) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    if (dir == 0)
+        v[r] = B[r * P + k];
+    else
+        B[r * P + k] = v[r];
+}
+
 // Partial Gram matrices: partial[(m * nch + chunk)][a][b] = sum over the
 // chunk's rows of Q_m[r][a] X[r][b] (float64 accumulation, fixed order).
 template <typename T, int P>
@@ -166,14 +178,19 @@ __global__ __launch_bounds__(BS) void k_gram(int64_t n, int64_t chunk_rows, int 
     }
 }
 
-__global__ void k_gram_reduce(int nm, int nch, int PP, const double *__restrict__ part,
-                              double *__restrict__ out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nm * PP) return;
+// out[m][e] = sum_c part[(m nch + c)][e]: one wavefront per output entry,
+// lanes stride over the chunks, fixed butterfly order.
+__global__ __launch_bounds__(256) void k_gram_reduce(int nm, int nch, int PP,
+                                                     const double *__restrict__ part,
+                                                     double *__restrict__ out) {
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= nm * PP) return;          // whole wavefront exits together
     const int m = i / PP, e = i % PP;
     double s = 0.0;
-    for (int c = 0; c < nch; c++) s += part[((int64_t)m * nch + c) * PP + e];
-    out[i] = s;
+    for (int c = lane; c < nch; c += 64) s += part[((int64_t)m * nch + c) * PP + e];
+    s = wave_sum(s);
+    if (lane == 0) out[i] = s;
 }
 
 // W -= sum_{m < nm} Q_m C_m  (sub != 0)   or   W = Q_0 C_0  (sub == 0, nm == 1).
@@ -327,6 +344,8 @@ struct BandRun {
     hipStream_t s;
     T *Qs = nullptr;          // [nstore][n][P]
     T *W = nullptr;           // [n][P]
+    T *colbuf = nullptr;      // [2][n] single-column staging (per-column mode)
+    bool per_column = false;
     double *part = nullptr;   // Gram partials
     double *dC = nullptr;     // device coefficient matrices
     double *dG = nullptr;     // reduced Gram matrices
@@ -338,7 +357,8 @@ struct BandRun {
 
     int gram(const T *Q0, int nm, const T *X, std::vector<double> &out) {
         const int PP = P * P;
-        int nch = (int)std::min<int64_t>(gridn(n, 256), std::max<int64_t>(1, 65536 / nm));
+        // ~2048 workgroups in total, at least 256 rows per chunk
+        int nch = (int)std::min<int64_t>(gridn(n, 256), std::max<int64_t>(1, 2048 / nm));
         nch = std::max(1, nch);
         const int64_t chunk_rows = (n + nch - 1) / nch;
         nch = (int)((n + chunk_rows - 1) / chunk_rows);
@@ -354,7 +374,7 @@ struct BandRun {
         }
 #undef GR
         MCD_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_gram_reduce, dim3(gridn((int64_t)nm * PP, 256)), dim3(256), 0, s, nm,
+        hipLaunchKernelGGL(k_gram_reduce, dim3(gridn((int64_t)nm * PP, 4)), dim3(256), 0, s, nm,
                            nch, PP, part, dG);
         MCD_HIP(hipGetLastError());
         out.resize((size_t)nm * PP);
@@ -440,7 +460,7 @@ struct BandRun {
         return MCD_OK;
     }
 
-    int run(T *phi, int max_blocks, double dtol_abs, bool reorth, BandResult &br) {
+    int run(T *phi, int max_blocks, double dtol_abs, int reorth, BandResult &br) {
         const int PP = P * P;
         br.P = P;
         br.A.clear();
@@ -456,7 +476,20 @@ struct BandRun {
         }
         std::vector<double> G, C;
         for (int j = 0; j < max_blocks; j++) {
-            MCD_TRY(apply_any(op, sizeof(T) == 8 ? MCD_F64 : MCD_F32, P, blk(j), W, s));
+            if (per_column) {
+                // unbatched reference: one single-vector product per column
+                for (int k = 0; k < P; k++) {
+                    hipLaunchKernelGGL((k_column<T>), dim3(gridn(n, 256)), dim3(256), 0, s, n, P,
+                                       k, blk(j), colbuf, 0);
+                    MCD_TRY(apply_any(op, sizeof(T) == 8 ? MCD_F64 : MCD_F32, 1, colbuf,
+                                      colbuf + n, s));
+                    hipLaunchKernelGGL((k_column<T>), dim3(gridn(n, 256)), dim3(256), 0, s, n, P,
+                                       k, W, colbuf + n, 1);
+                }
+                MCD_HIP(hipGetLastError());
+            } else {
+                MCD_TRY(apply_any(op, sizeof(T) == 8 ? MCD_F64 : MCD_F32, P, blk(j), W, s));
+            }
             MCD_TRY(gram(blk(j), 1, W, G));
             std::vector<double> Aj(PP);
             for (int a = 0; a < P; a++)        // symmetrise the projected block
@@ -470,8 +503,8 @@ struct BandRun {
                     for (int b = 0; b < P; b++) Bt[a * P + b] = br.B[j][b * P + a];
                 MCD_TRY(block_apply(blk(j - 1), 1, Bt, W, true));
             }
-            if (reorth) {
-                for (int pass = 0; pass < 2; pass++) {
+            if (reorth > 0) {
+                for (int pass = 0; pass < reorth; pass++) {
                     MCD_TRY(gram(blk(0), j + 1, W, C));
                     MCD_TRY(block_apply(blk(0), j + 1, C, W, true));
                 }
@@ -506,7 +539,8 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
     BandRun<T> run;
     auto cleanup = [&]() {
         for (void *p : {(void *)img, (void *)srt, (void *)uniq, (void *)d_nu, tmp, (void *)run.Qs,
-                        (void *)run.W, (void *)run.part, (void *)run.dC, (void *)run.dG})
+                        (void *)run.W, (void *)run.part, (void *)run.dC, (void *)run.dG,
+                        (void *)run.colbuf})
             if (p) (void)hipFree(p);
         if (op) mcd_op_destroy(op);
     };
@@ -560,12 +594,12 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
     }
     TRY(mcd_op_create(model, uniq, nu, cfg->storage, 0, s, &op));
     // Storage for the Krylov blocks.
-    const bool reorth = cfg->reorth != 0;
+    const int reorth = std::max(0, std::min(2, (int)cfg->reorth));
     run.op = op;
     run.P = P;
     run.n = nu;
     run.s = s;
-    run.nstore = reorth ? cfg->max_blocks + 1 : 3;
+    run.nstore = reorth > 0 ? cfg->max_blocks + 1 : 3;
     size_t fr = 0, tot = 0;
     CK(hipMemGetInfo(&fr, &tot));
     const double need = (double)run.nstore * nu * P * sizeof(T);
@@ -577,6 +611,8 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
     }
     CK(hipMalloc(&run.Qs, (size_t)run.nstore * nu * P * sizeof(T)));
     CK(hipMalloc(&run.W, (size_t)nu * P * sizeof(T)));
+    run.per_column = cfg->per_column != 0;
+    if (run.per_column) CK(hipMalloc(&run.colbuf, (size_t)2 * nu * sizeof(T)));
     run.part_cap = (int64_t)65536 * P * P + (int64_t)(cfg->max_blocks + 1) * P * P;
     CK(hipMalloc(&run.part, run.part_cap * sizeof(double)));
     run.coef_cap = (int64_t)(cfg->max_blocks + 1) * P * P;

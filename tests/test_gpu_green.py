@@ -64,6 +64,16 @@ def test_green_c1_chain_vs_oracle(sel):
     G, info = mcd.band_lanczos_green(m, mcd.keys_from_numpy(keys), torch.from_numpy(psi).cuda(),
                                      e0, orbs, spins, OM, max_blocks=blocks)
     assert _rel(G, Go) <= 1e-9
+    # unbatched reference form: one single-vector product per block column
+    Gc, _ = mcd.band_lanczos_green(m, mcd.keys_from_numpy(keys), torch.from_numpy(psi).cuda(),
+                                   e0, orbs, spins, OM, max_blocks=blocks, per_column=True)
+    assert _rel(Gc, G) <= 1e-11
+    # three-term block recurrence only (no reorthogonalisation), float64
+    G0, _ = mcd.band_lanczos_green(m, mcd.keys_from_numpy(keys), torch.from_numpy(psi).cuda(),
+                                   e0, orbs, spins, OM, max_blocks=blocks, reorth=0)
+    err0 = _rel(G0, Go)
+    print("[green] reorth=0 rel err", err0, flush=True)
+    assert err0 <= 1e-7
 
 
 def test_green_exhausted_equals_dense_definition():
