@@ -125,6 +125,48 @@ def pipeline_c3(mcd, W, torch, blocks=40):
     return out
 
 
+def batch_c3(mcd, W, torch, n_inst=32):
+    """Ground states of 32 bath-parameter instances of uneven basis size
+    (0.1M-0.5M chain states each): 32 single solves one after the other vs
+    one batched solve (all recurrences in lockstep, graph-replayed steps)."""
+    import numpy as np
+    sizes = W.bath_instance_sizes(n_inst, seed=3)
+    ops = []
+    t0 = time.perf_counter()
+    for k, nf in enumerate(sizes):
+        c = W.config_c3(seed=3 + k)
+        m = c["model"]
+        keys, _ = mcd.basis_build(m, "chain", start_key=W.neel_start(m), seed=c["seed"],
+                                  beta_s=c["beta_s"], burn_in=c["burn_in"],
+                                  max_steps=c["max_steps"], n_f=int(nf))
+        ops.append(mcd.Operator(m, keys, storage="csr"))
+    setup_s = time.perf_counter() - t0
+    kw = dict(max_iter=600, tol=1e-10, seed=11, check_every=10)
+    res = {}
+    for rep in range(2):                       # second repetition is timed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        single = [mcd.lanczos_ground(op, want_psi=True, **kw) for op in ops]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        e0b, psib, itb, info = mcd.batch_lanczos_ground(ops, want_psi=True, **kw)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res = dict(single_s=t1 - t0, batch_s=t2 - t1)
+    e_single = np.array([r[0] for r in single])
+    out = {"workload": f"{n_inst} impurity instances (2x2 + 8 baths, U=8), chain bases of "
+                       f"{int(min(sizes))}-{int(max(sizes))} states, E0 + ground state to a "
+                       "1e-10 Ritz residual",
+           "total_states": int(sum(op.n for op in ops)), "basis_and_op_build_s": round(setup_s, 2),
+           "single_solves_s": round(res["single_s"], 4), "batched_s": round(res["batch_s"], 4),
+           "speedup": round(res["single_s"] / res["batch_s"], 3),
+           "max_iters": int(max(itb)),
+           "max_rel_diff_e0": float(np.max(np.abs(np.array(e0b) - e_single) / np.abs(e_single)))}
+    for op in ops:
+        op.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +176,8 @@ def main():
     ap.add_argument("--storage", default="csr")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the plain-vs-chosen E0 + G comparison")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 32-instance batched ground-state comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for PMC byte counters)")
     args = ap.parse_args()
@@ -255,6 +299,8 @@ def main():
                                            nnz / n)
     if not args.no_pipeline:
         out["pipeline_e0_green"] = pipeline_c3(mcd, W, torch)
+    if not args.no_batch:
+        out["batch_ground_states"] = batch_c3(mcd, W, torch)
     if args.copy_probe:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)

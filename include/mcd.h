@@ -235,6 +235,25 @@ int mcd_lanczos_ground(const mcd_op *op, const mcd_lanczos_cfg *cfg, const doubl
                        mcd_solve_info *info, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * mcd_batch_lanczos_ground -- ground states of n_ops independent operators at
+ * once (App. Lanczos for each; e.g. bath-parameter instances of uneven basis
+ * size).  Same recurrence, start vectors and stopping rule as
+ * mcd_lanczos_ground, per operator; every step advances all unfinished
+ * operators with a fixed set of launches (per-instance scalars, per-instance
+ * deterministic reductions), and cfg->check_every steps are captured once
+ * as a HIP graph and replayed.  The Krylov vectors of all operators are kept
+ * (sum_i n_i (max_iter + 1) doubles; MCD_E_CAPACITY if they do not fit).
+ * ops: [n_ops] CSR operators on the current device.  e0_out: host [n_ops].
+ * psi0_dev: host array of n_ops device pointers ([n_i] doubles each) or NULL
+ * (entries may be NULL).  iters_out: host [n_ops] or NULL.  Work runs on an
+ * internal stream after `stream` has been synchronised; synchronises.
+ * MCD_NOCONV if any operator stopped at max_iter.
+ * ------------------------------------------------------------------------- */
+int mcd_batch_lanczos_ground(mcd_op *const *ops, int32_t n_ops, const mcd_lanczos_cfg *cfg,
+                             double *e0_out, double *const *psi0_dev, int32_t *iters_out,
+                             mcd_solve_info *info, void *stream);
+
+/* ---------------------------------------------------------------------------
  * mcd_band_lanczos_green -- Green function of the truncated ground state on
  * Matsubara frequencies (Sec. Subspace of the Green function, Sec. Further
  * truncation, App. Band Lanczos).

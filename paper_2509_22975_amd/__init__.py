@@ -90,13 +90,15 @@ def lib():
                                                P(c_i64), c_vp]
     L.mcd_lanczos_ground.argtypes = [c_vp, P(McdLanczosCfg), c_vp, P(c_dbl), c_vp, P(c_dbl),
                                      P(c_dbl), P(McdSolveInfo), c_vp]
+    L.mcd_batch_lanczos_ground.argtypes = [P(c_vp), c_i32, P(McdLanczosCfg), P(c_dbl), P(c_vp),
+                                           P(c_i32), P(McdSolveInfo), c_vp]
     if hasattr(L, "mcd_band_lanczos_green"):
         L.mcd_band_lanczos_green.argtypes = [P(McdModel), c_vp, c_i64, c_vp, c_dbl, c_i32,
                                              P(c_i32), P(c_i32), c_i32, P(c_dbl), P(McdBandCfg),
                                              P(c_dbl), P(c_dbl), P(c_dbl), P(McdSolveInfo), c_vp]
     for name in ("mcd_basis_build", "mcd_op_create", "mcd_op_info", "mcd_op_set_kernel", "mcd_hamiltonian_apply",
                  "mcd_hamiltonian_diagonal", "mcd_hamiltonian_connectivity", "mcd_lanczos_ground",
-                 "mcd_band_lanczos_green"):
+                 "mcd_band_lanczos_green", "mcd_batch_lanczos_ground"):
         if hasattr(L, name):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -306,6 +308,26 @@ def lanczos_ground(op: Operator, max_iter=300, tol=1e-12, seed=0, check_every=10
     _check(code, "mcd_lanczos_ground")
     si = SolveInfo.of(info)
     return e0.value, psi, a[: si.iters], b[: si.iters], si
+
+
+def batch_lanczos_ground(ops, max_iter=400, tol=1e-12, seed=0, check_every=10, min_iter=1,
+                         want_psi=True):
+    """Ground states of several operators at once (mcd_batch_lanczos_ground).
+
+    Returns (e0 list, psi list or None, iterations list, SolveInfo)."""
+    torch = _torch()
+    K = len(ops)
+    cfg = McdLanczosCfg(int(max_iter), int(check_every), float(tol), int(seed), 1, int(min_iter))
+    hs = (c_vp * K)(*[op.handle for op in ops])
+    psis = [torch.empty(op.n, dtype=torch.float64, device=op.device) for op in ops] if want_psi else None
+    pp = (c_vp * K)(*[c_vp(p.data_ptr()) for p in psis]) if want_psi else None
+    e0 = (c_dbl * K)()
+    it = (c_i32 * K)()
+    info = McdSolveInfo()
+    code = lib().mcd_batch_lanczos_ground(hs, K, ctypes.byref(cfg), e0, pp, it, ctypes.byref(info),
+                                          _stream())
+    _check(code, "mcd_batch_lanczos_ground")
+    return list(e0), psis, list(it), SolveInfo.of(info)
 
 
 def band_lanczos_green(model, keys, psi0, e0, orbitals, spins, omega, max_blocks=50,

@@ -28,4 +28,14 @@ __device__ __forceinline__ int64_t hash_find(const HashSlot *__restrict__ h, uin
     }
 }
 
+// Lanczos start value of a basis state: 2u - 1 with u the top 53 bits of
+// splitmix64's first output from the state (seed XOR key).
+__device__ __forceinline__ double start_value(uint64_t key, uint64_t seed) {
+    uint64_t z = (key ^ seed) + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+}
+
 }  // namespace mcd

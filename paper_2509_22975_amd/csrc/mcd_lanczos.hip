@@ -21,6 +21,7 @@
 #include <chrono>
 #include <vector>
 
+#include "mcd_hash.h"
 #include "mcd_internal.h"
 #include "mcd_reduce.h"
 #include "mcd_tridiag.h"
@@ -39,12 +40,7 @@ __global__ void k_start_vector(int64_t n, const uint64_t *__restrict__ keys, uin
                                double *__restrict__ out) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    uint64_t z = (keys[r] ^ seed) + 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z = z ^ (z >> 31);
-    const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
-    out[r] = 2.0 * u - 1.0;
+    out[r] = start_value(keys[r], seed);
 }
 
 __global__ __launch_bounds__(BS) void k_dot(int64_t n, const double *__restrict__ a,
