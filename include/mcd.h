@@ -191,6 +191,23 @@ int mcd_hamiltonian_connectivity(const mcd_op *op, int64_t row0, int64_t row1, i
                                  int64_t *count_out, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * mcd_hamiltonian_contract -- derivatives of H~ with respect to the model
+ * parameters of Eq. hubbard_model, contracted with two vectors:
+ *   d_t[q]   = <a| dH~/dt_q |b>   for every listed bond q (the hop operator of
+ *              the pair, both spins and directions, restricted to the basis;
+ *              bonds listed twice both receive the pair's value),
+ *   d_U[i]   = <a| dH~/dU_i |b>   = sum_r a_r b_r n_{i up} n_{i dn},
+ *   d_eps[i] = <a| dH~/deps_i |b> = sum_r a_r b_r (n_{i up} + n_{i dn}).
+ * With a = b = the normalised ground state these are dE0/dtheta
+ * (Hellmann-Feynman).  a_dev, b_dev: [n] double.  `model` must be the model
+ * the operator was built from.  d_t [n_bonds], d_U [n_orb], d_eps [n_orb]:
+ * host outputs (any may be NULL).  One pass on the GPU; synchronises.
+ * ------------------------------------------------------------------------- */
+int mcd_hamiltonian_contract(const mcd_op *op, const mcd_model *model, const double *a_dev,
+                             const double *b_dev, double *d_t, double *d_U, double *d_eps,
+                             void *stream);
+
+/* ---------------------------------------------------------------------------
  * mcd_lanczos_ground -- lowest eigenpair of H~ by Lanczos (App. Lanczos,
  * Eqs. next_vector / an_bn; ground state rebuilt by Eq. change_basis).
  *

@@ -90,6 +90,8 @@ def lib():
                                                P(c_i64), c_vp]
     L.mcd_lanczos_ground.argtypes = [c_vp, P(McdLanczosCfg), c_vp, P(c_dbl), c_vp, P(c_dbl),
                                      P(c_dbl), P(McdSolveInfo), c_vp]
+    L.mcd_hamiltonian_contract.argtypes = [c_vp, P(McdModel), c_vp, c_vp, P(c_dbl), P(c_dbl),
+                                           P(c_dbl), c_vp]
     L.mcd_batch_lanczos_ground.argtypes = [P(c_vp), c_i32, P(McdLanczosCfg), P(c_dbl), P(c_vp),
                                            P(c_i32), P(McdSolveInfo), c_vp]
     if hasattr(L, "mcd_band_lanczos_green"):
@@ -98,7 +100,8 @@ def lib():
                                              P(c_dbl), P(c_dbl), P(c_dbl), P(McdSolveInfo), c_vp]
     for name in ("mcd_basis_build", "mcd_op_create", "mcd_op_info", "mcd_op_set_kernel", "mcd_hamiltonian_apply",
                  "mcd_hamiltonian_diagonal", "mcd_hamiltonian_connectivity", "mcd_lanczos_ground",
-                 "mcd_band_lanczos_green", "mcd_batch_lanczos_ground"):
+                 "mcd_band_lanczos_green", "mcd_batch_lanczos_ground",
+                 "mcd_hamiltonian_contract"):
         if hasattr(L, name):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -250,6 +253,21 @@ class Operator:
                "mcd_hamiltonian_connectivity")
         k = cnt.value
         return r[:k].cpu().numpy(), c[:k].cpu().numpy(), v[:k].cpu().numpy()
+
+    def contract(self, a, b=None):
+        """(d_t [n_bonds], d_U [n_orb], d_eps [n_orb]) = <a| dH~/dtheta |b> (numpy)."""
+        b = a if b is None else b
+        m = self.model
+        dt = np.zeros(len(m.bonds))
+        dU = np.zeros(m.n_orb)
+        de = np.zeros(m.n_orb)
+        _check(lib().mcd_hamiltonian_contract(self.handle, ctypes.byref(self._mb.s),
+                                              c_vp(a.data_ptr()), c_vp(b.data_ptr()),
+                                              dt.ctypes.data_as(P(c_dbl)),
+                                              dU.ctypes.data_as(P(c_dbl)),
+                                              de.ctypes.data_as(P(c_dbl)), _stream()),
+               "mcd_hamiltonian_contract")
+        return dt, dU, de
 
     def close(self):
         if self._h:

@@ -59,8 +59,9 @@ int prepare_model(const mcd_model *m, HostModel *hm) {
     int nb = 0;
     hm->ok_classes = true;
     for (auto &e : merged) {
+        // zero-amplitude pairs are kept: their elements are zero, but the
+        // derivative of H with respect to their amplitude is not
         double t = e.second;
-        if (t == 0.0) continue;
         int i = e.first.first, j = e.first.second;
         DevBond &b = d.bonds[nb++];
         b.mask = (1u << i) | (1u << j);

@@ -1,0 +1,118 @@
+// Parameter derivatives of H~ contracted with two vectors:
+//   <a| dH~/dt_b |b>   for every listed bond b (the hop operator of the pair,
+//                      both spins, both directions, discarded outside F~),
+//   <a| dH~/dU_i |b>   = sum_r a_r b_r n_{i up} n_{i dn}(r),
+//   <a| dH~/deps_i |b> = sum_r a_r b_r (n_{i up} + n_{i dn})(r).
+// With a = b = |Omega> these are the Hellmann-Feynman derivatives dE0/dtheta
+// of the ground-state energy (Eq. hubbard_model with theta = t_ij, U_i, eps_i).
+// One pass over the rows; each workgroup keeps one partial per parameter and
+// the partials are added in index order (deterministic).
+#include <algorithm>
+#include <vector>
+
+#include "mcd_hash.h"
+#include "mcd_internal.h"
+#include "mcd_reduce.h"
+
+namespace mcd {
+
+static constexpr int GBS = 256;
+
+// part[p * nblk + block] for p in [0, NB + 2 n_orb): merged bonds, U_i, eps_i.
+__global__ __launch_bounds__(GBS) void k_contract(int64_t n, const uint64_t *__restrict__ keys,
+                                                  const DevModel *__restrict__ m,
+                                                  const HashSlot *__restrict__ h, uint64_t hmask,
+                                                  const double *__restrict__ a,
+                                                  const double *__restrict__ b,
+                                                  double *__restrict__ part) {
+    const int64_t r = (int64_t)blockIdx.x * GBS + threadIdx.x;
+    const bool own = r < n;
+    const uint64_t key = own ? keys[r] : 0ull;
+    const double ar = own ? a[r] : 0.0;
+    const double br = own ? b[r] : 0.0;
+    const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
+    const int nb = m->n_bonds, no = m->n_orb;
+    const int64_t nblk = gridDim.x;
+    for (int q = 0; q < nb; q++) {
+        double c = 0.0;
+        if (own) {
+            const uint32_t mask = m->bonds[q].mask, between = m->bonds[q].between;
+            if (__popc(up & mask) == 1) {
+                const int64_t col = hash_find(h, hmask, key ^ ((uint64_t)mask << 32));
+                if (col >= 0) c += (__popc(up & between) & 1) ? -b[col] : b[col];
+            }
+            if (__popc(dn & mask) == 1) {
+                const int64_t col = hash_find(h, hmask, key ^ (uint64_t)mask);
+                if (col >= 0) c += (__popc(dn & between) & 1) ? -b[col] : b[col];
+            }
+            c *= ar;
+        }
+        c = block_sum<GBS>(c);
+        if (threadIdx.x == 0) part[(int64_t)q * nblk + blockIdx.x] = c;
+    }
+    for (int i = 0; i < no; i++) {
+        const double nu = (double)((up >> i) & 1u), nd = (double)((dn >> i) & 1u);
+        const double ab = ar * br;
+        double cu = block_sum<GBS>(ab * (nu * nd));
+        if (threadIdx.x == 0) part[(int64_t)(nb + i) * nblk + blockIdx.x] = cu;
+        double ce = block_sum<GBS>(ab * (nu + nd));
+        if (threadIdx.x == 0) part[(int64_t)(nb + no + i) * nblk + blockIdx.x] = ce;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_contract_reduce(int np, int64_t nblk,
+                                                         const double *__restrict__ part,
+                                                         double *__restrict__ out) {
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (p >= np) return;
+    double s = 0.0;
+    for (int64_t c = lane; c < nblk; c += 64) s += part[(int64_t)p * nblk + c];
+    s = wave_sum(s);
+    if (lane == 0) out[p] = s;
+}
+
+}  // namespace mcd
+
+using namespace mcd;
+
+extern "C" int mcd_hamiltonian_contract(const mcd_op *op, const mcd_model *model,
+                                        const double *a_dev, const double *b_dev, double *d_t,
+                                        double *d_U, double *d_eps, void *stream) {
+    MCD_REQUIRE(op && model && a_dev && b_dev, MCD_E_INVALID, "op, model, a, b required");
+    MCD_REQUIRE(model->n_orb == op->hm.dm.n_orb, MCD_E_INVALID,
+                "model has %d orbitals, operator %d", model->n_orb, op->hm.dm.n_orb);
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = op->hm.dm.n_bonds, no = op->hm.dm.n_orb;
+    const int np = nb + 2 * no;
+    const int64_t nblk = std::max<int64_t>(1, (op->n + GBS - 1) / GBS);
+    double *part = nullptr, *out = nullptr;
+    MCD_HIP(hipMalloc(&part, (size_t)np * nblk * sizeof(double)));
+    MCD_HIP(hipMalloc(&out, (size_t)np * sizeof(double)));
+    hipLaunchKernelGGL(k_contract, dim3((unsigned)nblk), dim3(GBS), 0, s, op->n, op->d_keys,
+                       op->d_model, op->d_hash, op->hash_mask, a_dev, b_dev, part);
+    hipLaunchKernelGGL(k_contract_reduce, dim3((unsigned)((np + 3) / 4)), dim3(256), 0, s, np,
+                       nblk, part, out);
+    std::vector<double> h(np);
+    MCD_HIP(hipMemcpyAsync(h.data(), out, np * sizeof(double), hipMemcpyDeviceToHost, s));
+    MCD_HIP(hipStreamSynchronize(s));
+    MCD_HIP(hipFree(part));
+    MCD_HIP(hipFree(out));
+    // listed bond -> merged pair (bonds listed twice share the pair's derivative)
+    if (d_t) {
+        for (int q = 0; q < model->n_bonds; q++) {
+            const int i = std::min(model->bond_i[q], model->bond_j[q]);
+            const int j = std::max(model->bond_i[q], model->bond_j[q]);
+            const uint32_t mask = (1u << i) | (1u << j);
+            double v = 0.0;
+            for (int mb = 0; mb < nb; mb++)
+                if (op->hm.dm.bonds[mb].mask == mask) v = h[mb];
+            d_t[q] = v;
+        }
+    }
+    for (int i = 0; i < no; i++) {
+        if (d_U) d_U[i] = h[nb + i];
+        if (d_eps) d_eps[i] = h[nb + no + i];
+    }
+    return MCD_OK;
+}
