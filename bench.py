@@ -167,6 +167,24 @@ def batch_c3(mcd, W, torch, n_inst=32):
     return out
 
 
+def step_sampler_16(mcd, W, torch):
+    """The paper's step sampler on its own 16-site workload: 1D ring, U = 8,
+    mu = 4, half filling, f = 0.05 -> N_f = 8,281,845, beta = 0.2."""
+    m = W.chain(16, t=1.0, U=8.0, mu=4.0, pbc=True)
+    st = W.neel_start(m)
+    mcd.basis_build(m, "steps", start_key=st, seed=1, beta_s=0.2, max_steps=100000, n_f=10000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k, steps = mcd.basis_build(m, "steps", start_key=st, seed=1, beta_s=0.2, max_steps=100000,
+                               n_f=8281845)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": "paper step sampler, 16-site ring U=8 mu=4 (8,8), beta=0.2, "
+                        "N_f=8,281,845 (f=0.05)", "n_states": int(k.numel()), "steps": steps,
+            "seconds": round(dt, 3),
+            "paper_context": "about 10 minutes in the paper (hardware not stated)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +194,8 @@ def main():
     ap.add_argument("--storage", default="csr")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the plain-vs-chosen E0 + G comparison")
+    ap.add_argument("--no-sampler", action="store_true",
+                    help="skip the 16-site step-sampler timing")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 32-instance batched ground-state comparison")
     ap.add_argument("--copy-probe", action="store_true",
@@ -301,6 +321,8 @@ def main():
         out["pipeline_e0_green"] = pipeline_c3(mcd, W, torch)
     if not args.no_batch:
         out["batch_ground_states"] = batch_c3(mcd, W, torch)
+    if not args.no_sampler:
+        out["step_sampler"] = step_sampler_16(mcd, W, torch)
     if args.copy_probe:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)

@@ -60,7 +60,7 @@ enum {
 
 enum { MCD_STORAGE_AUTO = 0, MCD_STORAGE_ON_THE_FLY = 1, MCD_STORAGE_CSR = 2 };
 enum { MCD_F64 = 0, MCD_F32 = 1 };
-enum { MCD_BASIS_FULL = 0, MCD_BASIS_CHAIN = 1 };
+enum { MCD_BASIS_FULL = 0, MCD_BASIS_CHAIN = 1, MCD_BASIS_STEPS = 2 };
 
 typedef struct mcd_model {
     int32_t n_orb;            /* orbitals (sites), 1..32 */
@@ -97,6 +97,19 @@ int mcd_version(void);
  *   chain first), sorted.  steps_out = steps the chain ran.
  *   The chain itself is sequential and runs on the host; recording,
  *   de-duplication, first-visit selection and sorting run on the GPU.
+ * mode MCD_BASIS_STEPS: the paper's own sampler (Sec. Subspace of the ground
+ *   state, the numbered "step" procedure, Eq. boltzmann_factor), entirely on
+ *   the GPU.  F~ and the frontier start as {start_key}.  A step applies every
+ *   hop h in [0, 4 n_bonds) (bond h >> 2, spin (h >> 1) & 1, direction h & 1)
+ *   to every frontier state (ascending keys); a possible hop is accepted iff
+ *   u < exp(-beta_s U n_U), n_U the double occupation of the proposed state on
+ *   the orbitals with U != 0 (all of which must share one U), u = (z >> 11)
+ *   2^-53, z = f(f(f(seed ^ step G) ^ parent) ^ h), f(x) the splitmix64 output
+ *   function of x + G, G = 0x9E3779B97F4A7C15, step counted from 1.  Accepted
+ *   states (each once, first occurrence in (parent rank, h) order) form the
+ *   next frontier, whether new or not; new ones join F~ in that order until
+ *   it holds n_f states.  An empty frontier is refilled with F~.  steps_out =
+ *   steps taken; max_steps bounds them; burn_in is ignored.
  * keys_dev: [cap] device output.  Returns MCD_E_CAPACITY if cap is too
  * small, MCD_E_SECTOR if start_key is not in the sector.  Synchronises.
  * ------------------------------------------------------------------------- */

@@ -139,3 +139,148 @@ def chain_python(model, start: int, seed: int, n_f: int, burn_in: int, max_steps
         if step > burn_in:
             seen.add((spins[0] << 32) | spins[1])
     return np.array(sorted(seen), dtype=np.uint64), step
+
+
+# ---------------------------------------------------------------------------
+# The paper's MCD sampler (Sec. Subspace of the ground state, the numbered
+# "step" procedure and Eq. boltzmann_factor).
+#
+# Reading used (the paper leaves the RNG and tie-breaks open):
+#  * a step takes the frontier (the states accepted in the previous step)
+#    in ascending key order and applies every hop to each parent, hops in
+#    the order (bond, spin up then down, direction i->j then j->i), i.e. hop
+#    index h in [0, 4 n_bonds) with bond h >> 2, spin (h >> 1) & 1, dir h & 1;
+#  * a possible hop is accepted with probability min(exp(-beta U n_U), 1),
+#    where U is the (uniform) on-site repulsion of the orbitals with U != 0
+#    and n_U the double occupation of the proposed state on those orbitals;
+#    the uniform number is u = (z >> 11) 2^-53 with
+#    z = f(f(f(seed ^ (step * G)) ^ parent) ^ h), f(x) = the splitmix64
+#    output function applied to x + G, G = 0x9E3779B97F4A7C15;
+#  * the next frontier is every accepted proposal (new or already in F~),
+#    each state once; accepted proposals are ordered by (parent rank, h) and
+#    a state keeps its first occurrence;
+#  * new states join F~ in that order; the sampling stops as soon as F~
+#    holds n_f states (mid-step), or after max_steps steps;
+#  * an empty frontier is refilled with all of F~.
+# ---------------------------------------------------------------------------
+G64 = 0x9E3779B97F4A7C15
+
+
+def _f64(x):
+    z = (x + G64) & MASK
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK
+    return z ^ (z >> 31)
+
+
+def _uniform_u(seed, step, parent, h):
+    z = _f64((seed ^ ((step * G64) & MASK)) & MASK)
+    z = _f64(z ^ parent)
+    z = _f64(z ^ h)
+    return (z >> 11) * (1.0 / 9007199254740992.0)
+
+
+def _u_and_table(model, beta):
+    us = sorted(set(float(u) for u in model.U if u != 0.0))
+    if len(us) > 1:
+        raise ValueError("BFS sampler needs one common U on the interacting orbitals")
+    U0 = us[0] if us else 0.0
+    umask = sum(1 << i for i in range(model.n_orb) if model.U[i] != 0.0)
+    table = [math.exp(-beta * U0 * k) for k in range(model.n_orb + 1)]
+    return umask, table
+
+
+def bfs_python(model, start, seed, beta, n_f, max_steps):
+    """Plain-loop implementation of the MCD step sampler (small cases)."""
+    umask, table = _u_and_table(model, beta)
+    bonds = [tuple(sorted(b[:2])) for b in model.bonds]
+    H = 4 * len(bonds)
+    S = [start]
+    inS = {start}
+    F = [start]
+    step = 0
+    while len(S) < n_f and step < max_steps:
+        step += 1
+        if not F:
+            F = sorted(S)
+        F = sorted(F)
+        seen = {}
+        order = []
+        for rank, x in enumerate(F):
+            up, dn = x >> 32, x & 0xFFFFFFFF
+            for h in range(H):
+                i, j = bonds[h >> 2]
+                spin, d = (h >> 1) & 1, h & 1
+                src, dst = (i, j) if d == 0 else (j, i)
+                s = up if spin == 0 else dn
+                if not ((s >> src) & 1) or ((s >> dst) & 1):
+                    continue
+                s2 = s ^ ((1 << src) | (1 << dst))
+                y = (s2 << 32) | dn if spin == 0 else (up << 32) | s2
+                nu = bin((y >> 32) & y & umask).count("1")
+                if _uniform_u(seed, step, x, h) < table[nu]:
+                    if y not in seen:
+                        seen[y] = len(order)
+                        order.append(y)
+        for y in order:
+            if y not in inS:
+                S.append(y)
+                inS.add(y)
+                if len(S) >= n_f:
+                    break
+        F = order
+    return np.array(sorted(S), dtype=np.uint64), step
+
+
+def bfs_numpy(model, start, seed, beta, n_f, max_steps):
+    """Vectorised implementation of the same sampler (one step = array ops)."""
+    umask, table = _u_and_table(model, beta)
+    table = np.array(table)
+    bi = np.array([min(b[0], b[1]) for b in model.bonds], dtype=np.uint64)
+    bj = np.array([max(b[0], b[1]) for b in model.bonds], dtype=np.uint64)
+    H = 4 * len(bi)
+    h = np.arange(H, dtype=np.uint64)
+    hb = (h >> np.uint64(2)).astype(np.int64)
+    spin = (h >> np.uint64(1)) & np.uint64(1)
+    d = h & np.uint64(1)
+    src = np.where(d == 0, bi[hb], bj[hb])
+    dst = np.where(d == 0, bj[hb], bi[hb])
+    one = np.uint64(1)
+    S = np.array([start], dtype=np.uint64)
+    F = np.array([start], dtype=np.uint64)
+    step = 0
+    with np.errstate(over="ignore"):
+        while len(S) < n_f and step < max_steps:
+            step += 1
+            if len(F) == 0:
+                F = np.sort(S)
+            F = np.sort(F)
+            up = (F >> np.uint64(32))[:, None]
+            dn = (F & np.uint64(0xFFFFFFFF))[:, None]
+            s = np.where(spin[None, :] == 0, up, dn)
+            ok = (((s >> src[None, :]) & one) == 1) & (((s >> dst[None, :]) & one) == 0)
+            s2 = s ^ ((one << src[None, :]) | (one << dst[None, :]))
+            y = np.where(spin[None, :] == 0, (s2 << np.uint64(32)) | dn, (up << np.uint64(32)) | s2)
+            nu = np.bitwise_count((y >> np.uint64(32)) & y & np.uint64(umask)).astype(np.int64)
+            # counter-based uniforms
+            G = np.uint64(G64)
+            def f(x):
+                z = x + G
+                z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+                z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+                return z ^ (z >> np.uint64(31))
+            z0 = f(np.uint64(seed) ^ (np.uint64(step) * G))
+            z = f(f(z0 ^ F[:, None]) ^ h[None, :])
+            u = (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+            acc = ok & (u < table[nu])
+            ys = y[acc]                          # row-major = (parent rank, h) order
+            if len(ys) == 0:
+                F = ys
+                continue
+            uniq, first = np.unique(ys, return_index=True)
+            order = uniq[np.argsort(first, kind="stable")]
+            new = order[~np.isin(order, S)]
+            room = n_f - len(S)
+            S = np.concatenate([S, new[:room]])
+            F = order
+    return np.sort(S), step

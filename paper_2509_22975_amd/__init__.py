@@ -163,7 +163,7 @@ def basis_build(model, mode="full", n_up=None, n_dn=None, start_key=0, seed=0, b
     n_up = model.n_up if n_up is None else n_up
     n_dn = model.n_dn if n_dn is None else n_dn
     mb = _ModelBuf(model)
-    m = 0 if mode == "full" else 1
+    m = {"full": 0, "chain": 1, "steps": 2}[mode]
     if cap is None:
         import math
         cap = math.comb(model.n_orb, n_up) * math.comb(model.n_orb, n_dn) if m == 0 else int(n_f)

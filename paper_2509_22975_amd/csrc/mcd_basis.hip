@@ -156,6 +156,314 @@ struct ChainWalker {
     }
 };
 
+// ---------------------------------------------------------------------------
+// The paper's step sampler (Sec. Subspace of the ground state, numbered step
+// procedure; acceptance Eq. boltzmann_factor).  One step on the GPU:
+//   k_bfs_expand     every (frontier parent, hop) pair: possible? accepted
+//                    with probability table[n_U] (n_U on the interacting
+//                    orbitals) against a counter-based uniform; accepted
+//                    images compacted with one atomic per wavefront, tagged
+//                    with their order (parent rank * H + hop);
+//   radix sort by key, k_bfs_heads / scan / k_bfs_unique: each state once,
+//                    with its first order, and whether it is already in F~;
+//   the unique states (sorted by key) are the next frontier; the new ones,
+//   radix-sorted by order, join F~ until it holds n_f states.
+struct BfsHop {
+    uint32_t src, dst, spin, pad;
+};
+
+__device__ __forceinline__ uint64_t bfs_mix(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_bfs_expand(int64_t total, int H, const uint64_t *__restrict__ F,
+                             const BfsHop *__restrict__ hops, uint32_t umask,
+                             const double *__restrict__ table, uint64_t seed, uint64_t step,
+                             uint64_t *__restrict__ out_key, uint64_t *__restrict__ out_ord,
+                             unsigned long long *counter) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool acc = false;
+    uint64_t y = 0;
+    if (idx < total) {
+        const int64_t p = idx / H;
+        const int h = (int)(idx % H);
+        const uint64_t x = F[p];
+        const uint32_t up = (uint32_t)(x >> 32), dn = (uint32_t)x;
+        const BfsHop hp = hops[h];
+        const uint32_t sv = hp.spin ? dn : up;
+        if (((sv >> hp.src) & 1u) && !((sv >> hp.dst) & 1u)) {
+            const uint32_t s2 = sv ^ ((1u << hp.src) | (1u << hp.dst));
+            y = hp.spin ? (((uint64_t)up << 32) | s2) : (((uint64_t)s2 << 32) | dn);
+            const int nu = __popc((uint32_t)(y >> 32) & (uint32_t)y & umask);
+            const uint64_t z = bfs_mix(bfs_mix(bfs_mix(seed ^ (step * 0x9E3779B97F4A7C15ull)) ^ x) ^
+                                       (uint64_t)h);
+            const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+            acc = u < table[nu];
+        }
+    }
+    // one atomic per wavefront
+    const unsigned long long ball = __ballot(acc);
+    const int lane = __lane_id();
+    unsigned long long base = 0;
+    if (lane == __ffsll((long long)ball) - 1 && ball != 0ull) base = atomicAdd(counter, (unsigned long long)__popcll(ball));
+    base = __shfl(base, __ffsll((long long)ball) - 1 >= 0 ? __ffsll((long long)ball) - 1 : 0, 64);
+    if (acc) {
+        const unsigned long long pos = base + __popcll(ball & ((1ull << lane) - 1ull));
+        out_key[pos] = y;
+        out_ord[pos] = (uint64_t)idx;
+    }
+}
+
+__global__ void k_bfs_heads(int64_t m, const uint64_t *__restrict__ k, int64_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) flag[i] = (i == 0 || k[i] != k[i - 1]) ? 1 : 0;
+    if (i == m) flag[m] = 0;
+}
+
+__device__ __forceinline__ bool set_has(const uint64_t *__restrict__ t, uint64_t mask, uint64_t key) {
+    uint64_t p = vmix(key) & mask;
+    for (;;) {
+        const uint64_t v = t[p];
+        if (v == key) return true;
+        if (v == kEmpty) return false;
+        p = (p + 1) & mask;
+    }
+}
+
+__global__ void k_bfs_unique(int64_t m, const uint64_t *__restrict__ k, const uint64_t *__restrict__ ord,
+                             const int64_t *__restrict__ pos, const uint64_t *__restrict__ set,
+                             uint64_t smask, uint64_t *__restrict__ ukey, uint64_t *__restrict__ uord,
+                             int64_t *__restrict__ isnew) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    if (!(i == 0 || k[i] != k[i - 1])) return;
+    uint64_t best = ord[i];
+    for (int64_t j = i + 1; j < m && k[j] == k[i]; j++) best = min(best, ord[j]);
+    const int64_t q = pos[i];
+    ukey[q] = k[i];
+    uord[q] = best;
+    isnew[q] = set_has(set, smask, k[i]) ? 0 : 1;
+}
+
+__global__ void k_bfs_compact_new(int64_t u, const uint64_t *__restrict__ ukey,
+                                  const uint64_t *__restrict__ uord, const int64_t *__restrict__ isnew,
+                                  const int64_t *__restrict__ npos, uint64_t *__restrict__ nkey,
+                                  uint64_t *__restrict__ nord) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= u || !isnew[i]) return;
+    nkey[npos[i]] = ukey[i];
+    nord[npos[i]] = uord[i];
+}
+
+__global__ void k_set_insert(int64_t m, const uint64_t *__restrict__ keys, uint64_t *set,
+                             uint64_t mask, uint64_t *__restrict__ list, int64_t list0) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint64_t key = keys[i];
+    uint64_t p = vmix(key) & mask;
+    for (;;) {
+        const unsigned long long prev = atomicCAS((unsigned long long *)&set[p],
+                                                  (unsigned long long)kEmpty, (unsigned long long)key);
+        if (prev == kEmpty || prev == key) break;
+        p = (p + 1) & mask;
+    }
+    list[list0 + i] = key;
+}
+
+static int build_bfs(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t *keys_dev,
+                     int64_t cap, int64_t *n_out, int64_t *steps_out, hipStream_t s) {
+    const uint64_t lim = model->n_orb >= 32 ? 0xffffffffull : ((1ull << model->n_orb) - 1ull);
+    const uint64_t su = cfg->start_key >> 32, sd = cfg->start_key & 0xffffffffull;
+    MCD_REQUIRE((su & ~lim) == 0 && (sd & ~lim) == 0 && __builtin_popcountll(su) == cfg->n_up &&
+                    __builtin_popcountll(sd) == cfg->n_dn,
+                MCD_E_SECTOR, "start key is not in the (%d, %d) sector", cfg->n_up, cfg->n_dn);
+    MCD_REQUIRE(model->n_bonds >= 1 && cfg->n_f >= 1, MCD_E_INVALID, "need bonds and n_f >= 1");
+    MCD_REQUIRE(cfg->n_f <= cap, MCD_E_CAPACITY, "cap %lld < n_f %lld", (long long)cap,
+                (long long)cfg->n_f);
+    // common U of the interacting orbitals, acceptance table exp(-beta U k)
+    double U0 = 0.0;
+    uint32_t umask = 0;
+    for (int i = 0; i < model->n_orb; i++) {
+        if (model->U[i] == 0.0) continue;
+        MCD_REQUIRE(U0 == 0.0 || model->U[i] == U0, MCD_E_INVALID,
+                    "the step sampler needs one common U on the interacting orbitals");
+        U0 = model->U[i];
+        umask |= 1u << i;
+    }
+    double table[MCD_MAX_ORB + 1];
+    for (int k = 0; k <= MCD_MAX_ORB; k++) table[k] = exp(-cfg->beta_s * U0 * (double)k);
+    const int H = 4 * model->n_bonds;
+    std::vector<BfsHop> hh(H);
+    for (int h = 0; h < H; h++) {
+        const int b = h >> 2;
+        const uint32_t i = (uint32_t)std::min(model->bond_i[b], model->bond_j[b]);
+        const uint32_t j = (uint32_t)std::max(model->bond_i[b], model->bond_j[b]);
+        const bool rev = (h & 1) != 0;
+        hh[h] = BfsHop{rev ? j : i, rev ? i : j, (uint32_t)((h >> 1) & 1), 0u};
+    }
+    const int64_t nf = cfg->n_f;
+    uint64_t smask = 1023;
+    while (smask + 1 < (uint64_t)(4 * nf)) smask = (smask << 1) | 1;
+    // buffers (grown on demand)
+    BfsHop *d_hops = nullptr;
+    double *d_table = nullptr;
+    uint64_t *set = nullptr, *F = nullptr, *ak = nullptr, *ao = nullptr, *bk = nullptr, *bo = nullptr;
+    uint64_t *uk = nullptr, *uo = nullptr, *nk = nullptr, *no = nullptr, *nk2 = nullptr, *no2 = nullptr;
+    int64_t *flag = nullptr, *pos = nullptr, *isnew = nullptr, *npos = nullptr;
+    unsigned long long *cnt = nullptr;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    int64_t capA = 0, capF = 0, capM = 0;
+    auto cleanup = [&]() {
+        for (void *p : {(void *)d_hops, (void *)d_table, (void *)set, (void *)F, (void *)ak,
+                        (void *)ao, (void *)bk, (void *)bo, (void *)uk, (void *)uo, (void *)nk,
+                        (void *)no, (void *)nk2, (void *)no2, (void *)flag, (void *)pos,
+                        (void *)isnew, (void *)npos, (void *)cnt, tmp})
+            if (p) (void)hipFree(p);
+    };
+#define CK(expr)                                                              \
+    do {                                                                      \
+        hipError_t e_ = (expr);                                               \
+        if (e_ != hipSuccess) {                                               \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));         \
+            cleanup();                                                        \
+            return MCD_E_HIP;                                                 \
+        }                                                                     \
+    } while (0)
+    auto grow = [&](void **p, int64_t bytes) -> hipError_t {
+        if (*p) {
+            hipError_t e = hipFree(*p);
+            if (e != hipSuccess) return e;
+        }
+        *p = nullptr;
+        return hipMalloc(p, std::max<int64_t>(bytes, 8));
+    };
+    auto need_tmp = [&](size_t b) -> hipError_t {
+        if (b <= tmp_bytes) return hipSuccess;
+        if (tmp) (void)hipFree(tmp);
+        tmp = nullptr;
+        tmp_bytes = b;
+        return hipMalloc(&tmp, b);
+    };
+    CK(hipMalloc(&d_hops, H * sizeof(BfsHop)));
+    CK(hipMemcpyAsync(d_hops, hh.data(), H * sizeof(BfsHop), hipMemcpyHostToDevice, s));
+    CK(hipMalloc(&d_table, sizeof(table)));
+    CK(hipMemcpyAsync(d_table, table, sizeof(table), hipMemcpyHostToDevice, s));
+    CK(hipMalloc(&set, (smask + 1) * sizeof(uint64_t)));
+    CK(hipMemsetAsync(set, 0xff, (smask + 1) * sizeof(uint64_t), s));
+    CK(hipMalloc(&cnt, 2 * sizeof(unsigned long long)));
+    // F~ starts with the start state; the frontier too
+    CK(hipMemcpyAsync(keys_dev, &cfg->start_key, sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_set_insert, dim3(1), dim3(64), 0, s, (int64_t)1, keys_dev, set, smask,
+                       keys_dev, (int64_t)0);
+    capF = 1024;
+    CK(grow((void **)&F, capF * 8));
+    CK(hipMemcpyAsync(F, &cfg->start_key, sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    int64_t nF = 1, nS = 1, step = 0;
+    while (nS < nf && step < cfg->max_steps) {
+        step++;
+        if (nF == 0) {   // refill the frontier with all of F~ (sorted)
+            if (capF < nS) {
+                capF = nS;
+                CK(grow((void **)&F, capF * 8));
+            }
+            size_t b = 0;
+            CK(hipcub::DeviceRadixSort::SortKeys(nullptr, b, keys_dev, F, (int)nS, 0, 64, s));
+            CK(need_tmp(b));
+            b = tmp_bytes;
+            CK(hipcub::DeviceRadixSort::SortKeys(tmp, b, keys_dev, F, (int)nS, 0, 64, s));
+            nF = nS;
+        }
+        const int64_t total = nF * (int64_t)H;
+        if (capA < total) {       // expansion output: one slot per (parent, hop)
+            capA = total;
+            for (uint64_t **p : {&ak, &ao}) CK(grow((void **)p, capA * 8));
+        }
+        CK(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
+        hipLaunchKernelGGL(k_bfs_expand, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                           total, H, F, d_hops, umask, d_table, cfg->seed, (uint64_t)step, ak, ao,
+                           cnt);
+        CK(hipGetLastError());
+        unsigned long long na = 0;
+        CK(hipMemcpyAsync(&na, cnt, sizeof(na), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        const int64_t m = (int64_t)na;
+        if (m == 0) {
+            nF = 0;
+            continue;
+        }
+        if (capM < m) {           // accepted proposals only
+            capM = m;
+            for (uint64_t **p : {&bk, &bo, &uk, &uo, &nk, &no, &nk2, &no2})
+                CK(grow((void **)p, capM * 8));
+            for (int64_t **p : {&flag, &pos, &isnew, &npos}) CK(grow((void **)p, (capM + 1) * 8));
+        }
+        size_t b1 = 0, b2 = 0, b3 = 0;
+        CK(hipcub::DeviceRadixSort::SortPairs(nullptr, b1, ak, bk, ao, bo, (int)m, 0, 64, s));
+        CK(hipcub::DeviceScan::ExclusiveSum(nullptr, b2, flag, pos, m + 1, s));
+        CK(hipcub::DeviceRadixSort::SortPairs(nullptr, b3, no, no2, nk, nk2, (int)m, 0, 64, s));
+        CK(need_tmp(std::max(b1, std::max(b2, b3))));
+        size_t tb = tmp_bytes;
+        CK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, ak, bk, ao, bo, (int)m, 0, 64, s));
+        hipLaunchKernelGGL(k_bfs_heads, dim3((unsigned)((m + 1 + 255) / 256)), dim3(256), 0, s, m, bk,
+                           flag);
+        tb = tmp_bytes;
+        CK(hipcub::DeviceScan::ExclusiveSum(tmp, tb, flag, pos, m + 1, s));
+        int64_t nu = 0;
+        CK(hipMemcpyAsync(&nu, pos + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        hipLaunchKernelGGL(k_bfs_unique, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, m, bk, bo,
+                           pos, set, smask, uk, uo, isnew);
+        CK(hipStreamSynchronize(s));
+        // new states, in order of first occurrence
+        CK(hipMemsetAsync(isnew + nu, 0, sizeof(int64_t), s));
+        tb = tmp_bytes;
+        CK(hipcub::DeviceScan::ExclusiveSum(tmp, tb, isnew, npos, nu + 1, s));
+        int64_t nn = 0;
+        CK(hipMemcpyAsync(&nn, npos + nu, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        hipLaunchKernelGGL(k_bfs_compact_new, dim3((unsigned)((nu + 255) / 256)), dim3(256), 0, s, nu,
+                           uk, uo, isnew, npos, nk, no);
+        CK(hipStreamSynchronize(s));
+        if (nn > 0) {
+            tb = tmp_bytes;
+            CK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, no, no2, nk, nk2, (int)nn, 0, 64, s));
+            const int64_t take = std::min<int64_t>(nn, nf - nS);
+            hipLaunchKernelGGL(k_set_insert, dim3((unsigned)((take + 255) / 256)), dim3(256), 0, s,
+                               take, nk2, set, smask, keys_dev, nS);
+            CK(hipGetLastError());
+            nS += take;
+        }
+        // next frontier: every accepted state once (sorted by key)
+        if (capF < nu) {
+            capF = nu;
+            CK(grow((void **)&F, capF * 8));
+        }
+        CK(hipMemcpyAsync(F, uk, nu * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+        nF = nu;
+        CK(hipStreamSynchronize(s));
+    }
+    // output sorted
+    {
+        uint64_t *srt = nullptr;
+        CK(hipMalloc(&srt, nS * sizeof(uint64_t)));
+        size_t b = 0;
+        CK(hipcub::DeviceRadixSort::SortKeys(nullptr, b, keys_dev, srt, (int)nS, 0, 64, s));
+        CK(need_tmp(b));
+        b = tmp_bytes;
+        CK(hipcub::DeviceRadixSort::SortKeys(tmp, b, keys_dev, srt, (int)nS, 0, 64, s));
+        CK(hipMemcpyAsync(keys_dev, srt, nS * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+        CK(hipStreamSynchronize(s));
+        (void)hipFree(srt);
+    }
+    *n_out = nS;
+    if (steps_out) *steps_out = step;
+    cleanup();
+#undef CK
+    return MCD_OK;
+}
+
 static int build_full(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t *keys_dev,
                       int64_t cap, int64_t *n_out, hipStream_t s) {
     Binom hb;
@@ -311,6 +619,8 @@ extern "C" int mcd_basis_build(const mcd_model *model, const mcd_basis_cfg *cfg,
     if (cfg->mode == MCD_BASIS_FULL) return build_full(model, cfg, keys_dev, cap, n_out, s);
     if (cfg->mode == MCD_BASIS_CHAIN)
         return build_chain(model, cfg, keys_dev, cap, n_out, steps_out, s);
+    if (cfg->mode == MCD_BASIS_STEPS)
+        return build_bfs(model, cfg, keys_dev, cap, n_out, steps_out, s);
     set_error("basis mode %d unknown", cfg->mode);
     return MCD_E_INVALID;
 }

@@ -246,3 +246,20 @@ def test_apply_c2_full_size_sampled_rows():
             assert info["nnz"] > 0
             print("[c2] nnz", info["nnz"], "rows/block", info["rows_per_block"], flush=True)
         op.close()
+
+
+@pytest.mark.parametrize("case", ["c1", "ring4_18", "imp", "c1_beta0_full", "sq4x4_tp"])
+def test_step_sampler_bit_exact(case):
+    """The paper's step sampler on the GPU against the oracle (keys, steps)."""
+    torch, mcd = require_gpu()
+    m, nf, beta, seed = {"c1": (W.config_c1()["model"], 2000, 0.2, 7),
+                         "ring4_18": (W.chain(4, U=8.0, mu=4.0), 18, 0.2, 3),
+                         "imp": (W.impurity_plaquette_bath(3), 5000, 0.2, 7),
+                         "c1_beta0_full": (W.config_c1()["model"], 4900, 0.0, 1),
+                         "sq4x4_tp": (W.config_c2()["model"], 60000, 0.2, 5)}[case]
+    log_case("step_sampler", case=case, n_f=nf)
+    st = W.neel_start(m)
+    ko, so = sampler.bfs_numpy(m, st, seed, beta, nf, 1000)
+    kg, sg = mcd.basis_build(m, "steps", start_key=st, seed=seed, beta_s=beta, max_steps=1000,
+                             n_f=nf)
+    assert so == sg and np.array_equal(ko, mcd.keys_to_numpy(kg))

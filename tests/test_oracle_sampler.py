@@ -5,7 +5,7 @@ import pytest
 from scipy import stats
 
 import workloads as W
-from oracle import fock, sampler
+from oracle import fock, hamiltonian as ham, sampler
 
 
 def test_c_and_python_chains_agree_bit_for_bit():
@@ -65,3 +65,35 @@ def test_chain_stops_at_n_f_and_respects_cap():
     assert len(a) == 100
     b, s2 = sampler.chain_c(m, W.neel_start(m), 4, 4900, 10, 2000)
     assert s2 == 2000 and len(b) < 4900
+
+
+# --- the paper's step sampler (Sec. Subspace of the ground state) ----------
+def test_step_sampler_python_and_numpy_agree():
+    for m, nf, beta in [(W.config_c1()["model"], 2000, 0.2), (W.chain(4, U=8.0, mu=4.0), 18, 0.2),
+                        (W.impurity_plaquette_bath(3), 5000, 0.2)]:
+        st = W.neel_start(m)
+        a, sa = sampler.bfs_python(m, st, 7, beta, nf, 1000)
+        b, sb = sampler.bfs_numpy(m, st, 7, beta, nf, 1000)
+        assert sa == sb and np.array_equal(a, b) and len(a) == nf
+        fock.check_sector(a, m)
+        assert W.neel_start(m) in set(int(k) for k in a)
+
+
+def test_step_sampler_limits():
+    m = W.config_c1()["model"]
+    st = W.neel_start(m)
+    # beta = 0 accepts every hop: the whole (connected) sector is reached
+    a, _ = sampler.bfs_numpy(m, st, 1, 0.0, 4900, 1000)
+    assert np.array_equal(a, fock.sector_keys(8, 4, 4))
+    # beta = 0: the first steps are breadth-first shells around the start state
+    a2, s2 = sampler.bfs_numpy(m, st, 1, 0.0, 10**9, 2)
+    one = set()
+    H = ham.build_csr(fock.sector_keys(8, 4, 4), m)
+    keys = fock.sector_keys(8, 4, 4)
+    i0 = int(np.searchsorted(keys, np.uint64(st)))
+    d1 = set(H[i0].indices) | {i0}
+    d2 = set(j for i in d1 for j in H[i].indices) | d1
+    assert set(np.searchsorted(keys, a2)) == d2
+    # huge beta: only states without double occupation are accepted
+    a3, _ = sampler.bfs_numpy(m, st, 1, 1e3, 4900, 40)
+    assert np.all(fock.double_occupation(a3) == 0)
