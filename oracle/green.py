@@ -14,8 +14,10 @@ function, Sec. Further truncation).
   Jordan-Wigner sign of the ordering "all up orbitals, then all down":
   (-1)^(number of electrons in orbitals ordered before (i, s)).
 * ``green_from_band``: Q = rho^T S from the eigenpairs (E_m, S) of the band
-  H_eff (Eq. q_matrix) and the Lehmann sums of Eqs. green_qmatrix with
-  omega + i eta replaced by i omega_n (Matsubara frequencies).
+  H_eff (Eq. q_matrix) and the Lehmann sums of Eqs. green_qmatrix, either at
+  the real frequencies omega + i eta of the paper (eta > 0; the density of
+  states is -Im G_ii / pi) or with omega + i eta replaced by i omega_n
+  (Matsubara frequencies, eta = 0).
 * ``green_dense``: the definition, Eqs. green_plus / green_minus, by full
   diagonalisation of the N +- 1 Hamiltonians (small systems; used as a pin).
 * degenerate ground states (Sec. Subspace of the Green function, last
@@ -112,8 +114,14 @@ def green_from_band(H_plus, B_plus, H_minus, B_minus, e0, omega, max_dim=None):
     return out
 
 
+def frequency_argument(omega, eta: float = 0.0):
+    """z of the Lehmann sums: i omega_n (eta == 0) or omega + i eta (eta > 0)."""
+    omega = np.asarray(omega, dtype=np.float64)
+    return omega + 1j * eta if eta > 0 else 1j * omega
+
+
 def green_mcd(keys, model, psi0, e0, orbitals, spin, omega, max_dim=None,
-              w_t: float = 1.0, return_parts=False):
+              w_t: float = 1.0, return_parts=False, eta: float = 0.0):
     """Full MCD Green-function pipeline for one spin (Sec. GreenFunction).
 
     w_t truncation of |Omega~> -> F~+ and F~- -> start blocks c+|Omega~>,
@@ -131,12 +139,32 @@ def green_mcd(keys, model, psi0, e0, orbitals, spin, omega, max_dim=None,
         r = band_lanczos(Hx, B, max_dim=max_dim)
         E, Q = lehmann_from_band(r["T"], r["rho"])
         res[create] = (E, Q, kx, r["K"])
-    z = 1j * np.asarray(omega)
+    z = frequency_argument(omega, eta)
     Gp = green_sum(res[True][0], res[True][1], e0, z, True)
     Gm = green_sum(res[False][0], res[False][1], e0, z, False)
     if return_parts:
         return Gp + Gm, dict(plus=res[True], minus=res[False], keys_t=k_t, psi_t=p_t)
     return Gp + Gm
+
+
+def green_exact(keys, model, psi0, e0, orbitals, spin, omega, eta: float = 0.0):
+    """What band Lanczos run to exhaustion computes, written out: the Lehmann
+    sums of Eqs. green_qmatrix over every eigenpair of H~+ and H~- on F~+ and
+    F~- (dense; no target-weight cut), start vectors c+|psi0> and c|psi0>."""
+    keys = np.asarray(keys, dtype=np.uint64)
+    z = frequency_argument(omega, eta)
+    up_shift = 1 if spin == 0 else 0
+    G = 0.0
+    for create in (True, False):
+        d = 1 if create else -1
+        m2 = model.with_sector(model.n_up + d * up_shift, model.n_dn + d * (1 - up_shift))
+        kx = excited_basis(keys, orbitals, spin, create)
+        if len(kx) == 0:
+            continue
+        E, S = np.linalg.eigh(build_csr(kx, m2).toarray())
+        B = np.stack([apply_c(keys, psi0, kx, i, spin, create) for i in orbitals], axis=1)
+        G = G + green_sum(E, B.T @ S, e0, z, create)
+    return G
 
 
 def green_dense(model, gs_keys, gs_vecs, e0, orbitals, spin, z, degenerate="average"):

@@ -137,3 +137,26 @@ def test_wt_truncation():
         assert np.all(k2[1:] > k2[:-1]) and np.all(np.isin(k2, k))
         kept_w = r["psi0"][np.isin(k, k2)] ** 2
         assert kept_w.min() >= np.sort(r["psi0"] ** 2)[::-1][len(k2) - 1] - 1e-18
+
+
+def test_green_exact_equals_exhausted_band_and_definition():
+    """green_exact (all eigenpairs of H~+- on F~+-) equals band Lanczos run to
+    exhaustion on a sampled basis, and the full-sector definition on a full
+    sector; also at real frequencies with a Lorentzian width."""
+    from oracle import green as gr, sampler
+    m = W.square(3, 2, tp=-0.3, U=5.0, mu=1.0, pbc=False, n_up=3, n_dn=2)
+    keys, _ = sampler.chain_c(m, W.neel_start(m), 7, 180, 100, 10**6)
+    H = ham.build_csr(keys, m).toarray()
+    E, V = np.linalg.eigh(H)
+    for eta, om in ((0.0, W.matsubara(5, 20.0)), (0.05, np.linspace(-6, 6, 9))):
+        a = gr.green_exact(keys, m, V[:, 0], E[0], [0, 2, 5], 1, om, eta=eta)
+        b = gr.green_mcd(keys, m, V[:, 0], E[0], [0, 2, 5], 1, om, eta=eta)
+        assert np.max(np.abs(a - b)) < 1e-10 * np.max(np.abs(a))
+    kf = fock.sector_keys(6, 3, 2)
+    Hf = ham.build_csr(kf, m).toarray()
+    Ef, Vf = np.linalg.eigh(Hf)
+    om = W.matsubara(4, 10.0)
+    # every orbital selected: F~+- are then the whole N +- 1 sectors
+    a = gr.green_exact(kf, m, Vf[:, 0], Ef[0], range(6), 0, om)
+    c = gr.green_dense(m, kf, Vf[:, :1], Ef[0], range(6), 0, 1j * om)
+    assert np.max(np.abs(a - c)) < 1e-12 * np.max(np.abs(c))
