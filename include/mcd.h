@@ -302,8 +302,10 @@ int mcd_batch_lanczos_ground(mcd_op *const *ops, int32_t n_ops, const mcd_lanczo
  * a block continued fraction in complex128 on the host.
  *
  * keys_dev [n], psi0_dev [n]: ground-state basis and vector (double).
- * orb, spin: [n_sel] host; spin 0 = up, 1 = down; n_sel <= 32.
- * omega: [n_freq] host Matsubara frequencies w_n.
+ * orb, spin: [n_sel] host; spin 0 = up, 1 = down; n_sel <= 16.
+ * omega: [n_freq] host frequencies: Matsubara w_n (cfg->eta <= 0, z = i w_n)
+ *   or real w (cfg->eta > 0, z = w + i eta, the broadened real-frequency G
+ *   of Sec. Green function whose -Im G_ii / pi is the density of states).
  * G_out, Gp_out, Gm_out: host complex128 interleaved [n_freq][n_sel][n_sel]
  *   (G = G+ + G-); Gp_out / Gm_out may be NULL.
  * precision MCD_F64: float64 Krylov blocks.  MCD_F32: float32 blocks and
@@ -323,6 +325,8 @@ typedef struct mcd_band_cfg {
                                  the three-term recurrence; 3 blocks kept) */
     int32_t per_column;       /* 1 = one single-vector product per block column
                                  (the unbatched reference form), 0 = block SpMM */
+    double eta;               /* 0: Matsubara frequencies; > 0: real frequencies
+                                 broadened by eta (the paper uses 0.05) */
 } mcd_band_cfg;
 
 int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
@@ -330,6 +334,47 @@ int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int
                            const int32_t *spin, int32_t n_freq, const double *omega,
                            const mcd_band_cfg *cfg, double *G_out, double *Gp_out,
                            double *Gm_out, mcd_solve_info *info, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * mcd_band_green_vjp -- reverse-mode derivative of the Green function (and of
+ * E0) with respect to the Hamiltonian's parameters theta = (t_b, U_i, eps_i)
+ * of Eq. hubbard_model, for the G that mcd_band_lanczos_green returns with
+ * the same arguments.
+ *
+ * For a real function L(G, E0) with G_bar[f][mu][nu] = dL/dRe G + i dL/dIm G
+ * (the gradient convention of torch for complex tensors) and e0_bar =
+ * dL/dE0, writes dL/dtheta = Re sum conj(G_bar) dG/dtheta + e0_bar dE0/dtheta.
+ * G+(z) = B^T (z - H+)^-1 B with B = c+|psi0>, z = E0 + zeta (G- likewise
+ * with minus signs), so dG/dtheta has three parts, all evaluated here:
+ *   * the resolvent:  X^T (dH/dtheta - dE0/dtheta) X, X = (z - H)^-1 B,
+ *     through the stored Krylov blocks Q (X = Q S, S from the block
+ *     tridiagonal T): tr(Q^T dH/dtheta Q M) - tr(M) dE0/dtheta with M =
+ *     Re sum_f S_f conj(G_bar_f)^T S_f^T, one contraction pass over F~+-;
+ *   * dE0/dtheta = <psi0| dH/dtheta |psi0> (Hellmann-Feynman);
+ *   * the response of the start block through d psi0/dtheta =
+ *     -(H - E0)^+ dH/dtheta psi0: one conjugate-gradient solve
+ *     (H - E0) xi = P lambda on F~ (P projects out psi0, lambda collects the
+ *     adjoint of the start blocks), then -<xi| dH/dtheta |psi0>.
+ * The Krylov blocks are recomputed here (the forward call keeps none).
+ *
+ * psi0_dev: the normalised, non-degenerate ground state; cfg->w_t must be 1
+ *   (a target-weight cut is not differentiable); every Krylov block is
+ *   stored (max_blocks + 1 blocks of n_x * P values per sector).
+ * G_bar: host complex128 [n_freq][n_sel][n_sel].
+ * d_t [n_bonds] (listed bonds; a pair listed twice gets the pair's
+ *   derivative in both entries), d_U [n_orb], d_eps [n_orb]: host outputs.
+ * info: iters = conjugate-gradient iterations, residual = its relative
+ *   residual, krylov_dim, n_plus, n_minus, solve_ms.
+ * cg_tol: relative residual of the solve (1e-12 is typical); cg_max_iter.
+ * Returns MCD_NOCONV (outputs filled) if the solve stopped at cg_max_iter.
+ * Synchronises.
+ * ------------------------------------------------------------------------- */
+int mcd_band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                       const double *psi0_dev, double e0, int32_t n_sel, const int32_t *orb,
+                       const int32_t *spin, int32_t n_freq, const double *omega,
+                       const mcd_band_cfg *cfg, const double *G_bar, double e0_bar,
+                       double cg_tol, int32_t cg_max_iter, double *d_t, double *d_U,
+                       double *d_eps, mcd_solve_info *info, void *stream);
 
 #ifdef __cplusplus
 }

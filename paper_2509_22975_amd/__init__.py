@@ -61,7 +61,7 @@ class McdSolveInfo(ctypes.Structure):
 
 class McdBandCfg(ctypes.Structure):
     _fields_ = [("max_blocks", c_i32), ("precision", c_i32), ("w_t", c_dbl), ("dtol", c_dbl),
-                ("storage", c_i32), ("reorth", c_i32), ("per_column", c_i32)]
+                ("storage", c_i32), ("reorth", c_i32), ("per_column", c_i32), ("eta", c_dbl)]
 
 
 _lib = None
@@ -98,10 +98,14 @@ def lib():
         L.mcd_band_lanczos_green.argtypes = [P(McdModel), c_vp, c_i64, c_vp, c_dbl, c_i32,
                                              P(c_i32), P(c_i32), c_i32, P(c_dbl), P(McdBandCfg),
                                              P(c_dbl), P(c_dbl), P(c_dbl), P(McdSolveInfo), c_vp]
+    L.mcd_band_green_vjp.argtypes = [P(McdModel), c_vp, c_i64, c_vp, c_dbl, c_i32, P(c_i32),
+                                     P(c_i32), c_i32, P(c_dbl), P(McdBandCfg), P(c_dbl), c_dbl,
+                                     c_dbl, c_i32, P(c_dbl), P(c_dbl), P(c_dbl), P(McdSolveInfo),
+                                     c_vp]
     for name in ("mcd_basis_build", "mcd_op_create", "mcd_op_info", "mcd_op_set_kernel", "mcd_hamiltonian_apply",
                  "mcd_hamiltonian_diagonal", "mcd_hamiltonian_connectivity", "mcd_lanczos_ground",
                  "mcd_band_lanczos_green", "mcd_batch_lanczos_ground",
-                 "mcd_hamiltonian_contract"):
+                 "mcd_hamiltonian_contract", "mcd_band_green_vjp"):
         if hasattr(L, name):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -348,10 +352,19 @@ def batch_lanczos_ground(ops, max_iter=400, tol=1e-12, seed=0, check_every=10, m
     return list(e0), psis, list(it), SolveInfo.of(info)
 
 
+def _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, per_column, eta):
+    return McdBandCfg(int(max_blocks), DTYPE[precision], float(w_t), float(dtol),
+                      STORAGE[storage], (2 if reorth is True else int(reorth)),
+                      1 if per_column else 0, float(eta))
+
+
 def band_lanczos_green(model, keys, psi0, e0, orbitals, spins, omega, max_blocks=50,
                        precision="f64", w_t=1.0, dtol=1e-10, storage="auto", reorth=2,
-                       parts=False, per_column=False):
-    """G(i w_n) [n_freq, n_sel, n_sel] complex128 via mcd_band_lanczos_green."""
+                       parts=False, per_column=False, eta=0.0):
+    """G [n_freq, n_sel, n_sel] complex128 via mcd_band_lanczos_green.
+
+    eta == 0: omega are Matsubara frequencies (z = i w); eta > 0: real
+    frequencies broadened by eta (z = w + i eta)."""
     mb = _ModelBuf(model)
     orb = np.ascontiguousarray(orbitals, dtype=np.int32)
     sp = np.ascontiguousarray(spins, dtype=np.int32)
@@ -360,8 +373,7 @@ def band_lanczos_green(model, keys, psi0, e0, orbitals, spins, omega, max_blocks
     G = np.zeros((nf, ns, ns), dtype=np.complex128)
     Gp = np.zeros_like(G)
     Gm = np.zeros_like(G)
-    cfg = McdBandCfg(int(max_blocks), DTYPE[precision], float(w_t), float(dtol), STORAGE[storage],
-                     (2 if reorth is True else int(reorth)), 1 if per_column else 0)
+    cfg = _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, per_column, eta)
     info = McdSolveInfo()
     dp = lambda a: a.view(np.float64).ctypes.data_as(P(c_dbl))
     code = lib().mcd_band_lanczos_green(ctypes.byref(mb.s), c_vp(keys.data_ptr()), int(keys.numel()),
@@ -373,3 +385,31 @@ def band_lanczos_green(model, keys, psi0, e0, orbitals, spins, omega, max_blocks
     if parts:
         return G, Gp, Gm, SolveInfo.of(info)
     return G, SolveInfo.of(info)
+
+
+def band_green_vjp(model, keys, psi0, e0, orbitals, spins, omega, G_bar, e0_bar=0.0,
+                   max_blocks=50, precision="f64", dtol=1e-10, storage="auto", reorth=2, eta=0.0,
+                   cg_tol=1e-12, cg_max_iter=20000):
+    """(d_t [n_bonds], d_U [n_orb], d_eps [n_orb], SolveInfo) = Re sum conj(G_bar) dG/dtheta
+    + e0_bar dE0/dtheta via mcd_band_green_vjp (same arguments as band_lanczos_green)."""
+    mb = _ModelBuf(model)
+    orb = np.ascontiguousarray(orbitals, dtype=np.int32)
+    sp = np.ascontiguousarray(spins, dtype=np.int32)
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    ns, nf = len(orb), len(om)
+    gb = np.ascontiguousarray(np.asarray(G_bar, dtype=np.complex128).reshape(nf, ns, ns))
+    cfg = _band_cfg(max_blocks, precision, 1.0, dtol, storage, reorth, False, eta)
+    dt = np.zeros(len(model.bonds))
+    dU = np.zeros(model.n_orb)
+    de = np.zeros(model.n_orb)
+    info = McdSolveInfo()
+    dp = lambda a: a.ctypes.data_as(P(c_dbl))
+    code = lib().mcd_band_green_vjp(ctypes.byref(mb.s), c_vp(keys.data_ptr()), int(keys.numel()),
+                                    c_vp(psi0.data_ptr()), float(e0), ns,
+                                    orb.ctypes.data_as(P(c_i32)), sp.ctypes.data_as(P(c_i32)), nf,
+                                    om.ctypes.data_as(P(c_dbl)), ctypes.byref(cfg),
+                                    gb.view(np.float64).ctypes.data_as(P(c_dbl)), float(e0_bar),
+                                    float(cg_tol), int(cg_max_iter), dp(dt), dp(dU), dp(de),
+                                    ctypes.byref(info), _stream())
+    _check(code, "mcd_band_green_vjp")
+    return dt, dU, de, SolveInfo.of(info)

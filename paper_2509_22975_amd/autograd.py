@@ -1,4 +1,4 @@
-"""Differentiable ground-state energy (Hellmann-Feynman through the C ABI).
+"""Differentiable ground-state energy and Green function through the C ABI.
 
 ``ground_energy(model, keys, t, U, eps)`` returns E0 of H~(t, U, eps) on the
 basis ``keys`` as a torch scalar whose gradient with respect to the bond
@@ -7,12 +7,19 @@ is <Omega| dH~/dtheta |Omega> (Hellmann-Feynman), evaluated by
 ``mcd_hamiltonian_contract`` on the GPU.  Parameters can be functions of other
 tensors (for example the 33 impurity parameters eps_b, V_ib, U); autograd
 composes the chain rule.
+
+``green_function(...)`` returns (E0, G) with G the band-Lanczos Green
+function [n_freq, n_sel, n_sel] (complex128); its backward is one call of
+``mcd_band_green_vjp`` (resolvent contraction over the recomputed Krylov
+blocks, Hellmann-Feynman dE0, and one conjugate-gradient solve for the
+ground-state response), so a loss of G and E0 gets its gradient with respect
+to every bond amplitude, U_i and eps_i in one backward pass.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import Operator, lanczos_ground
+from . import Operator, band_green_vjp, band_lanczos_green, lanczos_ground
 
 
 def _torch():
@@ -51,6 +58,61 @@ def _make_function():
 
 
 _FN = None
+_GFN = None
+
+
+def _make_green_function():
+    torch = _torch()
+
+    class GreenFunction(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, t, U, eps, model, keys, orbitals, spins, omega, band_kw, lanczos_kw,
+                    storage):
+            m = model.with_params(
+                bonds=[(b[0], b[1], float(v)) for b, v in zip(model.bonds, t.detach().cpu().numpy())],
+                U=U.detach().cpu().numpy(), eps=eps.detach().cpu().numpy())
+            op = Operator(m, keys, storage=storage)
+            e0, psi, _, _, _ = lanczos_ground(op, **lanczos_kw)
+            op.close()
+            G, _ = band_lanczos_green(m, keys, psi, e0, orbitals, spins, omega, **band_kw)
+            ctx.m, ctx.keys, ctx.psi, ctx.e0 = m, keys, psi, e0
+            ctx.sel = (orbitals, spins, omega)
+            ctx.band_kw = band_kw
+            ctx.shapes = (t, U, eps)
+            return (torch.tensor(e0, dtype=torch.float64, device=t.device),
+                    torch.as_tensor(G, device=t.device))
+
+        @staticmethod
+        def backward(ctx, e0_bar, G_bar):
+            orbitals, spins, omega = ctx.sel
+            nf, ns = len(omega), len(orbitals)
+            gb = (np.zeros((nf, ns, ns), dtype=np.complex128) if G_bar is None
+                  else G_bar.detach().cpu().numpy().astype(np.complex128))
+            eb = 0.0 if e0_bar is None else float(e0_bar.item())
+            kw = {k: v for k, v in ctx.band_kw.items() if k not in ("w_t", "per_column")}
+            dt, dU, de, _ = band_green_vjp(ctx.m, ctx.keys, ctx.psi, ctx.e0, orbitals, spins,
+                                           omega, gb, e0_bar=eb, **kw)
+            t, U, eps = ctx.shapes
+            as_t = lambda a, ref: torch.as_tensor(a, dtype=ref.dtype, device=ref.device)
+            return (as_t(dt, t), as_t(dU, U), as_t(de, eps), None, None, None, None, None, None,
+                    None, None)
+
+    return GreenFunction
+
+
+def green_function(model, keys, t, U, eps, orbitals, spins, omega, storage="csr",
+                   lanczos_kw=None, **band_kw):
+    """(E0, G) as differentiable torch tensors; G = G+ + G- [n_freq, n_sel, n_sel]
+    complex128 from ``band_lanczos_green`` with ``band_kw`` (w_t must stay 1)."""
+    global _GFN
+    if _GFN is None:
+        _GFN = _make_green_function()
+    if band_kw.get("w_t", 1.0) != 1.0:
+        raise ValueError("the derivative of G needs w_t = 1")
+    kw = dict(max_iter=600, tol=1e-12, seed=11)
+    kw.update(lanczos_kw or {})
+    return _GFN.apply(t, U, eps, model, keys, list(orbitals), list(spins),
+                      np.asarray(omega, dtype=np.float64), dict(band_kw), kw, storage)
 
 
 def ground_energy(model, keys, t, U, eps, storage="csr", **lanczos_kw):

@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <chrono>
 #include <complex>
+#include <functional>
 #include <vector>
 
 #include "mcd_hash.h"
@@ -521,17 +522,32 @@ struct BandRun {
     }
 };
 
+// Frequency argument zeta of G: i w (Matsubara, eta <= 0) or w + i eta
+// (real frequency, Lorentzian width eta).  G+ is evaluated at z = E0 + zeta
+// and G- at z = E0 - zeta.
+static inline cplx freq_arg(const mcd_band_cfg *cfg, double w) {
+    return cfg->eta > 0.0 ? cplx(w, cfg->eta) : cplx(0.0, w);
+}
+
 static double wall_ms() {
     return std::chrono::duration<double, std::milli>(
                std::chrono::steady_clock::now().time_since_epoch())
         .count();
 }
 
-// One excited sector run (create = particle / G+, else hole / G-).
+// Called after a sector run with the run (stored Krylov blocks), the
+// operator on F~+- and the recurrence; returns an MCD status.
+template <typename T>
+using SectorHook = std::function<int(BandRun<T> &, mcd_op *, const BandResult &)>;
+
+// One excited sector run (create = particle / G+, else hole / G-).  With
+// store_all every Krylov block is kept (also without reorthogonalisation)
+// and `hook` runs before the sector's buffers are released.
 template <typename T>
 static int excited_run(const mcd_model *model, const uint64_t *keys_t, const double *psi_t,
                        int64_t nt, const SelOps &sel, bool create, const mcd_band_cfg *cfg,
-                       double dtol_scale, int P, BandResult &br, int64_t *n_x, hipStream_t s) {
+                       double dtol_scale, int P, BandResult &br, int64_t *n_x, hipStream_t s,
+                       bool store_all = false, const SectorHook<T> *hook = nullptr) {
     uint64_t *img = nullptr, *srt = nullptr, *uniq = nullptr;
     int64_t *d_nu = nullptr;
     void *tmp = nullptr;
@@ -599,7 +615,7 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
     run.P = P;
     run.n = nu;
     run.s = s;
-    run.nstore = reorth > 0 ? cfg->max_blocks + 1 : 3;
+    run.nstore = (reorth > 0 || store_all) ? cfg->max_blocks + 1 : 3;
     size_t fr = 0, tot = 0;
     CK(hipMemGetInfo(&fr, &tot));
     const double need = (double)run.nstore * nu * P * sizeof(T);
@@ -636,6 +652,14 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
         return rc;
     }
     CK(hipStreamSynchronize(s));
+    if (hook && br.m > 0) {
+        rc = (*hook)(run, op, br);
+        if (rc < 0) {
+            cleanup();
+            return rc;
+        }
+        CK(hipStreamSynchronize(s));
+    }
     cleanup();
 #undef CK
 #undef TRY
@@ -737,7 +761,7 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
         cplx *Gf = (cplx *)G_out + (size_t)f * p * p;
         for (int e = 0; e < p * p; e++) Gf[e] = 0.0;
         if (brp.m > 0) {
-            block_cf(brp, cplx(e0, omega[f]), p, g.data());
+            block_cf(brp, e0 + freq_arg(cfg, omega[f]), p, g.data());
             for (int e = 0; e < p * p; e++) {
                 Gf[e] += g[e];
                 if (Gp_out) ((cplx *)Gp_out)[(size_t)f * p * p + e] = g[e];
@@ -746,7 +770,7 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
             for (int e = 0; e < p * p; e++) ((cplx *)Gp_out)[(size_t)f * p * p + e] = 0.0;
         }
         if (brm.m > 0) {
-            block_cf(brm, cplx(e0, -omega[f]), p, g.data());
+            block_cf(brm, e0 - freq_arg(cfg, omega[f]), p, g.data());
             for (int e = 0; e < p * p; e++) {
                 Gf[e] -= g[e];
                 if (Gm_out) ((cplx *)Gm_out)[(size_t)f * p * p + e] = -g[e];
@@ -769,6 +793,406 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
         info->n_truncated = n_keep;
     }
     return MCD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Reverse-mode derivative of G (vector-Jacobian product).
+
+// lam[r] += sum_q sign * W[row(c_q x_r)][q]: the transpose of k_start_block
+// (adjoint of the start block with respect to psi0).
+template <typename T>
+__global__ void k_start_block_t(int64_t m, const uint64_t *__restrict__ keys, SelOps sel,
+                                int create, const HashSlot *__restrict__ h, uint64_t hmask, int P,
+                                const T *__restrict__ W, double *__restrict__ lam) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const uint64_t k = keys[r];
+    const uint32_t up = (uint32_t)(k >> 32), dn = (uint32_t)k;
+    double acc = 0.0;
+    for (int q = 0; q < sel.n; q++) {
+        uint64_t t;
+        if (!image(k, sel.orb[q], sel.spin[q], create != 0, &t)) continue;
+        const int64_t row = hash_find(h, hmask, t);
+        if (row >= 0) acc += jw_sign(up, dn, sel.orb[q], sel.spin[q]) * (double)W[row * P + q];
+    }
+    lam[r] += acc;
+}
+
+// part[p * gridDim.x + block] = sum over this workgroup's rows r of
+//   sum_a L[r][a] (dH/dtheta_p R)[r][a]
+// for the merged bonds p < nb, then U_i (p = nb + i) and eps_i (nb + no + i).
+// L and R hold nk blocks [k][n][P]; column a = (k, j).  One wavefront per
+// row: the hop target is found once and the wave sums over the nk * P
+// columns; each wave keeps its own accumulators (fixed order).
+static constexpr int kCWaves = 4;
+static constexpr int kMaxParams = MCD_MAX_BONDS + 2 * MCD_MAX_ORB;
+template <typename T>
+__global__ __launch_bounds__(64 * kCWaves) void k_contract_multi(
+    int64_t n, const uint64_t *__restrict__ keys, const DevModel *__restrict__ m,
+    const HashSlot *__restrict__ h, uint64_t hmask, const T *__restrict__ L,
+    const T *__restrict__ R, int nk, int P, double *__restrict__ part) {
+    __shared__ double acc[kCWaves][kMaxParams];
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nb = m->n_bonds, no = m->n_orb, np = nb + 2 * no;
+    for (int i = lane; i < np; i += 64) acc[wid][i] = 0.0;
+    const int KP = nk * P;
+    const int64_t bstride = n * (int64_t)P;
+    for (int64_t r = (int64_t)blockIdx.x * kCWaves + wid; r < n;
+         r += (int64_t)gridDim.x * kCWaves) {
+        const uint64_t key = keys[r];
+        const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
+        // sum_a L[r][a] R[col][a] over the wave (result in lane 0)
+        auto rowdot = [&](int64_t col) {
+            double s = 0.0;
+            for (int a = lane; a < KP; a += 64) {
+                const int k = a / P, j = a - k * P;
+                s += (double)L[k * bstride + r * P + j] * (double)R[k * bstride + col * P + j];
+            }
+            return wave_sum(s);
+        };
+        for (int q = 0; q < nb; q++) {
+            const uint32_t mask = m->bonds[q].mask, between = m->bonds[q].between;
+            double c = 0.0;
+            if (__popc(up & mask) == 1) {
+                const int64_t col = hash_find(h, hmask, key ^ ((uint64_t)mask << 32));
+                if (col >= 0) {
+                    const double d = rowdot(col);
+                    c += (__popc(up & between) & 1) ? -d : d;
+                }
+            }
+            if (__popc(dn & mask) == 1) {
+                const int64_t col = hash_find(h, hmask, key ^ (uint64_t)mask);
+                if (col >= 0) {
+                    const double d = rowdot(col);
+                    c += (__popc(dn & between) & 1) ? -d : d;
+                }
+            }
+            if (lane == 0) acc[wid][q] += c;
+        }
+        const double d = rowdot(r);
+        if (lane == 0) {
+            for (int i = 0; i < no; i++) {
+                const double nu = (double)((up >> i) & 1u), nd = (double)((dn >> i) & 1u);
+                acc[wid][nb + i] += nu * nd * d;
+                acc[wid][nb + no + i] += (nu + nd) * d;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < np; i += 64 * kCWaves) {
+        double s = 0.0;
+        for (int w = 0; w < kCWaves; w++) s += acc[w][i];
+        part[(int64_t)i * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// out[p] (+)= sum_c part[p * nblk + c]: one wavefront per parameter.
+__global__ __launch_bounds__(256) void k_param_reduce(int np, int nblk,
+                                                      const double *__restrict__ part,
+                                                      double *__restrict__ out, int accumulate) {
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (p >= np) return;
+    double s = 0.0;
+    for (int c = lane; c < nblk; c += 64) s += part[(int64_t)p * nblk + c];
+    s = wave_sum(s);
+    if (lane == 0) out[p] = accumulate ? out[p] + s : s;
+}
+
+// Conjugate-gradient vector updates (scalars from the host).
+__global__ void k_shift_project(int64_t n, double *__restrict__ y, const double *__restrict__ x,
+                                double e0, const double *__restrict__ psi, double c) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) y[r] = y[r] - e0 * x[r] - c * psi[r];
+}
+__global__ void k_axpy2(int64_t n, double a, const double *__restrict__ p,
+                        const double *__restrict__ ap, double *__restrict__ x,
+                        double *__restrict__ res) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    x[r] += a * p[r];
+    res[r] -= a * ap[r];
+}
+__global__ void k_xpby(int64_t n, const double *__restrict__ x, double b, double *__restrict__ y) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) y[r] = x[r] + b * y[r];
+}
+__global__ void k_sub_scaled(int64_t n, double *__restrict__ y, double c,
+                             const double *__restrict__ x) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) y[r] -= c * x[r];
+}
+
+// First block column of (z - T)^-1 times R0 (first p columns) for the block
+// tridiagonal T of a run: x_0 = S_0^-1 R0, x_j = S_j^-1 B_j x_{j-1}, with the
+// Schur complements S_{m-1} = z - A_{m-1}, S_j = z - A_j - B_{j+1}^T
+// S_{j+1}^-1 B_{j+1} (the same recursion as block_cf).  X: [m P][p].
+static void block_solve_first(const BandResult &br, cplx z, int p, std::vector<cplx> &X) {
+    const int P = br.P, m = br.m;
+    std::vector<std::vector<cplx>> S(m, std::vector<cplx>(P * P));
+    auto zA = [&](int j, std::vector<cplx> &out) {
+        for (int a = 0; a < P; a++)
+            for (int b = 0; b < P; b++)
+                out[a * P + b] = (a == b ? z : cplx(0.0)) - br.A[j][a * P + b];
+    };
+    zA(m - 1, S[m - 1]);
+    for (int j = m - 2; j >= 0; j--) {
+        std::vector<cplx> Y(P * P), Sc = S[j + 1];
+        for (int e = 0; e < P * P; e++) Y[e] = br.B[j + 1][e];
+        csolve(P, P, Sc, Y);
+        zA(j, S[j]);
+        for (int a = 0; a < P; a++)
+            for (int b = 0; b < P; b++) {
+                cplx acc = 0.0;
+                for (int q = 0; q < P; q++) acc += br.B[j + 1][q * P + a] * Y[q * P + b];
+                S[j][a * P + b] -= acc;
+            }
+    }
+    X.assign((size_t)m * P * p, cplx(0.0));
+    std::vector<cplx> rhs(P * p);
+    for (int a = 0; a < P; a++)
+        for (int b = 0; b < p; b++) rhs[a * p + b] = br.R0[a * P + b];
+    for (int j = 0; j < m; j++) {
+        if (j > 0) {
+            for (int a = 0; a < P; a++)
+                for (int b = 0; b < p; b++) {
+                    cplx acc = 0.0;
+                    for (int q = 0; q < P; q++)
+                        acc += br.B[j][a * P + q] * X[((size_t)(j - 1) * P + q) * p + b];
+                    rhs[a * p + b] = acc;
+                }
+        }
+        std::vector<cplx> Sc = S[j];
+        csolve(P, p, Sc, rhs);
+        for (int a = 0; a < P; a++)
+            for (int b = 0; b < p; b++) X[((size_t)j * P + a) * p + b] = rhs[a * p + b];
+    }
+}
+
+template <typename T>
+static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                          const double *psi0_dev, double e0, const SelOps &sel, int n_freq,
+                          const double *omega, const mcd_band_cfg *cfg, const double *G_bar,
+                          double e0_bar, double cg_tol, int cg_max_iter, double *d_t,
+                          double *d_U, double *d_eps, mcd_solve_info *info, hipStream_t s) {
+    const double t0 = wall_ms();
+    const int p = sel.n;
+    int P = 1;
+    while (P < p) P <<= 1;
+    mcd_op *op_gs = nullptr;
+    double *lam = nullptr, *acc = nullptr, *part = nullptr, *scal = nullptr;
+    double *xi = nullptr, *res = nullptr, *dir = nullptr, *adir = nullptr;
+    auto cleanup = [&]() {
+        for (void *q : {(void *)lam, (void *)acc, (void *)part, (void *)scal, (void *)xi,
+                        (void *)res, (void *)dir, (void *)adir})
+            if (q) (void)hipFree(q);
+        if (op_gs) mcd_op_destroy(op_gs);
+    };
+#define CK(expr)                                                              \
+    do {                                                                      \
+        hipError_t e_ = (expr);                                               \
+        if (e_ != hipSuccess) {                                               \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));         \
+            cleanup();                                                        \
+            return MCD_E_HIP;                                                 \
+        }                                                                     \
+    } while (0)
+#define TRY(expr)          \
+    do {                   \
+        int rc_ = (expr);  \
+        if (rc_ < 0) {     \
+            cleanup();     \
+            return rc_;    \
+        }                  \
+    } while (0)
+    TRY(mcd_op_create(model, keys_dev, n, MCD_STORAGE_AUTO, 0, s, &op_gs));
+    const int nb = op_gs->hm.dm.n_bonds, no = op_gs->hm.dm.n_orb, np = nb + 2 * no;
+    CK(hipMalloc(&lam, n * sizeof(double)));
+    CK(hipMalloc(&acc, np * sizeof(double)));
+    CK(hipMalloc(&scal, 8 * sizeof(double)));
+    CK(hipMemsetAsync(lam, 0, n * sizeof(double), s));
+    CK(hipMemsetAsync(acc, 0, np * sizeof(double), s));
+    const int cblk = 2048;
+    CK(hipMalloc(&part, (size_t)np * cblk * sizeof(double)));
+
+    double trM = 0.0;   // sum over sectors of tr(M)
+    int krylov = 0;
+    // Per sector: M, Omega on the host, Z = Q M and W = Q Omega on the device,
+    // tr(Q^T dH Q M) into acc, lam += (start-block map)^T W.
+    auto make_hook = [&](bool create) {
+        return SectorHook<T>([&, create](BandRun<T> &run, mcd_op *op, const BandResult &br) -> int {
+            const int m = br.m, KP = m * P;
+            const double sg = create ? 1.0 : -1.0;
+            std::vector<double> M((size_t)KP * KP, 0.0), Om((size_t)KP * P, 0.0);
+            std::vector<cplx> X, V((size_t)KP * p);
+            for (int f = 0; f < n_freq; f++) {
+                const cplx zeta = freq_arg(cfg, omega[f]);
+                block_solve_first(br, create ? e0 + zeta : e0 - zeta, p, X);
+                const cplx *Gb = (const cplx *)G_bar + (size_t)f * p * p;
+                for (int a = 0; a < KP; a++)
+                    for (int mu = 0; mu < p; mu++) {
+                        cplx v = 0.0, w = 0.0;
+                        for (int nu = 0; nu < p; nu++) {
+                            v += X[(size_t)a * p + nu] * std::conj(Gb[mu * p + nu]);
+                            w += X[(size_t)a * p + nu] * std::conj(Gb[nu * p + mu]);
+                        }
+                        V[(size_t)a * p + mu] = v;
+                        Om[(size_t)a * P + mu] += sg * (v + w).real();
+                    }
+                for (int a = 0; a < KP; a++)
+                    for (int b = 0; b < KP; b++) {
+                        double t = 0.0;
+                        for (int mu = 0; mu < p; mu++)
+                            t += (V[(size_t)a * p + mu] * X[(size_t)b * p + mu]).real();
+                        M[(size_t)a * KP + b] += sg * t;
+                    }
+            }
+            for (int a = 0; a < KP; a++) trM += M[(size_t)a * KP + a];
+            krylov += br.krylov;
+            const int64_t nx = run.n;
+            T *Z = nullptr;
+            MCD_HIP(hipMalloc(&Z, (size_t)m * nx * P * sizeof(T)));
+            // Z_k = sum_j Q_j M[j-block, k-block]  (W -= sum Q (-C))
+            std::vector<double> C((size_t)m * P * P);
+            int rc = MCD_OK;
+            for (int k = 0; k < m && rc == MCD_OK; k++) {
+                for (int j = 0; j < m; j++)
+                    for (int a = 0; a < P; a++)
+                        for (int b = 0; b < P; b++)
+                            C[((size_t)j * P + a) * P + b] = -M[((size_t)j * P + a) * KP + k * P + b];
+                T *Zk = Z + (size_t)k * nx * P;
+                if (hipMemsetAsync(Zk, 0, (size_t)nx * P * sizeof(T), s) != hipSuccess) rc = MCD_E_HIP;
+                if (rc == MCD_OK) rc = run.block_apply(run.blk(0), m, C, Zk, true);
+            }
+            if (rc == MCD_OK) {
+                const unsigned g = (unsigned)std::min<int64_t>(cblk, (nx + kCWaves - 1) / kCWaves);
+                hipLaunchKernelGGL((k_contract_multi<T>), dim3(g), dim3(64 * kCWaves), 0, s, nx,
+                                   op->d_keys, op->d_model, op->d_hash, op->hash_mask, run.blk(0),
+                                   Z, m, P, part);
+                hipLaunchKernelGGL(k_param_reduce, dim3((np + 3) / 4), dim3(256), 0, s, np, (int)g,
+                                   part, acc, 1);
+                if (hipGetLastError() != hipSuccess) rc = MCD_E_HIP;
+            }
+            // W = Q Omega (into run.W), then lam += map^T W
+            if (rc == MCD_OK) {
+                for (int j = 0; j < m; j++)
+                    for (int a = 0; a < P; a++)
+                        for (int b = 0; b < P; b++)
+                            C[((size_t)j * P + a) * P + b] = -Om[((size_t)j * P + a) * P + b];
+                if (hipMemsetAsync(run.W, 0, (size_t)nx * P * sizeof(T), s) != hipSuccess)
+                    rc = MCD_E_HIP;
+                if (rc == MCD_OK) rc = run.block_apply(run.blk(0), m, C, run.W, true);
+            }
+            if (rc == MCD_OK) {
+                hipLaunchKernelGGL((k_start_block_t<T>), dim3(gridn(n, 256)), dim3(256), 0, s, n,
+                                   keys_dev, sel, create ? 1 : 0, op->d_hash, op->hash_mask, P,
+                                   run.W, lam);
+                if (hipGetLastError() != hipSuccess) rc = MCD_E_HIP;
+            }
+            if (hipStreamSynchronize(s) != hipSuccess && rc == MCD_OK) rc = MCD_E_HIP;
+            (void)hipFree(Z);
+            if (rc == MCD_E_HIP) set_error("green vjp: device step failed in a sector hook");
+            return rc;
+        });
+    };
+    BandResult brp, brm;
+    int64_t npl = 0, nmi = 0;
+    {
+        const SectorHook<T> hp = make_hook(true), hm = make_hook(false);
+        TRY(excited_run<T>(model, keys_dev, psi0_dev, n, sel, true, cfg, 1.0, P, brp, &npl, s,
+                           true, &hp));
+        TRY(excited_run<T>(model, keys_dev, psi0_dev, n, sel, false, cfg, 1.0, P, brm, &nmi, s,
+                           true, &hm));
+    }
+
+    // (H - E0) xi = P lam on F~, xi orthogonal to psi0 (conjugate gradients;
+    // H - E0 is positive definite on the complement of a non-degenerate psi0).
+    CK(hipMalloc(&xi, n * sizeof(double)));
+    CK(hipMalloc(&res, n * sizeof(double)));
+    CK(hipMalloc(&dir, n * sizeof(double)));
+    CK(hipMalloc(&adir, n * sizeof(double)));
+    const unsigned gv = gridn(n, 256);
+    auto dot = [&](const double *a, const double *b, double *out) -> int {
+        MCD_TRY(dev_dot(op_gs, a, b, n, scal, s));
+        MCD_HIP(hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        MCD_HIP(hipStreamSynchronize(s));
+        return MCD_OK;
+    };
+    double c = 0.0;
+    CK(hipMemcpyAsync(res, lam, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    TRY(dot(psi0_dev, res, &c));
+    hipLaunchKernelGGL(k_sub_scaled, dim3(gv), dim3(256), 0, s, n, res, c, psi0_dev);
+    CK(hipMemsetAsync(xi, 0, n * sizeof(double), s));
+    CK(hipMemcpyAsync(dir, res, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double rr = 0.0;
+    TRY(dot(res, res, &rr));
+    const double bnorm = sqrt(rr);
+    int it = 0;
+    bool conv = bnorm == 0.0;
+    double rel = 0.0;
+    while (!conv && it < cg_max_iter) {
+        TRY(apply_any(op_gs, MCD_F64, 1, dir, adir, s));
+        double pc = 0.0;
+        TRY(dot(psi0_dev, adir, &pc));
+        hipLaunchKernelGGL(k_shift_project, dim3(gv), dim3(256), 0, s, n, adir, dir, e0, psi0_dev,
+                           pc);
+        double pap = 0.0;
+        TRY(dot(dir, adir, &pap));
+        if (!(pap > 0.0)) break;   // not positive definite: degenerate ground state
+        const double alpha = rr / pap;
+        hipLaunchKernelGGL(k_axpy2, dim3(gv), dim3(256), 0, s, n, alpha, dir, adir, xi, res);
+        double rr2 = 0.0;
+        TRY(dot(res, res, &rr2));
+        it++;
+        rel = sqrt(rr2) / bnorm;
+        if (rel <= cg_tol) {
+            conv = true;
+            break;
+        }
+        hipLaunchKernelGGL(k_xpby, dim3(gv), dim3(256), 0, s, n, res, rr2 / rr, dir);
+        rr = rr2;
+    }
+    CK(hipGetLastError());
+    // contractions with psi0: dE0 and <xi| dH |psi0>
+    const int nlb = model->n_bonds;
+    std::vector<double> e_t(nlb), e_U(no), e_e(no), x_t(nlb), x_U(no), x_e(no);
+    TRY(mcd_hamiltonian_contract(op_gs, model, psi0_dev, psi0_dev, e_t.data(), e_U.data(),
+                                 e_e.data(), s));
+    TRY(mcd_hamiltonian_contract(op_gs, model, xi, psi0_dev, x_t.data(), x_U.data(), x_e.data(),
+                                 s));
+    std::vector<double> h(np);
+    CK(hipMemcpyAsync(h.data(), acc, np * sizeof(double), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    const double ce = e0_bar - trM;
+    for (int q = 0; q < nlb; q++) {
+        const int i = std::min(model->bond_i[q], model->bond_j[q]);
+        const int j = std::max(model->bond_i[q], model->bond_j[q]);
+        const uint32_t mask = (1u << i) | (1u << j);
+        double v = 0.0;
+        for (int mb = 0; mb < nb; mb++)
+            if (op_gs->hm.dm.bonds[mb].mask == mask) v = h[mb];
+        if (d_t) d_t[q] = v + ce * e_t[q] - x_t[q];
+    }
+    for (int i = 0; i < no; i++) {
+        if (d_U) d_U[i] = h[nb + i] + ce * e_U[i] - x_U[i];
+        if (d_eps) d_eps[i] = h[nb + no + i] + ce * e_e[i] - x_e[i];
+    }
+    cleanup();
+#undef CK
+#undef TRY
+    if (info) {
+        memset(info, 0, sizeof(*info));
+        info->iters = it;
+        info->converged = conv ? 1 : 0;
+        info->e0 = e0;
+        info->residual = rel;
+        info->solve_ms = wall_ms() - t0;
+        info->krylov_dim = krylov;
+        info->n_plus = npl;
+        info->n_minus = nmi;
+        info->n_truncated = n;
+    }
+    return conv ? MCD_OK : MCD_NOCONV;
 }
 
 }  // namespace mcd
@@ -807,4 +1231,42 @@ extern "C" int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *ke
                                   G_out, Gp_out, Gm_out, info, s);
     return band_green<float>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg, G_out,
                              Gp_out, Gm_out, info, s);
+}
+
+extern "C" int mcd_band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                                  const double *psi0_dev, double e0, int32_t n_sel,
+                                  const int32_t *orb, const int32_t *spin, int32_t n_freq,
+                                  const double *omega, const mcd_band_cfg *cfg,
+                                  const double *G_bar, double e0_bar, double cg_tol,
+                                  int32_t cg_max_iter, double *d_t, double *d_U, double *d_eps,
+                                  mcd_solve_info *info, void *stream) {
+    MCD_REQUIRE(model && cfg && keys_dev && psi0_dev && orb && spin, MCD_E_INVALID,
+                "a required pointer is NULL");
+    MCD_REQUIRE(n >= 1, MCD_E_INVALID, "empty basis");
+    MCD_REQUIRE(n_sel >= 1 && n_sel <= 16, MCD_E_INVALID, "n_sel = %d outside 1..16", n_sel);
+    MCD_REQUIRE(n_freq >= 0 && (n_freq == 0 || (omega && G_bar)), MCD_E_INVALID,
+                "bad frequencies or G_bar");
+    MCD_REQUIRE(cfg->w_t >= 1.0, MCD_E_INVALID, "the derivative needs w_t = 1 (no weight cut)");
+    MCD_REQUIRE(cfg->max_blocks >= 1, MCD_E_INVALID, "max_blocks must be >= 1");
+    MCD_REQUIRE(cfg->per_column == 0, MCD_E_INVALID, "the derivative uses block products");
+    MCD_REQUIRE(cfg->precision == MCD_F64 || cfg->precision == MCD_F32, MCD_E_INVALID,
+                "precision must be MCD_F64 or MCD_F32");
+    MCD_REQUIRE(cg_tol > 0.0 && cg_max_iter >= 1, MCD_E_INVALID, "bad solve tolerance");
+    HostModel hm;
+    MCD_TRY(prepare_model(model, &hm));
+    SelOps sel;
+    memset(&sel, 0, sizeof(sel));
+    sel.n = n_sel;
+    for (int q = 0; q < n_sel; q++) {
+        MCD_REQUIRE(orb[q] >= 0 && orb[q] < model->n_orb && (spin[q] == 0 || spin[q] == 1),
+                    MCD_E_INVALID, "selection %d = (%d, %d) invalid", q, orb[q], spin[q]);
+        sel.orb[q] = orb[q];
+        sel.spin[q] = spin[q];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (cfg->precision == MCD_F64)
+        return band_green_vjp<double>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg,
+                                      G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, s);
+    return band_green_vjp<float>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg,
+                                 G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, s);
 }

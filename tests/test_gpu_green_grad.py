@@ -1,0 +1,112 @@
+"""GPU Green function at real frequencies and its parameter derivatives
+(mcd_band_green_vjp, the autograd GreenFunction) against the oracle.
+
+Derivatives: the oracle differences its exact Lehmann sums on F~+- (central,
+h = 1e-5: truncation error ~1e-10, rounding ~1e-11 relative); the GPU
+evaluates the adjoint formula with Krylov spaces run to exhaustion and a
+conjugate-gradient solve to 1e-12, so the two agree to ~1e-8 of max |dL|;
+the test allows 1e-6.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import derivatives as dv, green as gr, hamiltonian as ham, lanczos as lz, sampler
+from tests.gpu_common import log_case, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _tiny(sampled):
+    m = W.tiny_impurity(U=4.0, seed=2)
+    if sampled:
+        keys, _ = sampler.chain_c(m, W.neel_start(m), 5, 250, 100, 10**6)
+    else:
+        from oracle import fock
+        keys = fock.sector_keys(6, 3, 3)
+    return m, keys
+
+
+def _gpu_ground(mcd, m, kd):
+    op = mcd.Operator(m, kd, storage="csr")
+    e0, psi, _, _, info = mcd.lanczos_ground(op, max_iter=600, tol=1e-13, seed=11)
+    op.close()
+    return e0, psi
+
+
+def test_green_real_frequency_vs_oracle():
+    """G(w + i eta), eta = 0.05 (the paper's broadening), same Krylov space."""
+    torch, mcd = require_gpu()
+    c = W.config_c1()
+    m = c["model"]
+    keys, _ = sampler.chain_c(m, W.neel_start(m), c["seed"], c["n_f"], c["burn_in"], c["max_steps"])
+    log_case("green_real_freq", n=len(keys))
+    H = ham.build_csr(keys, m)
+    r = lz.lanczos_ground(H, lz.start_vector(keys, 11), tol=1e-13)
+    om = np.linspace(-8.0, 8.0, 41)
+    orbs, spins, blocks = [0, 3, 5], [0, 0, 0], 12
+    kd = mcd.keys_from_numpy(keys)
+    psi = torch.from_numpy(r["psi0"]).cuda()
+    G, _ = mcd.band_lanczos_green(m, kd, psi, r["e0"], orbs, spins, om, max_blocks=blocks,
+                                  reorth=2, eta=0.05)
+    ref = gr.green_mcd(keys, m, r["psi0"], r["e0"], orbs, 0, om, max_dim=len(orbs) * blocks,
+                       eta=0.05)
+    assert _rel(G, ref) < 1e-8
+    # density of states -Im G_ii / pi is non-negative on the real axis
+    assert np.all(-G[:, np.arange(3), np.arange(3)].imag >= -1e-12)
+
+
+@pytest.mark.parametrize("case", ["full_matsubara", "sampled_matsubara", "sampled_real"])
+def test_green_vjp_vs_oracle_finite_differences(case):
+    torch, mcd = require_gpu()
+    m, keys = _tiny(sampled=case != "full_matsubara")
+    eta = 0.05 if case == "sampled_real" else 0.0
+    om = np.linspace(-3, 3, 5) if eta else W.matsubara(6, 20.0)
+    orbs, spins = [0, 1, 2], [0, 0, 1]
+    rng = np.random.default_rng(7)
+    Gb = rng.normal(size=(len(om), 3, 3)) + 1j * rng.normal(size=(len(om), 3, 3))
+    e0_bar = 0.37
+    log_case("green_vjp", case=case, n=len(keys))
+    kd = mcd.keys_from_numpy(keys)
+    e0, psi = _gpu_ground(mcd, m, kd)
+    d_t, d_U, d_e, info = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=e0_bar,
+                                             max_blocks=400, reorth=2, eta=eta)
+    assert info.converged
+    r_t, r_U, r_e = dv.green_gradient(keys, m, orbs, spins, om, Gb, e0_bar=e0_bar, eta=eta)
+    got = np.concatenate([d_t, d_U, d_e])
+    ref = np.concatenate([r_t, r_U, r_e])
+    assert _rel(got, ref) < 1e-6, (got, ref)
+
+
+def test_green_function_autograd_and_float32():
+    """(E0, G) through torch.autograd: loss = sum Re(w G) + c E0; gradient
+    with respect to every bond amplitude, U_i and eps_i against the oracle;
+    float32 Krylov blocks give the same gradient to 1e-4."""
+    torch, mcd = require_gpu()
+    from paper_2509_22975_amd.autograd import green_function
+    m, keys = _tiny(sampled=True)
+    om = W.matsubara(4, 20.0)
+    orbs, spins = [0, 1], [0, 0]
+    kd = mcd.keys_from_numpy(keys)
+    rng = np.random.default_rng(11)
+    w = rng.normal(size=(4, 2, 2)) + 1j * rng.normal(size=(4, 2, 2))
+    c = -0.8
+    log_case("green_autograd", n=len(keys))
+    grads = {}
+    for prec in ("f64", "f32"):
+        t = torch.tensor([b[2] for b in m.bonds], dtype=torch.float64, requires_grad=True)
+        U = torch.tensor(m.U, dtype=torch.float64, requires_grad=True)
+        eps = torch.tensor(m.eps, dtype=torch.float64, requires_grad=True)
+        e0, G = green_function(m, kd, t, U, eps, orbs, spins, om, max_blocks=300,
+                               precision=prec, reorth=2)
+        loss = (torch.as_tensor(w) * G.cpu()).real.sum() + c * e0.cpu()
+        loss.backward()
+        grads[prec] = np.concatenate([t.grad.numpy(), U.grad.numpy(), eps.grad.numpy()])
+    r_t, r_U, r_e = dv.green_gradient(keys, m, orbs, spins, om, np.conj(w), e0_bar=c)
+    ref = np.concatenate([r_t, r_U, r_e])
+    assert _rel(grads["f64"], ref) < 1e-6
+    assert _rel(grads["f32"], grads["f64"]) < 1e-4

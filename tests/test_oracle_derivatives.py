@@ -63,12 +63,7 @@ def test_hellmann_feynman_vs_finite_differences_truncated_impurity():
 # Green-function derivatives (central differences of the oracle pipeline)
 
 def _tiny_impurity(U=4.0, seed=0, n_up=3, n_dn=3):
-    """2 interacting sites + 4 bath orbitals (6 orbitals)."""
-    rng = np.random.default_rng(seed)
-    bonds = [(0, 1, -1.0)] + [(b % 2, b, float(rng.uniform(0.3, 0.9))) for b in range(2, 6)]
-    Uv = np.array([U, U, 0, 0, 0, 0], dtype=float)
-    eps = np.concatenate([[-U / 2 + 0.13, -U / 2 - 0.07], rng.uniform(-2, 2, 4)])
-    return W.Model(6, bonds, Uv, eps, n_up, n_dn, "tiny_imp", [])
+    return W.tiny_impurity(U, seed, n_up, n_dn)
 
 
 def _one_body(m):

@@ -27,7 +27,7 @@ import numpy as np
 
 __all__ = [
     "Model", "chain", "square", "superlattice", "impurity_plaquette_bath",
-    "neel_start", "config_c1", "config_c2", "config_c3", "config_c5",
+    "neel_start", "tiny_impurity", "config_c1", "config_c2", "config_c3", "config_c5",
     "random_vector", "bath_instance_sizes", "matsubara",
 ]
 
@@ -241,6 +241,18 @@ def config_c5() -> dict:
     """4x8 periodic, t=1, t'=-0.3, U=8, mu=0, N_up=N_dn=14; 50M chain states."""
     m = square(8, 4, t=1.0, tp=-0.3, U=8.0, mu=0.0, pbc=True, n_up=14, n_dn=14)
     return dict(model=m, n_f=50_000_000, seed=5, burn_in=10**6, max_steps=10**10, beta_s=0.5)
+
+
+def tiny_impurity(U: float = 4.0, seed: int = 0, n_up: int = 3, n_dn: int = 3) -> Model:
+    """Two interacting sites (bond t = -1, eps = -U/2 +- small offsets that
+    lift degeneracies) coupled to four bath orbitals (bath b to site b mod 2,
+    V ~ U[0.3, 0.9], eps_b ~ U[-2, 2]); 6 orbitals, small enough for dense
+    checks of Green-function derivatives."""
+    rng = np.random.default_rng(seed)
+    bonds = [(0, 1, -1.0)] + [(b % 2, b, float(rng.uniform(0.3, 0.9))) for b in range(2, 6)]
+    Uv = np.array([U, U, 0, 0, 0, 0], dtype=float)
+    eps = np.concatenate([[-U / 2 + 0.13, -U / 2 - 0.07], rng.uniform(-2, 2, 4)])
+    return Model(6, bonds, Uv, eps, n_up, n_dn, "tiny_impurity", [])
 
 
 def bath_instance_sizes(n_inst: int = 32, seed: int = 3, lo: int = 100_000,
