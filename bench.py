@@ -185,6 +185,119 @@ def step_sampler_16(mcd, W, torch):
             "paper_context": "about 10 minutes in the paper (hardware not stated)"}
 
 
+def gradients_c4(mcd, W, torch, blocks=40):
+    """dE0/dtheta and dG(i w_n)/dtheta for the 33 impurity parameters
+    (eps_b, V_ib, U) of the 2x2 + 8 bath model on 0.5M chain states, 32
+    Matsubara frequencies, p = 8: forward (E0, G) + one backward pass of the
+    loss sum |G|^2 + E0, float64 (full reorthogonalisation) and float32 Krylov
+    blocks (one pass).  Finite differences would need 66 forward solves."""
+    from paper_2509_22975_amd.autograd import green_function, impurity_parameters
+    c = W.config_c3(3)
+    m = c["model"]
+    keys, _ = mcd.basis_build(m, "chain", start_key=W.neel_start(m), seed=c["seed"],
+                              beta_s=c["beta_s"], burn_in=c["burn_in"], max_steps=c["max_steps"],
+                              n_f=c["n_f"])
+    om = W.matsubara(32, 50.0)
+    orbs, spins = [0, 1, 2, 3] * 2, [0] * 4 + [1] * 4
+    theta0, expand = impurity_parameters(m)
+    out = {"workload": "2x2 + 8 baths U=8, 500k chain states (seed 3), 33 parameters "
+                       "(eps_b, V_ib, U), p=8, 32 Matsubara frequencies beta=50, %d blocks" % blocks,
+           "n_states": int(keys.numel())}
+    grads = {}
+    for name, prec, reorth in (("f64", "f64", 2), ("f32", "f32", 1)):
+        th = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+        t, U, eps = expand(th)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0, G = green_function(m, keys, t, U, eps, orbs, spins, om, max_blocks=blocks,
+                               precision=prec, reorth=reorth)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ((G.abs() ** 2).sum() + e0).backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        grads[name] = th.grad.clone()
+        out[name] = {"reorth_passes": reorth, "forward_s": round(t1 - t0, 3),
+                     "backward_s": round(t2 - t1, 3)}
+    out["f32"]["max_rel_grad_diff_vs_f64"] = float(
+        (grads["f32"] - grads["f64"]).abs().max() / grads["f64"].abs().max())
+    fd = 66 * out["f64"]["forward_s"]
+    out["finite_difference_estimate_s"] = round(fd, 2)
+    out["speedup_vs_finite_differences"] = round(
+        fd / (out["f32"]["forward_s"] + out["f32"]["backward_s"]), 1)
+    return out
+
+
+def c5_cluster(mcd, W, torch):
+    """The 4x8 periodic t-t' cluster, (14,14), 50M chain states: stored packed
+    CSR against on-the-fly products (1 and 16 vectors), the float64 ground
+    state, and G_ii for sites 0-15 (p = 16) on 128 Matsubara frequencies from
+    the w_t = 0.999 cut."""
+    c = W.config_c5()
+    m = c["model"]
+    t0 = time.perf_counter()
+    keys, steps = mcd.basis_build(m, "chain", start_key=W.neel_start(m), seed=c["seed"],
+                                  beta_s=c["beta_s"], burn_in=c["burn_in"],
+                                  max_steps=c["max_steps"], n_f=c["n_f"])
+    torch.cuda.synchronize()
+    basis_s = time.perf_counter() - t0
+    n = int(keys.numel())
+    dev = keys.device
+
+    def tm(f, reps):
+        f()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) / reps * 1e3
+
+    x = torch.rand(n, dtype=torch.float64, device=dev) * 2 - 1
+    y = torch.empty_like(x)
+    X = torch.rand(n, 16, dtype=torch.float32, device=dev) * 2 - 1
+    Y = torch.empty_like(X)
+    out = {"workload": "4x8 periodic Hubbard t=1 t'=-0.3 U=8 (14,14), 50M chain states (seed 5)",
+           "n_states": n, "chain_steps": steps, "basis_build_s": round(basis_s, 2)}
+    op = mcd.Operator(m, keys, storage="csr")
+    inf = op.info()
+    nnz = inf["nnz"]
+    b1 = 8 * (n + 1) + 4 * nnz + 24 * n
+    b16 = 16 * n + 4 * nnz + 2 * 16 * 4 * n
+    ms1, ms16 = tm(lambda: op.apply(x, y), 10), tm(lambda: op.apply(X, Y), 5)
+    out["csr"] = {"nnz_offdiag": nnz, "nnz_per_row": round(nnz / n, 3),
+                  "op_build_ms": round(inf["build_ms"], 1), "kernel": inf["kernel"],
+                  "device_bytes": inf["device_bytes"],
+                  "f64_1vec_ms": round(ms1, 4), "f64_1vec_GBs": round(b1 / ms1 / 1e6, 1),
+                  "f32_16vec_ms": round(ms16, 4), "f32_16vec_GBs": round(b16 / ms16 / 1e6, 1),
+                  "f32_16vec_ms_per_vector": round(ms16 / 16, 4)}
+    t0 = time.perf_counter()
+    e0, psi, _, _, si = mcd.lanczos_ground(op, max_iter=400, tol=1e-9, seed=5, store_vectors=False)
+    torch.cuda.synchronize()
+    out["lanczos"] = {"e0": e0, "iters": si.iters, "converged": si.converged,
+                      "residual": si.residual, "s": round(time.perf_counter() - t0, 3),
+                      "mode": "float64, vectors recomputed in a second pass"}
+    op.close()
+    del op
+    torch.cuda.empty_cache()
+    op = mcd.Operator(m, keys, storage="on_the_fly")
+    ms1o, ms16o = tm(lambda: op.apply(x, y), 2), tm(lambda: op.apply(X, Y), 1)
+    out["on_the_fly"] = {"f64_1vec_ms": round(ms1o, 3), "f32_16vec_ms": round(ms16o, 3),
+                         "csr_speedup_1vec": round(ms1o / ms1, 1),
+                         "csr_speedup_16vec": round(ms16o / ms16, 1)}
+    op.close()
+    del op, X, Y, x, y
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    G, gi = mcd.band_lanczos_green(m, keys, psi, e0, list(range(16)), [0] * 16,
+                                   W.matsubara(128, 50.0), max_blocks=30, precision="f32",
+                                   w_t=0.999, reorth=2)
+    out["green"] = {"s": round(time.perf_counter() - t0, 3), "n_kept_wt": gi.n_truncated,
+                    "n_plus": gi.n_plus, "n_minus": gi.n_minus, "krylov_dim": gi.krylov_dim,
+                    "p": 16, "n_freq": 128}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +309,10 @@ def main():
                     help="skip the plain-vs-chosen E0 + G comparison")
     ap.add_argument("--no-sampler", action="store_true",
                     help="skip the 16-site step-sampler timing")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the 33-parameter gradient workload")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the 32-site, 50M-state cluster")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 32-instance batched ground-state comparison")
     ap.add_argument("--copy-probe", action="store_true",
@@ -323,6 +440,10 @@ def main():
         out["batch_ground_states"] = batch_c3(mcd, W, torch)
     if not args.no_sampler:
         out["step_sampler"] = step_sampler_16(mcd, W, torch)
+    if not args.no_grad:
+        out["gradients_c4"] = gradients_c4(mcd, W, torch)
+    if not args.no_c5:
+        out["c5_32_sites"] = c5_cluster(mcd, W, torch)
     if args.copy_probe:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)

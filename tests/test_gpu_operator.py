@@ -248,6 +248,46 @@ def test_apply_c2_full_size_sampled_rows():
         op.close()
 
 
+def test_c5_full_size_keys_and_sampled_rows():
+    """The 4x8 t-t' cluster at its full size (50M chain states): GPU chain keys
+    bit-exact with the oracle's chain; float64 products (the kernel the
+    operator tunes to, as timed) and float32 16-vector block products on
+    20000 seeded rows against the oracle's element definition; on-the-fly
+    float64 too."""
+    torch, mcd = require_gpu()
+    c = W.config_c5()
+    m = c["model"]
+    log_case("c5_keys", n_f=c["n_f"])
+    kd, steps = mcd.basis_build(m, "chain", start_key=W.neel_start(m), seed=c["seed"],
+                                beta_s=c["beta_s"], burn_in=c["burn_in"],
+                                max_steps=c["max_steps"], n_f=c["n_f"])
+    keys, steps_ref = sampler.chain_c(m, W.neel_start(m), c["seed"], c["n_f"], c["burn_in"],
+                                      c["max_steps"])
+    got = mcd.keys_to_numpy(kd)
+    assert len(got) == len(keys) == c["n_f"] and steps == steps_ref
+    assert np.array_equal(got, keys)
+    n = len(keys)
+    rows = np.sort(np.random.default_rng(9).choice(n, 20000, replace=False))
+    x = W.random_vector(n, 31)
+    ref = ham.apply_rows(keys, rows, m, x)
+    log_case("c5_apply_f64_csr", n=n)
+    op = mcd.Operator(m, kd, storage="csr")
+    y = op.apply(torch.from_numpy(x).cuda())
+    assert _rel(y.cpu().numpy()[rows], ref) <= 1e-12
+    X = W.random_vector(n, 32, nvec=16, dtype=np.float32)
+    refX = ham.apply_rows(keys, rows, m, X.astype(np.float64))
+    log_case("c5_apply_f32_b16_csr", n=n)
+    Y = op.apply(torch.from_numpy(X).cuda())
+    assert _rel(Y.cpu().numpy()[rows].astype(np.float64), refX) <= 2e-6
+    op.close()
+    del Y
+    log_case("c5_apply_f64_otf", n=n)
+    op = mcd.Operator(m, kd, storage="otf")
+    y = op.apply(torch.from_numpy(x).cuda())
+    assert _rel(y.cpu().numpy()[rows], ref) <= 1e-12
+    op.close()
+
+
 @pytest.mark.parametrize("case", ["c1", "ring4_18", "imp", "c1_beta0_full", "sq4x4_tp"])
 def test_step_sampler_bit_exact(case):
     """The paper's step sampler on the GPU against the oracle (keys, steps)."""
