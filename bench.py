@@ -379,7 +379,8 @@ def main():
     chosen = info["kernel"]
     per_kernel = {}
     if info["storage"] == "csr":
-        for kname in ("stream", "stream_xcd", "merge", "rowchunk"):
+        for kname in ("stream", "stream_xcd", "merge", "rowchunk", "stream_small",
+                      "stream_small_xcd"):
             op.set_kernel(kname)
             per_kernel[kname] = round(time_apply(50), 5)
         op.set_kernel(chosen)
@@ -405,8 +406,10 @@ def main():
             spmm[f"{tname}_b{b}"] = {"ms": round(ms, 4), "ms_per_vector": round(ms / b, 5),
                                      "GBs": round(byts / ms / 1e6, 1)}
             del X, Y
-    kernel_names = {"stream": "k_spmv_stream<double,256>",
-                    "stream_xcd": "k_spmv_stream<double,256> (XCD-major order)",
+    kernel_names = {"stream": "k_spmv_stream<double,256,4096>",
+                    "stream_xcd": "k_spmv_stream<double,256,4096> (XCD-major order)",
+                    "stream_small": "k_spmv_stream<double,256,2560>",
+                    "stream_small_xcd": "k_spmv_stream<double,256,2560> (XCD-major order)",
                     "rowchunk": "k_apply_group<double,1,256,false> (row-chunk)",
                     "merge": "k_spmv_merge<double> + k_merge_fixup<double>"}
 

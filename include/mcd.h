@@ -169,9 +169,12 @@ int mcd_op_info(const mcd_op *op, mcd_op_info_t *info);
  *       one contiguous slice of rows, so its L2 serves mostly its own slice
  *       of x;
  *   4 = row-chunk: one thread per row, 16 column words then 16 gathers in
- *       flight per thread, no LDS staging (XCD-major row tiles).
- * Both give the same result up to summation order.  At creation a CSR
- * operator times both on its own matrix and keeps the faster one.
+ *       flight per thread, no LDS staging (XCD-major row tiles);
+ *   5 = stream with smaller row blocks (<= 2560 nonzeros per workgroup,
+ *       less LDS, more workgroups resident per CU);
+ *   6 = 5 in XCD-major order.
+ * All give the same result up to summation order.  At creation a CSR
+ * operator times every kernel on its own matrix and keeps the fastest.
  * MCD_E_INVALID for other values or an on-the-fly operator. */
 int mcd_op_set_kernel(mcd_op *op, int32_t kernel);
 

@@ -24,7 +24,8 @@ MCD_OK, MCD_NOCONV = 0, 1
 STORAGE = {"auto": 0, "on_the_fly": 1, "otf": 1, "csr": 2}
 STORAGE_NAME = {0: "auto", 1: "on_the_fly", 2: "csr"}
 DTYPE = {"f64": 0, "f32": 1}
-KERNEL_NAME = {1: "stream", 2: "merge", 3: "stream_xcd", 4: "rowchunk"}
+KERNEL_NAME = {1: "stream", 2: "merge", 3: "stream_xcd", 4: "rowchunk", 5: "stream_small",
+               6: "stream_small_xcd"}
 
 P = ctypes.POINTER
 c_i32, c_i64, c_u64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
@@ -212,7 +213,8 @@ class Operator:
                     device_bytes=i.device_bytes, build_ms=i.build_ms)
 
     def set_kernel(self, name: str):
-        """Force the one-vector CSR kernel: 'stream', 'merge', 'stream_xcd' or 'rowchunk'."""
+        """Force the one-vector CSR kernel: 'stream', 'merge', 'stream_xcd', 'rowchunk',
+        'stream_small' or 'stream_small_xcd'."""
         _check(lib().mcd_op_set_kernel(self.handle, {v: k for k, v in KERNEL_NAME.items()}[name]),
                "mcd_op_set_kernel")
 

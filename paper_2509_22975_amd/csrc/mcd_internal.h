@@ -45,12 +45,21 @@ constexpr uint64_t kEmpty = ~0ull;           // hash sentinel, never a valid key
 // so one |t| allows 2^31 rows, two 2^30, ..., 32 classes 2^26.
 constexpr int kMaxClasses = 32;              // packed CSR: distinct |t| values
 constexpr int kStreamNnzMax = 4096;          // LDS products per stream block
+constexpr int kStreamNnzSmall = 2560;        // ... of the small-block stream variant
 constexpr int kMergeBS = 256;                // merge-path SpMV: threads per workgroup
 constexpr int kMergeDepth = 8;               // nonzeros per thread per chunk
 constexpr int kMergeK = kMergeBS * kMergeDepth;  // path items (nonzeros + 9 per row) per chunk
 constexpr int kMergeRowCost = 9;             // so a chunk ends < kMergeBS rows
 
-enum { KERNEL_STREAM = 1, KERNEL_MERGE = 2, KERNEL_STREAM_XCD = 3, KERNEL_ROWCHUNK = 4 };
+enum {
+    KERNEL_STREAM = 1,
+    KERNEL_MERGE = 2,
+    KERNEL_STREAM_XCD = 3,
+    KERNEL_ROWCHUNK = 4,
+    KERNEL_STREAM_S = 5,       // stream with <= kStreamNnzSmall products per block
+    KERNEL_STREAM_S_XCD = 6,   // ... in XCD-major order
+    KERNEL_LAST = 6
+};
 constexpr int kNumXcd = 8;                   // gfx950: workgroups are dealt round-robin to 8 XCDs
 
 // One hopping bond with i < j, prepared for bit arithmetic.
@@ -94,7 +103,8 @@ struct mcd_op {
     int device;
     int64_t n;
     int32_t storage;
-    int32_t rows_per_block;
+    int32_t rows_per_block;    // stream kernel: rows per block (<= kStreamNnzMax nonzeros)
+    int32_t rows_per_block_s;  // small-block stream kernel (<= kStreamNnzSmall nonzeros)
     int64_t nnz;
     int64_t device_bytes;
     double build_ms;
@@ -121,15 +131,10 @@ struct mcd_op {
     int64_t *d_split_i, *d_split_j;   // [nchunks + 1]
     double *d_carry;                  // [nchunks]
     int64_t *d_carry_row;             // [nchunks]
-    double tune_ms[5];                // measured per-apply time per kernel
+    double tune_ms[mcd::KERNEL_LAST + 1];  // measured per-apply time per kernel
 };
 
 namespace mcd {
-
-// Launch geometry of the stream SpMV for an operator.
-inline int64_t stream_blocks(const mcd_op *op) {
-    return (op->n + op->rows_per_block - 1) / op->rows_per_block;
-}
 
 // Operator internals used by the solvers (defined in mcd_op.hip).
 // y = sx * H (x) for one double vector, sx read on the device (sx_mode 0:

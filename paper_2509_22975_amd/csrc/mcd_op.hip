@@ -134,14 +134,14 @@ __global__ void k_block_max(int64_t n, int R, const int64_t *__restrict__ rowptr
 // then up to DEPTH packed words (coalesced), then the DEPTH gathers of x;
 // the signed products go to LDS and each row adds its run in entry order
 // after d_r x_r.  Optional partial of sum_r (sx x_r) y_r per workgroup.
-template <typename T, int BS>
+template <typename T, int BS, int NMAX>
 __global__ __launch_bounds__(BS) void k_spmv_stream(
     int64_t n, int R, const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ colw,
     const DevModel *__restrict__ m, const double *__restrict__ diag, const T *__restrict__ x,
     T *__restrict__ y, const double *__restrict__ sx_dev, int sx_mode,
     double *__restrict__ partials, int64_t nblocks, int xcd_major) {
-    constexpr int DEPTH = kStreamNnzMax / BS;
-    __shared__ T prod[kStreamNnzMax];
+    constexpr int DEPTH = NMAX / BS;
+    __shared__ T prod[NMAX];
     __shared__ T vtab[kMaxClasses];
     const int tid = threadIdx.x;
     // XCD-major mapping: workgroup b runs on XCD b % 8, so giving XCD k the
@@ -158,41 +158,37 @@ __global__ __launch_bounds__(BS) void k_spmv_stream(
     }
     const int64_t r0 = blk * R;
     const int64_t r1 = min(r0 + (int64_t)R, n);
-    const int64_t r = r0 + tid;
-    const bool own = tid < R && r < r1;
-    int64_t rs = 0, re = 0;
-    double dr = 0.0;
-    T xr = (T)0;
-    if (own) {
-        rs = rowptr[r];
-        re = rowptr[r + 1];
-        dr = diag[r];
-        xr = x[r];
-    }
+    // Every load below is unconditional on a clamped, valid address (lanes
+    // past the end are masked when the products are formed): no branches
+    // around loads, so the compiler keeps them all in flight and waits by
+    // count instead of draining the memory queue.
+    const bool own = tid < R && r0 + tid < r1;
+    const int64_t r = min(r0 + (int64_t)tid, r1 - 1);
+    const int64_t rs = rowptr[r], re = rowptr[r + 1];
+    const double dr = diag[r];
+    const T xr = x[r];
     if (tid < kMaxClasses) vtab[tid] = (T)m->vtab[tid];
     const uint32_t cmask = m->col_mask, cbits = m->col_bits;
     const int64_t e0 = rowptr[r0];
     const int cnt = (int)(rowptr[r1] - e0);
-    const uint32_t *__restrict__ cw = colw + e0;
     uint32_t w[DEPTH];
     T xv[DEPTH];
+    if (cnt > 0) {   // uniform over the workgroup
+        const uint32_t *__restrict__ cw = colw + e0;
 #pragma unroll
-    for (int j = 0; j < DEPTH; j++) {
-        const int e = tid + j * BS;
-        w[j] = (e < cnt) ? cw[e] : 0u;
-    }
+        for (int j = 0; j < DEPTH; j++) w[j] = cw[min(tid + j * BS, cnt - 1)];
 #pragma unroll
-    for (int j = 0; j < DEPTH; j++) {
-        const int e = tid + j * BS;
-        xv[j] = (e < cnt) ? x[w[j] & cmask] : (T)0;
+        for (int j = 0; j < DEPTH; j++) xv[j] = x[w[j] & cmask];
     }
     __syncthreads();
+    if (cnt > 0) {
 #pragma unroll
-    for (int j = 0; j < DEPTH; j++) {
-        const int e = tid + j * BS;
-        if (e < cnt) {
-            const T v = vtab[(w[j] & 0x7fffffffu) >> cbits];
-            prod[e] = (w[j] >> 31) ? -(v * xv[j]) : v * xv[j];
+        for (int j = 0; j < DEPTH; j++) {
+            const int e = tid + j * BS;
+            if (e < cnt) {
+                const T v = vtab[(w[j] & 0x7fffffffu) >> cbits];
+                prod[e] = (w[j] >> 31) ? -(v * xv[j]) : v * xv[j];
+            }
         }
     }
     __syncthreads();
@@ -510,18 +506,25 @@ static int build_csr(mcd_op *op, hipStream_t s) {
     hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
                        op->d_model, op->d_hash, op->hash_mask, op->d_rowptr, op->d_colw);
     MCD_HIP(hipGetLastError());
-    // Largest power-of-two row block whose nonzeros fit the LDS product buffer.
+    // Largest power-of-two row block whose nonzeros fit the LDS product buffer
+    // (one choice per buffer size of the stream kernels).
     unsigned long long *d_max = nullptr;
     MCD_HIP(hipMalloc(&d_max, sizeof(unsigned long long)));
     op->rows_per_block = 1;
+    op->rows_per_block_s = 1;
+    bool got_big = false;
     for (int R = 256; R >= 1; R >>= 1) {
         MCD_HIP(hipMemsetAsync(d_max, 0, sizeof(unsigned long long), s));
         hipLaunchKernelGGL(k_block_max, dim3(512), dim3(256), 0, s, n, R, op->d_rowptr, d_max);
         unsigned long long mx = 0;
         MCD_HIP(hipMemcpyAsync(&mx, d_max, sizeof(mx), hipMemcpyDeviceToHost, s));
         MCD_HIP(hipStreamSynchronize(s));
-        if (mx <= (unsigned long long)kStreamNnzMax) {
+        if (!got_big && mx <= (unsigned long long)kStreamNnzMax) {
             op->rows_per_block = R;
+            got_big = true;
+        }
+        if (mx <= (unsigned long long)kStreamNnzSmall) {
+            op->rows_per_block_s = R;
             break;
         }
     }
@@ -587,14 +590,23 @@ static int csr_one(const mcd_op *op, const T *x, T *y, const double *sx_dev, int
         }
         return MCD_OK;
     }
-    const int64_t nb = stream_blocks(op);
-    const bool xcd = op->kernel == KERNEL_STREAM_XCD;
+    const bool small = op->kernel == KERNEL_STREAM_S || op->kernel == KERNEL_STREAM_S_XCD;
+    const int R = small ? op->rows_per_block_s : op->rows_per_block;
+    const int64_t nb = (n + R - 1) / R;
+    const bool xcd = op->kernel == KERNEL_STREAM_XCD || op->kernel == KERNEL_STREAM_S_XCD;
     const int64_t grid = xcd ? kNumXcd * ((nb + kNumXcd - 1) / kNumXcd) : nb;
     MCD_REQUIRE(!dot_out || grid <= op->max_partials, MCD_E_CAPACITY,
                 "reduction scratch too small");
-    hipLaunchKernelGGL((k_spmv_stream<T, 256>), dim3((unsigned)grid), dim3(256), 0, s, n,
-                       op->rows_per_block, op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x,
-                       y, sx_dev, sx_mode, dot_out ? op->d_partials : nullptr, nb, xcd ? 1 : 0);
+    if (small)
+        hipLaunchKernelGGL((k_spmv_stream<T, 256, kStreamNnzSmall>), dim3((unsigned)grid),
+                           dim3(256), 0, s, n, R, op->d_rowptr, op->d_colw, op->d_model,
+                           op->d_diag, x, y, sx_dev, sx_mode, dot_out ? op->d_partials : nullptr,
+                           nb, xcd ? 1 : 0);
+    else
+        hipLaunchKernelGGL((k_spmv_stream<T, 256, kStreamNnzMax>), dim3((unsigned)grid),
+                           dim3(256), 0, s, n, R, op->d_rowptr, op->d_colw, op->d_model,
+                           op->d_diag, x, y, sx_dev, sx_mode, dot_out ? op->d_partials : nullptr,
+                           nb, xcd ? 1 : 0);
     MCD_HIP(hipGetLastError());
     if (dot_out) {
         hipLaunchKernelGGL((k_finalize_sum<1024>), dim3(1), dim3(1024), 0, s, (int)grid,
@@ -604,7 +616,7 @@ static int csr_one(const mcd_op *op, const T *x, T *y, const double *sx_dev, int
     return MCD_OK;
 }
 
-// Time both one-vector kernels on this matrix and keep the faster (a
+// Time every one-vector kernel on this matrix and keep the fastest (a
 // per-operator autotune; a few applies of the diagonal as the vector).
 static int tune_kernel(mcd_op *op, hipStream_t s) {
     if (op->n == 0) return MCD_OK;
@@ -617,7 +629,8 @@ static int tune_kernel(mcd_op *op, hipStream_t s) {
     MCD_HIP(hipEventCreate(&b));
     double best = 1e300;
     int pick = KERNEL_STREAM;
-    for (int k : {KERNEL_STREAM, KERNEL_STREAM_XCD, KERNEL_MERGE, KERNEL_ROWCHUNK}) {
+    for (int k : {KERNEL_STREAM, KERNEL_STREAM_XCD, KERNEL_MERGE, KERNEL_ROWCHUNK,
+                  KERNEL_STREAM_S, KERNEL_STREAM_S_XCD}) {
         op->kernel = k;
         MCD_TRY(csr_one<double>(op, x, y, nullptr, 0, nullptr, s));
         MCD_HIP(hipEventRecord(a, s));
@@ -802,6 +815,7 @@ extern "C" int mcd_op_create(const mcd_model *model, const uint64_t *keys_dev, i
     }
     op->storage = st;
     op->rows_per_block = 256;
+    op->rows_per_block_s = 256;
     if (st == MCD_STORAGE_CSR) {
         rc = build_csr(op, s);
         if (rc < 0) return fail(rc);
@@ -854,7 +868,7 @@ extern "C" int mcd_op_info(const mcd_op *op, mcd_op_info_t *info) {
 extern "C" int mcd_op_set_kernel(mcd_op *op, int32_t kernel) {
     MCD_REQUIRE(op != nullptr, MCD_E_INVALID, "op is NULL");
     MCD_REQUIRE(op->storage == MCD_STORAGE_CSR, MCD_E_INVALID, "operator has no CSR");
-    MCD_REQUIRE(kernel >= KERNEL_STREAM && kernel <= KERNEL_ROWCHUNK, MCD_E_INVALID,
+    MCD_REQUIRE(kernel >= KERNEL_STREAM && kernel <= KERNEL_LAST, MCD_E_INVALID,
                 "kernel %d unknown", kernel);
     op->kernel = kernel;
     return MCD_OK;

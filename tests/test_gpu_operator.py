@@ -115,7 +115,8 @@ def test_connectivity_bit_exact(name, storage):
 
 
 def _kernels(op, storage):
-    return ["stream", "merge", "stream_xcd", "rowchunk"] if storage == "csr" else [None]
+    return (["stream", "merge", "stream_xcd", "rowchunk", "stream_small", "stream_small_xcd"]
+            if storage == "csr" else [None])
 
 
 @pytest.mark.parametrize("name", list(MODELS))
@@ -153,7 +154,8 @@ def test_merge_path_long_and_empty_rows():
         H = ham.build_csr(keys, m)
         x = W.random_vector(len(keys), 3)
         op = mcd.Operator(m, mcd.keys_from_numpy(keys), storage="csr")
-        for kern in ("stream", "merge", "stream_xcd", "rowchunk"):
+        for kern in ("stream", "merge", "stream_xcd", "rowchunk", "stream_small",
+                     "stream_small_xcd"):
             op.set_kernel(kern)
             y = op.apply(torch.from_numpy(x).cuda()).cpu().numpy()
             assert _rel(y, H @ x) <= 1e-12, (name, kern)
@@ -230,7 +232,8 @@ def test_apply_c2_full_size_sampled_rows():
     ref = ham.apply_rows(keys, rows, m, x)
     kd = mcd.keys_from_numpy(keys)
     for storage, kern in (("csr", "stream"), ("csr", "merge"), ("csr", "stream_xcd"),
-                          ("csr", "rowchunk"), ("otf", None)):
+                          ("csr", "rowchunk"), ("csr", "stream_small"),
+                          ("csr", "stream_small_xcd"), ("otf", None)):
         op = mcd.Operator(m, kd, storage=storage)
         if kern:
             op.set_kernel(kern)
