@@ -105,6 +105,7 @@ struct mcd_op {
     int32_t storage;
     int32_t rows_per_block;    // stream kernel: rows per block (<= kStreamNnzMax nonzeros)
     int32_t rows_per_block_s;  // small-block stream kernel (<= kStreamNnzSmall nonzeros)
+    int32_t group_chunk;       // block products: packed words per chunk (8 or 16)
     int64_t nnz;
     int64_t device_bytes;
     double build_ms;

@@ -447,6 +447,58 @@ __global__ __launch_bounds__(BS) void k_apply_group(
     if (partials != nullptr) store_partial<BS>(block_sum<BS>(dot), partials);
 }
 
+// Block product y = H~ X for NV vectors (row-major X[n][NV]) from the packed
+// CSR, without the scaling / dot-product options of k_apply_group: NV lanes
+// per row, the row's words loaded CH at a time (one coalesced access) and
+// broadcast by lane shuffles, CH gathers of NV contiguous values in flight,
+// sum in entry order.  CH follows the mean row length (short rows waste the
+// masked slots of a long chunk).  XCD-major row tiles.
+template <typename T, int NV, int CH>
+__global__ __launch_bounds__(256) void k_block_csr(
+    int64_t n, const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ colw,
+    const DevModel *__restrict__ m, const double *__restrict__ diag, const T *__restrict__ x,
+    T *__restrict__ y, int64_t ntiles, int rows_per_tile) {
+    __shared__ T vtab[kMaxClasses];
+    if (threadIdx.x < kMaxClasses) vtab[threadIdx.x] = (T)m->vtab[threadIdx.x];
+    __syncthreads();
+    const uint32_t cmask = m->col_mask, cbits = m->col_bits;
+    constexpr int RPB = 256 / NV;
+    constexpr int WPL = (CH + NV - 1) / NV;
+    const int64_t per = (ntiles + kNumXcd - 1) / kNumXcd;
+    const int64_t tile = (int64_t)(blockIdx.x % kNumXcd) * per + blockIdx.x / kNumXcd;
+    if (tile >= ntiles) return;
+    const int lane = threadIdx.x % NV;
+    const int64_t rbeg = tile * rows_per_tile;
+    const int64_t rend = min(rbeg + (int64_t)rows_per_tile, n);
+    for (int64_t r = rbeg + threadIdx.x / NV; r < rend; r += RPB) {
+        T acc = (T)diag[r] * x[r * NV + lane];
+        const int64_t e1 = rowptr[r + 1];
+        for (int64_t base = rowptr[r]; base < e1; base += CH) {
+            uint32_t mw[WPL];
+#pragma unroll
+            for (int q = 0; q < WPL; q++) {
+                const int64_t e = base + q * NV + lane;
+                mw[q] = (q * NV + lane < CH && e < e1) ? colw[e] : 0u;
+            }
+            uint32_t wj[CH];
+            T xv[CH];
+#pragma unroll
+            for (int j = 0; j < CH; j++) {
+                wj[j] = (uint32_t)__shfl((int)mw[j / NV], j % NV, NV);
+                xv[j] = (base + j < e1) ? x[(int64_t)(wj[j] & cmask) * NV + lane] : (T)0;
+            }
+#pragma unroll
+            for (int j = 0; j < CH; j++) {
+                if (base + j < e1) {
+                    const T v = vtab[(wj[j] & 0x7fffffffu) >> cbits];
+                    acc += (wj[j] >> 31) ? -(v * xv[j]) : v * xv[j];
+                }
+            }
+        }
+        y[r * NV + lane] = acc;
+    }
+}
+
 __global__ void k_conn_count(int64_t row0, int64_t row1, const uint64_t *__restrict__ keys,
                              const DevModel *__restrict__ m, const HashSlot *__restrict__ h,
                              uint64_t hmask, int64_t *__restrict__ cnt) {
@@ -529,6 +581,8 @@ static int build_csr(mcd_op *op, hipStream_t s) {
         }
     }
     MCD_HIP(hipFree(d_max));
+    // block products: 16-word chunks for long rows, 8 for short ones
+    op->group_chunk = (nnz < 10 * n) ? 8 : 16;
     // merge-path split points
     op->nchunks = (kMergeRowCost * n + nnz + kMergeK - 1) / kMergeK;
     if (op->nchunks < 1) op->nchunks = 1;
@@ -670,10 +724,14 @@ static int launch_apply(const mcd_op *op, int nvec, const T *x, T *y, hipStream_
             hipLaunchKernelGGL((k_apply_group<T, NV, 256, true>), dim3(grid), dim3(256), 0, s, \
                                n, op->d_rowptr, op->d_colw, op->d_model, op->d_keys,           \
                                op->d_hash, op->hash_mask, op->d_diag, x, y, ntiles, rpt);      \
+        else if (op->group_chunk == 8)                                                         \
+            hipLaunchKernelGGL((k_block_csr<T, NV, 8>), dim3(grid), dim3(256), 0, s, n,        \
+                               op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x, y,        \
+                               ntiles, rpt);                                                   \
         else                                                                                   \
-            hipLaunchKernelGGL((k_apply_group<T, NV, 256, false>), dim3(grid), dim3(256), 0,   \
-                               s, n, op->d_rowptr, op->d_colw, op->d_model, op->d_keys,        \
-                               op->d_hash, op->hash_mask, op->d_diag, x, y, ntiles, rpt);      \
+            hipLaunchKernelGGL((k_block_csr<T, NV, 16>), dim3(grid), dim3(256), 0, s, n,       \
+                               op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x, y,        \
+                               ntiles, rpt);                                                   \
         break;                                                                                 \
     }
     switch (nvec) {
@@ -816,6 +874,7 @@ extern "C" int mcd_op_create(const mcd_model *model, const uint64_t *keys_dev, i
     op->storage = st;
     op->rows_per_block = 256;
     op->rows_per_block_s = 256;
+    op->group_chunk = 16;
     if (st == MCD_STORAGE_CSR) {
         rc = build_csr(op, s);
         if (rc < 0) return fail(rc);
