@@ -265,10 +265,16 @@ def c5_cluster(mcd, W, torch):
     b1 = 8 * (n + 1) + 4 * nnz + 24 * n
     b16 = 16 * n + 4 * nnz + 2 * 16 * 4 * n
     ms1, ms16 = tm(lambda: op.apply(x, y), 10), tm(lambda: op.apply(X, Y), 5)
+    variants = {}
+    for kname in ("stream", "stream_xcd", "merge", "rowchunk", "stream_small", "stream_small_xcd"):
+        op.set_kernel(kname)
+        variants[kname] = round(tm(lambda: op.apply(x, y), 10), 4)
+    op.set_kernel(inf["kernel"])
     out["csr"] = {"nnz_offdiag": nnz, "nnz_per_row": round(nnz / n, 3),
                   "op_build_ms": round(inf["build_ms"], 1), "kernel": inf["kernel"],
                   "device_bytes": inf["device_bytes"],
                   "f64_1vec_ms": round(ms1, 4), "f64_1vec_GBs": round(b1 / ms1 / 1e6, 1),
+                  "f64_1vec_ms_per_kernel_variant": variants,
                   "f32_16vec_ms": round(ms16, 4), "f32_16vec_GBs": round(b16 / ms16 / 1e6, 1),
                   "f32_16vec_ms_per_vector": round(ms16 / 16, 4)}
     t0 = time.perf_counter()
@@ -408,8 +414,8 @@ def main():
             del X, Y
     kernel_names = {"stream": "k_spmv_stream<double,256,4096>",
                     "stream_xcd": "k_spmv_stream<double,256,4096> (XCD-major order)",
-                    "stream_small": "k_spmv_stream<double,256,2560>",
-                    "stream_small_xcd": "k_spmv_stream<double,256,2560> (XCD-major order)",
+                    "stream_small": "k_spmv_stream<double,256,1024>",
+                    "stream_small_xcd": "k_spmv_stream<double,256,1024> (XCD-major order)",
                     "rowchunk": "k_apply_group<double,1,256,false> (row-chunk)",
                     "merge": "k_spmv_merge<double> + k_merge_fixup<double>"}
 

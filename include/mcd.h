@@ -170,8 +170,8 @@ int mcd_op_info(const mcd_op *op, mcd_op_info_t *info);
  *       of x;
  *   4 = row-chunk: one thread per row, 16 column words then 16 gathers in
  *       flight per thread, no LDS staging (XCD-major row tiles);
- *   5 = stream with smaller row blocks (<= 2560 nonzeros per workgroup,
- *       less LDS, more workgroups resident per CU);
+ *   5 = stream with smaller row blocks (<= 1024 nonzeros per workgroup:
+ *       less LDS and fewer loads per thread, for short rows);
  *   6 = 5 in XCD-major order.
  * All give the same result up to summation order.  At creation a CSR
  * operator times every kernel on its own matrix and keeps the fastest.

@@ -45,7 +45,7 @@ constexpr uint64_t kEmpty = ~0ull;           // hash sentinel, never a valid key
 // so one |t| allows 2^31 rows, two 2^30, ..., 32 classes 2^26.
 constexpr int kMaxClasses = 32;              // packed CSR: distinct |t| values
 constexpr int kStreamNnzMax = 4096;          // LDS products per stream block
-constexpr int kStreamNnzSmall = 2560;        // ... of the small-block stream variant
+constexpr int kStreamNnzSmall = 1024;        // ... of the small-block stream variant
 constexpr int kMergeBS = 256;                // merge-path SpMV: threads per workgroup
 constexpr int kMergeDepth = 8;               // nonzeros per thread per chunk
 constexpr int kMergeK = kMergeBS * kMergeDepth;  // path items (nonzeros + 9 per row) per chunk
@@ -105,7 +105,7 @@ struct mcd_op {
     int32_t storage;
     int32_t rows_per_block;    // stream kernel: rows per block (<= kStreamNnzMax nonzeros)
     int32_t rows_per_block_s;  // small-block stream kernel (<= kStreamNnzSmall nonzeros)
-    int32_t group_chunk;       // block products: packed words per chunk (8 or 16)
+    int32_t group_chunk;       // row-parallel products: packed words per chunk (4, 8 or 16)
     int64_t nnz;
     int64_t device_bytes;
     double build_ms;

@@ -375,7 +375,7 @@ __global__ __launch_bounds__(256) void k_merge_fixup(int64_t n, int64_t nch,
 // are dealt XCD-major (XCD k gets one contiguous slice of rows), so the
 // gathered rows of X -- mostly inside the same up-string segment for
 // down-spin hops -- are reused from that XCD's L2.
-template <typename T, int NV, int BS, bool OTF>
+template <typename T, int NV, int BS, bool OTF, int CH = 16>
 __global__ __launch_bounds__(BS) void k_apply_group(
     int64_t n, const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ colw,
     const DevModel *__restrict__ m, const uint64_t *__restrict__ keys,
@@ -408,7 +408,6 @@ __global__ __launch_bounds__(BS) void k_apply_group(
             // a lane shuffle and issues all CH gathers before the first FMA, so
             // a row costs ~2 dependent memory round trips per chunk instead of
             // one per nonzero.  Accumulation stays in entry order.
-            constexpr int CH = 16;
             constexpr int WPL = (CH + NV - 1) / NV;
             const int64_t e1 = rowptr[r + 1];
             for (int64_t base = rowptr[r]; base < e1; base += CH) {
@@ -581,8 +580,8 @@ static int build_csr(mcd_op *op, hipStream_t s) {
         }
     }
     MCD_HIP(hipFree(d_max));
-    // block products: 16-word chunks for long rows, 8 for short ones
-    op->group_chunk = (nnz < 10 * n) ? 8 : 16;
+    // row-parallel products: words per chunk from the mean row length
+    op->group_chunk = (nnz < 4 * n) ? 4 : (nnz < 10 * n) ? 8 : 16;
     // merge-path split points
     op->nchunks = (kMergeRowCost * n + nnz + kMergeK - 1) / kMergeK;
     if (op->nchunks < 1) op->nchunks = 1;
@@ -632,10 +631,18 @@ static int csr_one(const mcd_op *op, const T *x, T *y, const double *sx_dev, int
         const int64_t grid = kNumXcd * ((ntiles + kNumXcd - 1) / kNumXcd);
         MCD_REQUIRE(!dot_out || grid <= op->max_partials, MCD_E_CAPACITY,
                     "reduction scratch too small");
-        hipLaunchKernelGGL((k_apply_group<T, 1, 256, false>), dim3((unsigned)grid), dim3(256), 0,
-                           s, n, op->d_rowptr, op->d_colw, op->d_model, op->d_keys, op->d_hash,
-                           op->hash_mask, op->d_diag, x, y, ntiles, rpt, sx_dev, sx_mode,
-                           dot_out ? op->d_partials : nullptr);
+#define MCD_ROWCHUNK(C)                                                                      \
+    hipLaunchKernelGGL((k_apply_group<T, 1, 256, false, C>), dim3((unsigned)grid), dim3(256), \
+                       0, s, n, op->d_rowptr, op->d_colw, op->d_model, op->d_keys, op->d_hash, \
+                       op->hash_mask, op->d_diag, x, y, ntiles, rpt, sx_dev, sx_mode,        \
+                       dot_out ? op->d_partials : nullptr)
+        if (op->group_chunk == 4)
+            MCD_ROWCHUNK(4);
+        else if (op->group_chunk == 8)
+            MCD_ROWCHUNK(8);
+        else
+            MCD_ROWCHUNK(16);
+#undef MCD_ROWCHUNK
         MCD_HIP(hipGetLastError());
         if (dot_out) {
             hipLaunchKernelGGL((k_finalize_sum<1024>), dim3(1), dim3(1024), 0, s, (int)grid,
@@ -724,6 +731,10 @@ static int launch_apply(const mcd_op *op, int nvec, const T *x, T *y, hipStream_
             hipLaunchKernelGGL((k_apply_group<T, NV, 256, true>), dim3(grid), dim3(256), 0, s, \
                                n, op->d_rowptr, op->d_colw, op->d_model, op->d_keys,           \
                                op->d_hash, op->hash_mask, op->d_diag, x, y, ntiles, rpt);      \
+        else if (op->group_chunk == 4)                                                         \
+            hipLaunchKernelGGL((k_block_csr<T, NV, 4>), dim3(grid), dim3(256), 0, s, n,        \
+                               op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x, y,        \
+                               ntiles, rpt);                                                   \
         else if (op->group_chunk == 8)                                                         \
             hipLaunchKernelGGL((k_block_csr<T, NV, 8>), dim3(grid), dim3(256), 0, s, n,        \
                                op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x, y,        \
