@@ -37,16 +37,18 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def traffic_from_profile(alg_bytes):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel source; else None."""
+def traffic_from_profile(grid_threads):
+    """HBM bytes per launch of the stream kernel at this launch shape (grid in
+    threads: the plain and XCD-major orders differ) from the committed
+    rocprofv3 PMC summary, if it was taken on the current kernel source;
+    else None."""
     p = os.path.join(HERE, "profiles", "spmv_stream_c2_pmc.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     if d.get("kernel_source_sha") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("hbm_bytes_per_launch_by_grid", {}).get(str(grid_threads))
 
 
 def cpu_baseline(model, keys_np, x_np, nnz_per_row):
@@ -392,6 +394,12 @@ def main():
         op.set_kernel(chosen)
     k_ms = time_apply()
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    # launch shape of the selected stream kernel (threads), to find its counters
+    rpb = info["rows_per_block"]
+    nblk = (n + rpb - 1) // rpb
+    grid_threads = 256 * (8 * ((nblk + 7) // 8) if chosen == "stream_xcd" else nblk)
+    if chosen not in ("stream", "stream_xcd"):
+        grid_threads = -1
 
     # Block products (the batched form): ms per apply and per vector.
     spmm = {}
@@ -434,7 +442,7 @@ def main():
                    "bytes_per_apply": alg_bytes},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profile(alg_bytes),
+                     "traffic": traffic_from_profile(grid_threads),
                      "kernel": kernel_names.get(chosen, "k_apply_group (on-the-fly)"),
                      "kernel_ms": round(k_ms, 5), "ms_per_kernel_variant": per_kernel},
         "cpu_baseline": None,

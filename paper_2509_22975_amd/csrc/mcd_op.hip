@@ -707,6 +707,14 @@ static int tune_kernel(mcd_op *op, hipStream_t s) {
             pick = k;
         }
     }
+    // Between the plain and the XCD-major order of the same kernel, keep the
+    // XCD-major one unless the plain one is clearly faster: it moves less
+    // data over the fabric (each L2 serves its own slice of x).
+    if (pick == KERNEL_STREAM && op->tune_ms[KERNEL_STREAM_XCD] <= 1.03 * op->tune_ms[KERNEL_STREAM])
+        pick = KERNEL_STREAM_XCD;
+    if (pick == KERNEL_STREAM_S &&
+        op->tune_ms[KERNEL_STREAM_S_XCD] <= 1.03 * op->tune_ms[KERNEL_STREAM_S])
+        pick = KERNEL_STREAM_S_XCD;
     op->kernel = pick;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
