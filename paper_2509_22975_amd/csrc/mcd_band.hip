@@ -337,6 +337,124 @@ static void block_cf(const BandResult &br, cplx z, int p, cplx *out) {
         }
 }
 
+// ---------------------------------------------------------------------------
+// Small dense steps of the block recurrence on the device (P <= 16, one
+// workgroup of one wavefront): the coefficient matrices never leave HBM, so
+// a block step needs no host round trip.
+
+// dst = (src + src^T) / 2
+__global__ __launch_bounds__(64) void k_sym(int P, const double *__restrict__ src,
+                                            double *__restrict__ dst) {
+    for (int e = threadIdx.x; e < P * P; e += 64) {
+        const int a = e / P, b = e % P;
+        dst[e] = 0.5 * (src[a * P + b] + src[b * P + a]);
+    }
+}
+
+// dst = src^T
+__global__ __launch_bounds__(64) void k_transpose(int P, const double *__restrict__ src,
+                                                  double *__restrict__ dst) {
+    for (int e = threadIdx.x; e < P * P; e += 64) {
+        const int a = e / P, b = e % P;
+        dst[e] = src[b * P + a];
+    }
+}
+
+// QR factor of a block W from its Gram matrix M = W^T W by pivoted Cholesky
+// (rank revealing, the band method's deflation): at step k the column with
+// the largest remaining Schur diagonal d is taken if d > thr (thr = thr_abs
+// for mode 0, 1e-2 max diag M for mode 1, the re-orthogonalising pass), row k
+// of R = sqrt(d)^-1 (Schur row), and the Schur complement is updated.  With
+// rank r, W = Q R (R: r x P, zero rows below), Q = W Xm with
+// Xm = Pi R11^-1 (zero columns beyond r).  Bacc <- R Bacc (R itself when
+// init), *rank_out = r.
+__global__ __launch_bounds__(64) void k_pchol(int P, const double *__restrict__ M, int mode,
+                                              double thr_abs, double *__restrict__ Xm,
+                                              double *__restrict__ Bm,
+                                              double *__restrict__ Bacc, int init,
+                                              int *__restrict__ rank_out) {
+    __shared__ double S[16][16];
+    __shared__ double R[16][16];
+    __shared__ double Ri[16][16];
+    __shared__ double Bt[16][16];
+    __shared__ int piv[16];
+    __shared__ int chosen[16];
+    const int t = threadIdx.x;
+    for (int e = t; e < 256; e += 64) {
+        const int a = e / 16, b = e % 16;
+        S[a][b] = (a < P && b < P) ? M[a * P + b] : 0.0;
+        R[a][b] = 0.0;
+        Ri[a][b] = 0.0;
+    }
+    if (t < 16) {
+        chosen[t] = 0;
+        piv[t] = 0;
+    }
+    __syncthreads();
+    double maxd = 0.0;
+    for (int i = 0; i < P; i++) maxd = fmax(maxd, S[i][i]);
+    const double thr = mode == 0 ? thr_abs : 1e-2 * maxd;
+    int r = 0;
+    for (int k = 0; k < P; k++) {
+        int q = -1;
+        double dq = 0.0;
+        for (int i = 0; i < P; i++)
+            if (!chosen[i] && S[i][i] > dq) {
+                dq = S[i][i];
+                q = i;
+            }
+        if (q < 0 || !(dq > thr)) break;     // the same decision in every lane
+        const double sq = sqrt(dq);
+        if (t < P) R[k][t] = chosen[t] ? 0.0 : S[q][t] / sq;
+        __syncthreads();
+        if (t == 0) {
+            chosen[q] = 1;
+            piv[k] = q;
+        }
+        for (int e = t; e < P * P; e += 64) {
+            const int i = e / P, j = e % P;
+            S[i][j] -= R[k][i] * R[k][j];
+        }
+        __syncthreads();
+        r++;
+    }
+    // R11^-1 (upper triangular, R11[k][l] = R[k][piv[l]]), one column per lane
+    if (t < r) {
+        const int l = t;
+        Ri[l][l] = 1.0 / R[l][piv[l]];
+        for (int kk = l - 1; kk >= 0; kk--) {
+            double acc = 0.0;
+            for (int mm = kk + 1; mm <= l; mm++) acc += R[kk][piv[mm]] * Ri[mm][l];
+            Ri[kk][l] = -acc / R[kk][piv[kk]];
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < P * P; e += 64) {
+        const int a = e / P, c = e % P;   // Xm row a (column of W), column c (new direction)
+        double x = 0.0;
+        if (c < r)
+            for (int l = 0; l <= c; l++)
+                if (piv[l] == a) x = Ri[l][c];
+        Xm[e] = x;
+        Bm[e] = a < r ? R[a][c] : 0.0;    // Bm row a, column c
+    }
+    // Bacc <- R Bacc
+    for (int e = t; e < P * P; e += 64) {
+        const int a = e / P, b = e % P;
+        double acc = 0.0;
+        if (init) {
+            acc = a < r ? R[a][b] : 0.0;
+        } else {
+            for (int q = 0; q < r; q++) acc += R[a][q] * Bacc[q * P + b];
+            if (a >= r) acc = 0.0;
+        }
+        Bt[a][b] = acc;
+    }
+    __syncthreads();
+    for (int e = t; e < P * P; e += 64) Bacc[e] = Bt[e / P][e % P];
+    if (t == 0) *rank_out = r;
+}
+
 template <typename T>
 struct BandRun {
     const mcd_op *op;
@@ -358,6 +476,17 @@ struct BandRun {
 
     int gram(const T *Q0, int nm, const T *X, std::vector<double> &out) {
         const int PP = P * P;
+        MCD_TRY(gram_dev(Q0, nm, X));
+        out.resize((size_t)nm * PP);
+        MCD_HIP(hipMemcpyAsync(out.data(), dG, (size_t)nm * PP * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        MCD_HIP(hipStreamSynchronize(s));
+        return MCD_OK;
+    }
+
+    // Gram matrices Q_m^T X (m < nm) into dG on the device.
+    int gram_dev(const T *Q0, int nm, const T *X) {
+        const int PP = P * P;
         // ~2048 workgroups in total, at least 256 rows per chunk
         int nch = (int)std::min<int64_t>(gridn(n, 256), std::max<int64_t>(1, 2048 / nm));
         nch = std::max(1, nch);
@@ -378,10 +507,30 @@ struct BandRun {
         hipLaunchKernelGGL(k_gram_reduce, dim3(gridn((int64_t)nm * PP, 4)), dim3(256), 0, s, nm,
                            nch, PP, part, dG);
         MCD_HIP(hipGetLastError());
-        out.resize((size_t)nm * PP);
-        MCD_HIP(hipMemcpyAsync(out.data(), dG, (size_t)nm * PP * sizeof(double),
-                               hipMemcpyDeviceToHost, s));
-        MCD_HIP(hipStreamSynchronize(s));
+        return MCD_OK;
+    }
+
+    // W (-)= sum_m Q_m C_m with C already on the device ([nm][P][P]).
+    int block_apply_dev(const T *Q0, int nm, const double *C, T *Wout, bool sub) {
+        const int PP = P * P;
+        const int group = std::max(1, (48 * 1024) / (PP * 8));
+        MCD_REQUIRE(sub || nm <= group, MCD_E_INVALID, "assigning block product must use one group");
+        for (int g0 = 0; g0 < nm; g0 += group) {
+            const int g = std::min(group, nm - g0);
+            const unsigned nb = (unsigned)std::min<int64_t>(gridn(n, BS / P), 4096);
+            const T *q = Q0 + (int64_t)g0 * n * P;
+            const double *c = C + (size_t)g0 * PP;
+#define BAD(PV)                                                                              \
+    case PV:                                                                                 \
+        hipLaunchKernelGGL((k_block_apply<T, PV>), dim3(nb), dim3(BS), g * PP * sizeof(double), \
+                           s, n, g, q, (int64_t)n * P, c, Wout, sub ? 1 : 0);                \
+        break;
+            switch (P) {
+                BAD(1) BAD(2) BAD(4) BAD(8) BAD(16)
+            }
+#undef BAD
+            MCD_HIP(hipGetLastError());
+        }
         return MCD_OK;
     }
 
@@ -459,6 +608,123 @@ struct BandRun {
         }
         Bout = Bacc;
         return MCD_OK;
+    }
+
+
+    // Block Lanczos with every small dense step on the device: Gram matrices,
+    // A_j = sym(Q_j^T W), the recurrence and reorthogonalisation read their
+    // coefficients from HBM, and the QR of each new block is a pivoted
+    // Cholesky (applied twice) in one wavefront.  T = (A_j, B_j) and R0 come
+    // back to the host once at the end; the ranks are read every 8 steps to
+    // stop after the Krylov space is exhausted (blocks past that point are
+    // zero and are not kept).
+    int run_dev(T *phi, int max_blocks, double dtol_abs, int reorth, BandResult &br) {
+        const int PP = P * P;
+        br.P = P;
+        br.A.clear();
+        br.B.assign(1, std::vector<double>());
+        double *dT = nullptr;
+        int *d_rank = nullptr;
+        // [A: max_blocks][B: max_blocks + 1][R0][Xm][Bm][Bacc][Bt]
+        const size_t nT = (size_t)(2 * max_blocks + 6) * PP;
+        MCD_HIP(hipMalloc(&dT, nT * sizeof(double)));
+        MCD_HIP(hipMalloc(&d_rank, (size_t)(max_blocks + 2) * sizeof(int)));
+        double *dA = dT, *dB = dA + (size_t)max_blocks * PP, *dR0 = dB + (size_t)(max_blocks + 1) * PP;
+        double *dXm = dR0 + PP, *dBm = dXm + PP, *dBacc = dBm + PP, *dBt = dBacc + PP;
+        auto fail = [&](int rc) {
+            (void)hipFree(dT);
+            (void)hipFree(d_rank);
+            return rc;
+        };
+#define DTRY(expr)           \
+    do {                     \
+        int rc_ = (expr);    \
+        if (rc_ < 0) return fail(rc_); \
+    } while (0)
+        auto qr_dev = [&](T *src, T *dst, double *outB, int slot) -> int {
+            T *cur = src;
+            for (int pass = 0; pass < 2; pass++) {
+                MCD_TRY(gram_dev(cur, 1, cur));
+                hipLaunchKernelGGL(k_pchol, dim3(1), dim3(64), 0, s, P, dG, pass,
+                                   dtol_abs * dtol_abs, dXm, dBm, dBacc, pass == 0 ? 1 : 0,
+                                   d_rank + slot);
+                T *out = (cur == dst) ? W : dst;
+                MCD_TRY(block_apply_dev(cur, 1, dXm, out, false));
+                if (out != dst)
+                    MCD_HIP(hipMemcpyAsync(dst, out, (size_t)n * P * sizeof(T),
+                                           hipMemcpyDeviceToDevice, s));
+                cur = dst;
+            }
+            MCD_HIP(hipMemcpyAsync(outB, dBacc, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
+            return MCD_OK;
+        };
+        std::vector<int> rank(max_blocks + 2, -1);
+        auto read_ranks = [&](int upto) -> int {
+            MCD_HIP(hipMemcpyAsync(rank.data(), d_rank, (size_t)(upto + 1) * sizeof(int),
+                                   hipMemcpyDeviceToHost, s));
+            MCD_HIP(hipStreamSynchronize(s));
+            return MCD_OK;
+        };
+        DTRY(qr_dev(phi, blk(0), dR0, 0));
+        DTRY(read_ranks(0));
+        int m = 0;
+        if (rank[0] > 0) {
+            for (int j = 0; j < max_blocks; j++) {
+                DTRY(apply_any(op, sizeof(T) == 8 ? MCD_F64 : MCD_F32, P, blk(j), W, s));
+                DTRY(gram_dev(blk(j), 1, W));
+                hipLaunchKernelGGL(k_sym, dim3(1), dim3(64), 0, s, P, dG, dA + (size_t)j * PP);
+                DTRY(block_apply_dev(blk(j), 1, dA + (size_t)j * PP, W, true));
+                if (j > 0) {
+                    hipLaunchKernelGGL(k_transpose, dim3(1), dim3(64), 0, s, P,
+                                       dB + (size_t)j * PP, dBt);
+                    DTRY(block_apply_dev(blk(j - 1), 1, dBt, W, true));
+                }
+                for (int pass = 0; pass < reorth; pass++) {
+                    DTRY(gram_dev(blk(0), j + 1, W));
+                    DTRY(block_apply_dev(blk(0), j + 1, dG, W, true));
+                }
+                m = j + 1;
+                if (j + 1 == max_blocks) break;
+                DTRY(qr_dev(W, blk(j + 1), dB + (size_t)(j + 1) * PP, j + 1));
+                if ((j + 1) % 8 == 0) {
+                    DTRY(read_ranks(j + 1));
+                    bool done = false;
+                    for (int z = 1; z <= j + 1; z++)
+                        if (rank[z] == 0) {
+                            m = z;
+                            done = true;
+                            break;
+                        }
+                    if (done) break;
+                }
+            }
+            DTRY(read_ranks(m));
+            for (int z = 1; z < m; z++)
+                if (rank[z] == 0) {
+                    m = z;
+                    break;
+                }
+        }
+        std::vector<double> hT(nT);
+        if (hipMemcpyAsync(hT.data(), dT, nT * sizeof(double), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            set_error("band run: copying T back failed");
+            return fail(MCD_E_HIP);
+        }
+        br.R0.assign(hT.begin() + (2 * max_blocks + 1) * PP, hT.begin() + (2 * max_blocks + 2) * PP);
+        br.krylov = rank[0] > 0 ? rank[0] : 0;
+        for (int j = 0; j < m; j++) {
+            br.A.emplace_back(hT.begin() + (size_t)j * PP, hT.begin() + (size_t)(j + 1) * PP);
+            if (j > 0) {
+                const size_t o = (size_t)(max_blocks + j) * PP;
+                br.B.emplace_back(hT.begin() + o, hT.begin() + o + PP);
+                br.krylov += rank[j];
+            }
+        }
+        br.m = m;
+#undef DTRY
+        return fail(MCD_OK);
     }
 
     int run(T *phi, int max_blocks, double dtol_abs, int reorth, BandResult &br) {
@@ -608,7 +874,7 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
         cleanup();
         return MCD_OK;
     }
-    TRY(mcd_op_create(model, uniq, nu, cfg->storage, 0, s, &op));
+    TRY(op_create(model, uniq, nu, cfg->storage, 0, cfg->per_column != 0, s, &op));
     // Storage for the Krylov blocks.
     const int reorth = std::max(0, std::min(2, (int)cfg->reorth));
     run.op = op;
@@ -645,7 +911,8 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
     CK(hipMalloc(&phi, (size_t)nu * P * sizeof(T)));
     CK(hipMemcpyAsync(phi, run.W, (size_t)nu * P * sizeof(T), hipMemcpyDeviceToDevice, s));
     const double dtol_abs = cfg->dtol * dtol_scale;
-    int rc = run.run(phi, cfg->max_blocks, dtol_abs, reorth, br);
+    int rc = run.per_column ? run.run(phi, cfg->max_blocks, dtol_abs, reorth, br)
+                            : run.run_dev(phi, cfg->max_blocks, dtol_abs, reorth, br);
     (void)hipFree(phi);
     if (rc < 0) {
         cleanup();

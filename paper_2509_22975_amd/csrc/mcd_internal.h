@@ -152,6 +152,11 @@ int apply_any(const mcd_op *op, int dtype, int nvec, const void *x, void *y, hip
 // only when it grows).  Not thread-safe per operator.
 int op_workspace(const mcd_op *op, size_t bytes, void **ptr);
 
+// Operator construction (mcd_op_create with tune = true); tune = false keeps
+// the default one-vector kernel (for operators used with block products).
+int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32_t storage,
+              int32_t validate, bool tune, void *stream, mcd_op **out);
+
 // Deterministic dot product a . b into *out_dev (mcd_lanczos.hip).
 int dev_dot(const mcd_op *op, const double *a, const double *b, int64_t n, double *out_dev,
             hipStream_t s);

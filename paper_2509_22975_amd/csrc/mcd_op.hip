@@ -798,12 +798,11 @@ int apply_f64_fused(const mcd_op *op, const double *x, double *y, const double *
     return MCD_OK;
 }
 
-}  // namespace mcd
-
-using namespace mcd;
-
-extern "C" int mcd_op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
-                             int32_t storage, int32_t validate, void *stream, mcd_op **out) {
+// Operator construction; `tune` times the one-vector kernels on the matrix
+// (operators that only ever see block products skip it and keep the
+// XCD-major stream kernel for the rare one-vector product).
+int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32_t storage,
+              int32_t validate, bool tune, void *stream, mcd_op **out) {
     MCD_REQUIRE(out != nullptr, MCD_E_INVALID, "out is NULL");
     *out = nullptr;
     MCD_REQUIRE(n >= 0 && (n == 0 || keys_dev != nullptr), MCD_E_INVALID, "bad keys/n");
@@ -894,17 +893,29 @@ extern "C" int mcd_op_create(const mcd_model *model, const uint64_t *keys_dev, i
     op->rows_per_block = 256;
     op->rows_per_block_s = 256;
     op->group_chunk = 16;
+    op->kernel = KERNEL_STREAM_XCD;
     if (st == MCD_STORAGE_CSR) {
         rc = build_csr(op, s);
         if (rc < 0) return fail(rc);
-        rc = tune_kernel(op, s);
-        if (rc < 0) return fail(rc);
+        if (tune) {
+            rc = tune_kernel(op, s);
+            if (rc < 0) return fail(rc);
+        }
     }
     CK(hipStreamSynchronize(s));
 #undef CK
     op->build_ms = now_ms() - t0;
     *out = op;
     return MCD_OK;
+}
+
+}  // namespace mcd
+
+using namespace mcd;
+
+extern "C" int mcd_op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                             int32_t storage, int32_t validate, void *stream, mcd_op **out) {
+    return op_create(model, keys_dev, n, storage, validate, true, stream, out);
 }
 
 extern "C" void mcd_op_destroy(mcd_op *op) {
