@@ -32,9 +32,32 @@ HBM_PEAK_GBS = 8000.0
 ITERS = 200
 
 
+def _function_text(src: str, marker: str) -> str:
+    """Source text of the function whose signature contains `marker`: from the
+    template line before it to its closing brace."""
+    i = src.index(marker)
+    start = src.rfind("template", 0, i)
+    start = start if start >= 0 and i - start < 200 else i
+    j = src.index("{", i)
+    depth = 0
+    for k in range(j, len(src)):
+        if src[k] == "{":
+            depth += 1
+        elif src[k] == "}":
+            depth -= 1
+            if depth == 0:
+                return src[start:k + 1]
+    raise ValueError(marker)
+
+
 def kernel_source_hash() -> str:
+    """Hash of the one-vector stream kernel and of the function that launches
+    it (launch shape): the counters in profiles/ stay valid while these are
+    unchanged."""
     p = os.path.join(HERE, "paper_2509_22975_amd", "csrc", "mcd_op.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    src = open(p).read()
+    text = _function_text(src, "void k_spmv_stream(") + _function_text(src, "static int csr_one(")
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def traffic_from_profile(grid_threads):

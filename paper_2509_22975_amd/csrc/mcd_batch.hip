@@ -89,16 +89,12 @@ __global__ __launch_bounds__(BBS) void k_bspmv(BState st) {
     const double sx = scale_from(&st.nrm2[inst * st.stride + k], 1);
     const int64_t r0 = (blockIdx.x - D.blk0) * (int64_t)st.R;
     const int64_t r1 = min(r0 + (int64_t)st.R, D.n);
-    const int64_t r = r0 + tid;
-    const bool own = tid < st.R && r < r1;
-    int64_t rs = 0, re = 0;
-    double dr = 0.0, xr = 0.0;
-    if (own) {
-        rs = D.rowptr[r];
-        re = D.rowptr[r + 1];
-        dr = D.diag[r];
-        xr = x[r];
-    }
+    // Unconditional loads on clamped addresses (as in the one-operator stream
+    // kernel): no branches around loads, waits by count.
+    const bool own = tid < st.R && r0 + tid < r1;
+    const int64_t r = min(r0 + (int64_t)tid, r1 - 1);
+    const int64_t rs = D.rowptr[r], re = D.rowptr[r + 1];
+    const double dr = D.diag[r], xr = x[r];
     if (tid < kMaxClasses) vtab[tid] = D.m->vtab[tid];
     const uint32_t cmask = D.m->col_mask, cbits = D.m->col_bits;
     const int64_t e0 = D.rowptr[r0];
@@ -106,23 +102,21 @@ __global__ __launch_bounds__(BBS) void k_bspmv(BState st) {
     const uint32_t *__restrict__ cw = D.colw + e0;
     uint32_t w[DEPTH];
     double xv[DEPTH];
+    if (cnt > 0) {   // uniform over the workgroup
 #pragma unroll
-    for (int j = 0; j < DEPTH; j++) {
-        const int e = tid + j * BBS;
-        w[j] = (e < cnt) ? cw[e] : 0u;
-    }
+        for (int j = 0; j < DEPTH; j++) w[j] = cw[min(tid + j * BBS, cnt - 1)];
 #pragma unroll
-    for (int j = 0; j < DEPTH; j++) {
-        const int e = tid + j * BBS;
-        xv[j] = (e < cnt) ? x[w[j] & cmask] : 0.0;
+        for (int j = 0; j < DEPTH; j++) xv[j] = x[w[j] & cmask];
     }
     __syncthreads();
+    if (cnt > 0) {
 #pragma unroll
-    for (int j = 0; j < DEPTH; j++) {
-        const int e = tid + j * BBS;
-        if (e < cnt) {
-            const double v = vtab[(w[j] & 0x7fffffffu) >> cbits];
-            prod[e] = (w[j] >> 31) ? -(v * xv[j]) : v * xv[j];
+        for (int j = 0; j < DEPTH; j++) {
+            const int e = tid + j * BBS;
+            if (e < cnt) {
+                const double v = vtab[(w[j] & 0x7fffffffu) >> cbits];
+                prod[e] = (w[j] >> 31) ? -(v * xv[j]) : v * xv[j];
+            }
         }
     }
     __syncthreads();
