@@ -187,6 +187,29 @@ def batch_c3(mcd, W, torch, n_inst=32):
            "speedup": round(res["single_s"] / res["batch_s"], 3),
            "max_iters": int(max(itb)),
            "max_rel_diff_e0": float(np.max(np.abs(np.array(e0b) - e_single) / np.abs(e_single)))}
+    # Green functions of all instances (p = 8, 64 Matsubara frequencies, 40
+    # block steps, float32 blocks / float64 recurrence): one after the other
+    # vs the batch entry point (4 streams)
+    models = [op.model for op in ops]
+    keys = [op.keys for op in ops]
+    om = W.matsubara(64, 50.0)
+    orbs, spins = [0, 1, 2, 3] * 2, [0] * 4 + [1] * 4
+    gkw = dict(max_blocks=40, precision="f32", reorth=0)
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g_single = [mcd.band_lanczos_green(mm, kk, pp, ee, orbs, spins, om, **gkw)[0]
+                    for mm, kk, pp, ee in zip(models, keys, psib, e0b)]
+        t1 = time.perf_counter()
+        g_batch, ginfo = mcd.batch_band_green(models, keys, psib, e0b, orbs, spins, om,
+                                              n_streams=4, **gkw)
+        t2 = time.perf_counter()
+    out["green"] = {"workload": "G for every instance: p=8, 64 Matsubara frequencies (beta=50), "
+                                "40 block steps, float32 blocks",
+                    "single_s": round(t1 - t0, 4), "batched_s": round(t2 - t1, 4),
+                    "speedup": round((t1 - t0) / (t2 - t1), 3), "streams": 4,
+                    "identical_to_single": bool(all(np.array_equal(a, b)
+                                                    for a, b in zip(g_single, g_batch)))}
     for op in ops:
         op.close()
     return out

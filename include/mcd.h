@@ -339,6 +339,34 @@ int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int
                            double *Gm_out, mcd_solve_info *info, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * mcd_batch_band_green -- mcd_band_lanczos_green for many independent
+ * instances (bath-parameter sets of a quantum impurity model, each with its
+ * own basis and ground state), same selection, frequencies and cfg.
+ *
+ * The instances run concurrently on n_streams (1..8) internal HIP streams,
+ * one host worker thread per stream taking the next instance, so the small
+ * kernels of the Lanczos steps of different instances overlap on the GPU.
+ * Each instance's result is computed exactly as by mcd_band_lanczos_green
+ * (bit-identical).
+ *
+ * models, keys_dev, n, psi0_dev, e0: [n_inst] per-instance inputs (device
+ *   keys / psi0 as in mcd_band_lanczos_green); G_out: [n_inst] host
+ *   complex128 outputs [n_freq][n_sel][n_sel] (G = G+ + G-).
+ * stream: the caller's stream; it is synchronised before the instances start
+ *   (their inputs are read from it).
+ * info (optional): iters = max over instances, krylov_dim / n_plus / n_minus /
+ *   n_truncated summed, solve_ms = wall time of the batch.
+ * Errors: the first failing instance's code, its message names the instance.
+ * Synchronises.
+ * ------------------------------------------------------------------------- */
+int mcd_batch_band_green(const mcd_model *const *models, const uint64_t *const *keys_dev,
+                         const int64_t *n, const double *const *psi0_dev, const double *e0,
+                         int32_t n_inst, int32_t n_sel, const int32_t *orb, const int32_t *spin,
+                         int32_t n_freq, const double *omega, const mcd_band_cfg *cfg,
+                         int32_t n_streams, double *const *G_out, mcd_solve_info *info,
+                         void *stream);
+
+/* ---------------------------------------------------------------------------
  * mcd_band_green_vjp -- reverse-mode derivative of the Green function (and of
  * E0) with respect to the Hamiltonian's parameters theta = (t_b, U_i, eps_i)
  * of Eq. hubbard_model, for the G that mcd_band_lanczos_green returns with

@@ -99,6 +99,9 @@ def lib():
         L.mcd_band_lanczos_green.argtypes = [P(McdModel), c_vp, c_i64, c_vp, c_dbl, c_i32,
                                              P(c_i32), P(c_i32), c_i32, P(c_dbl), P(McdBandCfg),
                                              P(c_dbl), P(c_dbl), P(c_dbl), P(McdSolveInfo), c_vp]
+    L.mcd_batch_band_green.argtypes = [P(c_vp), P(c_vp), P(c_i64), P(c_vp), P(c_dbl), c_i32,
+                                       c_i32, P(c_i32), P(c_i32), c_i32, P(c_dbl),
+                                       P(McdBandCfg), c_i32, P(c_vp), P(McdSolveInfo), c_vp]
     L.mcd_band_green_vjp.argtypes = [P(McdModel), c_vp, c_i64, c_vp, c_dbl, c_i32, P(c_i32),
                                      P(c_i32), c_i32, P(c_dbl), P(McdBandCfg), P(c_dbl), c_dbl,
                                      c_dbl, c_i32, P(c_dbl), P(c_dbl), P(c_dbl), P(McdSolveInfo),
@@ -106,7 +109,7 @@ def lib():
     for name in ("mcd_basis_build", "mcd_op_create", "mcd_op_info", "mcd_op_set_kernel", "mcd_hamiltonian_apply",
                  "mcd_hamiltonian_diagonal", "mcd_hamiltonian_connectivity", "mcd_lanczos_ground",
                  "mcd_band_lanczos_green", "mcd_batch_lanczos_ground",
-                 "mcd_hamiltonian_contract", "mcd_band_green_vjp"):
+                 "mcd_hamiltonian_contract", "mcd_band_green_vjp", "mcd_batch_band_green"):
         if hasattr(L, name):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -415,3 +418,31 @@ def band_green_vjp(model, keys, psi0, e0, orbitals, spins, omega, G_bar, e0_bar=
                                     ctypes.byref(info), _stream())
     _check(code, "mcd_band_green_vjp")
     return dt, dU, de, SolveInfo.of(info)
+
+
+def batch_band_green(models, keys_list, psi_list, e0_list, orbitals, spins, omega, n_streams=4,
+                     max_blocks=50, precision="f64", w_t=1.0, dtol=1e-10, storage="auto",
+                     reorth=2, eta=0.0):
+    """[G_i] for many instances at once (mcd_batch_band_green); each G_i as
+    band_lanczos_green would return it.  Returns (list of G, SolveInfo)."""
+    K = len(models)
+    bufs = [_ModelBuf(m) for m in models]
+    orb = np.ascontiguousarray(orbitals, dtype=np.int32)
+    sp = np.ascontiguousarray(spins, dtype=np.int32)
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    ns, nf = len(orb), len(om)
+    Gs = [np.zeros((nf, ns, ns), dtype=np.complex128) for _ in range(K)]
+    mp = (c_vp * K)(*[ctypes.cast(ctypes.byref(b.s), c_vp) for b in bufs])
+    kp = (c_vp * K)(*[c_vp(k.data_ptr()) for k in keys_list])
+    nn = (c_i64 * K)(*[int(k.numel()) for k in keys_list])
+    pp = (c_vp * K)(*[c_vp(p.data_ptr()) for p in psi_list])
+    ee = (c_dbl * K)(*[float(e) for e in e0_list])
+    gp = (c_vp * K)(*[c_vp(G.ctypes.data) for G in Gs])
+    cfg = _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, False, eta)
+    info = McdSolveInfo()
+    code = lib().mcd_batch_band_green(mp, kp, nn, pp, ee, K, ns, orb.ctypes.data_as(P(c_i32)),
+                                      sp.ctypes.data_as(P(c_i32)), nf,
+                                      om.ctypes.data_as(P(c_dbl)), ctypes.byref(cfg),
+                                      int(n_streams), gp, ctypes.byref(info), _stream())
+    _check(code, "mcd_batch_band_green")
+    return Gs, SolveInfo.of(info)

@@ -25,9 +25,12 @@
 #include <math.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <complex>
 #include <functional>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "mcd_hash.h"
@@ -627,13 +630,13 @@ struct BandRun {
         int *d_rank = nullptr;
         // [A: max_blocks][B: max_blocks + 1][R0][Xm][Bm][Bacc][Bt]
         const size_t nT = (size_t)(2 * max_blocks + 6) * PP;
-        MCD_HIP(hipMalloc(&dT, nT * sizeof(double)));
-        MCD_HIP(hipMalloc(&d_rank, (size_t)(max_blocks + 2) * sizeof(int)));
+        MCD_HIP(dmalloc((void **)&dT, nT * sizeof(double), Alloc{s, true}));
+        MCD_HIP(dmalloc((void **)&d_rank, (size_t)(max_blocks + 2) * sizeof(int), Alloc{s, true}));
         double *dA = dT, *dB = dA + (size_t)max_blocks * PP, *dR0 = dB + (size_t)(max_blocks + 1) * PP;
         double *dXm = dR0 + PP, *dBm = dXm + PP, *dBacc = dBm + PP, *dBt = dBacc + PP;
         auto fail = [&](int rc) {
-            (void)hipFree(dT);
-            (void)hipFree(d_rank);
+            (void)dfree(dT, Alloc{s, true});
+            (void)dfree(d_rank, Alloc{s, true});
             return rc;
         };
 #define DTRY(expr)           \
@@ -814,6 +817,7 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
                        int64_t nt, const SelOps &sel, bool create, const mcd_band_cfg *cfg,
                        double dtol_scale, int P, BandResult &br, int64_t *n_x, hipStream_t s,
                        bool store_all = false, const SectorHook<T> *hook = nullptr) {
+    const Alloc A{s, true};   // stream-ordered buffers (no device-wide sync on free)
     uint64_t *img = nullptr, *srt = nullptr, *uniq = nullptr;
     int64_t *d_nu = nullptr;
     void *tmp = nullptr;
@@ -823,7 +827,7 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
         for (void *p : {(void *)img, (void *)srt, (void *)uniq, (void *)d_nu, tmp, (void *)run.Qs,
                         (void *)run.W, (void *)run.part, (void *)run.dC, (void *)run.dG,
                         (void *)run.colbuf})
-            if (p) (void)hipFree(p);
+            if (p) (void)dfree(p, A);
         if (op) mcd_op_destroy(op);
     };
 #define CK(expr)                                                              \
@@ -844,17 +848,17 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
         }                  \
     } while (0)
     const int64_t ni = nt * sel.n;
-    CK(hipMalloc(&img, std::max<int64_t>(ni, 1) * sizeof(uint64_t)));
-    CK(hipMalloc(&srt, std::max<int64_t>(ni, 1) * sizeof(uint64_t)));
-    CK(hipMalloc(&uniq, std::max<int64_t>(ni, 1) * sizeof(uint64_t)));
-    CK(hipMalloc(&d_nu, sizeof(int64_t)));
+    CK(dmalloc((void **)&img, std::max<int64_t>(ni, 1) * sizeof(uint64_t), A));
+    CK(dmalloc((void **)&srt, std::max<int64_t>(ni, 1) * sizeof(uint64_t), A));
+    CK(dmalloc((void **)&uniq, std::max<int64_t>(ni, 1) * sizeof(uint64_t), A));
+    CK(dmalloc((void **)&d_nu, sizeof(int64_t), A));
     hipLaunchKernelGGL(k_images, dim3(gridn(nt, 256)), dim3(256), 0, s, nt, keys_t, sel,
                        create ? 1 : 0, img);
     CK(hipGetLastError());
     size_t b1 = 0, b2 = 0;
     CK(hipcub::DeviceRadixSort::SortKeys(nullptr, b1, img, srt, (int)ni, 0, 64, s));
     CK(hipcub::DeviceSelect::Unique(nullptr, b2, srt, uniq, d_nu, (int)ni, s));
-    CK(hipMalloc(&tmp, std::max(b1, b2)));
+    CK(dmalloc((void **)&tmp, std::max(b1, b2), A));
     size_t t1 = std::max(b1, b2), t2 = t1;
     CK(hipcub::DeviceRadixSort::SortKeys(tmp, t1, img, srt, (int)ni, 0, 64, s));
     CK(hipcub::DeviceSelect::Unique(tmp, t2, srt, uniq, d_nu, (int)ni, s));
@@ -874,7 +878,7 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
         cleanup();
         return MCD_OK;
     }
-    TRY(op_create(model, uniq, nu, cfg->storage, 0, cfg->per_column != 0, s, &op));
+    TRY(op_create(model, uniq, nu, cfg->storage, 0, cfg->per_column != 0, s, &op, true));
     // Storage for the Krylov blocks.
     const int reorth = std::max(0, std::min(2, (int)cfg->reorth));
     run.op = op;
@@ -891,15 +895,15 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
                   need / 1e9, fr / 1e9);
         return MCD_E_CAPACITY;
     }
-    CK(hipMalloc(&run.Qs, (size_t)run.nstore * nu * P * sizeof(T)));
-    CK(hipMalloc(&run.W, (size_t)nu * P * sizeof(T)));
+    CK(dmalloc((void **)&run.Qs, (size_t)run.nstore * nu * P * sizeof(T), A));
+    CK(dmalloc((void **)&run.W, (size_t)nu * P * sizeof(T), A));
     run.per_column = cfg->per_column != 0;
-    if (run.per_column) CK(hipMalloc(&run.colbuf, (size_t)2 * nu * sizeof(T)));
+    if (run.per_column) CK(dmalloc((void **)&run.colbuf, (size_t)2 * nu * sizeof(T), A));
     run.part_cap = (int64_t)65536 * P * P + (int64_t)(cfg->max_blocks + 1) * P * P;
-    CK(hipMalloc(&run.part, run.part_cap * sizeof(double)));
+    CK(dmalloc((void **)&run.part, run.part_cap * sizeof(double), A));
     run.coef_cap = (int64_t)(cfg->max_blocks + 1) * P * P;
-    CK(hipMalloc(&run.dC, run.coef_cap * sizeof(double)));
-    CK(hipMalloc(&run.dG, run.coef_cap * sizeof(double)));
+    CK(dmalloc((void **)&run.dC, run.coef_cap * sizeof(double), A));
+    CK(dmalloc((void **)&run.dG, run.coef_cap * sizeof(double), A));
     // start block (into W, then orthonormalised into Q_0)
     CK(hipMemsetAsync(run.W, 0, (size_t)nu * P * sizeof(T), s));
     hipLaunchKernelGGL((k_start_block<T>), dim3(gridn(nt, 256)), dim3(256), 0, s, nt, keys_t,
@@ -908,12 +912,12 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
     // the start block lives in W; qr() reads W and writes Q_0 (W is reused as
     // scratch only when source and destination coincide, not here)
     T *phi = nullptr;
-    CK(hipMalloc(&phi, (size_t)nu * P * sizeof(T)));
+    CK(dmalloc((void **)&phi, (size_t)nu * P * sizeof(T), A));
     CK(hipMemcpyAsync(phi, run.W, (size_t)nu * P * sizeof(T), hipMemcpyDeviceToDevice, s));
     const double dtol_abs = cfg->dtol * dtol_scale;
     int rc = run.per_column ? run.run(phi, cfg->max_blocks, dtol_abs, reorth, br)
                             : run.run_dev(phi, cfg->max_blocks, dtol_abs, reorth, br);
-    (void)hipFree(phi);
+    (void)dfree(phi, A);
     if (rc < 0) {
         cleanup();
         return rc;
@@ -938,6 +942,7 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
                       const double *psi0_dev, double e0, const SelOps &sel, int n_freq,
                       const double *omega, const mcd_band_cfg *cfg, double *G_out, double *Gp_out,
                       double *Gm_out, mcd_solve_info *info, hipStream_t s) {
+    const Alloc A{s, true};   // stream-ordered buffers (no device-wide sync on free)
     const double t0 = wall_ms();
     double *w = nullptr, *w2 = nullptr, *psi_t = nullptr, *scr = nullptr;
     uint32_t *idx = nullptr, *idx2 = nullptr, *kept = nullptr;
@@ -947,7 +952,7 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
     auto cleanup = [&]() {
         for (void *p : {(void *)w, (void *)w2, (void *)psi_t, (void *)scr, (void *)idx,
                         (void *)idx2, (void *)kept, (void *)keys_t, (void *)cnt, tmp})
-            if (p) (void)hipFree(p);
+            if (p) (void)dfree(p, A);
     };
 #define CK(expr)                                                              \
     do {                                                                      \
@@ -959,15 +964,15 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
         }                                                                     \
     } while (0)
     MCD_REQUIRE(n < (int64_t(1) << 31), MCD_E_CAPACITY, "basis too large for the w_t sort");
-    CK(hipMalloc(&w, n * sizeof(double)));
-    CK(hipMalloc(&w2, n * sizeof(double)));
-    CK(hipMalloc(&idx, n * sizeof(uint32_t)));
-    CK(hipMalloc(&idx2, n * sizeof(uint32_t)));
-    CK(hipMalloc(&kept, n * sizeof(uint32_t)));
-    CK(hipMalloc(&keys_t, n * sizeof(uint64_t)));
-    CK(hipMalloc(&psi_t, n * sizeof(double)));
-    CK(hipMalloc(&scr, (4096 + 8) * sizeof(double)));
-    CK(hipMalloc(&cnt, 8 * sizeof(unsigned int)));
+    CK(dmalloc((void **)&w, n * sizeof(double), A));
+    CK(dmalloc((void **)&w2, n * sizeof(double), A));
+    CK(dmalloc((void **)&idx, n * sizeof(uint32_t), A));
+    CK(dmalloc((void **)&idx2, n * sizeof(uint32_t), A));
+    CK(dmalloc((void **)&kept, n * sizeof(uint32_t), A));
+    CK(dmalloc((void **)&keys_t, n * sizeof(uint64_t), A));
+    CK(dmalloc((void **)&psi_t, n * sizeof(double), A));
+    CK(dmalloc((void **)&scr, (4096 + 8) * sizeof(double), A));
+    CK(dmalloc((void **)&cnt, 8 * sizeof(unsigned int), A));
     CK(hipMemsetAsync(cnt, 0, 8 * sizeof(unsigned int), s));
     hipLaunchKernelGGL(k_weights, dim3(gridn(n, 256)), dim3(256), 0, s, n, psi0_dev, w, idx);
     CK(hipGetLastError());
@@ -978,7 +983,7 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
                                                         64, s));
         size_t b2 = 0;
         CK(hipcub::DeviceRadixSort::SortKeys(nullptr, b2, idx2, kept, (int)n, 0, 32, s));
-        CK(hipMalloc(&tmp, std::max(b1, b2)));
+        CK(dmalloc((void **)&tmp, std::max(b1, b2), A));
         size_t t1 = std::max(b1, b2);
         CK(hipcub::DeviceRadixSort::SortPairsDescending(tmp, t1, w, w2, idx, idx2, (int)n, 0, 64,
                                                         s));
@@ -1242,6 +1247,7 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
                           const double *omega, const mcd_band_cfg *cfg, const double *G_bar,
                           double e0_bar, double cg_tol, int cg_max_iter, double *d_t,
                           double *d_U, double *d_eps, mcd_solve_info *info, hipStream_t s) {
+    const Alloc A{s, true};   // stream-ordered buffers (no device-wide sync on free)
     const double t0 = wall_ms();
     const int p = sel.n;
     int P = 1;
@@ -1252,7 +1258,7 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     auto cleanup = [&]() {
         for (void *q : {(void *)lam, (void *)acc, (void *)part, (void *)scal, (void *)xi,
                         (void *)res, (void *)dir, (void *)adir})
-            if (q) (void)hipFree(q);
+            if (q) (void)dfree(q, A);
         if (op_gs) mcd_op_destroy(op_gs);
     };
 #define CK(expr)                                                              \
@@ -1272,15 +1278,15 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             return rc_;    \
         }                  \
     } while (0)
-    TRY(mcd_op_create(model, keys_dev, n, MCD_STORAGE_AUTO, 0, s, &op_gs));
+    TRY(op_create(model, keys_dev, n, MCD_STORAGE_AUTO, 0, true, s, &op_gs, true));
     const int nb = op_gs->hm.dm.n_bonds, no = op_gs->hm.dm.n_orb, np = nb + 2 * no;
-    CK(hipMalloc(&lam, n * sizeof(double)));
-    CK(hipMalloc(&acc, np * sizeof(double)));
-    CK(hipMalloc(&scal, 8 * sizeof(double)));
+    CK(dmalloc((void **)&lam, n * sizeof(double), A));
+    CK(dmalloc((void **)&acc, np * sizeof(double), A));
+    CK(dmalloc((void **)&scal, 8 * sizeof(double), A));
     CK(hipMemsetAsync(lam, 0, n * sizeof(double), s));
     CK(hipMemsetAsync(acc, 0, np * sizeof(double), s));
     const int cblk = 2048;
-    CK(hipMalloc(&part, (size_t)np * cblk * sizeof(double)));
+    CK(dmalloc((void **)&part, (size_t)np * cblk * sizeof(double), A));
 
     double trM = 0.0;   // sum over sectors of tr(M)
     int krylov = 0;
@@ -1318,7 +1324,7 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             krylov += br.krylov;
             const int64_t nx = run.n;
             T *Z = nullptr;
-            MCD_HIP(hipMalloc(&Z, (size_t)m * nx * P * sizeof(T)));
+            MCD_HIP(dmalloc((void **)&Z, (size_t)m * nx * P * sizeof(T), A));
             // Z_k = sum_j Q_j M[j-block, k-block]  (W -= sum Q (-C))
             std::vector<double> C((size_t)m * P * P);
             int rc = MCD_OK;
@@ -1357,7 +1363,7 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
                 if (hipGetLastError() != hipSuccess) rc = MCD_E_HIP;
             }
             if (hipStreamSynchronize(s) != hipSuccess && rc == MCD_OK) rc = MCD_E_HIP;
-            (void)hipFree(Z);
+            (void)dfree(Z, A);
             if (rc == MCD_E_HIP) set_error("green vjp: device step failed in a sector hook");
             return rc;
         });
@@ -1374,10 +1380,10 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
 
     // (H - E0) xi = P lam on F~, xi orthogonal to psi0 (conjugate gradients;
     // H - E0 is positive definite on the complement of a non-degenerate psi0).
-    CK(hipMalloc(&xi, n * sizeof(double)));
-    CK(hipMalloc(&res, n * sizeof(double)));
-    CK(hipMalloc(&dir, n * sizeof(double)));
-    CK(hipMalloc(&adir, n * sizeof(double)));
+    CK(dmalloc((void **)&xi, n * sizeof(double), A));
+    CK(dmalloc((void **)&res, n * sizeof(double), A));
+    CK(dmalloc((void **)&dir, n * sizeof(double), A));
+    CK(dmalloc((void **)&adir, n * sizeof(double), A));
     const unsigned gv = gridn(n, 256);
     auto dot = [&](const double *a, const double *b, double *out) -> int {
         MCD_TRY(dev_dot(op_gs, a, b, n, scal, s));
@@ -1536,4 +1542,108 @@ extern "C" int mcd_band_green_vjp(const mcd_model *model, const uint64_t *keys_d
                                       G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, s);
     return band_green_vjp<float>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg,
                                  G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, s);
+}
+
+extern "C" int mcd_batch_band_green(const mcd_model *const *models,
+                                    const uint64_t *const *keys_dev, const int64_t *n,
+                                    const double *const *psi0_dev, const double *e0,
+                                    int32_t n_inst, int32_t n_sel, const int32_t *orb,
+                                    const int32_t *spin, int32_t n_freq, const double *omega,
+                                    const mcd_band_cfg *cfg, int32_t n_streams,
+                                    double *const *G_out, mcd_solve_info *info, void *stream) {
+    MCD_REQUIRE(models && keys_dev && n && psi0_dev && e0 && orb && spin && cfg && G_out,
+                MCD_E_INVALID, "a required pointer is NULL");
+    MCD_REQUIRE(n_inst >= 0, MCD_E_INVALID, "n_inst < 0");
+    MCD_REQUIRE(n_sel >= 1 && n_sel <= 16, MCD_E_INVALID, "n_sel = %d outside 1..16", n_sel);
+    MCD_REQUIRE(n_freq >= 0 && (n_freq == 0 || omega), MCD_E_INVALID, "bad frequencies");
+    MCD_REQUIRE(cfg->w_t > 0.0 && cfg->w_t <= 1.0, MCD_E_INVALID, "w_t must be in (0, 1]");
+    MCD_REQUIRE(cfg->max_blocks >= 1, MCD_E_INVALID, "max_blocks must be >= 1");
+    MCD_REQUIRE(cfg->precision == MCD_F64 || cfg->precision == MCD_F32, MCD_E_INVALID,
+                "precision must be MCD_F64 or MCD_F32");
+    SelOps sel;
+    memset(&sel, 0, sizeof(sel));
+    sel.n = n_sel;
+    for (int i = 0; i < n_inst; i++) {
+        MCD_REQUIRE(models[i] && keys_dev[i] && psi0_dev[i] && G_out[i] && n[i] >= 1,
+                    MCD_E_INVALID, "instance %d: missing input or empty basis", i);
+        HostModel hm;
+        MCD_TRY(prepare_model(models[i], &hm));
+        for (int q = 0; q < n_sel; q++)
+            MCD_REQUIRE(orb[q] >= 0 && orb[q] < models[i]->n_orb && (spin[q] == 0 || spin[q] == 1),
+                        MCD_E_INVALID, "instance %d: selection %d = (%d, %d) invalid", i, q,
+                        orb[q], spin[q]);
+    }
+    for (int q = 0; q < n_sel; q++) {
+        sel.orb[q] = orb[q];
+        sel.spin[q] = spin[q];
+    }
+    const double t0 = wall_ms();
+    MCD_HIP(hipStreamSynchronize((hipStream_t)stream));   // inputs written on the caller's stream
+    int dev = 0;
+    MCD_HIP(hipGetDevice(&dev));
+    const int W = std::max(1, std::min<int>(std::min<int>(n_streams, 8), std::max(n_inst, 1)));
+    std::atomic<int> next{0};
+    std::vector<int> rcs(W, MCD_OK);
+    std::vector<std::string> msgs(W);
+    std::vector<mcd_solve_info> agg(W);
+    for (auto &a : agg) memset(&a, 0, sizeof(a));
+    auto worker = [&](int w) {
+        if (hipSetDevice(dev) != hipSuccess) {
+            rcs[w] = MCD_E_HIP;
+            msgs[w] = "hipSetDevice failed in a batch worker";
+            return;
+        }
+        hipStream_t ws = nullptr;
+        if (hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) {
+            rcs[w] = MCD_E_HIP;
+            msgs[w] = "hipStreamCreate failed in a batch worker";
+            return;
+        }
+        for (;;) {
+            const int i = next.fetch_add(1);
+            if (i >= n_inst) break;
+            mcd_solve_info one;
+            const int rc = cfg->precision == MCD_F64
+                               ? band_green<double>(models[i], keys_dev[i], n[i], psi0_dev[i], e0[i],
+                                                    sel, n_freq, omega, cfg, G_out[i], nullptr,
+                                                    nullptr, &one, ws)
+                               : band_green<float>(models[i], keys_dev[i], n[i], psi0_dev[i], e0[i],
+                                                   sel, n_freq, omega, cfg, G_out[i], nullptr,
+                                                   nullptr, &one, ws);
+            if (rc < 0) {
+                rcs[w] = rc;
+                msgs[w] = std::string("instance ") + std::to_string(i) + ": " + mcd_last_error();
+                break;
+            }
+            agg[w].iters = std::max(agg[w].iters, one.iters);
+            agg[w].krylov_dim += one.krylov_dim;
+            agg[w].n_plus += one.n_plus;
+            agg[w].n_minus += one.n_minus;
+            agg[w].n_truncated += one.n_truncated;
+        }
+        (void)hipStreamSynchronize(ws);
+        (void)hipStreamDestroy(ws);
+    };
+    std::vector<std::thread> th;
+    for (int w = 1; w < W; w++) th.emplace_back(worker, w);
+    worker(0);
+    for (auto &t : th) t.join();
+    for (int w = 0; w < W; w++)
+        if (rcs[w] < 0) {
+            set_error("%s", msgs[w].c_str());
+            return rcs[w];
+        }
+    if (info) {
+        memset(info, 0, sizeof(*info));
+        for (const auto &a : agg) {
+            info->iters = std::max(info->iters, a.iters);
+            info->krylov_dim += a.krylov_dim;
+            info->n_plus += a.n_plus;
+            info->n_minus += a.n_minus;
+            info->n_truncated += a.n_truncated;
+        }
+        info->converged = 1;
+        info->solve_ms = wall_ms() - t0;
+    }
+    return MCD_OK;
 }

@@ -84,6 +84,22 @@ struct DevModel {
     DevBond bonds[MCD_MAX_BONDS];
 };
 
+// Device buffers of the library.  Stream-ordered (async): memory comes from
+// the device's stream-ordered pool (hipMallocAsync) and goes back on the same
+// stream (hipFreeAsync), so solves running concurrently on different streams
+// never synchronise the whole device when they release memory; otherwise
+// hipMalloc / hipFree.
+struct Alloc {
+    hipStream_t s = nullptr;
+    bool async = false;
+};
+inline hipError_t dmalloc(void **p, size_t bytes, const Alloc &a) {
+    return a.async ? hipMallocAsync(p, bytes, a.s) : hipMalloc(p, bytes);
+}
+inline hipError_t dfree(void *p, const Alloc &a) {
+    return a.async ? hipFreeAsync(p, a.s) : hipFree(p);
+}
+
 struct HashSlot {
     uint64_t key;
     int64_t val;
@@ -133,6 +149,7 @@ struct mcd_op {
     double *d_carry;                  // [nchunks]
     int64_t *d_carry_row;             // [nchunks]
     double tune_ms[mcd::KERNEL_LAST + 1];  // measured per-apply time per kernel
+    mcd::Alloc alloc;                 // how the operator's buffers were allocated
 };
 
 namespace mcd {
@@ -154,8 +171,11 @@ int op_workspace(const mcd_op *op, size_t bytes, void **ptr);
 
 // Operator construction (mcd_op_create with tune = true); tune = false keeps
 // the default one-vector kernel (for operators used with block products).
+// async: buffers stream-ordered on `stream` (the operator must then only be
+// used on that stream; mcd_op_destroy releases them on it without a device
+// synchronisation).
 int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32_t storage,
-              int32_t validate, bool tune, void *stream, mcd_op **out);
+              int32_t validate, bool tune, void *stream, mcd_op **out, bool async = false);
 
 // Deterministic dot product a . b into *out_dev (mcd_lanczos.hip).
 int dev_dot(const mcd_op *op, const double *a, const double *b, int64_t n, double *out_dev,

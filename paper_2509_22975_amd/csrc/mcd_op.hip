@@ -535,8 +535,8 @@ static double now_ms() {
 static int build_csr(mcd_op *op, hipStream_t s) {
     const int64_t n = op->n;
     int64_t *cnt = nullptr;
-    MCD_HIP(hipMalloc(&op->d_rowptr, (n + 1) * sizeof(int64_t)));
-    MCD_HIP(hipMalloc(&cnt, (n + 1) * sizeof(int64_t)));
+    MCD_HIP(dmalloc((void **)&op->d_rowptr, (n + 1) * sizeof(int64_t), op->alloc));
+    MCD_HIP(dmalloc((void **)&cnt, (n + 1) * sizeof(int64_t), op->alloc));
     op->device_bytes += (n + 1) * sizeof(int64_t);
     hipLaunchKernelGGL(k_csr_count, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, n, op->d_keys,
                        op->d_model, op->d_hash, op->hash_mask, cnt);
@@ -544,15 +544,15 @@ static int build_csr(mcd_op *op, hipStream_t s) {
     size_t tmp_bytes = 0;
     MCD_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, op->d_rowptr, n + 1, s));
     void *tmp = nullptr;
-    MCD_HIP(hipMalloc(&tmp, tmp_bytes));
+    MCD_HIP(dmalloc((void **)&tmp, tmp_bytes, op->alloc));
     MCD_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, op->d_rowptr, n + 1, s));
     int64_t nnz = 0;
     MCD_HIP(hipMemcpyAsync(&nnz, op->d_rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     MCD_HIP(hipStreamSynchronize(s));
-    MCD_HIP(hipFree(tmp));
-    MCD_HIP(hipFree(cnt));
+    MCD_HIP(dfree(tmp, op->alloc));
+    MCD_HIP(dfree(cnt, op->alloc));
     op->nnz = nnz;
-    MCD_HIP(hipMalloc(&op->d_colw, std::max<int64_t>(nnz, 1) * sizeof(uint32_t)));
+    MCD_HIP(dmalloc((void **)&op->d_colw, std::max<int64_t>(nnz, 1) * sizeof(uint32_t), op->alloc));
     op->device_bytes += nnz * sizeof(uint32_t);
     hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
                        op->d_model, op->d_hash, op->hash_mask, op->d_rowptr, op->d_colw);
@@ -560,7 +560,7 @@ static int build_csr(mcd_op *op, hipStream_t s) {
     // Largest power-of-two row block whose nonzeros fit the LDS product buffer
     // (one choice per buffer size of the stream kernels).
     unsigned long long *d_max = nullptr;
-    MCD_HIP(hipMalloc(&d_max, sizeof(unsigned long long)));
+    MCD_HIP(dmalloc((void **)&d_max, sizeof(unsigned long long), op->alloc));
     op->rows_per_block = 1;
     op->rows_per_block_s = 1;
     bool got_big = false;
@@ -579,16 +579,16 @@ static int build_csr(mcd_op *op, hipStream_t s) {
             break;
         }
     }
-    MCD_HIP(hipFree(d_max));
+    MCD_HIP(dfree(d_max, op->alloc));
     // row-parallel products: words per chunk from the mean row length
     op->group_chunk = (nnz < 4 * n) ? 4 : (nnz < 10 * n) ? 8 : 16;
     // merge-path split points
     op->nchunks = (kMergeRowCost * n + nnz + kMergeK - 1) / kMergeK;
     if (op->nchunks < 1) op->nchunks = 1;
-    MCD_HIP(hipMalloc(&op->d_split_i, (op->nchunks + 1) * sizeof(int64_t)));
-    MCD_HIP(hipMalloc(&op->d_split_j, (op->nchunks + 1) * sizeof(int64_t)));
-    MCD_HIP(hipMalloc(&op->d_carry, op->nchunks * sizeof(double)));
-    MCD_HIP(hipMalloc(&op->d_carry_row, op->nchunks * sizeof(int64_t)));
+    MCD_HIP(dmalloc((void **)&op->d_split_i, (op->nchunks + 1) * sizeof(int64_t), op->alloc));
+    MCD_HIP(dmalloc((void **)&op->d_split_j, (op->nchunks + 1) * sizeof(int64_t), op->alloc));
+    MCD_HIP(dmalloc((void **)&op->d_carry, op->nchunks * sizeof(double), op->alloc));
+    MCD_HIP(dmalloc((void **)&op->d_carry_row, op->nchunks * sizeof(int64_t), op->alloc));
     op->device_bytes += op->nchunks * 32;
     hipLaunchKernelGGL(k_merge_splits, dim3(grid_for(op->nchunks + 1, 256)), dim3(256), 0, s, n,
                        op->nchunks, op->d_rowptr, op->d_split_i, op->d_split_j);
@@ -682,8 +682,8 @@ static int csr_one(const mcd_op *op, const T *x, T *y, const double *sx_dev, int
 static int tune_kernel(mcd_op *op, hipStream_t s) {
     if (op->n == 0) return MCD_OK;
     double *x = nullptr, *y = nullptr;
-    MCD_HIP(hipMalloc(&x, op->n * sizeof(double)));
-    MCD_HIP(hipMalloc(&y, op->n * sizeof(double)));
+    MCD_HIP(dmalloc((void **)&x, op->n * sizeof(double), op->alloc));
+    MCD_HIP(dmalloc((void **)&y, op->n * sizeof(double), op->alloc));
     MCD_HIP(hipMemcpyAsync(x, op->d_diag, op->n * sizeof(double), hipMemcpyDeviceToDevice, s));
     hipEvent_t a, b;
     MCD_HIP(hipEventCreate(&a));
@@ -718,8 +718,8 @@ static int tune_kernel(mcd_op *op, hipStream_t s) {
     op->kernel = pick;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    MCD_HIP(hipFree(x));
-    MCD_HIP(hipFree(y));
+    MCD_HIP(dfree(x, op->alloc));
+    MCD_HIP(dfree(y, op->alloc));
     return MCD_OK;
 }
 
@@ -771,10 +771,10 @@ static int launch_apply(const mcd_op *op, int nvec, const T *x, T *y, hipStream_
 int op_workspace(const mcd_op *op_c, size_t bytes, void **ptr) {
     mcd_op *op = const_cast<mcd_op *>(op_c);
     if (op->ws_bytes < bytes) {
-        if (op->ws) MCD_HIP(hipFree(op->ws));
+        if (op->ws) MCD_HIP(dfree(op->ws, op->alloc));
         op->ws = nullptr;
         op->ws_bytes = 0;
-        MCD_HIP(hipMalloc(&op->ws, bytes));
+        MCD_HIP(dmalloc((void **)&op->ws, bytes, op->alloc));
         op->ws_bytes = bytes;
     }
     *ptr = op->ws;
@@ -802,7 +802,7 @@ int apply_f64_fused(const mcd_op *op, const double *x, double *y, const double *
 // (operators that only ever see block products skip it and keep the
 // XCD-major stream kernel for the rare one-vector product).
 int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32_t storage,
-              int32_t validate, bool tune, void *stream, mcd_op **out) {
+              int32_t validate, bool tune, void *stream, mcd_op **out, bool async) {
     MCD_REQUIRE(out != nullptr, MCD_E_INVALID, "out is NULL");
     *out = nullptr;
     MCD_REQUIRE(n >= 0 && (n == 0 || keys_dev != nullptr), MCD_E_INVALID, "bad keys/n");
@@ -812,6 +812,8 @@ int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32
     const double t0 = now_ms();
     mcd_op *op = new mcd_op();
     memset(op, 0, sizeof(*op));
+    op->alloc.s = s;
+    op->alloc.async = async;
     auto fail = [&](int rc) {
         mcd_op_destroy(op);
         return rc;
@@ -830,21 +832,21 @@ int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32
         }                                                                                    \
     } while (0)
     const int64_t nn = std::max<int64_t>(n, 1);
-    CK(hipMalloc(&op->d_model, sizeof(DevModel)));
+    CK(dmalloc((void **)&op->d_model, sizeof(DevModel), op->alloc));
     CK(hipMemcpyAsync(op->d_model, &op->hm.dm, sizeof(DevModel), hipMemcpyHostToDevice, s));
-    CK(hipMalloc(&op->d_keys, nn * sizeof(uint64_t)));
+    CK(dmalloc((void **)&op->d_keys, nn * sizeof(uint64_t), op->alloc));
     if (n) CK(hipMemcpyAsync(op->d_keys, keys_dev, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-    CK(hipMalloc(&op->d_diag, nn * sizeof(double)));
+    CK(dmalloc((void **)&op->d_diag, nn * sizeof(double), op->alloc));
     op->device_bytes = sizeof(DevModel) + nn * 16;
     if (validate && n) {
         int *bad = nullptr, hbad = 0;
-        CK(hipMalloc(&bad, sizeof(int)));
+        CK(dmalloc((void **)&bad, sizeof(int), op->alloc));
         CK(hipMemsetAsync(bad, 0, sizeof(int), s));
         hipLaunchKernelGGL(k_validate, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
                            op->hm.dm.n_orb, bad);
         CK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
-        CK(hipFree(bad));
+        CK(dfree(bad, op->alloc));
         if (hbad) {
             set_error("keys are not sorted/unique or exceed n_orb bits");
             return fail(MCD_E_SECTOR);
@@ -859,7 +861,7 @@ int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32
     uint64_t cap = 16;
     while (cap < (uint64_t)(4 * nn)) cap <<= 1;
     op->hash_mask = cap - 1;
-    CK(hipMalloc(&op->d_hash, cap * sizeof(HashSlot)));
+    CK(dmalloc((void **)&op->d_hash, cap * sizeof(HashSlot), op->alloc));
     CK(hipMemsetAsync(op->d_hash, 0xff, cap * sizeof(HashSlot), s));
     op->device_bytes += cap * sizeof(HashSlot);
     if (n) {
@@ -869,10 +871,10 @@ int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32
     }
     // Reduction scratch.
     op->max_partials = std::max<int64_t>(grid_for(n, 1) + 1024, 4096);
-    CK(hipMalloc(&op->d_partials, op->max_partials * sizeof(double)));
-    CK(hipMalloc(&op->d_counter, 8 * sizeof(unsigned int)));
+    CK(dmalloc((void **)&op->d_partials, op->max_partials * sizeof(double), op->alloc));
+    CK(dmalloc((void **)&op->d_counter, 8 * sizeof(unsigned int), op->alloc));
     CK(hipMemsetAsync(op->d_counter, 0, 8 * sizeof(unsigned int), s));
-    CK(hipMalloc(&op->d_scalars, 64 * sizeof(double)));
+    CK(dmalloc((void **)&op->d_scalars, 64 * sizeof(double), op->alloc));
     op->device_bytes += op->max_partials * sizeof(double);
     // Storage choice.
     const bool fmt_ok = n <= (int64_t(1) << op->hm.dm.col_bits) && op->hm.ok_classes;
@@ -923,20 +925,15 @@ extern "C" void mcd_op_destroy(mcd_op *op) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(op->device);
-    (void)hipDeviceSynchronize();
-    if (op->d_model) (void)hipFree(op->d_model);
-    if (op->d_keys) (void)hipFree(op->d_keys);
-    if (op->d_diag) (void)hipFree(op->d_diag);
-    if (op->d_hash) (void)hipFree(op->d_hash);
-    if (op->d_rowptr) (void)hipFree(op->d_rowptr);
-    if (op->d_colw) (void)hipFree(op->d_colw);
-    if (op->d_partials) (void)hipFree(op->d_partials);
-    if (op->d_counter) (void)hipFree(op->d_counter);
-    if (op->d_scalars) (void)hipFree(op->d_scalars);
-    if (op->ws) (void)hipFree(op->ws);
-    for (void *p : {(void *)op->d_split_i, (void *)op->d_split_j, (void *)op->d_carry,
+    // Stream-ordered buffers go back on their stream (after the work queued
+    // there); others wait for the device before hipFree.
+    if (!op->alloc.async) (void)hipDeviceSynchronize();
+    for (void *p : {(void *)op->d_model, (void *)op->d_keys, (void *)op->d_diag,
+                    (void *)op->d_hash, (void *)op->d_rowptr, (void *)op->d_colw,
+                    (void *)op->d_partials, (void *)op->d_counter, (void *)op->d_scalars,
+                    op->ws, (void *)op->d_split_i, (void *)op->d_split_j, (void *)op->d_carry,
                     (void *)op->d_carry_row})
-        if (p) (void)hipFree(p);
+        if (p) (void)dfree(p, op->alloc);
     (void)hipSetDevice(cur);
     delete op;
 }

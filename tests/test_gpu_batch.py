@@ -53,3 +53,44 @@ def test_batch_single_instance_and_step_cap():
     assert not info.converged and its[0] == 37 and si.iters == 37
     assert abs(e0s[0] - e1) <= 1e-12 * abs(e1)
     op.close()
+
+
+def test_batch_green_equals_single_and_oracle():
+    """mcd_batch_band_green on several instances (3 streams) returns exactly
+    what mcd_band_lanczos_green returns per instance; one instance is also
+    checked against the oracle (same Krylov space, float64)."""
+    torch, mcd = require_gpu()
+    from oracle import green as gr
+    inst = _instances()[:5]
+    om = W.matsubara(16, 50.0)
+    orbs, spins = [0, 1, 2, 3, 0, 1, 2, 3], [0, 0, 0, 0, 1, 1, 1, 1]
+    log_case("batch_green", sizes=[len(k) for _, k in inst])
+    kds, psis, e0s = [], [], []
+    for m, keys in inst:
+        kd = mcd.keys_from_numpy(keys)
+        op = mcd.Operator(m, kd, storage="csr")
+        e0, psi, _, _, _ = mcd.lanczos_ground(op, max_iter=600, tol=1e-12, seed=11)
+        op.close()
+        kds.append(kd)
+        psis.append(psi)
+        e0s.append(e0)
+    for prec, reorth in (("f64", 2), ("f32", 0)):
+        Gb, info = mcd.batch_band_green([m for m, _ in inst], kds, psis, e0s, orbs, spins, om,
+                                        n_streams=3, max_blocks=12, precision=prec,
+                                        reorth=reorth)
+        assert info.krylov_dim > 0
+        for i, (m, keys) in enumerate(inst):
+            G1, _ = mcd.band_lanczos_green(m, kds[i], psis[i], e0s[i], orbs, spins, om,
+                                           max_blocks=12, precision=prec, reorth=reorth)
+            assert np.array_equal(Gb[i], G1), (prec, i)
+    # instance 1 against the oracle (up spin block), float64
+    m, keys = inst[1]
+    G1, _ = mcd.band_lanczos_green(m, kds[1], psis[1], e0s[1], orbs, spins, om, max_blocks=12,
+                                   reorth=2)
+    psi = psis[1].cpu().numpy()
+    ref = gr.green_mcd(keys, m, psi, e0s[1], [0, 1, 2, 3], 0, om, max_dim=4 * 12)
+    assert np.max(np.abs(G1[:, :4, :4] - ref)) <= 1e-9 * np.max(np.abs(ref))
+    # an invalid selection for one instance is rejected before any work
+    bad = [m for m, _ in inst]
+    with pytest.raises(mcd.McdError):
+        mcd.batch_band_green(bad, kds, psis, e0s, [0, 40], [0, 0], om, n_streams=2)
