@@ -22,6 +22,8 @@ import subprocess
 
 import numpy as np
 
+from . import fock
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "_chain.so")
 _lib = None
@@ -162,6 +164,13 @@ def chain_python(model, start: int, seed: int, n_f: int, burn_in: int, max_steps
 #  * new states join F~ in that order; the sampling stops as soon as F~
 #    holds n_f states (mid-step), or after max_steps steps;
 #  * an empty frontier is refilled with all of F~.
+#  * pre-acceptance (Sec. Monte Carlo sampling, last paragraph): with a level
+#    L > 0 every sector state with n_U < L is accepted before the search
+#    (F~ and the first frontier are that set, the start state is not used),
+#    so the search only has to find states of the remaining n_U; if that set
+#    already holds >= n_f states, F~ is its first n_f states in (n_U, key)
+#    order and no step is taken.  Reading: every orbital is interacting (one
+#    common U), as in the paper's lattice clusters.
 # ---------------------------------------------------------------------------
 G64 = 0x9E3779B97F4A7C15
 
@@ -190,14 +199,39 @@ def _u_and_table(model, beta):
     return umask, table
 
 
-def bfs_python(model, start, seed, beta, n_f, max_steps):
+def preaccepted(model, level):
+    """Sector states with fewer than `level` doubly occupied orbitals, in
+    (n_U, key) order (brute force over the enumerated sector)."""
+    if level <= 0:
+        return np.zeros(0, dtype=np.uint64)
+    if any(u == 0.0 for u in model.U):
+        raise ValueError("pre-acceptance needs U != 0 on every orbital")
+    keys = fock.sector_keys(model.n_orb, model.n_up, model.n_dn)
+    nu = fock.double_occupation(keys)
+    sel = nu < level
+    order = np.lexsort((keys[sel], nu[sel]))
+    return keys[sel][order]
+
+
+def _initial(model, start, n_f, level):
+    """(F~, frontier, done) at the start of the search."""
+    P = preaccepted(model, level)
+    if len(P) == 0:
+        return [int(start)], [int(start)], False
+    if len(P) >= n_f:
+        return [int(k) for k in P[:n_f]], [], True
+    return [int(k) for k in P], sorted(int(k) for k in P), False
+
+
+def bfs_python(model, start, seed, beta, n_f, max_steps, pre_level=0):
     """Plain-loop implementation of the MCD step sampler (small cases)."""
     umask, table = _u_and_table(model, beta)
     bonds = [tuple(sorted(b[:2])) for b in model.bonds]
     H = 4 * len(bonds)
-    S = [start]
-    inS = {start}
-    F = [start]
+    S, F, done = _initial(model, start, n_f, pre_level)
+    if done:
+        return np.array(sorted(S), dtype=np.uint64), 0
+    inS = set(S)
     step = 0
     while len(S) < n_f and step < max_steps:
         step += 1
@@ -232,7 +266,7 @@ def bfs_python(model, start, seed, beta, n_f, max_steps):
     return np.array(sorted(S), dtype=np.uint64), step
 
 
-def bfs_numpy(model, start, seed, beta, n_f, max_steps):
+def bfs_numpy(model, start, seed, beta, n_f, max_steps, pre_level=0):
     """Vectorised implementation of the same sampler (one step = array ops)."""
     umask, table = _u_and_table(model, beta)
     table = np.array(table)
@@ -246,8 +280,11 @@ def bfs_numpy(model, start, seed, beta, n_f, max_steps):
     src = np.where(d == 0, bi[hb], bj[hb])
     dst = np.where(d == 0, bj[hb], bi[hb])
     one = np.uint64(1)
-    S = np.array([start], dtype=np.uint64)
-    F = np.array([start], dtype=np.uint64)
+    S0, F0, done = _initial(model, start, n_f, pre_level)
+    S = np.array(S0, dtype=np.uint64)
+    F = np.array(F0, dtype=np.uint64)
+    if done:
+        return np.sort(S), 0
     step = 0
     with np.errstate(over="ignore"):
         while len(S) < n_f and step < max_steps:

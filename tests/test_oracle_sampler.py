@@ -97,3 +97,28 @@ def test_step_sampler_limits():
     # huge beta: only states without double occupation are accepted
     a3, _ = sampler.bfs_numpy(m, st, 1, 1e3, 4900, 40)
     assert np.all(fock.double_occupation(a3) == 0)
+
+
+def test_step_sampler_preacceptance():
+    """Pre-accepted low-n_U levels (Sec. Monte Carlo sampling): the n_U = 0
+    level of a half-filled N-site cluster holds C(N, N_up) states (one
+    electron per site, any spin pattern with N_up ups); a level above every
+    n_U takes the whole sector without a step; the two implementations agree;
+    the result keeps every pre-accepted state and adds only higher-n_U ones."""
+    import math
+    m = W.chain(8, U=8.0, mu=4.0)
+    P = sampler.preaccepted(m, 1)
+    assert len(P) == math.comb(8, 4) and np.all(fock.double_occupation(P) == 0)
+    P2 = sampler.preaccepted(m, 2)
+    assert len(P2) == math.comb(8, 4) + 8 * 7 * math.comb(6, 3)
+    full, st = sampler.bfs_numpy(m, W.neel_start(m), 1, 0.2, 4900, 50, pre_level=9)
+    assert st == 0 and np.array_equal(full, fock.sector_keys(8, 4, 4))
+    for lvl, nf in ((1, 600), (2, 2500), (2, 1000)):
+        a, sa = sampler.bfs_python(m, W.neel_start(m), 3, 0.2, nf, 200, pre_level=lvl)
+        b, sb = sampler.bfs_numpy(m, W.neel_start(m), 3, 0.2, nf, 200, pre_level=lvl)
+        assert sa == sb and np.array_equal(a, b) and len(a) == nf
+        Pl = sampler.preaccepted(m, lvl)
+        if nf <= len(Pl):           # first nf of the pre-accepted set, no step
+            assert sa == 0 and np.array_equal(a, np.sort(Pl[:nf]))
+        else:
+            assert np.all(np.isin(Pl, a)) and np.all(fock.double_occupation(a[~np.isin(a, Pl)]) >= lvl)
