@@ -110,6 +110,14 @@ int mcd_version(void);
  *   next frontier, whether new or not; new ones join F~ in that order until
  *   it holds n_f states.  An empty frontier is refilled with F~.  steps_out =
  *   steps taken; max_steps bounds them; burn_in is ignored.
+ *   pre_level L > 0 (Sec. Subspace of the ground state, the speed-up by
+ *   pre-accepting low double occupations; every orbital must be
+ *   interacting): all sector states with n_U < L are accepted first -- they
+ *   are enumerated level by level on the GPU (doubly occupied sites, then
+ *   up-only, then down-only sites, each a ranked combination) -- and F~ and
+ *   the first frontier are that set (start_key is then not used); if it
+ *   already holds >= n_f states, F~ is its first n_f states in (n_U, key)
+ *   order and steps_out = 0.  A level must hold < 2^31 states.
  * keys_dev: [cap] device output.  Returns MCD_E_CAPACITY if cap is too
  * small, MCD_E_SECTOR if start_key is not in the sector.  Synchronises.
  * ------------------------------------------------------------------------- */
@@ -122,6 +130,8 @@ typedef struct mcd_basis_cfg {
     int64_t burn_in;
     int64_t max_steps;        /* total steps, burn-in included */
     int64_t n_f;              /* target number of distinct states */
+    int32_t pre_level;        /* MCD_BASIS_STEPS: pre-accept every state with
+                                 n_U < pre_level (0 = none) */
 } mcd_basis_cfg;
 
 int mcd_basis_build(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t *keys_dev,

@@ -39,7 +39,7 @@ class McdModel(ctypes.Structure):
 class McdBasisCfg(ctypes.Structure):
     _fields_ = [("mode", c_i32), ("n_up", c_i32), ("n_dn", c_i32), ("start_key", c_u64),
                 ("seed", c_u64), ("beta_s", c_dbl), ("burn_in", c_i64), ("max_steps", c_i64),
-                ("n_f", c_i64)]
+                ("n_f", c_i64), ("pre_level", c_i32)]
 
 
 class McdOpInfo(ctypes.Structure):
@@ -165,7 +165,7 @@ def keys_from_numpy(keys: np.ndarray, device="cuda"):
 
 
 def basis_build(model, mode="full", n_up=None, n_dn=None, start_key=0, seed=0, beta_s=0.5,
-                burn_in=0, max_steps=0, n_f=0, cap=None, device="cuda"):
+                burn_in=0, max_steps=0, n_f=0, cap=None, device="cuda", pre_level=0):
     """Basis keys (torch.int64 on device) and the number of chain steps."""
     torch = _torch()
     n_up = model.n_up if n_up is None else n_up
@@ -176,7 +176,7 @@ def basis_build(model, mode="full", n_up=None, n_dn=None, start_key=0, seed=0, b
         import math
         cap = math.comb(model.n_orb, n_up) * math.comb(model.n_orb, n_dn) if m == 0 else int(n_f)
     cfg = McdBasisCfg(m, n_up, n_dn, int(start_key), int(seed), float(beta_s), int(burn_in),
-                      int(max_steps), int(n_f))
+                      int(max_steps), int(n_f), int(pre_level))
     out = torch.empty(max(int(cap), 1), dtype=torch.int64, device=device)
     n_out, steps = c_i64(0), c_i64(0)
     _check(lib().mcd_basis_build(ctypes.byref(mb.s), ctypes.byref(cfg), c_vp(out.data_ptr()),

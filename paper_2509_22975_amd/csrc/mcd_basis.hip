@@ -273,6 +273,39 @@ __global__ void k_set_insert(int64_t m, const uint64_t *__restrict__ keys, uint6
     list[list0 + i] = key;
 }
 
+
+// Map the bits of `rel` (positions counted among the set bits of `freem`,
+// lowest first) to absolute positions.
+__device__ __forceinline__ uint32_t spread_bits(uint32_t rel, uint32_t freem) {
+    uint32_t out = 0;
+    int j = 0;
+    while (freem) {
+        const uint32_t low = freem & (~freem + 1u);
+        if ((rel >> j) & 1u) out |= low;
+        freem ^= low;
+        j++;
+    }
+    return out;
+}
+
+// Level n_U = k of the (nu, nd) sector on n orbitals: state q = (i1, i2, i3)
+// in mixed radix -> k doubly occupied sites (rank i1 among C(n, k)), nu - k
+// up-only sites among the other n - k (rank i2), nd - k down-only sites among
+// the n - nu sites still empty (rank i3).
+__global__ void k_enum_level(uint64_t count, int n, int nu, int nd, int k,
+                             const Binom *__restrict__ B, uint64_t *__restrict__ out) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const uint64_t c3 = B->c[n - nu][nd - k], c2 = B->c[n - k][nu - k];
+    const uint64_t i3 = q % c3, t = q / c3;
+    const uint64_t i2 = t % c2, i1 = t / c2;
+    const uint32_t all = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
+    const uint32_t D = unrank(i1, n, k, B);
+    const uint32_t A = spread_bits(unrank(i2, n - k, nu - k, B), all & ~D);
+    const uint32_t Bd = spread_bits(unrank(i3, n - nu, nd - k, B), all & ~(D | A));
+    out[q] = ((uint64_t)(D | A) << 32) | (uint64_t)(D | Bd);
+}
+
 static int build_bfs(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t *keys_dev,
                      int64_t cap, int64_t *n_out, int64_t *steps_out, hipStream_t s) {
     const uint64_t lim = model->n_orb >= 32 ? 0xffffffffull : ((1ull << model->n_orb) - 1ull);
@@ -355,14 +388,104 @@ static int build_bfs(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t 
     CK(hipMalloc(&set, (smask + 1) * sizeof(uint64_t)));
     CK(hipMemsetAsync(set, 0xff, (smask + 1) * sizeof(uint64_t), s));
     CK(hipMalloc(&cnt, 2 * sizeof(unsigned long long)));
-    // F~ starts with the start state; the frontier too
-    CK(hipMemcpyAsync(keys_dev, &cfg->start_key, sizeof(uint64_t), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_set_insert, dim3(1), dim3(64), 0, s, (int64_t)1, keys_dev, set, smask,
-                       keys_dev, (int64_t)0);
-    capF = 1024;
-    CK(grow((void **)&F, capF * 8));
-    CK(hipMemcpyAsync(F, &cfg->start_key, sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    // Pre-accepted levels n_U < pre_level, level by level, each sorted by key.
+    int64_t npre = 0;
+    bool pre_done = false;
+    if (cfg->pre_level > 0) {
+        const uint32_t all = model->n_orb >= 32 ? 0xffffffffu : ((1u << model->n_orb) - 1u);
+        if (umask != all) {
+            cleanup();
+            set_error("pre-acceptance needs U != 0 on every orbital");
+            return MCD_E_INVALID;
+        }
+        Binom hb;
+        fill_binom(hb);
+        Binom *db = nullptr;
+        uint64_t *lv = nullptr, *lv2 = nullptr;
+        auto freelv = [&]() {
+            for (void *p : {(void *)db, (void *)lv, (void *)lv2})
+                if (p) (void)hipFree(p);
+        };
+        const int n = model->n_orb, nu = cfg->n_up, nd = cfg->n_dn;
+        if (hipMalloc(&db, sizeof(Binom)) != hipSuccess ||
+            hipMemcpyAsync(db, &hb, sizeof(Binom), hipMemcpyHostToDevice, s) != hipSuccess) {
+            freelv();
+            cleanup();
+            set_error("pre-acceptance: binomial table upload failed");
+            return MCD_E_HIP;
+        }
+        for (int k = 0; k < cfg->pre_level && k <= std::min(nu, nd) && !pre_done; k++) {
+            if (nd - k > n - nu) continue;   // no room for the down-only sites
+            const uint64_t cnt_k = hb.c[n][k] * hb.c[n - k][nu - k] * hb.c[n - nu][nd - k];
+            if (cnt_k == 0) continue;
+            if (cnt_k >= (1ull << 31)) {
+                freelv();
+                cleanup();
+                set_error("pre-accepted level n_U = %d has %llu states (limit 2^31)", k,
+                          (unsigned long long)cnt_k);
+                return MCD_E_CAPACITY;
+            }
+            const int64_t c = (int64_t)cnt_k;
+            int rc = MCD_OK;
+            if (hipMalloc(&lv, c * 8) != hipSuccess || hipMalloc(&lv2, c * 8) != hipSuccess)
+                rc = MCD_E_HIP;
+            if (rc == MCD_OK) {
+                hipLaunchKernelGGL(k_enum_level, dim3((unsigned)((c + 255) / 256)), dim3(256), 0,
+                                   s, cnt_k, n, nu, nd, k, db, lv);
+                size_t b = 0;
+                if (hipGetLastError() != hipSuccess ||
+                    hipcub::DeviceRadixSort::SortKeys(nullptr, b, lv, lv2, (int)c, 0, 64, s) !=
+                        hipSuccess ||
+                    need_tmp(b) != hipSuccess)
+                    rc = MCD_E_HIP;
+                b = tmp_bytes;
+                if (rc == MCD_OK &&
+                    hipcub::DeviceRadixSort::SortKeys(tmp, b, lv, lv2, (int)c, 0, 64, s) != hipSuccess)
+                    rc = MCD_E_HIP;
+            }
+            const int64_t take = std::min<int64_t>(c, nf - npre);
+            if (rc == MCD_OK && hipMemcpyAsync(keys_dev + npre, lv2, take * 8,
+                                               hipMemcpyDeviceToDevice, s) != hipSuccess)
+                rc = MCD_E_HIP;
+            if (rc == MCD_OK && hipStreamSynchronize(s) != hipSuccess) rc = MCD_E_HIP;
+            (void)hipFree(lv);
+            (void)hipFree(lv2);
+            lv = lv2 = nullptr;
+            if (rc != MCD_OK) {
+                freelv();
+                cleanup();
+                set_error("pre-acceptance: enumerating level n_U = %d failed", k);
+                return rc;
+            }
+            npre += take;
+            if (npre >= nf) pre_done = true;
+        }
+        freelv();
+    }
     int64_t nF = 1, nS = 1, step = 0;
+    if (npre > 0) {
+        // F~ = the pre-accepted states; the frontier = the same set by key
+        hipLaunchKernelGGL(k_set_insert, dim3((unsigned)((npre + 255) / 256)), dim3(256), 0, s,
+                           npre, keys_dev, set, smask, keys_dev, (int64_t)0);
+        CK(hipGetLastError());
+        capF = std::max<int64_t>(npre, 1024);
+        CK(grow((void **)&F, capF * 8));
+        size_t b = 0;
+        CK(hipcub::DeviceRadixSort::SortKeys(nullptr, b, keys_dev, F, (int)npre, 0, 64, s));
+        CK(need_tmp(b));
+        b = tmp_bytes;
+        CK(hipcub::DeviceRadixSort::SortKeys(tmp, b, keys_dev, F, (int)npre, 0, 64, s));
+        nF = nS = npre;
+        if (pre_done) nF = 0;
+    } else {
+        // F~ starts with the start state; the frontier too
+        CK(hipMemcpyAsync(keys_dev, &cfg->start_key, sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_set_insert, dim3(1), dim3(64), 0, s, (int64_t)1, keys_dev, set,
+                           smask, keys_dev, (int64_t)0);
+        capF = 1024;
+        CK(grow((void **)&F, capF * 8));
+        CK(hipMemcpyAsync(F, &cfg->start_key, sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    }
     while (nS < nf && step < cfg->max_steps) {
         step++;
         if (nF == 0) {   // refill the frontier with all of F~ (sorted)

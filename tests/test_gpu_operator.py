@@ -306,3 +306,24 @@ def test_step_sampler_bit_exact(case):
     kg, sg = mcd.basis_build(m, "steps", start_key=st, seed=seed, beta_s=beta, max_steps=1000,
                              n_f=nf)
     assert so == sg and np.array_equal(ko, mcd.keys_to_numpy(kg))
+
+
+@pytest.mark.parametrize("case", ["ring8_l1", "ring8_l2", "ring8_l2_cut", "c1_l1", "sq4x4_l1",
+                                  "ring12_l2"])
+def test_step_sampler_preaccepted_levels_bit_exact(case):
+    """Pre-accepted low-n_U levels (enumerated on the GPU by ranked
+    combinations) then the step search, against the oracle's brute-force
+    level sets; 'cut': the levels alone exceed N_f (no step is taken)."""
+    torch, mcd = require_gpu()
+    m, nf, lvl = {"ring8_l1": (W.chain(8, U=8.0, mu=4.0), 600, 1),
+                  "ring8_l2": (W.chain(8, U=8.0, mu=4.0), 2500, 2),
+                  "ring8_l2_cut": (W.chain(8, U=8.0, mu=4.0), 1000, 2),
+                  "c1_l1": (W.config_c1()["model"], 3000, 1),
+                  "sq4x4_l1": (W.square(4, 4, U=8.0, mu=4.0, pbc=True, n_up=7, n_dn=7), 200000, 1),
+                  "ring12_l2": (W.chain(12, U=8.0, mu=4.0), 100000, 2)}[case]
+    log_case("step_sampler_pre", case=case, n_f=nf, level=lvl)
+    st = W.neel_start(m)
+    ko, so = sampler.bfs_numpy(m, st, 5, 0.2, nf, 1000, pre_level=lvl)
+    kg, sg = mcd.basis_build(m, "steps", start_key=st, seed=5, beta_s=0.2, max_steps=1000,
+                             n_f=nf, pre_level=lvl)
+    assert so == sg and np.array_equal(ko, mcd.keys_to_numpy(kg))
