@@ -340,6 +340,11 @@ typedef struct mcd_band_cfg {
                                  (the unbatched reference form), 0 = block SpMM */
     double eta;               /* 0: Matsubara frequencies; > 0: real frequencies
                                  broadened by eta (the paper uses 0.05) */
+    double g_tol;             /* > 0: stop a run once G at the check points (every
+                                 frequency if <= 8, else the one nearest the real
+                                 axis and 7 evenly spaced) changes by <= g_tol
+                                 max|G| between checks 8 block steps apart;
+                                 0: run max_blocks steps (or to exhaustion) */
 } mcd_band_cfg;
 
 int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int64_t n,

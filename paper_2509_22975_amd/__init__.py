@@ -62,7 +62,8 @@ class McdSolveInfo(ctypes.Structure):
 
 class McdBandCfg(ctypes.Structure):
     _fields_ = [("max_blocks", c_i32), ("precision", c_i32), ("w_t", c_dbl), ("dtol", c_dbl),
-                ("storage", c_i32), ("reorth", c_i32), ("per_column", c_i32), ("eta", c_dbl)]
+                ("storage", c_i32), ("reorth", c_i32), ("per_column", c_i32), ("eta", c_dbl),
+                ("g_tol", c_dbl)]
 
 
 _lib = None
@@ -357,15 +358,15 @@ def batch_lanczos_ground(ops, max_iter=400, tol=1e-12, seed=0, check_every=10, m
     return list(e0), psis, list(it), SolveInfo.of(info)
 
 
-def _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, per_column, eta):
+def _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, per_column, eta, g_tol=0.0):
     return McdBandCfg(int(max_blocks), DTYPE[precision], float(w_t), float(dtol),
                       STORAGE[storage], (2 if reorth is True else int(reorth)),
-                      1 if per_column else 0, float(eta))
+                      1 if per_column else 0, float(eta), float(g_tol))
 
 
 def band_lanczos_green(model, keys, psi0, e0, orbitals, spins, omega, max_blocks=50,
                        precision="f64", w_t=1.0, dtol=1e-10, storage="auto", reorth=2,
-                       parts=False, per_column=False, eta=0.0):
+                       parts=False, per_column=False, eta=0.0, g_tol=0.0):
     """G [n_freq, n_sel, n_sel] complex128 via mcd_band_lanczos_green.
 
     eta == 0: omega are Matsubara frequencies (z = i w); eta > 0: real
@@ -378,7 +379,7 @@ def band_lanczos_green(model, keys, psi0, e0, orbitals, spins, omega, max_blocks
     G = np.zeros((nf, ns, ns), dtype=np.complex128)
     Gp = np.zeros_like(G)
     Gm = np.zeros_like(G)
-    cfg = _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, per_column, eta)
+    cfg = _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, per_column, eta, g_tol)
     info = McdSolveInfo()
     dp = lambda a: a.view(np.float64).ctypes.data_as(P(c_dbl))
     code = lib().mcd_band_lanczos_green(ctypes.byref(mb.s), c_vp(keys.data_ptr()), int(keys.numel()),
@@ -394,7 +395,7 @@ def band_lanczos_green(model, keys, psi0, e0, orbitals, spins, omega, max_blocks
 
 def band_green_vjp(model, keys, psi0, e0, orbitals, spins, omega, G_bar, e0_bar=0.0,
                    max_blocks=50, precision="f64", dtol=1e-10, storage="auto", reorth=2, eta=0.0,
-                   cg_tol=1e-12, cg_max_iter=20000):
+                   cg_tol=1e-12, cg_max_iter=20000, g_tol=0.0):
     """(d_t [n_bonds], d_U [n_orb], d_eps [n_orb], SolveInfo) = Re sum conj(G_bar) dG/dtheta
     + e0_bar dE0/dtheta via mcd_band_green_vjp (same arguments as band_lanczos_green)."""
     mb = _ModelBuf(model)
@@ -403,7 +404,7 @@ def band_green_vjp(model, keys, psi0, e0, orbitals, spins, omega, G_bar, e0_bar=
     om = np.ascontiguousarray(omega, dtype=np.float64)
     ns, nf = len(orb), len(om)
     gb = np.ascontiguousarray(np.asarray(G_bar, dtype=np.complex128).reshape(nf, ns, ns))
-    cfg = _band_cfg(max_blocks, precision, 1.0, dtol, storage, reorth, False, eta)
+    cfg = _band_cfg(max_blocks, precision, 1.0, dtol, storage, reorth, False, eta, g_tol)
     dt = np.zeros(len(model.bonds))
     dU = np.zeros(model.n_orb)
     de = np.zeros(model.n_orb)
@@ -422,7 +423,7 @@ def band_green_vjp(model, keys, psi0, e0, orbitals, spins, omega, G_bar, e0_bar=
 
 def batch_band_green(models, keys_list, psi_list, e0_list, orbitals, spins, omega, n_streams=4,
                      max_blocks=50, precision="f64", w_t=1.0, dtol=1e-10, storage="auto",
-                     reorth=2, eta=0.0):
+                     reorth=2, eta=0.0, g_tol=0.0):
     """[G_i] for many instances at once (mcd_batch_band_green); each G_i as
     band_lanczos_green would return it.  Returns (list of G, SolveInfo)."""
     K = len(models)
@@ -438,7 +439,7 @@ def batch_band_green(models, keys_list, psi_list, e0_list, orbitals, spins, omeg
     pp = (c_vp * K)(*[c_vp(p.data_ptr()) for p in psi_list])
     ee = (c_dbl * K)(*[float(e) for e in e0_list])
     gp = (c_vp * K)(*[c_vp(G.ctypes.data) for G in Gs])
-    cfg = _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, False, eta)
+    cfg = _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, False, eta, g_tol)
     info = McdSolveInfo()
     code = lib().mcd_batch_band_green(mp, kp, nn, pp, ee, K, ns, orb.ctypes.data_as(P(c_i32)),
                                       sp.ctypes.data_as(P(c_i32)), nf,

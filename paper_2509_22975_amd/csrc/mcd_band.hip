@@ -474,6 +474,32 @@ struct BandRun {
     int nstore = 0;
     int64_t part_cap = 0;
     int64_t coef_cap = 0;
+    // convergence of G: stop when G at the check points zcheck changes by
+    // <= g_tol max|G| between two checks (8 block steps apart)
+    std::vector<cplx> zcheck;
+    double g_tol = 0.0;
+    int p_sel = 1;
+    std::vector<cplx> gprev;
+
+    bool g_converged(const BandResult &b) {
+        if (g_tol <= 0.0 || zcheck.empty() || b.m == 0) return false;
+        std::vector<cplx> g((size_t)zcheck.size() * p_sel * p_sel), one(p_sel * p_sel);
+        for (size_t f = 0; f < zcheck.size(); f++) {
+            block_cf(b, zcheck[f], p_sel, one.data());
+            for (int e = 0; e < p_sel * p_sel; e++) g[f * p_sel * p_sel + e] = one[e];
+        }
+        bool conv = false;
+        if (gprev.size() == g.size()) {
+            double dmax = 0.0, gmax = 0.0;
+            for (size_t e = 0; e < g.size(); e++) {
+                dmax = std::max(dmax, std::abs(g[e] - gprev[e]));
+                gmax = std::max(gmax, std::abs(g[e]));
+            }
+            conv = dmax <= g_tol * gmax;
+        }
+        gprev = g;
+        return conv;
+    }
 
     T *blk(int j) { return Qs + (int64_t)(nstore == 3 ? j % 3 : j) * n * P; }
 
@@ -668,6 +694,28 @@ struct BandRun {
             MCD_HIP(hipStreamSynchronize(s));
             return MCD_OK;
         };
+        // T of the first mm blocks (and R0) to the host
+        auto read_T = [&](int mm, BandResult &out) -> int {
+            std::vector<double> hT(nT);
+            MCD_HIP(hipMemcpyAsync(hT.data(), dT, nT * sizeof(double), hipMemcpyDeviceToHost, s));
+            MCD_HIP(hipStreamSynchronize(s));
+            out = BandResult();
+            out.P = P;
+            out.B.assign(1, std::vector<double>());
+            out.R0.assign(hT.begin() + (2 * max_blocks + 1) * PP,
+                          hT.begin() + (2 * max_blocks + 2) * PP);
+            out.krylov = rank[0] > 0 ? rank[0] : 0;
+            for (int j = 0; j < mm; j++) {
+                out.A.emplace_back(hT.begin() + (size_t)j * PP, hT.begin() + (size_t)(j + 1) * PP);
+                if (j > 0) {
+                    const size_t o = (size_t)(max_blocks + j) * PP;
+                    out.B.emplace_back(hT.begin() + o, hT.begin() + o + PP);
+                    out.krylov += std::max(rank[j], 0);
+                }
+            }
+            out.m = mm;
+            return MCD_OK;
+        };
         DTRY(qr_dev(phi, blk(0), dR0, 0));
         DTRY(read_ranks(0));
         int m = 0;
@@ -699,6 +747,11 @@ struct BandRun {
                             break;
                         }
                     if (done) break;
+                    if (g_tol > 0.0) {   // G from the blocks so far, at the check points
+                        BandResult tmp;
+                        DTRY(read_T(m, tmp));
+                        if (g_converged(tmp)) break;
+                    }
                 }
             }
             DTRY(read_ranks(m));
@@ -708,24 +761,7 @@ struct BandRun {
                     break;
                 }
         }
-        std::vector<double> hT(nT);
-        if (hipMemcpyAsync(hT.data(), dT, nT * sizeof(double), hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            set_error("band run: copying T back failed");
-            return fail(MCD_E_HIP);
-        }
-        br.R0.assign(hT.begin() + (2 * max_blocks + 1) * PP, hT.begin() + (2 * max_blocks + 2) * PP);
-        br.krylov = rank[0] > 0 ? rank[0] : 0;
-        for (int j = 0; j < m; j++) {
-            br.A.emplace_back(hT.begin() + (size_t)j * PP, hT.begin() + (size_t)(j + 1) * PP);
-            if (j > 0) {
-                const size_t o = (size_t)(max_blocks + j) * PP;
-                br.B.emplace_back(hT.begin() + o, hT.begin() + o + PP);
-                br.krylov += rank[j];
-            }
-        }
-        br.m = m;
+        DTRY(read_T(m, br));
 #undef DTRY
         return fail(MCD_OK);
     }
@@ -785,6 +821,10 @@ struct BandRun {
             br.B.push_back(Bn);
             if (rk == 0) break;
             br.krylov += rk;
+            if ((j + 1) % 8 == 0 && g_tol > 0.0) {
+                br.m = (int)br.A.size();
+                if (g_converged(br)) break;
+            }
         }
         br.m = (int)br.A.size();
         return MCD_OK;
@@ -816,7 +856,8 @@ template <typename T>
 static int excited_run(const mcd_model *model, const uint64_t *keys_t, const double *psi_t,
                        int64_t nt, const SelOps &sel, bool create, const mcd_band_cfg *cfg,
                        double dtol_scale, int P, BandResult &br, int64_t *n_x, hipStream_t s,
-                       bool store_all = false, const SectorHook<T> *hook = nullptr) {
+                       bool store_all = false, const SectorHook<T> *hook = nullptr,
+                       const std::vector<cplx> *zcheck = nullptr) {
     const Alloc A{s, true};   // stream-ordered buffers (no device-wide sync on free)
     uint64_t *img = nullptr, *srt = nullptr, *uniq = nullptr;
     int64_t *d_nu = nullptr;
@@ -898,6 +939,9 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
     CK(dmalloc((void **)&run.Qs, (size_t)run.nstore * nu * P * sizeof(T), A));
     CK(dmalloc((void **)&run.W, (size_t)nu * P * sizeof(T), A));
     run.per_column = cfg->per_column != 0;
+    run.g_tol = cfg->g_tol;
+    run.p_sel = sel.n;
+    if (zcheck) run.zcheck = *zcheck;
     if (run.per_column) CK(dmalloc((void **)&run.colbuf, (size_t)2 * nu * sizeof(T), A));
     run.part_cap = (int64_t)65536 * P * P + (int64_t)(cfg->max_blocks + 1) * P * P;
     CK(dmalloc((void **)&run.part, run.part_cap * sizeof(double), A));
@@ -935,6 +979,31 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
 #undef CK
 #undef TRY
     return MCD_OK;
+}
+
+// Points where the convergence of G is checked: every frequency if there are
+// at most 8, else the one closest to the real axis (smallest |w|) and 7 more
+// evenly spaced; z = E0 + zeta (particle run) or E0 - zeta (hole run).
+static void check_points(const mcd_band_cfg *cfg, int n_freq, const double *omega, double e0,
+                         std::vector<cplx> &zp, std::vector<cplx> &zm) {
+    std::vector<int> idx;
+    if (n_freq <= 8) {
+        for (int f = 0; f < n_freq; f++) idx.push_back(f);
+    } else {
+        int fmin = 0;
+        for (int f = 1; f < n_freq; f++)
+            if (fabs(omega[f]) < fabs(omega[fmin])) fmin = f;
+        idx.push_back(fmin);
+        for (int k = 0; k < 7; k++) idx.push_back((int)((int64_t)k * (n_freq - 1) / 6));
+        std::sort(idx.begin(), idx.end());
+        idx.erase(std::unique(idx.begin(), idx.end()), idx.end());
+    }
+    zp.clear();
+    zm.clear();
+    for (int f : idx) {
+        zp.push_back(e0 + freq_arg(cfg, omega[f]));
+        zm.push_back(e0 - freq_arg(cfg, omega[f]));
+    }
 }
 
 template <typename T>
@@ -1021,9 +1090,13 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
     const int p = sel.n;
     BandResult brp, brm;
     int64_t np = 0, nm = 0;
-    int rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, true, cfg, 1.0, P, brp, &np, s);
+    std::vector<cplx> zp, zm;
+    check_points(cfg, n_freq, omega, e0, zp, zm);
+    int rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, true, cfg, 1.0, P, brp, &np, s,
+                            false, nullptr, &zp);
     if (rc >= 0)
-        rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, false, cfg, 1.0, P, brm, &nm, s);
+        rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, false, cfg, 1.0, P, brm, &nm, s,
+                            false, nullptr, &zm);
     if (rc < 0) {
         cleanup();
         return rc;
@@ -1372,10 +1445,12 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     int64_t npl = 0, nmi = 0;
     {
         const SectorHook<T> hp = make_hook(true), hm = make_hook(false);
+        std::vector<cplx> zp, zm;
+        check_points(cfg, n_freq, omega, e0, zp, zm);
         TRY(excited_run<T>(model, keys_dev, psi0_dev, n, sel, true, cfg, 1.0, P, brp, &npl, s,
-                           true, &hp));
+                           true, &hp, &zp));
         TRY(excited_run<T>(model, keys_dev, psi0_dev, n, sel, false, cfg, 1.0, P, brm, &nmi, s,
-                           true, &hm));
+                           true, &hm, &zm));
     }
 
     // (H - E0) xi = P lam on F~, xi orthogonal to psi0 (conjugate gradients;

@@ -155,3 +155,27 @@ def test_green_deflation_duplicate_selection():
     Go = _oracle_G(keys, m, psi, e0, [0, 3], [0, 0], 20)
     assert _rel(G[:, 0, 0], G[:, 1, 1]) < 1e-10
     assert _rel(G[:, 0, 2], Go[:, 0, 1]) < 1e-8
+
+
+def test_green_stops_at_convergence():
+    """g_tol: the band runs stop once G at the check points has settled; the
+    result agrees with a run 48 block steps longer to well within g_tol, and
+    the same g_tol gives the same stopping point in float64 every time."""
+    torch, mcd = require_gpu()
+    m = W.impurity_plaquette_bath(5)
+    keys, _ = sampler.chain_c(m, W.neel_start(m), 4, 20000, 500, 10**7)
+    log_case("green_gtol", n=len(keys))
+    e0, psi = _gs(m, keys)
+    kd = mcd.keys_from_numpy(keys)
+    pt = torch.from_numpy(psi).cuda()
+    orbs, spins = [0, 1, 2, 3, 0, 1, 2, 3], [0, 0, 0, 0, 1, 1, 1, 1]
+    om = W.matsubara(32, 50.0)
+    G1, i1 = mcd.band_lanczos_green(m, kd, pt, e0, orbs, spins, om, max_blocks=300, reorth=2,
+                                    g_tol=1e-9)
+    assert i1.iters < 300
+    G2, i2 = mcd.band_lanczos_green(m, kd, pt, e0, orbs, spins, om, max_blocks=i1.iters + 48,
+                                    reorth=2)
+    assert _rel(G1, G2) <= 1e-8
+    G3, i3 = mcd.band_lanczos_green(m, kd, pt, e0, orbs, spins, om, max_blocks=300, reorth=2,
+                                    g_tol=1e-9)
+    assert i3.iters == i1.iters and np.array_equal(G1, G3)
