@@ -1328,9 +1328,10 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     mcd_op *op_gs = nullptr;
     double *lam = nullptr, *acc = nullptr, *part = nullptr, *scal = nullptr;
     double *xi = nullptr, *res = nullptr, *dir = nullptr, *adir = nullptr;
+    double *psi_n = nullptr, *scr = nullptr;
     auto cleanup = [&]() {
         for (void *q : {(void *)lam, (void *)acc, (void *)part, (void *)scal, (void *)xi,
-                        (void *)res, (void *)dir, (void *)adir})
+                        (void *)res, (void *)dir, (void *)adir, (void *)psi_n, (void *)scr})
             if (q) (void)dfree(q, A);
         if (op_gs) mcd_op_destroy(op_gs);
     };
@@ -1353,6 +1354,20 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     } while (0)
     TRY(op_create(model, keys_dev, n, MCD_STORAGE_AUTO, 0, true, s, &op_gs, true));
     const int nb = op_gs->hm.dm.n_bonds, no = op_gs->hm.dm.n_orb, np = nb + 2 * no;
+    // psi0 normalised exactly as the forward call does, so the band runs below
+    // reproduce the forward's recurrence (and stopping point) bit for bit
+    CK(dmalloc((void **)&psi_n, n * sizeof(double), A));
+    CK(dmalloc((void **)&scr, (4096 + 8) * sizeof(double), A));
+    CK(hipMemcpyAsync(psi_n, psi0_dev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    {
+        const unsigned nbn = std::min<unsigned>(gridn(n, BS), 2048);
+        hipLaunchKernelGGL(k_norm2, dim3(nbn), dim3(BS), 0, s, n, psi_n, scr);
+        hipLaunchKernelGGL((k_finalize_sum<BS>), dim3(1), dim3(BS), 0, s, (int)nbn, scr,
+                           scr + 4096);
+        hipLaunchKernelGGL(k_scale_by, dim3(gridn(n, 256)), dim3(256), 0, s, n, psi_n,
+                           scr + 4096);
+        CK(hipGetLastError());
+    }
     CK(dmalloc((void **)&lam, n * sizeof(double), A));
     CK(dmalloc((void **)&acc, np * sizeof(double), A));
     CK(dmalloc((void **)&scal, 8 * sizeof(double), A));
@@ -1447,9 +1462,9 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
         const SectorHook<T> hp = make_hook(true), hm = make_hook(false);
         std::vector<cplx> zp, zm;
         check_points(cfg, n_freq, omega, e0, zp, zm);
-        TRY(excited_run<T>(model, keys_dev, psi0_dev, n, sel, true, cfg, 1.0, P, brp, &npl, s,
+        TRY(excited_run<T>(model, keys_dev, psi_n, n, sel, true, cfg, 1.0, P, brp, &npl, s,
                            true, &hp, &zp));
-        TRY(excited_run<T>(model, keys_dev, psi0_dev, n, sel, false, cfg, 1.0, P, brm, &nmi, s,
+        TRY(excited_run<T>(model, keys_dev, psi_n, n, sel, false, cfg, 1.0, P, brm, &nmi, s,
                            true, &hm, &zm));
     }
 
@@ -1468,8 +1483,8 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     };
     double c = 0.0;
     CK(hipMemcpyAsync(res, lam, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    TRY(dot(psi0_dev, res, &c));
-    hipLaunchKernelGGL(k_sub_scaled, dim3(gv), dim3(256), 0, s, n, res, c, psi0_dev);
+    TRY(dot(psi_n, res, &c));
+    hipLaunchKernelGGL(k_sub_scaled, dim3(gv), dim3(256), 0, s, n, res, c, psi_n);
     CK(hipMemsetAsync(xi, 0, n * sizeof(double), s));
     CK(hipMemcpyAsync(dir, res, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     double rr = 0.0;
@@ -1481,8 +1496,8 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     while (!conv && it < cg_max_iter) {
         TRY(apply_any(op_gs, MCD_F64, 1, dir, adir, s));
         double pc = 0.0;
-        TRY(dot(psi0_dev, adir, &pc));
-        hipLaunchKernelGGL(k_shift_project, dim3(gv), dim3(256), 0, s, n, adir, dir, e0, psi0_dev,
+        TRY(dot(psi_n, adir, &pc));
+        hipLaunchKernelGGL(k_shift_project, dim3(gv), dim3(256), 0, s, n, adir, dir, e0, psi_n,
                            pc);
         double pap = 0.0;
         TRY(dot(dir, adir, &pap));
@@ -1504,9 +1519,9 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     // contractions with psi0: dE0 and <xi| dH |psi0>
     const int nlb = model->n_bonds;
     std::vector<double> e_t(nlb), e_U(no), e_e(no), x_t(nlb), x_U(no), x_e(no);
-    TRY(mcd_hamiltonian_contract(op_gs, model, psi0_dev, psi0_dev, e_t.data(), e_U.data(),
+    TRY(mcd_hamiltonian_contract(op_gs, model, psi_n, psi_n, e_t.data(), e_U.data(),
                                  e_e.data(), s));
-    TRY(mcd_hamiltonian_contract(op_gs, model, xi, psi0_dev, x_t.data(), x_U.data(), x_e.data(),
+    TRY(mcd_hamiltonian_contract(op_gs, model, xi, psi_n, x_t.data(), x_U.data(), x_e.data(),
                                  s));
     std::vector<double> h(np);
     CK(hipMemcpyAsync(h.data(), acc, np * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -110,3 +110,45 @@ def test_green_function_autograd_and_float32():
     ref = np.concatenate([r_t, r_U, r_e])
     assert _rel(grads["f64"], ref) < 1e-6
     assert _rel(grads["f32"], grads["f64"]) < 1e-4
+
+
+def test_green_vjp_with_convergence_stop_replays_forward():
+    """With g_tol the forward run stops early; the adjoint recomputes the same
+    Krylov spaces (same normalised psi0, same stopping point) and its
+    gradient matches central differences of the forward G (float64, h=1e-5)."""
+    torch, mcd = require_gpu()
+    m = W.impurity_plaquette_bath(6)
+    keys, _ = sampler.chain_c(m, W.neel_start(m), 2, 15000, 500, 10**7)
+    kd = mcd.keys_from_numpy(keys)
+    om = W.matsubara(16, 50.0)
+    orbs, spins = [0, 1, 2, 3], [0, 0, 0, 0]
+    rng = np.random.default_rng(3)
+    Gb = rng.normal(size=(16, 4, 4)) + 1j * rng.normal(size=(16, 4, 4))
+    kw = dict(max_blocks=300, reorth=2, g_tol=1e-10)
+    log_case("green_vjp_gtol", n=len(keys))
+
+    def forward(model):
+        e0, psi = _gpu_ground(mcd, model, kd)
+        G, info = mcd.band_lanczos_green(model, kd, psi, e0, orbs, spins, om, **kw)
+        return e0, psi, G, info
+
+    e0, psi, G, info = forward(m)
+    assert info.iters < 300
+    d_t, d_U, d_e, vinfo = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, **kw)
+    assert vinfo.krylov_dim == info.krylov_dim
+    h = 1e-5
+    for kind, idx, got in (("eps", 5, d_e[5]), ("U", 1, d_U[1])):
+        vals = []
+        for sgn in (1, -1):
+            if kind == "eps":
+                e = m.eps.copy()
+                e[idx] += sgn * h
+                mm = m.with_params(eps=e)
+            else:
+                u = m.U.copy()
+                u[idx] += sgn * h
+                mm = m.with_params(U=u)
+            _, _, Gs, _ = forward(mm)
+            vals.append(float(np.sum((np.conj(Gb) * Gs).real)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(got - fd) <= 1e-6 * max(1.0, abs(fd)), (kind, got, fd)
