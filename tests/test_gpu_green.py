@@ -51,12 +51,13 @@ def _c1_chain():
     return m, k
 
 
-@pytest.mark.parametrize("sel", ["up4", "mixed8", "ragged3"])
+@pytest.mark.parametrize("sel", ["up4", "mixed8", "ragged3", "all16"])
 def test_green_c1_chain_vs_oracle(sel):
     torch, mcd = require_gpu()
     m, keys = _c1_chain()
     orbs, spins = {"up4": ([0, 1, 2, 3], [0] * 4), "mixed8": ([0, 1, 2, 3] * 2, [0] * 4 + [1] * 4),
-                   "ragged3": ([1, 5, 6], [1, 0, 1])}[sel]
+                   "ragged3": ([1, 5, 6], [1, 0, 1]),
+                   "all16": (list(range(8)) * 2, [0] * 8 + [1] * 8)}[sel]
     log_case("green_c1", sel=sel)
     e0, psi = _gs(m, keys)
     blocks = 30
