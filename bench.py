@@ -51,27 +51,36 @@ def _function_text(src: str, marker: str) -> str:
 
 
 def kernel_source_hash() -> str:
-    """Hash of the one-vector stream kernel and of the function that launches
-    it (launch shape): the counters in profiles/ stay valid while these are
-    unchanged."""
-    p = os.path.join(HERE, "paper_2509_22975_amd", "csrc", "mcd_op.hip")
-    src = open(p).read()
-    text = _function_text(src, "void k_spmv_stream(") + _function_text(src, "static int csr_one(")
+    """Hash of the one-vector kernels whose counters are kept (row-major stream
+    and grouped) and of the functions that launch them (launch shapes): the
+    counters in profiles/ stay valid while these are unchanged."""
+    csrc = os.path.join(HERE, "paper_2509_22975_amd", "csrc")
+    op_src = open(os.path.join(csrc, "mcd_op.hip")).read()
+    g_src = open(os.path.join(csrc, "mcd_grouped.hip")).read()
+    text = (_function_text(op_src, "void k_spmv_stream(") + _function_text(op_src, "static int csr_one(")
+            + _function_text(g_src, "void k_spmv_grouped(") + _function_text(g_src, "int grouped_one("))
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
-def traffic_from_profile(grid_threads):
-    """HBM bytes per launch of the stream kernel at this launch shape (grid in
-    threads: the plain and XCD-major orders differ) from the committed
+# rocprofv3 names of the kernels whose counters are kept
+PROF_KERNEL = {"stream": "k_spmv_stream<double, 256, 4096>",
+               "stream_xcd": "k_spmv_stream<double, 256, 4096>",
+               "grouped": "k_spmv_grouped<double, 3072>",
+               "grouped_xcd": "k_spmv_grouped<double, 3072>"}
+
+
+def traffic_from_profile(kernel, grid_threads):
+    """HBM bytes per launch of a one-vector kernel at this launch shape (grid
+    in threads: the plain and XCD-major orders differ) from the committed
     rocprofv3 PMC summary, if it was taken on the current kernel source;
     else None."""
-    p = os.path.join(HERE, "profiles", "spmv_stream_c2_pmc.json")
-    if not os.path.exists(p):
+    p = os.path.join(HERE, "profiles", "spmv_c2_pmc.json")
+    if not os.path.exists(p) or kernel not in PROF_KERNEL:
         return None
     d = json.load(open(p))
     if d.get("kernel_source_sha") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch_by_grid", {}).get(str(grid_threads))
+    return d.get("hbm_bytes_per_launch", {}).get(f"{PROF_KERNEL[kernel]}@{grid_threads}")
 
 
 def cpu_baseline(model, keys_np, x_np, nnz_per_row):
@@ -388,7 +397,7 @@ def c5_cluster(mcd, W, torch):
     b16 = 16 * n + 4 * nnz + 2 * 16 * 4 * n
     ms1, ms16 = tm(lambda: op.apply(x, y), 10), tm(lambda: op.apply(X, Y), 5)
     variants = {}
-    for kname in ("stream", "stream_xcd", "merge", "rowchunk", "stream_small", "stream_small_xcd"):
+    for kname in op.kernels():
         op.set_kernel(kname)
         variants[kname] = round(tm(lambda: op.apply(x, y), 10), 4)
     op.set_kernel(inf["kernel"])
@@ -472,7 +481,12 @@ def main():
     op = mcd.Operator(m, keys, storage=args.storage)
     info = op.info()
     n, nnz = info["n"], info["nnz"]
+    # compulsory bytes of one product: row pointers, entry words, diagonal,
+    # x and y; the grouped layout also reads its block row starts, group
+    # offsets and group table once per product
     alg_bytes = 8.0 * (n + 1) + 4.0 * nnz + 24.0 * n
+    if info["kernel"] in ("grouped", "grouped_xcd"):
+        alg_bytes += 16.0 * (info["grouped_blocks"] + 1) + 8.0 * (info["grouped_groups"] + 1)
 
     def step():
         return mcd.lanczos_ground(op, max_iter=ITERS, tol=0.0, seed=11, check_every=50,
@@ -509,19 +523,18 @@ def main():
     chosen = info["kernel"]
     per_kernel = {}
     if info["storage"] == "csr":
-        for kname in ("stream", "stream_xcd", "merge", "rowchunk", "stream_small",
-                      "stream_small_xcd"):
+        for kname in op.kernels():
             op.set_kernel(kname)
             per_kernel[kname] = round(time_apply(50), 5)
         op.set_kernel(chosen)
     k_ms = time_apply()
+    # launch shape of the selected kernel (threads), to find its counters
+    if chosen in ("grouped", "grouped_xcd"):
+        nblk = info["grouped_blocks"]
+    else:
+        nblk = (n + info["rows_per_block"] - 1) // info["rows_per_block"]
+    grid_threads = 256 * (8 * ((nblk + 7) // 8) if chosen.endswith("_xcd") else nblk)
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    # launch shape of the selected stream kernel (threads), to find its counters
-    rpb = info["rows_per_block"]
-    nblk = (n + rpb - 1) // rpb
-    grid_threads = 256 * (8 * ((nblk + 7) // 8) if chosen == "stream_xcd" else nblk)
-    if chosen not in ("stream", "stream_xcd"):
-        grid_threads = -1
 
     # Block products (the batched form): ms per apply and per vector.
     spmm = {}
@@ -542,7 +555,9 @@ def main():
             spmm[f"{tname}_b{b}"] = {"ms": round(ms, 4), "ms_per_vector": round(ms / b, 5),
                                      "GBs": round(byts / ms / 1e6, 1)}
             del X, Y
-    kernel_names = {"stream": "k_spmv_stream<double,256,4096>",
+    kernel_names = {"grouped": "k_spmv_grouped<double,3072>",
+                    "grouped_xcd": "k_spmv_grouped<double,3072> (XCD-major order)",
+                    "stream": "k_spmv_stream<double,256,4096>",
                     "stream_xcd": "k_spmv_stream<double,256,4096> (XCD-major order)",
                     "stream_small": "k_spmv_stream<double,256,1024>",
                     "stream_small_xcd": "k_spmv_stream<double,256,1024> (XCD-major order)",
@@ -564,7 +579,7 @@ def main():
                    "bytes_per_apply": alg_bytes},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profile(grid_threads),
+                     "traffic": traffic_from_profile(chosen, grid_threads),
                      "kernel": kernel_names.get(chosen, "k_apply_group (on-the-fly)"),
                      "kernel_ms": round(k_ms, 5), "ms_per_kernel_variant": per_kernel},
         "cpu_baseline": None,

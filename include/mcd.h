@@ -163,10 +163,13 @@ typedef struct mcd_op_info_t {
     int32_t storage;          /* resolved storage */
     int32_t n_classes;        /* distinct |t| amplitudes */
     int32_t rows_per_block;   /* CSR stream kernel row block */
-    int32_t kernel;           /* one-vector CSR kernel: 1 stream, 2 merge-path, 3 stream XCD,
-                                 4 row-chunk */
+    int32_t kernel;           /* one-vector CSR kernel (mcd_op_set_kernel numbering) */
     int64_t device_bytes;     /* device memory held by the operator */
     double build_ms;          /* time of index + CSR build */
+    int64_t grouped_blocks;   /* row blocks of the grouped layout (kernels 7, 8); 0 = not
+                                 built (on-the-fly operator, operator made for block
+                                 products only, or a basis that does not fit the layout) */
+    int64_t grouped_groups;   /* up-hop groups of the grouped layout (table entries) */
 } mcd_op_info_t;
 
 int mcd_op_info(const mcd_op *op, mcd_op_info_t *info);
@@ -182,10 +185,20 @@ int mcd_op_info(const mcd_op *op, mcd_op_info_t *info);
  *       flight per thread, no LDS staging (XCD-major row tiles);
  *   5 = stream with smaller row blocks (<= 1024 nonzeros per workgroup:
  *       less LDS and fewer loads per thread, for short rows);
- *   6 = 5 in XCD-major order.
+ *   6 = 5 in XCD-major order;
+ *   7 = grouped: the entries of each row block (<= 256 rows, <= 3072
+ *       nonzeros) are stored in a second order in which up-spin hops are
+ *       grouped by (source up string, target up string), so the lanes of a
+ *       gather take the same hop of consecutive rows and read neighbouring
+ *       x; each entry keeps its row-major slot, so every row still adds its
+ *       terms in entry order (y bit-identical to kernel 1).  Built at
+ *       creation when the basis has up-string segments of >= 16 rows on
+ *       average and every block fits 128 groups (mcd_op_info_t.grouped_blocks);
+ *   8 = 7 in XCD-major order.
  * All give the same result up to summation order.  At creation a CSR
  * operator times every kernel on its own matrix and keeps the fastest.
- * MCD_E_INVALID for other values or an on-the-fly operator. */
+ * MCD_E_INVALID for other values, an on-the-fly operator, or 7 / 8 on an
+ * operator without the grouped layout. */
 int mcd_op_set_kernel(mcd_op *op, int32_t kernel);
 
 /* ---------------------------------------------------------------------------

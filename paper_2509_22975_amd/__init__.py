@@ -25,7 +25,7 @@ STORAGE = {"auto": 0, "on_the_fly": 1, "otf": 1, "csr": 2}
 STORAGE_NAME = {0: "auto", 1: "on_the_fly", 2: "csr"}
 DTYPE = {"f64": 0, "f32": 1}
 KERNEL_NAME = {1: "stream", 2: "merge", 3: "stream_xcd", 4: "rowchunk", 5: "stream_small",
-               6: "stream_small_xcd"}
+               6: "stream_small_xcd", 7: "grouped", 8: "grouped_xcd"}
 
 P = ctypes.POINTER
 c_i32, c_i64, c_u64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
@@ -45,7 +45,8 @@ class McdBasisCfg(ctypes.Structure):
 class McdOpInfo(ctypes.Structure):
     _fields_ = [("n", c_i64), ("nnz", c_i64), ("storage", c_i32), ("n_classes", c_i32),
                 ("rows_per_block", c_i32), ("kernel", c_i32), ("device_bytes", c_i64),
-                ("build_ms", c_dbl)]
+                ("build_ms", c_dbl), ("grouped_blocks", c_i64),
+                ("grouped_groups", c_i64)]
 
 
 class McdLanczosCfg(ctypes.Structure):
@@ -214,11 +215,20 @@ class Operator:
         _check(lib().mcd_op_info(self.handle, ctypes.byref(i)), "mcd_op_info")
         return dict(n=i.n, nnz=i.nnz, storage=STORAGE_NAME[i.storage], n_classes=i.n_classes,
                     rows_per_block=i.rows_per_block, kernel=KERNEL_NAME.get(i.kernel, "none"),
-                    device_bytes=i.device_bytes, build_ms=i.build_ms)
+                    device_bytes=i.device_bytes, build_ms=i.build_ms,
+                    grouped_blocks=i.grouped_blocks, grouped_groups=i.grouped_groups)
+
+    def kernels(self) -> list:
+        """One-vector CSR kernels this operator can run (grouped ones only when
+        its grouped layout was built)."""
+        if self.info()["storage"] != "csr":
+            return []
+        g = self.info()["grouped_blocks"] > 0
+        return [v for k, v in sorted(KERNEL_NAME.items()) if g or k < 7]
 
     def set_kernel(self, name: str):
         """Force the one-vector CSR kernel: 'stream', 'merge', 'stream_xcd', 'rowchunk',
-        'stream_small' or 'stream_small_xcd'."""
+        'stream_small', 'stream_small_xcd', 'grouped' or 'grouped_xcd'."""
         _check(lib().mcd_op_set_kernel(self.handle, {v: k for k, v in KERNEL_NAME.items()}[name]),
                "mcd_op_set_kernel")
 

@@ -58,8 +58,15 @@ enum {
     KERNEL_ROWCHUNK = 4,
     KERNEL_STREAM_S = 5,       // stream with <= kStreamNnzSmall products per block
     KERNEL_STREAM_S_XCD = 6,   // ... in XCD-major order
-    KERNEL_LAST = 6
+    KERNEL_GROUPED = 7,        // grouped entry order (coalesced up-hop gathers)
+    KERNEL_GROUPED_XCD = 8,    // ... in XCD-major order
+    KERNEL_LAST = 8
 };
+// Grouped one-vector layout: row blocks of <= kGroupedRows rows and
+// <= kGroupedNnz nonzeros; <= kGroupedMaxGroups up-hop groups per block.
+constexpr int kGroupedNnz = 3072;
+constexpr int kGroupedRows = 256;
+constexpr int kGroupedMaxGroups = 128;
 constexpr int kNumXcd = 8;                   // gfx950: workgroups are dealt round-robin to 8 XCDs
 
 // One hopping bond with i < j, prepared for bit arithmetic.
@@ -149,6 +156,13 @@ struct mcd_op {
     double *d_carry;                  // [nchunks]
     int64_t *d_carry_row;             // [nchunks]
     double tune_ms[mcd::KERNEL_LAST + 1];  // measured per-apply time per kernel
+    // grouped one-vector layout (g_nblocks = 0: not built or not applicable)
+    int64_t g_nblocks;
+    int64_t g_ngroups;
+    int64_t *d_gbs;                   // [g_nblocks + 1] first row of each block
+    int64_t *d_goff;                  // [g_nblocks + 1] first group of each block
+    uint64_t *d_gtab;                 // [g_ngroups + 1] column | class << 32 | sign << 37
+    uint32_t *d_gw;                   // [nnz] entry words in grouped order
     mcd::Alloc alloc;                 // how the operator's buffers were allocated
 };
 
@@ -168,6 +182,17 @@ int apply_any(const mcd_op *op, int dtype, int nvec, const void *x, void *y, hip
 // Solver workspace of at least `bytes` held by the operator (reallocated
 // only when it grows).  Not thread-safe per operator.
 int op_workspace(const mcd_op *op, size_t bytes, void **ptr);
+
+// Grouped one-vector layout (mcd_grouped.hip).  build_grouped leaves
+// g_nblocks = 0 when the basis does not fit the layout (short up-string
+// segments, too many groups per block, offsets out of range); only HIP
+// errors are returned as errors.  grouped_one launches the product (same
+// contract as the other one-vector kernels; partials per workgroup when
+// `partials` != nullptr, *grid = number of workgroups).
+int build_grouped(mcd_op *op, hipStream_t s);
+template <typename T>
+int grouped_one(const mcd_op *op, bool xcd, const T *x, T *y, const double *sx_dev, int sx_mode,
+                double *partials, int64_t *grid, hipStream_t s);
 
 // Operator construction (mcd_op_create with tune = true); tune = false keeps
 // the default one-vector kernel (for operators used with block products).

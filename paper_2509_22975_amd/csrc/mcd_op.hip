@@ -651,6 +651,17 @@ static int csr_one(const mcd_op *op, const T *x, T *y, const double *sx_dev, int
         }
         return MCD_OK;
     }
+    if (op->kernel == KERNEL_GROUPED || op->kernel == KERNEL_GROUPED_XCD) {
+        int64_t grid = 0;
+        MCD_TRY(grouped_one<T>(op, op->kernel == KERNEL_GROUPED_XCD, x, y, sx_dev, sx_mode,
+                               dot_out ? op->d_partials : nullptr, &grid, s));
+        if (dot_out) {
+            hipLaunchKernelGGL((k_finalize_sum<1024>), dim3(1), dim3(1024), 0, s, (int)grid,
+                               op->d_partials, dot_out);
+            MCD_HIP(hipGetLastError());
+        }
+        return MCD_OK;
+    }
     const bool small = op->kernel == KERNEL_STREAM_S || op->kernel == KERNEL_STREAM_S_XCD;
     const int R = small ? op->rows_per_block_s : op->rows_per_block;
     const int64_t nb = (n + R - 1) / R;
@@ -691,7 +702,9 @@ static int tune_kernel(mcd_op *op, hipStream_t s) {
     double best = 1e300;
     int pick = KERNEL_STREAM;
     for (int k : {KERNEL_STREAM, KERNEL_STREAM_XCD, KERNEL_MERGE, KERNEL_ROWCHUNK,
-                  KERNEL_STREAM_S, KERNEL_STREAM_S_XCD}) {
+                  KERNEL_STREAM_S, KERNEL_STREAM_S_XCD, KERNEL_GROUPED, KERNEL_GROUPED_XCD}) {
+        op->tune_ms[k] = 0.0;
+        if ((k == KERNEL_GROUPED || k == KERNEL_GROUPED_XCD) && op->g_nblocks == 0) continue;
         op->kernel = k;
         MCD_TRY(csr_one<double>(op, x, y, nullptr, 0, nullptr, s));
         MCD_HIP(hipEventRecord(a, s));
@@ -715,6 +728,9 @@ static int tune_kernel(mcd_op *op, hipStream_t s) {
     if (pick == KERNEL_STREAM_S &&
         op->tune_ms[KERNEL_STREAM_S_XCD] <= 1.03 * op->tune_ms[KERNEL_STREAM_S])
         pick = KERNEL_STREAM_S_XCD;
+    if (pick == KERNEL_GROUPED &&
+        op->tune_ms[KERNEL_GROUPED_XCD] <= 1.03 * op->tune_ms[KERNEL_GROUPED])
+        pick = KERNEL_GROUPED_XCD;
     op->kernel = pick;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
@@ -900,6 +916,8 @@ int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32
         rc = build_csr(op, s);
         if (rc < 0) return fail(rc);
         if (tune) {
+            rc = build_grouped(op, s);
+            if (rc < 0) return fail(rc);
             rc = tune_kernel(op, s);
             if (rc < 0) return fail(rc);
         }
@@ -932,7 +950,8 @@ extern "C" void mcd_op_destroy(mcd_op *op) {
                     (void *)op->d_hash, (void *)op->d_rowptr, (void *)op->d_colw,
                     (void *)op->d_partials, (void *)op->d_counter, (void *)op->d_scalars,
                     op->ws, (void *)op->d_split_i, (void *)op->d_split_j, (void *)op->d_carry,
-                    (void *)op->d_carry_row})
+                    (void *)op->d_carry_row, (void *)op->d_gbs, (void *)op->d_goff,
+                    (void *)op->d_gtab, (void *)op->d_gw})
         if (p) (void)dfree(p, op->alloc);
     (void)hipSetDevice(cur);
     delete op;
@@ -948,6 +967,8 @@ extern "C" int mcd_op_info(const mcd_op *op, mcd_op_info_t *info) {
     info->kernel = op->kernel;
     info->device_bytes = op->device_bytes;
     info->build_ms = op->build_ms;
+    info->grouped_blocks = op->g_nblocks;
+    info->grouped_groups = op->g_nblocks > 0 ? op->g_ngroups : 0;
     return MCD_OK;
 }
 
@@ -956,6 +977,9 @@ extern "C" int mcd_op_set_kernel(mcd_op *op, int32_t kernel) {
     MCD_REQUIRE(op->storage == MCD_STORAGE_CSR, MCD_E_INVALID, "operator has no CSR");
     MCD_REQUIRE(kernel >= KERNEL_STREAM && kernel <= KERNEL_LAST, MCD_E_INVALID,
                 "kernel %d unknown", kernel);
+    MCD_REQUIRE(op->g_nblocks > 0 || (kernel != KERNEL_GROUPED && kernel != KERNEL_GROUPED_XCD),
+                MCD_E_INVALID, "the grouped layout was not built for this operator (kernel %d)",
+                kernel);
     op->kernel = kernel;
     return MCD_OK;
 }

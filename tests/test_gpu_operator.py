@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import fock, hamiltonian as ham, sampler
+from oracle import fock, hamiltonian as ham, lanczos as lz, sampler
 from tests.gpu_common import log_case, random_model, require_gpu
 
 pytestmark = pytest.mark.gpu
@@ -115,8 +115,7 @@ def test_connectivity_bit_exact(name, storage):
 
 
 def _kernels(op, storage):
-    return (["stream", "merge", "stream_xcd", "rowchunk", "stream_small", "stream_small_xcd"]
-            if storage == "csr" else [None])
+    return op.kernels() if storage == "csr" else [None]
 
 
 @pytest.mark.parametrize("name", list(MODELS))
@@ -154,8 +153,7 @@ def test_merge_path_long_and_empty_rows():
         H = ham.build_csr(keys, m)
         x = W.random_vector(len(keys), 3)
         op = mcd.Operator(m, mcd.keys_from_numpy(keys), storage="csr")
-        for kern in ("stream", "merge", "stream_xcd", "rowchunk", "stream_small",
-                     "stream_small_xcd"):
+        for kern in op.kernels():
             op.set_kernel(kern)
             y = op.apply(torch.from_numpy(x).cuda()).cpu().numpy()
             assert _rel(y, H @ x) <= 1e-12, (name, kern)
@@ -231,15 +229,22 @@ def test_apply_c2_full_size_sampled_rows():
     rows = np.sort(np.random.default_rng(5).choice(len(keys), 3000, replace=False))
     ref = ham.apply_rows(keys, rows, m, x)
     kd = mcd.keys_from_numpy(keys)
+    y_stream = None
     for storage, kern in (("csr", "stream"), ("csr", "merge"), ("csr", "stream_xcd"),
                           ("csr", "rowchunk"), ("csr", "stream_small"),
-                          ("csr", "stream_small_xcd"), ("otf", None)):
+                          ("csr", "stream_small_xcd"), ("csr", "grouped"),
+                          ("csr", "grouped_xcd"), ("otf", None)):
         op = mcd.Operator(m, kd, storage=storage)
         if kern:
             op.set_kernel(kern)
         xt = torch.from_numpy(x).cuda()
         y = op.apply(xt)
         assert _rel(y.cpu().numpy()[rows], ref) <= 1e-12
+        if kern == "stream":
+            y_stream = y.clone()
+        if kern in ("grouped", "grouped_xcd"):
+            # same terms in the same order per row: bit-identical to row-major
+            assert torch.equal(y, y_stream), kern
         x2 = torch.from_numpy(W.random_vector(len(keys), 22)).cuda()
         y2 = op.apply(x2)
         a, b = float(torch.dot(x2, y)), float(torch.dot(xt, y2))
@@ -327,3 +332,66 @@ def test_step_sampler_preaccepted_levels_bit_exact(case):
     kg, sg = mcd.basis_build(m, "steps", start_key=st, seed=5, beta_s=0.2, max_steps=1000,
                              n_f=nf, pre_level=lvl)
     assert so == sg and np.array_equal(ko, mcd.keys_to_numpy(kg))
+
+
+def _grouped_cases():
+    rng = np.random.default_rng(17)
+    ch12 = W.chain(12, U=8.0, mu=4.0, pbc=True, n_up=6, n_dn=6)
+    full12 = fock.sector_keys(12, 6, 6)
+    c1 = W.config_c1()
+    m1 = c1["model"]
+    k1, _ = sampler.chain_c(m1, W.neel_start(m1), c1["seed"], c1["n_f"], c1["burn_in"],
+                            c1["max_steps"])
+    return {
+        # one up-string segment of 924 rows spans several blocks
+        "chain12_full": (ch12, full12, True),
+        # 30% of the sector: short rows, chunks split by the 256-row cap
+        "chain12_subset": (ch12, np.sort(rng.choice(full12, 250000, replace=False)), True),
+        # C1 full sector: 70 segments of 70 rows, several segments per block
+        "c1_full": (m1, fock.sector_keys(8, 4, 4), True),
+        # C1 chain basis (2000 states, ~28 rows per segment): built or not
+        "c1_chain": (m1, k1, None),
+        # segments of ~1 row: the layout is not built
+        "sparse": (ch12, np.sort(rng.choice(full12, 900, replace=False)), False),
+    }
+
+
+@pytest.mark.parametrize("case", ["chain12_full", "chain12_subset", "c1_full", "c1_chain", "sparse"])
+def test_grouped_layout(case):
+    """Kernels 7 / 8 (grouped entry order) against the oracle and bit-for-bit
+    against the row-major kernel, float64 and float32; the fused scale + dot
+    of the Lanczos step through the grouped kernel gives the oracle's E0."""
+    torch, mcd = require_gpu()
+    m, keys, expect = _grouped_cases()[case]
+    log_case("grouped", case=case, n=len(keys))
+    op = mcd.Operator(m, mcd.keys_from_numpy(keys), storage="csr")
+    have = op.info()["grouped_blocks"] > 0
+    print(f"[grouped] {case}: n {len(keys)} blocks {op.info()['grouped_blocks']} "
+          f"chosen {op.info()['kernel']}", flush=True)
+    if expect is not None:
+        assert have == expect
+    if not have:
+        with pytest.raises(mcd.McdError):
+            op.set_kernel("grouped")
+        op.close()
+        return
+    H = ham.build_csr(keys, m)
+    x = W.random_vector(len(keys), 5)
+    xt = torch.from_numpy(x).cuda()
+    x32 = torch.from_numpy(x.astype(np.float32)).cuda()
+    op.set_kernel("stream")
+    y_ref, y32_ref = op.apply(xt), op.apply(x32)
+    for kern in ("grouped", "grouped_xcd"):
+        op.set_kernel(kern)
+        y = op.apply(xt)
+        assert _rel(y.cpu().numpy(), H @ x) <= 1e-12, kern
+        assert torch.equal(y, y_ref), kern
+        assert torch.equal(op.apply(x32), y32_ref), kern
+    if len(keys) > 300000:
+        op.close()
+        return
+    op.set_kernel("grouped_xcd")
+    e0, psi, *_ = mcd.lanczos_ground(op, max_iter=400, tol=1e-12, seed=11)
+    ro = lz.lanczos_ground(H, lz.start_vector(keys, 11), tol=1e-13)
+    assert abs(e0 - ro["e0"]) <= 1e-10 * abs(ro["e0"])
+    op.close()
