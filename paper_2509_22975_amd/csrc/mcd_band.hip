@@ -345,21 +345,19 @@ static void block_cf(const BandResult &br, cplx z, int p, cplx *out) {
 // workgroup of one wavefront): the coefficient matrices never leave HBM, so
 // a block step needs no host round trip.
 
-// dst = (src + src^T) / 2
-__global__ __launch_bounds__(64) void k_sym(int P, const double *__restrict__ src,
-                                            double *__restrict__ dst) {
-    for (int e = threadIdx.x; e < P * P; e += 64) {
+// Coefficients of W -= Q_{j-1} B_j^T + Q_j A_j in one pass over W:
+// A_j = sym(G) (also kept in dA), C2 = [B_j^T ; A_j] (B_j^T only when dB).
+__global__ __launch_bounds__(64) void k_sym_pair(int P, const double *__restrict__ G,
+                                                 double *__restrict__ dA,
+                                                 const double *__restrict__ dB,
+                                                 double *__restrict__ C2) {
+    const int PP = P * P;
+    for (int e = threadIdx.x; e < PP; e += 64) {
         const int a = e / P, b = e % P;
-        dst[e] = 0.5 * (src[a * P + b] + src[b * P + a]);
-    }
-}
-
-// dst = src^T
-__global__ __launch_bounds__(64) void k_transpose(int P, const double *__restrict__ src,
-                                                  double *__restrict__ dst) {
-    for (int e = threadIdx.x; e < P * P; e += 64) {
-        const int a = e / P, b = e % P;
-        dst[e] = src[b * P + a];
+        const double v = 0.5 * (G[a * P + b] + G[b * P + a]);
+        dA[e] = v;
+        C2[PP + e] = v;
+        if (dB != nullptr) C2[e] = dB[b * P + a];
     }
 }
 
@@ -466,6 +464,7 @@ struct BandRun {
     hipStream_t s;
     T *Qs = nullptr;          // [nstore][n][P]
     T *W = nullptr;           // [n][P]
+    T *W2 = nullptr;          // [n][P] scratch of the two-pass QR (device run)
     T *colbuf = nullptr;      // [2][n] single-column staging (per-column mode)
     bool per_column = false;
     double *part = nullptr;   // Gram partials
@@ -654,12 +653,12 @@ struct BandRun {
         br.B.assign(1, std::vector<double>());
         double *dT = nullptr;
         int *d_rank = nullptr;
-        // [A: max_blocks][B: max_blocks + 1][R0][Xm][Bm][Bacc][Bt]
-        const size_t nT = (size_t)(2 * max_blocks + 6) * PP;
+        // [A: max_blocks][B: max_blocks + 1][R0][Xm][Bm][Bacc][C2: 2]
+        const size_t nT = (size_t)(2 * max_blocks + 7) * PP;
         MCD_HIP(dmalloc((void **)&dT, nT * sizeof(double), Alloc{s, true}));
         MCD_HIP(dmalloc((void **)&d_rank, (size_t)(max_blocks + 2) * sizeof(int), Alloc{s, true}));
         double *dA = dT, *dB = dA + (size_t)max_blocks * PP, *dR0 = dB + (size_t)(max_blocks + 1) * PP;
-        double *dXm = dR0 + PP, *dBm = dXm + PP, *dBacc = dBm + PP, *dBt = dBacc + PP;
+        double *dXm = dR0 + PP, *dBm = dXm + PP, *dBacc = dBm + PP, *dC2 = dBacc + PP;
         auto fail = [&](int rc) {
             (void)dfree(dT, Alloc{s, true});
             (void)dfree(d_rank, Alloc{s, true});
@@ -670,6 +669,7 @@ struct BandRun {
         int rc_ = (expr);    \
         if (rc_ < 0) return fail(rc_); \
     } while (0)
+        // src -> W2 (first pass) -> dst (second pass); src and dst are never W2
         auto qr_dev = [&](T *src, T *dst, double *outB, int slot) -> int {
             T *cur = src;
             for (int pass = 0; pass < 2; pass++) {
@@ -677,12 +677,9 @@ struct BandRun {
                 hipLaunchKernelGGL(k_pchol, dim3(1), dim3(64), 0, s, P, dG, pass,
                                    dtol_abs * dtol_abs, dXm, dBm, dBacc, pass == 0 ? 1 : 0,
                                    d_rank + slot);
-                T *out = (cur == dst) ? W : dst;
+                T *out = pass == 0 ? W2 : dst;
                 MCD_TRY(block_apply_dev(cur, 1, dXm, out, false));
-                if (out != dst)
-                    MCD_HIP(hipMemcpyAsync(dst, out, (size_t)n * P * sizeof(T),
-                                           hipMemcpyDeviceToDevice, s));
-                cur = dst;
+                cur = out;
             }
             MCD_HIP(hipMemcpyAsync(outB, dBacc, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
             return MCD_OK;
@@ -723,12 +720,16 @@ struct BandRun {
             for (int j = 0; j < max_blocks; j++) {
                 DTRY(apply_any(op, sizeof(T) == 8 ? MCD_F64 : MCD_F32, P, blk(j), W, s));
                 DTRY(gram_dev(blk(j), 1, W));
-                hipLaunchKernelGGL(k_sym, dim3(1), dim3(64), 0, s, P, dG, dA + (size_t)j * PP);
-                DTRY(block_apply_dev(blk(j), 1, dA + (size_t)j * PP, W, true));
-                if (j > 0) {
-                    hipLaunchKernelGGL(k_transpose, dim3(1), dim3(64), 0, s, P,
-                                       dB + (size_t)j * PP, dBt);
-                    DTRY(block_apply_dev(blk(j - 1), 1, dBt, W, true));
+                // W -= Q_{j-1} B_j^T + Q_j A_j: one pass when the two blocks
+                // are adjacent in the store
+                hipLaunchKernelGGL(k_sym_pair, dim3(1), dim3(64), 0, s, P, dG,
+                                   dA + (size_t)j * PP, j > 0 ? dB + (size_t)j * PP : nullptr,
+                                   dC2);
+                if (j > 0 && blk(j) == blk(j - 1) + (int64_t)n * P) {
+                    DTRY(block_apply_dev(blk(j - 1), 2, dC2, W, true));
+                } else {
+                    DTRY(block_apply_dev(blk(j), 1, dC2 + PP, W, true));
+                    if (j > 0) DTRY(block_apply_dev(blk(j - 1), 1, dC2, W, true));
                 }
                 for (int pass = 0; pass < reorth; pass++) {
                     DTRY(gram_dev(blk(0), j + 1, W));
@@ -866,8 +867,8 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
     BandRun<T> run;
     auto cleanup = [&]() {
         for (void *p : {(void *)img, (void *)srt, (void *)uniq, (void *)d_nu, tmp, (void *)run.Qs,
-                        (void *)run.W, (void *)run.part, (void *)run.dC, (void *)run.dG,
-                        (void *)run.colbuf})
+                        (void *)run.W, (void *)run.W2, (void *)run.part, (void *)run.dC,
+                        (void *)run.dG, (void *)run.colbuf})
             if (p) (void)dfree(p, A);
         if (op) mcd_op_destroy(op);
     };
@@ -938,6 +939,7 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
     }
     CK(dmalloc((void **)&run.Qs, (size_t)run.nstore * nu * P * sizeof(T), A));
     CK(dmalloc((void **)&run.W, (size_t)nu * P * sizeof(T), A));
+    if (!(cfg->per_column != 0)) CK(dmalloc((void **)&run.W2, (size_t)nu * P * sizeof(T), A));
     run.per_column = cfg->per_column != 0;
     run.g_tol = cfg->g_tol;
     run.p_sel = sel.n;
@@ -1010,7 +1012,8 @@ template <typename T>
 static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
                       const double *psi0_dev, double e0, const SelOps &sel, int n_freq,
                       const double *omega, const mcd_band_cfg *cfg, double *G_out, double *Gp_out,
-                      double *Gm_out, mcd_solve_info *info, hipStream_t s) {
+                      double *Gm_out, mcd_solve_info *info, hipStream_t s,
+                      bool concurrent_sectors) {
     const Alloc A{s, true};   // stream-ordered buffers (no device-wide sync on free)
     const double t0 = wall_ms();
     double *w = nullptr, *w2 = nullptr, *psi_t = nullptr, *scr = nullptr;
@@ -1092,11 +1095,48 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
     int64_t np = 0, nm = 0;
     std::vector<cplx> zp, zm;
     check_points(cfg, n_freq, omega, e0, zp, zm);
-    int rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, true, cfg, 1.0, P, brp, &np, s,
+    // The particle (c+) and hole (c) runs are independent: with
+    // concurrent_sectors the hole run goes to a second stream from a second
+    // host thread (both read keys_t / psi_t, complete at the synchronisation
+    // above), so the two chains of small dependent kernels overlap on the
+    // GPU.  Each run is the same sequence of kernels either way, so the
+    // results do not depend on it.
+    int rc = MCD_OK, rc_m = MCD_OK;
+    std::string msg_m;
+    if (concurrent_sectors) {
+        int dev = 0;
+        CK(hipGetDevice(&dev));
+        std::thread hole([&]() {
+            hipStream_t s2 = nullptr;
+            if (hipSetDevice(dev) != hipSuccess ||
+                hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
+                rc_m = MCD_E_HIP;
+                msg_m = "stream set-up for the hole run failed";
+                return;
+            }
+            rc_m = excited_run<T>(model, keys_t, psi_t, n_keep, sel, false, cfg, 1.0, P, brm, &nm,
+                                  s2, false, nullptr, &zm);
+            if (rc_m < 0) msg_m = mcd_last_error();
+            if (hipStreamSynchronize(s2) != hipSuccess && rc_m >= 0) {
+                rc_m = MCD_E_HIP;
+                msg_m = "hole run stream failed";
+            }
+            (void)hipStreamDestroy(s2);
+        });
+        rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, true, cfg, 1.0, P, brp, &np, s,
                             false, nullptr, &zp);
-    if (rc >= 0)
-        rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, false, cfg, 1.0, P, brm, &nm, s,
-                            false, nullptr, &zm);
+        hole.join();
+        if (rc >= 0 && rc_m < 0) {
+            set_error("%s", msg_m.c_str());
+            rc = rc_m;
+        }
+    } else {
+        rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, true, cfg, 1.0, P, brp, &np, s,
+                            false, nullptr, &zp);
+        if (rc >= 0)
+            rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, false, cfg, 1.0, P, brm, &nm, s,
+                                false, nullptr, &zm);
+    }
     if (rc < 0) {
         cleanup();
         return rc;
@@ -1591,9 +1631,9 @@ extern "C" int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *ke
     hipStream_t s = (hipStream_t)stream;
     if (cfg->precision == MCD_F64)
         return band_green<double>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg,
-                                  G_out, Gp_out, Gm_out, info, s);
+                                  G_out, Gp_out, Gm_out, info, s, true);
     return band_green<float>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg, G_out,
-                             Gp_out, Gm_out, info, s);
+                             Gp_out, Gm_out, info, s, true);
 }
 
 extern "C" int mcd_band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
@@ -1696,10 +1736,10 @@ extern "C" int mcd_batch_band_green(const mcd_model *const *models,
             const int rc = cfg->precision == MCD_F64
                                ? band_green<double>(models[i], keys_dev[i], n[i], psi0_dev[i], e0[i],
                                                     sel, n_freq, omega, cfg, G_out[i], nullptr,
-                                                    nullptr, &one, ws)
+                                                    nullptr, &one, ws, false)
                                : band_green<float>(models[i], keys_dev[i], n[i], psi0_dev[i], e0[i],
                                                    sel, n_freq, omega, cfg, G_out[i], nullptr,
-                                                   nullptr, &one, ws);
+                                                   nullptr, &one, ws, false);
             if (rc < 0) {
                 rcs[w] = rc;
                 msgs[w] = std::string("instance ") + std::to_string(i) + ": " + mcd_last_error();

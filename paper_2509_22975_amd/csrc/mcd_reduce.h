@@ -51,20 +51,45 @@ __device__ __forceinline__ void store_partial(double block_val, double *partials
     if (threadIdx.x == 0) partials[blockIdx.x] = block_val;
 }
 
-// out[0] = sum_i partials[i]: one workgroup, four independent accumulators
-// per thread so the loads overlap; fixed order.
+// out[0] = sum_i partials[i]: one workgroup; thread t adds t, t + BS, ...
+// into four accumulators (k mod 4, a last partial group into the first) in
+// index order, then the workgroup sum.  Up to 32 partials per thread are all
+// loaded before the first add (one memory round trip instead of one per
+// group of four); the order of the additions is the same either way.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_finalize_sum(int n, const double *__restrict__ partials,
                                                      double *__restrict__ out) {
+    constexpr int KMAX = 32;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int i = threadIdx.x;
-    for (; i + 3 * BS < n; i += 4 * BS) {
-        s0 += partials[i];
-        s1 += partials[i + BS];
-        s2 += partials[i + 2 * BS];
-        s3 += partials[i + 3 * BS];
+    const int t = threadIdx.x;
+    if (n > 0 && n <= KMAX * BS) {
+        double v[KMAX];
+#pragma unroll
+        for (int k = 0; k < KMAX; k++) v[k] = partials[min(t + k * BS, n - 1)];
+        const int K = t < n ? (n - 1 - t) / BS + 1 : 0;
+        const int K4 = K & ~3;
+#pragma unroll
+        for (int g = 0; g < KMAX / 4; g++) {
+            if (4 * g < K4) {
+                s0 += v[4 * g];
+                s1 += v[4 * g + 1];
+                s2 += v[4 * g + 2];
+                s3 += v[4 * g + 3];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KMAX; k++)
+            if (k >= K4 && k < K) s0 += v[k];
+    } else {
+        int i = t;
+        for (; i + 3 * BS < n; i += 4 * BS) {
+            s0 += partials[i];
+            s1 += partials[i + BS];
+            s2 += partials[i + 2 * BS];
+            s3 += partials[i + 3 * BS];
+        }
+        for (; i < n; i += BS) s0 += partials[i];
     }
-    for (; i < n; i += BS) s0 += partials[i];
     const double s = block_sum<BS>((s0 + s1) + (s2 + s3));
     if (threadIdx.x == 0) *out = s;
 }
