@@ -182,6 +182,76 @@ __global__ __launch_bounds__(BS) void k_gram(int64_t n, int64_t chunk_rows, int 
     }
 }
 
+// One step of a recursive-halving sum over the lanes of a wavefront: lanes
+// with bit O set keep the upper H of their values, the others the lower H,
+// each adds its partner's copy of the half it keeps.  After the steps
+// O = 32, 16, ..., lane l holds the wavefront sums of the values whose index
+// bits match its lane bits (a reduce-scatter in 63 shuffles for 64 values).
+template <int H, int O>
+__device__ __forceinline__ void halve_sum(double *v, int lane) {
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < H; i++) {
+        const double mine = up ? v[i + H] : v[i];
+        const double other = up ? v[i] : v[i + H];
+        v[i] = mine + __shfl_xor(other, O, 64);
+    }
+}
+
+// Partial Gram matrices for P = 8 and 16, register-tiled: a thread owns 64
+// of the P x P products (P = 8: all of them, one row per thread; P = 16: a
+// quarter, rows a in [4 qq, 4 qq + 4), four threads per row), reads its rows
+// straight from memory (coalesced, no LDS staging, no barriers in the row
+// loop) and accumulates in float64; the 64 sums are reduced over the
+// wavefront by recursive halving and over the four wavefronts in LDS, in a
+// fixed order.  partial[(m * nch + chunk)][a][b] as for k_gram.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_gram_rt(int64_t n, int64_t chunk_rows, int nch,
+                                                 const T *__restrict__ Q0, int64_t qstride,
+                                                 const T *__restrict__ X,
+                                                 double *__restrict__ part) {
+    static_assert(P == 8 || P == 16, "register-tiled Gram for P = 8, 16");
+    constexpr int PP = P * P, TPR = PP / 64, NA = P / TPR, RPB = 256 / TPR;
+    __shared__ double red[4][PP];
+    const int m = blockIdx.y, chunk = blockIdx.x;
+    const T *__restrict__ Q = Q0 + (int64_t)m * qstride;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int qq = t % TPR;
+    const int64_t r0 = (int64_t)chunk * chunk_rows;
+    const int64_t r1 = min(r0 + chunk_rows, n);
+    double v[64];
+#pragma unroll
+    for (int i = 0; i < 64; i++) v[i] = 0.0;
+#pragma unroll 2
+    for (int64_t r = r0 + t / TPR; r < r1; r += RPB) {
+        T qa[NA], xb[P];
+#pragma unroll
+        for (int i = 0; i < NA; i++) qa[i] = Q[r * P + qq * NA + i];
+#pragma unroll
+        for (int b = 0; b < P; b++) xb[b] = X[r * P + b];
+#pragma unroll
+        for (int i = 0; i < NA; i++)
+#pragma unroll
+            for (int b = 0; b < P; b++) v[i * P + b] += (double)qa[i] * (double)xb[b];
+    }
+    halve_sum<32, 32>(v, lane);
+    halve_sum<16, 16>(v, lane);
+    halve_sum<8, 8>(v, lane);
+    halve_sum<4, 4>(v, lane);
+    if (TPR == 1) {
+        halve_sum<2, 2>(v, lane);
+        halve_sum<1, 1>(v, lane);
+        red[w][lane] = v[0];   // value index = lane
+    } else {
+        // lane l holds values (l & ~3) + j of its quarter qq = l & 3
+#pragma unroll
+        for (int j = 0; j < 4; j++) red[w][64 * (lane & 3) + (lane & ~3) + j] = v[j];
+    }
+    __syncthreads();
+    for (int e = t; e < PP; e += 256)
+        part[((int64_t)m * nch + chunk) * PP + e] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+}
+
 // out[m][e] = sum_c part[(m nch + c)][e]: one wavefront per output entry,
 // lanes stride over the chunks, fixed butterfly order.
 __global__ __launch_bounds__(256) void k_gram_reduce(int nm, int nch, int PP,
@@ -515,8 +585,16 @@ struct BandRun {
     // Gram matrices Q_m^T X (m < nm) into dG on the device.
     int gram_dev(const T *Q0, int nm, const T *X) {
         const int PP = P * P;
-        // ~2048 workgroups in total, at least 256 rows per chunk
-        int nch = (int)std::min<int64_t>(gridn(n, 256), std::max<int64_t>(1, 2048 / nm));
+        int nch;
+        if (P >= 8) {
+            // register-tiled kernel: >= 8 rows per thread slot, ~1024 workgroups
+            const int64_t rpb = 256 / (PP / 64);
+            nch = (int)std::min<int64_t>(std::max<int64_t>(1, n / (8 * rpb)),
+                                         std::max<int64_t>(1, 1024 / nm));
+        } else {
+            // ~2048 workgroups in total, at least 256 rows per chunk
+            nch = (int)std::min<int64_t>(gridn(n, 256), std::max<int64_t>(1, 2048 / nm));
+        }
         nch = std::max(1, nch);
         const int64_t chunk_rows = (n + nch - 1) / nch;
         nch = (int)((n + chunk_rows - 1) / chunk_rows);
@@ -527,10 +605,16 @@ struct BandRun {
         hipLaunchKernelGGL((k_gram<T, PV>), grid, dim3(BS), 0, s, n, chunk_rows, nch, Q0, \
                            (int64_t)n * P, X, part);                                     \
         break;
+#define GRT(PV)                                                                            \
+    case PV:                                                                               \
+        hipLaunchKernelGGL((k_gram_rt<T, PV>), grid, dim3(256), 0, s, n, chunk_rows, nch, Q0, \
+                           (int64_t)n * P, X, part);                                       \
+        break;
         switch (P) {
-            GR(1) GR(2) GR(4) GR(8) GR(16)
+            GR(1) GR(2) GR(4) GRT(8) GRT(16)
         }
 #undef GR
+#undef GRT
         MCD_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_gram_reduce, dim3(gridn((int64_t)nm * PP, 4)), dim3(256), 0, s, nm,
                            nch, PP, part, dG);
