@@ -6,7 +6,11 @@
 //   k_diag          d_r = sum_i U_i n_iu n_id + sum_is eps_i n_is
 //   k_hash_insert   open-addressing hash key -> row (load <= 1/4)
 //   k_csr_count     kept hops per row (hop enumeration + lookup)
-//   k_csr_fill      packed words: column | class << 26 | sign << 31
+//   k_csr_fill      packed words: column | class << col_bits | sign << 31
+//   k_csr_count_stage, k_csr_compact
+//                   the same CSR in one hash pass (words staged per row)
+//   k_block_max_all largest block nonzero count for every power-of-two block
+//   k_spmv_grouped  (mcd_grouped.hip) one vector, grouped entry order
 //   k_spmv_stream   one vector: a workgroup streams the nonzeros of a row
 //                   block into LDS products, then each row sums its run
 //   k_apply_group   nvec vectors (row-major): nvec lanes per row, each lane
@@ -115,16 +119,59 @@ __global__ void k_csr_fill(int64_t n, const uint64_t *__restrict__ keys,
     });
 }
 
-__global__ void k_block_max(int64_t n, int R, const int64_t *__restrict__ rowptr,
-                            unsigned long long *out) {
-    const int64_t nb = (n + R - 1) / R;
-    unsigned long long best = 0;
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
-         b += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r0 = b * R, r1 = min(r0 + (int64_t)R, n);
-        best = max(best, (unsigned long long)(rowptr[r1] - rowptr[r0]));
+// Count and words in one hash pass (instead of k_csr_count + k_csr_fill):
+// word q of row r goes to stage[q * n + r] (stores coalesced across rows),
+// in the order k_csr_fill writes them; k_csr_compact moves them into place
+// once the row pointers are known.
+__global__ void k_csr_count_stage(int64_t n, const uint64_t *__restrict__ keys,
+                                  const DevModel *__restrict__ m, const HashSlot *__restrict__ h,
+                                  uint64_t hmask, int64_t *__restrict__ cnt,
+                                  uint32_t *__restrict__ stage) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > n) return;
+    if (r == n) {
+        cnt[n] = 0;
+        return;
     }
-    atomicMax(out, best);
+    int64_t c = 0;
+    for_each_hop(keys[r], m, h, hmask, [&](int64_t col, int b, uint32_t par) {
+        const uint32_t neg = par ^ m->bonds[b].neg;
+        stage[c * n + r] = (uint32_t)col | (m->bonds[b].cls << m->col_bits) | (neg << 31);
+        c++;
+    });
+    cnt[r] = c;
+}
+
+__global__ void k_csr_compact(int64_t n, const uint32_t *__restrict__ stage,
+                              const int64_t *__restrict__ rowptr, uint32_t *__restrict__ colw) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int64_t e0 = rowptr[r], c = rowptr[r + 1] - e0;
+    for (int64_t q = 0; q < c; q++) colw[e0 + q] = stage[q * n + r];
+}
+
+// Largest nonzero count of a row block [b R, (b + 1) R) for every R = 2^k,
+// k = 0..8, in one pass: out[k] (atomic max of wavefront maxima).
+__global__ void k_block_max_all(int64_t n, const int64_t *__restrict__ rowptr,
+                                unsigned long long *__restrict__ out) {
+    unsigned long long best[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) best[k] = 0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            const int64_t R = int64_t(1) << k;
+            if ((r & (R - 1)) == 0)
+                best[k] = max(best[k], (unsigned long long)(rowptr[min(r + R, n)] - rowptr[r]));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        unsigned long long v = best[k];
+        for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+        if ((threadIdx.x & 63) == 0) atomicMax(&out[k], v);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -538,8 +585,21 @@ static int build_csr(mcd_op *op, hipStream_t s) {
     MCD_HIP(dmalloc((void **)&op->d_rowptr, (n + 1) * sizeof(int64_t), op->alloc));
     MCD_HIP(dmalloc((void **)&cnt, (n + 1) * sizeof(int64_t), op->alloc));
     op->device_bytes += (n + 1) * sizeof(int64_t);
-    hipLaunchKernelGGL(k_csr_count, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, n, op->d_keys,
-                       op->d_model, op->d_hash, op->hash_mask, cnt);
+    // One hash pass when the staging buffer (2 n_bonds words per row, the most
+    // a row can keep) is modest; else count, then fill.
+    const int64_t maxc = 2 * (int64_t)op->hm.dm.n_bonds;
+    size_t fr = 0, tot = 0;
+    MCD_HIP(hipMemGetInfo(&fr, &tot));
+    const double stage_bytes = (double)n * (double)maxc * sizeof(uint32_t);
+    uint32_t *stage = nullptr;
+    if (n > 0 && maxc > 0 && stage_bytes <= std::min(4e9, 0.25 * (double)fr))
+        MCD_HIP(dmalloc((void **)&stage, (size_t)stage_bytes, op->alloc));
+    if (stage)
+        hipLaunchKernelGGL(k_csr_count_stage, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, n,
+                           op->d_keys, op->d_model, op->d_hash, op->hash_mask, cnt, stage);
+    else
+        hipLaunchKernelGGL(k_csr_count, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, n,
+                           op->d_keys, op->d_model, op->d_hash, op->hash_mask, cnt);
     MCD_HIP(hipGetLastError());
     size_t tmp_bytes = 0;
     MCD_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, op->d_rowptr, n + 1, s));
@@ -554,32 +614,39 @@ static int build_csr(mcd_op *op, hipStream_t s) {
     op->nnz = nnz;
     MCD_HIP(dmalloc((void **)&op->d_colw, std::max<int64_t>(nnz, 1) * sizeof(uint32_t), op->alloc));
     op->device_bytes += nnz * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
-                       op->d_model, op->d_hash, op->hash_mask, op->d_rowptr, op->d_colw);
-    MCD_HIP(hipGetLastError());
+    if (stage) {
+        hipLaunchKernelGGL(k_csr_compact, dim3(grid_for(n, 256)), dim3(256), 0, s, n, stage,
+                           op->d_rowptr, op->d_colw);
+        MCD_HIP(hipGetLastError());
+        MCD_HIP(dfree(stage, op->alloc));
+    } else {
+        hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
+                           op->d_model, op->d_hash, op->hash_mask, op->d_rowptr, op->d_colw);
+        MCD_HIP(hipGetLastError());
+    }
     // Largest power-of-two row block whose nonzeros fit the LDS product buffer
-    // (one choice per buffer size of the stream kernels).
+    // (one choice per buffer size of the stream kernels), all sizes in one pass.
     unsigned long long *d_max = nullptr;
-    MCD_HIP(dmalloc((void **)&d_max, sizeof(unsigned long long), op->alloc));
+    MCD_HIP(dmalloc((void **)&d_max, 9 * sizeof(unsigned long long), op->alloc));
+    MCD_HIP(hipMemsetAsync(d_max, 0, 9 * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_block_max_all, dim3(512), dim3(256), 0, s, n, op->d_rowptr, d_max);
+    MCD_HIP(hipGetLastError());
+    unsigned long long mx[9] = {};
+    MCD_HIP(hipMemcpyAsync(mx, d_max, sizeof(mx), hipMemcpyDeviceToHost, s));
+    MCD_HIP(hipStreamSynchronize(s));
+    MCD_HIP(dfree(d_max, op->alloc));
     op->rows_per_block = 1;
     op->rows_per_block_s = 1;
-    bool got_big = false;
-    for (int R = 256; R >= 1; R >>= 1) {
-        MCD_HIP(hipMemsetAsync(d_max, 0, sizeof(unsigned long long), s));
-        hipLaunchKernelGGL(k_block_max, dim3(512), dim3(256), 0, s, n, R, op->d_rowptr, d_max);
-        unsigned long long mx = 0;
-        MCD_HIP(hipMemcpyAsync(&mx, d_max, sizeof(mx), hipMemcpyDeviceToHost, s));
-        MCD_HIP(hipStreamSynchronize(s));
-        if (!got_big && mx <= (unsigned long long)kStreamNnzMax) {
-            op->rows_per_block = R;
-            got_big = true;
-        }
-        if (mx <= (unsigned long long)kStreamNnzSmall) {
-            op->rows_per_block_s = R;
+    for (int k = 8; k >= 0; k--)
+        if (mx[k] <= (unsigned long long)kStreamNnzMax) {
+            op->rows_per_block = 1 << k;
             break;
         }
-    }
-    MCD_HIP(dfree(d_max, op->alloc));
+    for (int k = 8; k >= 0; k--)
+        if (mx[k] <= (unsigned long long)kStreamNnzSmall) {
+            op->rows_per_block_s = 1 << k;
+            break;
+        }
     // row-parallel products: words per chunk from the mean row length
     op->group_chunk = (nnz < 4 * n) ? 4 : (nnz < 10 * n) ? 8 : 16;
     // merge-path split points
