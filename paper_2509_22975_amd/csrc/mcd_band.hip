@@ -340,6 +340,26 @@ static void jacobi_eig(int n, std::vector<double> A, std::vector<double> &w,
 
 // Solve S X = B (S n x n, B n x k, complex, row-major) by Gaussian
 // elimination with partial pivoting; S and B are overwritten, X returned in B.
+// fn(i) for i in [0, n) on up to 16 host threads (static round-robin); the
+// callers give every index its own output, so results do not depend on the
+// thread count.
+template <typename F>
+static void parallel_for(int n, F &&fn) {
+    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    const int nt = std::max(1, std::min({n, hw, 16}));
+    if (nt <= 1) {
+        for (int i = 0; i < n; i++) fn(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; t++)
+        th.emplace_back([&, t]() {
+            for (int i = t; i < n; i += nt) fn(i);
+        });
+    for (int i = 0; i < n; i += nt) fn(i);
+    for (auto &x : th) x.join();
+}
+
 static void csolve(int n, int k, std::vector<cplx> &S, std::vector<cplx> &B) {
     for (int c = 0; c < n; c++) {
         int piv = c;
@@ -552,11 +572,10 @@ struct BandRun {
 
     bool g_converged(const BandResult &b) {
         if (g_tol <= 0.0 || zcheck.empty() || b.m == 0) return false;
-        std::vector<cplx> g((size_t)zcheck.size() * p_sel * p_sel), one(p_sel * p_sel);
-        for (size_t f = 0; f < zcheck.size(); f++) {
-            block_cf(b, zcheck[f], p_sel, one.data());
-            for (int e = 0; e < p_sel * p_sel; e++) g[f * p_sel * p_sel + e] = one[e];
-        }
+        std::vector<cplx> g((size_t)zcheck.size() * p_sel * p_sel);
+        parallel_for((int)zcheck.size(), [&](int f) {
+            block_cf(b, zcheck[f], p_sel, g.data() + (size_t)f * p_sel * p_sel);
+        });
         bool conv = false;
         if (gprev.size() == g.size()) {
             double dmax = 0.0, gmax = 0.0;
@@ -1100,6 +1119,10 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
                       bool concurrent_sectors) {
     const Alloc A{s, true};   // stream-ordered buffers (no device-wide sync on free)
     const double t0 = wall_ms();
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) pool_keep_freed(dev);
+    }
     double *w = nullptr, *w2 = nullptr, *psi_t = nullptr, *scr = nullptr;
     uint32_t *idx = nullptr, *idx2 = nullptr, *kept = nullptr;
     uint64_t *keys_t = nullptr;
@@ -1225,8 +1248,9 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
         cleanup();
         return rc;
     }
-    std::vector<cplx> g(p * p);
-    for (int f = 0; f < n_freq; f++) {
+    // resolvents: frequencies are independent (one host thread each)
+    parallel_for(n_freq, [&](int f) {
+        std::vector<cplx> g(p * p);
         cplx *Gf = (cplx *)G_out + (size_t)f * p * p;
         for (int e = 0; e < p * p; e++) Gf[e] = 0.0;
         if (brp.m > 0) {
@@ -1247,7 +1271,7 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
         } else if (Gm_out) {
             for (int e = 0; e < p * p; e++) ((cplx *)Gm_out)[(size_t)f * p * p + e] = 0.0;
         }
-    }
+    });
     cleanup();
 #undef CK
     if (info) {
@@ -1446,6 +1470,10 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
                           double *d_U, double *d_eps, mcd_solve_info *info, hipStream_t s) {
     const Alloc A{s, true};   // stream-ordered buffers (no device-wide sync on free)
     const double t0 = wall_ms();
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) pool_keep_freed(dev);
+    }
     const int p = sel.n;
     int P = 1;
     while (P < p) P <<= 1;
@@ -1509,10 +1537,20 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             const int m = br.m, KP = m * P;
             const double sg = create ? 1.0 : -1.0;
             std::vector<double> M((size_t)KP * KP, 0.0), Om((size_t)KP * P, 0.0);
-            std::vector<cplx> X, V((size_t)KP * p);
-            for (int f = 0; f < n_freq; f++) {
+            // Per frequency (in parallel): X_f = first block column of
+            // (z - T)^-1 R0, V_f = X_f conj(G_bar_f)^T.  Then M and Omega
+            // (in parallel over their rows a), each element summed over the
+            // frequencies in index order.
+            std::vector<std::vector<cplx>> Xs(n_freq), Vs(n_freq);
+            std::vector<std::vector<double>> Ws(n_freq);
+            parallel_for(n_freq, [&](int f) {
                 const cplx zeta = freq_arg(cfg, omega[f]);
-                block_solve_first(br, create ? e0 + zeta : e0 - zeta, p, X);
+                block_solve_first(br, create ? e0 + zeta : e0 - zeta, p, Xs[f]);
+                const std::vector<cplx> &X = Xs[f];
+                std::vector<cplx> &V = Vs[f];
+                std::vector<double> &Wf = Ws[f];
+                V.assign((size_t)KP * p, cplx(0.0));
+                Wf.assign((size_t)KP * p, 0.0);
                 const cplx *Gb = (const cplx *)G_bar + (size_t)f * p * p;
                 for (int a = 0; a < KP; a++)
                     for (int mu = 0; mu < p; mu++) {
@@ -1522,16 +1560,21 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
                             w += X[(size_t)a * p + nu] * std::conj(Gb[nu * p + mu]);
                         }
                         V[(size_t)a * p + mu] = v;
-                        Om[(size_t)a * P + mu] += sg * (v + w).real();
+                        Wf[(size_t)a * p + mu] = (v + w).real();
                     }
-                for (int a = 0; a < KP; a++)
+            });
+            parallel_for(KP, [&](int a) {
+                for (int f = 0; f < n_freq; f++) {
+                    const cplx *Va = Vs[f].data() + (size_t)a * p;
+                    const cplx *X = Xs[f].data();
+                    for (int mu = 0; mu < p; mu++) Om[(size_t)a * P + mu] += sg * Ws[f][(size_t)a * p + mu];
                     for (int b = 0; b < KP; b++) {
                         double t = 0.0;
-                        for (int mu = 0; mu < p; mu++)
-                            t += (V[(size_t)a * p + mu] * X[(size_t)b * p + mu]).real();
+                        for (int mu = 0; mu < p; mu++) t += (Va[mu] * X[(size_t)b * p + mu]).real();
                         M[(size_t)a * KP + b] += sg * t;
                     }
-            }
+                }
+            });
             for (int a = 0; a < KP; a++) trM += M[(size_t)a * KP + a];
             krylov += br.krylov;
             const int64_t nx = run.n;

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <utility>
 
 #include "mcd_internal.h"
@@ -13,6 +14,19 @@
 namespace mcd {
 
 static thread_local char g_err[1024] = "";
+
+void pool_keep_freed(int device) {
+    static std::mutex mu;
+    static bool done[64] = {};
+    if (device < 0 || device >= 64) return;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done[device]) return;
+    done[device] = true;
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, device) != hipSuccess || pool == nullptr) return;
+    uint64_t keep = kPoolKeepBytes;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+}
 
 void set_error(const char *fmt, ...) {
     va_list ap;

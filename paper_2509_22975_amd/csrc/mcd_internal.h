@@ -106,6 +106,12 @@ inline hipError_t dmalloc(void **p, size_t bytes, const Alloc &a) {
 inline hipError_t dfree(void *p, const Alloc &a) {
     return a.async ? hipFreeAsync(p, a.s) : hipFree(p);
 }
+// Once per device: let the default stream-ordered memory pool keep up to
+// kPoolKeepBytes of freed memory instead of returning it to the driver at
+// every synchronisation, so the many short-lived buffers of the band runs
+// are reused without driver calls.
+constexpr uint64_t kPoolKeepBytes = uint64_t(8) << 30;
+void pool_keep_freed(int device);
 
 struct HashSlot {
     uint64_t key;

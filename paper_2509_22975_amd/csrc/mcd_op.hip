@@ -904,6 +904,7 @@ int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32
     int rc = prepare_model(model, &op->hm);
     if (rc < 0) return fail(rc);
     if (hipGetDevice(&op->device) != hipSuccess) return fail(MCD_E_HIP);
+    if (async) pool_keep_freed(op->device);
     op->n = n;
     op->nnz = -1;
 #define CK(expr)                                                                             \
