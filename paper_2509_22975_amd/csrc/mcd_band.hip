@@ -555,6 +555,7 @@ struct BandRun {
     T *Qs = nullptr;          // [nstore][n][P]
     T *W = nullptr;           // [n][P]
     T *W2 = nullptr;          // [n][P] scratch of the two-pass QR (device run)
+    Alloc al;                 // allocator of the device run's small buffers
     T *colbuf = nullptr;      // [2][n] single-column staging (per-column mode)
     bool per_column = false;
     double *part = nullptr;   // Gram partials
@@ -758,13 +759,13 @@ struct BandRun {
         int *d_rank = nullptr;
         // [A: max_blocks][B: max_blocks + 1][R0][Xm][Bm][Bacc][C2: 2]
         const size_t nT = (size_t)(2 * max_blocks + 7) * PP;
-        MCD_HIP(dmalloc((void **)&dT, nT * sizeof(double), Alloc{s, true}));
-        MCD_HIP(dmalloc((void **)&d_rank, (size_t)(max_blocks + 2) * sizeof(int), Alloc{s, true}));
+        MCD_HIP(dmalloc((void **)&dT, nT * sizeof(double), al));
+        MCD_HIP(dmalloc((void **)&d_rank, (size_t)(max_blocks + 2) * sizeof(int), al));
         double *dA = dT, *dB = dA + (size_t)max_blocks * PP, *dR0 = dB + (size_t)(max_blocks + 1) * PP;
         double *dXm = dR0 + PP, *dBm = dXm + PP, *dBacc = dBm + PP, *dC2 = dBacc + PP;
         auto fail = [&](int rc) {
-            (void)dfree(dT, Alloc{s, true});
-            (void)dfree(d_rank, Alloc{s, true});
+            (void)dfree(dT, al);
+            (void)dfree(d_rank, al);
             return rc;
         };
 #define DTRY(expr)           \
@@ -963,17 +964,26 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
                        bool store_all = false, const SectorHook<T> *hook = nullptr,
                        const std::vector<cplx> *zcheck = nullptr) {
     const Alloc A{s, true};   // stream-ordered buffers (no device-wide sync on free)
+    // the operator and the run's buffers: one arena, released at the end
+    Arena arena(s);
+    const Alloc AR{s, true, &arena};
     uint64_t *img = nullptr, *srt = nullptr, *uniq = nullptr;
     int64_t *d_nu = nullptr;
     void *tmp = nullptr;
     mcd_op *op = nullptr;
     BandRun<T> run;
-    auto cleanup = [&]() {
-        for (void *p : {(void *)img, (void *)srt, (void *)uniq, (void *)d_nu, tmp, (void *)run.Qs,
-                        (void *)run.W, (void *)run.W2, (void *)run.part, (void *)run.dC,
-                        (void *)run.dG, (void *)run.colbuf})
+    auto free_images = [&]() {
+        for (void *p : {(void *)img, (void *)srt, (void *)uniq, (void *)d_nu, tmp})
             if (p) (void)dfree(p, A);
+        img = srt = uniq = nullptr;
+        d_nu = nullptr;
+        tmp = nullptr;
+    };
+    auto cleanup = [&]() {
+        free_images();
         if (op) mcd_op_destroy(op);
+        op = nullptr;
+        arena.release();
     };
 #define CK(expr)                                                              \
     do {                                                                      \
@@ -1023,13 +1033,15 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
         cleanup();
         return MCD_OK;
     }
-    TRY(op_create(model, uniq, nu, cfg->storage, 0, cfg->per_column != 0, s, &op, true));
+    TRY(op_create(model, uniq, nu, cfg->storage, 0, cfg->per_column != 0, s, &op, true, &arena));
+    free_images();   // the operator holds its own copy of the keys
     // Storage for the Krylov blocks.
     const int reorth = std::max(0, std::min(2, (int)cfg->reorth));
     run.op = op;
     run.P = P;
     run.n = nu;
     run.s = s;
+    run.al = AR;
     run.nstore = (reorth > 0 || store_all) ? cfg->max_blocks + 1 : 3;
     size_t fr = 0, tot = 0;
     CK(hipMemGetInfo(&fr, &tot));
@@ -1040,19 +1052,19 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
                   need / 1e9, fr / 1e9);
         return MCD_E_CAPACITY;
     }
-    CK(dmalloc((void **)&run.Qs, (size_t)run.nstore * nu * P * sizeof(T), A));
-    CK(dmalloc((void **)&run.W, (size_t)nu * P * sizeof(T), A));
-    if (!(cfg->per_column != 0)) CK(dmalloc((void **)&run.W2, (size_t)nu * P * sizeof(T), A));
+    CK(dmalloc((void **)&run.Qs, (size_t)run.nstore * nu * P * sizeof(T), AR));
+    CK(dmalloc((void **)&run.W, (size_t)nu * P * sizeof(T), AR));
+    if (!(cfg->per_column != 0)) CK(dmalloc((void **)&run.W2, (size_t)nu * P * sizeof(T), AR));
     run.per_column = cfg->per_column != 0;
     run.g_tol = cfg->g_tol;
     run.p_sel = sel.n;
     if (zcheck) run.zcheck = *zcheck;
-    if (run.per_column) CK(dmalloc((void **)&run.colbuf, (size_t)2 * nu * sizeof(T), A));
+    if (run.per_column) CK(dmalloc((void **)&run.colbuf, (size_t)2 * nu * sizeof(T), AR));
     run.part_cap = (int64_t)65536 * P * P + (int64_t)(cfg->max_blocks + 1) * P * P;
-    CK(dmalloc((void **)&run.part, run.part_cap * sizeof(double), A));
+    CK(dmalloc((void **)&run.part, run.part_cap * sizeof(double), AR));
     run.coef_cap = (int64_t)(cfg->max_blocks + 1) * P * P;
-    CK(dmalloc((void **)&run.dC, run.coef_cap * sizeof(double), A));
-    CK(dmalloc((void **)&run.dG, run.coef_cap * sizeof(double), A));
+    CK(dmalloc((void **)&run.dC, run.coef_cap * sizeof(double), AR));
+    CK(dmalloc((void **)&run.dG, run.coef_cap * sizeof(double), AR));
     // start block (into W, then orthonormalised into Q_0)
     CK(hipMemsetAsync(run.W, 0, (size_t)nu * P * sizeof(T), s));
     hipLaunchKernelGGL((k_start_block<T>), dim3(gridn(nt, 256)), dim3(256), 0, s, nt, keys_t,
@@ -1061,12 +1073,12 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
     // the start block lives in W; qr() reads W and writes Q_0 (W is reused as
     // scratch only when source and destination coincide, not here)
     T *phi = nullptr;
-    CK(dmalloc((void **)&phi, (size_t)nu * P * sizeof(T), A));
+    CK(dmalloc((void **)&phi, (size_t)nu * P * sizeof(T), AR));
     CK(hipMemcpyAsync(phi, run.W, (size_t)nu * P * sizeof(T), hipMemcpyDeviceToDevice, s));
     const double dtol_abs = cfg->dtol * dtol_scale;
     int rc = run.per_column ? run.run(phi, cfg->max_blocks, dtol_abs, reorth, br)
                             : run.run_dev(phi, cfg->max_blocks, dtol_abs, reorth, br);
-    (void)dfree(phi, A);
+    (void)dfree(phi, AR);
     if (rc < 0) {
         cleanup();
         return rc;
@@ -1117,7 +1129,8 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
                       const double *omega, const mcd_band_cfg *cfg, double *G_out, double *Gp_out,
                       double *Gm_out, mcd_solve_info *info, hipStream_t s,
                       bool concurrent_sectors) {
-    const Alloc A{s, true};   // stream-ordered buffers (no device-wide sync on free)
+    Arena arena(s);
+    const Alloc A{s, true, &arena};   // stream-ordered, released together
     const double t0 = wall_ms();
     {
         int dev = 0;

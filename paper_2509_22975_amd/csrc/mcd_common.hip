@@ -8,12 +8,107 @@
 #include <map>
 #include <mutex>
 #include <utility>
+#include <vector>
 
 #include "mcd_internal.h"
 
 namespace mcd {
 
 static thread_local char g_err[1024] = "";
+
+namespace {
+struct CachedChunk {
+    char *p;
+    size_t bytes;
+    int dev;
+    hipEvent_t ready;   // recorded on the releasing stream
+};
+std::mutex g_chunk_mu;
+std::vector<CachedChunk> g_chunks;   // free chunks
+size_t g_chunk_bytes = 0;            // bytes held by g_chunks
+}  // namespace
+
+hipError_t chunk_acquire(size_t bytes, hipStream_t s, void **out, size_t *got) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    {
+        std::lock_guard<std::mutex> lock(g_chunk_mu);
+        int best = -1;
+        for (int i = 0; i < (int)g_chunks.size(); i++) {
+            const CachedChunk &c = g_chunks[i];
+            if (c.dev != dev || c.bytes < bytes || c.bytes > 2 * bytes + (size_t(64) << 20))
+                continue;
+            if (best < 0 || c.bytes < g_chunks[best].bytes) best = i;
+        }
+        if (best >= 0) {
+            const CachedChunk c = g_chunks[best];
+            g_chunks.erase(g_chunks.begin() + best);
+            g_chunk_bytes -= c.bytes;
+            e = hipStreamWaitEvent(s, c.ready, 0);
+            (void)hipEventDestroy(c.ready);
+            if (e != hipSuccess) {
+                (void)hipFree(c.p);
+                return e;
+            }
+            *out = c.p;
+            *got = c.bytes;
+            return hipSuccess;
+        }
+    }
+    const size_t unit = size_t(64) << 20;
+    const size_t sz = (std::max<size_t>(bytes, 1) + unit - 1) / unit * unit;
+    e = hipMalloc(out, sz);
+    if (e != hipSuccess) {
+        // free this device's cached chunks once, then retry
+        (void)hipGetLastError();
+        std::vector<CachedChunk> mine;
+        {
+            std::lock_guard<std::mutex> lock(g_chunk_mu);
+            for (auto it = g_chunks.begin(); it != g_chunks.end();) {
+                if (it->dev == dev) {
+                    mine.push_back(*it);
+                    g_chunk_bytes -= it->bytes;
+                    it = g_chunks.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+        }
+        for (auto &c : mine) {
+            (void)hipEventSynchronize(c.ready);
+            (void)hipEventDestroy(c.ready);
+            (void)hipFree(c.p);
+        }
+        e = hipMalloc(out, sz);
+    }
+    if (e == hipSuccess) *got = sz;
+    return e;
+}
+
+void chunk_release(void *p, size_t bytes, hipStream_t s) {
+    int dev = 0;
+    hipEvent_t ev = nullptr;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(ev, s) != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        if (ev) (void)hipEventDestroy(ev);
+        (void)hipFree(p);
+        return;
+    }
+    {
+        std::lock_guard<std::mutex> lock(g_chunk_mu);
+        if (g_chunk_bytes + bytes <= kChunkCacheBytes) {
+            g_chunks.push_back({(char *)p, bytes, dev, ev});
+            g_chunk_bytes += bytes;
+            return;
+        }
+    }
+    (void)hipEventSynchronize(ev);
+    (void)hipEventDestroy(ev);
+    (void)hipFree(p);
+}
 
 void pool_keep_freed(int device) {
     static std::mutex mu;

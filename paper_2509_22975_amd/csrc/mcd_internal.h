@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include <string.h>
@@ -96,14 +98,59 @@ struct DevModel {
 // stream (hipFreeAsync), so solves running concurrently on different streams
 // never synchronise the whole device when they release memory; otherwise
 // hipMalloc / hipFree.
+// Process-wide cache of device memory chunks (mcd_common.hip).  A released
+// chunk keeps an event recorded on the releasing stream; the next stream to
+// take it waits on that event, so reuse is stream-ordered without a device
+// synchronisation.  Chunks are sized in multiples of 64 MB; at most
+// kChunkCacheBytes stay cached (beyond that a released chunk is freed).
+constexpr size_t kChunkCacheBytes = size_t(8) << 30;
+hipError_t chunk_acquire(size_t bytes, hipStream_t s, void **out, size_t *got);
+void chunk_release(void *p, size_t bytes, hipStream_t s);
+
+// Bump allocator over cached chunks: every buffer of a short-lived solve (a
+// band run and its operator) comes from it and all go back together, with
+// no driver allocation or free per buffer (hipMallocAsync / hipFreeAsync
+// cost 0.1-1 ms of host time each here).  Pieces are 256-byte aligned;
+// freeing a piece does nothing.  One owner thread.
+struct Arena {
+    hipStream_t s = nullptr;
+    std::vector<std::pair<char *, size_t>> chunks;
+    size_t used = 0;   // bytes taken from the last chunk
+    explicit Arena(hipStream_t st) : s(st) {}
+    Arena(const Arena &) = delete;
+    Arena &operator=(const Arena &) = delete;
+    ~Arena() { release(); }
+    hipError_t get(void **p, size_t bytes) {
+        bytes = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+        if (chunks.empty() || used + bytes > chunks.back().second) {
+            void *c = nullptr;
+            size_t got = 0;
+            const hipError_t e = chunk_acquire(bytes, s, &c, &got);
+            if (e != hipSuccess) return e;
+            chunks.emplace_back((char *)c, got);
+            used = 0;
+        }
+        *p = chunks.back().first + used;
+        used += bytes;
+        return hipSuccess;
+    }
+    void release() {
+        for (auto &c : chunks) chunk_release(c.first, c.second, s);
+        chunks.clear();
+        used = 0;
+    }
+};
 struct Alloc {
     hipStream_t s = nullptr;
     bool async = false;
+    Arena *arena = nullptr;
 };
 inline hipError_t dmalloc(void **p, size_t bytes, const Alloc &a) {
+    if (a.arena) return a.arena->get(p, bytes);
     return a.async ? hipMallocAsync(p, bytes, a.s) : hipMalloc(p, bytes);
 }
 inline hipError_t dfree(void *p, const Alloc &a) {
+    if (a.arena) return hipSuccess;
     return a.async ? hipFreeAsync(p, a.s) : hipFree(p);
 }
 // Once per device: let the default stream-ordered memory pool keep up to
@@ -205,8 +252,11 @@ int grouped_one(const mcd_op *op, bool xcd, const T *x, T *y, const double *sx_d
 // async: buffers stream-ordered on `stream` (the operator must then only be
 // used on that stream; mcd_op_destroy releases them on it without a device
 // synchronisation).
+// arena: when given (async only), every buffer of the operator comes from it
+// and stays until the arena is released (after mcd_op_destroy).
 int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32_t storage,
-              int32_t validate, bool tune, void *stream, mcd_op **out, bool async = false);
+              int32_t validate, bool tune, void *stream, mcd_op **out, bool async = false,
+              Arena *arena = nullptr);
 
 // Deterministic dot product a . b into *out_dev (mcd_lanczos.hip).
 int dev_dot(const mcd_op *op, const double *a, const double *b, int64_t n, double *out_dev,

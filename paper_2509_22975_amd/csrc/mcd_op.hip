@@ -885,7 +885,7 @@ int apply_f64_fused(const mcd_op *op, const double *x, double *y, const double *
 // (operators that only ever see block products skip it and keep the
 // XCD-major stream kernel for the rare one-vector product).
 int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32_t storage,
-              int32_t validate, bool tune, void *stream, mcd_op **out, bool async) {
+              int32_t validate, bool tune, void *stream, mcd_op **out, bool async, Arena *arena) {
     MCD_REQUIRE(out != nullptr, MCD_E_INVALID, "out is NULL");
     *out = nullptr;
     MCD_REQUIRE(n >= 0 && (n == 0 || keys_dev != nullptr), MCD_E_INVALID, "bad keys/n");
@@ -897,6 +897,7 @@ int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32
     memset(op, 0, sizeof(*op));
     op->alloc.s = s;
     op->alloc.async = async;
+    op->alloc.arena = async ? arena : nullptr;
     auto fail = [&](int rc) {
         mcd_op_destroy(op);
         return rc;
