@@ -15,6 +15,7 @@
 //                   block into LDS products, then each row sums its run
 //   k_apply_group   nvec vectors (row-major): nvec lanes per row, each lane
 //                   one column of the block; CSR or on-the-fly elements
+//   k_block_csr(_v) nvec vectors from the CSR; _v gathers 16 bytes per lane
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
@@ -545,6 +546,93 @@ __global__ __launch_bounds__(256) void k_block_csr(
     }
 }
 
+// Vector types of one 16-byte gather.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using type = float4;
+    static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+    using type = double2;
+    static constexpr int n = 2;
+};
+__device__ __forceinline__ float4 vscale(float a, const float4 &x) {
+    return make_float4(a * x.x, a * x.y, a * x.z, a * x.w);
+}
+__device__ __forceinline__ double2 vscale(double a, const double2 &x) {
+    return make_double2(a * x.x, a * x.y);
+}
+__device__ __forceinline__ void vscale_add(float4 &acc, float a, const float4 &x) {
+    acc.x += a * x.x;
+    acc.y += a * x.y;
+    acc.z += a * x.z;
+    acc.w += a * x.w;
+}
+__device__ __forceinline__ void vscale_add(double2 &acc, double a, const double2 &x) {
+    acc.x += a * x.x;
+    acc.y += a * x.y;
+}
+
+// k_block_csr with 16-byte gathers: L = NV / (16 / sizeof(T)) lanes per row,
+// each lane 16 bytes of the gathered row (float4 / double2), so one gather
+// instruction covers 4 / L times more rows; the same terms are added in the
+// same order per column as in k_block_csr (bit-identical y).  X and Y
+// 16-byte aligned.
+template <typename T, int NV, int CH>
+__global__ __launch_bounds__(256) void k_block_csr_v(
+    int64_t n, const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ colw,
+    const DevModel *__restrict__ m, const double *__restrict__ diag, const T *__restrict__ x,
+    T *__restrict__ y, int64_t ntiles, int rows_per_tile) {
+    using V = typename Vec16<T>::type;
+    constexpr int L = NV / Vec16<T>::n;
+    static_assert(L >= 1 && L * Vec16<T>::n == NV, "NV must be a multiple of the vector width");
+    __shared__ T vtab[kMaxClasses];
+    if (threadIdx.x < kMaxClasses) vtab[threadIdx.x] = (T)m->vtab[threadIdx.x];
+    __syncthreads();
+    const uint32_t cmask = m->col_mask, cbits = m->col_bits;
+    constexpr int RPB = 256 / L;
+    constexpr int WPL = (CH + L - 1) / L;
+    const int64_t per = (ntiles + kNumXcd - 1) / kNumXcd;
+    const int64_t tile = (int64_t)(blockIdx.x % kNumXcd) * per + blockIdx.x / kNumXcd;
+    if (tile >= ntiles) return;
+    const int lane = threadIdx.x % L;
+    const V *__restrict__ xv4 = reinterpret_cast<const V *>(x);
+    V *__restrict__ yv4 = reinterpret_cast<V *>(y);
+    const int64_t rbeg = tile * rows_per_tile;
+    const int64_t rend = min(rbeg + (int64_t)rows_per_tile, n);
+    for (int64_t r = rbeg + threadIdx.x / L; r < rend; r += RPB) {
+        const T d = (T)diag[r];
+        V acc = vscale(d, xv4[r * L + lane]);
+        const int64_t e1 = rowptr[r + 1];
+        for (int64_t base = rowptr[r]; base < e1; base += CH) {
+            uint32_t mw[WPL];
+#pragma unroll
+            for (int q = 0; q < WPL; q++) {
+                const int64_t e = base + q * L + lane;
+                mw[q] = (q * L + lane < CH && e < e1) ? colw[e] : 0u;
+            }
+            uint32_t wj[CH];
+            V xg[CH];
+#pragma unroll
+            for (int j = 0; j < CH; j++) {
+                wj[j] = (uint32_t)__shfl((int)mw[j / L], j % L, L);
+                xg[j] = (base + j < e1) ? xv4[(int64_t)(wj[j] & cmask) * L + lane] : V{};
+            }
+#pragma unroll
+            for (int j = 0; j < CH; j++) {
+                if (base + j < e1) {
+                    const T v = vtab[(wj[j] & 0x7fffffffu) >> cbits];
+                    vscale_add(acc, (wj[j] >> 31) ? -v : v, xg[j]);
+                }
+            }
+        }
+        yv4[r * L + lane] = acc;
+    }
+}
+
 __global__ void k_conn_count(int64_t row0, int64_t row1, const uint64_t *__restrict__ keys,
                              const DevModel *__restrict__ m, const HashSlot *__restrict__ h,
                              uint64_t hmask, int64_t *__restrict__ cnt) {
@@ -806,12 +894,49 @@ static int tune_kernel(mcd_op *op, hipStream_t s) {
     return MCD_OK;
 }
 
+// Block CSR product with 16-byte gathers (k_block_csr_v), when a row of the
+// block is a whole number of them: tiles of max(64, rows per pass / 2) rows
+// (measured best for float and double at 8 and 16 vectors).
+template <typename T, int NV>
+static void launch_block_v(const mcd_op *op, const T *x, T *y, hipStream_t s) {
+    if constexpr (NV % Vec16<T>::n == 0) {
+        constexpr int L = NV / Vec16<T>::n;
+        const int rpt = std::max(64, (256 / L) / 2);
+        const int64_t n = op->n;
+        const int64_t ntiles = (n + rpt - 1) / rpt;
+        const unsigned grid = (unsigned)(kNumXcd * ((ntiles + kNumXcd - 1) / kNumXcd));
+        if (op->group_chunk == 4)
+            hipLaunchKernelGGL((k_block_csr_v<T, NV, 4>), dim3(grid), dim3(256), 0, s, n,
+                               op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x, y, ntiles,
+                               rpt);
+        else if (op->group_chunk == 8)
+            hipLaunchKernelGGL((k_block_csr_v<T, NV, 8>), dim3(grid), dim3(256), 0, s, n,
+                               op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x, y, ntiles,
+                               rpt);
+        else
+            hipLaunchKernelGGL((k_block_csr_v<T, NV, 16>), dim3(grid), dim3(256), 0, s, n,
+                               op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x, y, ntiles,
+                               rpt);
+    }
+}
+
 template <typename T>
 static int launch_apply(const mcd_op *op, int nvec, const T *x, T *y, hipStream_t s) {
     const bool otf = op->storage == MCD_STORAGE_ON_THE_FLY;
     const int64_t n = op->n;
     if (n == 0) return MCD_OK;
     if (!otf && nvec == 1) return csr_one<T>(op, x, y, nullptr, 0, nullptr, s);
+    const bool aligned16 = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15u) == 0;
+    if (!otf && aligned16 && nvec % Vec16<T>::n == 0 && (nvec == 2 || nvec == 4 || nvec == 8 || nvec == 16)) {
+        switch (nvec) {
+            case 2: launch_block_v<T, 2>(op, x, y, s); break;
+            case 4: launch_block_v<T, 4>(op, x, y, s); break;
+            case 8: launch_block_v<T, 8>(op, x, y, s); break;
+            case 16: launch_block_v<T, 16>(op, x, y, s); break;
+        }
+        MCD_HIP(hipGetLastError());
+        return MCD_OK;
+    }
     // row tile per workgroup: 4 passes of 256/NV rows (>= 64 rows)
 #define MCD_GROUP(NV)                                                                          \
     case NV: {                                                                                 \
