@@ -347,6 +347,8 @@ int build_grouped(mcd_op *op, hipStream_t s) {
     op->g_nblocks = 0;
     const int64_t n = op->n, nnz = op->nnz;
     if (n == 0 || nnz <= 0 || nnz >= (int64_t(1) << 31)) return MCD_OK;
+    // a down-hop word holds a 3-bit amplitude class
+    if (op->hm.dm.n_classes > 8) return MCD_OK;
     const Alloc &al = op->alloc;
     // Temporaries are released on every path.
     void *tmp[32] = {};
