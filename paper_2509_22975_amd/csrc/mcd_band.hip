@@ -1392,6 +1392,78 @@ __global__ __launch_bounds__(64 * kCWaves) void k_contract_multi(
     }
 }
 
+// Row-major copy of a Krylov store: Xt[r][k P + a] = X[k][r][a] (nk blocks of
+// n x P).  One thread per (row, block) moves the P contiguous values.
+template <typename T>
+__global__ void k_to_rows(int64_t n, int nk, int P, const T *__restrict__ X, T *__restrict__ Xt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * nk) return;
+    const int64_t r = i % n, k = i / n;
+    const T *__restrict__ src = X + (k * n + r) * P;
+    T *__restrict__ dst = Xt + r * (int64_t)nk * P + k * P;
+    for (int a = 0; a < P; a++) dst[a] = src[a];
+}
+
+// k_contract_multi on row-major copies (Lt, Rt: [n][KP]): a hop's dot reads
+// two contiguous rows of KP values (about four times fewer cache lines than
+// the block-major store, where a row is KP / P pieces of P values).  Same
+// hop enumeration, terms and reduction order per row as k_contract_multi.
+template <typename T>
+__global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
+    int64_t n, const uint64_t *__restrict__ keys, const DevModel *__restrict__ m,
+    const HashSlot *__restrict__ h, uint64_t hmask, const T *__restrict__ Lt,
+    const T *__restrict__ Rt, int KP, double *__restrict__ part) {
+    __shared__ double acc[kCWaves][kMaxParams];
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nb = m->n_bonds, no = m->n_orb, np = nb + 2 * no;
+    for (int i = lane; i < np; i += 64) acc[wid][i] = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * kCWaves + wid; r < n;
+         r += (int64_t)gridDim.x * kCWaves) {
+        const uint64_t key = keys[r];
+        const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
+        const T *__restrict__ lr = Lt + r * (int64_t)KP;
+        auto rowdot = [&](int64_t col) {
+            const T *__restrict__ rc = Rt + col * (int64_t)KP;
+            double s = 0.0;
+            for (int a = lane; a < KP; a += 64) s += (double)lr[a] * (double)rc[a];
+            return wave_sum(s);
+        };
+        for (int q = 0; q < nb; q++) {
+            const uint32_t mask = m->bonds[q].mask, between = m->bonds[q].between;
+            double c = 0.0;
+            if (__popc(up & mask) == 1) {
+                const int64_t col = hash_find(h, hmask, key ^ ((uint64_t)mask << 32));
+                if (col >= 0) {
+                    const double d = rowdot(col);
+                    c += (__popc(up & between) & 1) ? -d : d;
+                }
+            }
+            if (__popc(dn & mask) == 1) {
+                const int64_t col = hash_find(h, hmask, key ^ (uint64_t)mask);
+                if (col >= 0) {
+                    const double d = rowdot(col);
+                    c += (__popc(dn & between) & 1) ? -d : d;
+                }
+            }
+            if (lane == 0) acc[wid][q] += c;
+        }
+        const double d = rowdot(r);
+        if (lane == 0) {
+            for (int i = 0; i < no; i++) {
+                const double nu = (double)((up >> i) & 1u), nd = (double)((dn >> i) & 1u);
+                acc[wid][nb + i] += nu * nd * d;
+                acc[wid][nb + no + i] += (nu + nd) * d;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < np; i += 64 * kCWaves) {
+        double s = 0.0;
+        for (int w = 0; w < kCWaves; w++) s += acc[w][i];
+        part[(int64_t)i * gridDim.x + blockIdx.x] = s;
+    }
+}
+
 // out[p] (+)= sum_c part[p * nblk + c]: one wavefront per parameter.
 __global__ __launch_bounds__(256) void k_param_reduce(int np, int nblk,
                                                       const double *__restrict__ part,
@@ -1607,12 +1679,32 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             }
             if (rc == MCD_OK) {
                 const unsigned g = (unsigned)std::min<int64_t>(cblk, (nx + kCWaves - 1) / kCWaves);
-                hipLaunchKernelGGL((k_contract_multi<T>), dim3(g), dim3(64 * kCWaves), 0, s, nx,
-                                   op->d_keys, op->d_model, op->d_hash, op->hash_mask, run.blk(0),
-                                   Z, m, P, part);
+                // row-major copies of Q and Z for the contraction when memory
+                // allows (else the block-major form)
+                T *Qt = nullptr, *Zt = nullptr;
+                size_t fr = 0, tot = 0;
+                const size_t rows_bytes = (size_t)m * nx * P * sizeof(T);
+                if (hipMemGetInfo(&fr, &tot) == hipSuccess && 2.0 * rows_bytes < 0.5 * (double)fr &&
+                    dmalloc((void **)&Qt, rows_bytes, A) == hipSuccess &&
+                    dmalloc((void **)&Zt, rows_bytes, A) == hipSuccess) {
+                    const unsigned gt = gridn(nx * m, 256);
+                    hipLaunchKernelGGL((k_to_rows<T>), dim3(gt), dim3(256), 0, s, nx, m, P,
+                                       run.blk(0), Qt);
+                    hipLaunchKernelGGL((k_to_rows<T>), dim3(gt), dim3(256), 0, s, nx, m, P, Z, Zt);
+                    hipLaunchKernelGGL((k_contract_rows<T>), dim3(g), dim3(64 * kCWaves), 0, s, nx,
+                                       op->d_keys, op->d_model, op->d_hash, op->hash_mask, Qt, Zt,
+                                       m * P, part);
+                } else {
+                    (void)hipGetLastError();
+                    hipLaunchKernelGGL((k_contract_multi<T>), dim3(g), dim3(64 * kCWaves), 0, s,
+                                       nx, op->d_keys, op->d_model, op->d_hash, op->hash_mask,
+                                       run.blk(0), Z, m, P, part);
+                }
                 hipLaunchKernelGGL(k_param_reduce, dim3((np + 3) / 4), dim3(256), 0, s, np, (int)g,
                                    part, acc, 1);
                 if (hipGetLastError() != hipSuccess) rc = MCD_E_HIP;
+                if (Qt) (void)dfree(Qt, A);
+                if (Zt) (void)dfree(Zt, A);
             }
             // W = Q Omega (into run.W), then lam += map^T W
             if (rc == MCD_OK) {
