@@ -295,6 +295,71 @@ __global__ __launch_bounds__(BS) void k_block_apply(int64_t n, int nm, const T *
     }
 }
 
+// k_block_apply with one thread per row (P >= 4): the row's P values of each
+// block come in 16-byte loads and are converted once, the P outputs are
+// accumulated in registers.  Each output receives the same terms in the same
+// (m, a) order as k_block_apply, so the results are bit-identical.
+template <typename T, int P>
+__global__ __launch_bounds__(BS) void k_block_apply_r(int64_t n, int nm, const T *__restrict__ Q0,
+                                                      int64_t qstride, const double *__restrict__ C,
+                                                      T *__restrict__ W, int sub) {
+    static_assert(P * sizeof(T) % 16 == 0, "row of P values must be whole 16-byte units");
+    constexpr int U = 16 / sizeof(T);
+    using V16 = T __attribute__((ext_vector_type(16 / sizeof(T))));
+    extern __shared__ double sC[];
+    for (int e = threadIdx.x; e < nm * P * P; e += BS) sC[e] = C[e];
+    __syncthreads();
+    for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * BS) {
+        double acc[P];
+#pragma unroll
+        for (int b = 0; b < P; b++) acc[b] = 0.0;
+        for (int m = 0; m < nm; m++) {
+            const V16 *__restrict__ q = (const V16 *)(Q0 + (int64_t)m * qstride + r * P);
+            V16 qv[P / U];
+#pragma unroll
+            for (int u = 0; u < P / U; u++) qv[u] = q[u];
+            const double *__restrict__ c = sC + m * P * P;
+#pragma unroll
+            for (int a = 0; a < P; a++) {
+                const double qa = (double)qv[a / U][a % U];
+#pragma unroll
+                for (int b = 0; b < P; b++) acc[b] += qa * c[a * P + b];
+            }
+        }
+        V16 *__restrict__ w = (V16 *)(W + r * P);
+#pragma unroll
+        for (int u = 0; u < P / U; u++) {
+            V16 o;
+            if (sub) {
+                const V16 wv = w[u];
+#pragma unroll
+                for (int e = 0; e < U; e++) o[e] = (T)((double)wv[e] - acc[u * U + e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < U; e++) o[e] = (T)acc[u * U + e];
+            }
+            w[u] = o;
+        }
+    }
+}
+
+// W (-)= sum_m Q_m C_m for nm blocks (C on the device), one launch.
+template <typename T, int P>
+static void launch_block_apply(int64_t n, int nm, const T *Q0, const double *C, T *W, bool sub,
+                               hipStream_t s) {
+    const size_t lds = (size_t)nm * P * P * sizeof(double);
+    if constexpr (P * sizeof(T) % 16 == 0) {
+        const unsigned nb = (unsigned)std::min<int64_t>(gridn(n, BS), 8192);
+        hipLaunchKernelGGL((k_block_apply_r<T, P>), dim3(nb), dim3(BS), lds, s, n, nm, Q0,
+                           (int64_t)n * P, C, W, sub ? 1 : 0);
+    } else {
+        const unsigned nb = (unsigned)std::min<int64_t>(gridn(n, BS / P), 4096);
+        hipLaunchKernelGGL((k_block_apply<T, P>), dim3(nb), dim3(BS), lds, s, n, nm, Q0,
+                           (int64_t)n * P, C, W, sub ? 1 : 0);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host small linear algebra (float64 / complex128, P <= 16).
 // Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (row-major):
@@ -649,13 +714,11 @@ struct BandRun {
         MCD_REQUIRE(sub || nm <= group, MCD_E_INVALID, "assigning block product must use one group");
         for (int g0 = 0; g0 < nm; g0 += group) {
             const int g = std::min(group, nm - g0);
-            const unsigned nb = (unsigned)std::min<int64_t>(gridn(n, BS / P), 4096);
             const T *q = Q0 + (int64_t)g0 * n * P;
             const double *c = C + (size_t)g0 * PP;
-#define BAD(PV)                                                                              \
-    case PV:                                                                                 \
-        hipLaunchKernelGGL((k_block_apply<T, PV>), dim3(nb), dim3(BS), g * PP * sizeof(double), \
-                           s, n, g, q, (int64_t)n * P, c, Wout, sub ? 1 : 0);                \
+#define BAD(PV)                                                     \
+    case PV:                                                        \
+        launch_block_apply<T, PV>(n, g, q, c, Wout, sub, s);        \
         break;
             switch (P) {
                 BAD(1) BAD(2) BAD(4) BAD(8) BAD(16)
@@ -674,12 +737,10 @@ struct BandRun {
             const int g = std::min(group, nm - g0);
             MCD_HIP(hipMemcpyAsync(dC, C.data() + (size_t)g0 * PP, (size_t)g * PP * sizeof(double),
                                    hipMemcpyHostToDevice, s));
-            const unsigned nb = (unsigned)std::min<int64_t>(gridn(n, BS / P), 4096);
             const T *q = Q0 + (int64_t)g0 * n * P;
-#define BA(PV)                                                                               \
-    case PV:                                                                                 \
-        hipLaunchKernelGGL((k_block_apply<T, PV>), dim3(nb), dim3(BS), g * PP * sizeof(double), \
-                           s, n, g, q, (int64_t)n * P, dC, Wout, sub ? 1 : 0);               \
+#define BA(PV)                                                      \
+    case PV:                                                        \
+        launch_block_apply<T, PV>(n, g, q, dC, Wout, sub, s);       \
         break;
             switch (P) {
                 BA(1) BA(2) BA(4) BA(8) BA(16)
@@ -1392,27 +1453,112 @@ __global__ __launch_bounds__(64 * kCWaves) void k_contract_multi(
     }
 }
 
-// Row-major copy of a Krylov store: Xt[r][k P + a] = X[k][r][a] (nk blocks of
-// n x P).  One thread per (row, block) moves the P contiguous values.
+// Row-major copy of a Krylov store: Xt[r][k P + a] = X[k][r][a] for the nk
+// blocks of n x P, and zero for k P + a in [nk P, S) (S a multiple of P).  One
+// thread per (row, block); consecutive threads fill one row.
 template <typename T>
-__global__ void k_to_rows(int64_t n, int nk, int P, const T *__restrict__ X, T *__restrict__ Xt) {
+__global__ void k_to_rows(int64_t n, int nk, int P, int S, const T *__restrict__ X,
+                          T *__restrict__ Xt) {
+    const int kS = S / P;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * nk) return;
-    const int64_t r = i % n, k = i / n;
-    const T *__restrict__ src = X + (k * n + r) * P;
-    T *__restrict__ dst = Xt + r * (int64_t)nk * P + k * P;
-    for (int a = 0; a < P; a++) dst[a] = src[a];
+    if (i >= n * kS) return;
+    const int64_t r = i / kS;
+    const int k = (int)(i - r * kS);
+    T *__restrict__ dst = Xt + r * S + (int64_t)k * P;
+    if (k < nk) {
+        const T *__restrict__ src = X + ((int64_t)k * n + r) * P;
+        for (int a = 0; a < P; a++) dst[a] = src[a];
+    } else {
+        for (int a = 0; a < P; a++) dst[a] = (T)0;
+    }
 }
 
-// k_contract_multi on row-major copies (Lt, Rt: [n][KP]): a hop's dot reads
-// two contiguous rows of KP values (about four times fewer cache lines than
+// Zt = Qt M for the adjoint's Z = Q M: Qt [n][S] and M [S][S] row-major,
+// S a multiple of 128 (zero rows and columns past the Krylov dimension).  A
+// workgroup of four wavefronts makes one 128 x 128 tile of Zt, each wavefront
+// a 64 x 64 quarter as 4 x 4 MFMA 16x16x4 products (float32 or float64 in,
+// same type accumulated), with both operands staged through LDS in steps of
+// 128 bytes of k.  Tiles are handed out XCD-major, so the S / 128 column tiles
+// of one row tile run on one XCD and share its L2 copy of the Qt rows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rows_times(int64_t n, int S, const T *__restrict__ Qt,
+                                                   const T *__restrict__ M, T *__restrict__ Zt) {
+    constexpr int BM = 128, BN = 128, U = 16 / sizeof(T), BK = 8 * U;
+    constexpr int LA = BK + U, LB = BN + 4 * U;   // padded LDS rows (conflict-free reads)
+    using V16 = T __attribute__((ext_vector_type(16 / sizeof(T))));
+    using V4 = T __attribute__((ext_vector_type(4)));
+    __shared__ __attribute__((aligned(16))) T As[BM * LA];   // As[row][k]
+    __shared__ __attribute__((aligned(16))) T Bs[BK * LB];   // Bs[k][col]
+    const int ntc = S / BN;
+    const int64_t ntr = (n + BM - 1) / BM, G = ntr * ntc, Gp = (G + 7) / 8 * 8;
+    const int64_t t = (int64_t)(blockIdx.x % 8) * (Gp / 8) + blockIdx.x / 8;
+    if (t >= G) return;   // whole workgroup, before any barrier
+    const int64_t r0 = (t / ntc) * BM;
+    const int c0 = (int)(t % ntc) * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wr = (wid >> 1) * 64, wc = (wid & 1) * 64;
+    const int li = lane & 15, lk = lane >> 4;
+    V4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = (V4)(T)0;
+    for (int k0 = 0; k0 < S; k0 += BK) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {   // A: 128 rows x 8 units of 16 bytes
+            const int e = tid + q * 256, row = e >> 3, ku = (e & 7) * U;
+            const int64_t r = r0 + row;
+            V16 v = (V16)(T)0;
+            if (r < n) v = *(const V16 *)(Qt + r * S + k0 + ku);
+            *(V16 *)(As + row * LA + ku) = v;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {   // B: BK rows x (BN / U) units
+            const int e = tid + q * 256, kr = e / (BN / U), cu = (e % (BN / U)) * U;
+            *(V16 *)(Bs + kr * LB + cu) = *(const V16 *)(M + (int64_t)(k0 + kr) * S + c0 + cu);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            T a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) a[i] = As[(wr + i * 16 + li) * LA + kk + lk];
+#pragma unroll
+            for (int j = 0; j < 4; j++) b[j] = Bs[(kk + lk) * LB + wc + j * 16 + li];
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    if constexpr (sizeof(T) == 4)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+                    else
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    // value v of a lane is D[4 (lane / 16) + v][lane % 16] of its 16 x 16 product
+    // for float32 and D[lane / 16 + 4 v][lane % 16] for float64
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int64_t r = r0 + wr + i * 16 + (sizeof(T) == 4 ? 4 * lk + v : lk + 4 * v);
+            if (r >= n) continue;
+#pragma unroll
+            for (int j = 0; j < 4; j++) Zt[r * S + c0 + wc + j * 16 + li] = acc[i][j][v];
+        }
+}
+
+// k_contract_multi on row-major copies (Lt, Rt: [n][S], first KP columns
+// used): a hop's dot reads two contiguous rows of KP values (about four times fewer cache lines than
 // the block-major store, where a row is KP / P pieces of P values).  Same
 // hop enumeration, terms and reduction order per row as k_contract_multi.
 template <typename T>
 __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
     int64_t n, const uint64_t *__restrict__ keys, const DevModel *__restrict__ m,
     const HashSlot *__restrict__ h, uint64_t hmask, const T *__restrict__ Lt,
-    const T *__restrict__ Rt, int KP, double *__restrict__ part) {
+    const T *__restrict__ Rt, int KP, int S, double *__restrict__ part) {
     __shared__ double acc[kCWaves][kMaxParams];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nb = m->n_bonds, no = m->n_orb, np = nb + 2 * no;
@@ -1421,9 +1567,9 @@ __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
          r += (int64_t)gridDim.x * kCWaves) {
         const uint64_t key = keys[r];
         const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
-        const T *__restrict__ lr = Lt + r * (int64_t)KP;
+        const T *__restrict__ lr = Lt + r * (int64_t)S;
         auto rowdot = [&](int64_t col) {
-            const T *__restrict__ rc = Rt + col * (int64_t)KP;
+            const T *__restrict__ rc = Rt + col * (int64_t)S;
             double s = 0.0;
             for (int a = lane; a < KP; a += 64) s += (double)lr[a] * (double)rc[a];
             return wave_sum(s);
@@ -1663,48 +1809,60 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             for (int a = 0; a < KP; a++) trM += M[(size_t)a * KP + a];
             krylov += br.krylov;
             const int64_t nx = run.n;
-            T *Z = nullptr;
-            MCD_HIP(dmalloc((void **)&Z, (size_t)m * nx * P * sizeof(T), A));
-            // Z_k = sum_j Q_j M[j-block, k-block]  (W -= sum Q (-C))
             std::vector<double> C((size_t)m * P * P);
             int rc = MCD_OK;
-            for (int k = 0; k < m && rc == MCD_OK; k++) {
-                for (int j = 0; j < m; j++)
-                    for (int a = 0; a < P; a++)
-                        for (int b = 0; b < P; b++)
-                            C[((size_t)j * P + a) * P + b] = -M[((size_t)j * P + a) * KP + k * P + b];
-                T *Zk = Z + (size_t)k * nx * P;
-                if (hipMemsetAsync(Zk, 0, (size_t)nx * P * sizeof(T), s) != hipSuccess) rc = MCD_E_HIP;
-                if (rc == MCD_OK) rc = run.block_apply(run.blk(0), m, C, Zk, true);
-            }
-            if (rc == MCD_OK) {
-                const unsigned g = (unsigned)std::min<int64_t>(cblk, (nx + kCWaves - 1) / kCWaves);
-                // row-major copies of Q and Z for the contraction when memory
-                // allows (else the block-major form)
-                T *Qt = nullptr, *Zt = nullptr;
-                size_t fr = 0, tot = 0;
-                const size_t rows_bytes = (size_t)m * nx * P * sizeof(T);
-                if (hipMemGetInfo(&fr, &tot) == hipSuccess && 2.0 * rows_bytes < 0.5 * (double)fr &&
-                    dmalloc((void **)&Qt, rows_bytes, A) == hipSuccess &&
-                    dmalloc((void **)&Zt, rows_bytes, A) == hipSuccess) {
-                    const unsigned gt = gridn(nx * m, 256);
-                    hipLaunchKernelGGL((k_to_rows<T>), dim3(gt), dim3(256), 0, s, nx, m, P,
-                                       run.blk(0), Qt);
-                    hipLaunchKernelGGL((k_to_rows<T>), dim3(gt), dim3(256), 0, s, nx, m, P, Z, Zt);
+            const unsigned g = (unsigned)std::min<int64_t>(cblk, (nx + kCWaves - 1) / kCWaves);
+            // Z = Q M as one product on row-major copies (Qt, Zt: [nx][S]) when
+            // memory allows, else block by block on the block-major store.
+            const int S = (KP + 127) / 128 * 128;
+            T *Qt = nullptr, *Zt = nullptr, *Md = nullptr, *Z = nullptr;
+            std::vector<T> Mp;
+            size_t fr = 0, tot = 0;
+            const size_t rows_bytes = (size_t)nx * S * sizeof(T);
+            if (hipMemGetInfo(&fr, &tot) == hipSuccess && 2.0 * rows_bytes < 0.5 * (double)fr &&
+                dmalloc((void **)&Qt, rows_bytes, A) == hipSuccess &&
+                dmalloc((void **)&Zt, rows_bytes, A) == hipSuccess &&
+                dmalloc((void **)&Md, (size_t)S * S * sizeof(T), A) == hipSuccess) {
+                Mp.assign((size_t)S * S, (T)0);
+                for (int i = 0; i < KP; i++)
+                    for (int j = 0; j < KP; j++) Mp[(size_t)i * S + j] = (T)M[(size_t)i * KP + j];
+                if (hipMemcpyAsync(Md, Mp.data(), Mp.size() * sizeof(T), hipMemcpyHostToDevice,
+                                   s) != hipSuccess)
+                    rc = MCD_E_HIP;
+                if (rc == MCD_OK) {
+                    hipLaunchKernelGGL((k_to_rows<T>), dim3(gridn(nx * (S / P), 256)), dim3(256), 0,
+                                       s, nx, m, P, S, run.blk(0), Qt);
+                    const int64_t tiles = (nx + 127) / 128 * (S / 128);
+                    hipLaunchKernelGGL((k_rows_times<T>), dim3((unsigned)((tiles + 7) / 8 * 8)),
+                                       dim3(256), 0, s, nx, S, Qt, Md, Zt);
                     hipLaunchKernelGGL((k_contract_rows<T>), dim3(g), dim3(64 * kCWaves), 0, s, nx,
                                        op->d_keys, op->d_model, op->d_hash, op->hash_mask, Qt, Zt,
-                                       m * P, part);
-                } else {
-                    (void)hipGetLastError();
+                                       KP, S, part);
+                }
+            } else {
+                (void)hipGetLastError();
+                // Z_k = sum_j Q_j M[j-block, k-block]  (W -= sum Q (-C))
+                if (dmalloc((void **)&Z, (size_t)m * nx * P * sizeof(T), A) != hipSuccess)
+                    rc = MCD_E_HIP;
+                for (int k = 0; k < m && rc == MCD_OK; k++) {
+                    for (int j = 0; j < m; j++)
+                        for (int a = 0; a < P; a++)
+                            for (int b = 0; b < P; b++)
+                                C[((size_t)j * P + a) * P + b] = -M[((size_t)j * P + a) * KP + k * P + b];
+                    T *Zk = Z + (size_t)k * nx * P;
+                    if (hipMemsetAsync(Zk, 0, (size_t)nx * P * sizeof(T), s) != hipSuccess)
+                        rc = MCD_E_HIP;
+                    if (rc == MCD_OK) rc = run.block_apply(run.blk(0), m, C, Zk, true);
+                }
+                if (rc == MCD_OK)
                     hipLaunchKernelGGL((k_contract_multi<T>), dim3(g), dim3(64 * kCWaves), 0, s,
                                        nx, op->d_keys, op->d_model, op->d_hash, op->hash_mask,
                                        run.blk(0), Z, m, P, part);
-                }
+            }
+            if (rc == MCD_OK) {
                 hipLaunchKernelGGL(k_param_reduce, dim3((np + 3) / 4), dim3(256), 0, s, np, (int)g,
                                    part, acc, 1);
                 if (hipGetLastError() != hipSuccess) rc = MCD_E_HIP;
-                if (Qt) (void)dfree(Qt, A);
-                if (Zt) (void)dfree(Zt, A);
             }
             // W = Q Omega (into run.W), then lam += map^T W
             if (rc == MCD_OK) {
@@ -1723,7 +1881,8 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
                 if (hipGetLastError() != hipSuccess) rc = MCD_E_HIP;
             }
             if (hipStreamSynchronize(s) != hipSuccess && rc == MCD_OK) rc = MCD_E_HIP;
-            (void)dfree(Z, A);
+            for (T *q : {Z, Qt, Zt, Md})
+                if (q) (void)dfree(q, A);
             if (rc == MCD_E_HIP) set_error("green vjp: device step failed in a sector hook");
             return rc;
         });
