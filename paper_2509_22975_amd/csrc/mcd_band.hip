@@ -1453,35 +1453,17 @@ __global__ __launch_bounds__(64 * kCWaves) void k_contract_multi(
     }
 }
 
-// Row-major copy of a Krylov store: Xt[r][k P + a] = X[k][r][a] for the nk
-// blocks of n x P, and zero for k P + a in [nk P, S) (S a multiple of P).  One
-// thread per (row, block); consecutive threads fill one row.
-template <typename T>
-__global__ void k_to_rows(int64_t n, int nk, int P, int S, const T *__restrict__ X,
-                          T *__restrict__ Xt) {
-    const int kS = S / P;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * kS) return;
-    const int64_t r = i / kS;
-    const int k = (int)(i - r * kS);
-    T *__restrict__ dst = Xt + r * S + (int64_t)k * P;
-    if (k < nk) {
-        const T *__restrict__ src = X + ((int64_t)k * n + r) * P;
-        for (int a = 0; a < P; a++) dst[a] = src[a];
-    } else {
-        for (int a = 0; a < P; a++) dst[a] = (T)0;
-    }
-}
-
-// Zt = Qt M for the adjoint's Z = Q M: Qt [n][S] and M [S][S] row-major,
-// S a multiple of 128 (zero rows and columns past the Krylov dimension).  A
+// Zt = Q M for the adjoint: Q the Krylov store (blocks of n x P, P a power of
+// two; Q[r][k] = block k / P, row r, column k % P, k < KP), M [S][S] row-major
+// and Zt [n][S] row-major, S a multiple of 128 (M and Zt zero past KP).  A
 // workgroup of four wavefronts makes one 128 x 128 tile of Zt, each wavefront
 // a 64 x 64 quarter as 4 x 4 MFMA 16x16x4 products (float32 or float64 in,
 // same type accumulated), with both operands staged through LDS in steps of
 // 128 bytes of k.  Tiles are handed out XCD-major, so the S / 128 column tiles
-// of one row tile run on one XCD and share its L2 copy of the Qt rows.
+// of one row tile run on one XCD and share its L2 copy of the Q rows.
 template <typename T>
-__global__ __launch_bounds__(256) void k_rows_times(int64_t n, int S, const T *__restrict__ Qt,
+__global__ __launch_bounds__(256) void k_rows_times(int64_t n, int S, int KP, int pl,
+                                                   const T *__restrict__ Q,
                                                    const T *__restrict__ M, T *__restrict__ Zt) {
     constexpr int BM = 128, BN = 128, U = 16 / sizeof(T), BK = 8 * U;
     constexpr int LA = BK + U, LB = BN + 4 * U;   // padded LDS rows (conflict-free reads)
@@ -1489,6 +1471,7 @@ __global__ __launch_bounds__(256) void k_rows_times(int64_t n, int S, const T *_
     using V4 = T __attribute__((ext_vector_type(4)));
     __shared__ __attribute__((aligned(16))) T As[BM * LA];   // As[row][k]
     __shared__ __attribute__((aligned(16))) T Bs[BK * LB];   // Bs[k][col]
+    const int P = 1 << pl;
     const int ntc = S / BN;
     const int64_t ntr = (n + BM - 1) / BM, G = ntr * ntc, Gp = (G + 7) / 8 * 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * (Gp / 8) + blockIdx.x / 8;
@@ -1506,10 +1489,20 @@ __global__ __launch_bounds__(256) void k_rows_times(int64_t n, int S, const T *_
     for (int k0 = 0; k0 < S; k0 += BK) {
 #pragma unroll
         for (int q = 0; q < 4; q++) {   // A: 128 rows x 8 units of 16 bytes
-            const int e = tid + q * 256, row = e >> 3, ku = (e & 7) * U;
+            const int e = tid + q * 256, row = e >> 3, ku = (e & 7) * U, kg = k0 + ku;
             const int64_t r = r0 + row;
             V16 v = (V16)(T)0;
-            if (r < n) v = *(const V16 *)(Qt + r * S + k0 + ku);
+            if (r < n && kg < KP) {
+                if (P >= U) {   // the unit lies in one block
+                    v = *(const V16 *)(Q + ((((int64_t)(kg >> pl) * n + r) << pl) | (kg & (P - 1))));
+                } else {
+#pragma unroll
+                    for (int u = 0; u < U; u++) {
+                        const int k = kg + u;
+                        if (k < KP) v[u] = Q[(((int64_t)(k >> pl) * n + r) << pl) | (k & (P - 1))];
+                    }
+                }
+            }
             *(V16 *)(As + row * LA + ku) = v;
         }
 #pragma unroll
@@ -1550,48 +1543,85 @@ __global__ __launch_bounds__(256) void k_rows_times(int64_t n, int S, const T *_
         }
 }
 
-// k_contract_multi on row-major copies (Lt, Rt: [n][S], first KP columns
-// used): a hop's dot reads two contiguous rows of KP values (about four times fewer cache lines than
-// the block-major store, where a row is KP / P pieces of P values).  Same
-// hop enumeration, terms and reduction order per row as k_contract_multi.
-template <typename T>
+// k_contract_multi with R row-major (Rt: [n][S], zero past KP): one wavefront
+// per row r.  The lanes look up all of the row's hop targets at once (lane
+// 2q + s: bond q, spin s), the row L[r] (block-major store, KP = nk P values)
+// is loaded once into registers (NR per lane; NR = 0 re-reads it, any S), and
+// the hops are then taken in lane order, each a gather of the contiguous row
+// Rt[col] with all NR loads issued together: loads past column S read the
+// next row (or a zeroed tail of at least 64 (NR - S / 64) values after the
+// last row) and meet zero weights.  Per row the terms and their order match
+// k_contract_multi.
+template <typename T, int NR>
 __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
     int64_t n, const uint64_t *__restrict__ keys, const DevModel *__restrict__ m,
-    const HashSlot *__restrict__ h, uint64_t hmask, const T *__restrict__ Lt,
-    const T *__restrict__ Rt, int KP, int S, double *__restrict__ part) {
+    const HashSlot *__restrict__ h, uint64_t hmask, const T *__restrict__ L, int KP, int pl,
+    const T *__restrict__ Rt, int S, double *__restrict__ part) {
     __shared__ double acc[kCWaves][kMaxParams];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nb = m->n_bonds, no = m->n_orb, np = nb + 2 * no;
+    const int nr = S / 64, P = 1 << pl;
     for (int i = lane; i < np; i += 64) acc[wid][i] = 0.0;
     for (int64_t r = (int64_t)blockIdx.x * kCWaves + wid; r < n;
          r += (int64_t)gridDim.x * kCWaves) {
         const uint64_t key = keys[r];
         const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
-        const T *__restrict__ lr = Lt + r * (int64_t)S;
+        auto lval = [&](int a) -> T {
+            return a < KP ? L[(((int64_t)(a >> pl) * n + r) << pl) | (a & (P - 1))] : (T)0;
+        };
+        T qv[NR > 0 ? NR : 1];
+        if constexpr (NR > 0) {
+#pragma unroll
+            for (int i = 0; i < NR; i++) qv[i] = lval(lane + 64 * i);
+        }
+        // sum_a L[r][a] Rt[col][a] over the wave (result in every lane)
         auto rowdot = [&](int64_t col) {
             const T *__restrict__ rc = Rt + col * (int64_t)S;
-            double s = 0.0;
-            for (int a = lane; a < KP; a += 64) s += (double)lr[a] * (double)rc[a];
-            return wave_sum(s);
+            double sum = 0.0;
+            if constexpr (NR > 0) {
+                T rv[NR];
+#pragma unroll
+                for (int i = 0; i < NR; i++) rv[i] = rc[lane + 64 * i];
+#pragma unroll
+                for (int i = 0; i < NR; i++) sum += (double)qv[i] * (double)rv[i];
+            } else {
+                for (int a = lane; a < S; a += 64) sum += (double)lval(a) * (double)rc[a];
+            }
+            return wave_sum(sum);
         };
-        for (int q = 0; q < nb; q++) {
-            const uint32_t mask = m->bonds[q].mask, between = m->bonds[q].between;
+        for (int base = 0; base < 2 * nb; base += 64) {
+            const int hl = base + lane;
+            int64_t col = -1;
+            int neg = 0;
+            if (hl < 2 * nb) {
+                const uint32_t mask = m->bonds[hl >> 1].mask, between = m->bonds[hl >> 1].between;
+                const uint32_t sp = (hl & 1) ? dn : up;
+                if (__popc(sp & mask) == 1) {
+                    col = hash_find(h, hmask, key ^ ((uint64_t)mask << ((hl & 1) ? 0 : 32)));
+                    neg = __popc(sp & between) & 1;
+                }
+            }
+            uint64_t live = __ballot(col >= 0);
+            int cur = -1;
             double c = 0.0;
-            if (__popc(up & mask) == 1) {
-                const int64_t col = hash_find(h, hmask, key ^ ((uint64_t)mask << 32));
-                if (col >= 0) {
-                    const double d = rowdot(col);
-                    c += (__popc(up & between) & 1) ? -d : d;
+            while (live) {
+                const int l = __ffsll((unsigned long long)live) - 1;
+                live &= live - 1;
+                // the hop of lane l, read into scalar registers (uniform)
+                const uint32_t clo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)col, l);
+                const uint32_t chi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(col >> 32), l);
+                const int64_t cl = (int64_t)(((uint64_t)chi << 32) | clo);
+                const int ng = __builtin_amdgcn_readlane(neg, l);
+                const int q = (base + l) >> 1;
+                if (q != cur) {
+                    if (cur >= 0 && lane == 0) acc[wid][cur] += c;
+                    cur = q;
+                    c = 0.0;
                 }
+                const double d = rowdot(cl);
+                c += ng ? -d : d;
             }
-            if (__popc(dn & mask) == 1) {
-                const int64_t col = hash_find(h, hmask, key ^ (uint64_t)mask);
-                if (col >= 0) {
-                    const double d = rowdot(col);
-                    c += (__popc(dn & between) & 1) ? -d : d;
-                }
-            }
-            if (lane == 0) acc[wid][q] += c;
+            if (cur >= 0 && lane == 0) acc[wid][cur] += c;
         }
         const double d = rowdot(r);
         if (lane == 0) {
@@ -1604,10 +1634,29 @@ __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
     }
     __syncthreads();
     for (int i = threadIdx.x; i < np; i += 64 * kCWaves) {
-        double s = 0.0;
-        for (int w = 0; w < kCWaves; w++) s += acc[w][i];
-        part[(int64_t)i * gridDim.x + blockIdx.x] = s;
+        double sum = 0.0;
+        for (int w = 0; w < kCWaves; w++) sum += acc[w][i];
+        part[(int64_t)i * gridDim.x + blockIdx.x] = sum;
     }
+}
+
+template <typename T>
+static void launch_contract_rows(unsigned g, hipStream_t s, int64_t n, const mcd_op *op,
+                                 const T *L, int KP, int pl, const T *Rt, int S, double *part) {
+#define CR(NRV)                                                                             \
+    hipLaunchKernelGGL((k_contract_rows<T, NRV>), dim3(g), dim3(64 * kCWaves), 0, s, n,    \
+                       op->d_keys, op->d_model, op->d_hash, op->hash_mask, L, KP, pl, Rt, S, part)
+    const int nr = S / 64;
+    if (nr <= 2) CR(2);
+    else if (nr <= 4) CR(4);
+    else if (nr <= 6) CR(6);
+    else if (nr <= 8) CR(8);
+    else if (nr <= 12) CR(12);
+    else if (nr <= 16) CR(16);
+    else if (nr <= 24) CR(24);
+    else if (nr <= 32) CR(32);
+    else CR(0);
+#undef CR
 }
 
 // out[p] (+)= sum_c part[p * nblk + c]: one wavefront per parameter.
@@ -1756,7 +1805,7 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     CK(dmalloc((void **)&scal, 8 * sizeof(double), A));
     CK(hipMemsetAsync(lam, 0, n * sizeof(double), s));
     CK(hipMemsetAsync(acc, 0, np * sizeof(double), s));
-    const int cblk = 2048;
+    const int cblk = 16384;   // contraction workgroups at most (partials per parameter)
     CK(dmalloc((void **)&part, (size_t)np * cblk * sizeof(double), A));
 
     double trM = 0.0;   // sum over sectors of tr(M)
@@ -1811,33 +1860,34 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             const int64_t nx = run.n;
             std::vector<double> C((size_t)m * P * P);
             int rc = MCD_OK;
-            const unsigned g = (unsigned)std::min<int64_t>(cblk, (nx + kCWaves - 1) / kCWaves);
-            // Z = Q M as one product on row-major copies (Qt, Zt: [nx][S]) when
-            // memory allows, else block by block on the block-major store.
+            // about 16 rows per wavefront
+            const unsigned g =
+                (unsigned)std::min<int64_t>(cblk, (nx + 16 * kCWaves - 1) / (16 * kCWaves));
+            // Z = Q M as one product into a row-major Zt [nx][S] when memory
+            // allows, else block by block on the block-major store.
             const int S = (KP + 127) / 128 * 128;
-            T *Qt = nullptr, *Zt = nullptr, *Md = nullptr, *Z = nullptr;
+            int pl = 0;
+            while ((1 << pl) < P) pl++;
+            T *Zt = nullptr, *Md = nullptr, *Z = nullptr;
             std::vector<T> Mp;
             size_t fr = 0, tot = 0;
-            const size_t rows_bytes = (size_t)nx * S * sizeof(T);
-            if (hipMemGetInfo(&fr, &tot) == hipSuccess && 2.0 * rows_bytes < 0.5 * (double)fr &&
-                dmalloc((void **)&Qt, rows_bytes, A) == hipSuccess &&
+            constexpr int kTail = 1024;   // zeroed values after the last row of Zt
+            const size_t rows_bytes = ((size_t)nx * S + kTail) * sizeof(T);
+            if (hipMemGetInfo(&fr, &tot) == hipSuccess && (double)rows_bytes < 0.5 * (double)fr &&
                 dmalloc((void **)&Zt, rows_bytes, A) == hipSuccess &&
                 dmalloc((void **)&Md, (size_t)S * S * sizeof(T), A) == hipSuccess) {
                 Mp.assign((size_t)S * S, (T)0);
                 for (int i = 0; i < KP; i++)
                     for (int j = 0; j < KP; j++) Mp[(size_t)i * S + j] = (T)M[(size_t)i * KP + j];
                 if (hipMemcpyAsync(Md, Mp.data(), Mp.size() * sizeof(T), hipMemcpyHostToDevice,
-                                   s) != hipSuccess)
+                                   s) != hipSuccess ||
+                    hipMemsetAsync(Zt + (size_t)nx * S, 0, kTail * sizeof(T), s) != hipSuccess)
                     rc = MCD_E_HIP;
                 if (rc == MCD_OK) {
-                    hipLaunchKernelGGL((k_to_rows<T>), dim3(gridn(nx * (S / P), 256)), dim3(256), 0,
-                                       s, nx, m, P, S, run.blk(0), Qt);
                     const int64_t tiles = (nx + 127) / 128 * (S / 128);
                     hipLaunchKernelGGL((k_rows_times<T>), dim3((unsigned)((tiles + 7) / 8 * 8)),
-                                       dim3(256), 0, s, nx, S, Qt, Md, Zt);
-                    hipLaunchKernelGGL((k_contract_rows<T>), dim3(g), dim3(64 * kCWaves), 0, s, nx,
-                                       op->d_keys, op->d_model, op->d_hash, op->hash_mask, Qt, Zt,
-                                       KP, S, part);
+                                       dim3(256), 0, s, nx, S, KP, pl, run.blk(0), Md, Zt);
+                    launch_contract_rows<T>(g, s, nx, op, run.blk(0), KP, pl, Zt, S, part);
                 }
             } else {
                 (void)hipGetLastError();
@@ -1881,7 +1931,7 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
                 if (hipGetLastError() != hipSuccess) rc = MCD_E_HIP;
             }
             if (hipStreamSynchronize(s) != hipSuccess && rc == MCD_OK) rc = MCD_E_HIP;
-            for (T *q : {Z, Qt, Zt, Md})
+            for (T *q : {Z, Zt, Md})
                 if (q) (void)dfree(q, A);
             if (rc == MCD_E_HIP) set_error("green vjp: device step failed in a sector hook");
             return rc;
