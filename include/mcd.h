@@ -367,6 +367,33 @@ int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int
                            double *Gm_out, mcd_solve_info *info, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * mcd_band_lanczos_green_keep -- mcd_band_lanczos_green that also keeps the
+ * two sector runs it makes (App. Band Lanczos: the Krylov blocks Q, the block
+ * tridiagonal T, the operator on F~+-) for mcd_band_green_vjp_keep, so that
+ * the derivative does not recompute them.
+ *
+ * Arguments and outputs as mcd_band_lanczos_green; cfg->w_t must be 1 and
+ * cfg->per_column 0.  Every Krylov block is stored (max_blocks + 1 blocks of
+ * n_x * P values per sector, P = n_sel rounded up to a power of two, in the
+ * cfg->precision type), and all of it stays on the device until
+ * mcd_band_keep_destroy.  On success *keep_out is a new handle owned by the
+ * caller; on error it is NULL and nothing is kept.  keys_dev and psi0_dev are
+ * not retained (the later derivative call passes them again).
+ * Synchronises.
+ * ------------------------------------------------------------------------- */
+typedef struct mcd_band_keep mcd_band_keep;
+int mcd_band_lanczos_green_keep(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                                const double *psi0_dev, double e0, int32_t n_sel,
+                                const int32_t *orb, const int32_t *spin, int32_t n_freq,
+                                const double *omega, const mcd_band_cfg *cfg, double *G_out,
+                                double *Gp_out, double *Gm_out, mcd_solve_info *info,
+                                void *stream, mcd_band_keep **keep_out);
+
+/* Releases a handle of mcd_band_lanczos_green_keep (NULL is ignored).  No
+ * call on the handle may be running. */
+void mcd_band_keep_destroy(mcd_band_keep *keep);
+
+/* ---------------------------------------------------------------------------
  * mcd_batch_band_green -- mcd_band_lanczos_green for many independent
  * instances (bath-parameter sets of a quantum impurity model, each with its
  * own basis and ground state), same selection, frequencies and cfg.
@@ -414,7 +441,8 @@ int mcd_batch_band_green(const mcd_model *const *models, const uint64_t *const *
  *     -(H - E0)^+ dH/dtheta psi0: one conjugate-gradient solve
  *     (H - E0) xi = P lambda on F~ (P projects out psi0, lambda collects the
  *     adjoint of the start blocks), then -<xi| dH/dtheta |psi0>.
- * The Krylov blocks are recomputed here (the forward call keeps none).
+ * The Krylov blocks are recomputed here (mcd_band_green_vjp_keep instead
+ * takes them from a forward call that kept them).
  *
  * psi0_dev: the normalised, non-degenerate ground state; cfg->w_t must be 1
  *   (a target-weight cut is not differentiable); every Krylov block is
@@ -434,6 +462,25 @@ int mcd_band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int64_t
                        const mcd_band_cfg *cfg, const double *G_bar, double e0_bar,
                        double cg_tol, int32_t cg_max_iter, double *d_t, double *d_U,
                        double *d_eps, mcd_solve_info *info, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * mcd_band_green_vjp_keep -- mcd_band_green_vjp on the sector runs kept by
+ * mcd_band_lanczos_green_keep instead of recomputed ones.  The arguments are
+ * those of mcd_band_green_vjp and must equal the kept forward call's (n,
+ * e0, selection, frequencies, and cfg's max_blocks, precision, dtol,
+ * storage, reorth, eta, g_tol; else MCD_E_INVALID); keys_dev, psi0_dev and
+ * model must be the same data.  The results are those of mcd_band_green_vjp
+ * (the kept runs are the runs it would recompute).  keep is not consumed and
+ * may serve several calls, one at a time (they share its scratch blocks).
+ * Synchronises.
+ * ------------------------------------------------------------------------- */
+int mcd_band_green_vjp_keep(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                            const double *psi0_dev, double e0, int32_t n_sel, const int32_t *orb,
+                            const int32_t *spin, int32_t n_freq, const double *omega,
+                            const mcd_band_cfg *cfg, const double *G_bar, double e0_bar,
+                            double cg_tol, int32_t cg_max_iter, double *d_t, double *d_U,
+                            double *d_eps, mcd_solve_info *info, void *stream,
+                            mcd_band_keep *keep);
 
 #ifdef __cplusplus
 }

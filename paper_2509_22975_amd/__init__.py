@@ -108,10 +108,15 @@ def lib():
                                      P(c_i32), c_i32, P(c_dbl), P(McdBandCfg), P(c_dbl), c_dbl,
                                      c_dbl, c_i32, P(c_dbl), P(c_dbl), P(c_dbl), P(McdSolveInfo),
                                      c_vp]
+    L.mcd_band_lanczos_green_keep.argtypes = L.mcd_band_lanczos_green.argtypes + [P(c_vp)]
+    L.mcd_band_green_vjp_keep.argtypes = L.mcd_band_green_vjp.argtypes + [c_vp]
+    L.mcd_band_keep_destroy.argtypes = [c_vp]
+    L.mcd_band_keep_destroy.restype = None
     for name in ("mcd_basis_build", "mcd_op_create", "mcd_op_info", "mcd_op_set_kernel", "mcd_hamiltonian_apply",
                  "mcd_hamiltonian_diagonal", "mcd_hamiltonian_connectivity", "mcd_lanczos_ground",
                  "mcd_band_lanczos_green", "mcd_batch_lanczos_ground",
-                 "mcd_hamiltonian_contract", "mcd_band_green_vjp", "mcd_batch_band_green"):
+                 "mcd_hamiltonian_contract", "mcd_band_green_vjp", "mcd_batch_band_green",
+                 "mcd_band_lanczos_green_keep", "mcd_band_green_vjp_keep"):
         if hasattr(L, name):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -374,13 +379,34 @@ def _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, per_column, eta
                       1 if per_column else 0, float(eta), float(g_tol))
 
 
+class BandKeep:
+    """The two sector runs of a forward band_lanczos_green(..., keep=True)
+    call (mcd_band_keep: Krylov blocks, T, operators on F~+-), held on the
+    device until close() for band_green_vjp(..., keep=...)."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def close(self):
+        if self._h:
+            lib().mcd_band_keep_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def band_lanczos_green(model, keys, psi0, e0, orbitals, spins, omega, max_blocks=50,
                        precision="f64", w_t=1.0, dtol=1e-10, storage="auto", reorth=2,
-                       parts=False, per_column=False, eta=0.0, g_tol=0.0):
+                       parts=False, per_column=False, eta=0.0, g_tol=0.0, keep=False):
     """G [n_freq, n_sel, n_sel] complex128 via mcd_band_lanczos_green.
 
     eta == 0: omega are Matsubara frequencies (z = i w); eta > 0: real
-    frequencies broadened by eta (z = w + i eta)."""
+    frequencies broadened by eta (z = w + i eta).  keep=True calls
+    mcd_band_lanczos_green_keep and appends a BandKeep to the returned tuple."""
     mb = _ModelBuf(model)
     orb = np.ascontiguousarray(orbitals, dtype=np.int32)
     sp = np.ascontiguousarray(spins, dtype=np.int32)
@@ -392,22 +418,29 @@ def band_lanczos_green(model, keys, psi0, e0, orbitals, spins, omega, max_blocks
     cfg = _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, per_column, eta, g_tol)
     info = McdSolveInfo()
     dp = lambda a: a.view(np.float64).ctypes.data_as(P(c_dbl))
-    code = lib().mcd_band_lanczos_green(ctypes.byref(mb.s), c_vp(keys.data_ptr()), int(keys.numel()),
-                                        c_vp(psi0.data_ptr()), float(e0), ns,
-                                        orb.ctypes.data_as(P(c_i32)), sp.ctypes.data_as(P(c_i32)),
-                                        nf, om.ctypes.data_as(P(c_dbl)), ctypes.byref(cfg), dp(G),
-                                        dp(Gp), dp(Gm), ctypes.byref(info), _stream())
-    _check(code, "mcd_band_lanczos_green")
-    if parts:
-        return G, Gp, Gm, SolveInfo.of(info)
-    return G, SolveInfo.of(info)
+    args = [ctypes.byref(mb.s), c_vp(keys.data_ptr()), int(keys.numel()), c_vp(psi0.data_ptr()),
+            float(e0), ns, orb.ctypes.data_as(P(c_i32)), sp.ctypes.data_as(P(c_i32)), nf,
+            om.ctypes.data_as(P(c_dbl)), ctypes.byref(cfg), dp(G), dp(Gp), dp(Gm),
+            ctypes.byref(info), _stream()]
+    kept = None
+    if keep:
+        h = c_vp()
+        code = lib().mcd_band_lanczos_green_keep(*args, ctypes.byref(h))
+        _check(code, "mcd_band_lanczos_green_keep")
+        kept = BandKeep(h.value)
+    else:
+        code = lib().mcd_band_lanczos_green(*args)
+        _check(code, "mcd_band_lanczos_green")
+    out = (G, Gp, Gm, SolveInfo.of(info)) if parts else (G, SolveInfo.of(info))
+    return out + (kept,) if keep else out
 
 
 def band_green_vjp(model, keys, psi0, e0, orbitals, spins, omega, G_bar, e0_bar=0.0,
                    max_blocks=50, precision="f64", dtol=1e-10, storage="auto", reorth=2, eta=0.0,
-                   cg_tol=1e-12, cg_max_iter=20000, g_tol=0.0):
+                   cg_tol=1e-12, cg_max_iter=20000, g_tol=0.0, keep=None):
     """(d_t [n_bonds], d_U [n_orb], d_eps [n_orb], SolveInfo) = Re sum conj(G_bar) dG/dtheta
-    + e0_bar dE0/dtheta via mcd_band_green_vjp (same arguments as band_lanczos_green)."""
+    + e0_bar dE0/dtheta via mcd_band_green_vjp (same arguments as band_lanczos_green), or
+    via mcd_band_green_vjp_keep on the runs of a BandKeep."""
     mb = _ModelBuf(model)
     orb = np.ascontiguousarray(orbitals, dtype=np.int32)
     sp = np.ascontiguousarray(spins, dtype=np.int32)
@@ -420,14 +453,19 @@ def band_green_vjp(model, keys, psi0, e0, orbitals, spins, omega, G_bar, e0_bar=
     de = np.zeros(model.n_orb)
     info = McdSolveInfo()
     dp = lambda a: a.ctypes.data_as(P(c_dbl))
-    code = lib().mcd_band_green_vjp(ctypes.byref(mb.s), c_vp(keys.data_ptr()), int(keys.numel()),
-                                    c_vp(psi0.data_ptr()), float(e0), ns,
-                                    orb.ctypes.data_as(P(c_i32)), sp.ctypes.data_as(P(c_i32)), nf,
-                                    om.ctypes.data_as(P(c_dbl)), ctypes.byref(cfg),
-                                    gb.view(np.float64).ctypes.data_as(P(c_dbl)), float(e0_bar),
-                                    float(cg_tol), int(cg_max_iter), dp(dt), dp(dU), dp(de),
-                                    ctypes.byref(info), _stream())
-    _check(code, "mcd_band_green_vjp")
+    args = [ctypes.byref(mb.s), c_vp(keys.data_ptr()), int(keys.numel()), c_vp(psi0.data_ptr()),
+            float(e0), ns, orb.ctypes.data_as(P(c_i32)), sp.ctypes.data_as(P(c_i32)), nf,
+            om.ctypes.data_as(P(c_dbl)), ctypes.byref(cfg),
+            gb.view(np.float64).ctypes.data_as(P(c_dbl)), float(e0_bar), float(cg_tol),
+            int(cg_max_iter), dp(dt), dp(dU), dp(de), ctypes.byref(info), _stream()]
+    if keep is not None:
+        if not keep._h:
+            raise ValueError("the BandKeep is closed")
+        code = lib().mcd_band_green_vjp_keep(*args, c_vp(keep._h))
+        _check(code, "mcd_band_green_vjp_keep")
+    else:
+        code = lib().mcd_band_green_vjp(*args)
+        _check(code, "mcd_band_green_vjp")
     return dt, dU, de, SolveInfo.of(info)
 
 

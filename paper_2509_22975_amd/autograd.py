@@ -9,11 +9,13 @@ tensors (for example the 33 impurity parameters eps_b, V_ib, U); autograd
 composes the chain rule.
 
 ``green_function(...)`` returns (E0, G) with G the band-Lanczos Green
-function [n_freq, n_sel, n_sel] (complex128); its backward is one call of
-``mcd_band_green_vjp`` (resolvent contraction over the recomputed Krylov
-blocks, Hellmann-Feynman dE0, and one conjugate-gradient solve for the
-ground-state response), so a loss of G and E0 gets its gradient with respect
-to every bond amplitude, U_i and eps_i in one backward pass.
+function [n_freq, n_sel, n_sel] (complex128); when a derivative is needed
+the forward keeps its two sector runs (``mcd_band_lanczos_green_keep``) and
+the backward is one call of ``mcd_band_green_vjp_keep`` (resolvent
+contraction over the kept Krylov blocks, Hellmann-Feynman dE0, and one
+conjugate-gradient solve for the ground-state response), so a loss of G and
+E0 gets its gradient with respect to every bond amplitude, U_i and eps_i in
+one backward pass.
 """
 from __future__ import annotations
 
@@ -74,7 +76,13 @@ def _make_green_function():
             op = Operator(m, keys, storage=storage)
             e0, psi, _, _, _ = lanczos_ground(op, **lanczos_kw)
             op.close()
-            G, _ = band_lanczos_green(m, keys, psi, e0, orbitals, spins, omega, **band_kw)
+            # with a derivative ahead, keep the sector runs for it (no recomputation)
+            ctx.keep = None
+            if any(ctx.needs_input_grad[:3]) and not band_kw.get("per_column", False):
+                G, _, ctx.keep = band_lanczos_green(m, keys, psi, e0, orbitals, spins, omega,
+                                                    keep=True, **band_kw)
+            else:
+                G, _ = band_lanczos_green(m, keys, psi, e0, orbitals, spins, omega, **band_kw)
             ctx.m, ctx.keys, ctx.psi, ctx.e0 = m, keys, psi, e0
             ctx.sel = (orbitals, spins, omega)
             ctx.band_kw = band_kw
@@ -90,8 +98,15 @@ def _make_green_function():
                   else G_bar.detach().cpu().numpy().astype(np.complex128))
             eb = 0.0 if e0_bar is None else float(e0_bar.item())
             kw = {k: v for k, v in ctx.band_kw.items() if k not in ("w_t", "per_column")}
-            dt, dU, de, _ = band_green_vjp(ctx.m, ctx.keys, ctx.psi, ctx.e0, orbitals, spins,
-                                           omega, gb, e0_bar=eb, **kw)
+            # the kept runs serve the first backward and are then released (a
+            # second backward recomputes them: same result)
+            kept, ctx.keep = ctx.keep, None
+            try:
+                dt, dU, de, _ = band_green_vjp(ctx.m, ctx.keys, ctx.psi, ctx.e0, orbitals, spins,
+                                               omega, gb, e0_bar=eb, keep=kept, **kw)
+            finally:
+                if kept is not None:
+                    kept.close()
             t, U, eps = ctx.shapes
             as_t = lambda a, ref: torch.as_tensor(a, dtype=ref.dtype, device=ref.device)
             return (as_t(dt, t), as_t(dU, U), as_t(de, eps), None, None, None, None, None, None,

@@ -29,6 +29,7 @@
 #include <chrono>
 #include <complex>
 #include <functional>
+#include <memory>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1015,6 +1016,41 @@ static double wall_ms() {
 template <typename T>
 using SectorHook = std::function<int(BandRun<T> &, mcd_op *, const BandResult &)>;
 
+// A sector run kept after the forward call for the adjoint: the Krylov store
+// and scratch blocks, the operator on F~+- and the recurrence, with the arena
+// all their device buffers live in.
+template <typename T>
+struct SectorKeep {
+    std::unique_ptr<Arena> arena;
+    BandRun<T> run;
+    mcd_op *op = nullptr;
+    BandResult br;
+    int64_t n_x = 0;
+    SectorKeep() = default;
+    SectorKeep(const SectorKeep &) = delete;
+    SectorKeep &operator=(const SectorKeep &) = delete;
+    ~SectorKeep() { clear(); }
+    void clear() {
+        if (op) mcd_op_destroy(op);   // its buffers are the arena's
+        op = nullptr;
+        if (arena) arena->release();
+        arena.reset();
+    }
+    // the stream later work on the kept buffers runs on (the forward's hole
+    // run stream no longer exists)
+    void set_stream(hipStream_t st) {
+        run.s = st;
+        run.al.s = st;
+        if (op) op->alloc.s = st;
+        if (arena) arena->s = st;
+    }
+};
+
+template <typename T>
+struct BandKeep {
+    SectorKeep<T> plus, minus;
+};
+
 // One excited sector run (create = particle / G+, else hole / G-).  With
 // store_all every Krylov block is kept (also without reorthogonalisation)
 // and `hook` runs before the sector's buffers are released.
@@ -1023,10 +1059,13 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
                        int64_t nt, const SelOps &sel, bool create, const mcd_band_cfg *cfg,
                        double dtol_scale, int P, BandResult &br, int64_t *n_x, hipStream_t s,
                        bool store_all = false, const SectorHook<T> *hook = nullptr,
-                       const std::vector<cplx> *zcheck = nullptr) {
+                       const std::vector<cplx> *zcheck = nullptr,
+                       SectorKeep<T> *keep = nullptr) {
     const Alloc A{s, true};   // stream-ordered buffers (no device-wide sync on free)
-    // the operator and the run's buffers: one arena, released at the end
-    Arena arena(s);
+    // the operator and the run's buffers: one arena, released at the end (or
+    // handed to keep)
+    std::unique_ptr<Arena> arena_own(new Arena(s));
+    Arena &arena = *arena_own;
     const Alloc AR{s, true, &arena};
     uint64_t *img = nullptr, *srt = nullptr, *uniq = nullptr;
     int64_t *d_nu = nullptr;
@@ -1092,6 +1131,11 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
         br = BandResult();
         br.P = P;
         cleanup();
+        if (keep) {
+            keep->clear();
+            keep->br = br;
+            keep->n_x = 0;
+        }
         return MCD_OK;
     }
     TRY(op_create(model, uniq, nu, cfg->storage, 0, cfg->per_column != 0, s, &op, true, &arena));
@@ -1153,6 +1197,16 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
         }
         CK(hipStreamSynchronize(s));
     }
+    if (keep) {   // hand the run, operator and arena over (all work has completed)
+        keep->clear();
+        keep->arena = std::move(arena_own);
+        keep->run = std::move(run);
+        keep->op = op;
+        keep->br = br;
+        keep->n_x = nu;
+        keep->set_stream(nullptr);
+        return MCD_OK;
+    }
     cleanup();
 #undef CK
 #undef TRY
@@ -1189,7 +1243,7 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
                       const double *psi0_dev, double e0, const SelOps &sel, int n_freq,
                       const double *omega, const mcd_band_cfg *cfg, double *G_out, double *Gp_out,
                       double *Gm_out, mcd_solve_info *info, hipStream_t s,
-                      bool concurrent_sectors) {
+                      bool concurrent_sectors, BandKeep<T> *keep = nullptr) {
     Arena arena(s);
     const Alloc A{s, true, &arena};   // stream-ordered, released together
     const double t0 = wall_ms();
@@ -1296,7 +1350,8 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
                 return;
             }
             rc_m = excited_run<T>(model, keys_t, psi_t, n_keep, sel, false, cfg, 1.0, P, brm, &nm,
-                                  s2, false, nullptr, &zm);
+                                  s2, keep != nullptr, nullptr, &zm,
+                                  keep ? &keep->minus : nullptr);
             if (rc_m < 0) msg_m = mcd_last_error();
             if (hipStreamSynchronize(s2) != hipSuccess && rc_m >= 0) {
                 rc_m = MCD_E_HIP;
@@ -1305,7 +1360,7 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
             (void)hipStreamDestroy(s2);
         });
         rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, true, cfg, 1.0, P, brp, &np, s,
-                            false, nullptr, &zp);
+                            keep != nullptr, nullptr, &zp, keep ? &keep->plus : nullptr);
         hole.join();
         if (rc >= 0 && rc_m < 0) {
             set_error("%s", msg_m.c_str());
@@ -1313,10 +1368,10 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
         }
     } else {
         rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, true, cfg, 1.0, P, brp, &np, s,
-                            false, nullptr, &zp);
+                            keep != nullptr, nullptr, &zp, keep ? &keep->plus : nullptr);
         if (rc >= 0)
             rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, false, cfg, 1.0, P, brm, &nm, s,
-                                false, nullptr, &zm);
+                                keep != nullptr, nullptr, &zm, keep ? &keep->minus : nullptr);
     }
     if (rc < 0) {
         cleanup();
@@ -1747,7 +1802,8 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
                           const double *psi0_dev, double e0, const SelOps &sel, int n_freq,
                           const double *omega, const mcd_band_cfg *cfg, const double *G_bar,
                           double e0_bar, double cg_tol, int cg_max_iter, double *d_t,
-                          double *d_U, double *d_eps, mcd_solve_info *info, hipStream_t s) {
+                          double *d_U, double *d_eps, mcd_solve_info *info, hipStream_t s,
+                          BandKeep<T> *keep = nullptr) {
     const Alloc A{s, true};   // stream-ordered buffers (no device-wide sync on free)
     const double t0 = wall_ms();
     {
@@ -1941,12 +1997,26 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     int64_t npl = 0, nmi = 0;
     {
         const SectorHook<T> hp = make_hook(true), hm = make_hook(false);
-        std::vector<cplx> zp, zm;
-        check_points(cfg, n_freq, omega, e0, zp, zm);
-        TRY(excited_run<T>(model, keys_dev, psi_n, n, sel, true, cfg, 1.0, P, brp, &npl, s,
-                           true, &hp, &zp));
-        TRY(excited_run<T>(model, keys_dev, psi_n, n, sel, false, cfg, 1.0, P, brm, &nmi, s,
-                           true, &hm, &zm));
+        if (keep) {   // the forward call's sector runs, kept (no recomputation)
+            for (int side = 0; side < 2; side++) {
+                SectorKeep<T> &k = side == 0 ? keep->plus : keep->minus;
+                (side == 0 ? npl : nmi) = k.n_x;
+                (side == 0 ? brp : brm) = k.br;
+                if (k.br.m > 0 && k.op) {
+                    k.set_stream(s);
+                    const int rc_h = (side == 0 ? hp : hm)(k.run, k.op, k.br);
+                    k.set_stream(nullptr);
+                    TRY(rc_h);
+                }
+            }
+        } else {
+            std::vector<cplx> zp, zm;
+            check_points(cfg, n_freq, omega, e0, zp, zm);
+            TRY(excited_run<T>(model, keys_dev, psi_n, n, sel, true, cfg, 1.0, P, brp, &npl, s,
+                               true, &hp, &zp));
+            TRY(excited_run<T>(model, keys_dev, psi_n, n, sel, false, cfg, 1.0, P, brm, &nmi, s,
+                               true, &hm, &zm));
+        }
     }
 
     // (H - E0) xi = P lam on F~, xi orthogonal to psi0 (conjugate gradients;
@@ -2043,12 +2113,11 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
 
 using namespace mcd;
 
-extern "C" int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
-                                      const double *psi0_dev, double e0, int32_t n_sel,
-                                      const int32_t *orb, const int32_t *spin, int32_t n_freq,
-                                      const double *omega, const mcd_band_cfg *cfg,
-                                      double *G_out, double *Gp_out, double *Gm_out,
-                                      mcd_solve_info *info, void *stream) {
+// Checks of the forward call's arguments; fills sel.
+static int band_args(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                     const double *psi0_dev, int32_t n_sel, const int32_t *orb,
+                     const int32_t *spin, int32_t n_freq, const double *omega,
+                     const mcd_band_cfg *cfg, const double *G_out, SelOps &sel) {
     MCD_REQUIRE(model && cfg && keys_dev && psi0_dev && orb && spin && G_out, MCD_E_INVALID,
                 "a required pointer is NULL");
     MCD_REQUIRE(n >= 1, MCD_E_INVALID, "empty basis");
@@ -2060,7 +2129,6 @@ extern "C" int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *ke
                 "precision must be MCD_F64 or MCD_F32");
     HostModel hm;
     MCD_TRY(prepare_model(model, &hm));
-    SelOps sel;
     memset(&sel, 0, sizeof(sel));
     sel.n = n_sel;
     for (int q = 0; q < n_sel; q++) {
@@ -2069,6 +2137,29 @@ extern "C" int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *ke
         sel.orb[q] = orb[q];
         sel.spin[q] = spin[q];
     }
+    return MCD_OK;
+}
+
+// What a kept forward call was made with, and its two sector runs.
+struct mcd_band_keep {
+    int64_t n = 0;
+    int32_t n_sel = 0, orb[16] = {}, spin[16] = {};
+    double e0 = 0.0;
+    mcd_band_cfg cfg{};
+    std::vector<double> omega;
+    std::unique_ptr<mcd::BandKeep<float>> kf;
+    std::unique_ptr<mcd::BandKeep<double>> kd;
+};
+
+extern "C" int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                                      const double *psi0_dev, double e0, int32_t n_sel,
+                                      const int32_t *orb, const int32_t *spin, int32_t n_freq,
+                                      const double *omega, const mcd_band_cfg *cfg,
+                                      double *G_out, double *Gp_out, double *Gm_out,
+                                      mcd_solve_info *info, void *stream) {
+    SelOps sel;
+    MCD_TRY(band_args(model, keys_dev, n, psi0_dev, n_sel, orb, spin, n_freq, omega, cfg, G_out,
+                      sel));
     hipStream_t s = (hipStream_t)stream;
     if (cfg->precision == MCD_F64)
         return band_green<double>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg,
@@ -2077,13 +2168,56 @@ extern "C" int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *ke
                              Gp_out, Gm_out, info, s, true);
 }
 
-extern "C" int mcd_band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
-                                  const double *psi0_dev, double e0, int32_t n_sel,
-                                  const int32_t *orb, const int32_t *spin, int32_t n_freq,
-                                  const double *omega, const mcd_band_cfg *cfg,
-                                  const double *G_bar, double e0_bar, double cg_tol,
-                                  int32_t cg_max_iter, double *d_t, double *d_U, double *d_eps,
-                                  mcd_solve_info *info, void *stream) {
+extern "C" int mcd_band_lanczos_green_keep(const mcd_model *model, const uint64_t *keys_dev,
+                                           int64_t n, const double *psi0_dev, double e0,
+                                           int32_t n_sel, const int32_t *orb,
+                                           const int32_t *spin, int32_t n_freq,
+                                           const double *omega, const mcd_band_cfg *cfg,
+                                           double *G_out, double *Gp_out, double *Gm_out,
+                                           mcd_solve_info *info, void *stream,
+                                           mcd_band_keep **keep_out) {
+    MCD_REQUIRE(keep_out, MCD_E_INVALID, "keep_out is NULL");
+    *keep_out = nullptr;
+    SelOps sel;
+    MCD_TRY(band_args(model, keys_dev, n, psi0_dev, n_sel, orb, spin, n_freq, omega, cfg, G_out,
+                      sel));
+    MCD_REQUIRE(cfg->w_t >= 1.0, MCD_E_INVALID, "a kept run needs w_t = 1 (no weight cut)");
+    MCD_REQUIRE(cfg->per_column == 0, MCD_E_INVALID, "a kept run uses block products");
+    std::unique_ptr<mcd_band_keep> k(new mcd_band_keep());
+    k->n = n;
+    k->n_sel = n_sel;
+    for (int q = 0; q < n_sel; q++) {
+        k->orb[q] = orb[q];
+        k->spin[q] = spin[q];
+    }
+    k->e0 = e0;
+    k->cfg = *cfg;
+    k->omega.assign(omega, omega + n_freq);
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if (cfg->precision == MCD_F64) {
+        k->kd.reset(new BandKeep<double>());
+        rc = band_green<double>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg, G_out,
+                                Gp_out, Gm_out, info, s, true, k->kd.get());
+    } else {
+        k->kf.reset(new BandKeep<float>());
+        rc = band_green<float>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg, G_out,
+                               Gp_out, Gm_out, info, s, true, k->kf.get());
+    }
+    if (rc < 0) return rc;   // k and whatever it holds are released
+    *keep_out = k.release();
+    return rc;
+}
+
+extern "C" void mcd_band_keep_destroy(mcd_band_keep *keep) { delete keep; }
+
+static int band_vjp_entry(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                          const double *psi0_dev, double e0, int32_t n_sel, const int32_t *orb,
+                          const int32_t *spin, int32_t n_freq, const double *omega,
+                          const mcd_band_cfg *cfg, const double *G_bar, double e0_bar,
+                          double cg_tol, int32_t cg_max_iter, double *d_t, double *d_U,
+                          double *d_eps, mcd_solve_info *info, void *stream,
+                          mcd_band_keep *keep) {
     MCD_REQUIRE(model && cfg && keys_dev && psi0_dev && orb && spin, MCD_E_INVALID,
                 "a required pointer is NULL");
     MCD_REQUIRE(n >= 1, MCD_E_INVALID, "empty basis");
@@ -2108,11 +2242,53 @@ extern "C" int mcd_band_green_vjp(const mcd_model *model, const uint64_t *keys_d
         sel.spin[q] = spin[q];
     }
     hipStream_t s = (hipStream_t)stream;
+    if (keep) {   // the arguments must be those of the kept forward call
+        bool same = keep->n == n && keep->n_sel == n_sel && keep->e0 == e0 &&
+                    (int64_t)keep->omega.size() == n_freq &&
+                    keep->cfg.max_blocks == cfg->max_blocks &&
+                    keep->cfg.precision == cfg->precision && keep->cfg.dtol == cfg->dtol &&
+                    keep->cfg.storage == cfg->storage && keep->cfg.reorth == cfg->reorth &&
+                    keep->cfg.eta == cfg->eta && keep->cfg.g_tol == cfg->g_tol;
+        for (int q = 0; same && q < n_sel; q++)
+            same = keep->orb[q] == orb[q] && keep->spin[q] == spin[q];
+        for (int f = 0; same && f < n_freq; f++) same = keep->omega[f] == omega[f];
+        MCD_REQUIRE(same, MCD_E_INVALID,
+                    "arguments differ from those of the kept forward call");
+        MCD_REQUIRE(cfg->precision == MCD_F64 ? (bool)keep->kd : (bool)keep->kf, MCD_E_INVALID,
+                    "kept run has another precision");
+    }
     if (cfg->precision == MCD_F64)
         return band_green_vjp<double>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg,
-                                      G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, s);
+                                      G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, s,
+                                      keep ? keep->kd.get() : nullptr);
     return band_green_vjp<float>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg,
-                                 G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, s);
+                                 G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, s,
+                                 keep ? keep->kf.get() : nullptr);
+}
+
+extern "C" int mcd_band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                                  const double *psi0_dev, double e0, int32_t n_sel,
+                                  const int32_t *orb, const int32_t *spin, int32_t n_freq,
+                                  const double *omega, const mcd_band_cfg *cfg,
+                                  const double *G_bar, double e0_bar, double cg_tol,
+                                  int32_t cg_max_iter, double *d_t, double *d_U, double *d_eps,
+                                  mcd_solve_info *info, void *stream) {
+    return band_vjp_entry(model, keys_dev, n, psi0_dev, e0, n_sel, orb, spin, n_freq, omega, cfg,
+                          G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, stream,
+                          nullptr);
+}
+
+extern "C" int mcd_band_green_vjp_keep(const mcd_model *model, const uint64_t *keys_dev,
+                                       int64_t n, const double *psi0_dev, double e0,
+                                       int32_t n_sel, const int32_t *orb, const int32_t *spin,
+                                       int32_t n_freq, const double *omega,
+                                       const mcd_band_cfg *cfg, const double *G_bar,
+                                       double e0_bar, double cg_tol, int32_t cg_max_iter,
+                                       double *d_t, double *d_U, double *d_eps,
+                                       mcd_solve_info *info, void *stream, mcd_band_keep *keep) {
+    MCD_REQUIRE(keep, MCD_E_INVALID, "keep is NULL");
+    return band_vjp_entry(model, keys_dev, n, psi0_dev, e0, n_sel, orb, spin, n_freq, omega, cfg,
+                          G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, stream, keep);
 }
 
 extern "C" int mcd_batch_band_green(const mcd_model *const *models,

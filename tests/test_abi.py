@@ -42,3 +42,16 @@ def test_argument_errors_without_device_work():
     assert b"NULL" in L.mcd_last_error()
     rc = L.mcd_lanczos_ground(None, None, None, None, None, None, None, None, None)
     assert rc == -1
+
+
+def test_kept_band_run_entry_points_reject_null_handles():
+    import paper_2509_22975_amd as mcd
+    L = mcd.lib()
+    L.mcd_band_keep_destroy(None)   # NULL is ignored
+    fwd = [None, None, 0, None, 0.0, 0, None, None, 0, None, None, None, None, None, None, None]
+    assert L.mcd_band_lanczos_green_keep(*fwd, None) == -1
+    assert b"keep_out" in L.mcd_last_error()
+    vjp = [None, None, 0, None, 0.0, 0, None, None, 0, None, None, None, 0.0, 0.0, 0, None,
+           None, None, None, None]
+    assert L.mcd_band_green_vjp_keep(*vjp, None) == -1
+    assert b"keep" in L.mcd_last_error()

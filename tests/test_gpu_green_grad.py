@@ -152,3 +152,75 @@ def test_green_vjp_with_convergence_stop_replays_forward():
             vals.append(float(np.sum((np.conj(Gb) * Gs).real)))
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(got - fd) <= 1e-6 * max(1.0, abs(fd)), (kind, got, fd)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_green_vjp_on_kept_runs_is_bit_identical(prec):
+    """mcd_band_green_vjp_keep on the sector runs kept by the forward call gives
+    exactly the derivative of mcd_band_green_vjp (which recomputes the same
+    runs), twice in a row on one handle; the kept forward's G equals the plain
+    forward's; arguments that differ from the kept call are rejected."""
+    torch, mcd = require_gpu()
+    m = W.impurity_plaquette_bath(6)
+    keys, _ = sampler.chain_c(m, W.neel_start(m), 2, 15000, 500, 10**7)
+    kd = mcd.keys_from_numpy(keys)
+    om = W.matsubara(16, 50.0)
+    orbs, spins = [0, 1, 2, 3], [0, 0, 1, 1]
+    rng = np.random.default_rng(4)
+    Gb = rng.normal(size=(16, 4, 4)) + 1j * rng.normal(size=(16, 4, 4))
+    kw = dict(max_blocks=120, reorth=1, g_tol=1e-8, precision=prec)
+    log_case("green_vjp_keep", n=len(keys), prec=prec)
+    e0, psi = _gpu_ground(mcd, m, kd)
+    G0, info0 = mcd.band_lanczos_green(m, kd, psi, e0, orbs, spins, om, **kw)
+    G1, info1, kept = mcd.band_lanczos_green(m, kd, psi, e0, orbs, spins, om, keep=True, **kw)
+    try:
+        assert np.array_equal(G0, G1) and info0.iters == info1.iters
+        ref = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=0.3, **kw)
+        for _ in range(2):
+            got = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=0.3,
+                                     keep=kept, **kw)
+            for a, b in zip(got[:3], ref[:3]):
+                assert np.array_equal(a, b)
+            assert got[3].krylov_dim == ref[3].krylov_dim
+        bad = dict(kw, max_blocks=119)
+        with pytest.raises(mcd.McdError):
+            mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, keep=kept, **bad)
+        with pytest.raises(mcd.McdError):
+            mcd.band_green_vjp(m, kd, psi, e0, [0, 1, 2, 3], [0, 0, 0, 0], om, Gb, keep=kept,
+                               **kw)
+    finally:
+        kept.close()
+
+
+def test_autograd_green_function_keeps_runs_for_backward():
+    """The autograd Green function keeps its sector runs for the backward;
+    the gradient equals that of the recomputing adjoint."""
+    torch, mcd = require_gpu()
+    from paper_2509_22975_amd.autograd import green_function, impurity_parameters
+    m = W.impurity_plaquette_bath(6)
+    keys, _ = sampler.chain_c(m, W.neel_start(m), 2, 15000, 500, 10**7)
+    kd = mcd.keys_from_numpy(keys)
+    om = W.matsubara(8, 50.0)
+    orbs, spins = [0, 1], [0, 1]
+    kw = dict(max_blocks=100, precision="f32", reorth=1, g_tol=1e-6)
+    log_case("green_autograd_keep", n=len(keys))
+    theta0, expand = impurity_parameters(m)
+    th = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+    t, U, eps = expand(th)
+    e0, G = green_function(m, kd, t, U, eps, orbs, spins, om, **kw)
+    loss = (G.abs() ** 2).sum() + e0
+    loss.backward()
+    # the same derivative from the recomputing adjoint
+    mm = m.with_params(bonds=[(b[0], b[1], float(v)) for b, v in zip(m.bonds, t.detach().numpy())],
+                       U=U.detach().numpy(), eps=eps.detach().numpy())
+    op = mcd.Operator(mm, kd, storage="csr")   # as green_function's forward
+    e0r, psi, *_ = mcd.lanczos_ground(op, max_iter=600, tol=1e-12, seed=11)
+    op.close()
+    Gr, _ = mcd.band_lanczos_green(mm, kd, psi, e0r, orbs, spins, om, **kw)
+    assert np.array_equal(Gr, G.detach().cpu().numpy())
+    d_t, d_U, d_e, _ = mcd.band_green_vjp(mm, kd, psi, e0r, orbs, spins, om, 2 * Gr,
+                                          e0_bar=1.0, **kw)
+    gt, gU, ge = (torch.as_tensor(a) for a in (d_t, d_U, d_e))
+    t2, U2, eps2 = expand(th)
+    ref = torch.autograd.grad((t2 * gt).sum() + (U2 * gU).sum() + (eps2 * ge).sum(), th)[0]
+    assert torch.allclose(th.grad, ref, rtol=1e-12, atol=1e-12)
