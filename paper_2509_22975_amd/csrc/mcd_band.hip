@@ -205,16 +205,20 @@ __device__ __forceinline__ void halve_sum(double *v, int lane) {
 // straight from memory (coalesced, no LDS staging, no barriers in the row
 // loop) and accumulates in float64; the 64 sums are reduced over the
 // wavefront by recursive halving and over the four wavefronts in LDS, in a
-// fixed order.  partial[(m * nch + chunk)][a][b] as for k_gram.
+// fixed order.  partial[(m * nch + chunk)][a][b] as for k_gram.  One
+// dimension of 8 ceil(nch / 8) nm workgroups, handed out XCD-major: the nm
+// workgroups of one row chunk (one per block m) run on one XCD, so that the
+// chunk's X rows are fetched once into its L2 instead of once per block.
 template <typename T, int P>
-__global__ __launch_bounds__(256) void k_gram_rt(int64_t n, int64_t chunk_rows, int nch,
+__global__ __launch_bounds__(256) void k_gram_rt(int64_t n, int64_t chunk_rows, int nch, int nm,
                                                  const T *__restrict__ Q0, int64_t qstride,
                                                  const T *__restrict__ X,
                                                  double *__restrict__ part) {
     static_assert(P == 8 || P == 16, "register-tiled Gram for P = 8, 16");
     constexpr int PP = P * P, TPR = PP / 64, NA = P / TPR, RPB = 256 / TPR;
     __shared__ double red[4][PP];
-    const int m = blockIdx.y, chunk = blockIdx.x;
+    const int k = blockIdx.x / 8, m = k % nm, chunk = (k / nm) * 8 + blockIdx.x % 8;
+    if (chunk >= nch) return;   // whole workgroup, before any barrier
     const T *__restrict__ Q = Q0 + (int64_t)m * qstride;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int qq = t % TPR;
@@ -677,6 +681,7 @@ struct BandRun {
             const int64_t rpb = 256 / (PP / 64);
             nch = (int)std::min<int64_t>(std::max<int64_t>(1, n / (8 * rpb)),
                                          std::max<int64_t>(1, 1024 / nm));
+            if (nch > 8) nch = (nch + 7) / 8 * 8;   // the same number of chunks per XCD
         } else {
             // ~2048 workgroups in total, at least 256 rows per chunk
             nch = (int)std::min<int64_t>(gridn(n, 256), std::max<int64_t>(1, 2048 / nm));
@@ -691,10 +696,10 @@ struct BandRun {
         hipLaunchKernelGGL((k_gram<T, PV>), grid, dim3(BS), 0, s, n, chunk_rows, nch, Q0, \
                            (int64_t)n * P, X, part);                                     \
         break;
-#define GRT(PV)                                                                            \
-    case PV:                                                                               \
-        hipLaunchKernelGGL((k_gram_rt<T, PV>), grid, dim3(256), 0, s, n, chunk_rows, nch, Q0, \
-                           (int64_t)n * P, X, part);                                       \
+#define GRT(PV)                                                                              \
+    case PV:                                                                                 \
+        hipLaunchKernelGGL((k_gram_rt<T, PV>), dim3((unsigned)((nch + 7) / 8 * 8 * nm)),      \
+                           dim3(256), 0, s, n, chunk_rows, nch, nm, Q0, (int64_t)n * P, X, part); \
         break;
         switch (P) {
             GR(1) GR(2) GR(4) GRT(8) GRT(16)
