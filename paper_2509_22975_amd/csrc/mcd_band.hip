@@ -1445,74 +1445,6 @@ __global__ void k_start_block_t(int64_t m, const uint64_t *__restrict__ keys, Se
     lam[r] += acc;
 }
 
-// part[p * gridDim.x + block] = sum over this workgroup's rows r of
-//   sum_a L[r][a] (dH/dtheta_p R)[r][a]
-// for the merged bonds p < nb, then U_i (p = nb + i) and eps_i (nb + no + i).
-// L and R hold nk blocks [k][n][P]; column a = (k, j).  One wavefront per
-// row: the hop target is found once and the wave sums over the nk * P
-// columns; each wave keeps its own accumulators (fixed order).
-static constexpr int kCWaves = 4;
-static constexpr int kMaxParams = MCD_MAX_BONDS + 2 * MCD_MAX_ORB;
-template <typename T>
-__global__ __launch_bounds__(64 * kCWaves) void k_contract_multi(
-    int64_t n, const uint64_t *__restrict__ keys, const DevModel *__restrict__ m,
-    const HashSlot *__restrict__ h, uint64_t hmask, const T *__restrict__ L,
-    const T *__restrict__ R, int nk, int P, double *__restrict__ part) {
-    __shared__ double acc[kCWaves][kMaxParams];
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int nb = m->n_bonds, no = m->n_orb, np = nb + 2 * no;
-    for (int i = lane; i < np; i += 64) acc[wid][i] = 0.0;
-    const int KP = nk * P;
-    const int64_t bstride = n * (int64_t)P;
-    for (int64_t r = (int64_t)blockIdx.x * kCWaves + wid; r < n;
-         r += (int64_t)gridDim.x * kCWaves) {
-        const uint64_t key = keys[r];
-        const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
-        // sum_a L[r][a] R[col][a] over the wave (result in lane 0)
-        auto rowdot = [&](int64_t col) {
-            double s = 0.0;
-            for (int a = lane; a < KP; a += 64) {
-                const int k = a / P, j = a - k * P;
-                s += (double)L[k * bstride + r * P + j] * (double)R[k * bstride + col * P + j];
-            }
-            return wave_sum(s);
-        };
-        for (int q = 0; q < nb; q++) {
-            const uint32_t mask = m->bonds[q].mask, between = m->bonds[q].between;
-            double c = 0.0;
-            if (__popc(up & mask) == 1) {
-                const int64_t col = hash_find(h, hmask, key ^ ((uint64_t)mask << 32));
-                if (col >= 0) {
-                    const double d = rowdot(col);
-                    c += (__popc(up & between) & 1) ? -d : d;
-                }
-            }
-            if (__popc(dn & mask) == 1) {
-                const int64_t col = hash_find(h, hmask, key ^ (uint64_t)mask);
-                if (col >= 0) {
-                    const double d = rowdot(col);
-                    c += (__popc(dn & between) & 1) ? -d : d;
-                }
-            }
-            if (lane == 0) acc[wid][q] += c;
-        }
-        const double d = rowdot(r);
-        if (lane == 0) {
-            for (int i = 0; i < no; i++) {
-                const double nu = (double)((up >> i) & 1u), nd = (double)((dn >> i) & 1u);
-                acc[wid][nb + i] += nu * nd * d;
-                acc[wid][nb + no + i] += (nu + nd) * d;
-            }
-        }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < np; i += 64 * kCWaves) {
-        double s = 0.0;
-        for (int w = 0; w < kCWaves; w++) s += acc[w][i];
-        part[(int64_t)i * gridDim.x + blockIdx.x] = s;
-    }
-}
-
 // Zt = Q M for the adjoint: Q the Krylov store (blocks of n x P, P a power of
 // two; Q[r][k] = block k / P, row r, column k % P, k < KP), M [S][S] row-major
 // and Zt [n][S] row-major, S a multiple of 128 (M and Zt zero past KP).  A
@@ -1603,15 +1535,22 @@ __global__ __launch_bounds__(256) void k_rows_times(int64_t n, int S, int KP, in
         }
 }
 
-// k_contract_multi with R row-major (Rt: [n][S], zero past KP): one wavefront
-// per row r.  The lanes look up all of the row's hop targets at once (lane
-// 2q + s: bond q, spin s), the row L[r] (block-major store, KP = nk P values)
-// is loaded once into registers (NR per lane; NR = 0 re-reads it, any S), and
-// the hops are then taken in lane order, each a gather of the contiguous row
-// Rt[col] with all NR loads issued together: loads past column S read the
+static constexpr int kCWaves = 4;
+static constexpr int kMaxParams = MCD_MAX_BONDS + 2 * MCD_MAX_ORB;
+
+// part[p * gridDim.x + block] = sum over this workgroup's rows r of
+//   sum_a L[r][a] (dH/dtheta_p R)[r][a]
+// for the merged bonds p < nb, then U_i (p = nb + i) and eps_i (nb + no + i);
+// L is a block-major Krylov store (KP = nk P columns, column a = block a / P,
+// entry a % P), R is row-major (Rt: [n][S], zero past KP).  One wavefront per
+// row r.  The lanes look up all of the row's hop targets at once (lane
+// 2q + s: bond q, spin s), the row L[r] is loaded once into registers (NR
+// values per lane; NR = 0 re-reads it, any S), and the hops are then taken in
+// lane order (bond by bond, up spin first), each a gather of the contiguous
+// row Rt[col] with all NR loads issued together: loads past column S read the
 // next row (or a zeroed tail of at least 64 (NR - S / 64) values after the
-// last row) and meet zero weights.  Per row the terms and their order match
-// k_contract_multi.
+// last row) and meet zero weights.  Each wave keeps its own accumulators
+// (fixed order).
 template <typename T, int NR>
 __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
     int64_t n, const uint64_t *__restrict__ keys, const DevModel *__restrict__ m,
@@ -1924,51 +1863,33 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             // about 16 rows per wavefront
             const unsigned g =
                 (unsigned)std::min<int64_t>(cblk, (nx + 16 * kCWaves - 1) / (16 * kCWaves));
-            // Z = Q M as one product into a row-major Zt [nx][S] when memory
-            // allows, else block by block on the block-major store.
+            // Z = Q M as one product into a row-major Zt [nx][S] (the size of
+            // the Krylov store it is made from), then the contraction
             const int S = (KP + 127) / 128 * 128;
             int pl = 0;
             while ((1 << pl) < P) pl++;
-            T *Zt = nullptr, *Md = nullptr, *Z = nullptr;
-            std::vector<T> Mp;
-            size_t fr = 0, tot = 0;
             constexpr int kTail = 1024;   // zeroed values after the last row of Zt
-            const size_t rows_bytes = ((size_t)nx * S + kTail) * sizeof(T);
-            if (hipMemGetInfo(&fr, &tot) == hipSuccess && (double)rows_bytes < 0.5 * (double)fr &&
-                dmalloc((void **)&Zt, rows_bytes, A) == hipSuccess &&
-                dmalloc((void **)&Md, (size_t)S * S * sizeof(T), A) == hipSuccess) {
-                Mp.assign((size_t)S * S, (T)0);
-                for (int i = 0; i < KP; i++)
-                    for (int j = 0; j < KP; j++) Mp[(size_t)i * S + j] = (T)M[(size_t)i * KP + j];
-                if (hipMemcpyAsync(Md, Mp.data(), Mp.size() * sizeof(T), hipMemcpyHostToDevice,
-                                   s) != hipSuccess ||
-                    hipMemsetAsync(Zt + (size_t)nx * S, 0, kTail * sizeof(T), s) != hipSuccess)
-                    rc = MCD_E_HIP;
-                if (rc == MCD_OK) {
-                    const int64_t tiles = (nx + 127) / 128 * (S / 128);
-                    hipLaunchKernelGGL((k_rows_times<T>), dim3((unsigned)((tiles + 7) / 8 * 8)),
-                                       dim3(256), 0, s, nx, S, KP, pl, run.blk(0), Md, Zt);
-                    launch_contract_rows<T>(g, s, nx, op, run.blk(0), KP, pl, Zt, S, part);
-                }
-            } else {
+            T *Zt = nullptr, *Md = nullptr;
+            std::vector<T> Mp((size_t)S * S, (T)0);
+            for (int i = 0; i < KP; i++)
+                for (int j = 0; j < KP; j++) Mp[(size_t)i * S + j] = (T)M[(size_t)i * KP + j];
+            if (dmalloc((void **)&Zt, ((size_t)nx * S + kTail) * sizeof(T), A) != hipSuccess ||
+                dmalloc((void **)&Md, (size_t)S * S * sizeof(T), A) != hipSuccess) {
                 (void)hipGetLastError();
-                // Z_k = sum_j Q_j M[j-block, k-block]  (W -= sum Q (-C))
-                if (dmalloc((void **)&Z, (size_t)m * nx * P * sizeof(T), A) != hipSuccess)
-                    rc = MCD_E_HIP;
-                for (int k = 0; k < m && rc == MCD_OK; k++) {
-                    for (int j = 0; j < m; j++)
-                        for (int a = 0; a < P; a++)
-                            for (int b = 0; b < P; b++)
-                                C[((size_t)j * P + a) * P + b] = -M[((size_t)j * P + a) * KP + k * P + b];
-                    T *Zk = Z + (size_t)k * nx * P;
-                    if (hipMemsetAsync(Zk, 0, (size_t)nx * P * sizeof(T), s) != hipSuccess)
-                        rc = MCD_E_HIP;
-                    if (rc == MCD_OK) rc = run.block_apply(run.blk(0), m, C, Zk, true);
-                }
-                if (rc == MCD_OK)
-                    hipLaunchKernelGGL((k_contract_multi<T>), dim3(g), dim3(64 * kCWaves), 0, s,
-                                       nx, op->d_keys, op->d_model, op->d_hash, op->hash_mask,
-                                       run.blk(0), Z, m, P, part);
+                set_error("green vjp: no device memory for Z = Q M (%.1f GB)",
+                          (double)nx * S * sizeof(T) / 1e9);
+                rc = MCD_E_CAPACITY;
+            }
+            if (rc == MCD_OK &&
+                (hipMemcpyAsync(Md, Mp.data(), Mp.size() * sizeof(T), hipMemcpyHostToDevice, s) !=
+                     hipSuccess ||
+                 hipMemsetAsync(Zt + (size_t)nx * S, 0, kTail * sizeof(T), s) != hipSuccess))
+                rc = MCD_E_HIP;
+            if (rc == MCD_OK) {
+                const int64_t tiles = (nx + 127) / 128 * (S / 128);
+                hipLaunchKernelGGL((k_rows_times<T>), dim3((unsigned)((tiles + 7) / 8 * 8)),
+                                   dim3(256), 0, s, nx, S, KP, pl, run.blk(0), Md, Zt);
+                launch_contract_rows<T>(g, s, nx, op, run.blk(0), KP, pl, Zt, S, part);
             }
             if (rc == MCD_OK) {
                 hipLaunchKernelGGL(k_param_reduce, dim3((np + 3) / 4), dim3(256), 0, s, np, (int)g,
@@ -1992,7 +1913,7 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
                 if (hipGetLastError() != hipSuccess) rc = MCD_E_HIP;
             }
             if (hipStreamSynchronize(s) != hipSuccess && rc == MCD_OK) rc = MCD_E_HIP;
-            for (T *q : {Z, Zt, Md})
+            for (T *q : {Zt, Md})
                 if (q) (void)dfree(q, A);
             if (rc == MCD_E_HIP) set_error("green vjp: device step failed in a sector hook");
             return rc;

@@ -60,15 +60,19 @@ def test_green_real_frequency_vs_oracle():
     assert np.all(-G[:, np.arange(3), np.arange(3)].imag >= -1e-12)
 
 
-@pytest.mark.parametrize("case", ["full_matsubara", "sampled_matsubara", "sampled_real"])
+@pytest.mark.parametrize("case", ["full_matsubara", "sampled_matsubara", "sampled_real",
+                                  "single_orbital"])
 def test_green_vjp_vs_oracle_finite_differences(case):
+    """Selections of 3 operators (block width P = 4) and of one (P = 1: the
+    scalar-load path of the Z = Q M product)."""
     torch, mcd = require_gpu()
     m, keys = _tiny(sampled=case != "full_matsubara")
     eta = 0.05 if case == "sampled_real" else 0.0
     om = np.linspace(-3, 3, 5) if eta else W.matsubara(6, 20.0)
-    orbs, spins = [0, 1, 2], [0, 0, 1]
+    orbs, spins = ([1], [1]) if case == "single_orbital" else ([0, 1, 2], [0, 0, 1])
+    ns = len(orbs)
     rng = np.random.default_rng(7)
-    Gb = rng.normal(size=(len(om), 3, 3)) + 1j * rng.normal(size=(len(om), 3, 3))
+    Gb = rng.normal(size=(len(om), ns, ns)) + 1j * rng.normal(size=(len(om), ns, ns))
     e0_bar = 0.37
     log_case("green_vjp", case=case, n=len(keys))
     kd = mcd.keys_from_numpy(keys)
