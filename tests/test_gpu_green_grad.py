@@ -228,3 +228,29 @@ def test_autograd_green_function_keeps_runs_for_backward():
     t2, U2, eps2 = expand(th)
     ref = torch.autograd.grad((t2 * gt).sum() + (U2 * gU).sum() + (eps2 * ge).sum(), th)[0]
     assert torch.allclose(th.grad, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_green_vjp_wide_krylov_paths_agree():
+    """Block width P = 16 (12 selected operators) with 120 and 140 block steps:
+    m P = 1920 runs the contraction with the Krylov row in registers, m P =
+    2240 its re-reading form (more than 2048 columns).  Both Green functions
+    are converged, so G and the gradient agree between the two."""
+    torch, mcd = require_gpu()
+    m = W.impurity_plaquette_bath(6)
+    keys, _ = sampler.chain_c(m, W.neel_start(m), 2, 15000, 500, 10**7)
+    kd = mcd.keys_from_numpy(keys)
+    om = W.matsubara(8, 50.0)
+    orbs, spins = list(range(6)) * 2, [0] * 6 + [1] * 6
+    rng = np.random.default_rng(5)
+    Gb = rng.normal(size=(8, 12, 12)) + 1j * rng.normal(size=(8, 12, 12))
+    log_case("green_vjp_wide", n=len(keys))
+    e0, psi = _gpu_ground(mcd, m, kd)
+    out = {}
+    for mb in (120, 140):
+        kw = dict(max_blocks=mb, reorth=1, precision="f64")
+        G, info = mcd.band_lanczos_green(m, kd, psi, e0, orbs, spins, om, **kw)
+        assert info.iters == mb
+        d = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=0.2, **kw)
+        out[mb] = (G, np.concatenate(d[:3]))
+    assert _rel(out[140][0], out[120][0]) < 1e-8
+    assert _rel(out[140][1], out[120][1]) < 1e-6
