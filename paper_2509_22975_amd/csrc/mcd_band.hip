@@ -199,23 +199,26 @@ __device__ __forceinline__ void halve_sum(double *v, int lane) {
     }
 }
 
-// Partial Gram matrices for P = 8 and 16, register-tiled: a thread owns 64
-// of the P x P products (P = 8: all of them, one row per thread; P = 16: a
-// quarter, rows a in [4 qq, 4 qq + 4), four threads per row), reads its rows
+// Partial Gram matrices for P = 8 and 16, register-tiled: TPR threads share
+// a row and each owns P^2 / TPR of its products (rows a in [NA qq, NA qq +
+// NA), NA = P / TPR, all b): P = 8 in float32, TPR = 1 (64 products); P = 8
+// in float64, TPR = 2 (32 products: half the registers, twice the waves of
+// the one-thread form); P = 16, TPR = 4 (64).  A thread reads its rows
 // straight from memory (coalesced, no LDS staging, no barriers in the row
-// loop) and accumulates in float64; the 64 sums are reduced over the
-// wavefront by recursive halving and over the four wavefronts in LDS, in a
+// loop) and accumulates in float64; the sums are reduced over the lanes of
+// equal qq by recursive halving and over the four wavefronts in LDS, in a
 // fixed order.  partial[(m * nch + chunk)][a][b] as for k_gram.  One
 // dimension of 8 ceil(nch / 8) nm workgroups, handed out XCD-major: the nm
 // workgroups of one row chunk (one per block m) run on one XCD, so that the
 // chunk's X rows are fetched once into its L2 instead of once per block.
-template <typename T, int P>
+template <typename T, int P, int TPR>
 __global__ __launch_bounds__(256) void k_gram_rt(int64_t n, int64_t chunk_rows, int nch, int nm,
                                                  const T *__restrict__ Q0, int64_t qstride,
                                                  const T *__restrict__ X,
                                                  double *__restrict__ part) {
-    static_assert(P == 8 || P == 16, "register-tiled Gram for P = 8, 16");
-    constexpr int PP = P * P, TPR = PP / 64, NA = P / TPR, RPB = 256 / TPR;
+    static_assert((P == 8 && (TPR == 1 || TPR == 2)) || (P == 16 && TPR == 4),
+                  "register-tiled Gram for P = 8, 16");
+    constexpr int PP = P * P, NA = P / TPR, NV = NA * P, RPB = 256 / TPR;
     __shared__ double red[4][PP];
     const int k = blockIdx.x / 8, m = k % nm, chunk = (k / nm) * 8 + blockIdx.x % 8;
     if (chunk >= nch) return;   // whole workgroup, before any barrier
@@ -224,9 +227,9 @@ __global__ __launch_bounds__(256) void k_gram_rt(int64_t n, int64_t chunk_rows, 
     const int qq = t % TPR;
     const int64_t r0 = (int64_t)chunk * chunk_rows;
     const int64_t r1 = min(r0 + chunk_rows, n);
-    double v[64];
+    double v[NV];
 #pragma unroll
-    for (int i = 0; i < 64; i++) v[i] = 0.0;
+    for (int i = 0; i < NV; i++) v[i] = 0.0;
 #pragma unroll 2
     for (int64_t r = r0 + t / TPR; r < r1; r += RPB) {
         T qa[NA], xb[P];
@@ -239,15 +242,27 @@ __global__ __launch_bounds__(256) void k_gram_rt(int64_t n, int64_t chunk_rows, 
 #pragma unroll
             for (int b = 0; b < P; b++) v[i * P + b] += (double)qa[i] * (double)xb[b];
     }
-    halve_sum<32, 32>(v, lane);
-    halve_sum<16, 16>(v, lane);
-    halve_sum<8, 8>(v, lane);
-    halve_sum<4, 4>(v, lane);
-    if (TPR == 1) {
+    if constexpr (TPR == 1) {
+        halve_sum<32, 32>(v, lane);
+        halve_sum<16, 16>(v, lane);
+        halve_sum<8, 8>(v, lane);
+        halve_sum<4, 4>(v, lane);
         halve_sum<2, 2>(v, lane);
         halve_sum<1, 1>(v, lane);
         red[w][lane] = v[0];   // value index = lane
+    } else if constexpr (TPR == 2) {
+        halve_sum<16, 32>(v, lane);
+        halve_sum<8, 16>(v, lane);
+        halve_sum<4, 8>(v, lane);
+        halve_sum<2, 4>(v, lane);
+        halve_sum<1, 2>(v, lane);
+        // lane l holds value (l >> 1) of its half qq = l & 1
+        red[w][32 * (lane & 1) + (lane >> 1)] = v[0];
     } else {
+        halve_sum<32, 32>(v, lane);
+        halve_sum<16, 16>(v, lane);
+        halve_sum<8, 8>(v, lane);
+        halve_sum<4, 4>(v, lane);
         // lane l holds values (l & ~3) + j of its quarter qq = l & 3
 #pragma unroll
         for (int j = 0; j < 4; j++) red[w][64 * (lane & 3) + (lane & ~3) + j] = v[j];
@@ -677,11 +692,18 @@ struct BandRun {
         const int PP = P * P;
         int nch;
         if (P >= 8) {
-            // register-tiled kernel: >= 8 rows per thread slot, ~1024 workgroups
-            const int64_t rpb = 256 / (PP / 64);
-            nch = (int)std::min<int64_t>(std::max<int64_t>(1, n / (8 * rpb)),
-                                         std::max<int64_t>(1, 1024 / nm));
-            if (nch > 8) nch = (nch + 7) / 8 * 8;   // the same number of chunks per XCD
+            // register-tiled kernel: >= 8 rows per thread slot, ~1024
+            // workgroups, and chunks small enough that a chunk's X rows (read
+            // by all nm workgroups of the chunk on one XCD) stay within 2 MB of
+            // its L2; at most 65536 / nm chunks (the partials' capacity)
+            const int64_t rpb = 256 / (P == 16 ? 4 : sizeof(T) == 8 ? 2 : 1);
+            const int64_t fit = ((int64_t)n * P * (int64_t)sizeof(T) + (2 << 20) - 1) / (2 << 20);
+            const int64_t cap = std::max<int64_t>(1, 65536 / nm);
+            nch = (int)std::min<int64_t>(
+                cap, std::min<int64_t>(std::max<int64_t>(1, n / (8 * rpb)),
+                                       std::max<int64_t>(fit, std::max<int64_t>(1, 1024 / nm))));
+            if (nch > 8)   // the same number of chunks per XCD
+                nch = (int)std::min<int64_t>((nch + 7) / 8 * 8, cap / 8 * 8);
         } else {
             // ~2048 workgroups in total, at least 256 rows per chunk
             nch = (int)std::min<int64_t>(gridn(n, 256), std::max<int64_t>(1, 2048 / nm));
@@ -696,13 +718,20 @@ struct BandRun {
         hipLaunchKernelGGL((k_gram<T, PV>), grid, dim3(BS), 0, s, n, chunk_rows, nch, Q0, \
                            (int64_t)n * P, X, part);                                     \
         break;
-#define GRT(PV)                                                                              \
-    case PV:                                                                                 \
-        hipLaunchKernelGGL((k_gram_rt<T, PV>), dim3((unsigned)((nch + 7) / 8 * 8 * nm)),      \
-                           dim3(256), 0, s, n, chunk_rows, nch, nm, Q0, (int64_t)n * P, X, part); \
-        break;
+#define GRT(PV, TV)                                                                          \
+    hipLaunchKernelGGL((k_gram_rt<T, PV, TV>), dim3((unsigned)((nch + 7) / 8 * 8 * nm)),      \
+                       dim3(256), 0, s, n, chunk_rows, nch, nm, Q0, (int64_t)n * P, X, part)
         switch (P) {
-            GR(1) GR(2) GR(4) GRT(8) GRT(16)
+            GR(1) GR(2) GR(4)
+        case 8:
+            if (sizeof(T) == 8)
+                GRT(8, 2);
+            else
+                GRT(8, 1);
+            break;
+        case 16:
+            GRT(16, 4);
+            break;
         }
 #undef GR
 #undef GRT
