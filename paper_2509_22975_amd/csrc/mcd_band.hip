@@ -543,12 +543,14 @@ __global__ __launch_bounds__(64) void k_sym_pair(int P, const double *__restrict
 // of R = sqrt(d)^-1 (Schur row), and the Schur complement is updated.  With
 // rank r, W = Q R (R: r x P, zero rows below), Q = W Xm with
 // Xm = Pi R11^-1 (zero columns beyond r).  Bacc <- R Bacc (R itself when
-// init), *rank_out = r.
+// init), also written to Bcopy when not NULL (the factor's place in T);
+// *rank_out = r.
 __global__ __launch_bounds__(64) void k_pchol(int P, const double *__restrict__ M, int mode,
                                               double thr_abs, double *__restrict__ Xm,
                                               double *__restrict__ Bm,
                                               double *__restrict__ Bacc, int init,
-                                              int *__restrict__ rank_out) {
+                                              int *__restrict__ rank_out,
+                                              double *__restrict__ Bcopy) {
     __shared__ double S[16][16];
     __shared__ double R[16][16];
     __shared__ double Ri[16][16];
@@ -627,7 +629,10 @@ __global__ __launch_bounds__(64) void k_pchol(int P, const double *__restrict__ 
         Bt[a][b] = acc;
     }
     __syncthreads();
-    for (int e = t; e < P * P; e += 64) Bacc[e] = Bt[e / P][e % P];
+    for (int e = t; e < P * P; e += 64) {
+        Bacc[e] = Bt[e / P][e % P];
+        if (Bcopy) Bcopy[e] = Bt[e / P][e % P];   // the final factor, stored in place
+    }
     if (t == 0) *rank_out = r;
 }
 
@@ -876,12 +881,11 @@ struct BandRun {
                 MCD_TRY(gram_dev(cur, 1, cur));
                 hipLaunchKernelGGL(k_pchol, dim3(1), dim3(64), 0, s, P, dG, pass,
                                    dtol_abs * dtol_abs, dXm, dBm, dBacc, pass == 0 ? 1 : 0,
-                                   d_rank + slot);
+                                   d_rank + slot, pass == 1 ? outB : nullptr);
                 T *out = pass == 0 ? W2 : dst;
                 MCD_TRY(block_apply_dev(cur, 1, dXm, out, false));
                 cur = out;
             }
-            MCD_HIP(hipMemcpyAsync(outB, dBacc, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
             return MCD_OK;
         };
         std::vector<int> rank(max_blocks + 2, -1);

@@ -198,7 +198,11 @@ def test_green_vjp_on_kept_runs_is_bit_identical(prec):
 
 def test_autograd_green_function_keeps_runs_for_backward():
     """The autograd Green function keeps its sector runs for the backward;
-    the gradient equals that of the recomputing adjoint."""
+    the gradient equals that of the recomputing adjoint.  The reference
+    builds its own operator, whose autotuned product kernel may add a row's
+    terms in another order than the autograd forward's (merge path vs row
+    major), so the two ground states, and with them G and the gradient, agree
+    to rounding rather than bit for bit."""
     torch, mcd = require_gpu()
     from paper_2509_22975_amd.autograd import green_function, impurity_parameters
     m = W.impurity_plaquette_bath(6)
@@ -221,13 +225,13 @@ def test_autograd_green_function_keeps_runs_for_backward():
     e0r, psi, *_ = mcd.lanczos_ground(op, max_iter=600, tol=1e-12, seed=11)
     op.close()
     Gr, _ = mcd.band_lanczos_green(mm, kd, psi, e0r, orbs, spins, om, **kw)
-    assert np.array_equal(Gr, G.detach().cpu().numpy())
+    assert _rel(G.detach().cpu().numpy(), Gr) < 1e-10
     d_t, d_U, d_e, _ = mcd.band_green_vjp(mm, kd, psi, e0r, orbs, spins, om, 2 * Gr,
                                           e0_bar=1.0, **kw)
     gt, gU, ge = (torch.as_tensor(a) for a in (d_t, d_U, d_e))
     t2, U2, eps2 = expand(th)
     ref = torch.autograd.grad((t2 * gt).sum() + (U2 * gU).sum() + (eps2 * ge).sum(), th)[0]
-    assert torch.allclose(th.grad, ref, rtol=1e-12, atol=1e-12)
+    assert _rel(th.grad.numpy(), ref.numpy()) < 1e-8
 
 
 def test_green_vjp_wide_krylov_paths_agree():
