@@ -195,8 +195,13 @@ int mcd_op_info(const mcd_op *op, mcd_op_info_t *info);
  *       creation when the basis has up-string segments of >= 16 rows on
  *       average and every block fits 128 groups (mcd_op_info_t.grouped_blocks);
  *   8 = 7 in XCD-major order.
- * All give the same result up to summation order.  At creation a CSR
- * operator times every kernel on its own matrix and keeps the fastest.
+ * All give the same result up to summation order: kernels 1, 3, 5, 6, 7
+ * and 8 add each row's terms in the same order (bit-identical y); 2 and 4
+ * associate a row's sum differently (last-bit differences).  At creation a
+ * CSR operator times every kernel on its own matrix and keeps the fastest,
+ * so two operators of one basis may pick kernels of the two kinds: select
+ * one here for results that are reproducible bit for bit across operators
+ * and runs (a fixed kernel is deterministic).
  * MCD_E_INVALID for other values, an on-the-fly operator, or 7 / 8 on an
  * operator without the grouped layout. */
 int mcd_op_set_kernel(mcd_op *op, int32_t kernel);
