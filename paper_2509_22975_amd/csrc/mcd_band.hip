@@ -364,19 +364,20 @@ __global__ __launch_bounds__(BS) void k_block_apply_r(int64_t n, int nm, const T
     }
 }
 
-// W (-)= sum_m Q_m C_m for nm blocks (C on the device), one launch.
+// W (-)= sum_m Q_m C_m for nm blocks (C on the device), one launch; block m
+// at Q0 + m qstride (elements, any sign).
 template <typename T, int P>
-static void launch_block_apply(int64_t n, int nm, const T *Q0, const double *C, T *W, bool sub,
-                               hipStream_t s) {
+static void launch_block_apply(int64_t n, int nm, const T *Q0, int64_t qstride, const double *C,
+                               T *W, bool sub, hipStream_t s) {
     const size_t lds = (size_t)nm * P * P * sizeof(double);
     if constexpr (P * sizeof(T) % 16 == 0) {
         const unsigned nb = (unsigned)std::min<int64_t>(gridn(n, BS), 8192);
         hipLaunchKernelGGL((k_block_apply_r<T, P>), dim3(nb), dim3(BS), lds, s, n, nm, Q0,
-                           (int64_t)n * P, C, W, sub ? 1 : 0);
+                           qstride, C, W, sub ? 1 : 0);
     } else {
         const unsigned nb = (unsigned)std::min<int64_t>(gridn(n, BS / P), 4096);
         hipLaunchKernelGGL((k_block_apply<T, P>), dim3(nb), dim3(BS), lds, s, n, nm, Q0,
-                           (int64_t)n * P, C, W, sub ? 1 : 0);
+                           qstride, C, W, sub ? 1 : 0);
     }
 }
 
@@ -748,17 +749,20 @@ struct BandRun {
     }
 
     // W (-)= sum_m Q_m C_m with C already on the device ([nm][P][P]).
-    int block_apply_dev(const T *Q0, int nm, const double *C, T *Wout, bool sub) {
+    // Block m at Q0 + m qstride (elements; default n P, the contiguous store).
+    int block_apply_dev(const T *Q0, int nm, const double *C, T *Wout, bool sub,
+                        int64_t qstride = 0) {
         const int PP = P * P;
         const int group = std::max(1, (48 * 1024) / (PP * 8));
+        if (qstride == 0) qstride = (int64_t)n * P;
         MCD_REQUIRE(sub || nm <= group, MCD_E_INVALID, "assigning block product must use one group");
         for (int g0 = 0; g0 < nm; g0 += group) {
             const int g = std::min(group, nm - g0);
-            const T *q = Q0 + (int64_t)g0 * n * P;
+            const T *q = Q0 + (int64_t)g0 * qstride;
             const double *c = C + (size_t)g0 * PP;
 #define BAD(PV)                                                     \
     case PV:                                                        \
-        launch_block_apply<T, PV>(n, g, q, c, Wout, sub, s);        \
+        launch_block_apply<T, PV>(n, g, q, qstride, c, Wout, sub, s); \
         break;
             switch (P) {
                 BAD(1) BAD(2) BAD(4) BAD(8) BAD(16)
@@ -780,7 +784,7 @@ struct BandRun {
             const T *q = Q0 + (int64_t)g0 * n * P;
 #define BA(PV)                                                      \
     case PV:                                                        \
-        launch_block_apply<T, PV>(n, g, q, dC, Wout, sub, s);       \
+        launch_block_apply<T, PV>(n, g, q, (int64_t)n * P, dC, Wout, sub, s); \
         break;
             switch (P) {
                 BA(1) BA(2) BA(4) BA(8) BA(16)
@@ -924,17 +928,18 @@ struct BandRun {
             for (int j = 0; j < max_blocks; j++) {
                 DTRY(apply_any(op, sizeof(T) == 8 ? MCD_F64 : MCD_F32, P, blk(j), W, s));
                 DTRY(gram_dev(blk(j), 1, W));
-                // W -= Q_{j-1} B_j^T + Q_j A_j: one pass when the two blocks
-                // are adjacent in the store
+                // W -= Q_{j-1} B_j^T + Q_j A_j in one pass (both terms summed
+                // in float64, then subtracted), with the stride between the
+                // two blocks as stored: negative where the three-block ring of
+                // reorth = 0 wraps, so a run gives the same result whether it
+                // keeps three blocks or all of them
                 hipLaunchKernelGGL(k_sym_pair, dim3(1), dim3(64), 0, s, P, dG,
                                    dA + (size_t)j * PP, j > 0 ? dB + (size_t)j * PP : nullptr,
                                    dC2);
-                if (j > 0 && blk(j) == blk(j - 1) + (int64_t)n * P) {
-                    DTRY(block_apply_dev(blk(j - 1), 2, dC2, W, true));
-                } else {
+                if (j > 0)
+                    DTRY(block_apply_dev(blk(j - 1), 2, dC2, W, true, blk(j) - blk(j - 1)));
+                else
                     DTRY(block_apply_dev(blk(j), 1, dC2 + PP, W, true));
-                    if (j > 0) DTRY(block_apply_dev(blk(j - 1), 1, dC2, W, true));
-                }
                 for (int pass = 0; pass < reorth; pass++) {
                     DTRY(gram_dev(blk(0), j + 1, W));
                     DTRY(block_apply_dev(blk(0), j + 1, dG, W, true));

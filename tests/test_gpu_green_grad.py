@@ -158,12 +158,13 @@ def test_green_vjp_with_convergence_stop_replays_forward():
         assert abs(got - fd) <= 1e-6 * max(1.0, abs(fd)), (kind, got, fd)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_green_vjp_on_kept_runs_is_bit_identical(prec):
+@pytest.mark.parametrize("prec,reorth", [("f64", 1), ("f32", 1), ("f32", 0)])
+def test_green_vjp_on_kept_runs_is_bit_identical(prec, reorth):
     """mcd_band_green_vjp_keep on the sector runs kept by the forward call gives
     exactly the derivative of mcd_band_green_vjp (which recomputes the same
     runs), twice in a row on one handle; the kept forward's G equals the plain
-    forward's; arguments that differ from the kept call are rejected."""
+    forward's (with reorth = 0 the plain forward stores three blocks, the kept
+    one all of them); arguments that differ from the kept call are rejected."""
     torch, mcd = require_gpu()
     m = W.impurity_plaquette_bath(6)
     keys, _ = sampler.chain_c(m, W.neel_start(m), 2, 15000, 500, 10**7)
@@ -172,8 +173,8 @@ def test_green_vjp_on_kept_runs_is_bit_identical(prec):
     orbs, spins = [0, 1, 2, 3], [0, 0, 1, 1]
     rng = np.random.default_rng(4)
     Gb = rng.normal(size=(16, 4, 4)) + 1j * rng.normal(size=(16, 4, 4))
-    kw = dict(max_blocks=120, reorth=1, g_tol=1e-8, precision=prec)
-    log_case("green_vjp_keep", n=len(keys), prec=prec)
+    kw = dict(max_blocks=120, reorth=reorth, g_tol=1e-8, precision=prec)
+    log_case("green_vjp_keep", n=len(keys), prec=prec, reorth=reorth)
     e0, psi = _gpu_ground(mcd, m, kd)
     G0, info0 = mcd.band_lanczos_green(m, kd, psi, e0, orbs, spins, om, **kw)
     G1, info1, kept = mcd.band_lanczos_green(m, kd, psi, e0, orbs, spins, om, keep=True, **kw)
