@@ -303,7 +303,9 @@ def gradients_c4(mcd, W, torch, blocks=200):
     (eps_b, V_ib, U) of the 2x2 + 8 bath model on 0.5M chain states, 32
     Matsubara frequencies, p = 8: forward (E0, G) + one backward pass of the
     loss sum |G|^2 + E0, float64 (full reorthogonalisation) and float32 Krylov
-    blocks (one pass).  Finite differences would need 66 forward solves."""
+    blocks (one pass), and both without reorthogonalisation (the gradient of
+    each against the first).  Finite differences would need 66 forward
+    solves."""
     from paper_2509_22975_amd.autograd import green_function, impurity_parameters
     c = W.config_c3(3)
     m = c["model"]
@@ -318,7 +320,9 @@ def gradients_c4(mcd, W, torch, blocks=200):
                        "converged (g_tol 1e-9 float64, 1e-6 float32; <= %d blocks)" % blocks,
            "n_states": int(keys.numel())}
     grads = {}
-    for name, prec, reorth, gt in (("f64", "f64", 2, 1e-9), ("f32", "f32", 1, 1e-6)):
+    for name, prec, reorth, gt in (("f64", "f64", 2, 1e-9), ("f32", "f32", 1, 1e-6),
+                                   ("f64_no_reorth", "f64", 0, 1e-9),
+                                   ("f32_no_reorth", "f32", 0, 1e-6)):
         th = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
         t, U, eps = expand(th)
         torch.cuda.synchronize()
@@ -333,8 +337,9 @@ def gradients_c4(mcd, W, torch, blocks=200):
         grads[name] = th.grad.clone()
         out[name] = {"reorth_passes": reorth, "g_tol": gt, "forward_s": round(t1 - t0, 3),
                      "backward_s": round(t2 - t1, 3)}
-    out["f32"]["max_rel_grad_diff_vs_f64"] = float(
-        (grads["f32"] - grads["f64"]).abs().max() / grads["f64"].abs().max())
+    for name in ("f32", "f64_no_reorth", "f32_no_reorth"):
+        out[name]["max_rel_grad_diff_vs_f64"] = float(
+            (grads[name] - grads["f64"]).abs().max() / grads["f64"].abs().max())
     # central differences (h = 1e-5) of the same loss through the float64
     # forward solve, for a bath energy, a hybridisation and U
     def loss_at(theta):
