@@ -1588,7 +1588,10 @@ static constexpr int kMaxParams = MCD_MAX_BONDS + 2 * MCD_MAX_ORB;
 // row Rt[col] with all NR loads issued together: loads past column S read the
 // next row (or a zeroed tail of at least 64 (NR - S / 64) values after the
 // last row) and meet zero weights.  Each wave keeps its own accumulators
-// (fixed order).
+// (fixed order).  Symmetric form: with Rt = L (M + M^T) row-major, a hop pair
+// r <-> c (same bond, same sign both ways) adds L[r].Rt'[c] + L[c].Rt'[r] =
+// L[r].Rt[c] for Rt' = L M, so only hops with c > r are taken (half the
+// gathers), and the diagonal term is L[r].Rt[r] / 2.
 template <typename T, int NR>
 __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
     int64_t n, const uint64_t *__restrict__ keys, const DevModel *__restrict__ m,
@@ -1636,6 +1639,7 @@ __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
                 if (__popc(sp & mask) == 1) {
                     col = hash_find(h, hmask, key ^ ((uint64_t)mask << ((hl & 1) ? 0 : 32)));
                     neg = __popc(sp & between) & 1;
+                    if (col <= r) col = -1;   // each pair once (from its lower row)
                 }
             }
             uint64_t live = __ballot(col >= 0);
@@ -1660,7 +1664,7 @@ __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
             }
             if (cur >= 0 && lane == 0) acc[wid][cur] += c;
         }
-        const double d = rowdot(r);
+        const double d = 0.5 * rowdot(r);
         if (lane == 0) {
             for (int i = 0; i < no; i++) {
                 const double nu = (double)((up >> i) & 1u), nd = (double)((dn >> i) & 1u);
@@ -1901,8 +1905,9 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             // about 16 rows per wavefront
             const unsigned g =
                 (unsigned)std::min<int64_t>(cblk, (nx + 16 * kCWaves - 1) / (16 * kCWaves));
-            // Z = Q M as one product into a row-major Zt [nx][S] (the size of
-            // the Krylov store it is made from), then the contraction
+            // Z = Q (M + M^T) as one product into a row-major Zt [nx][S] (the
+            // size of the Krylov store it is made from), then the contraction
+            // (symmetric form: each hop pair once)
             const int S = (KP + 127) / 128 * 128;
             int pl = 0;
             while ((1 << pl) < P) pl++;
@@ -1910,7 +1915,8 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             T *Zt = nullptr, *Md = nullptr;
             std::vector<T> Mp((size_t)S * S, (T)0);
             for (int i = 0; i < KP; i++)
-                for (int j = 0; j < KP; j++) Mp[(size_t)i * S + j] = (T)M[(size_t)i * KP + j];
+                for (int j = 0; j < KP; j++)
+                    Mp[(size_t)i * S + j] = (T)(M[(size_t)i * KP + j] + M[(size_t)j * KP + i]);
             if (dmalloc((void **)&Zt, ((size_t)nx * S + kTail) * sizeof(T), A) != hipSuccess ||
                 dmalloc((void **)&Md, (size_t)S * S * sizeof(T), A) != hipSuccess) {
                 (void)hipGetLastError();
