@@ -1714,20 +1714,31 @@ __global__ __launch_bounds__(256) void k_param_reduce(int np, int nblk,
 }
 
 // Conjugate-gradient vector updates (scalars from the host).
+// (The solve's scalars stay on the device: each kernel reads them there.)
+// y = y - e0 x - c psi, c = *c_dev.
 __global__ void k_shift_project(int64_t n, double *__restrict__ y, const double *__restrict__ x,
-                                double e0, const double *__restrict__ psi, double c) {
+                                double e0, const double *__restrict__ psi,
+                                const double *__restrict__ c_dev) {
+    const double c = *c_dev;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r < n) y[r] = y[r] - e0 * x[r] - c * psi[r];
 }
-__global__ void k_axpy2(int64_t n, double a, const double *__restrict__ p,
-                        const double *__restrict__ ap, double *__restrict__ x,
-                        double *__restrict__ res) {
+// x += a p, res -= a ap with a = *rr / *pap; nothing when pap <= 0 (the
+// solve stops there).
+__global__ void k_axpy2(int64_t n, const double *__restrict__ rr, const double *__restrict__ pap,
+                        const double *__restrict__ p, const double *__restrict__ ap,
+                        double *__restrict__ x, double *__restrict__ res) {
+    if (!(*pap > 0.0)) return;
+    const double a = *rr / *pap;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     x[r] += a * p[r];
     res[r] -= a * ap[r];
 }
-__global__ void k_xpby(int64_t n, const double *__restrict__ x, double b, double *__restrict__ y) {
+// y = x + b y with b = *rr2 / *rr.
+__global__ void k_xpby(int64_t n, const double *__restrict__ x, const double *__restrict__ rr2,
+                       const double *__restrict__ rr, double *__restrict__ y) {
+    const double b = *rr2 / *rr;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r < n) y[r] = x[r] + b * y[r];
 }
@@ -1885,16 +1896,38 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
                         Wf[(size_t)a * p + mu] = (v + w).real();
                     }
             });
+            // M[a][b] = sg Re sum_f sum_mu V_f[a][mu] X_f[b][mu] as a real
+            // product A B^T over K2 = 2 n_freq p terms: A[a] = (Re V, -Im V),
+            // B[b] = (Re X, Im X), contiguous per row; each entry by one
+            // thread, eight partial sums in a fixed order.
+            const int K2 = 2 * n_freq * p;
+            std::vector<double> Am((size_t)KP * K2), Bm((size_t)KP * K2);
             parallel_for(KP, [&](int a) {
-                for (int f = 0; f < n_freq; f++) {
-                    const cplx *Va = Vs[f].data() + (size_t)a * p;
-                    const cplx *X = Xs[f].data();
-                    for (int mu = 0; mu < p; mu++) Om[(size_t)a * P + mu] += sg * Ws[f][(size_t)a * p + mu];
-                    for (int b = 0; b < KP; b++) {
-                        double t = 0.0;
-                        for (int mu = 0; mu < p; mu++) t += (Va[mu] * X[(size_t)b * p + mu]).real();
-                        M[(size_t)a * KP + b] += sg * t;
+                double *Aa = Am.data() + (size_t)a * K2, *Ba = Bm.data() + (size_t)a * K2;
+                for (int f = 0; f < n_freq; f++)
+                    for (int mu = 0; mu < p; mu++) {
+                        const cplx v = Vs[f][(size_t)a * p + mu], x = Xs[f][(size_t)a * p + mu];
+                        const size_t k = 2 * ((size_t)f * p + mu);
+                        Aa[k] = v.real();
+                        Aa[k + 1] = -v.imag();
+                        Ba[k] = x.real();
+                        Ba[k + 1] = x.imag();
                     }
+            });
+            parallel_for(KP, [&](int a) {
+                for (int f = 0; f < n_freq; f++)
+                    for (int mu = 0; mu < p; mu++)
+                        Om[(size_t)a * P + mu] += sg * Ws[f][(size_t)a * p + mu];
+                const double *Aa = Am.data() + (size_t)a * K2;
+                for (int b = 0; b < KP; b++) {
+                    const double *Bb = Bm.data() + (size_t)b * K2;
+                    double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                    int k = 0;
+                    for (; k + 8 <= K2; k += 8)
+                        for (int u = 0; u < 8; u++) t[u] += Aa[k + u] * Bb[k + u];
+                    for (; k < K2; k++) t[0] += Aa[k] * Bb[k];
+                    M[(size_t)a * KP + b] =
+                        sg * (((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7])));
                 }
             });
             for (int a = 0; a < KP; a++) trM += M[(size_t)a * KP + a];
@@ -2008,32 +2041,39 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     hipLaunchKernelGGL(k_sub_scaled, dim3(gv), dim3(256), 0, s, n, res, c, psi_n);
     CK(hipMemsetAsync(xi, 0, n * sizeof(double), s));
     CK(hipMemcpyAsync(dir, res, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // device scalars: scal[1] = <psi0, A dir>, scal[2] = <dir, A dir>,
+    // scal[3 + (it & 1)] = <res, res> at the start of iteration it; the host
+    // reads pap and the new <res, res> once per iteration
     double rr = 0.0;
-    TRY(dot(res, res, &rr));
+    TRY(dev_dot(op_gs, res, res, n, scal + 3, s));
+    CK(hipMemcpyAsync(&rr, scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
     const double bnorm = sqrt(rr);
     int it = 0;
     bool conv = bnorm == 0.0;
     double rel = 0.0;
     while (!conv && it < cg_max_iter) {
+        double *rr_d = scal + 3 + (it & 1), *rr2_d = scal + 3 + ((it + 1) & 1);
         TRY(apply_any(op_gs, MCD_F64, 1, dir, adir, s));
-        double pc = 0.0;
-        TRY(dot(psi_n, adir, &pc));
+        TRY(dev_dot(op_gs, psi_n, adir, n, scal + 1, s));
         hipLaunchKernelGGL(k_shift_project, dim3(gv), dim3(256), 0, s, n, adir, dir, e0, psi_n,
-                           pc);
-        double pap = 0.0;
-        TRY(dot(dir, adir, &pap));
+                           scal + 1);
+        TRY(dev_dot(op_gs, dir, adir, n, scal + 2, s));
+        hipLaunchKernelGGL(k_axpy2, dim3(gv), dim3(256), 0, s, n, rr_d, scal + 2, dir, adir, xi,
+                           res);
+        TRY(dev_dot(op_gs, res, res, n, rr2_d, s));
+        double pap = 0.0, rr2 = 0.0;
+        CK(hipMemcpyAsync(&pap, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(&rr2, rr2_d, sizeof(double), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
         if (!(pap > 0.0)) break;   // not positive definite: degenerate ground state
-        const double alpha = rr / pap;
-        hipLaunchKernelGGL(k_axpy2, dim3(gv), dim3(256), 0, s, n, alpha, dir, adir, xi, res);
-        double rr2 = 0.0;
-        TRY(dot(res, res, &rr2));
         it++;
         rel = sqrt(rr2) / bnorm;
         if (rel <= cg_tol) {
             conv = true;
             break;
         }
-        hipLaunchKernelGGL(k_xpby, dim3(gv), dim3(256), 0, s, n, res, rr2 / rr, dir);
+        hipLaunchKernelGGL(k_xpby, dim3(gv), dim3(256), 0, s, n, res, rr2_d, rr_d, dir);
         rr = rr2;
     }
     CK(hipGetLastError());
