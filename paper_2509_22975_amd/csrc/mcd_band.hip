@@ -1516,7 +1516,8 @@ __global__ __launch_bounds__(256) void k_rows_times(int64_t n, int S, int KP, in
     for (int i = 0; i < 4; i++)
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[i][j] = (V4)(T)0;
-    for (int k0 = 0; k0 < S; k0 += BK) {
+    const int kend = (KP + BK - 1) / BK * BK;   // rows of M past KP are zero
+    for (int k0 = 0; k0 < kend; k0 += BK) {
 #pragma unroll
         for (int q = 0; q < 4; q++) {   // A: 128 rows x 8 units of 16 bytes
             const int e = tid + q * 256, row = e >> 3, ku = (e & 7) * U, kg = k0 + ku;
