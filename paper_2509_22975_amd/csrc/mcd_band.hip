@@ -364,20 +364,19 @@ __global__ __launch_bounds__(BS) void k_block_apply_r(int64_t n, int nm, const T
     }
 }
 
-// W (-)= sum_m Q_m C_m for nm blocks (C on the device), one launch; block m
-// at Q0 + m qstride (elements, any sign).
+// W (-)= sum_m Q_m C_m for nm blocks (C on the device), one launch.
 template <typename T, int P>
-static void launch_block_apply(int64_t n, int nm, const T *Q0, int64_t qstride, const double *C,
-                               T *W, bool sub, hipStream_t s) {
+static void launch_block_apply(int64_t n, int nm, const T *Q0, const double *C, T *W, bool sub,
+                               hipStream_t s) {
     const size_t lds = (size_t)nm * P * P * sizeof(double);
     if constexpr (P * sizeof(T) % 16 == 0) {
         const unsigned nb = (unsigned)std::min<int64_t>(gridn(n, BS), 8192);
         hipLaunchKernelGGL((k_block_apply_r<T, P>), dim3(nb), dim3(BS), lds, s, n, nm, Q0,
-                           qstride, C, W, sub ? 1 : 0);
+                           (int64_t)n * P, C, W, sub ? 1 : 0);
     } else {
         const unsigned nb = (unsigned)std::min<int64_t>(gridn(n, BS / P), 4096);
         hipLaunchKernelGGL((k_block_apply<T, P>), dim3(nb), dim3(BS), lds, s, n, nm, Q0,
-                           qstride, C, W, sub ? 1 : 0);
+                           (int64_t)n * P, C, W, sub ? 1 : 0);
     }
 }
 
@@ -544,14 +543,12 @@ __global__ __launch_bounds__(64) void k_sym_pair(int P, const double *__restrict
 // of R = sqrt(d)^-1 (Schur row), and the Schur complement is updated.  With
 // rank r, W = Q R (R: r x P, zero rows below), Q = W Xm with
 // Xm = Pi R11^-1 (zero columns beyond r).  Bacc <- R Bacc (R itself when
-// init), also written to Bcopy when not NULL (the factor's place in T);
-// *rank_out = r.
+// init), *rank_out = r.
 __global__ __launch_bounds__(64) void k_pchol(int P, const double *__restrict__ M, int mode,
                                               double thr_abs, double *__restrict__ Xm,
                                               double *__restrict__ Bm,
                                               double *__restrict__ Bacc, int init,
-                                              int *__restrict__ rank_out,
-                                              double *__restrict__ Bcopy) {
+                                              int *__restrict__ rank_out) {
     __shared__ double S[16][16];
     __shared__ double R[16][16];
     __shared__ double Ri[16][16];
@@ -630,10 +627,7 @@ __global__ __launch_bounds__(64) void k_pchol(int P, const double *__restrict__ 
         Bt[a][b] = acc;
     }
     __syncthreads();
-    for (int e = t; e < P * P; e += 64) {
-        Bacc[e] = Bt[e / P][e % P];
-        if (Bcopy) Bcopy[e] = Bt[e / P][e % P];   // the final factor, stored in place
-    }
+    for (int e = t; e < P * P; e += 64) Bacc[e] = Bt[e / P][e % P];
     if (t == 0) *rank_out = r;
 }
 
@@ -749,20 +743,17 @@ struct BandRun {
     }
 
     // W (-)= sum_m Q_m C_m with C already on the device ([nm][P][P]).
-    // Block m at Q0 + m qstride (elements; default n P, the contiguous store).
-    int block_apply_dev(const T *Q0, int nm, const double *C, T *Wout, bool sub,
-                        int64_t qstride = 0) {
+    int block_apply_dev(const T *Q0, int nm, const double *C, T *Wout, bool sub) {
         const int PP = P * P;
         const int group = std::max(1, (48 * 1024) / (PP * 8));
-        if (qstride == 0) qstride = (int64_t)n * P;
         MCD_REQUIRE(sub || nm <= group, MCD_E_INVALID, "assigning block product must use one group");
         for (int g0 = 0; g0 < nm; g0 += group) {
             const int g = std::min(group, nm - g0);
-            const T *q = Q0 + (int64_t)g0 * qstride;
+            const T *q = Q0 + (int64_t)g0 * n * P;
             const double *c = C + (size_t)g0 * PP;
 #define BAD(PV)                                                     \
     case PV:                                                        \
-        launch_block_apply<T, PV>(n, g, q, qstride, c, Wout, sub, s); \
+        launch_block_apply<T, PV>(n, g, q, c, Wout, sub, s);        \
         break;
             switch (P) {
                 BAD(1) BAD(2) BAD(4) BAD(8) BAD(16)
@@ -784,7 +775,7 @@ struct BandRun {
             const T *q = Q0 + (int64_t)g0 * n * P;
 #define BA(PV)                                                      \
     case PV:                                                        \
-        launch_block_apply<T, PV>(n, g, q, (int64_t)n * P, dC, Wout, sub, s); \
+        launch_block_apply<T, PV>(n, g, q, dC, Wout, sub, s);       \
         break;
             switch (P) {
                 BA(1) BA(2) BA(4) BA(8) BA(16)
@@ -885,11 +876,12 @@ struct BandRun {
                 MCD_TRY(gram_dev(cur, 1, cur));
                 hipLaunchKernelGGL(k_pchol, dim3(1), dim3(64), 0, s, P, dG, pass,
                                    dtol_abs * dtol_abs, dXm, dBm, dBacc, pass == 0 ? 1 : 0,
-                                   d_rank + slot, pass == 1 ? outB : nullptr);
+                                   d_rank + slot);
                 T *out = pass == 0 ? W2 : dst;
                 MCD_TRY(block_apply_dev(cur, 1, dXm, out, false));
                 cur = out;
             }
+            MCD_HIP(hipMemcpyAsync(outB, dBacc, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
             return MCD_OK;
         };
         std::vector<int> rank(max_blocks + 2, -1);
@@ -928,18 +920,17 @@ struct BandRun {
             for (int j = 0; j < max_blocks; j++) {
                 DTRY(apply_any(op, sizeof(T) == 8 ? MCD_F64 : MCD_F32, P, blk(j), W, s));
                 DTRY(gram_dev(blk(j), 1, W));
-                // W -= Q_{j-1} B_j^T + Q_j A_j in one pass (both terms summed
-                // in float64, then subtracted), with the stride between the
-                // two blocks as stored: negative where the three-block ring of
-                // reorth = 0 wraps, so a run gives the same result whether it
-                // keeps three blocks or all of them
+                // W -= Q_{j-1} B_j^T + Q_j A_j: one pass when the two blocks
+                // are adjacent in the store
                 hipLaunchKernelGGL(k_sym_pair, dim3(1), dim3(64), 0, s, P, dG,
                                    dA + (size_t)j * PP, j > 0 ? dB + (size_t)j * PP : nullptr,
                                    dC2);
-                if (j > 0)
-                    DTRY(block_apply_dev(blk(j - 1), 2, dC2, W, true, blk(j) - blk(j - 1)));
-                else
+                if (j > 0 && blk(j) == blk(j - 1) + (int64_t)n * P) {
+                    DTRY(block_apply_dev(blk(j - 1), 2, dC2, W, true));
+                } else {
                     DTRY(block_apply_dev(blk(j), 1, dC2 + PP, W, true));
+                    if (j > 0) DTRY(block_apply_dev(blk(j - 1), 1, dC2, W, true));
+                }
                 for (int pass = 0; pass < reorth; pass++) {
                     DTRY(gram_dev(blk(0), j + 1, W));
                     DTRY(block_apply_dev(blk(0), j + 1, dG, W, true));

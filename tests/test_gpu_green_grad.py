@@ -162,9 +162,11 @@ def test_green_vjp_with_convergence_stop_replays_forward():
 def test_green_vjp_on_kept_runs_is_bit_identical(prec, reorth):
     """mcd_band_green_vjp_keep on the sector runs kept by the forward call gives
     exactly the derivative of mcd_band_green_vjp (which recomputes the same
-    runs), twice in a row on one handle; the kept forward's G equals the plain
-    forward's (with reorth = 0 the plain forward stores three blocks, the kept
-    one all of them); arguments that differ from the kept call are rejected."""
+    runs, every block stored), twice in a row on one handle; the kept
+    forward's G equals the plain forward's (bit for bit with reorth = 1; with
+    reorth = 0 the plain forward keeps a ring of three blocks, whose
+    three-term update takes two passes where the ring wraps, so to rounding);
+    arguments that differ from the kept call are rejected."""
     torch, mcd = require_gpu()
     m = W.impurity_plaquette_bath(6)
     keys, _ = sampler.chain_c(m, W.neel_start(m), 2, 15000, 500, 10**7)
@@ -179,7 +181,10 @@ def test_green_vjp_on_kept_runs_is_bit_identical(prec, reorth):
     G0, info0 = mcd.band_lanczos_green(m, kd, psi, e0, orbs, spins, om, **kw)
     G1, info1, kept = mcd.band_lanczos_green(m, kd, psi, e0, orbs, spins, om, keep=True, **kw)
     try:
-        assert np.array_equal(G0, G1) and info0.iters == info1.iters
+        if reorth > 0:
+            assert np.array_equal(G0, G1) and info0.iters == info1.iters
+        else:
+            assert _rel(G1, G0) < (1e-5 if prec == "f32" else 1e-12)
         ref = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=0.3, **kw)
         for _ in range(2):
             got = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=0.3,
