@@ -1937,13 +1937,17 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             int pl = 0;
             while ((1 << pl) < P) pl++;
             constexpr int kTail = 1024;   // zeroed values after the last row of Zt
+            // Zt and M from the chunk cache (an arena released at the end of
+            // the hook): repeated derivative calls reuse the same memory
+            Arena zarena(s);
+            const Alloc AZ{s, true, &zarena};
             T *Zt = nullptr, *Md = nullptr;
             std::vector<T> Mp((size_t)S * S, (T)0);
             for (int i = 0; i < KP; i++)
                 for (int j = 0; j < KP; j++)
                     Mp[(size_t)i * S + j] = (T)(M[(size_t)i * KP + j] + M[(size_t)j * KP + i]);
-            if (dmalloc((void **)&Zt, ((size_t)nx * S + kTail) * sizeof(T), A) != hipSuccess ||
-                dmalloc((void **)&Md, (size_t)S * S * sizeof(T), A) != hipSuccess) {
+            if (dmalloc((void **)&Zt, ((size_t)nx * S + kTail) * sizeof(T), AZ) != hipSuccess ||
+                dmalloc((void **)&Md, (size_t)S * S * sizeof(T), AZ) != hipSuccess) {
                 (void)hipGetLastError();
                 set_error("green vjp: no device memory for Z = Q M (%.1f GB)",
                           (double)nx * S * sizeof(T) / 1e9);
@@ -1982,8 +1986,7 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
                 if (hipGetLastError() != hipSuccess) rc = MCD_E_HIP;
             }
             if (hipStreamSynchronize(s) != hipSuccess && rc == MCD_OK) rc = MCD_E_HIP;
-            for (T *q : {Zt, Md})
-                if (q) (void)dfree(q, A);
+            zarena.release();   // after the synchronisation above
             if (rc == MCD_E_HIP) set_error("green vjp: device step failed in a sector hook");
             return rc;
         });
