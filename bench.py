@@ -470,7 +470,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU layout is described in DESIGN.md)", file=sys.stderr)
+              "(sharding across GPUs is a design, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
