@@ -1829,7 +1829,9 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             return rc_;    \
         }                  \
     } while (0)
-    TRY(op_create(model, keys_dev, n, MCD_STORAGE_AUTO, 0, true, s, &op_gs, true));
+    // untuned: the default row-ordered product kernel, so that the solve (and
+    // the derivative) is reproducible bit for bit across calls
+    TRY(op_create(model, keys_dev, n, MCD_STORAGE_AUTO, 0, false, s, &op_gs, true));
     const int nb = op_gs->hm.dm.n_bonds, no = op_gs->hm.dm.n_orb, np = nb + 2 * no;
     // psi0 normalised exactly as the forward call does, so the band runs below
     // reproduce the forward's recurrence (and stopping point) bit for bit

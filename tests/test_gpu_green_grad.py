@@ -80,6 +80,15 @@ def test_green_vjp_vs_oracle_finite_differences(case):
     d_t, d_U, d_e, info = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=e0_bar,
                                              max_blocks=400, reorth=2, eta=eta)
     assert info.converged
+    # the same derivative from the forward's kept runs (bit for bit)
+    _, _, kept = mcd.band_lanczos_green(m, kd, psi, e0, orbs, spins, om, max_blocks=400,
+                                        reorth=2, eta=eta, keep=True)
+    try:
+        kt, kU, ke, _ = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=e0_bar,
+                                           max_blocks=400, reorth=2, eta=eta, keep=kept)
+    finally:
+        kept.close()
+    assert np.array_equal(kt, d_t) and np.array_equal(kU, d_U) and np.array_equal(ke, d_e)
     r_t, r_U, r_e = dv.green_gradient(keys, m, orbs, spins, om, Gb, e0_bar=e0_bar, eta=eta)
     got = np.concatenate([d_t, d_U, d_e])
     ref = np.concatenate([r_t, r_U, r_e])
