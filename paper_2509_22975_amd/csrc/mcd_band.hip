@@ -1592,7 +1592,7 @@ __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
     __shared__ double acc[kCWaves][kMaxParams];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nb = m->n_bonds, no = m->n_orb, np = nb + 2 * no;
-    const int nr = S / 64, P = 1 << pl;
+    const int P = 1 << pl;
     for (int i = lane; i < np; i += 64) acc[wid][i] = 0.0;
     for (int64_t r = (int64_t)blockIdx.x * kCWaves + wid; r < n;
          r += (int64_t)gridDim.x * kCWaves) {

@@ -177,8 +177,8 @@ __global__ void k_g_goff(int64_t nb, const int64_t *__restrict__ gbs,
     }
 }
 
-__global__ void k_g_tables(int64_t nnz, const uint64_t *__restrict__ skey,
-                           const uint32_t *__restrict__ sval, const uint32_t *__restrict__ flag,
+__global__ void k_g_tables(int64_t nnz, const uint32_t *__restrict__ sval,
+                           const uint32_t *__restrict__ flag,
                            const uint32_t *__restrict__ gid, const uint32_t *__restrict__ colw,
                            uint32_t col_mask, int col_bits, uint64_t *__restrict__ gtab) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -474,7 +474,7 @@ int build_grouped(mcd_op *op, hipStream_t s) {
     GK(hipStreamSynchronize(s));
     GK(dmalloc((void **)&d_gtab, ((int64_t)ngroups + 1) * sizeof(uint64_t), al));
     GK(hipMemsetAsync(d_gtab, 0, ((int64_t)ngroups + 1) * sizeof(uint64_t), s));
-    hipLaunchKernelGGL(k_g_tables, dim3(gridn(nnz)), dim3(BS), 0, s, nnz, k_out, v_out, flag, gid,
+    hipLaunchKernelGGL(k_g_tables, dim3(gridn(nnz)), dim3(BS), 0, s, nnz, v_out, flag, gid,
                        op->d_colw, dm.col_mask, (int)dm.col_bits, d_gtab);
     GK(hipGetLastError());
     GK(dmalloc((void **)&d_gw, nnz * sizeof(uint32_t), al));
