@@ -1474,6 +1474,45 @@ __global__ void k_start_block_t(int64_t m, const uint64_t *__restrict__ keys, Se
     lam[r] += acc;
 }
 
+// The adjoint's weight matrix in symmetric form: Mp[i][j] = sg (A[i].B[j] +
+// A[j].B[i]) for i, j < KP and 0 elsewhere in the S x S output, with A and B
+// [KP][K2] row-major float64 (M = sg A B^T is the real part of the
+// frequency sum).  A 16 x 16 workgroup makes one 16 x 16 tile; the four row
+// panels it needs are staged through LDS 32 k at a time (zeros past KP and
+// K2), and each dot is one accumulator summed in k order, so the result does
+// not depend on the launch.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sym_gram(int KP, int K2, int S, double sg,
+                                                 const double *__restrict__ A,
+                                                 const double *__restrict__ B,
+                                                 T *__restrict__ Mp) {
+    constexpr int TW = 16, KC = 32;
+    __shared__ double Ai[TW][KC + 1], Bj[TW][KC + 1], Aj[TW][KC + 1], Bi[TW][KC + 1];
+    const int tx = threadIdx.x, ty = threadIdx.y, t = ty * TW + tx;
+    const int i0 = blockIdx.y * TW, j0 = blockIdx.x * TW;
+    double s1 = 0.0, s2 = 0.0;
+    for (int k0 = 0; k0 < K2; k0 += KC) {
+        for (int e = t; e < TW * KC; e += TW * TW) {
+            const int rr = e / KC, kk = e % KC, k = k0 + kk;
+            const int ri = i0 + rr, rj = j0 + rr;
+            const bool kin = k < K2;
+            Ai[rr][kk] = kin && ri < KP ? A[(size_t)ri * K2 + k] : 0.0;
+            Bi[rr][kk] = kin && ri < KP ? B[(size_t)ri * K2 + k] : 0.0;
+            Aj[rr][kk] = kin && rj < KP ? A[(size_t)rj * K2 + k] : 0.0;
+            Bj[rr][kk] = kin && rj < KP ? B[(size_t)rj * K2 + k] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < KC; kk++) {
+            s1 = fma(Ai[ty][kk], Bj[tx][kk], s1);
+            s2 = fma(Aj[tx][kk], Bi[ty][kk], s2);
+        }
+        __syncthreads();
+    }
+    const int i = i0 + ty, j = j0 + tx;
+    if (i < S && j < S) Mp[(size_t)i * S + j] = (T)(sg * s1 + sg * s2);
+}
+
 // Zt = Q M for the adjoint: Q the Krylov store (blocks of n x P, P a power of
 // two; Q[r][k] = block k / P, row r, column k % P, k < KP), M [S][S] row-major
 // and Zt [n][S] row-major, S a multiple of 128 (M and Zt zero past KP).  A
@@ -1857,13 +1896,14 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
 
     double trM = 0.0;   // sum over sectors of tr(M)
     int krylov = 0;
-    // Per sector: M, Omega on the host, Z = Q M and W = Q Omega on the device,
+    // Per sector: the per-frequency solves, Omega and the two factors of M
+    // on the host; M + M^T, Z = Q (M + M^T) and W = Q Omega on the device,
     // tr(Q^T dH Q M) into acc, lam += (start-block map)^T W.
     auto make_hook = [&](bool create) {
         return SectorHook<T>([&, create](BandRun<T> &run, mcd_op *op, const BandResult &br) -> int {
             const int m = br.m, KP = m * P;
             const double sg = create ? 1.0 : -1.0;
-            std::vector<double> M((size_t)KP * KP, 0.0), Om((size_t)KP * P, 0.0);
+            std::vector<double> Om((size_t)KP * P, 0.0);
             // Per frequency (in parallel): X_f = first block column of
             // (z - T)^-1 R0, V_f = X_f conj(G_bar_f)^T.  Then M and Omega
             // (in parallel over their rows a), each element summed over the
@@ -1892,8 +1932,9 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             });
             // M[a][b] = sg Re sum_f sum_mu V_f[a][mu] X_f[b][mu] as a real
             // product A B^T over K2 = 2 n_freq p terms: A[a] = (Re V, -Im V),
-            // B[b] = (Re X, Im X), contiguous per row; each entry by one
-            // thread, eight partial sums in a fixed order.
+            // B[b] = (Re X, Im X), contiguous per row.  The product itself
+            // (in the symmetric form M + M^T) is made on the device below;
+            // the host keeps its trace.
             const int K2 = 2 * n_freq * p;
             std::vector<double> Am((size_t)KP * K2), Bm((size_t)KP * K2);
             parallel_for(KP, [&](int a) {
@@ -1908,23 +1949,17 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
                         Ba[k + 1] = x.imag();
                     }
             });
+            std::vector<double> diag(KP);
             parallel_for(KP, [&](int a) {
                 for (int f = 0; f < n_freq; f++)
                     for (int mu = 0; mu < p; mu++)
                         Om[(size_t)a * P + mu] += sg * Ws[f][(size_t)a * p + mu];
-                const double *Aa = Am.data() + (size_t)a * K2;
-                for (int b = 0; b < KP; b++) {
-                    const double *Bb = Bm.data() + (size_t)b * K2;
-                    double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                    int k = 0;
-                    for (; k + 8 <= K2; k += 8)
-                        for (int u = 0; u < 8; u++) t[u] += Aa[k + u] * Bb[k + u];
-                    for (; k < K2; k++) t[0] += Aa[k] * Bb[k];
-                    M[(size_t)a * KP + b] =
-                        sg * (((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7])));
-                }
+                const double *Aa = Am.data() + (size_t)a * K2, *Ba = Bm.data() + (size_t)a * K2;
+                double t = 0.0;
+                for (int k = 0; k < K2; k++) t += Aa[k] * Ba[k];
+                diag[a] = sg * t;
             });
-            for (int a = 0; a < KP; a++) trM += M[(size_t)a * KP + a];
+            for (int a = 0; a < KP; a++) trM += diag[a];
             krylov += br.krylov;
             const int64_t nx = run.n;
             std::vector<double> C((size_t)m * P * P);
@@ -1939,28 +1974,32 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             int pl = 0;
             while ((1 << pl) < P) pl++;
             constexpr int kTail = 1024;   // zeroed values after the last row of Zt
-            // Zt and M from the chunk cache (an arena released at the end of
-            // the hook): repeated derivative calls reuse the same memory
+            // Zt, M and its factors from the chunk cache (an arena released at
+            // the end of the hook): repeated derivative calls reuse the memory
             Arena zarena(s);
             const Alloc AZ{s, true, &zarena};
             T *Zt = nullptr, *Md = nullptr;
-            std::vector<T> Mp((size_t)S * S, (T)0);
-            for (int i = 0; i < KP; i++)
-                for (int j = 0; j < KP; j++)
-                    Mp[(size_t)i * S + j] = (T)(M[(size_t)i * KP + j] + M[(size_t)j * KP + i]);
+            double *dA = nullptr, *dB = nullptr;
             if (dmalloc((void **)&Zt, ((size_t)nx * S + kTail) * sizeof(T), AZ) != hipSuccess ||
-                dmalloc((void **)&Md, (size_t)S * S * sizeof(T), AZ) != hipSuccess) {
+                dmalloc((void **)&Md, (size_t)S * S * sizeof(T), AZ) != hipSuccess ||
+                dmalloc((void **)&dA, Am.size() * sizeof(double), AZ) != hipSuccess ||
+                dmalloc((void **)&dB, Bm.size() * sizeof(double), AZ) != hipSuccess) {
                 (void)hipGetLastError();
                 set_error("green vjp: no device memory for Z = Q M (%.1f GB)",
                           (double)nx * S * sizeof(T) / 1e9);
                 rc = MCD_E_CAPACITY;
             }
             if (rc == MCD_OK &&
-                (hipMemcpyAsync(Md, Mp.data(), Mp.size() * sizeof(T), hipMemcpyHostToDevice, s) !=
-                     hipSuccess ||
+                (hipMemcpyAsync(dA, Am.data(), Am.size() * sizeof(double), hipMemcpyHostToDevice,
+                                s) != hipSuccess ||
+                 hipMemcpyAsync(dB, Bm.data(), Bm.size() * sizeof(double), hipMemcpyHostToDevice,
+                                s) != hipSuccess ||
                  hipMemsetAsync(Zt + (size_t)nx * S, 0, kTail * sizeof(T), s) != hipSuccess))
                 rc = MCD_E_HIP;
             if (rc == MCD_OK) {
+                // M + M^T on the device (S x S, zero past KP)
+                hipLaunchKernelGGL((k_sym_gram<T>), dim3(S / 16, S / 16), dim3(16, 16), 0, s, KP,
+                                   K2, S, sg, dA, dB, Md);
                 const int64_t tiles = (nx + 127) / 128 * (S / 128);
                 hipLaunchKernelGGL((k_rows_times<T>), dim3((unsigned)((tiles + 7) / 8 * 8)),
                                    dim3(256), 0, s, nx, S, KP, pl, run.blk(0), Md, Zt);
