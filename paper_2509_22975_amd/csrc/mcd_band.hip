@@ -423,8 +423,6 @@ static void jacobi_eig(int n, std::vector<double> A, std::vector<double> &w,
     for (int i = 0; i < n; i++) w[i] = A[i * n + i];
 }
 
-// Solve S X = B (S n x n, B n x k, complex, row-major) by Gaussian
-// elimination with partial pivoting; S and B are overwritten, X returned in B.
 // fn(i) for i in [0, n) on up to 16 host threads (static round-robin); the
 // callers give every index its own output, so results do not depend on the
 // thread count.
@@ -445,6 +443,8 @@ static void parallel_for(int n, F &&fn) {
     for (auto &x : th) x.join();
 }
 
+// Solve S X = B (S n x n, B n x k, complex, row-major) by Gaussian
+// elimination with partial pivoting; S and B are overwritten, X returned in B.
 static void csolve(int n, int k, std::vector<cplx> &S, std::vector<cplx> &B) {
     for (int c = 0; c < n; c++) {
         int piv = c;
