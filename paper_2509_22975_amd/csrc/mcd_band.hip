@@ -14,9 +14,12 @@
 //  4. block Lanczos with block width P (the selected p padded to a power of
 //     two; zero columns deflate at once): W = H Q_j (block SpMM), A_j = Q_j^T W,
 //     W -= Q_j A_j + Q_{j-1} B_j^T, optional full reorthogonalisation against
-//     every stored block (two passes), W = Q_{j+1} B_{j+1} by a twice-applied
-//     Gram eigen-decomposition that drops directions of norm <= dtol (the
-//     band method's deflation) -- this spans the block Krylov space K_r^L;
+//     every stored block (one or two passes), W = Q_{j+1} B_{j+1} by a
+//     rank-revealing QR applied twice that drops directions of norm <= dtol
+//     (the band method's deflation): pivoted Cholesky of the Gram matrix in
+//     one wavefront for the block products, a Gram eigen-decomposition on
+//     the host in the per-column reference form -- either way the columns
+//     span the block Krylov space K_r^L;
 //  5. G(z) = R^T [(z - T)^-1]_{00} R by a block continued fraction over the
 //     block tridiagonal T (complex128, host), z = i w + E0 for G+ and
 //     G- = -R^T [(E0 - i w) - T]^-1 R; this is the resolvent that the Lehmann
