@@ -284,8 +284,18 @@ __global__ __launch_bounds__(256) void k_gram_reduce(int nm, int nch, int PP,
     const int lane = threadIdx.x & 63;
     if (i >= nm * PP) return;          // whole wavefront exits together
     const int m = i / PP, e = i % PP;
+    const double *__restrict__ pm = part + (int64_t)m * nch * PP + e;
     double s = 0.0;
-    for (int c = lane; c < nch; c += 64) s += part[((int64_t)m * nch + c) * PP + e];
+    int c = lane;
+    // eight loads in flight, then added in chunk order
+    for (; c + 7 * 64 < nch; c += 8 * 64) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = pm[(int64_t)(c + u * 64) * PP];
+#pragma unroll
+        for (int u = 0; u < 8; u++) s += v[u];
+    }
+    for (; c < nch; c += 64) s += pm[(int64_t)c * PP];
     s = wave_sum(s);
     if (lane == 0) out[i] = s;
 }
@@ -546,91 +556,108 @@ __global__ __launch_bounds__(64) void k_sym_pair(int P, const double *__restrict
 // of R = sqrt(d)^-1 (Schur row), and the Schur complement is updated.  With
 // rank r, W = Q R (R: r x P, zero rows below), Q = W Xm with
 // Xm = Pi R11^-1 (zero columns beyond r).  Bacc <- R Bacc (R itself when
-// init), *rank_out = r.
-__global__ __launch_bounds__(64) void k_pchol(int P, const double *__restrict__ M, int mode,
+// init; Bacc's rows past the previous rank are zero), *rank_out = r.
+// One wavefront, P a compile-time power of two: every loop is unrolled, the
+// chosen set is a register mask (the same in every lane), and M and Bacc are
+// loaded together at the start, so the steps are LDS round trips only.
+template <int P>
+__global__ __launch_bounds__(64) void k_pchol(const double *__restrict__ M, int mode,
                                               double thr_abs, double *__restrict__ Xm,
                                               double *__restrict__ Bm,
                                               double *__restrict__ Bacc, int init,
                                               int *__restrict__ rank_out) {
-    __shared__ double S[16][16];
-    __shared__ double R[16][16];
-    __shared__ double Ri[16][16];
-    __shared__ double Bt[16][16];
-    __shared__ int piv[16];
-    __shared__ int chosen[16];
+    constexpr int PP = P * P;
+    __shared__ double S[P][P], R[P][P], Ri[P][P], U[P][P], Bs[P][P];
+    __shared__ int piv[P];
     const int t = threadIdx.x;
-    for (int e = t; e < 256; e += 64) {
-        const int a = e / 16, b = e % 16;
-        S[a][b] = (a < P && b < P) ? M[a * P + b] : 0.0;
+    for (int e = t; e < PP; e += 64) {
+        const int a = e / P, b = e % P;
+        S[a][b] = M[e];
+        Bs[a][b] = init ? 0.0 : Bacc[e];
         R[a][b] = 0.0;
         Ri[a][b] = 0.0;
     }
-    if (t < 16) {
-        chosen[t] = 0;
-        piv[t] = 0;
-    }
+    if (t < P) piv[t] = 0;
     __syncthreads();
     double maxd = 0.0;
+#pragma unroll
     for (int i = 0; i < P; i++) maxd = fmax(maxd, S[i][i]);
     const double thr = mode == 0 ? thr_abs : 1e-2 * maxd;
+    unsigned chosen = 0u;
     int r = 0;
+#pragma unroll
     for (int k = 0; k < P; k++) {
+        double d[P];
+#pragma unroll
+        for (int i = 0; i < P; i++) d[i] = S[i][i];
         int q = -1;
         double dq = 0.0;
+#pragma unroll
         for (int i = 0; i < P; i++)
-            if (!chosen[i] && S[i][i] > dq) {
-                dq = S[i][i];
+            if (!((chosen >> i) & 1u) && d[i] > dq) {
+                dq = d[i];
                 q = i;
             }
         if (q < 0 || !(dq > thr)) break;     // the same decision in every lane
         const double sq = sqrt(dq);
-        if (t < P) R[k][t] = chosen[t] ? 0.0 : S[q][t] / sq;
+        if (t < P) R[k][t] = ((chosen >> t) & 1u) ? 0.0 : S[q][t] / sq;
         __syncthreads();
-        if (t == 0) {
-            chosen[q] = 1;
-            piv[k] = q;
-        }
-        for (int e = t; e < P * P; e += 64) {
+        chosen |= 1u << q;
+        if (t == 0) piv[k] = q;
+        for (int e = t; e < PP; e += 64) {
             const int i = e / P, j = e % P;
             S[i][j] -= R[k][i] * R[k][j];
         }
         __syncthreads();
         r++;
     }
-    // R11^-1 (upper triangular, R11[k][l] = R[k][piv[l]]), one column per lane
+    // R11 with its columns in pivot order: U[k][m] = R[k][piv[m]]
+    for (int e = t; e < PP; e += 64) {
+        const int k = e / P, m = e % P;
+        U[k][m] = m < r ? R[k][piv[m]] : 0.0;
+    }
+    __syncthreads();
+    // R11^-1 (upper triangular), one column l per lane, back substitution
+    // from the diagonal up, each entry summed in ascending order
     if (t < r) {
         const int l = t;
-        Ri[l][l] = 1.0 / R[l][piv[l]];
-        for (int kk = l - 1; kk >= 0; kk--) {
-            double acc = 0.0;
-            for (int mm = kk + 1; mm <= l; mm++) acc += R[kk][piv[mm]] * Ri[mm][l];
-            Ri[kk][l] = -acc / R[kk][piv[kk]];
+        double x[P];
+#pragma unroll
+        for (int kk = P - 1; kk >= 0; kk--) {
+            x[kk] = 0.0;
+            if (kk == l) {
+                x[kk] = 1.0 / U[l][l];
+            } else if (kk < l) {
+                double acc = 0.0;
+#pragma unroll
+                for (int mm = kk + 1; mm < P; mm++)
+                    if (mm <= l) acc += U[kk][mm] * x[mm];
+                x[kk] = -acc / U[kk][kk];
+            }
         }
+#pragma unroll
+        for (int kk = 0; kk < P; kk++)
+            if (kk <= l) Ri[kk][l] = x[kk];
     }
     __syncthreads();
-    for (int e = t; e < P * P; e += 64) {
+    for (int e = t; e < PP; e += 64) {
         const int a = e / P, c = e % P;   // Xm row a (column of W), column c (new direction)
         double x = 0.0;
-        if (c < r)
-            for (int l = 0; l <= c; l++)
-                if (piv[l] == a) x = Ri[l][c];
+#pragma unroll
+        for (int l = 0; l < P; l++)
+            if (l <= c && c < r && piv[l] == a) x = Ri[l][c];
         Xm[e] = x;
         Bm[e] = a < r ? R[a][c] : 0.0;    // Bm row a, column c
-    }
-    // Bacc <- R Bacc
-    for (int e = t; e < P * P; e += 64) {
-        const int a = e / P, b = e % P;
+        // Bacc <- R Bacc (the previous Bacc is in Bs)
         double acc = 0.0;
         if (init) {
-            acc = a < r ? R[a][b] : 0.0;
-        } else {
-            for (int q = 0; q < r; q++) acc += R[a][q] * Bacc[q * P + b];
-            if (a >= r) acc = 0.0;
+            acc = a < r ? R[a][c] : 0.0;
+        } else if (a < r) {
+#pragma unroll
+            for (int q = 0; q < P; q++) acc += R[a][q] * Bs[q][c];
         }
-        Bt[a][b] = acc;
+        Bacc[e] = acc;
     }
-    __syncthreads();
-    for (int e = t; e < P * P; e += 64) Bacc[e] = Bt[e / P][e % P];
     if (t == 0) *rank_out = r;
 }
 
@@ -877,9 +904,19 @@ struct BandRun {
             T *cur = src;
             for (int pass = 0; pass < 2; pass++) {
                 MCD_TRY(gram_dev(cur, 1, cur));
-                hipLaunchKernelGGL(k_pchol, dim3(1), dim3(64), 0, s, P, dG, pass,
-                                   dtol_abs * dtol_abs, dXm, dBm, dBacc, pass == 0 ? 1 : 0,
-                                   d_rank + slot);
+#define PCH(PV)                                                                         \
+    case PV:                                                                            \
+        hipLaunchKernelGGL((k_pchol<PV>), dim3(1), dim3(64), 0, s, dG, pass,             \
+                           dtol_abs * dtol_abs, dXm, dBm, dBacc, pass == 0 ? 1 : 0,       \
+                           d_rank + slot);                                              \
+        break;
+                switch (P) {
+                    PCH(1) PCH(2) PCH(4) PCH(8) PCH(16)
+                    default:
+                        set_error("block width %d is not a power of two <= 16", P);
+                        return MCD_E_INVALID;
+                }
+#undef PCH
                 T *out = pass == 0 ? W2 : dst;
                 MCD_TRY(block_apply_dev(cur, 1, dXm, out, false));
                 cur = out;
