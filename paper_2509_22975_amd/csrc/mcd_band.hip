@@ -556,8 +556,7 @@ __global__ __launch_bounds__(64) void k_sym_pair(int P, const double *__restrict
 // of R = sqrt(d)^-1 (Schur row), and the Schur complement is updated.  With
 // rank r, W = Q R (R: r x P, zero rows below), Q = W Xm with
 // Xm = Pi R11^-1 (zero columns beyond r).  Bacc <- R Bacc (R itself when
-// init; Bacc's rows past the previous rank are zero), also into Bout unless
-// it is null, *rank_out = r.
+// init; Bacc's rows past the previous rank are zero), *rank_out = r.
 // One wavefront, P a compile-time power of two: every loop is unrolled, the
 // chosen set is a register mask (the same in every lane), and M and Bacc are
 // loaded together at the start, so the steps are LDS round trips only.
@@ -566,7 +565,6 @@ __global__ __launch_bounds__(64) void k_pchol(const double *__restrict__ M, int 
                                               double thr_abs, double *__restrict__ Xm,
                                               double *__restrict__ Bm,
                                               double *__restrict__ Bacc, int init,
-                                              double *__restrict__ Bout,
                                               int *__restrict__ rank_out) {
     constexpr int PP = P * P;
     __shared__ double S[P][P], R[P][P], Ri[P][P], U[P][P], Bs[P][P];
@@ -659,7 +657,6 @@ __global__ __launch_bounds__(64) void k_pchol(const double *__restrict__ M, int 
             for (int q = 0; q < P; q++) acc += R[a][q] * Bs[q][c];
         }
         Bacc[e] = acc;
-        if (Bout != nullptr) Bout[e] = acc;
     }
     if (t == 0) *rank_out = r;
 }
@@ -911,7 +908,7 @@ struct BandRun {
     case PV:                                                                            \
         hipLaunchKernelGGL((k_pchol<PV>), dim3(1), dim3(64), 0, s, dG, pass,             \
                            dtol_abs * dtol_abs, dXm, dBm, dBacc, pass == 0 ? 1 : 0,       \
-                           pass == 1 ? outB : nullptr, d_rank + slot);                  \
+                           d_rank + slot);                                              \
         break;
                 switch (P) {
                     PCH(1) PCH(2) PCH(4) PCH(8) PCH(16)
@@ -924,7 +921,8 @@ struct BandRun {
                 MCD_TRY(block_apply_dev(cur, 1, dXm, out, false));
                 cur = out;
             }
-            return MCD_OK;   // the second pass wrote R (accumulated) into outB
+            MCD_HIP(hipMemcpyAsync(outB, dBacc, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
+            return MCD_OK;
         };
         std::vector<int> rank(max_blocks + 2, -1);
         auto read_ranks = [&](int upto) -> int {
