@@ -204,15 +204,23 @@ __global__ __launch_bounds__(BBS) void k_bcombine(int64_t n, int K, const double
     }
 }
 
-__global__ __launch_bounds__(BBS) void k_bnormalize(int64_t n, double *__restrict__ v) {
-    __shared__ double tot;
+// Normalising psi: workgroup partial sums of squares (grid-stride, fixed
+// order), k_finalize_sum into a device scalar, then v *= 1 / sqrt(sum).
+__global__ __launch_bounds__(BBS) void k_bsumsq(int64_t n, const double *__restrict__ v,
+                                                double *__restrict__ partials) {
     double acc = 0.0;
-    for (int64_t r = threadIdx.x; r < n; r += BBS) acc += v[r] * v[r];
-    acc = block_sum<BBS>(acc);
-    if (threadIdx.x == 0) tot = acc;
-    __syncthreads();
-    const double s = tot > 0.0 ? 1.0 / sqrt(tot) : 0.0;
-    for (int64_t r = threadIdx.x; r < n; r += BBS) v[r] *= s;
+    for (int64_t r = (int64_t)blockIdx.x * BBS + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * BBS)
+        acc += v[r] * v[r];
+    store_partial<BBS>(block_sum<BBS>(acc), partials);
+}
+
+__global__ __launch_bounds__(BBS) void k_bscale(int64_t n, double *__restrict__ v,
+                                                const double *__restrict__ nrm2) {
+    const double s = scale_from(nrm2, 1);
+    for (int64_t r = (int64_t)blockIdx.x * BBS + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * BBS)
+        v[r] *= s;
 }
 
 static double bwall_ms() {
@@ -295,7 +303,10 @@ extern "C" int mcd_batch_lanczos_ground(mcd_op *const *ops, int32_t n_ops,
     CK(hipMalloc(&sc, (size_t)2 * K * stride * sizeof(double)));
     CK(hipMemsetAsync(sc, 0, (size_t)2 * K * stride * sizeof(double), s));
     CK(hipMalloc(&part, std::max(nb, ub) * sizeof(double)));
-    CK(hipMalloc(&coef, (size_t)stride * sizeof(double)));
+    // psi coefficients of every instance, then the norm partials (at most
+    // 2048 workgroups) and one squared norm per instance
+    constexpr int kNormPart = 2048;
+    CK(hipMalloc(&coef, ((size_t)K * stride + kNormPart + K) * sizeof(double)));
     CK(hipMalloc(&iv, (K + 1) * sizeof(int)));
     std::vector<int> hact(K + 1, 1);
     hact[K] = 0;   // step counter
@@ -386,21 +397,34 @@ extern "C" int mcd_batch_lanczos_ground(mcd_op *const *ops, int32_t n_ops,
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
     int all_conv = 1, max_it = 0;
+    // psi_i = sum_q (s_q / ||u_q||) u_q, normalised: all coefficients in one
+    // upload (hc lives until the synchronisation below), then per instance
+    // the combination, its norm and the scaling, with no host round trip
+    std::vector<double> hc((size_t)K * stride, 0.0);
     for (int i = 0; i < K; i++) {
         e0_out[i] = lam[i];
         if (iters_out) iters_out[i] = Kdone[i];
         all_conv &= conv[i];
         max_it = std::max(max_it, Kdone[i]);
-        if (psi0_dev && psi0_dev[i]) {
-            const int Ki = Kdone[i];
-            std::vector<double> c(Ki);
-            for (int q = 0; q < Ki; q++) c[q] = svec[i][q] / sqrt(hn[(size_t)i * stride + q]);
-            CK(hipMemcpyAsync(coef, c.data(), Ki * sizeof(double), hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_bcombine, dim3((unsigned)std::min<int64_t>((hd[i].n + 255) / 256, 2048)),
-                               dim3(BBS), 0, s, hd[i].n, Ki, U + hd[i].ubase, coef, psi0_dev[i]);
-            hipLaunchKernelGGL(k_bnormalize, dim3(1), dim3(BBS), 0, s, hd[i].n, psi0_dev[i]);
+        if (psi0_dev && psi0_dev[i])
+            for (int q = 0; q < Kdone[i]; q++)
+                hc[(size_t)i * stride + q] = svec[i][q] / sqrt(hn[(size_t)i * stride + q]);
+    }
+    if (psi0_dev) {
+        double *npart = coef + (size_t)K * stride, *nrm2 = npart + kNormPart;
+        CK(hipMemcpyAsync(coef, hc.data(), hc.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        for (int i = 0; i < K; i++) {
+            if (!psi0_dev[i]) continue;
+            const int64_t ni = hd[i].n;
+            const unsigned g = (unsigned)std::max<int64_t>(
+                1, std::min<int64_t>((ni + BBS - 1) / BBS, kNormPart));
+            hipLaunchKernelGGL(k_bcombine, dim3(g), dim3(BBS), 0, s, ni, Kdone[i],
+                               U + hd[i].ubase, coef + (size_t)i * stride, psi0_dev[i]);
+            hipLaunchKernelGGL(k_bsumsq, dim3(g), dim3(BBS), 0, s, ni, psi0_dev[i], npart);
+            hipLaunchKernelGGL((k_finalize_sum<BBS>), dim3(1), dim3(BBS), 0, s, (int)g, npart,
+                               nrm2 + i);
+            hipLaunchKernelGGL(k_bscale, dim3(g), dim3(BBS), 0, s, ni, psi0_dev[i], nrm2 + i);
             CK(hipGetLastError());
-            CK(hipStreamSynchronize(s));
         }
     }
     CK(hipStreamSynchronize(s));
