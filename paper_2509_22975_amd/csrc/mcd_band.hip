@@ -1794,8 +1794,8 @@ __global__ void k_shift_project(int64_t n, double *__restrict__ y, const double 
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r < n) y[r] = y[r] - e0 * x[r] - c * psi[r];
 }
-// x += a p, res -= a ap with a = *rr / *pap; nothing when pap <= 0 (the
-// solve stops there).
+// x += a p, res -= a ap with a = *rr / *pap (rr = <res, z>, z the
+// preconditioned residual); nothing when pap <= 0 (the solve stops there).
 __global__ void k_axpy2(int64_t n, const double *__restrict__ rr, const double *__restrict__ pap,
                         const double *__restrict__ p, const double *__restrict__ ap,
                         double *__restrict__ x, double *__restrict__ res) {
@@ -1817,6 +1817,39 @@ __global__ void k_sub_scaled(int64_t n, double *__restrict__ y, double c,
                              const double *__restrict__ x) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r < n) y[r] -= c * x[r];
+}
+// Jacobi step of the preconditioned solve: z = r / max(d - e0, dfloor) (d the
+// diagonal of H) and the workgroup partials of <psi, z>; grid-stride, fixed
+// order.
+__global__ __launch_bounds__(BS) void k_jacobi(int64_t n, const double *__restrict__ r,
+                                               const double *__restrict__ d, double e0,
+                                               double dfloor, const double *__restrict__ psi,
+                                               double *__restrict__ z,
+                                               double *__restrict__ partials) {
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * BS) {
+        const double v = r[i] / fmax(d[i] - e0, dfloor);
+        z[i] = v;
+        acc += psi[i] * v;
+    }
+    store_partial<BS>(block_sum<BS>(acc), partials);
+}
+// z -= c psi (c = *c_dev) and the workgroup partials of <r, z>.
+__global__ __launch_bounds__(BS) void k_project_dot(int64_t n, double *__restrict__ z,
+                                                    const double *__restrict__ psi,
+                                                    const double *__restrict__ c_dev,
+                                                    const double *__restrict__ r,
+                                                    double *__restrict__ partials) {
+    const double c = *c_dev;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * BS) {
+        const double v = z[i] - c * psi[i];
+        z[i] = v;
+        acc += r[i] * v;
+    }
+    store_partial<BS>(block_sum<BS>(acc), partials);
 }
 
 // First block column of (z - T)^-1 times R0 (first p columns) for the block
@@ -1884,10 +1917,11 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     mcd_op *op_gs = nullptr;
     double *lam = nullptr, *acc = nullptr, *part = nullptr, *scal = nullptr;
     double *xi = nullptr, *res = nullptr, *dir = nullptr, *adir = nullptr;
-    double *psi_n = nullptr, *scr = nullptr;
+    double *psi_n = nullptr, *scr = nullptr, *zv = nullptr;
     auto cleanup = [&]() {
         for (void *q : {(void *)lam, (void *)acc, (void *)part, (void *)scal, (void *)xi,
-                        (void *)res, (void *)dir, (void *)adir, (void *)psi_n, (void *)scr})
+                        (void *)res, (void *)dir, (void *)adir, (void *)psi_n, (void *)scr,
+                        (void *)zv})
             if (q) (void)dfree(q, A);
         if (op_gs) mcd_op_destroy(op_gs);
     };
@@ -2098,17 +2132,35 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
         }
     }
 
-    // (H - E0) xi = P lam on F~, xi orthogonal to psi0 (conjugate gradients;
-    // H - E0 is positive definite on the complement of a non-degenerate psi0).
+    // (H - E0) xi = P lam on F~, xi orthogonal to psi0: conjugate gradients
+    // (H - E0 is positive definite on the complement of a non-degenerate
+    // psi0), preconditioned by P D^-1 P with D = diag(H) - E0 (Jacobi; D >= 0
+    // since E0 is at most any diagonal element, floored for safety).
     CK(dmalloc((void **)&xi, n * sizeof(double), A));
     CK(dmalloc((void **)&res, n * sizeof(double), A));
     CK(dmalloc((void **)&dir, n * sizeof(double), A));
     CK(dmalloc((void **)&adir, n * sizeof(double), A));
+    CK(dmalloc((void **)&zv, n * sizeof(double), A));
     const unsigned gv = gridn(n, 256);
+    const unsigned gp = std::min<unsigned>(gridn(n, BS), 2048);   // partial-sum kernels
+    const double dfloor = 1e-6 * std::max(1.0, fabs(e0));
     auto dot = [&](const double *a, const double *b, double *out) -> int {
         MCD_TRY(dev_dot(op_gs, a, b, n, scal, s));
         MCD_HIP(hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, s));
         MCD_HIP(hipStreamSynchronize(s));
+        return MCD_OK;
+    };
+    // zv = P D^-1 res, *rz_d = <res, zv> (scal[6] holds <psi0, D^-1 res>)
+    auto precond = [&](double *rz_d) -> int {
+        hipLaunchKernelGGL(k_jacobi, dim3(gp), dim3(BS), 0, s, n, res, op_gs->d_diag, e0, dfloor,
+                           psi_n, zv, op_gs->d_partials);
+        hipLaunchKernelGGL((k_finalize_sum<BS>), dim3(1), dim3(BS), 0, s, (int)gp,
+                           op_gs->d_partials, scal + 6);
+        hipLaunchKernelGGL(k_project_dot, dim3(gp), dim3(BS), 0, s, n, zv, psi_n, scal + 6, res,
+                           op_gs->d_partials);
+        hipLaunchKernelGGL((k_finalize_sum<BS>), dim3(1), dim3(BS), 0, s, (int)gp,
+                           op_gs->d_partials, rz_d);
+        MCD_HIP(hipGetLastError());
         return MCD_OK;
     };
     double c = 0.0;
@@ -2116,31 +2168,33 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     TRY(dot(psi_n, res, &c));
     hipLaunchKernelGGL(k_sub_scaled, dim3(gv), dim3(256), 0, s, n, res, c, psi_n);
     CK(hipMemsetAsync(xi, 0, n * sizeof(double), s));
-    CK(hipMemcpyAsync(dir, res, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     // device scalars: scal[1] = <psi0, A dir>, scal[2] = <dir, A dir>,
-    // scal[3 + (it & 1)] = <res, res> at the start of iteration it; the host
-    // reads pap and the new <res, res> once per iteration
+    // scal[3 + (it & 1)] = <res, z> at the start of iteration it, scal[5] =
+    // <res, res>; the host reads pap and <res, res> once per iteration
     double rr = 0.0;
-    TRY(dev_dot(op_gs, res, res, n, scal + 3, s));
-    CK(hipMemcpyAsync(&rr, scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+    TRY(dev_dot(op_gs, res, res, n, scal + 5, s));
+    TRY(precond(scal + 3));
+    CK(hipMemcpyAsync(dir, zv, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    CK(hipMemcpyAsync(&rr, scal + 5, sizeof(double), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
     const double bnorm = sqrt(rr);
     int it = 0;
     bool conv = bnorm == 0.0;
     double rel = 0.0;
     while (!conv && it < cg_max_iter) {
-        double *rr_d = scal + 3 + (it & 1), *rr2_d = scal + 3 + ((it + 1) & 1);
+        double *rz_d = scal + 3 + (it & 1), *rz2_d = scal + 3 + ((it + 1) & 1);
         TRY(apply_any(op_gs, MCD_F64, 1, dir, adir, s));
         TRY(dev_dot(op_gs, psi_n, adir, n, scal + 1, s));
         hipLaunchKernelGGL(k_shift_project, dim3(gv), dim3(256), 0, s, n, adir, dir, e0, psi_n,
                            scal + 1);
         TRY(dev_dot(op_gs, dir, adir, n, scal + 2, s));
-        hipLaunchKernelGGL(k_axpy2, dim3(gv), dim3(256), 0, s, n, rr_d, scal + 2, dir, adir, xi,
+        hipLaunchKernelGGL(k_axpy2, dim3(gv), dim3(256), 0, s, n, rz_d, scal + 2, dir, adir, xi,
                            res);
-        TRY(dev_dot(op_gs, res, res, n, rr2_d, s));
+        TRY(dev_dot(op_gs, res, res, n, scal + 5, s));
+        TRY(precond(rz2_d));
         double pap = 0.0, rr2 = 0.0;
         CK(hipMemcpyAsync(&pap, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-        CK(hipMemcpyAsync(&rr2, rr2_d, sizeof(double), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(&rr2, scal + 5, sizeof(double), hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
         if (!(pap > 0.0)) break;   // not positive definite: degenerate ground state
         it++;
@@ -2149,8 +2203,7 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             conv = true;
             break;
         }
-        hipLaunchKernelGGL(k_xpby, dim3(gv), dim3(256), 0, s, n, res, rr2_d, rr_d, dir);
-        rr = rr2;
+        hipLaunchKernelGGL(k_xpby, dim3(gv), dim3(256), 0, s, n, zv, rz2_d, rz_d, dir);
     }
     CK(hipGetLastError());
     // contractions with psi0: dE0 and <xi| dH |psi0>
