@@ -15,7 +15,11 @@ Pins (tests/test_oracle_hamiltonian.py): the independent Kronecker-product
 Jordan-Wigner construction ``jw_full`` below on <= 6-8 orbitals (pattern and
 values), H = H^T, the 4-site 36x36 sector of App. BFS vs DFS (off-diagonal
 count and values, diagonal multiples of U), and every energy pin of the
-Lanczos tests.
+Lanczos tests.  The row checker (``hop_terms_rows`` / ``apply_rows``, used for
+single rows of bases too large for ``build_csr``) is pinned to the rows of
+``build_csr`` and ``offdiag_pattern`` (full sectors and random subsets, one and
+several vectors) and to the dense Kronecker matrix; planted mistakes (a sign,
+a column, a row, a dropped element) are shown to fail that comparison.
 """
 from __future__ import annotations
 

@@ -12,6 +12,14 @@ plain-C version (built by ``build_c``).  The two are pinned against each other
 bit for bit, and the C chain's visit frequencies are pinned against the exact
 stationary distribution exp(-beta_s E_diag)/Z on enumerated sectors
 (detailed balance of a symmetric proposal with Metropolis acceptance).
+
+The paper's step sampler (``bfs_python`` / ``bfs_numpy``, Eq.
+boltzmann_factor) is pinned by: the two forms bit for bit; its limits (beta = 0
+reaches the whole sector in breadth-first shells, large beta keeps only states
+without double occupation); the sizes of the pre-accepted levels; and the
+acceptance law itself -- over many seeds, the kept fraction of first-step
+proposals with n_U = 0, 1, 2 matches min(1, exp(-beta U n_U)) at two values of
+U (a law without U, or one taken on the change of n_U, is rejected).
 """
 from __future__ import annotations
 

@@ -95,3 +95,92 @@ def test_conservation_and_hermiticity_random_basis():
     # each image differs from its source in exactly two bits of one spin string
     x = keys[r] ^ keys[c]
     assert np.all(np.bitwise_count(x) == 2)
+
+
+# --- the row checker used at full size (hop_terms_rows / apply_rows) --------
+# The full-size parity tests and the CPU baseline check single rows of H~ x
+# with oracle.hamiltonian.apply_rows; these tests tie it to the whole-matrix
+# definition (build_csr, itself pinned to the Kronecker construction above)
+# and to the dense Kronecker matrix directly.
+def _row_cases():
+    out = []
+    for model in MODELS[1:] + [_random_model(7)]:
+        k = fock.sector_keys(model.n_orb, model.n_up, model.n_dn)
+        out.append((model, k))
+        rng = np.random.default_rng(model.n_orb)
+        out.append((model, np.sort(rng.choice(k, size=max(2, len(k) // 3), replace=False))))
+    return out
+
+
+@pytest.mark.parametrize("case", range(len(MODELS[1:]) * 2 + 2))
+def test_apply_rows_equals_matrix_rows(case):
+    model, keys = _row_cases()[case]
+    H = ham.build_csr(keys, model)
+    rng = np.random.default_rng(case)
+    n = len(keys)
+    rows = np.sort(rng.choice(n, size=max(1, n // 4), replace=False))
+    x1 = rng.uniform(-1, 1, n)
+    x2 = rng.uniform(-1, 1, (n, 3))
+    y1 = ham.apply_rows(keys, rows, model, x1)
+    y2 = ham.apply_rows(keys, rows, model, x2)
+    assert y1.shape == (len(rows),) and y2.shape == (len(rows), 3)
+    assert np.max(np.abs(y1 - (H @ x1)[rows])) <= 1e-15 * max(1.0, np.max(np.abs(y1)))
+    assert np.max(np.abs(y2 - (H @ x2)[rows])) <= 1e-15 * max(1.0, np.max(np.abs(y2)))
+    # every row at once, against the dense Kronecker-product matrix
+    if n <= 1000:
+        Hj = ham.jw_restricted(keys, model)
+        yall = ham.apply_rows(keys, np.arange(n), model, x1)
+        assert np.max(np.abs(yall - Hj @ x1)) <= 1e-13
+
+
+@pytest.mark.parametrize("case", range(len(MODELS[1:]) * 2 + 2))
+def test_hop_terms_rows_equal_pattern_rows(case):
+    model, keys = _row_cases()[case]
+    pr, pc, pv = ham.offdiag_pattern(keys, model)
+    rng = np.random.default_rng(100 + case)
+    rows = np.sort(rng.choice(len(keys), size=max(1, len(keys) // 5), replace=False))
+    r, c, v = ham.hop_terms_rows(keys, rows, model)
+    # merge duplicates (a pair listed twice) the way the pattern does
+    import scipy.sparse as sp
+    m = sp.coo_matrix((v, (r, c)), shape=(len(keys), len(keys))).tocsr()
+    m.sum_duplicates()
+    m = m.tocoo()
+    o = np.lexsort((m.col, m.row))
+    sel = np.isin(pr, rows)
+    assert np.array_equal(m.row[o], pr[sel]) and np.array_equal(m.col[o], pc[sel])
+    assert np.array_equal(m.data[o], pv[sel])
+
+
+def _planted(kind, keys, rows, model, x):
+    """apply_rows with one plausible mistake planted in its element list."""
+    r, c, v = ham.hop_terms_rows(keys, rows, model)
+    if kind == "sign":          # one element with the wrong fermion sign
+        v = v.copy()
+        v[len(v) // 2] = -v[len(v) // 2]
+    elif kind == "column":      # one element read from the neighbouring column
+        c = c.copy()
+        c[len(c) // 2] = (c[len(c) // 2] + 1) % len(keys)
+    elif kind == "row":         # one element credited to the neighbouring row
+        r = r.copy()
+        i = len(r) // 2
+        r[i] = rows[(np.searchsorted(rows, r[i]) + 1) % len(rows)]
+    elif kind == "dropped":     # one element missing
+        r, c, v = np.delete(r, len(r) // 2), np.delete(c, len(c) // 2), np.delete(v, len(v) // 2)
+    d = fock.diagonal(np.asarray(keys, dtype=np.uint64)[rows], model)
+    y = d * x[rows]
+    np.add.at(y, np.searchsorted(rows, r), v * x[c])
+    return y
+
+
+@pytest.mark.parametrize("kind", ["sign", "column", "row", "dropped"])
+def test_row_pin_catches_planted_mistakes(kind):
+    """The comparison above fails for each planted mistake (so it is a pin)."""
+    model, keys = _row_cases()[1]
+    H = ham.build_csr(keys, model)
+    rng = np.random.default_rng(0)
+    rows = np.arange(0, len(keys), 2)
+    x = rng.uniform(-1, 1, len(keys))
+    good = _planted("none", keys, rows, model, x)
+    assert np.max(np.abs(good - (H @ x)[rows])) <= 1e-15 * np.max(np.abs(good))
+    bad = _planted(kind, keys, rows, model, x)
+    assert np.max(np.abs(bad - (H @ x)[rows])) > 1e-6

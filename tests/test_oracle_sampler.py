@@ -122,3 +122,47 @@ def test_step_sampler_preacceptance():
             assert sa == 0 and np.array_equal(a, np.sort(Pl[:nf]))
         else:
             assert np.all(np.isin(Pl, a)) and np.all(fock.double_occupation(a[~np.isin(a, Pl)]) >= lvl)
+
+
+@pytest.mark.parametrize("U", [4.0, 8.0])
+def test_step_sampler_acceptance_law(U):
+    """Acceptance of the step sampler (Eq. boltzmann_factor): a proposal is
+    kept with probability min(1, exp(-beta U n_U)), n_U the double occupation
+    of the proposed state.  First step from a state with one doubly occupied
+    site, so the proposals fall in the classes n_U = 0, 1 and 2; over many
+    seeds the kept fraction of each class must match exp(-beta U n_U) (a law
+    without U, or one indexed by the change of n_U, fails)."""
+    beta = 0.2
+    m = W.chain(8, U=U, mu=U / 2, pbc=True)
+    up, dn = 0b01010110, 0b10101010                  # site 1 doubly occupied, site 0 empty
+    start = (up << 32) | dn
+    # the proposals of the first step and their classes
+    props = []
+    for (i, j, _) in m.bonds:
+        for spin in (0, 1):
+            for src, dst in ((i, j), (j, i)):
+                s = up if spin == 0 else dn
+                if not (s >> src) & 1 or (s >> dst) & 1:
+                    continue
+                s2 = s ^ ((1 << src) | (1 << dst))
+                y = (s2 << 32) | dn if spin == 0 else (up << 32) | s2
+                props.append((y, bin((y >> 32) & y & 0xFF).count("1")))
+    classes = sorted(set(k for _, k in props))
+    assert classes == [0, 1, 2]
+    tried = {k: 0 for k in classes}
+    kept = {k: 0 for k in classes}
+    for seed in range(2500):
+        a, st = sampler.bfs_numpy(m, start, seed, beta, 10**9, 1)
+        got = set(int(k) for k in a)
+        for y, k in props:
+            tried[k] += 1
+            kept[k] += y in got
+    for k in classes:
+        p = np.exp(-beta * U * k)
+        f = kept[k] / tried[k]
+        sd = np.sqrt(max(p * (1 - p), 1e-12) / tried[k])
+        assert abs(f - p) <= 4.5 * sd + 1e-12, (k, f, p)
+        if k > 0:
+            # the same law without U, and one counting the change of n_U
+            for wrong in (np.exp(-beta * k), np.exp(-beta * U * (k - 1))):
+                assert abs(f - wrong) > 8 * sd, (k, f, wrong)
