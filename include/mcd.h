@@ -25,13 +25,26 @@
  *   and j); c+_{i s} or c_{i s} carries (-1)^(electrons in orbitals ordered
  *   before (i, s)).
  * Memory.  Pointers named *_dev are device pointers on the current HIP
- *   device; all others are host pointers.  Device inputs and outputs belong
- *   to the caller; an operator handle owns the device memory it allocates
- *   (its copy of the keys, index, CSR, scratch) until mcd_op_destroy.
+ *   device; all others are host pointers.  The library allocates no device
+ *   memory: every device buffer it uses is a piece of a caller-owned
+ *   workspace (mcd_ws, below) -- typically a torch tensor -- and device
+ *   inputs and outputs belong to the caller.  An operator handle holds its
+ *   copy of the keys, index, CSR and reduction scratch in the workspace it
+ *   was created from until mcd_op_destroy; a solver call takes its scratch
+ *   from the workspace it is given and returns it before it returns.  Size
+ *   queries (mcd_op_workspace_size, mcd_lanczos_workspace_size,
+ *   mcd_band_workspace_size) give the bytes a call needs from an empty
+ *   workspace; a call whose workspace runs out returns MCD_E_WORKSPACE
+ *   having released what it took, and mcd_ws_stats reports a size at which
+ *   the failing request would have been served (the caller may grow its
+ *   buffer to it and call again).
  * Streams.  `stream` is a hipStream_t (NULL = default stream).  Work is
- *   enqueued on it; calls that return host values synchronise it first and
- *   say so.  Calls on one operator from several host threads or streams at
- *   once race on its scratch buffers.
+ *   enqueued on it and nowhere else: the library creates no streams and no
+ *   host threads that touch the GPU.  Calls that return host values
+ *   synchronise it first and say so.  All calls that use one workspace must
+ *   be ordered on one stream (a released piece is reused by later work on
+ *   that stream); calls on one operator from several host threads or streams
+ *   at once race on its scratch buffers.
  * Errors.  Every call returns MCD_OK (0), a positive warning (the result is
  *   still written) or a negative error code; mcd_last_error() gives a
  *   message for the calling thread.  Nothing aborts or throws across the ABI.
@@ -56,6 +69,10 @@ enum {
     MCD_E_SECTOR = -2,       /* key outside the sector, unsorted or duplicate */
     MCD_E_HIP = -3,          /* a HIP runtime call failed */
     MCD_E_CAPACITY = -4,     /* output buffer or format limit too small */
+    MCD_E_WORKSPACE = -5,    /* the caller's workspace is too small (see mcd_ws_stats) */
+    MCD_E_NUMERIC = -6,      /* a non-finite value (NaN / Inf) in an input or in the
+                                recurrence coefficients read back from the device */
+    MCD_E_BREAKDOWN = -7,    /* a solve met a degenerate or indefinite system */
 };
 
 enum { MCD_STORAGE_AUTO = 0, MCD_STORAGE_ON_THE_FLY = 1, MCD_STORAGE_CSR = 2 };
@@ -73,9 +90,26 @@ typedef struct mcd_model {
 } mcd_model;
 
 typedef struct mcd_op mcd_op;
+typedef struct mcd_ws mcd_ws;
 
 const char *mcd_last_error(void);
 int mcd_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Workspace.  mcd_ws_create wraps a caller-owned device buffer of `bytes`
+ * bytes at base_dev (256-byte aligned; e.g. a torch.uint8 tensor's
+ * data_ptr()).  Only host bookkeeping is created: the buffer stays the
+ * caller's and must outlive the handle and every operator or kept run made
+ * from it.  Pieces are handed out first-fit, 256-byte aligned.
+ * mcd_ws_stats: size, bytes in use, the most ever in use, and `need` -- after
+ * a call returned MCD_E_WORKSPACE, a workspace size at which the failing
+ * request would have been served (0 if none failed).  Any output may be
+ * NULL.  mcd_ws_destroy frees the bookkeeping only (NULL is ignored).
+ * ------------------------------------------------------------------------- */
+int mcd_ws_create(void *base_dev, size_t bytes, mcd_ws **out);
+void mcd_ws_destroy(mcd_ws *ws);
+int mcd_ws_stats(const mcd_ws *ws, size_t *size, size_t *in_use, size_t *high_water,
+                 size_t *need);
 
 /* ---------------------------------------------------------------------------
  * mcd_basis_build -- the truncated basis F~ (Sec. Subspace of the ground
@@ -119,7 +153,8 @@ int mcd_version(void);
  *   already holds >= n_f states, F~ is its first n_f states in (n_U, key)
  *   order and steps_out = 0.  A level must hold < 2^31 states.
  * keys_dev: [cap] device output.  Returns MCD_E_CAPACITY if cap is too
- * small, MCD_E_SECTOR if start_key is not in the sector.  Synchronises.
+ * small, MCD_E_SECTOR if start_key is not in the sector.  Scratch (visit
+ * tables, sort buffers, frontier) comes from ws.  Synchronises.
  * ------------------------------------------------------------------------- */
 typedef struct mcd_basis_cfg {
     int32_t mode;             /* MCD_BASIS_FULL or MCD_BASIS_CHAIN */
@@ -135,7 +170,7 @@ typedef struct mcd_basis_cfg {
 } mcd_basis_cfg;
 
 int mcd_basis_build(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t *keys_dev,
-                    int64_t cap, int64_t *n_out, int64_t *steps_out, void *stream);
+                    int64_t cap, int64_t *n_out, int64_t *steps_out, mcd_ws *ws, void *stream);
 
 /* ---------------------------------------------------------------------------
  * mcd_op_create -- the operator H~ = P H P on a basis (Eq.
@@ -148,14 +183,29 @@ int mcd_basis_build(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t *
  *   MCD_STORAGE_CSR stores the matrix once as a packed CSR (one 32-bit word
  *   per nonzero: column, sign, amplitude class); MCD_STORAGE_AUTO picks CSR
  *   when it fits the format (n <= 2^(31 - ceil(log2 #classes)), <= 32 distinct
- *   |t|) and the memory
- *   budget (free HBM / 2), else on-the-fly.
+ *   |t|) and the workspace holds it, else on-the-fly.
  * validate != 0 checks on the GPU that the keys are sorted, unique and within
- *   n_orb bits (MCD_E_SECTOR otherwise).  Synchronises.
+ *   n_orb bits (MCD_E_SECTOR otherwise).
+ * ws: every buffer of the operator is taken from it and stays until
+ *   mcd_op_destroy (which returns them).  A CSR operator also times its
+ *   one-vector kernels and, when ws has room left, builds the grouped layout
+ *   of kernels 7 / 8 (mcd_op_set_kernel).  Synchronises.
  * ------------------------------------------------------------------------- */
 int mcd_op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32_t storage,
-                  int32_t validate, void *stream, mcd_op **out);
+                  int32_t validate, mcd_ws *ws, void *stream, mcd_op **out);
 void mcd_op_destroy(mcd_op *op);
+
+/* Workspace bytes mcd_op_create needs from an empty workspace, for keys_dev
+ * [n] and `storage`.  On the fly: a closed form (ws may be NULL).  CSR (and
+ * AUTO when the format fits): the count of kept hops is needed, so the index
+ * is built and the nonzeros counted in the probe workspace ws; with ws NULL
+ * or smaller than the probe the call returns MCD_E_WORKSPACE with *bytes =
+ * the probe size.  *bytes covers the operator and its construction scratch;
+ * *bytes_grouped (may be NULL) also the largest grouped layout, so that
+ * mcd_op_create builds it.  Synchronises. */
+int mcd_op_workspace_size(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                          int32_t storage, mcd_ws *ws, void *stream, size_t *bytes,
+                          size_t *bytes_grouped);
 
 typedef struct mcd_op_info_t {
     int64_t n;                /* basis size */
@@ -228,11 +278,11 @@ int mcd_hamiltonian_diagonal(const mcd_op *op, double *diag_dev, void *stream);
  * enumerates them (bond order, up before down), for checking connectivity and
  * signs exactly.  rows_dev, cols_dev: int64 [cap]; vals_dev: double [cap].
  * count_out (host) = number of triples; MCD_E_CAPACITY if cap is too small.
- * Synchronises.
+ * ws: 8 (row1 - row0) bytes of scratch.  Synchronises.
  * ------------------------------------------------------------------------- */
 int mcd_hamiltonian_connectivity(const mcd_op *op, int64_t row0, int64_t row1, int64_t *rows_dev,
                                  int64_t *cols_dev, double *vals_dev, int64_t cap,
-                                 int64_t *count_out, void *stream);
+                                 int64_t *count_out, mcd_ws *ws, void *stream);
 
 /* ---------------------------------------------------------------------------
  * mcd_hamiltonian_contract -- derivatives of H~ with respect to the model
@@ -245,11 +295,13 @@ int mcd_hamiltonian_connectivity(const mcd_op *op, int64_t row0, int64_t row1, i
  * With a = b = the normalised ground state these are dE0/dtheta
  * (Hellmann-Feynman).  a_dev, b_dev: [n] double.  `model` must be the model
  * the operator was built from.  d_t [n_bonds], d_U [n_orb], d_eps [n_orb]:
- * host outputs (any may be NULL).  One pass on the GPU; synchronises.
+ * host outputs (any may be NULL).  One pass on the GPU; workgroup partials
+ * (8 (n_bonds + 2 n_orb) min(ceil(n / 256), 2048) bytes) come from ws.
+ * Synchronises.
  * ------------------------------------------------------------------------- */
 int mcd_hamiltonian_contract(const mcd_op *op, const mcd_model *model, const double *a_dev,
                              const double *b_dev, double *d_t, double *d_U, double *d_eps,
-                             void *stream);
+                             mcd_ws *ws, void *stream);
 
 /* ---------------------------------------------------------------------------
  * mcd_lanczos_ground -- lowest eigenpair of H~ by Lanczos (App. Lanczos,
@@ -262,12 +314,20 @@ int mcd_hamiltonian_contract(const mcd_op *op, const mcd_model *model, const dou
  * breakdown, or at max_iter (MCD_NOCONV, result still written).
  * phi0_dev: [n] start vector or NULL; NULL draws phi0[r] = 2u - 1 with u the
  *   top 53 bits of the first splitmix64 output of the state (seed XOR key_r).
- * psi0_dev: [n] output ground state (unit norm), or NULL.  With
- *   store_vectors != 0 the Krylov vectors are kept in HBM (n * iters * 8 B)
- *   and psi0 is one weighted sum; otherwise the recurrence is run a second
- *   time (Eq. change_basis without storage).
+ * psi0_dev: [n] output ground state (unit norm, float64), or NULL.  With
+ *   store_vectors != 0 the Krylov vectors are kept in the workspace and psi0
+ *   is one weighted sum; otherwise the recurrence is run a second time
+ *   (Eq. change_basis without storage).
+ * precision MCD_F64: float64 vectors throughout.  MCD_F32: the Krylov vectors
+ *   and the product are float32 (float accumulation); the coefficients a_k,
+ *   b_k, the tridiagonal solve and psi0's combination stay float64, and E0 is
+ *   refined at the end by one float64 product: E0 = <psi0|H~|psi0> of the
+ *   (float64, normalised) Ritz vector, with info->residual = ||H~ psi0 -
+ *   E0 psi0|| from the same product.
  * alpha_out / beta_out: optional host arrays [max_iter] receiving a_k, b_{k+1}.
- * Synchronises.
+ * ws: scratch of mcd_lanczos_workspace_size bytes.  Returns MCD_E_NUMERIC if a
+ * coefficient read back is not finite (a NaN / Inf in the input or the
+ * operator).  Synchronises.
  * ------------------------------------------------------------------------- */
 typedef struct mcd_lanczos_cfg {
     int32_t max_iter;
@@ -276,6 +336,7 @@ typedef struct mcd_lanczos_cfg {
     uint64_t seed;
     int32_t store_vectors;
     int32_t min_iter;         /* run at least this many steps */
+    int32_t precision;        /* MCD_F64 or MCD_F32 (Krylov vectors) */
 } mcd_lanczos_cfg;
 
 typedef struct mcd_solve_info {
@@ -293,7 +354,10 @@ typedef struct mcd_solve_info {
 
 int mcd_lanczos_ground(const mcd_op *op, const mcd_lanczos_cfg *cfg, const double *phi0_dev,
                        double *e0, double *psi0_dev, double *alpha_out, double *beta_out,
-                       mcd_solve_info *info, void *stream);
+                       mcd_solve_info *info, mcd_ws *ws, void *stream);
+
+/* Workspace bytes mcd_lanczos_ground needs with this operator and cfg. */
+int mcd_lanczos_workspace_size(const mcd_op *op, const mcd_lanczos_cfg *cfg, size_t *bytes);
 
 /* ---------------------------------------------------------------------------
  * mcd_batch_lanczos_ground -- ground states of n_ops independent operators at
@@ -306,13 +370,14 @@ int mcd_lanczos_ground(const mcd_op *op, const mcd_lanczos_cfg *cfg, const doubl
  * (sum_i n_i (max_iter + 1) doubles; MCD_E_CAPACITY if they do not fit).
  * ops: [n_ops] CSR operators on the current device.  e0_out: host [n_ops].
  * psi0_dev: host array of n_ops device pointers ([n_i] doubles each) or NULL
- * (entries may be NULL).  iters_out: host [n_ops] or NULL.  Work runs on an
- * internal stream after `stream` has been synchronised; synchronises.
- * MCD_NOCONV if any operator stopped at max_iter.
+ * (entries may be NULL).  iters_out: host [n_ops] or NULL.  ws: the Krylov
+ * store and scratch (sum_i n_i (max_iter + 2) doubles and tables).  The graph
+ * is captured on `stream`.  Synchronises.  MCD_NOCONV if any operator stopped
+ * at max_iter.  cfg->precision must be MCD_F64.
  * ------------------------------------------------------------------------- */
 int mcd_batch_lanczos_ground(mcd_op *const *ops, int32_t n_ops, const mcd_lanczos_cfg *cfg,
                              double *e0_out, double *const *psi0_dev, int32_t *iters_out,
-                             mcd_solve_info *info, void *stream);
+                             mcd_solve_info *info, mcd_ws *ws, void *stream);
 
 /* ---------------------------------------------------------------------------
  * mcd_band_lanczos_green -- Green function of the truncated ground state on
@@ -330,7 +395,9 @@ int mcd_batch_lanczos_ground(mcd_op *const *ops, int32_t n_ops, const mcd_lanczo
  * G+_{mu nu}(i w) = [R^T (z - T)^-1 R]_{mu nu} at z = i w + E0 and
  * G-_{mu nu}(i w) = -[R^T (z - T)^-1 R] at z = E0 - i w (the resolvent form
  * of Eqs. green_qmatrix; R = start block in the Lanczos basis), evaluated by
- * a block continued fraction in complex128 on the host.
+ * a block continued fraction in complex128 on the host.  The particle and
+ * hole runs advance in lockstep on `stream` (each block step's kernels are
+ * enqueued for both runs before the next step).
  *
  * keys_dev [n], psi0_dev [n]: ground-state basis and vector (double).
  * orb, spin: [n_sel] host; spin 0 = up, 1 = down; n_sel <= 16.
@@ -343,7 +410,11 @@ int mcd_batch_lanczos_ground(mcd_op *const *ops, int32_t n_ops, const mcd_lanczo
  *   SpMM with float accumulation; Gram matrices, recurrence, deflation and
  *   the continued fraction stay float64.
  * max_blocks: block steps per run (Krylov dim <= max_blocks * p).
- * Synchronises.
+ * ws: every buffer of the call (cut, F~+- images, operators, Krylov blocks)
+ *   is taken from it and returned before the call returns;
+ *   mcd_band_workspace_size gives the bytes.  MCD_E_NUMERIC if psi0 has no
+ *   finite nonzero weight or a recurrence coefficient read back is not
+ *   finite.  Synchronises.
  * ------------------------------------------------------------------------- */
 typedef struct mcd_band_cfg {
     int32_t max_blocks;
@@ -369,7 +440,22 @@ int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int
                            const double *psi0_dev, double e0, int32_t n_sel, const int32_t *orb,
                            const int32_t *spin, int32_t n_freq, const double *omega,
                            const mcd_band_cfg *cfg, double *G_out, double *Gp_out,
-                           double *Gm_out, mcd_solve_info *info, void *stream);
+                           double *Gm_out, mcd_solve_info *info, mcd_ws *ws, void *stream);
+
+/* Workspace bytes mcd_band_lanczos_green (keep = 0) or
+ * mcd_band_lanczos_green_keep (keep != 0) needs from an empty workspace with
+ * these arguments.  The sizes of F~+- and of their operators are data
+ * dependent, so the call makes the cut, the images and both operators in the
+ * probe workspace ws, replays the takes of the Krylov blocks on its host
+ * bookkeeping, and releases everything (no block step is run).  If ws is too
+ * small for that preparation it returns MCD_E_WORKSPACE with *bytes = a size
+ * at which the failing request would have been served (grow ws and call
+ * again).  Synchronises. */
+int mcd_band_workspace_size(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                            const double *psi0_dev, double e0, int32_t n_sel, const int32_t *orb,
+                            const int32_t *spin, int32_t n_freq, const double *omega,
+                            const mcd_band_cfg *cfg, int32_t keep, mcd_ws *ws, void *stream,
+                            size_t *bytes);
 
 /* ---------------------------------------------------------------------------
  * mcd_band_lanczos_green_keep -- mcd_band_lanczos_green that also keeps the
@@ -380,11 +466,11 @@ int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int
  * Arguments and outputs as mcd_band_lanczos_green; cfg->w_t must be 1 and
  * cfg->per_column 0.  Every Krylov block is stored (max_blocks + 1 blocks of
  * n_x * P values per sector, P = n_sel rounded up to a power of two, in the
- * cfg->precision type), and all of it stays on the device until
- * mcd_band_keep_destroy.  On success *keep_out is a new handle owned by the
- * caller; on error it is NULL and nothing is kept.  keys_dev and psi0_dev are
- * not retained (the later derivative call passes them again).
- * Synchronises.
+ * cfg->precision type), and all of it stays in ws until mcd_band_keep_destroy
+ * (ws and its buffer must outlive the handle).  On success *keep_out is a new
+ * handle owned by the caller; on error it is NULL and nothing is kept.
+ * keys_dev and psi0_dev are not retained (the later derivative call passes
+ * them again).  Synchronises.
  * ------------------------------------------------------------------------- */
 typedef struct mcd_band_keep mcd_band_keep;
 int mcd_band_lanczos_green_keep(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
@@ -392,10 +478,11 @@ int mcd_band_lanczos_green_keep(const mcd_model *model, const uint64_t *keys_dev
                                 const int32_t *orb, const int32_t *spin, int32_t n_freq,
                                 const double *omega, const mcd_band_cfg *cfg, double *G_out,
                                 double *Gp_out, double *Gm_out, mcd_solve_info *info,
-                                void *stream, mcd_band_keep **keep_out);
+                                mcd_ws *ws, void *stream, mcd_band_keep **keep_out);
 
-/* Releases a handle of mcd_band_lanczos_green_keep (NULL is ignored).  No
- * call on the handle may be running. */
+/* Releases a handle of mcd_band_lanczos_green_keep (NULL is ignored): its
+ * pieces go back to the workspace of the forward call.  No call on the handle
+ * may be running. */
 void mcd_band_keep_destroy(mcd_band_keep *keep);
 
 /* ---------------------------------------------------------------------------
@@ -403,28 +490,27 @@ void mcd_band_keep_destroy(mcd_band_keep *keep);
  * instances (bath-parameter sets of a quantum impurity model, each with its
  * own basis and ground state), same selection, frequencies and cfg.
  *
- * The instances run concurrently on n_streams (1..8) internal HIP streams,
- * one host worker thread per stream taking the next instance, so the small
- * kernels of the Lanczos steps of different instances overlap on the GPU.
- * Each instance's result is computed exactly as by mcd_band_lanczos_green
- * (bit-identical).
+ * All runs (particle and hole of every instance) advance in lockstep: each
+ * kernel of a block step is enqueued for every unfinished run before the
+ * next, on `stream`, with one synchronisation every 8 block steps for the
+ * ranks and convergence checks of all of them.  Instances are prepared (cut,
+ * F~+-, operators) and run in groups of as many as ws holds at once.  Each
+ * instance's result is computed exactly as by mcd_band_lanczos_green
+ * (bit-identical: a run's arithmetic does not depend on the other runs).
  *
  * models, keys_dev, n, psi0_dev, e0: [n_inst] per-instance inputs (device
  *   keys / psi0 as in mcd_band_lanczos_green); G_out: [n_inst] host
  *   complex128 outputs [n_freq][n_sel][n_sel] (G = G+ + G-).
- * stream: the caller's stream; it is synchronised before the instances start
- *   (their inputs are read from it).
  * info (optional): iters = max over instances, krylov_dim / n_plus / n_minus /
  *   n_truncated summed, solve_ms = wall time of the batch.
- * Errors: the first failing instance's code, its message names the instance.
- * Synchronises.
+ * ws: must hold at least the largest single instance (MCD_E_WORKSPACE
+ *   otherwise).  Synchronises.
  * ------------------------------------------------------------------------- */
 int mcd_batch_band_green(const mcd_model *const *models, const uint64_t *const *keys_dev,
                          const int64_t *n, const double *const *psi0_dev, const double *e0,
                          int32_t n_inst, int32_t n_sel, const int32_t *orb, const int32_t *spin,
                          int32_t n_freq, const double *omega, const mcd_band_cfg *cfg,
-                         int32_t n_streams, double *const *G_out, mcd_solve_info *info,
-                         void *stream);
+                         double *const *G_out, mcd_solve_info *info, mcd_ws *ws, void *stream);
 
 /* ---------------------------------------------------------------------------
  * mcd_band_green_vjp -- reverse-mode derivative of the Green function (and of
@@ -458,7 +544,12 @@ int mcd_batch_band_green(const mcd_model *const *models, const uint64_t *const *
  * info: iters = conjugate-gradient iterations, residual = its relative
  *   residual, krylov_dim, n_plus, n_minus, solve_ms.
  * cg_tol: relative residual of the solve (1e-12 is typical); cg_max_iter.
- * Returns MCD_NOCONV (outputs filled) if the solve stopped at cg_max_iter.
+ * ws: the scratch of the call (ground-sector operator, solve vectors, the
+ *   Z = Q M product, which has the size of one sector's Krylov store; without
+ *   a kept forward also the two sector runs).
+ * Returns MCD_NOCONV (outputs filled) if the solve stopped at cg_max_iter,
+ * MCD_E_BREAKDOWN if it met <p, (H - E0) p> <= 0 (psi0 is not a
+ * non-degenerate ground state of H~: the response is undefined).
  * Synchronises.
  * ------------------------------------------------------------------------- */
 int mcd_band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
@@ -466,7 +557,7 @@ int mcd_band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int64_t
                        const int32_t *spin, int32_t n_freq, const double *omega,
                        const mcd_band_cfg *cfg, const double *G_bar, double e0_bar,
                        double cg_tol, int32_t cg_max_iter, double *d_t, double *d_U,
-                       double *d_eps, mcd_solve_info *info, void *stream);
+                       double *d_eps, mcd_solve_info *info, mcd_ws *ws, void *stream);
 
 /* ---------------------------------------------------------------------------
  * mcd_band_green_vjp_keep -- mcd_band_green_vjp on the sector runs kept by
@@ -477,14 +568,15 @@ int mcd_band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int64_t
  * model must be the same data.  The results are those of mcd_band_green_vjp
  * (the kept runs are the runs it would recompute).  keep is not consumed and
  * may serve several calls, one at a time (they share its scratch blocks).
- * Synchronises.
+ * ws: this call's scratch (the kept runs stay in the forward call's
+ * workspace).  Synchronises.
  * ------------------------------------------------------------------------- */
 int mcd_band_green_vjp_keep(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
                             const double *psi0_dev, double e0, int32_t n_sel, const int32_t *orb,
                             const int32_t *spin, int32_t n_freq, const double *omega,
                             const mcd_band_cfg *cfg, const double *G_bar, double e0_bar,
                             double cg_tol, int32_t cg_max_iter, double *d_t, double *d_U,
-                            double *d_eps, mcd_solve_info *info, void *stream,
+                            double *d_eps, mcd_solve_info *info, mcd_ws *ws, void *stream,
                             mcd_band_keep *keep);
 
 #ifdef __cplusplus

@@ -8,6 +8,14 @@ package without it raises, there is no fallback.
 
 Keys are passed as torch.int64 tensors holding the uint64 bit pattern
 (up << 32) | down.
+
+Device memory: the library allocates none; every call that needs device
+memory takes a workspace (``Workspace``: a torch.uint8 tensor wrapped by
+mcd_ws_create).  An ``Operator`` owns a workspace of exactly the size
+mcd_op_workspace_size reports; a kept band run (``BandKeep``) one of the size
+mcd_band_workspace_size reports; solver calls take their scratch from a
+workspace per (device, stream) that this module keeps and grows when a call
+reports MCD_E_WORKSPACE (``release_scratch()`` hands it back to torch).
 """
 from __future__ import annotations
 
@@ -21,6 +29,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmcd.so")
 
 MCD_OK, MCD_NOCONV = 0, 1
+MCD_E_WORKSPACE = -5
 STORAGE = {"auto": 0, "on_the_fly": 1, "otf": 1, "csr": 2}
 STORAGE_NAME = {0: "auto", 1: "on_the_fly", 2: "csr"}
 DTYPE = {"f64": 0, "f32": 1}
@@ -51,7 +60,7 @@ class McdOpInfo(ctypes.Structure):
 
 class McdLanczosCfg(ctypes.Structure):
     _fields_ = [("max_iter", c_i32), ("check_every", c_i32), ("tol", c_dbl), ("seed", c_u64),
-                ("store_vectors", c_i32), ("min_iter", c_i32)]
+                ("store_vectors", c_i32), ("min_iter", c_i32), ("precision", c_i32)]
 
 
 class McdSolveInfo(ctypes.Structure):
@@ -81,8 +90,16 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     L.mcd_last_error.restype = ctypes.c_char_p
     L.mcd_version.restype = ctypes.c_int
-    L.mcd_basis_build.argtypes = [P(McdModel), P(McdBasisCfg), c_vp, c_i64, P(c_i64), P(c_i64), c_vp]
-    L.mcd_op_create.argtypes = [P(McdModel), c_vp, c_i64, c_i32, c_i32, c_vp, P(c_vp)]
+    c_sz = ctypes.c_size_t
+    L.mcd_ws_create.argtypes = [c_vp, c_sz, P(c_vp)]
+    L.mcd_ws_destroy.argtypes = [c_vp]
+    L.mcd_ws_destroy.restype = None
+    L.mcd_ws_stats.argtypes = [c_vp, P(c_sz), P(c_sz), P(c_sz), P(c_sz)]
+    L.mcd_basis_build.argtypes = [P(McdModel), P(McdBasisCfg), c_vp, c_i64, P(c_i64), P(c_i64),
+                                  c_vp, c_vp]
+    L.mcd_op_create.argtypes = [P(McdModel), c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, P(c_vp)]
+    L.mcd_op_workspace_size.argtypes = [P(McdModel), c_vp, c_i64, c_i32, c_vp, c_vp, P(c_sz),
+                                        P(c_sz)]
     L.mcd_op_destroy.argtypes = [c_vp]
     L.mcd_op_destroy.restype = None
     L.mcd_op_info.argtypes = [c_vp, P(McdOpInfo)]
@@ -90,35 +107,37 @@ def lib():
     L.mcd_hamiltonian_apply.argtypes = [c_vp, c_i32, c_i32, c_vp, c_vp, c_vp]
     L.mcd_hamiltonian_diagonal.argtypes = [c_vp, c_vp, c_vp]
     L.mcd_hamiltonian_connectivity.argtypes = [c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_i64,
-                                               P(c_i64), c_vp]
+                                               P(c_i64), c_vp, c_vp]
     L.mcd_lanczos_ground.argtypes = [c_vp, P(McdLanczosCfg), c_vp, P(c_dbl), c_vp, P(c_dbl),
-                                     P(c_dbl), P(McdSolveInfo), c_vp]
+                                     P(c_dbl), P(McdSolveInfo), c_vp, c_vp]
+    L.mcd_lanczos_workspace_size.argtypes = [c_vp, P(McdLanczosCfg), P(c_sz)]
     L.mcd_hamiltonian_contract.argtypes = [c_vp, P(McdModel), c_vp, c_vp, P(c_dbl), P(c_dbl),
-                                           P(c_dbl), c_vp]
+                                           P(c_dbl), c_vp, c_vp]
     L.mcd_batch_lanczos_ground.argtypes = [P(c_vp), c_i32, P(McdLanczosCfg), P(c_dbl), P(c_vp),
-                                           P(c_i32), P(McdSolveInfo), c_vp]
-    if hasattr(L, "mcd_band_lanczos_green"):
-        L.mcd_band_lanczos_green.argtypes = [P(McdModel), c_vp, c_i64, c_vp, c_dbl, c_i32,
-                                             P(c_i32), P(c_i32), c_i32, P(c_dbl), P(McdBandCfg),
-                                             P(c_dbl), P(c_dbl), P(c_dbl), P(McdSolveInfo), c_vp]
+                                           P(c_i32), P(McdSolveInfo), c_vp, c_vp]
+    band = [P(McdModel), c_vp, c_i64, c_vp, c_dbl, c_i32, P(c_i32), P(c_i32), c_i32, P(c_dbl),
+            P(McdBandCfg)]
+    L.mcd_band_lanczos_green.argtypes = band + [P(c_dbl), P(c_dbl), P(c_dbl), P(McdSolveInfo),
+                                                c_vp, c_vp]
+    L.mcd_band_workspace_size.argtypes = band + [c_i32, c_vp, c_vp, P(c_sz)]
     L.mcd_batch_band_green.argtypes = [P(c_vp), P(c_vp), P(c_i64), P(c_vp), P(c_dbl), c_i32,
                                        c_i32, P(c_i32), P(c_i32), c_i32, P(c_dbl),
-                                       P(McdBandCfg), c_i32, P(c_vp), P(McdSolveInfo), c_vp]
-    L.mcd_band_green_vjp.argtypes = [P(McdModel), c_vp, c_i64, c_vp, c_dbl, c_i32, P(c_i32),
-                                     P(c_i32), c_i32, P(c_dbl), P(McdBandCfg), P(c_dbl), c_dbl,
-                                     c_dbl, c_i32, P(c_dbl), P(c_dbl), P(c_dbl), P(McdSolveInfo),
-                                     c_vp]
+                                       P(McdBandCfg), P(c_vp), P(McdSolveInfo), c_vp, c_vp]
+    vjp = band + [P(c_dbl), c_dbl, c_dbl, c_i32, P(c_dbl), P(c_dbl), P(c_dbl), P(McdSolveInfo),
+                  c_vp, c_vp]
+    L.mcd_band_green_vjp.argtypes = vjp
     L.mcd_band_lanczos_green_keep.argtypes = L.mcd_band_lanczos_green.argtypes + [P(c_vp)]
-    L.mcd_band_green_vjp_keep.argtypes = L.mcd_band_green_vjp.argtypes + [c_vp]
+    L.mcd_band_green_vjp_keep.argtypes = vjp + [c_vp]
     L.mcd_band_keep_destroy.argtypes = [c_vp]
     L.mcd_band_keep_destroy.restype = None
-    for name in ("mcd_basis_build", "mcd_op_create", "mcd_op_info", "mcd_op_set_kernel", "mcd_hamiltonian_apply",
-                 "mcd_hamiltonian_diagonal", "mcd_hamiltonian_connectivity", "mcd_lanczos_ground",
-                 "mcd_band_lanczos_green", "mcd_batch_lanczos_ground",
-                 "mcd_hamiltonian_contract", "mcd_band_green_vjp", "mcd_batch_band_green",
-                 "mcd_band_lanczos_green_keep", "mcd_band_green_vjp_keep"):
-        if hasattr(L, name):
-            getattr(L, name).restype = ctypes.c_int
+    for name in ("mcd_basis_build", "mcd_op_create", "mcd_op_info", "mcd_op_set_kernel",
+                 "mcd_hamiltonian_apply", "mcd_hamiltonian_diagonal",
+                 "mcd_hamiltonian_connectivity", "mcd_lanczos_ground", "mcd_band_lanczos_green",
+                 "mcd_batch_lanczos_ground", "mcd_hamiltonian_contract", "mcd_band_green_vjp",
+                 "mcd_batch_band_green", "mcd_band_lanczos_green_keep", "mcd_band_green_vjp_keep",
+                 "mcd_ws_create", "mcd_ws_stats", "mcd_op_workspace_size",
+                 "mcd_lanczos_workspace_size", "mcd_band_workspace_size"):
+        getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
 
@@ -144,6 +163,89 @@ def _torch():
 def _stream():
     torch = _torch()
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Workspace:
+    """A caller-owned device buffer handed to the library (mcd_ws): a
+    torch.uint8 tensor of `nbytes` bytes on `device` and its handle."""
+
+    def __init__(self, nbytes, device="cuda"):
+        torch = _torch()
+        self.nbytes = int(max(nbytes, 256) + 255) // 256 * 256
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        if self.buf.data_ptr() % 256:
+            raise RuntimeError("workspace buffer is not 256-byte aligned")
+        h = c_vp(0)
+        _check(lib().mcd_ws_create(c_vp(self.buf.data_ptr()), self.nbytes, ctypes.byref(h)),
+               "mcd_ws_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self) -> dict:
+        sz, used, high, need = (ctypes.c_size_t(0) for _ in range(4))
+        _check(lib().mcd_ws_stats(self._h, ctypes.byref(sz), ctypes.byref(used),
+                                  ctypes.byref(high), ctypes.byref(need)), "mcd_ws_stats")
+        return dict(size=sz.value, in_use=used.value, high_water=high.value, need=need.value)
+
+    def close(self):
+        if self._h:
+            lib().mcd_ws_destroy(self._h)
+            self._h = c_vp(0)
+            self.buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_SCRATCH = {}
+
+
+def _scratch_key():
+    torch = _torch()
+    return (torch.cuda.current_device(), torch.cuda.current_stream().cuda_stream)
+
+
+def scratch(min_bytes=0) -> Workspace:
+    """The solver scratch workspace of the current device and stream (kept
+    between calls, grown on demand; calls on one stream are ordered, so its
+    pieces are reused safely)."""
+    key = _scratch_key()
+    ws = _SCRATCH.get(key)
+    if ws is None or ws.nbytes < min_bytes:
+        if ws is not None:
+            ws.close()
+        ws = Workspace(max(min_bytes, 64 << 20), device=f"cuda:{key[0]}")
+        _SCRATCH[key] = ws
+    return ws
+
+
+def release_scratch():
+    """Hands every scratch workspace of this module back to torch."""
+    _torch().cuda.synchronize()
+    for ws in _SCRATCH.values():
+        ws.close()
+    _SCRATCH.clear()
+
+
+def _with_scratch(call, where, min_bytes=0, tries=8):
+    """call(ws_handle) on the scratch workspace; on MCD_E_WORKSPACE the scratch
+    grows to the size the failed request needed (at least doubling) and the
+    call is made again."""
+    need = min_bytes
+    for _ in range(tries):
+        ws = scratch(need)
+        code = call(ws.handle)
+        if code != MCD_E_WORKSPACE:
+            return _check(code, where)
+        need = max(ws.stats()["need"], 2 * ws.nbytes)
+        need = (need + (1 << 20) - 1) // (1 << 20) * (1 << 20)
+    raise McdError(MCD_E_WORKSPACE, where)
 
 
 class _ModelBuf:
@@ -186,9 +288,11 @@ def basis_build(model, mode="full", n_up=None, n_dn=None, start_key=0, seed=0, b
                       int(max_steps), int(n_f), int(pre_level))
     out = torch.empty(max(int(cap), 1), dtype=torch.int64, device=device)
     n_out, steps = c_i64(0), c_i64(0)
-    _check(lib().mcd_basis_build(ctypes.byref(mb.s), ctypes.byref(cfg), c_vp(out.data_ptr()),
-                                 int(cap), ctypes.byref(n_out), ctypes.byref(steps), _stream()),
-           "mcd_basis_build")
+    _with_scratch(lambda ws: lib().mcd_basis_build(ctypes.byref(mb.s), ctypes.byref(cfg),
+                                                   c_vp(out.data_ptr()), int(cap),
+                                                   ctypes.byref(n_out), ctypes.byref(steps), ws,
+                                                   _stream()),
+                  "mcd_basis_build")
     return out[: n_out.value], steps.value
 
 
@@ -203,10 +307,12 @@ class Operator:
         self.keys = keys.contiguous()
         self.n = int(keys.numel())
         self.device = keys.device
+        self.ws_bytes = operator_workspace_size(model, self.keys, storage, mb=self._mb)
+        self._ws = Workspace(self.ws_bytes, device=self.device)
         h = c_vp(0)
         _check(lib().mcd_op_create(ctypes.byref(self._mb.s), c_vp(self.keys.data_ptr()), self.n,
-                                   STORAGE[storage], 1 if validate else 0, _stream(),
-                                   ctypes.byref(h)), "mcd_op_create")
+                                   STORAGE[storage], 1 if validate else 0, self._ws.handle,
+                                   _stream(), ctypes.byref(h)), "mcd_op_create")
         self._h = h
 
     @property
@@ -264,8 +370,9 @@ class Operator:
         torch = _torch()
         row1 = self.n if row1 is None else row1
         cnt = c_i64(0)
+        ws = scratch(8 * max(row1 - row0, 1) + 4096)
         code = lib().mcd_hamiltonian_connectivity(self.handle, row0, row1, None, None, None, 0,
-                                                  ctypes.byref(cnt), _stream())
+                                                  ctypes.byref(cnt), ws.handle, _stream())
         if code not in (0, -4):
             _check(code, "mcd_hamiltonian_connectivity")
         m = max(cnt.value, 1)
@@ -274,7 +381,7 @@ class Operator:
         v = torch.empty(m, dtype=torch.float64, device=self.device)
         _check(lib().mcd_hamiltonian_connectivity(self.handle, row0, row1, c_vp(r.data_ptr()),
                                                   c_vp(c.data_ptr()), c_vp(v.data_ptr()), m,
-                                                  ctypes.byref(cnt), _stream()),
+                                                  ctypes.byref(cnt), ws.handle, _stream()),
                "mcd_hamiltonian_connectivity")
         k = cnt.value
         return r[:k].cpu().numpy(), c[:k].cpu().numpy(), v[:k].cpu().numpy()
@@ -286,18 +393,17 @@ class Operator:
         dt = np.zeros(len(m.bonds))
         dU = np.zeros(m.n_orb)
         de = np.zeros(m.n_orb)
-        _check(lib().mcd_hamiltonian_contract(self.handle, ctypes.byref(self._mb.s),
-                                              c_vp(a.data_ptr()), c_vp(b.data_ptr()),
-                                              dt.ctypes.data_as(P(c_dbl)),
-                                              dU.ctypes.data_as(P(c_dbl)),
-                                              de.ctypes.data_as(P(c_dbl)), _stream()),
-               "mcd_hamiltonian_contract")
+        _with_scratch(lambda ws: lib().mcd_hamiltonian_contract(
+            self.handle, ctypes.byref(self._mb.s), c_vp(a.data_ptr()), c_vp(b.data_ptr()),
+            dt.ctypes.data_as(P(c_dbl)), dU.ctypes.data_as(P(c_dbl)),
+            de.ctypes.data_as(P(c_dbl)), ws, _stream()), "mcd_hamiltonian_contract")
         return dt, dU, de
 
     def close(self):
         if self._h:
             lib().mcd_op_destroy(self._h)
             self._h = c_vp(0)
+            self._ws.close()
 
     def __del__(self):
         try:
@@ -332,23 +438,66 @@ class SolveInfo:
                          i.n_apply, i.krylov_dim, i.n_plus, i.n_minus, i.n_truncated)
 
 
+def operator_workspace_size(model, keys, storage="auto", grouped=None, mb=None) -> int:
+    """Bytes mcd_op_create takes for this model, basis and storage
+    (mcd_op_workspace_size; the nonzeros are counted in a probe workspace).
+    grouped: include room for the grouped one-vector layout (None: when that
+    room, an upper bound, is under half the free device memory)."""
+    mb = _ModelBuf(model) if mb is None else mb
+    n = int(keys.numel())
+    b, bg = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    code = lib().mcd_op_workspace_size(ctypes.byref(mb.s), c_vp(keys.data_ptr()), n,
+                                       STORAGE[storage], None, _stream(), ctypes.byref(b),
+                                       ctypes.byref(bg))
+    if code == MCD_E_WORKSPACE:   # the CSR count needs a probe workspace of b bytes
+        probe = Workspace(b.value, device=keys.device)
+        try:
+            code = lib().mcd_op_workspace_size(ctypes.byref(mb.s), c_vp(keys.data_ptr()), n,
+                                               STORAGE[storage], probe.handle, _stream(),
+                                               ctypes.byref(b), ctypes.byref(bg))
+        finally:
+            probe.close()
+    _check(code, "mcd_op_workspace_size")
+    if grouped is None:
+        free, _ = _torch().cuda.mem_get_info(keys.device)
+        grouped = bg.value < 0.5 * free
+    return bg.value if grouped else b.value
+
+
+def _lanczos_cfg(max_iter, check_every, tol, seed, store_vectors, min_iter, precision):
+    return McdLanczosCfg(int(max_iter), int(check_every), float(tol), int(seed),
+                         1 if store_vectors else 0, int(min_iter), DTYPE[precision])
+
+
 def lanczos_ground(op: Operator, max_iter=300, tol=1e-12, seed=0, check_every=10,
-                   store_vectors=True, min_iter=1, phi0=None, want_psi=True):
-    """(E0, psi0 tensor or None, alpha, beta, SolveInfo) via mcd_lanczos_ground."""
+                   store_vectors=None, min_iter=1, phi0=None, want_psi=True, precision="f64"):
+    """(E0, psi0 tensor or None, alpha, beta, SolveInfo) via mcd_lanczos_ground.
+    precision "f32": float32 Krylov vectors, E0 refined by a float64 Rayleigh
+    quotient (info.residual = its float64 residual norm).  store_vectors None:
+    keep every Krylov vector when that store takes under half the free device
+    memory, else run the recurrence a second time for psi0."""
     torch = _torch()
-    cfg = McdLanczosCfg(int(max_iter), int(check_every), float(tol), int(seed),
-                        1 if store_vectors else 0, int(min_iter))
+    if store_vectors is None:
+        cfg = _lanczos_cfg(max_iter, check_every, tol, seed, True, min_iter, precision)
+        need = ctypes.c_size_t(0)
+        _check(lib().mcd_lanczos_workspace_size(op.handle, ctypes.byref(cfg), ctypes.byref(need)),
+               "mcd_lanczos_workspace_size")
+        free, _ = torch.cuda.mem_get_info(op.device)
+        store_vectors = need.value < 0.5 * free
+    cfg = _lanczos_cfg(max_iter, check_every, tol, seed, store_vectors, min_iter, precision)
     psi = torch.empty(op.n, dtype=torch.float64, device=op.device) if want_psi else None
     e0 = c_dbl(0)
     a = np.zeros(max_iter)
     b = np.zeros(max_iter)
     info = McdSolveInfo()
-    code = lib().mcd_lanczos_ground(op.handle, ctypes.byref(cfg),
-                                    c_vp(phi0.data_ptr()) if phi0 is not None else None,
-                                    ctypes.byref(e0), c_vp(psi.data_ptr()) if want_psi else None,
-                                    a.ctypes.data_as(P(c_dbl)), b.ctypes.data_as(P(c_dbl)),
-                                    ctypes.byref(info), _stream())
-    _check(code, "mcd_lanczos_ground")
+    need = ctypes.c_size_t(0)
+    _check(lib().mcd_lanczos_workspace_size(op.handle, ctypes.byref(cfg), ctypes.byref(need)),
+           "mcd_lanczos_workspace_size")
+    _with_scratch(lambda ws: lib().mcd_lanczos_ground(
+        op.handle, ctypes.byref(cfg), c_vp(phi0.data_ptr()) if phi0 is not None else None,
+        ctypes.byref(e0), c_vp(psi.data_ptr()) if want_psi else None,
+        a.ctypes.data_as(P(c_dbl)), b.ctypes.data_as(P(c_dbl)), ctypes.byref(info), ws,
+        _stream()), "mcd_lanczos_ground", min_bytes=need.value)
     si = SolveInfo.of(info)
     return e0.value, psi, a[: si.iters], b[: si.iters], si
 
@@ -360,16 +509,18 @@ def batch_lanczos_ground(ops, max_iter=400, tol=1e-12, seed=0, check_every=10, m
     Returns (e0 list, psi list or None, iterations list, SolveInfo)."""
     torch = _torch()
     K = len(ops)
-    cfg = McdLanczosCfg(int(max_iter), int(check_every), float(tol), int(seed), 1, int(min_iter))
+    cfg = _lanczos_cfg(max_iter, check_every, tol, seed, True, min_iter, "f64")
     hs = (c_vp * K)(*[op.handle for op in ops])
     psis = [torch.empty(op.n, dtype=torch.float64, device=op.device) for op in ops] if want_psi else None
     pp = (c_vp * K)(*[c_vp(p.data_ptr()) for p in psis]) if want_psi else None
     e0 = (c_dbl * K)()
     it = (c_i32 * K)()
     info = McdSolveInfo()
-    code = lib().mcd_batch_lanczos_ground(hs, K, ctypes.byref(cfg), e0, pp, it, ctypes.byref(info),
-                                          _stream())
-    _check(code, "mcd_batch_lanczos_ground")
+    ntot = sum(op.n for op in ops)
+    est = 8 * (ntot * (min(max_iter, max(op.n for op in ops)) + 3) + K * (2 * max_iter + 8)) + (4 << 20)
+    code = _with_scratch(lambda ws: lib().mcd_batch_lanczos_ground(
+        hs, K, ctypes.byref(cfg), e0, pp, it, ctypes.byref(info), ws, _stream()),
+        "mcd_batch_lanczos_ground", min_bytes=est)
     return list(e0), psis, list(it), SolveInfo.of(info)
 
 
@@ -381,16 +532,20 @@ def _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, per_column, eta
 
 class BandKeep:
     """The two sector runs of a forward band_lanczos_green(..., keep=True)
-    call (mcd_band_keep: Krylov blocks, T, operators on F~+-), held on the
-    device until close() for band_green_vjp(..., keep=...)."""
+    call (mcd_band_keep: Krylov blocks, T, operators on F~+-), held in their
+    own workspace until close() for band_green_vjp(..., keep=...)."""
 
-    def __init__(self, handle):
+    def __init__(self, handle, ws):
         self._h = handle
+        self._ws = ws
 
     def close(self):
         if self._h:
             lib().mcd_band_keep_destroy(self._h)
             self._h = None
+        if self._ws is not None:
+            self._ws.close()
+            self._ws = None
 
     def __del__(self):
         try:
@@ -399,38 +554,70 @@ class BandKeep:
             pass
 
 
-def band_lanczos_green(model, keys, psi0, e0, orbitals, spins, omega, max_blocks=50,
-                       precision="f64", w_t=1.0, dtol=1e-10, storage="auto", reorth=2,
-                       parts=False, per_column=False, eta=0.0, g_tol=0.0, keep=False):
-    """G [n_freq, n_sel, n_sel] complex128 via mcd_band_lanczos_green.
-
-    eta == 0: omega are Matsubara frequencies (z = i w); eta > 0: real
-    frequencies broadened by eta (z = w + i eta).  keep=True calls
-    mcd_band_lanczos_green_keep and appends a BandKeep to the returned tuple."""
+def _band_args(model, keys, psi0, e0, orbitals, spins, omega, cfg):
     mb = _ModelBuf(model)
     orb = np.ascontiguousarray(orbitals, dtype=np.int32)
     sp = np.ascontiguousarray(spins, dtype=np.int32)
     om = np.ascontiguousarray(omega, dtype=np.float64)
-    ns, nf = len(orb), len(om)
+    keepalive = (mb, orb, sp, om, cfg)
+    args = [ctypes.byref(mb.s), c_vp(keys.data_ptr()), int(keys.numel()), c_vp(psi0.data_ptr()),
+            float(e0), len(orb), orb.ctypes.data_as(P(c_i32)), sp.ctypes.data_as(P(c_i32)),
+            len(om), om.ctypes.data_as(P(c_dbl)), ctypes.byref(cfg)]
+    return args, keepalive, len(orb), len(om)
+
+
+def band_workspace_size(model, keys, psi0, e0, orbitals, spins, omega, keep=False, **kw) -> int:
+    """Bytes mcd_band_lanczos_green(_keep) takes with these arguments
+    (mcd_band_workspace_size; the preparation runs in the scratch workspace)."""
+    cfg = _band_cfg(kw.get("max_blocks", 50), kw.get("precision", "f64"), kw.get("w_t", 1.0),
+                    kw.get("dtol", 1e-10), kw.get("storage", "auto"), kw.get("reorth", 2),
+                    kw.get("per_column", False), kw.get("eta", 0.0), kw.get("g_tol", 0.0))
+    args, keepalive, _, _ = _band_args(model, keys, psi0, e0, orbitals, spins, omega, cfg)
+    out = ctypes.c_size_t(0)
+    _with_scratch(lambda ws: lib().mcd_band_workspace_size(*args, 1 if keep else 0, ws, _stream(),
+                                                           ctypes.byref(out)),
+                  "mcd_band_workspace_size")
+    return out.value
+
+
+def band_lanczos_green(model, keys, psi0, e0, orbitals, spins, omega, max_blocks=50,
+                       precision="f64", w_t=1.0, dtol=1e-10, storage="auto", reorth=2,
+                       parts=False, per_column=False, eta=0.0, g_tol=0.0, keep=False, ws=None):
+    """G [n_freq, n_sel, n_sel] complex128 via mcd_band_lanczos_green.
+
+    eta == 0: omega are Matsubara frequencies (z = i w); eta > 0: real
+    frequencies broadened by eta (z = w + i eta).  keep=True calls
+    mcd_band_lanczos_green_keep (in a workspace of its own, sized by
+    mcd_band_workspace_size) and appends a BandKeep to the returned tuple.
+    ws: a Workspace to use instead of the scratch one (no retry)."""
+    cfg = _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, per_column, eta, g_tol)
+    args, keepalive, ns, nf = _band_args(model, keys, psi0, e0, orbitals, spins, omega, cfg)
     G = np.zeros((nf, ns, ns), dtype=np.complex128)
     Gp = np.zeros_like(G)
     Gm = np.zeros_like(G)
-    cfg = _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, per_column, eta, g_tol)
     info = McdSolveInfo()
     dp = lambda a: a.view(np.float64).ctypes.data_as(P(c_dbl))
-    args = [ctypes.byref(mb.s), c_vp(keys.data_ptr()), int(keys.numel()), c_vp(psi0.data_ptr()),
-            float(e0), ns, orb.ctypes.data_as(P(c_i32)), sp.ctypes.data_as(P(c_i32)), nf,
-            om.ctypes.data_as(P(c_dbl)), ctypes.byref(cfg), dp(G), dp(Gp), dp(Gm),
-            ctypes.byref(info), _stream()]
+    outs = [dp(G), dp(Gp), dp(Gm), ctypes.byref(info)]
     kept = None
     if keep:
+        nbytes = band_workspace_size(model, keys, psi0, e0, orbitals, spins, omega, keep=True,
+                                     max_blocks=max_blocks, precision=precision, w_t=w_t,
+                                     dtol=dtol, storage=storage, reorth=reorth, eta=eta,
+                                     g_tol=g_tol)
+        kws = Workspace(nbytes, device=keys.device)
         h = c_vp()
-        code = lib().mcd_band_lanczos_green_keep(*args, ctypes.byref(h))
+        code = lib().mcd_band_lanczos_green_keep(*args, *outs, kws.handle, _stream(),
+                                                 ctypes.byref(h))
+        if code < 0:
+            kws.close()
         _check(code, "mcd_band_lanczos_green_keep")
-        kept = BandKeep(h.value)
+        kept = BandKeep(h.value, kws)
+    elif ws is not None:
+        _check(lib().mcd_band_lanczos_green(*args, *outs, ws.handle, _stream()),
+               "mcd_band_lanczos_green")
     else:
-        code = lib().mcd_band_lanczos_green(*args)
-        _check(code, "mcd_band_lanczos_green")
+        _with_scratch(lambda w: lib().mcd_band_lanczos_green(*args, *outs, w, _stream()),
+                      "mcd_band_lanczos_green")
     out = (G, Gp, Gm, SolveInfo.of(info)) if parts else (G, SolveInfo.of(info))
     return out + (kept,) if keep else out
 
@@ -441,39 +628,35 @@ def band_green_vjp(model, keys, psi0, e0, orbitals, spins, omega, G_bar, e0_bar=
     """(d_t [n_bonds], d_U [n_orb], d_eps [n_orb], SolveInfo) = Re sum conj(G_bar) dG/dtheta
     + e0_bar dE0/dtheta via mcd_band_green_vjp (same arguments as band_lanczos_green), or
     via mcd_band_green_vjp_keep on the runs of a BandKeep."""
-    mb = _ModelBuf(model)
-    orb = np.ascontiguousarray(orbitals, dtype=np.int32)
-    sp = np.ascontiguousarray(spins, dtype=np.int32)
-    om = np.ascontiguousarray(omega, dtype=np.float64)
-    ns, nf = len(orb), len(om)
-    gb = np.ascontiguousarray(np.asarray(G_bar, dtype=np.complex128).reshape(nf, ns, ns))
     cfg = _band_cfg(max_blocks, precision, 1.0, dtol, storage, reorth, False, eta, g_tol)
+    args, keepalive, ns, nf = _band_args(model, keys, psi0, e0, orbitals, spins, omega, cfg)
+    gb = np.ascontiguousarray(np.asarray(G_bar, dtype=np.complex128).reshape(nf, ns, ns))
     dt = np.zeros(len(model.bonds))
     dU = np.zeros(model.n_orb)
     de = np.zeros(model.n_orb)
     info = McdSolveInfo()
     dp = lambda a: a.ctypes.data_as(P(c_dbl))
-    args = [ctypes.byref(mb.s), c_vp(keys.data_ptr()), int(keys.numel()), c_vp(psi0.data_ptr()),
-            float(e0), ns, orb.ctypes.data_as(P(c_i32)), sp.ctypes.data_as(P(c_i32)), nf,
-            om.ctypes.data_as(P(c_dbl)), ctypes.byref(cfg),
-            gb.view(np.float64).ctypes.data_as(P(c_dbl)), float(e0_bar), float(cg_tol),
-            int(cg_max_iter), dp(dt), dp(dU), dp(de), ctypes.byref(info), _stream()]
+    rest = [gb.view(np.float64).ctypes.data_as(P(c_dbl)), float(e0_bar), float(cg_tol),
+            int(cg_max_iter), dp(dt), dp(dU), dp(de), ctypes.byref(info)]
     if keep is not None:
         if not keep._h:
             raise ValueError("the BandKeep is closed")
-        code = lib().mcd_band_green_vjp_keep(*args, c_vp(keep._h))
-        _check(code, "mcd_band_green_vjp_keep")
+        _with_scratch(lambda w: lib().mcd_band_green_vjp_keep(*args, *rest, w, _stream(),
+                                                             c_vp(keep._h)),
+                      "mcd_band_green_vjp_keep")
     else:
-        code = lib().mcd_band_green_vjp(*args)
-        _check(code, "mcd_band_green_vjp")
+        _with_scratch(lambda w: lib().mcd_band_green_vjp(*args, *rest, w, _stream()),
+                      "mcd_band_green_vjp")
     return dt, dU, de, SolveInfo.of(info)
 
 
-def batch_band_green(models, keys_list, psi_list, e0_list, orbitals, spins, omega, n_streams=4,
+def batch_band_green(models, keys_list, psi_list, e0_list, orbitals, spins, omega,
                      max_blocks=50, precision="f64", w_t=1.0, dtol=1e-10, storage="auto",
-                     reorth=2, eta=0.0, g_tol=0.0):
-    """[G_i] for many instances at once (mcd_batch_band_green); each G_i as
-    band_lanczos_green would return it.  Returns (list of G, SolveInfo)."""
+                     reorth=2, eta=0.0, g_tol=0.0, ws=None):
+    """[G_i] for many instances at once (mcd_batch_band_green): every run of
+    every instance in lockstep; each G_i as band_lanczos_green would return it.
+    Returns (list of G, SolveInfo).  ws: a Workspace to use instead of the
+    scratch one (no retry; instances then run in groups that fit it)."""
     K = len(models)
     bufs = [_ModelBuf(m) for m in models]
     orb = np.ascontiguousarray(orbitals, dtype=np.int32)
@@ -489,9 +672,13 @@ def batch_band_green(models, keys_list, psi_list, e0_list, orbitals, spins, omeg
     gp = (c_vp * K)(*[c_vp(G.ctypes.data) for G in Gs])
     cfg = _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, False, eta, g_tol)
     info = McdSolveInfo()
-    code = lib().mcd_batch_band_green(mp, kp, nn, pp, ee, K, ns, orb.ctypes.data_as(P(c_i32)),
-                                      sp.ctypes.data_as(P(c_i32)), nf,
-                                      om.ctypes.data_as(P(c_dbl)), ctypes.byref(cfg),
-                                      int(n_streams), gp, ctypes.byref(info), _stream())
-    _check(code, "mcd_batch_band_green")
+    call = lambda w: lib().mcd_batch_band_green(mp, kp, nn, pp, ee, K, ns,
+                                                orb.ctypes.data_as(P(c_i32)),
+                                                sp.ctypes.data_as(P(c_i32)), nf,
+                                                om.ctypes.data_as(P(c_dbl)), ctypes.byref(cfg),
+                                                gp, ctypes.byref(info), w, _stream())
+    if ws is not None:
+        _check(call(ws.handle), "mcd_batch_band_green")
+    else:
+        _with_scratch(call, "mcd_batch_band_green")
     return Gs, SolveInfo.of(info)

@@ -661,30 +661,116 @@ __global__ __launch_bounds__(64) void k_pchol(const double *__restrict__ M, int 
     if (t == 0) *rank_out = r;
 }
 
+// Frequency argument zeta of G: i w (Matsubara, eta <= 0) or w + i eta
+// (real frequency, Lorentzian width eta).  G+ is evaluated at z = E0 + zeta
+// and G- at z = E0 - zeta.
+static inline cplx freq_arg(const mcd_band_cfg *cfg, double w) {
+    return cfg->eta > 0.0 ? cplx(w, cfg->eta) : cplx(0.0, w);
+}
+
+static double wall_ms() {
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// ---------------------------------------------------------------------------
+// One band run: block Lanczos on one excited sector (F~+ or F~-) of one
+// instance.  Every buffer is a piece of the caller's workspace.  The device
+// form keeps the whole recurrence on the GPU (Gram matrices, coefficients,
+// pivoted-Cholesky QR); several runs advance in lockstep (run_lockstep), so
+// the particle and hole runs of one call, and the runs of many instances,
+// share every block step on one stream.
 template <typename T>
 struct BandRun {
-    const mcd_op *op;
-    int P;
-    int64_t n;
-    hipStream_t s;
-    T *Qs = nullptr;          // [nstore][n][P]
-    T *W = nullptr;           // [n][P]
-    T *W2 = nullptr;          // [n][P] scratch of the two-pass QR (device run)
-    Alloc al;                 // allocator of the device run's small buffers
-    T *colbuf = nullptr;      // [2][n] single-column staging (per-column mode)
+    const mcd_op *op = nullptr;   // operator on F~+- (owned: destroyed in release())
+    int P = 0;
+    int64_t n = 0;
+    hipStream_t s = nullptr;
+    int mb = 0;                   // max block steps
+    int nstore = 0;               // stored blocks: mb + 1, or a ring of 3
+    T *Qs = nullptr;              // [nstore][n][P]
+    T *W = nullptr;               // [n][P]
+    T *W2 = nullptr;              // [n][P] scratch of the two-pass QR (device form)
+    T *colbuf = nullptr;          // [2][n] single-column staging (per-column form)
     bool per_column = false;
-    double *part = nullptr;   // Gram partials
-    double *dC = nullptr;     // device coefficient matrices
-    double *dG = nullptr;     // reduced Gram matrices
-    int nstore = 0;
+    double *part = nullptr;       // Gram partials
     int64_t part_cap = 0;
-    int64_t coef_cap = 0;
+    double *dG = nullptr;         // reduced Gram matrices [(mb + 1) P P]
+    double *dC = nullptr;         // coefficients staged from the host [(mb + 1) P P]
+    double *dT = nullptr;         // [A: mb][B: mb + 1][R0][Xm][Bm][Bacc][C2: 2], P x P each
+    int *d_rank = nullptr;        // [mb + 2]
+    int64_t chunk_rows = 0;       // Gram row chunks (fixed per run)
+    int nch = 0;
+    Alloc al;
+    std::vector<void *> pieces;   // workspace pieces of the run (released together)
+    // lockstep state
+    bool active = false;
+    int m = 0;                    // block steps in T
+    std::vector<int> rank;        // host copy of d_rank
+    std::vector<double> hT;       // host copy of dT
+    BandResult br;
     // convergence of G: stop when G at the check points zcheck changes by
     // <= g_tol max|G| between two checks (8 block steps apart)
     std::vector<cplx> zcheck;
     double g_tol = 0.0;
     int p_sel = 1;
     std::vector<cplx> gprev;
+
+    BandRun() = default;
+    BandRun(const BandRun &) = delete;
+    BandRun &operator=(const BandRun &) = delete;
+    ~BandRun() { release(); }
+
+    int PP() const { return P * P; }
+    T *blk(int j) { return Qs + (int64_t)(nstore == 3 ? j % 3 : j) * n * P; }
+    double *dA(int j) { return dT + (size_t)j * PP(); }
+    double *dB(int j) { return dT + (size_t)(mb + j) * PP(); }
+    double *dR0() { return dT + (size_t)(2 * mb + 1) * PP(); }
+    double *dXm() { return dR0() + PP(); }
+    double *dBm() { return dXm() + PP(); }
+    double *dBacc() { return dBm() + PP(); }
+    double *dC2() { return dBacc() + PP(); }
+    size_t nT() const { return (size_t)(2 * mb + 7) * PP(); }
+
+    // the run's pieces back to the workspace, its operator destroyed
+    void release() {
+        if (op) mcd_op_destroy(const_cast<mcd_op *>(op));
+        op = nullptr;
+        for (auto it = pieces.rbegin(); it != pieces.rend(); ++it) (void)dfree(*it, al);
+        pieces.clear();
+        Qs = W = W2 = colbuf = nullptr;
+        part = dG = dC = dT = nullptr;
+        d_rank = nullptr;
+    }
+    hipError_t take(void **p, size_t bytes) {
+        const hipError_t e = dmalloc(p, bytes, al);
+        if (e == hipSuccess) pieces.push_back(*p);
+        return e;
+    }
+
+    // Gram row chunks of the run: a function of (n, P, T) only, so a run
+    // gives the same sums whichever runs share its launches.  Register-tiled
+    // kernel (P >= 8): >= 8 rows per thread slot and at most 1024 chunks; LDS
+    // kernel (P < 8): at least 256 rows per chunk, at most 2048 chunks.
+    void set_chunks() {
+        int64_t c;
+        if (P >= 8) {
+            const int64_t rpb = 256 / (P == 16 ? 4 : sizeof(T) == 8 ? 2 : 1);
+            c = std::max<int64_t>(1, std::min<int64_t>(n / (8 * rpb), 1024));
+            if (c > 8) c = (c + 7) / 8 * 8;
+        } else {
+            c = std::min<int64_t>(gridn(n, 256), 2048);
+        }
+        c = std::max<int64_t>(1, c);
+        chunk_rows = (n + c - 1) / c;
+        nch = (int)((n + chunk_rows - 1) / chunk_rows);
+    }
+    // Gram partial capacity for up to mb + 1 blocks at once
+    int64_t partials_needed() const {
+        const int64_t pad = P >= 8 ? ((int64_t)nch + 7) / 8 * 8 : nch;
+        return pad * (int64_t)(mb + 1) * PP();
+    }
 
     bool g_converged(const BandResult &b) {
         if (g_tol <= 0.0 || zcheck.empty() || b.m == 0) return false;
@@ -705,8 +791,6 @@ struct BandRun {
         return conv;
     }
 
-    T *blk(int j) { return Qs + (int64_t)(nstore == 3 ? j % 3 : j) * n * P; }
-
     int gram(const T *Q0, int nm, const T *X, std::vector<double> &out) {
         const int PP = P * P;
         MCD_TRY(gram_dev(Q0, nm, X));
@@ -720,28 +804,8 @@ struct BandRun {
     // Gram matrices Q_m^T X (m < nm) into dG on the device.
     int gram_dev(const T *Q0, int nm, const T *X) {
         const int PP = P * P;
-        int nch;
-        if (P >= 8) {
-            // register-tiled kernel: >= 8 rows per thread slot, ~1024
-            // workgroups, and chunks small enough that a chunk's X rows (read
-            // by all nm workgroups of the chunk on one XCD) stay within 2 MB of
-            // its L2; at most 65536 / nm chunks (the partials' capacity)
-            const int64_t rpb = 256 / (P == 16 ? 4 : sizeof(T) == 8 ? 2 : 1);
-            const int64_t fit = ((int64_t)n * P * (int64_t)sizeof(T) + (2 << 20) - 1) / (2 << 20);
-            const int64_t cap = std::max<int64_t>(1, 65536 / nm);
-            nch = (int)std::min<int64_t>(
-                cap, std::min<int64_t>(std::max<int64_t>(1, n / (8 * rpb)),
-                                       std::max<int64_t>(fit, std::max<int64_t>(1, 1024 / nm))));
-            if (nch > 8)   // the same number of chunks per XCD
-                nch = (int)std::min<int64_t>((nch + 7) / 8 * 8, cap / 8 * 8);
-        } else {
-            // ~2048 workgroups in total, at least 256 rows per chunk
-            nch = (int)std::min<int64_t>(gridn(n, 256), std::max<int64_t>(1, 2048 / nm));
-        }
-        nch = std::max(1, nch);
-        const int64_t chunk_rows = (n + nch - 1) / nch;
-        nch = (int)((n + chunk_rows - 1) / chunk_rows);
-        MCD_REQUIRE((int64_t)nm * nch * PP <= part_cap, MCD_E_CAPACITY, "gram scratch too small");
+        MCD_REQUIRE((int64_t)nm * (P >= 8 ? ((int64_t)nch + 7) / 8 * 8 : nch) * PP <= part_cap,
+                    MCD_E_CAPACITY, "gram scratch too small");
         dim3 grid(nch, nm);
 #define GR(PV)                                                                           \
     case PV:                                                                             \
@@ -794,35 +858,25 @@ struct BandRun {
         return MCD_OK;
     }
 
-    // W (-)= sum_m Q_m C_m with C given on the host ([nm][P][P]).
+    // W (-)= sum_m Q_m C_m with C given on the host ([nm][P][P]); the staging
+    // buffer dC holds every group at once, so no copy overwrites coefficients
+    // a queued product still reads.
     int block_apply(const T *Q0, int nm, const std::vector<double> &C, T *Wout, bool sub) {
         const int PP = P * P;
-        const int group = std::max(1, (48 * 1024) / (PP * 8));
-        for (int g0 = 0; g0 < nm; g0 += group) {
-            const int g = std::min(group, nm - g0);
-            MCD_HIP(hipMemcpyAsync(dC, C.data() + (size_t)g0 * PP, (size_t)g * PP * sizeof(double),
-                                   hipMemcpyHostToDevice, s));
-            const T *q = Q0 + (int64_t)g0 * n * P;
-#define BA(PV)                                                      \
-    case PV:                                                        \
-        launch_block_apply<T, PV>(n, g, q, dC, Wout, sub, s);       \
-        break;
-            switch (P) {
-                BA(1) BA(2) BA(4) BA(8) BA(16)
-            }
-#undef BA
-            MCD_HIP(hipGetLastError());
-            if (!sub && g0 + g < nm) {
-                set_error("assigning block product must use one block");
-                return MCD_E_INVALID;
-            }
-        }
+        MCD_REQUIRE((size_t)nm * PP <= (size_t)(mb + 1) * PP, MCD_E_CAPACITY,
+                    "coefficient staging too small");
+        MCD_REQUIRE(sub || nm <= std::max(1, (48 * 1024) / (PP * 8)), MCD_E_INVALID,
+                    "assigning block product must use one group");
+        MCD_HIP(hipMemcpyAsync(dC, C.data(), (size_t)nm * PP * sizeof(double),
+                               hipMemcpyHostToDevice, s));
+        MCD_TRY(block_apply_dev(Q0, nm, dC, Wout, sub));
+        MCD_HIP(hipStreamSynchronize(s));   // C (host) is read by the copy above
         return MCD_OK;
     }
 
     // Orthonormalise X (n x P) into dst: X = dst Bout; drops directions with
     // Gram eigenvalue <= thr2 (first pass) and repeats once for accuracy.
-    int qr(T *X, T *dst, double thr2, std::vector<double> &Bout, int *rank) {
+    int qr(T *X, T *dst, double thr2, std::vector<double> &Bout, int *rank_out) {
         const int PP = P * P;
         std::vector<double> Bacc(PP, 0.0);
         for (int i = 0; i < P; i++) Bacc[i * P + i] = 1.0;
@@ -830,6 +884,9 @@ struct BandRun {
         for (int pass = 0; pass < 2; pass++) {
             std::vector<double> M, w, V;
             MCD_TRY(gram(src, 1, src, M));
+            for (double v : M)
+                MCD_REQUIRE(std::isfinite(v), MCD_E_NUMERIC,
+                            "band Lanczos: non-finite Gram matrix (NaN or Inf in psi0 or H)");
             jacobi_eig(P, M, w, V);
             std::vector<double> Xm(PP, 0.0), Bm(PP, 0.0);
             double wmax = 0.0;
@@ -845,7 +902,7 @@ struct BandRun {
                     Bm[i * P + a] = sq * V[a * P + i];   // row i of L^1/2 U^T
                 }
             }
-            *rank = rk;
+            *rank_out = rk;
             // dst = src Xm  (when src == dst go through W)
             T *out = (src == dst) ? W : dst;
             MCD_TRY(block_apply(src, 1, Xm, out, false));
@@ -868,163 +925,118 @@ struct BandRun {
         return MCD_OK;
     }
 
-
-    // Block Lanczos with every small dense step on the device: Gram matrices,
-    // A_j = sym(Q_j^T W), the recurrence and reorthogonalisation read their
-    // coefficients from HBM, and the QR of each new block is a pivoted
-    // Cholesky (applied twice) in one wavefront.  T = (A_j, B_j) and R0 come
-    // back to the host once at the end; the ranks are read every 8 steps to
-    // stop after the Krylov space is exhausted (blocks past that point are
-    // zero and are not kept).
-    int run_dev(T *phi, int max_blocks, double dtol_abs, int reorth, BandResult &br) {
-        const int PP = P * P;
-        br.P = P;
-        br.A.clear();
-        br.B.assign(1, std::vector<double>());
-        double *dT = nullptr;
-        int *d_rank = nullptr;
-        // [A: max_blocks][B: max_blocks + 1][R0][Xm][Bm][Bacc][C2: 2]
-        const size_t nT = (size_t)(2 * max_blocks + 7) * PP;
-        MCD_HIP(dmalloc((void **)&dT, nT * sizeof(double), al));
-        MCD_HIP(dmalloc((void **)&d_rank, (size_t)(max_blocks + 2) * sizeof(int), al));
-        double *dA = dT, *dB = dA + (size_t)max_blocks * PP, *dR0 = dB + (size_t)(max_blocks + 1) * PP;
-        double *dXm = dR0 + PP, *dBm = dXm + PP, *dBacc = dBm + PP, *dC2 = dBacc + PP;
-        auto fail = [&](int rc) {
-            (void)dfree(dT, al);
-            (void)dfree(d_rank, al);
-            return rc;
-        };
-#define DTRY(expr)           \
-    do {                     \
-        int rc_ = (expr);    \
-        if (rc_ < 0) return fail(rc_); \
-    } while (0)
-        // src -> W2 (first pass) -> dst (second pass); src and dst are never W2
-        auto qr_dev = [&](T *src, T *dst, double *outB, int slot) -> int {
-            T *cur = src;
-            for (int pass = 0; pass < 2; pass++) {
-                MCD_TRY(gram_dev(cur, 1, cur));
+    // Device QR of src into dst (two pivoted-Cholesky passes through W2); the
+    // factor goes to outB, the rank to d_rank[slot].  src and dst are never W2.
+    int qr_dev(T *src, T *dst, double *outB, int slot, double dtol_abs) {
+        T *cur = src;
+        for (int pass = 0; pass < 2; pass++) {
+            MCD_TRY(gram_dev(cur, 1, cur));
 #define PCH(PV)                                                                         \
     case PV:                                                                            \
         hipLaunchKernelGGL((k_pchol<PV>), dim3(1), dim3(64), 0, s, dG, pass,             \
-                           dtol_abs * dtol_abs, dXm, dBm, dBacc, pass == 0 ? 1 : 0,       \
+                           dtol_abs * dtol_abs, dXm(), dBm(), dBacc(), pass == 0 ? 1 : 0, \
                            d_rank + slot);                                              \
         break;
-                switch (P) {
-                    PCH(1) PCH(2) PCH(4) PCH(8) PCH(16)
-                    default:
-                        set_error("block width %d is not a power of two <= 16", P);
-                        return MCD_E_INVALID;
-                }
+            switch (P) {
+                PCH(1) PCH(2) PCH(4) PCH(8) PCH(16)
+                default:
+                    set_error("block width %d is not a power of two <= 16", P);
+                    return MCD_E_INVALID;
+            }
 #undef PCH
-                T *out = pass == 0 ? W2 : dst;
-                MCD_TRY(block_apply_dev(cur, 1, dXm, out, false));
-                cur = out;
-            }
-            MCD_HIP(hipMemcpyAsync(outB, dBacc, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
-            return MCD_OK;
-        };
-        std::vector<int> rank(max_blocks + 2, -1);
-        auto read_ranks = [&](int upto) -> int {
-            MCD_HIP(hipMemcpyAsync(rank.data(), d_rank, (size_t)(upto + 1) * sizeof(int),
-                                   hipMemcpyDeviceToHost, s));
-            MCD_HIP(hipStreamSynchronize(s));
-            return MCD_OK;
-        };
-        // T of the first mm blocks (and R0) to the host
-        auto read_T = [&](int mm, BandResult &out) -> int {
-            std::vector<double> hT(nT);
-            MCD_HIP(hipMemcpyAsync(hT.data(), dT, nT * sizeof(double), hipMemcpyDeviceToHost, s));
-            MCD_HIP(hipStreamSynchronize(s));
-            out = BandResult();
-            out.P = P;
-            out.B.assign(1, std::vector<double>());
-            out.R0.assign(hT.begin() + (2 * max_blocks + 1) * PP,
-                          hT.begin() + (2 * max_blocks + 2) * PP);
-            out.krylov = rank[0] > 0 ? rank[0] : 0;
-            for (int j = 0; j < mm; j++) {
-                out.A.emplace_back(hT.begin() + (size_t)j * PP, hT.begin() + (size_t)(j + 1) * PP);
-                if (j > 0) {
-                    const size_t o = (size_t)(max_blocks + j) * PP;
-                    out.B.emplace_back(hT.begin() + o, hT.begin() + o + PP);
-                    out.krylov += std::max(rank[j], 0);
-                }
-            }
-            out.m = mm;
-            return MCD_OK;
-        };
-        DTRY(qr_dev(phi, blk(0), dR0, 0));
-        DTRY(read_ranks(0));
-        int m = 0;
-        if (rank[0] > 0) {
-            for (int j = 0; j < max_blocks; j++) {
-                DTRY(apply_any(op, sizeof(T) == 8 ? MCD_F64 : MCD_F32, P, blk(j), W, s));
-                DTRY(gram_dev(blk(j), 1, W));
-                // W -= Q_{j-1} B_j^T + Q_j A_j: one pass when the two blocks
-                // are adjacent in the store
-                hipLaunchKernelGGL(k_sym_pair, dim3(1), dim3(64), 0, s, P, dG,
-                                   dA + (size_t)j * PP, j > 0 ? dB + (size_t)j * PP : nullptr,
-                                   dC2);
-                if (j > 0 && blk(j) == blk(j - 1) + (int64_t)n * P) {
-                    DTRY(block_apply_dev(blk(j - 1), 2, dC2, W, true));
-                } else {
-                    DTRY(block_apply_dev(blk(j), 1, dC2 + PP, W, true));
-                    if (j > 0) DTRY(block_apply_dev(blk(j - 1), 1, dC2, W, true));
-                }
-                for (int pass = 0; pass < reorth; pass++) {
-                    DTRY(gram_dev(blk(0), j + 1, W));
-                    DTRY(block_apply_dev(blk(0), j + 1, dG, W, true));
-                }
-                m = j + 1;
-                if (j + 1 == max_blocks) break;
-                DTRY(qr_dev(W, blk(j + 1), dB + (size_t)(j + 1) * PP, j + 1));
-                if ((j + 1) % 8 == 0) {
-                    DTRY(read_ranks(j + 1));
-                    bool done = false;
-                    for (int z = 1; z <= j + 1; z++)
-                        if (rank[z] == 0) {
-                            m = z;
-                            done = true;
-                            break;
-                        }
-                    if (done) break;
-                    if (g_tol > 0.0) {   // G from the blocks so far, at the check points
-                        BandResult tmp;
-                        DTRY(read_T(m, tmp));
-                        if (g_converged(tmp)) break;
-                    }
-                }
-            }
-            DTRY(read_ranks(m));
-            for (int z = 1; z < m; z++)
-                if (rank[z] == 0) {
-                    m = z;
-                    break;
-                }
+            T *out = pass == 0 ? W2 : dst;
+            MCD_TRY(block_apply_dev(cur, 1, dXm(), out, false));
+            cur = out;
         }
-        DTRY(read_T(m, br));
-#undef DTRY
-        return fail(MCD_OK);
+        MCD_HIP(hipMemcpyAsync(outB, dBacc(), PP() * sizeof(double), hipMemcpyDeviceToDevice, s));
+        return MCD_OK;
     }
 
-    int run(T *phi, int max_blocks, double dtol_abs, int reorth, BandResult &br) {
+    // One block step j of the device form, up to W = the new residual block
+    // (product, A_j, three-term update, reorthogonalisation).
+    int step_dev(int j, int reorth) {
+        MCD_TRY(apply_any(op, sizeof(T) == 8 ? MCD_F64 : MCD_F32, P, blk(j), W, s));
+        MCD_TRY(gram_dev(blk(j), 1, W));
+        // W -= Q_{j-1} B_j^T + Q_j A_j: one pass when the two blocks are
+        // adjacent in the store
+        hipLaunchKernelGGL(k_sym_pair, dim3(1), dim3(64), 0, s, P, dG, dA(j),
+                           j > 0 ? dB(j) : nullptr, dC2());
+        MCD_HIP(hipGetLastError());
+        if (j > 0 && blk(j) == blk(j - 1) + (int64_t)n * P) {
+            MCD_TRY(block_apply_dev(blk(j - 1), 2, dC2(), W, true));
+        } else {
+            MCD_TRY(block_apply_dev(blk(j), 1, dC2() + PP(), W, true));
+            if (j > 0) MCD_TRY(block_apply_dev(blk(j - 1), 1, dC2(), W, true));
+        }
+        for (int pass = 0; pass < reorth; pass++) {
+            MCD_TRY(gram_dev(blk(0), j + 1, W));
+            MCD_TRY(block_apply_dev(blk(0), j + 1, dG, W, true));
+        }
+        return MCD_OK;
+    }
+
+    // Host copies of the ranks [0, upto] and of T (enqueued; the caller
+    // synchronises the stream before reading them).
+    int fetch_ranks(int upto) {
+        rank.resize(mb + 2);
+        MCD_HIP(hipMemcpyAsync(rank.data(), d_rank, (size_t)(upto + 1) * sizeof(int),
+                               hipMemcpyDeviceToHost, s));
+        return MCD_OK;
+    }
+    int fetch_T() {
+        hT.resize(nT());
+        MCD_HIP(hipMemcpyAsync(hT.data(), dT, nT() * sizeof(double), hipMemcpyDeviceToHost, s));
+        return MCD_OK;
+    }
+    // T of the first mm blocks (and R0) from the host copy; MCD_E_NUMERIC if
+    // an entry in use is not finite
+    int make_T(int mm, BandResult &out) const {
         const int PP = P * P;
-        br.P = P;
-        br.A.clear();
-        br.B.assign(1, std::vector<double>());
+        out = BandResult();
+        out.P = P;
+        out.B.assign(1, std::vector<double>());
+        out.R0.assign(hT.begin() + (size_t)(2 * mb + 1) * PP, hT.begin() + (size_t)(2 * mb + 2) * PP);
+        out.krylov = rank[0] > 0 ? rank[0] : 0;
+        for (int j = 0; j < mm; j++) {
+            out.A.emplace_back(hT.begin() + (size_t)j * PP, hT.begin() + (size_t)(j + 1) * PP);
+            if (j > 0) {
+                const size_t o = (size_t)(mb + j) * PP;
+                out.B.emplace_back(hT.begin() + o, hT.begin() + o + PP);
+                out.krylov += std::max(rank[j], 0);
+            }
+        }
+        out.m = mm;
+        auto finite = [](const std::vector<double> &v) {
+            for (double x : v)
+                if (!std::isfinite(x)) return false;
+            return true;
+        };
+        bool ok = finite(out.R0);
+        for (int j = 0; j < mm && ok; j++) ok = finite(out.A[j]) && (j == 0 || finite(out.B[j]));
+        MCD_REQUIRE(ok, MCD_E_NUMERIC,
+                    "band Lanczos: non-finite block tridiagonal entry (NaN or Inf in psi0 or H)");
+        return MCD_OK;
+    }
+
+    // Host-driven form with one single-vector product per block column (the
+    // unbatched reference): Gram matrices on the host, Gram-eigen QR.
+    int run(double dtol_abs, int reorth, BandResult &out) {
+        const int PP = P * P;
+        out = BandResult();
+        out.P = P;
+        out.B.assign(1, std::vector<double>());
         int rk = 0;
         std::vector<double> R0;
-        MCD_TRY(qr(phi, blk(0), dtol_abs * dtol_abs, R0, &rk));
-        br.R0 = R0;
-        br.krylov = rk;
+        MCD_TRY(qr(W, blk(0), dtol_abs * dtol_abs, R0, &rk));
+        out.R0 = R0;
+        out.krylov = rk;
         if (rk == 0) {
-            br.m = 0;
+            out.m = 0;
             return MCD_OK;
         }
         std::vector<double> G, C;
-        for (int j = 0; j < max_blocks; j++) {
+        for (int j = 0; j < mb; j++) {
             if (per_column) {
-                // unbatched reference: one single-vector product per column
                 for (int k = 0; k < P; k++) {
                     hipLaunchKernelGGL((k_column<T>), dim3(gridn(n, 256)), dim3(256), 0, s, n, P,
                                        k, blk(j), colbuf, 0);
@@ -1041,141 +1053,161 @@ struct BandRun {
             std::vector<double> Aj(PP);
             for (int a = 0; a < P; a++)        // symmetrise the projected block
                 for (int b = 0; b < P; b++) Aj[a * P + b] = 0.5 * (G[a * P + b] + G[b * P + a]);
-            br.A.push_back(Aj);
+            out.A.push_back(Aj);
             // W -= Q_j A_j + Q_{j-1} B_j^T
             MCD_TRY(block_apply(blk(j), 1, Aj, W, true));
             if (j > 0) {
                 std::vector<double> Bt(PP);
                 for (int a = 0; a < P; a++)
-                    for (int b = 0; b < P; b++) Bt[a * P + b] = br.B[j][b * P + a];
+                    for (int b = 0; b < P; b++) Bt[a * P + b] = out.B[j][b * P + a];
                 MCD_TRY(block_apply(blk(j - 1), 1, Bt, W, true));
             }
-            if (reorth > 0) {
-                for (int pass = 0; pass < reorth; pass++) {
-                    MCD_TRY(gram(blk(0), j + 1, W, C));
-                    MCD_TRY(block_apply(blk(0), j + 1, C, W, true));
-                }
+            for (int pass = 0; pass < reorth; pass++) {
+                MCD_TRY(gram(blk(0), j + 1, W, C));
+                MCD_TRY(block_apply(blk(0), j + 1, C, W, true));
             }
-            if (j + 1 == max_blocks) break;
+            if (j + 1 == mb) break;
             std::vector<double> Bn;
             MCD_TRY(qr(W, blk(j + 1), dtol_abs * dtol_abs, Bn, &rk));
-            br.B.push_back(Bn);
+            out.B.push_back(Bn);
             if (rk == 0) break;
-            br.krylov += rk;
+            out.krylov += rk;
             if ((j + 1) % 8 == 0 && g_tol > 0.0) {
-                br.m = (int)br.A.size();
-                if (g_converged(br)) break;
+                out.m = (int)out.A.size();
+                if (g_converged(out)) break;
             }
         }
-        br.m = (int)br.A.size();
+        out.m = (int)out.A.size();
         return MCD_OK;
     }
 };
 
-// Frequency argument zeta of G: i w (Matsubara, eta <= 0) or w + i eta
-// (real frequency, Lorentzian width eta).  G+ is evaluated at z = E0 + zeta
-// and G- at z = E0 - zeta.
-static inline cplx freq_arg(const mcd_band_cfg *cfg, double w) {
-    return cfg->eta > 0.0 ? cplx(w, cfg->eta) : cplx(0.0, w);
+// Block Lanczos of every run in `runs` (device form) in lockstep: at block
+// step j every active run does its product, A_j, update,
+// reorthogonalisation and QR, each kernel enqueued for all runs before the
+// next, on one stream.  Every 8 steps the ranks (and, with g_tol, G at the
+// check points) are read back with one synchronisation for all runs; a run
+// whose Krylov space is exhausted or whose G has settled stops there.  Each
+// run's arithmetic depends on that run alone, so its result is the same in
+// any company.  Each run's start block is in its W.
+template <typename T>
+static int run_lockstep(std::vector<BandRun<T> *> &runs, double dtol_abs, int reorth,
+                        hipStream_t s) {
+    int mb = 0;
+    for (auto *r : runs) {
+        r->m = 0;
+        r->active = r->n > 0;
+        r->gprev.clear();
+        if (r->active) {
+            MCD_TRY(r->qr_dev(r->W, r->blk(0), r->dR0(), 0, dtol_abs));
+            MCD_TRY(r->fetch_ranks(0));
+        }
+        mb = std::max(mb, r->mb);
+    }
+    MCD_HIP(hipStreamSynchronize(s));
+    for (auto *r : runs)
+        if (r->active && r->rank[0] <= 0) r->active = false;
+    std::vector<BandRun<T> *> act;
+    for (int j = 0; j < mb; j++) {
+        act.clear();
+        for (auto *r : runs)
+            if (r->active) act.push_back(r);
+        if (act.empty()) break;
+        for (auto *r : act) MCD_TRY(r->step_dev(j, reorth));
+        for (auto *r : act) r->m = j + 1;
+        if (j + 1 == mb) break;
+        for (auto *r : act) MCD_TRY(r->qr_dev(r->W, r->blk(j + 1), r->dB(j + 1), j + 1, dtol_abs));
+        if ((j + 1) % 8 == 0) {
+            bool gt = false;
+            for (auto *r : act) {
+                MCD_TRY(r->fetch_ranks(j + 1));
+                if (r->g_tol > 0.0) {
+                    MCD_TRY(r->fetch_T());
+                    gt = true;
+                }
+            }
+            MCD_HIP(hipStreamSynchronize(s));
+            for (auto *r : act)
+                for (int z = 1; z <= j + 1; z++)
+                    if (r->rank[z] == 0) {   // exhausted: blocks from z on are zero
+                        r->m = z;
+                        r->active = false;
+                        break;
+                    }
+            if (gt) {
+                std::vector<BandRun<T> *> chk;
+                for (auto *r : act)
+                    if (r->active && r->g_tol > 0.0) chk.push_back(r);
+                std::vector<int> rcs(chk.size(), MCD_OK), stop(chk.size(), 0);
+                parallel_for((int)chk.size(), [&](int i) {
+                    BandResult tmp;
+                    rcs[i] = chk[i]->make_T(chk[i]->m, tmp);
+                    if (rcs[i] == MCD_OK && chk[i]->g_converged(tmp)) stop[i] = 1;
+                });
+                for (size_t i = 0; i < chk.size(); i++) {
+                    MCD_TRY(rcs[i]);
+                    if (stop[i]) chk[i]->active = false;
+                }
+            }
+        }
+    }
+    // final ranks and T of every run
+    for (auto *r : runs)
+        if (r->n > 0) {
+            MCD_TRY(r->fetch_ranks(std::max(r->m - 1, 0)));
+            MCD_TRY(r->fetch_T());
+        }
+    MCD_HIP(hipStreamSynchronize(s));
+    for (auto *r : runs) {
+        r->active = false;
+        if (r->n == 0) {
+            r->br = BandResult();
+            r->br.P = r->P;
+            continue;
+        }
+        if (r->rank[0] <= 0) r->m = 0;
+        for (int z = 1; z < r->m; z++)
+            if (r->rank[z] == 0) {
+                r->m = z;
+                break;
+            }
+        MCD_TRY(r->make_T(r->m, r->br));
+    }
+    return MCD_OK;
 }
 
-static double wall_ms() {
-    return std::chrono::duration<double, std::milli>(
-               std::chrono::steady_clock::now().time_since_epoch())
-        .count();
-}
-
-// Called after a sector run with the run (stored Krylov blocks), the
-// operator on F~+- and the recurrence; returns an MCD status.
+// F~+- of the kept states for the selection (images c+_mu x or c_mu x,
+// radix sort, unique; Eq. excited_subspace) and the operator on it.  The
+// image buffers are scratch; the operator's pieces stay in the workspace
+// (run.op, released with the run).  n_x = 0: the sector is empty.
 template <typename T>
-using SectorHook = std::function<int(BandRun<T> &, mcd_op *, const BandResult &)>;
-
-// A sector run kept after the forward call for the adjoint: the Krylov store
-// and scratch blocks, the operator on F~+- and the recurrence, with the arena
-// all their device buffers live in.
-template <typename T>
-struct SectorKeep {
-    std::unique_ptr<Arena> arena;
-    BandRun<T> run;
-    mcd_op *op = nullptr;
-    BandResult br;
-    int64_t n_x = 0;
-    SectorKeep() = default;
-    SectorKeep(const SectorKeep &) = delete;
-    SectorKeep &operator=(const SectorKeep &) = delete;
-    ~SectorKeep() { clear(); }
-    void clear() {
-        if (op) mcd_op_destroy(op);   // its buffers are the arena's
-        op = nullptr;
-        if (arena) arena->release();
-        arena.reset();
-    }
-    // the stream later work on the kept buffers runs on (the forward's hole
-    // run stream no longer exists)
-    void set_stream(hipStream_t st) {
-        run.s = st;
-        run.al.s = st;
-        if (op) op->alloc.s = st;
-        if (arena) arena->s = st;
-    }
-};
-
-template <typename T>
-struct BandKeep {
-    SectorKeep<T> plus, minus;
-};
-
-// One excited sector run (create = particle / G+, else hole / G-).  With
-// store_all every Krylov block is kept (also without reorthogonalisation)
-// and `hook` runs before the sector's buffers are released.
-template <typename T>
-static int excited_run(const mcd_model *model, const uint64_t *keys_t, const double *psi_t,
-                       int64_t nt, const SelOps &sel, bool create, const mcd_band_cfg *cfg,
-                       double dtol_scale, int P, BandResult &br, int64_t *n_x, hipStream_t s,
-                       bool store_all = false, const SectorHook<T> *hook = nullptr,
-                       const std::vector<cplx> *zcheck = nullptr,
-                       SectorKeep<T> *keep = nullptr) {
-    const Alloc A{s, true};   // stream-ordered buffers (no device-wide sync on free)
-    // the operator and the run's buffers: one arena, released at the end (or
-    // handed to keep)
-    std::unique_ptr<Arena> arena_own(new Arena(s));
-    Arena &arena = *arena_own;
-    const Alloc AR{s, true, &arena};
+static int prepare_sector(const mcd_model *model, const uint64_t *keys_t, int64_t nt,
+                          const SelOps &sel, bool create, const mcd_band_cfg *cfg, mcd_ws *ws,
+                          hipStream_t s, BandRun<T> &run) {
+    const Alloc A{ws};
     uint64_t *img = nullptr, *srt = nullptr, *uniq = nullptr;
     int64_t *d_nu = nullptr;
     void *tmp = nullptr;
-    mcd_op *op = nullptr;
-    BandRun<T> run;
     auto free_images = [&]() {
-        for (void *p : {(void *)img, (void *)srt, (void *)uniq, (void *)d_nu, tmp})
+        (void)hipStreamSynchronize(s);
+        for (void *p : {tmp, (void *)d_nu, (void *)uniq, (void *)srt, (void *)img})
             if (p) (void)dfree(p, A);
         img = srt = uniq = nullptr;
         d_nu = nullptr;
         tmp = nullptr;
-    };
-    auto cleanup = [&]() {
-        free_images();
-        if (op) mcd_op_destroy(op);
-        op = nullptr;
-        arena.release();
     };
 #define CK(expr)                                                              \
     do {                                                                      \
         hipError_t e_ = (expr);                                               \
         if (e_ != hipSuccess) {                                               \
             set_error("%s failed: %s", #expr, hipGetErrorString(e_));         \
-            cleanup();                                                        \
-            return MCD_E_HIP;                                                 \
+            free_images();                                                    \
+            return hip_status(e_);                                            \
         }                                                                     \
     } while (0)
-#define TRY(expr)          \
-    do {                   \
-        int rc_ = (expr);  \
-        if (rc_ < 0) {     \
-            cleanup();     \
-            return rc_;    \
-        }                  \
-    } while (0)
+    run.al.ws = ws;
+    run.s = s;
+    run.n = 0;
     const int64_t ni = nt * sel.n;
     CK(dmalloc((void **)&img, std::max<int64_t>(ni, 1) * sizeof(uint64_t), A));
     CK(dmalloc((void **)&srt, std::max<int64_t>(ni, 1) * sizeof(uint64_t), A));
@@ -1200,91 +1232,102 @@ static int excited_run(const mcd_model *model, const uint64_t *keys_t, const dou
         CK(hipStreamSynchronize(s));
         if (lastk == kEmpty) nu--;
     }
-    *n_x = nu;
-    if (nu == 0) {
-        br = BandResult();
-        br.P = P;
-        cleanup();
-        if (keep) {
-            keep->clear();
-            keep->br = br;
-            keep->n_x = 0;
-        }
-        return MCD_OK;
-    }
-    TRY(op_create(model, uniq, nu, cfg->storage, 0, cfg->per_column != 0, s, &op, true, &arena));
-    free_images();   // the operator holds its own copy of the keys
-    // Storage for the Krylov blocks.
-    const int reorth = std::max(0, std::min(2, (int)cfg->reorth));
-    run.op = op;
-    run.P = P;
-    run.n = nu;
-    run.s = s;
-    run.al = AR;
-    run.nstore = (reorth > 0 || store_all) ? cfg->max_blocks + 1 : 3;
-    size_t fr = 0, tot = 0;
-    CK(hipMemGetInfo(&fr, &tot));
-    const double need = (double)run.nstore * nu * P * sizeof(T);
-    if (need > 0.8 * (double)fr) {
-        cleanup();
-        set_error("Krylov store needs %.1f GB, %.1f GB free (lower max_blocks or reorth=0)",
-                  need / 1e9, fr / 1e9);
-        return MCD_E_CAPACITY;
-    }
-    CK(dmalloc((void **)&run.Qs, (size_t)run.nstore * nu * P * sizeof(T), AR));
-    CK(dmalloc((void **)&run.W, (size_t)nu * P * sizeof(T), AR));
-    if (!(cfg->per_column != 0)) CK(dmalloc((void **)&run.W2, (size_t)nu * P * sizeof(T), AR));
-    run.per_column = cfg->per_column != 0;
-    run.g_tol = cfg->g_tol;
-    run.p_sel = sel.n;
-    if (zcheck) run.zcheck = *zcheck;
-    if (run.per_column) CK(dmalloc((void **)&run.colbuf, (size_t)2 * nu * sizeof(T), AR));
-    run.part_cap = (int64_t)65536 * P * P + (int64_t)(cfg->max_blocks + 1) * P * P;
-    CK(dmalloc((void **)&run.part, run.part_cap * sizeof(double), AR));
-    run.coef_cap = (int64_t)(cfg->max_blocks + 1) * P * P;
-    CK(dmalloc((void **)&run.dC, run.coef_cap * sizeof(double), AR));
-    CK(dmalloc((void **)&run.dG, run.coef_cap * sizeof(double), AR));
-    // start block (into W, then orthonormalised into Q_0)
-    CK(hipMemsetAsync(run.W, 0, (size_t)nu * P * sizeof(T), s));
-    hipLaunchKernelGGL((k_start_block<T>), dim3(gridn(nt, 256)), dim3(256), 0, s, nt, keys_t,
-                       psi_t, sel, create ? 1 : 0, op->d_hash, op->hash_mask, P, run.W);
-    CK(hipGetLastError());
-    // the start block lives in W; qr() reads W and writes Q_0 (W is reused as
-    // scratch only when source and destination coincide, not here)
-    T *phi = nullptr;
-    CK(dmalloc((void **)&phi, (size_t)nu * P * sizeof(T), AR));
-    CK(hipMemcpyAsync(phi, run.W, (size_t)nu * P * sizeof(T), hipMemcpyDeviceToDevice, s));
-    const double dtol_abs = cfg->dtol * dtol_scale;
-    int rc = run.per_column ? run.run(phi, cfg->max_blocks, dtol_abs, reorth, br)
-                            : run.run_dev(phi, cfg->max_blocks, dtol_abs, reorth, br);
-    (void)dfree(phi, AR);
-    if (rc < 0) {
-        cleanup();
-        return rc;
-    }
-    CK(hipStreamSynchronize(s));
-    if (hook && br.m > 0) {
-        rc = (*hook)(run, op, br);
+#undef CK
+    if (nu > 0) {
+        mcd_op *op = nullptr;
+        const int rc = op_create(model, uniq, nu, cfg->storage, 0, cfg->per_column != 0, ws, s, &op);
         if (rc < 0) {
-            cleanup();
+            free_images();
             return rc;
         }
-        CK(hipStreamSynchronize(s));
+        run.op = op;
+        run.n = nu;
     }
-    if (keep) {   // hand the run, operator and arena over (all work has completed)
-        keep->clear();
-        keep->arena = std::move(arena_own);
-        keep->run = std::move(run);
-        keep->op = op;
-        keep->br = br;
-        keep->n_x = nu;
-        keep->set_stream(nullptr);
-        return MCD_OK;
-    }
-    cleanup();
-#undef CK
-#undef TRY
+    free_images();   // the operator holds its own copy of the keys
     return MCD_OK;
+}
+
+// Pieces of a prepared run (n > 0): Krylov store, work blocks, Gram
+// partials, coefficient store.  `plan` replays the takes on host bookkeeping
+// instead (for the workspace-size answer).
+template <typename T>
+static size_t run_piece_sizes(const BandRun<T> &r, size_t out[9]) {
+    const size_t PPb = (size_t)r.P * r.P * sizeof(double);
+    out[0] = (size_t)r.nstore * r.n * r.P * sizeof(T);                   // Qs
+    out[1] = (size_t)r.n * r.P * sizeof(T);                              // W
+    out[2] = r.per_column ? 0 : (size_t)r.n * r.P * sizeof(T);           // W2
+    out[3] = r.per_column ? (size_t)2 * r.n * sizeof(T) : 0;             // colbuf
+    out[4] = (size_t)r.part_cap * sizeof(double);                        // part
+    out[5] = (size_t)(r.mb + 1) * PPb;                                   // dG
+    out[6] = (size_t)(r.mb + 1) * PPb;                                   // dC
+    out[7] = r.nT() * sizeof(double);                                    // dT
+    out[8] = (size_t)(r.mb + 2) * sizeof(int);                           // d_rank
+    return 9;
+}
+
+template <typename T>
+static void run_configure(BandRun<T> &r, const mcd_band_cfg *cfg, int P, bool store_all,
+                          const SelOps &sel, const std::vector<cplx> *zcheck) {
+    const int reorth = std::max(0, std::min(2, (int)cfg->reorth));
+    r.P = P;
+    r.mb = cfg->max_blocks;
+    r.nstore = (reorth > 0 || store_all) ? cfg->max_blocks + 1 : 3;
+    r.per_column = cfg->per_column != 0;
+    r.g_tol = cfg->g_tol;
+    r.p_sel = sel.n;
+    if (zcheck) r.zcheck = *zcheck;
+    r.set_chunks();
+    r.part_cap = r.partials_needed();
+}
+
+template <typename T>
+static int run_allocate(BandRun<T> &r) {
+    size_t sz[9];
+    run_piece_sizes(r, sz);
+    void **dst[9] = {(void **)&r.Qs, (void **)&r.W, (void **)&r.W2, (void **)&r.colbuf,
+                     (void **)&r.part, (void **)&r.dG, (void **)&r.dC, (void **)&r.dT,
+                     (void **)&r.d_rank};
+    for (int i = 0; i < 9; i++) {
+        if (sz[i] == 0) continue;
+        const hipError_t e = r.take(dst[i], sz[i]);
+        if (e != hipSuccess) {
+            set_error("band run: workspace too small for its blocks (%.1f MB more)",
+                      sz[i] / 1048576.0);
+            return hip_status(e);
+        }
+    }
+    return MCD_OK;
+}
+
+// Start block c+_mu|psi> (c_mu|psi>) of the kept states scattered into W.
+template <typename T>
+static int run_start_block(BandRun<T> &r, const uint64_t *keys_t, const double *psi_t, int64_t nt,
+                           const SelOps &sel, bool create) {
+    MCD_HIP(hipMemsetAsync(r.W, 0, (size_t)r.n * r.P * sizeof(T), r.s));
+    hipLaunchKernelGGL((k_start_block<T>), dim3(gridn(nt, 256)), dim3(256), 0, r.s, nt, keys_t,
+                       psi_t, sel, create ? 1 : 0, r.op->d_hash, r.op->hash_mask, r.P, r.W);
+    MCD_HIP(hipGetLastError());
+    return MCD_OK;
+}
+
+// Workspace extent after taking the pieces of `runs` (n > 0, not yet
+// allocated), replayed on a copy of the workspace's bookkeeping.
+template <typename T>
+static size_t plan_runs(mcd_ws *ws, const std::vector<BandRun<T> *> &runs) {
+    WsAlloc sim(0);
+    {
+        std::lock_guard<std::mutex> lock(ws->mu);
+        sim = ws->a;
+    }
+    sim.grow_to(size_t(1) << 62);   // the same live pieces, an unbounded range
+    for (auto *r : runs) {
+        if (r->n == 0) continue;
+        size_t sz[9];
+        run_piece_sizes(*r, sz);
+        for (int i = 0; i < 9; i++)
+            if (sz[i]) (void)sim.alloc(sz[i]);
+    }
+    return sim.extent();
 }
 
 // Points where the convergence of G is checked: every frequency if there are
@@ -1312,53 +1355,53 @@ static void check_points(const mcd_band_cfg *cfg, int n_freq, const double *omeg
     }
 }
 
-template <typename T>
-static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
-                      const double *psi0_dev, double e0, const SelOps &sel, int n_freq,
-                      const double *omega, const mcd_band_cfg *cfg, double *G_out, double *Gp_out,
-                      double *Gm_out, mcd_solve_info *info, hipStream_t s,
-                      bool concurrent_sectors, BandKeep<T> *keep = nullptr) {
-    Arena arena(s);
-    const Alloc A{s, true, &arena};   // stream-ordered, released together
-    const double t0 = wall_ms();
-    {
-        int dev = 0;
-        if (hipGetDevice(&dev) == hipSuccess) pool_keep_freed(dev);
-    }
-    double *w = nullptr, *w2 = nullptr, *psi_t = nullptr, *scr = nullptr;
+// The w_t cut of one ground state (Sec. Further truncation): the kept keys
+// and the renormalised kept amplitudes (keys_t, psi_t: pieces of the
+// workspace, released by the caller).
+static int wt_cut(const uint64_t *keys_dev, int64_t n, const double *psi0_dev, double w_t,
+                  mcd_ws *ws, hipStream_t s, uint64_t **keys_t_out, double **psi_t_out,
+                  int64_t *n_keep_out) {
+    const Alloc A{ws};
+    double *w = nullptr, *w2 = nullptr, *scr = nullptr, *psi_t = nullptr;
     uint32_t *idx = nullptr, *idx2 = nullptr, *kept = nullptr;
     uint64_t *keys_t = nullptr;
-    unsigned int *cnt = nullptr;
     void *tmp = nullptr;
-    auto cleanup = [&]() {
-        for (void *p : {(void *)w, (void *)w2, (void *)psi_t, (void *)scr, (void *)idx,
-                        (void *)idx2, (void *)kept, (void *)keys_t, (void *)cnt, tmp})
+    *keys_t_out = nullptr;
+    *psi_t_out = nullptr;
+    auto scratch_free = [&]() {
+        (void)hipStreamSynchronize(s);
+        for (void *p : {tmp, (void *)scr, (void *)kept, (void *)idx2, (void *)idx, (void *)w2,
+                        (void *)w})
             if (p) (void)dfree(p, A);
+        tmp = scr = nullptr;
+        kept = idx2 = idx = nullptr;
+        w2 = w = nullptr;
     };
 #define CK(expr)                                                              \
     do {                                                                      \
         hipError_t e_ = (expr);                                               \
         if (e_ != hipSuccess) {                                               \
             set_error("%s failed: %s", #expr, hipGetErrorString(e_));         \
-            cleanup();                                                        \
-            return MCD_E_HIP;                                                 \
+            scratch_free();                                                   \
+            (void)dfree(psi_t, A);                                            \
+            (void)dfree(keys_t, A);                                           \
+            return hip_status(e_);                                            \
         }                                                                     \
     } while (0)
     MCD_REQUIRE(n < (int64_t(1) << 31), MCD_E_CAPACITY, "basis too large for the w_t sort");
-    CK(dmalloc((void **)&w, n * sizeof(double), A));
-    CK(dmalloc((void **)&w2, n * sizeof(double), A));
-    CK(dmalloc((void **)&idx, n * sizeof(uint32_t), A));
-    CK(dmalloc((void **)&idx2, n * sizeof(uint32_t), A));
-    CK(dmalloc((void **)&kept, n * sizeof(uint32_t), A));
+    // kept outputs first (they outlive the scratch)
     CK(dmalloc((void **)&keys_t, n * sizeof(uint64_t), A));
     CK(dmalloc((void **)&psi_t, n * sizeof(double), A));
+    CK(dmalloc((void **)&w, n * sizeof(double), A));
+    CK(dmalloc((void **)&idx, n * sizeof(uint32_t), A));
+    CK(dmalloc((void **)&kept, n * sizeof(uint32_t), A));
     CK(dmalloc((void **)&scr, (4096 + 8) * sizeof(double), A));
-    CK(dmalloc((void **)&cnt, 8 * sizeof(unsigned int), A));
-    CK(hipMemsetAsync(cnt, 0, 8 * sizeof(unsigned int), s));
     hipLaunchKernelGGL(k_weights, dim3(gridn(n, 256)), dim3(256), 0, s, n, psi0_dev, w, idx);
     CK(hipGetLastError());
     int64_t n_keep = n;
-    if (cfg->w_t < 1.0) {
+    if (w_t < 1.0) {
+        CK(dmalloc((void **)&w2, n * sizeof(double), A));
+        CK(dmalloc((void **)&idx2, n * sizeof(uint32_t), A));
         size_t b1 = 0;
         CK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, b1, w, w2, idx, idx2, (int)n, 0,
                                                         64, s));
@@ -1373,11 +1416,18 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
         CK(hipStreamSynchronize(s));
         double total = 0.0;
         for (int64_t i = 0; i < n; i++) total += hw[i];
+        if (!std::isfinite(total) || !(total > 0.0)) {
+            scratch_free();
+            (void)dfree(psi_t, A);
+            (void)dfree(keys_t, A);
+            set_error("w_t cut: psi0 has no finite, nonzero weight");
+            return MCD_E_NUMERIC;
+        }
         double cum = 0.0;
         n_keep = n;
         for (int64_t i = 0; i < n; i++) {
             cum += hw[i] / total;
-            if (cum >= cfg->w_t) {
+            if (cum >= w_t) {
                 n_keep = i + 1;
                 break;
             }
@@ -1395,98 +1445,238 @@ static int band_green(const mcd_model *model, const uint64_t *keys_dev, int64_t 
     hipLaunchKernelGGL(k_scale_by, dim3(gridn(n_keep, 256)), dim3(256), 0, s, n_keep, psi_t,
                        scr + 4096);
     CK(hipGetLastError());
+    double nrm2 = 0.0;
+    CK(hipMemcpyAsync(&nrm2, scr + 4096, sizeof(double), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
+#undef CK
+    scratch_free();
+    if (!std::isfinite(nrm2) || !(nrm2 > 0.0)) {
+        (void)dfree(psi_t, A);
+        (void)dfree(keys_t, A);
+        set_error("w_t cut: the kept ground state has norm^2 %g (NaN, Inf or zero in psi0)", nrm2);
+        return MCD_E_NUMERIC;
+    }
+    *keys_t_out = keys_t;
+    *psi_t_out = psi_t;
+    *n_keep_out = n_keep;
+    return MCD_OK;
+}
 
-    int P = 1;
-    while (P < sel.n) P <<= 1;
-    const int p = sel.n;
-    BandResult brp, brm;
-    int64_t np = 0, nm = 0;
-    std::vector<cplx> zp, zm;
-    check_points(cfg, n_freq, omega, e0, zp, zm);
-    // The particle (c+) and hole (c) runs are independent: with
-    // concurrent_sectors the hole run goes to a second stream from a second
-    // host thread (both read keys_t / psi_t, complete at the synchronisation
-    // above), so the two chains of small dependent kernels overlap on the
-    // GPU.  Each run is the same sequence of kernels either way, so the
-    // results do not depend on it.
-    int rc = MCD_OK, rc_m = MCD_OK;
-    std::string msg_m;
-    if (concurrent_sectors) {
-        int dev = 0;
-        CK(hipGetDevice(&dev));
-        std::thread hole([&]() {
-            hipStream_t s2 = nullptr;
-            if (hipSetDevice(dev) != hipSuccess ||
-                hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
-                rc_m = MCD_E_HIP;
-                msg_m = "stream set-up for the hole run failed";
-                return;
-            }
-            rc_m = excited_run<T>(model, keys_t, psi_t, n_keep, sel, false, cfg, 1.0, P, brm, &nm,
-                                  s2, keep != nullptr, nullptr, &zm,
-                                  keep ? &keep->minus : nullptr);
-            if (rc_m < 0) msg_m = mcd_last_error();
-            if (hipStreamSynchronize(s2) != hipSuccess && rc_m >= 0) {
-                rc_m = MCD_E_HIP;
-                msg_m = "hole run stream failed";
-            }
-            (void)hipStreamDestroy(s2);
-        });
-        rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, true, cfg, 1.0, P, brp, &np, s,
-                            keep != nullptr, nullptr, &zp, keep ? &keep->plus : nullptr);
-        hole.join();
-        if (rc >= 0 && rc_m < 0) {
-            set_error("%s", msg_m.c_str());
-            rc = rc_m;
-        }
-    } else {
-        rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, true, cfg, 1.0, P, brp, &np, s,
-                            keep != nullptr, nullptr, &zp, keep ? &keep->plus : nullptr);
-        if (rc >= 0)
-            rc = excited_run<T>(model, keys_t, psi_t, n_keep, sel, false, cfg, 1.0, P, brm, &nm, s,
-                                keep != nullptr, nullptr, &zm, keep ? &keep->minus : nullptr);
-    }
-    if (rc < 0) {
-        cleanup();
-        return rc;
-    }
-    // resolvents: frequencies are independent (one host thread each)
+// One instance of a (batched) Green-function call: its cut ground state and
+// its two sector runs.
+template <typename T>
+struct Instance {
+    const mcd_model *model = nullptr;
+    const uint64_t *keys = nullptr;
+    int64_t n = 0;
+    const double *psi = nullptr;
+    double e0 = 0.0;
+    double *G_out = nullptr, *Gp_out = nullptr, *Gm_out = nullptr;
+    uint64_t *keys_t = nullptr;   // kept states and amplitudes (workspace)
+    double *psi_t = nullptr;
+    int64_t n_keep = 0;
+    BandRun<T> plus, minus;
+};
+
+// G of one instance from its two runs (resolvents at every frequency, one
+// host thread per frequency).
+template <typename T>
+static void assemble_green(const Instance<T> &in, int p, int n_freq, const double *omega,
+                           const mcd_band_cfg *cfg) {
+    const BandResult &brp = in.plus.br, &brm = in.minus.br;
+    const double e0 = in.e0;
     parallel_for(n_freq, [&](int f) {
         std::vector<cplx> g(p * p);
-        cplx *Gf = (cplx *)G_out + (size_t)f * p * p;
+        cplx *Gf = (cplx *)in.G_out + (size_t)f * p * p;
         for (int e = 0; e < p * p; e++) Gf[e] = 0.0;
         if (brp.m > 0) {
             block_cf(brp, e0 + freq_arg(cfg, omega[f]), p, g.data());
             for (int e = 0; e < p * p; e++) {
                 Gf[e] += g[e];
-                if (Gp_out) ((cplx *)Gp_out)[(size_t)f * p * p + e] = g[e];
+                if (in.Gp_out) ((cplx *)in.Gp_out)[(size_t)f * p * p + e] = g[e];
             }
-        } else if (Gp_out) {
-            for (int e = 0; e < p * p; e++) ((cplx *)Gp_out)[(size_t)f * p * p + e] = 0.0;
+        } else if (in.Gp_out) {
+            for (int e = 0; e < p * p; e++) ((cplx *)in.Gp_out)[(size_t)f * p * p + e] = 0.0;
         }
         if (brm.m > 0) {
             block_cf(brm, e0 - freq_arg(cfg, omega[f]), p, g.data());
             for (int e = 0; e < p * p; e++) {
                 Gf[e] -= g[e];
-                if (Gm_out) ((cplx *)Gm_out)[(size_t)f * p * p + e] = -g[e];
+                if (in.Gm_out) ((cplx *)in.Gm_out)[(size_t)f * p * p + e] = -g[e];
             }
-        } else if (Gm_out) {
-            for (int e = 0; e < p * p; e++) ((cplx *)Gm_out)[(size_t)f * p * p + e] = 0.0;
+        } else if (in.Gm_out) {
+            for (int e = 0; e < p * p; e++) ((cplx *)in.Gm_out)[(size_t)f * p * p + e] = 0.0;
         }
     });
-    cleanup();
-#undef CK
+}
+
+
+// Green functions of instances [0, K): cut, F~+- and operators for a group
+// of instances at a time (as many as the workspace holds: their runs are
+// planned on the host before any block is taken), then all runs of the group
+// in lockstep.  plan_need != nullptr: prepare the first instance only and
+// report the bytes it needs (no block steps; MCD_E_WORKSPACE when even the
+// preparation did not fit, with the workspace's `need` as a lower bound).
+// keep_runs (one instance): its runs stay (operators, Krylov blocks, T) for
+// the caller to release.
+template <typename T>
+static int band_green_multi(std::vector<Instance<T> *> &inst, const SelOps &sel, int n_freq,
+                            const double *omega, const mcd_band_cfg *cfg, mcd_ws *ws,
+                            hipStream_t s, bool store_all, size_t *plan_need, bool keep_runs,
+                            mcd_solve_info *info) {
+    const double t0 = wall_ms();
+    const int K = (int)inst.size();
+    int P = 1;
+    while (P < sel.n) P <<= 1;
+    const int p = sel.n;
+    const int reorth = std::max(0, std::min(2, (int)cfg->reorth));
+    const double dtol_abs = cfg->dtol;
+    const Alloc A{ws};
+    auto drop_inst = [&](Instance<T> &in) {
+        (void)hipStreamSynchronize(s);
+        in.plus.release();
+        in.minus.release();
+        (void)dfree(in.psi_t, A);
+        (void)dfree(in.keys_t, A);
+        in.psi_t = nullptr;
+        in.keys_t = nullptr;
+    };
+    mcd_solve_info agg;
+    memset(&agg, 0, sizeof(agg));
+    size_t need_max = 0;
+    int k0 = 0;
+    while (k0 < K) {
+        // prepare instances k0, k0 + 1, ... while their runs fit
+        int k1 = k0;
+        std::vector<BandRun<T> *> group;
+        for (; k1 < K; k1++) {
+            Instance<T> &in = *inst[k1];
+            std::vector<cplx> zp, zm;
+            check_points(cfg, n_freq, omega, in.e0, zp, zm);
+            int rc = wt_cut(in.keys, in.n, in.psi, cfg->w_t, ws, s, &in.keys_t, &in.psi_t,
+                            &in.n_keep);
+            if (rc >= 0) rc = prepare_sector<T>(in.model, in.keys_t, in.n_keep, sel, true, cfg, ws, s, in.plus);
+            if (rc >= 0) rc = prepare_sector<T>(in.model, in.keys_t, in.n_keep, sel, false, cfg, ws, s, in.minus);
+            if (rc >= 0) {
+                run_configure(in.plus, cfg, P, store_all, sel, &zp);
+                run_configure(in.minus, cfg, P, store_all, sel, &zm);
+            }
+            size_t need = 0;
+            if (rc >= 0) {
+                std::vector<BandRun<T> *> g2 = group;
+                g2.push_back(&in.plus);
+                g2.push_back(&in.minus);
+                need = plan_runs<T>(ws, g2);
+            }
+            const bool fits = rc >= 0 && need <= ws->a.size();
+            if (rc >= 0 && fits) {
+                group.push_back(&in.plus);
+                group.push_back(&in.minus);
+                need_max = std::max(need_max, need);
+                if (plan_need) {   // the size answer: this instance, as the call would take it
+                    k1++;
+                    break;
+                }
+                continue;
+            }
+            // does not fit (or failed): undo this instance
+            const int rc_keep = rc;
+            drop_inst(in);
+            if (rc_keep < 0 && rc_keep != MCD_E_WORKSPACE) {
+                for (int k = k0; k < k1; k++) drop_inst(*inst[k]);
+                return rc_keep;
+            }
+            if (plan_need) {
+                if (rc_keep >= 0) {
+                    *plan_need = std::max(need_max, need);
+                    return MCD_OK;
+                }
+                size_t nd = 0;
+                {
+                    std::lock_guard<std::mutex> lock(ws->mu);
+                    nd = ws->a.need();
+                }
+                *plan_need = std::max(need_max, nd);
+                set_error("band workspace size: the probe workspace is too small for the "
+                          "preparation (grow it to %zu bytes)", *plan_need);
+                return MCD_E_WORKSPACE;
+            }
+            if (k1 == k0) {   // not even one instance fits
+                std::lock_guard<std::mutex> lock(ws->mu);
+                if (rc_keep >= 0) ws->a.set_need(need);
+                set_error("band Green function: the workspace (%zu bytes) holds no instance "
+                          "(instance %d needs %zu bytes)", ws->a.size(), k1,
+                          rc_keep >= 0 ? need : ws->a.need());
+                return MCD_E_WORKSPACE;
+            }
+            break;
+        }
+        if (plan_need) {
+            for (int k = k0; k < k1; k++) drop_inst(*inst[k]);
+            *plan_need = need_max;
+            return MCD_OK;
+        }
+        // blocks of the group's runs, start blocks; the cut states go back
+        int rc = MCD_OK;
+        for (int k = k0; k < k1 && rc >= 0; k++) {
+            Instance<T> &in = *inst[k];
+            for (int side = 0; side < 2 && rc >= 0; side++) {
+                BandRun<T> &r = side == 0 ? in.plus : in.minus;
+                if (r.n == 0) continue;
+                rc = run_allocate(r);
+                if (rc >= 0) rc = run_start_block(r, in.keys_t, in.psi_t, in.n_keep, sel, side == 0);
+            }
+        }
+        if (rc >= 0) rc = hipStreamSynchronize(s) == hipSuccess ? MCD_OK : MCD_E_HIP;
+        for (int k = k0; k < k1; k++) {
+            (void)dfree(inst[k]->psi_t, A);
+            (void)dfree(inst[k]->keys_t, A);
+            inst[k]->psi_t = nullptr;
+            inst[k]->keys_t = nullptr;
+        }
+        if (rc >= 0) {
+            if (cfg->per_column) {
+                for (auto *r : group) {
+                    if (r->n == 0) {
+                        r->br = BandResult();
+                        r->br.P = P;
+                        continue;
+                    }
+                    rc = r->run(dtol_abs, reorth, r->br);
+                    if (rc < 0) break;
+                }
+            } else {
+                rc = run_lockstep<T>(group, dtol_abs, reorth, s);
+            }
+        }
+        if (rc < 0) {
+            for (int k = k0; k < k1; k++) drop_inst(*inst[k]);
+            return rc;
+        }
+        for (int k = k0; k < k1; k++) {
+            Instance<T> &in = *inst[k];
+            if (in.G_out) assemble_green(in, p, n_freq, omega, cfg);
+            agg.iters = std::max(agg.iters, std::max(in.plus.br.m, in.minus.br.m));
+            agg.krylov_dim += in.plus.br.krylov + in.minus.br.krylov;
+            agg.n_plus += in.plus.n;
+            agg.n_minus += in.minus.n;
+            agg.n_truncated += in.n_keep;
+        }
+        if (!keep_runs)
+            for (int k = k0; k < k1; k++) drop_inst(*inst[k]);
+        k0 = k1;
+    }
+    if (plan_need) *plan_need = need_max;
     if (info) {
         memset(info, 0, sizeof(*info));
-        info->iters = std::max(brp.m, brm.m);
+        info->iters = agg.iters;
         info->converged = 1;
-        info->e0 = e0;
+        info->e0 = K == 1 ? inst[0]->e0 : 0.0;
         info->solve_ms = wall_ms() - t0;
-        info->krylov_dim = brp.krylov + brm.krylov;
-        info->n_plus = np;
-        info->n_minus = nm;
-        info->n_truncated = n_keep;
+        info->krylov_dim = agg.krylov_dim;
+        info->n_plus = agg.n_plus;
+        info->n_minus = agg.n_minus;
+        info->n_truncated = agg.n_truncated;
     }
     return MCD_OK;
 }
@@ -1903,14 +2093,10 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
                           const double *psi0_dev, double e0, const SelOps &sel, int n_freq,
                           const double *omega, const mcd_band_cfg *cfg, const double *G_bar,
                           double e0_bar, double cg_tol, int cg_max_iter, double *d_t,
-                          double *d_U, double *d_eps, mcd_solve_info *info, hipStream_t s,
-                          BandKeep<T> *keep = nullptr) {
-    const Alloc A{s, true};   // stream-ordered buffers (no device-wide sync on free)
+                          double *d_U, double *d_eps, mcd_solve_info *info, mcd_ws *ws,
+                          hipStream_t s, Instance<T> *keep = nullptr) {
+    const Alloc A{ws};
     const double t0 = wall_ms();
-    {
-        int dev = 0;
-        if (hipGetDevice(&dev) == hipSuccess) pool_keep_freed(dev);
-    }
     const int p = sel.n;
     int P = 1;
     while (P < p) P <<= 1;
@@ -1918,12 +2104,17 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     double *lam = nullptr, *acc = nullptr, *part = nullptr, *scal = nullptr;
     double *xi = nullptr, *res = nullptr, *dir = nullptr, *adir = nullptr;
     double *psi_n = nullptr, *scr = nullptr, *zv = nullptr;
+    Instance<T> rec;   // the recomputed sector runs (without a kept forward)
     auto cleanup = [&]() {
-        for (void *q : {(void *)lam, (void *)acc, (void *)part, (void *)scal, (void *)xi,
-                        (void *)res, (void *)dir, (void *)adir, (void *)psi_n, (void *)scr,
-                        (void *)zv})
+        (void)hipStreamSynchronize(s);   // queued work reads the pieces
+        rec.plus.release();
+        rec.minus.release();
+        for (void *q : {(void *)zv, (void *)adir, (void *)dir, (void *)res, (void *)xi,
+                        (void *)part, (void *)scal, (void *)acc, (void *)lam, (void *)scr,
+                        (void *)psi_n})
             if (q) (void)dfree(q, A);
         if (op_gs) mcd_op_destroy(op_gs);
+        op_gs = nullptr;
     };
 #define CK(expr)                                                              \
     do {                                                                      \
@@ -1931,7 +2122,7 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
         if (e_ != hipSuccess) {                                               \
             set_error("%s failed: %s", #expr, hipGetErrorString(e_));         \
             cleanup();                                                        \
-            return MCD_E_HIP;                                                 \
+            return hip_status(e_);                                            \
         }                                                                     \
     } while (0)
 #define TRY(expr)          \
@@ -1944,7 +2135,7 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     } while (0)
     // untuned: the default row-ordered product kernel, so that the solve (and
     // the derivative) is reproducible bit for bit across calls
-    TRY(op_create(model, keys_dev, n, MCD_STORAGE_AUTO, 0, false, s, &op_gs, true));
+    TRY(op_create(model, keys_dev, n, MCD_STORAGE_AUTO, 0, false, ws, s, &op_gs));
     const int nb = op_gs->hm.dm.n_bonds, no = op_gs->hm.dm.n_orb, np = nb + 2 * no;
     // psi0 normalised exactly as the forward call does, so the band runs below
     // reproduce the forward's recurrence (and stopping point) bit for bit
@@ -1973,8 +2164,10 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     // Per sector: the per-frequency solves, Omega and the two factors of M
     // on the host; M + M^T, Z = Q (M + M^T) and W = Q Omega on the device,
     // tr(Q^T dH Q M) into acc, lam += (start-block map)^T W.
-    auto make_hook = [&](bool create) {
-        return SectorHook<T>([&, create](BandRun<T> &run, mcd_op *op, const BandResult &br) -> int {
+    auto hook = [&](BandRun<T> &run, bool create) -> int {
+        {
+            const mcd_op *op = run.op;
+            const BandResult &br = run.br;
             const int m = br.m, KP = m * P;
             const double sg = create ? 1.0 : -1.0;
             std::vector<double> Om((size_t)KP * P, 0.0);
@@ -2050,18 +2243,16 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             constexpr int kTail = 1024;   // zeroed values after the last row of Zt
             // Zt, M and its factors from the chunk cache (an arena released at
             // the end of the hook): repeated derivative calls reuse the memory
-            Arena zarena(s);
-            const Alloc AZ{s, true, &zarena};
+            Arena zarena(ws);
             T *Zt = nullptr, *Md = nullptr;
             double *dA = nullptr, *dB = nullptr;
-            if (dmalloc((void **)&Zt, ((size_t)nx * S + kTail) * sizeof(T), AZ) != hipSuccess ||
-                dmalloc((void **)&Md, (size_t)S * S * sizeof(T), AZ) != hipSuccess ||
-                dmalloc((void **)&dA, Am.size() * sizeof(double), AZ) != hipSuccess ||
-                dmalloc((void **)&dB, Bm.size() * sizeof(double), AZ) != hipSuccess) {
-                (void)hipGetLastError();
-                set_error("green vjp: no device memory for Z = Q M (%.1f GB)",
+            if (zarena.get((void **)&Zt, ((size_t)nx * S + kTail) * sizeof(T)) != hipSuccess ||
+                zarena.get((void **)&Md, (size_t)S * S * sizeof(T)) != hipSuccess ||
+                zarena.get((void **)&dA, Am.size() * sizeof(double)) != hipSuccess ||
+                zarena.get((void **)&dB, Bm.size() * sizeof(double)) != hipSuccess) {
+                set_error("green vjp: workspace too small for Z = Q M (%.1f GB)",
                           (double)nx * S * sizeof(T) / 1e9);
-                rc = MCD_E_CAPACITY;
+                rc = MCD_E_WORKSPACE;
             }
             if (rc == MCD_OK &&
                 (hipMemcpyAsync(dA, Am.data(), Am.size() * sizeof(double), hipMemcpyHostToDevice,
@@ -2104,32 +2295,39 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             zarena.release();   // after the synchronisation above
             if (rc == MCD_E_HIP) set_error("green vjp: device step failed in a sector hook");
             return rc;
-        });
+        }
     };
-    BandResult brp, brm;
     int64_t npl = 0, nmi = 0;
     {
-        const SectorHook<T> hp = make_hook(true), hm = make_hook(false);
-        if (keep) {   // the forward call's sector runs, kept (no recomputation)
-            for (int side = 0; side < 2; side++) {
-                SectorKeep<T> &k = side == 0 ? keep->plus : keep->minus;
-                (side == 0 ? npl : nmi) = k.n_x;
-                (side == 0 ? brp : brm) = k.br;
-                if (k.br.m > 0 && k.op) {
-                    k.set_stream(s);
-                    const int rc_h = (side == 0 ? hp : hm)(k.run, k.op, k.br);
-                    k.set_stream(nullptr);
-                    TRY(rc_h);
-                }
-            }
-        } else {
-            std::vector<cplx> zp, zm;
-            check_points(cfg, n_freq, omega, e0, zp, zm);
-            TRY(excited_run<T>(model, keys_dev, psi_n, n, sel, true, cfg, 1.0, P, brp, &npl, s,
-                               true, &hp, &zp));
-            TRY(excited_run<T>(model, keys_dev, psi_n, n, sel, false, cfg, 1.0, P, brm, &nmi, s,
-                               true, &hm, &zm));
+        // the forward call's sector runs, kept, or recomputed here with every
+        // Krylov block stored (from psi0 as given: the cut normalises it
+        // exactly as the forward call does, so the recurrence is the same)
+        Instance<T> *src = keep;
+        if (!keep) {
+            rec.model = model;
+            rec.keys = keys_dev;
+            rec.n = n;
+            rec.psi = psi0_dev;
+            rec.e0 = e0;
+            std::vector<Instance<T> *> one{&rec};
+            TRY(band_green_multi<T>(one, sel, n_freq, omega, cfg, ws, s, true, nullptr, true,
+                                    nullptr));
+            src = &rec;
         }
+        npl = src->plus.n;
+        nmi = src->minus.n;
+        for (int side = 0; side < 2; side++) {
+            BandRun<T> &r = side == 0 ? src->plus : src->minus;
+            if (r.br.m > 0 && r.op) {
+                const hipStream_t s_prev = r.s;
+                r.s = s;
+                const int rc_h = hook(r, side == 0);
+                r.s = s_prev;
+                TRY(rc_h);
+            }
+        }
+        rec.plus.release();
+        rec.minus.release();
     }
 
     // (H - E0) xi = P lam on F~, xi orthogonal to psi0: conjugate gradients
@@ -2177,6 +2375,11 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     CK(hipMemcpyAsync(dir, zv, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     CK(hipMemcpyAsync(&rr, scal + 5, sizeof(double), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
+    if (!std::isfinite(rr)) {
+        cleanup();
+        set_error("green vjp: non-finite right-hand side of the response solve");
+        return MCD_E_NUMERIC;
+    }
     const double bnorm = sqrt(rr);
     int it = 0;
     bool conv = bnorm == 0.0;
@@ -2196,7 +2399,17 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
         CK(hipMemcpyAsync(&pap, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
         CK(hipMemcpyAsync(&rr2, scal + 5, sizeof(double), hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
-        if (!(pap > 0.0)) break;   // not positive definite: degenerate ground state
+        if (!std::isfinite(pap) || !std::isfinite(rr2)) {
+            cleanup();
+            set_error("green vjp: non-finite value in the response solve (iteration %d)", it);
+            return MCD_E_NUMERIC;
+        }
+        if (!(pap > 0.0)) {   // not positive definite: psi0 is no non-degenerate ground state
+            cleanup();
+            set_error("green vjp: the response solve met <p, (H - E0) p> = %g <= 0 at iteration "
+                      "%d (psi0 is not a non-degenerate ground state of H~)", pap, it);
+            return MCD_E_BREAKDOWN;
+        }
         it++;
         rel = sqrt(rr2) / bnorm;
         if (rel <= cg_tol) {
@@ -2210,9 +2423,9 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     const int nlb = model->n_bonds;
     std::vector<double> e_t(nlb), e_U(no), e_e(no), x_t(nlb), x_U(no), x_e(no);
     TRY(mcd_hamiltonian_contract(op_gs, model, psi_n, psi_n, e_t.data(), e_U.data(),
-                                 e_e.data(), s));
+                                 e_e.data(), ws, s));
     TRY(mcd_hamiltonian_contract(op_gs, model, xi, psi_n, x_t.data(), x_U.data(), x_e.data(),
-                                 s));
+                                 ws, s));
     std::vector<double> h(np);
     CK(hipMemcpyAsync(h.data(), acc, np * sizeof(double), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
@@ -2279,32 +2492,83 @@ static int band_args(const mcd_model *model, const uint64_t *keys_dev, int64_t n
     return MCD_OK;
 }
 
-// What a kept forward call was made with, and its two sector runs.
+// What a kept forward call was made with, and its two sector runs (their
+// operators and blocks stay in the forward call's workspace).
 struct mcd_band_keep {
     int64_t n = 0;
     int32_t n_sel = 0, orb[16] = {}, spin[16] = {};
     double e0 = 0.0;
     mcd_band_cfg cfg{};
     std::vector<double> omega;
-    std::unique_ptr<mcd::BandKeep<float>> kf;
-    std::unique_ptr<mcd::BandKeep<double>> kd;
+    std::unique_ptr<mcd::Instance<float>> kf;
+    std::unique_ptr<mcd::Instance<double>> kd;
 };
+
+template <typename T>
+static int band_one(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                    const double *psi0_dev, double e0, const SelOps &sel, int32_t n_freq,
+                    const double *omega, const mcd_band_cfg *cfg, double *G_out, double *Gp_out,
+                    double *Gm_out, mcd_solve_info *info, mcd_ws *ws, hipStream_t s,
+                    size_t *plan_need, Instance<T> *keep) {
+    Instance<T> local;
+    Instance<T> &in = keep ? *keep : local;
+    in.model = model;
+    in.keys = keys_dev;
+    in.n = n;
+    in.psi = psi0_dev;
+    in.e0 = e0;
+    in.G_out = G_out;
+    in.Gp_out = Gp_out;
+    in.Gm_out = Gm_out;
+    std::vector<Instance<T> *> one{&in};
+    return band_green_multi<T>(one, sel, n_freq, omega, cfg, ws, s, keep != nullptr, plan_need,
+                               keep != nullptr, info);
+}
 
 extern "C" int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
                                       const double *psi0_dev, double e0, int32_t n_sel,
                                       const int32_t *orb, const int32_t *spin, int32_t n_freq,
                                       const double *omega, const mcd_band_cfg *cfg,
                                       double *G_out, double *Gp_out, double *Gm_out,
-                                      mcd_solve_info *info, void *stream) {
+                                      mcd_solve_info *info, mcd_ws *ws, void *stream) {
     SelOps sel;
     MCD_TRY(band_args(model, keys_dev, n, psi0_dev, n_sel, orb, spin, n_freq, omega, cfg, G_out,
                       sel));
+    MCD_REQUIRE(ws != nullptr, MCD_E_INVALID, "workspace is NULL");
     hipStream_t s = (hipStream_t)stream;
     if (cfg->precision == MCD_F64)
-        return band_green<double>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg,
-                                  G_out, Gp_out, Gm_out, info, s, true);
-    return band_green<float>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg, G_out,
-                             Gp_out, Gm_out, info, s, true);
+        return band_one<double>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg, G_out,
+                                Gp_out, Gm_out, info, ws, s, nullptr, nullptr);
+    return band_one<float>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg, G_out,
+                           Gp_out, Gm_out, info, ws, s, nullptr, nullptr);
+}
+
+extern "C" int mcd_band_workspace_size(const mcd_model *model, const uint64_t *keys_dev,
+                                       int64_t n, const double *psi0_dev, double e0,
+                                       int32_t n_sel, const int32_t *orb, const int32_t *spin,
+                                       int32_t n_freq, const double *omega,
+                                       const mcd_band_cfg *cfg, int32_t keep, mcd_ws *ws,
+                                       void *stream, size_t *bytes) {
+    MCD_REQUIRE(bytes != nullptr, MCD_E_INVALID, "bytes is NULL");
+    *bytes = 0;
+    SelOps sel;
+    double g_dummy = 0.0;
+    MCD_TRY(band_args(model, keys_dev, n, psi0_dev, n_sel, orb, spin, n_freq, omega, cfg,
+                      &g_dummy, sel));
+    MCD_REQUIRE(ws != nullptr, MCD_E_INVALID, "probe workspace is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const mcd_band_cfg c = *cfg;
+    int rc;
+    if (cfg->precision == MCD_F64) {
+        Instance<double> in;
+        rc = band_one<double>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, &c, nullptr,
+                              nullptr, nullptr, nullptr, ws, s, bytes, keep ? &in : nullptr);
+    } else {
+        Instance<float> in;
+        rc = band_one<float>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, &c, nullptr,
+                             nullptr, nullptr, nullptr, ws, s, bytes, keep ? &in : nullptr);
+    }
+    return rc;
 }
 
 extern "C" int mcd_band_lanczos_green_keep(const mcd_model *model, const uint64_t *keys_dev,
@@ -2313,13 +2577,14 @@ extern "C" int mcd_band_lanczos_green_keep(const mcd_model *model, const uint64_
                                            const int32_t *spin, int32_t n_freq,
                                            const double *omega, const mcd_band_cfg *cfg,
                                            double *G_out, double *Gp_out, double *Gm_out,
-                                           mcd_solve_info *info, void *stream,
+                                           mcd_solve_info *info, mcd_ws *ws, void *stream,
                                            mcd_band_keep **keep_out) {
     MCD_REQUIRE(keep_out, MCD_E_INVALID, "keep_out is NULL");
     *keep_out = nullptr;
     SelOps sel;
     MCD_TRY(band_args(model, keys_dev, n, psi0_dev, n_sel, orb, spin, n_freq, omega, cfg, G_out,
                       sel));
+    MCD_REQUIRE(ws != nullptr, MCD_E_INVALID, "workspace is NULL");
     MCD_REQUIRE(cfg->w_t >= 1.0, MCD_E_INVALID, "a kept run needs w_t = 1 (no weight cut)");
     MCD_REQUIRE(cfg->per_column == 0, MCD_E_INVALID, "a kept run uses block products");
     std::unique_ptr<mcd_band_keep> k(new mcd_band_keep());
@@ -2335,13 +2600,13 @@ extern "C" int mcd_band_lanczos_green_keep(const mcd_model *model, const uint64_
     hipStream_t s = (hipStream_t)stream;
     int rc;
     if (cfg->precision == MCD_F64) {
-        k->kd.reset(new BandKeep<double>());
-        rc = band_green<double>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg, G_out,
-                                Gp_out, Gm_out, info, s, true, k->kd.get());
+        k->kd.reset(new Instance<double>());
+        rc = band_one<double>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg, G_out,
+                              Gp_out, Gm_out, info, ws, s, nullptr, k->kd.get());
     } else {
-        k->kf.reset(new BandKeep<float>());
-        rc = band_green<float>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg, G_out,
-                               Gp_out, Gm_out, info, s, true, k->kf.get());
+        k->kf.reset(new Instance<float>());
+        rc = band_one<float>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg, G_out,
+                             Gp_out, Gm_out, info, ws, s, nullptr, k->kf.get());
     }
     if (rc < 0) return rc;   // k and whatever it holds are released
     *keep_out = k.release();
@@ -2355,7 +2620,7 @@ static int band_vjp_entry(const mcd_model *model, const uint64_t *keys_dev, int6
                           const int32_t *spin, int32_t n_freq, const double *omega,
                           const mcd_band_cfg *cfg, const double *G_bar, double e0_bar,
                           double cg_tol, int32_t cg_max_iter, double *d_t, double *d_U,
-                          double *d_eps, mcd_solve_info *info, void *stream,
+                          double *d_eps, mcd_solve_info *info, mcd_ws *ws, void *stream,
                           mcd_band_keep *keep) {
     MCD_REQUIRE(model && cfg && keys_dev && psi0_dev && orb && spin, MCD_E_INVALID,
                 "a required pointer is NULL");
@@ -2398,10 +2663,10 @@ static int band_vjp_entry(const mcd_model *model, const uint64_t *keys_dev, int6
     }
     if (cfg->precision == MCD_F64)
         return band_green_vjp<double>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg,
-                                      G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, s,
-                                      keep ? keep->kd.get() : nullptr);
+                                      G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info,
+                                      ws, s, keep ? keep->kd.get() : nullptr);
     return band_green_vjp<float>(model, keys_dev, n, psi0_dev, e0, sel, n_freq, omega, cfg,
-                                 G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, s,
+                                 G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, ws, s,
                                  keep ? keep->kf.get() : nullptr);
 }
 
@@ -2411,9 +2676,9 @@ extern "C" int mcd_band_green_vjp(const mcd_model *model, const uint64_t *keys_d
                                   const double *omega, const mcd_band_cfg *cfg,
                                   const double *G_bar, double e0_bar, double cg_tol,
                                   int32_t cg_max_iter, double *d_t, double *d_U, double *d_eps,
-                                  mcd_solve_info *info, void *stream) {
+                                  mcd_solve_info *info, mcd_ws *ws, void *stream) {
     return band_vjp_entry(model, keys_dev, n, psi0_dev, e0, n_sel, orb, spin, n_freq, omega, cfg,
-                          G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, stream,
+                          G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, ws, stream,
                           nullptr);
 }
 
@@ -2424,10 +2689,12 @@ extern "C" int mcd_band_green_vjp_keep(const mcd_model *model, const uint64_t *k
                                        const mcd_band_cfg *cfg, const double *G_bar,
                                        double e0_bar, double cg_tol, int32_t cg_max_iter,
                                        double *d_t, double *d_U, double *d_eps,
-                                       mcd_solve_info *info, void *stream, mcd_band_keep *keep) {
+                                       mcd_solve_info *info, mcd_ws *ws, void *stream,
+                                       mcd_band_keep *keep) {
     MCD_REQUIRE(keep, MCD_E_INVALID, "keep is NULL");
     return band_vjp_entry(model, keys_dev, n, psi0_dev, e0, n_sel, orb, spin, n_freq, omega, cfg,
-                          G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, stream, keep);
+                          G_bar, e0_bar, cg_tol, cg_max_iter, d_t, d_U, d_eps, info, ws, stream,
+                          keep);
 }
 
 extern "C" int mcd_batch_band_green(const mcd_model *const *models,
@@ -2435,10 +2702,11 @@ extern "C" int mcd_batch_band_green(const mcd_model *const *models,
                                     const double *const *psi0_dev, const double *e0,
                                     int32_t n_inst, int32_t n_sel, const int32_t *orb,
                                     const int32_t *spin, int32_t n_freq, const double *omega,
-                                    const mcd_band_cfg *cfg, int32_t n_streams,
-                                    double *const *G_out, mcd_solve_info *info, void *stream) {
+                                    const mcd_band_cfg *cfg, double *const *G_out,
+                                    mcd_solve_info *info, mcd_ws *ws, void *stream) {
     MCD_REQUIRE(models && keys_dev && n && psi0_dev && e0 && orb && spin && cfg && G_out,
                 MCD_E_INVALID, "a required pointer is NULL");
+    MCD_REQUIRE(ws != nullptr, MCD_E_INVALID, "workspace is NULL");
     MCD_REQUIRE(n_inst >= 0, MCD_E_INVALID, "n_inst < 0");
     MCD_REQUIRE(n_sel >= 1 && n_sel <= 16, MCD_E_INVALID, "n_sel = %d outside 1..16", n_sel);
     MCD_REQUIRE(n_freq >= 0 && (n_freq == 0 || omega), MCD_E_INVALID, "bad frequencies");
@@ -2463,73 +2731,25 @@ extern "C" int mcd_batch_band_green(const mcd_model *const *models,
         sel.orb[q] = orb[q];
         sel.spin[q] = spin[q];
     }
-    const double t0 = wall_ms();
-    MCD_HIP(hipStreamSynchronize((hipStream_t)stream));   // inputs written on the caller's stream
-    int dev = 0;
-    MCD_HIP(hipGetDevice(&dev));
-    const int W = std::max(1, std::min<int>(std::min<int>(n_streams, 8), std::max(n_inst, 1)));
-    std::atomic<int> next{0};
-    std::vector<int> rcs(W, MCD_OK);
-    std::vector<std::string> msgs(W);
-    std::vector<mcd_solve_info> agg(W);
-    for (auto &a : agg) memset(&a, 0, sizeof(a));
-    auto worker = [&](int w) {
-        if (hipSetDevice(dev) != hipSuccess) {
-            rcs[w] = MCD_E_HIP;
-            msgs[w] = "hipSetDevice failed in a batch worker";
-            return;
+    hipStream_t s = (hipStream_t)stream;
+    auto go = [&](auto tag) -> int {
+        using T = decltype(tag);
+        std::vector<std::unique_ptr<Instance<T>>> own(n_inst);
+        std::vector<Instance<T> *> inst(n_inst);
+        for (int i = 0; i < n_inst; i++) {
+            own[i].reset(new Instance<T>());
+            Instance<T> &in = *own[i];
+            in.model = models[i];
+            in.keys = keys_dev[i];
+            in.n = n[i];
+            in.psi = psi0_dev[i];
+            in.e0 = e0[i];
+            in.G_out = G_out[i];
+            inst[i] = own[i].get();
         }
-        hipStream_t ws = nullptr;
-        if (hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) {
-            rcs[w] = MCD_E_HIP;
-            msgs[w] = "hipStreamCreate failed in a batch worker";
-            return;
-        }
-        for (;;) {
-            const int i = next.fetch_add(1);
-            if (i >= n_inst) break;
-            mcd_solve_info one;
-            const int rc = cfg->precision == MCD_F64
-                               ? band_green<double>(models[i], keys_dev[i], n[i], psi0_dev[i], e0[i],
-                                                    sel, n_freq, omega, cfg, G_out[i], nullptr,
-                                                    nullptr, &one, ws, false)
-                               : band_green<float>(models[i], keys_dev[i], n[i], psi0_dev[i], e0[i],
-                                                   sel, n_freq, omega, cfg, G_out[i], nullptr,
-                                                   nullptr, &one, ws, false);
-            if (rc < 0) {
-                rcs[w] = rc;
-                msgs[w] = std::string("instance ") + std::to_string(i) + ": " + mcd_last_error();
-                break;
-            }
-            agg[w].iters = std::max(agg[w].iters, one.iters);
-            agg[w].krylov_dim += one.krylov_dim;
-            agg[w].n_plus += one.n_plus;
-            agg[w].n_minus += one.n_minus;
-            agg[w].n_truncated += one.n_truncated;
-        }
-        (void)hipStreamSynchronize(ws);
-        (void)hipStreamDestroy(ws);
+        return band_green_multi<T>(inst, sel, n_freq, omega, cfg, ws, s, false, nullptr, false,
+                                   info);
     };
-    std::vector<std::thread> th;
-    for (int w = 1; w < W; w++) th.emplace_back(worker, w);
-    worker(0);
-    for (auto &t : th) t.join();
-    for (int w = 0; w < W; w++)
-        if (rcs[w] < 0) {
-            set_error("%s", msgs[w].c_str());
-            return rcs[w];
-        }
-    if (info) {
-        memset(info, 0, sizeof(*info));
-        for (const auto &a : agg) {
-            info->iters = std::max(info->iters, a.iters);
-            info->krylov_dim += a.krylov_dim;
-            info->n_plus += a.n_plus;
-            info->n_minus += a.n_minus;
-            info->n_truncated += a.n_truncated;
-        }
-        info->converged = 1;
-        info->solve_ms = wall_ms() - t0;
-    }
-    return MCD_OK;
+    if (cfg->precision == MCD_F64) return go(double());
+    return go(float());
 }

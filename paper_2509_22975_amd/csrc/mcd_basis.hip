@@ -307,7 +307,8 @@ __global__ void k_enum_level(uint64_t count, int n, int nu, int nd, int k,
 }
 
 static int build_bfs(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t *keys_dev,
-                     int64_t cap, int64_t *n_out, int64_t *steps_out, hipStream_t s) {
+                     int64_t cap, int64_t *n_out, int64_t *steps_out, mcd_ws *ws, hipStream_t s) {
+    const Alloc al{ws};
     const uint64_t lim = model->n_orb >= 32 ? 0xffffffffull : ((1ull << model->n_orb) - 1ull);
     const uint64_t su = cfg->start_key >> 32, sd = cfg->start_key & 0xffffffffull;
     MCD_REQUIRE((su & ~lim) == 0 && (sd & ~lim) == 0 && __builtin_popcountll(su) == cfg->n_up &&
@@ -355,7 +356,7 @@ static int build_bfs(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t 
                         (void *)ao, (void *)bk, (void *)bo, (void *)uk, (void *)uo, (void *)nk,
                         (void *)no, (void *)nk2, (void *)no2, (void *)flag, (void *)pos,
                         (void *)isnew, (void *)npos, (void *)cnt, tmp})
-            if (p) (void)hipFree(p);
+            if (p) (void)dfree(p, al);
     };
 #define CK(expr)                                                              \
     do {                                                                      \
@@ -363,31 +364,31 @@ static int build_bfs(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t 
         if (e_ != hipSuccess) {                                               \
             set_error("%s failed: %s", #expr, hipGetErrorString(e_));         \
             cleanup();                                                        \
-            return MCD_E_HIP;                                                 \
+            return hip_status(e_);                                            \
         }                                                                     \
     } while (0)
     auto grow = [&](void **p, int64_t bytes) -> hipError_t {
         if (*p) {
-            hipError_t e = hipFree(*p);
+            hipError_t e = dfree(*p, al);
             if (e != hipSuccess) return e;
         }
         *p = nullptr;
-        return hipMalloc(p, std::max<int64_t>(bytes, 8));
+        return dmalloc(p, std::max<int64_t>(bytes, 8), al);
     };
     auto need_tmp = [&](size_t b) -> hipError_t {
         if (b <= tmp_bytes) return hipSuccess;
-        if (tmp) (void)hipFree(tmp);
+        if (tmp) (void)dfree(tmp, al);
         tmp = nullptr;
         tmp_bytes = b;
-        return hipMalloc(&tmp, b);
+        return dmalloc((void **)&tmp, b, al);
     };
-    CK(hipMalloc(&d_hops, H * sizeof(BfsHop)));
+    CK(dmalloc((void **)&d_hops, H * sizeof(BfsHop), al));
     CK(hipMemcpyAsync(d_hops, hh.data(), H * sizeof(BfsHop), hipMemcpyHostToDevice, s));
-    CK(hipMalloc(&d_table, sizeof(table)));
+    CK(dmalloc((void **)&d_table, sizeof(table), al));
     CK(hipMemcpyAsync(d_table, table, sizeof(table), hipMemcpyHostToDevice, s));
-    CK(hipMalloc(&set, (smask + 1) * sizeof(uint64_t)));
+    CK(dmalloc((void **)&set, (smask + 1) * sizeof(uint64_t), al));
     CK(hipMemsetAsync(set, 0xff, (smask + 1) * sizeof(uint64_t), s));
-    CK(hipMalloc(&cnt, 2 * sizeof(unsigned long long)));
+    CK(dmalloc((void **)&cnt, 2 * sizeof(unsigned long long), al));
     // Pre-accepted levels n_U < pre_level, level by level, each sorted by key.
     int64_t npre = 0;
     bool pre_done = false;
@@ -404,11 +405,15 @@ static int build_bfs(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t 
         uint64_t *lv = nullptr, *lv2 = nullptr;
         auto freelv = [&]() {
             for (void *p : {(void *)db, (void *)lv, (void *)lv2})
-                if (p) (void)hipFree(p);
+                if (p) (void)dfree(p, al);
         };
         const int n = model->n_orb, nu = cfg->n_up, nd = cfg->n_dn;
-        if (hipMalloc(&db, sizeof(Binom)) != hipSuccess ||
-            hipMemcpyAsync(db, &hb, sizeof(Binom), hipMemcpyHostToDevice, s) != hipSuccess) {
+        if (dmalloc((void **)&db, sizeof(Binom), al) != hipSuccess) {
+            cleanup();
+            set_error("pre-acceptance: workspace too small for the binomial table");
+            return MCD_E_WORKSPACE;
+        }
+        if (hipMemcpyAsync(db, &hb, sizeof(Binom), hipMemcpyHostToDevice, s) != hipSuccess) {
             freelv();
             cleanup();
             set_error("pre-acceptance: binomial table upload failed");
@@ -427,8 +432,9 @@ static int build_bfs(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t 
             }
             const int64_t c = (int64_t)cnt_k;
             int rc = MCD_OK;
-            if (hipMalloc(&lv, c * 8) != hipSuccess || hipMalloc(&lv2, c * 8) != hipSuccess)
-                rc = MCD_E_HIP;
+            if (dmalloc((void **)&lv, c * 8, al) != hipSuccess ||
+                dmalloc((void **)&lv2, c * 8, al) != hipSuccess)
+                rc = MCD_E_WORKSPACE;
             if (rc == MCD_OK) {
                 hipLaunchKernelGGL(k_enum_level, dim3((unsigned)((c + 255) / 256)), dim3(256), 0,
                                    s, cnt_k, n, nu, nd, k, db, lv);
@@ -448,8 +454,8 @@ static int build_bfs(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t 
                                                hipMemcpyDeviceToDevice, s) != hipSuccess)
                 rc = MCD_E_HIP;
             if (rc == MCD_OK && hipStreamSynchronize(s) != hipSuccess) rc = MCD_E_HIP;
-            (void)hipFree(lv);
-            (void)hipFree(lv2);
+            (void)dfree(lv, al);
+            (void)dfree(lv2, al);
             lv = lv2 = nullptr;
             if (rc != MCD_OK) {
                 freelv();
@@ -570,7 +576,7 @@ static int build_bfs(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t 
     // output sorted
     {
         uint64_t *srt = nullptr;
-        CK(hipMalloc(&srt, nS * sizeof(uint64_t)));
+        CK(dmalloc((void **)&srt, nS * sizeof(uint64_t), al));
         size_t b = 0;
         CK(hipcub::DeviceRadixSort::SortKeys(nullptr, b, keys_dev, srt, (int)nS, 0, 64, s));
         CK(need_tmp(b));
@@ -578,7 +584,7 @@ static int build_bfs(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t 
         CK(hipcub::DeviceRadixSort::SortKeys(tmp, b, keys_dev, srt, (int)nS, 0, 64, s));
         CK(hipMemcpyAsync(keys_dev, srt, nS * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
         CK(hipStreamSynchronize(s));
-        (void)hipFree(srt);
+        (void)dfree(srt, al);
     }
     *n_out = nS;
     if (steps_out) *steps_out = step;
@@ -588,7 +594,8 @@ static int build_bfs(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t 
 }
 
 static int build_full(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t *keys_dev,
-                      int64_t cap, int64_t *n_out, hipStream_t s) {
+                      int64_t cap, int64_t *n_out, mcd_ws *ws, hipStream_t s) {
+    const Alloc al{ws};
     Binom hb;
     fill_binom(hb);
     const int n = model->n_orb;
@@ -598,19 +605,21 @@ static int build_full(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t
     MCD_REQUIRE((int64_t)total <= cap, MCD_E_CAPACITY, "sector has %llu states, cap is %lld",
                 (unsigned long long)total, (long long)cap);
     Binom *db = nullptr;
-    MCD_HIP(hipMalloc(&db, sizeof(Binom)));
+    MCD_HIP(dmalloc((void **)&db, sizeof(Binom), al));
     MCD_HIP(hipMemcpyAsync(db, &hb, sizeof(Binom), hipMemcpyHostToDevice, s));
     if (total)
         hipLaunchKernelGGL(k_enumerate, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                            total, nd_states, n, cfg->n_up, cfg->n_dn, db, keys_dev);
     MCD_HIP(hipGetLastError());
     MCD_HIP(hipStreamSynchronize(s));
-    MCD_HIP(hipFree(db));
+    MCD_HIP(dfree(db, al));
     return MCD_OK;
 }
 
 static int build_chain(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_t *keys_dev,
-                       int64_t cap, int64_t *n_out, int64_t *steps_out, hipStream_t s) {
+                       int64_t cap, int64_t *n_out, int64_t *steps_out, mcd_ws *ws,
+                       hipStream_t s) {
+    const Alloc al{ws};
     const uint64_t lim = model->n_orb >= 32 ? 0xffffffffull : ((1ull << model->n_orb) - 1ull);
     const uint64_t su = cfg->start_key >> 32, sd = cfg->start_key & 0xffffffffull;
     MCD_REQUIRE((su & ~lim) == 0 && (sd & ~lim) == 0 && __builtin_popcountll(su) == cfg->n_up &&
@@ -642,7 +651,7 @@ static int build_chain(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_
     auto cleanup = [&]() {
         for (void *p : {(void *)tab, (void *)d_ek, (void *)d_es, (void *)d_cnt, (void *)d_steps,
                         (void *)d_keys, (void *)d_steps2, (void *)d_keys2, tmp})
-            if (p) (void)hipFree(p);
+            if (p) (void)dfree(p, al);
     };
 #define CK(expr)                                                                    \
     do {                                                                            \
@@ -650,14 +659,14 @@ static int build_chain(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_
         if (e_ != hipSuccess) {                                                     \
             set_error("%s failed: %s", #expr, hipGetErrorString(e_));               \
             cleanup();                                                              \
-            return MCD_E_HIP;                                                       \
+            return hip_status(e_);                                                  \
         }                                                                           \
     } while (0)
-    CK(hipMalloc(&tab, tcap * sizeof(VisitSlot)));
+    CK(dmalloc((void **)&tab, tcap * sizeof(VisitSlot), al));
     CK(hipMemsetAsync(tab, 0xff, tcap * sizeof(VisitSlot), s));
-    CK(hipMalloc(&d_ek, chunk * sizeof(uint64_t)));
-    CK(hipMalloc(&d_es, chunk * sizeof(uint64_t)));
-    CK(hipMalloc(&d_cnt, 2 * sizeof(unsigned long long)));
+    CK(dmalloc((void **)&d_ek, chunk * sizeof(uint64_t), al));
+    CK(dmalloc((void **)&d_es, chunk * sizeof(uint64_t), al));
+    CK(dmalloc((void **)&d_cnt, 2 * sizeof(unsigned long long), al));
     CK(hipMemsetAsync(d_cnt, 0, 2 * sizeof(unsigned long long), s));
     std::vector<uint64_t> ek, es;
     ek.reserve(chunk);
@@ -688,10 +697,10 @@ static int build_chain(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_
     }
     int64_t steps_done = w.step;
     if (D > 0) {
-        CK(hipMalloc(&d_steps, D * sizeof(uint64_t)));
-        CK(hipMalloc(&d_keys, D * sizeof(uint64_t)));
-        CK(hipMalloc(&d_steps2, D * sizeof(uint64_t)));
-        CK(hipMalloc(&d_keys2, D * sizeof(uint64_t)));
+        CK(dmalloc((void **)&d_steps, D * sizeof(uint64_t), al));
+        CK(dmalloc((void **)&d_keys, D * sizeof(uint64_t), al));
+        CK(dmalloc((void **)&d_steps2, D * sizeof(uint64_t), al));
+        CK(dmalloc((void **)&d_keys2, D * sizeof(uint64_t), al));
         hipLaunchKernelGGL(k_visit_compact, dim3((unsigned)((tcap + 255) / 256)), dim3(256), 0, s,
                            tcap, tab, d_steps, d_keys, d_cnt + 1);
         CK(hipGetLastError());
@@ -700,7 +709,7 @@ static int build_chain(const mcd_model *model, const mcd_basis_cfg *cfg, uint64_
                                               (int)D, 0, 64, s));
         CK(hipcub::DeviceRadixSort::SortKeys(nullptr, tb2, d_keys2, keys_dev, (int)nf, 0, 64, s));
         const size_t tb = std::max(tb1, tb2);
-        CK(hipMalloc(&tmp, tb));
+        CK(dmalloc((void **)&tmp, tb, al));
         size_t t1 = tb;
         CK(hipcub::DeviceRadixSort::SortPairs(tmp, t1, d_steps, d_steps2, d_keys, d_keys2, (int)D,
                                               0, 64, s));
@@ -728,7 +737,7 @@ using namespace mcd;
 
 extern "C" int mcd_basis_build(const mcd_model *model, const mcd_basis_cfg *cfg,
                                uint64_t *keys_dev, int64_t cap, int64_t *n_out,
-                               int64_t *steps_out, void *stream) {
+                               int64_t *steps_out, mcd_ws *ws, void *stream) {
     MCD_REQUIRE(model && cfg && n_out, MCD_E_INVALID, "model, cfg or n_out is NULL");
     HostModel hm;
     MCD_TRY(prepare_model(model, &hm));
@@ -739,11 +748,11 @@ extern "C" int mcd_basis_build(const mcd_model *model, const mcd_basis_cfg *cfg,
     MCD_REQUIRE(cap == 0 || keys_dev != nullptr, MCD_E_INVALID, "keys_dev is NULL");
     hipStream_t s = (hipStream_t)stream;
     if (steps_out) *steps_out = 0;
-    if (cfg->mode == MCD_BASIS_FULL) return build_full(model, cfg, keys_dev, cap, n_out, s);
+    if (cfg->mode == MCD_BASIS_FULL) return build_full(model, cfg, keys_dev, cap, n_out, ws, s);
     if (cfg->mode == MCD_BASIS_CHAIN)
-        return build_chain(model, cfg, keys_dev, cap, n_out, steps_out, s);
+        return build_chain(model, cfg, keys_dev, cap, n_out, steps_out, ws, s);
     if (cfg->mode == MCD_BASIS_STEPS)
-        return build_bfs(model, cfg, keys_dev, cap, n_out, steps_out, s);
+        return build_bfs(model, cfg, keys_dev, cap, n_out, steps_out, ws, s);
     set_error("basis mode %d unknown", cfg->mode);
     return MCD_E_INVALID;
 }

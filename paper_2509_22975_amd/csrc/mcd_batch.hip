@@ -236,9 +236,10 @@ using namespace mcd;
 extern "C" int mcd_batch_lanczos_ground(mcd_op *const *ops, int32_t n_ops,
                                         const mcd_lanczos_cfg *cfg, double *e0_out,
                                         double *const *psi0_dev, int32_t *iters_out,
-                                        mcd_solve_info *info, void *stream) {
+                                        mcd_solve_info *info, mcd_ws *ws, void *stream) {
     MCD_REQUIRE(ops && cfg && e0_out && n_ops >= 1 && n_ops <= 4096, MCD_E_INVALID,
                 "ops, cfg, e0_out required; 1 <= n_ops <= 4096");
+    MCD_REQUIRE(cfg->precision == MCD_F64, MCD_E_INVALID, "batched Lanczos is float64 only");
     const double t_start = bwall_ms();
     const int K = n_ops;
     int R = 256;
@@ -266,12 +267,8 @@ extern "C" int mcd_batch_lanczos_ground(mcd_op *const *ops, int32_t n_ops,
         row0 += op->n;
     }
     const size_t store_bytes = (size_t)stride * Ntot * sizeof(double);
-    size_t fr = 0, tot = 0;
-    MCD_HIP(hipMemGetInfo(&fr, &tot));
-    MCD_REQUIRE((double)store_bytes < 0.7 * (double)fr, MCD_E_CAPACITY,
-                "batched Krylov store needs %.1f GB, %.1f GB free", store_bytes / 1e9, fr / 1e9);
-    hipStream_t us = (hipStream_t)stream;
-    hipStream_t s = nullptr;
+    const Alloc al{ws};
+    hipStream_t s = (hipStream_t)stream;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     BDesc *dd = nullptr;
@@ -280,10 +277,10 @@ extern "C" int mcd_batch_lanczos_ground(mcd_op *const *ops, int32_t n_ops,
     auto cleanup = [&]() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamSynchronize(s);   // queued work reads the pieces
         for (void *p : {(void *)dd, (void *)U, (void *)Y, (void *)sc, (void *)part, (void *)coef,
                         (void *)iv})
-            if (p) (void)hipFree(p);
-        if (s) (void)hipStreamDestroy(s);
+            if (p) (void)dfree(p, al);
     };
 #define CK(expr)                                                              \
     do {                                                                      \
@@ -291,23 +288,21 @@ extern "C" int mcd_batch_lanczos_ground(mcd_op *const *ops, int32_t n_ops,
         if (e_ != hipSuccess) {                                               \
             set_error("%s failed: %s", #expr, hipGetErrorString(e_));         \
             cleanup();                                                        \
-            return MCD_E_HIP;                                                 \
+            return hip_status(e_);                                            \
         }                                                                     \
     } while (0)
-    CK(hipStreamSynchronize(us));
-    CK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    CK(hipMalloc(&dd, K * sizeof(BDesc)));
+    CK(dmalloc((void **)&dd, K * sizeof(BDesc), al));
     CK(hipMemcpyAsync(dd, hd.data(), K * sizeof(BDesc), hipMemcpyHostToDevice, s));
-    CK(hipMalloc(&U, store_bytes));
-    CK(hipMalloc(&Y, Ntot * sizeof(double)));
-    CK(hipMalloc(&sc, (size_t)2 * K * stride * sizeof(double)));
+    CK(dmalloc((void **)&U, store_bytes, al));
+    CK(dmalloc((void **)&Y, Ntot * sizeof(double), al));
+    CK(dmalloc((void **)&sc, (size_t)2 * K * stride * sizeof(double), al));
     CK(hipMemsetAsync(sc, 0, (size_t)2 * K * stride * sizeof(double), s));
-    CK(hipMalloc(&part, std::max(nb, ub) * sizeof(double)));
+    CK(dmalloc((void **)&part, std::max(nb, ub) * sizeof(double), al));
     // psi coefficients of every instance, then the norm partials (at most
     // 2048 workgroups) and one squared norm per instance
     constexpr int kNormPart = 2048;
-    CK(hipMalloc(&coef, ((size_t)K * stride + kNormPart + K) * sizeof(double)));
-    CK(hipMalloc(&iv, (K + 1) * sizeof(int)));
+    CK(dmalloc((void **)&coef, ((size_t)K * stride + kNormPart + K) * sizeof(double), al));
+    CK(dmalloc((void **)&iv, (K + 1) * sizeof(int), al));
     std::vector<int> hact(K + 1, 1);
     hact[K] = 0;   // step counter
     CK(hipMemcpyAsync(iv, hact.data(), (K + 1) * sizeof(int), hipMemcpyHostToDevice, s));
@@ -327,12 +322,16 @@ extern "C" int mcd_batch_lanczos_ground(mcd_op *const *ops, int32_t n_ops,
         hipLaunchKernelGGL(k_bfinal, dim3(K), dim3(BBS), 0, s, st, 1, st.nrm2, 1);
         hipLaunchKernelGGL(k_bstep, dim3(1), dim3(64), 0, s, iv + K);
     };
-    // One graph of `every` steps, replayed.
+    // One graph of `every` steps, captured on the caller's stream and
+    // replayed; a stream that cannot be captured (the legacy NULL stream)
+    // gets the same launches one by one.
     const int chunk = std::min(every, maxit);
-    CK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int q = 0; q < chunk; q++) enqueue_step();
-    CK(hipStreamEndCapture(s, &graph));
-    CK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    if (s != nullptr) {
+        CK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int q = 0; q < chunk; q++) enqueue_step();
+        CK(hipStreamEndCapture(s, &graph));
+        CK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    }
 
     hipEvent_t ev0, ev1;
     CK(hipEventCreate(&ev0));
@@ -346,7 +345,11 @@ extern "C" int mcd_batch_lanczos_ground(mcd_op *const *ops, int32_t n_ops,
     int n_active = K;
     while (steps < maxit && n_active > 0) {
         if (steps + chunk <= maxit) {
-            CK(hipGraphLaunch(gexec, s));
+            if (gexec) {
+                CK(hipGraphLaunch(gexec, s));
+            } else {
+                for (int q = 0; q < chunk; q++) enqueue_step();
+            }
             steps += chunk;
         } else {
             enqueue_step();

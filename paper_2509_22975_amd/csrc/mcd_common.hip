@@ -16,111 +16,24 @@ namespace mcd {
 
 static thread_local char g_err[1024] = "";
 
-namespace {
-struct CachedChunk {
-    char *p;
-    size_t bytes;
-    int dev;
-    hipEvent_t ready;   // recorded on the releasing stream
-};
-std::mutex g_chunk_mu;
-std::vector<CachedChunk> g_chunks;   // free chunks
-size_t g_chunk_bytes = 0;            // bytes held by g_chunks
-}  // namespace
+int hip_status(hipError_t e) { return e == hipErrorOutOfMemory ? MCD_E_WORKSPACE : MCD_E_HIP; }
 
-hipError_t chunk_acquire(size_t bytes, hipStream_t s, void **out, size_t *got) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    {
-        std::lock_guard<std::mutex> lock(g_chunk_mu);
-        int best = -1;
-        for (int i = 0; i < (int)g_chunks.size(); i++) {
-            const CachedChunk &c = g_chunks[i];
-            if (c.dev != dev || c.bytes < bytes || c.bytes > 2 * bytes + (size_t(64) << 20))
-                continue;
-            if (best < 0 || c.bytes < g_chunks[best].bytes) best = i;
-        }
-        if (best >= 0) {
-            const CachedChunk c = g_chunks[best];
-            g_chunks.erase(g_chunks.begin() + best);
-            g_chunk_bytes -= c.bytes;
-            e = hipStreamWaitEvent(s, c.ready, 0);
-            (void)hipEventDestroy(c.ready);
-            if (e != hipSuccess) {
-                (void)hipFree(c.p);
-                return e;
-            }
-            *out = c.p;
-            *got = c.bytes;
-            return hipSuccess;
-        }
-    }
-    const size_t unit = size_t(64) << 20;
-    const size_t sz = (std::max<size_t>(bytes, 1) + unit - 1) / unit * unit;
-    e = hipMalloc(out, sz);
-    if (e != hipSuccess) {
-        // free this device's cached chunks once, then retry
-        (void)hipGetLastError();
-        std::vector<CachedChunk> mine;
-        {
-            std::lock_guard<std::mutex> lock(g_chunk_mu);
-            for (auto it = g_chunks.begin(); it != g_chunks.end();) {
-                if (it->dev == dev) {
-                    mine.push_back(*it);
-                    g_chunk_bytes -= it->bytes;
-                    it = g_chunks.erase(it);
-                } else {
-                    ++it;
-                }
-            }
-        }
-        for (auto &c : mine) {
-            (void)hipEventSynchronize(c.ready);
-            (void)hipEventDestroy(c.ready);
-            (void)hipFree(c.p);
-        }
-        e = hipMalloc(out, sz);
-    }
-    if (e == hipSuccess) *got = sz;
-    return e;
+hipError_t dmalloc(void **p, size_t bytes, const Alloc &a) {
+    *p = nullptr;
+    if (a.ws == nullptr) return hipErrorOutOfMemory;   // no workspace: nothing to take
+    std::lock_guard<std::mutex> lock(a.ws->mu);
+    const size_t off = a.ws->a.alloc(bytes);
+    if (off == WsAlloc::kFail) return hipErrorOutOfMemory;
+    *p = a.ws->base + off;
+    return hipSuccess;
 }
 
-void chunk_release(void *p, size_t bytes, hipStream_t s) {
-    int dev = 0;
-    hipEvent_t ev = nullptr;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(ev, s) != hipSuccess) {
-        (void)hipStreamSynchronize(s);
-        if (ev) (void)hipEventDestroy(ev);
-        (void)hipFree(p);
-        return;
-    }
-    {
-        std::lock_guard<std::mutex> lock(g_chunk_mu);
-        if (g_chunk_bytes + bytes <= kChunkCacheBytes) {
-            g_chunks.push_back({(char *)p, bytes, dev, ev});
-            g_chunk_bytes += bytes;
-            return;
-        }
-    }
-    (void)hipEventSynchronize(ev);
-    (void)hipEventDestroy(ev);
-    (void)hipFree(p);
-}
-
-void pool_keep_freed(int device) {
-    static std::mutex mu;
-    static bool done[64] = {};
-    if (device < 0 || device >= 64) return;
-    std::lock_guard<std::mutex> lock(mu);
-    if (done[device]) return;
-    done[device] = true;
-    hipMemPool_t pool = nullptr;
-    if (hipDeviceGetDefaultMemPool(&pool, device) != hipSuccess || pool == nullptr) return;
-    uint64_t keep = kPoolKeepBytes;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+hipError_t dfree(void *p, const Alloc &a) {
+    if (p == nullptr || a.ws == nullptr) return hipSuccess;
+    std::lock_guard<std::mutex> lock(a.ws->mu);
+    const char *c = (const char *)p;
+    if (c < a.ws->base || !a.ws->a.release((size_t)(c - a.ws->base))) return hipErrorInvalidValue;
+    return hipSuccess;
 }
 
 void set_error(const char *fmt, ...) {
@@ -204,4 +117,28 @@ int prepare_model(const mcd_model *m, HostModel *hm) {
 }  // namespace mcd
 
 extern "C" const char *mcd_last_error(void) { return mcd::g_err; }
+
+extern "C" int mcd_ws_create(void *base_dev, size_t bytes, mcd_ws **out) {
+    MCD_REQUIRE(out != nullptr, MCD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    MCD_REQUIRE(base_dev != nullptr || bytes == 0, MCD_E_INVALID, "base is NULL");
+    MCD_REQUIRE(((uintptr_t)base_dev & 255u) == 0, MCD_E_INVALID,
+                "workspace base must be 256-byte aligned");
+    mcd_ws *w = new mcd_ws(base_dev, bytes);
+    *out = w;
+    return MCD_OK;
+}
+
+extern "C" void mcd_ws_destroy(mcd_ws *ws) { delete ws; }
+
+extern "C" int mcd_ws_stats(const mcd_ws *ws, size_t *size, size_t *in_use, size_t *high_water,
+                            size_t *need) {
+    MCD_REQUIRE(ws != nullptr, MCD_E_INVALID, "ws is NULL");
+    std::lock_guard<std::mutex> lock(const_cast<mcd_ws *>(ws)->mu);
+    if (size) *size = ws->a.size();
+    if (in_use) *in_use = ws->a.in_use();
+    if (high_water) *high_water = ws->a.high_water();
+    if (need) *need = ws->a.need();
+    return MCD_OK;
+}
 extern "C" int mcd_version(void) { return 10000; }

@@ -18,46 +18,57 @@ namespace mcd {
 
 static constexpr int GBS = 256;
 
-// part[p * nblk + block] for p in [0, NB + 2 n_orb): merged bonds, U_i, eps_i.
+static constexpr int kMaxContractBlocks = 2048;
+static constexpr int kMaxParams = MCD_MAX_BONDS + 2 * MCD_MAX_ORB;
+
+// part[p * gridDim.x + block] for p in [0, NB + 2 n_orb): merged bonds, U_i,
+// eps_i.  Workgroup b takes the row tiles b, b + G, ... (G = gridDim.x) and
+// adds each tile's workgroup sum to its per-parameter total in tile order.
 __global__ __launch_bounds__(GBS) void k_contract(int64_t n, const uint64_t *__restrict__ keys,
                                                   const DevModel *__restrict__ m,
                                                   const HashSlot *__restrict__ h, uint64_t hmask,
                                                   const double *__restrict__ a,
                                                   const double *__restrict__ b,
                                                   double *__restrict__ part) {
-    const int64_t r = (int64_t)blockIdx.x * GBS + threadIdx.x;
-    const bool own = r < n;
-    const uint64_t key = own ? keys[r] : 0ull;
-    const double ar = own ? a[r] : 0.0;
-    const double br = own ? b[r] : 0.0;
-    const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
-    const int nb = m->n_bonds, no = m->n_orb;
-    const int64_t nblk = gridDim.x;
-    for (int q = 0; q < nb; q++) {
-        double c = 0.0;
-        if (own) {
-            const uint32_t mask = m->bonds[q].mask, between = m->bonds[q].between;
-            if (__popc(up & mask) == 1) {
-                const int64_t col = hash_find(h, hmask, key ^ ((uint64_t)mask << 32));
-                if (col >= 0) c += (__popc(up & between) & 1) ? -b[col] : b[col];
+    __shared__ double tot[kMaxParams];
+    const int nb = m->n_bonds, no = m->n_orb, np = nb + 2 * no;
+    for (int i = threadIdx.x; i < np; i += GBS) tot[i] = 0.0;
+    __syncthreads();
+    for (int64_t tile = blockIdx.x; tile * GBS < n; tile += gridDim.x) {
+        const int64_t r = tile * GBS + threadIdx.x;
+        const bool own = r < n;
+        const uint64_t key = own ? keys[r] : 0ull;
+        const double ar = own ? a[r] : 0.0;
+        const double br = own ? b[r] : 0.0;
+        const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
+        for (int q = 0; q < nb; q++) {
+            double c = 0.0;
+            if (own) {
+                const uint32_t mask = m->bonds[q].mask, between = m->bonds[q].between;
+                if (__popc(up & mask) == 1) {
+                    const int64_t col = hash_find(h, hmask, key ^ ((uint64_t)mask << 32));
+                    if (col >= 0) c += (__popc(up & between) & 1) ? -b[col] : b[col];
+                }
+                if (__popc(dn & mask) == 1) {
+                    const int64_t col = hash_find(h, hmask, key ^ (uint64_t)mask);
+                    if (col >= 0) c += (__popc(dn & between) & 1) ? -b[col] : b[col];
+                }
+                c *= ar;
             }
-            if (__popc(dn & mask) == 1) {
-                const int64_t col = hash_find(h, hmask, key ^ (uint64_t)mask);
-                if (col >= 0) c += (__popc(dn & between) & 1) ? -b[col] : b[col];
-            }
-            c *= ar;
+            c = block_sum<GBS>(c);
+            if (threadIdx.x == 0) tot[q] += c;
         }
-        c = block_sum<GBS>(c);
-        if (threadIdx.x == 0) part[(int64_t)q * nblk + blockIdx.x] = c;
+        for (int i = 0; i < no; i++) {
+            const double nu = (double)((up >> i) & 1u), nd = (double)((dn >> i) & 1u);
+            const double ab = ar * br;
+            const double cu = block_sum<GBS>(ab * (nu * nd));
+            if (threadIdx.x == 0) tot[nb + i] += cu;
+            const double ce = block_sum<GBS>(ab * (nu + nd));
+            if (threadIdx.x == 0) tot[nb + no + i] += ce;
+        }
     }
-    for (int i = 0; i < no; i++) {
-        const double nu = (double)((up >> i) & 1u), nd = (double)((dn >> i) & 1u);
-        const double ab = ar * br;
-        double cu = block_sum<GBS>(ab * (nu * nd));
-        if (threadIdx.x == 0) part[(int64_t)(nb + i) * nblk + blockIdx.x] = cu;
-        double ce = block_sum<GBS>(ab * (nu + nd));
-        if (threadIdx.x == 0) part[(int64_t)(nb + no + i) * nblk + blockIdx.x] = ce;
-    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < np; i += GBS) part[(int64_t)i * gridDim.x + blockIdx.x] = tot[i];
 }
 
 __global__ __launch_bounds__(256) void k_contract_reduce(int np, int64_t nblk,
@@ -72,32 +83,27 @@ __global__ __launch_bounds__(256) void k_contract_reduce(int np, int64_t nblk,
     if (lane == 0) out[p] = s;
 }
 
-}  // namespace mcd
+static int contract_blocks(int64_t n) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n + GBS - 1) / GBS, kMaxContractBlocks));
+}
 
-using namespace mcd;
-
-extern "C" int mcd_hamiltonian_contract(const mcd_op *op, const mcd_model *model,
-                                        const double *a_dev, const double *b_dev, double *d_t,
-                                        double *d_U, double *d_eps, void *stream) {
-    MCD_REQUIRE(op && model && a_dev && b_dev, MCD_E_INVALID, "op, model, a, b required");
-    MCD_REQUIRE(model->n_orb == op->hm.dm.n_orb, MCD_E_INVALID,
-                "model has %d orbitals, operator %d", model->n_orb, op->hm.dm.n_orb);
-    hipStream_t s = (hipStream_t)stream;
+// The contraction with partials in `part` ([np][nblk] + np doubles) and the
+// host-side mapping of merged bonds back to listed bonds.
+static int contract_into(const mcd_op *op, const mcd_model *model, const double *a_dev,
+                         const double *b_dev, double *part, double *d_t, double *d_U,
+                         double *d_eps, hipStream_t s) {
     const int nb = op->hm.dm.n_bonds, no = op->hm.dm.n_orb;
     const int np = nb + 2 * no;
-    const int64_t nblk = std::max<int64_t>(1, (op->n + GBS - 1) / GBS);
-    double *part = nullptr, *out = nullptr;
-    MCD_HIP(hipMalloc(&part, (size_t)np * nblk * sizeof(double)));
-    MCD_HIP(hipMalloc(&out, (size_t)np * sizeof(double)));
+    const int nblk = contract_blocks(op->n);
+    double *out = part + (size_t)np * nblk;
     hipLaunchKernelGGL(k_contract, dim3((unsigned)nblk), dim3(GBS), 0, s, op->n, op->d_keys,
                        op->d_model, op->d_hash, op->hash_mask, a_dev, b_dev, part);
     hipLaunchKernelGGL(k_contract_reduce, dim3((unsigned)((np + 3) / 4)), dim3(256), 0, s, np,
-                       nblk, part, out);
+                       (int64_t)nblk, part, out);
+    MCD_HIP(hipGetLastError());
     std::vector<double> h(np);
     MCD_HIP(hipMemcpyAsync(h.data(), out, np * sizeof(double), hipMemcpyDeviceToHost, s));
     MCD_HIP(hipStreamSynchronize(s));
-    MCD_HIP(hipFree(part));
-    MCD_HIP(hipFree(out));
     // listed bond -> merged pair (bonds listed twice share the pair's derivative)
     if (d_t) {
         for (int q = 0; q < model->n_bonds; q++) {
@@ -115,4 +121,29 @@ extern "C" int mcd_hamiltonian_contract(const mcd_op *op, const mcd_model *model
         if (d_eps) d_eps[i] = h[nb + no + i];
     }
     return MCD_OK;
+}
+
+static size_t contract_scratch_bytes(const mcd_op *op) {
+    const int np = op->hm.dm.n_bonds + 2 * op->hm.dm.n_orb;
+    return ((size_t)np * contract_blocks(op->n) + np) * sizeof(double);
+}
+
+}  // namespace mcd
+
+using namespace mcd;
+
+extern "C" int mcd_hamiltonian_contract(const mcd_op *op, const mcd_model *model,
+                                        const double *a_dev, const double *b_dev, double *d_t,
+                                        double *d_U, double *d_eps, mcd_ws *ws, void *stream) {
+    MCD_REQUIRE(op && model && a_dev && b_dev, MCD_E_INVALID, "op, model, a, b required");
+    MCD_REQUIRE(model->n_orb == op->hm.dm.n_orb, MCD_E_INVALID,
+                "model has %d orbitals, operator %d", model->n_orb, op->hm.dm.n_orb);
+    hipStream_t s = (hipStream_t)stream;
+    const Alloc al{ws};
+    double *part = nullptr;
+    MCD_HIP(dmalloc((void **)&part, contract_scratch_bytes(op), al));
+    const int rc = contract_into(op, model, a_dev, b_dev, part, d_t, d_U, d_eps, s);
+    (void)hipStreamSynchronize(s);
+    (void)dfree(part, al);
+    return rc;
 }

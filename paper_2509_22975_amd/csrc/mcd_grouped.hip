@@ -341,6 +341,51 @@ template int grouped_one<double>(const mcd_op *, bool, const double *, double *,
 template int grouped_one<float>(const mcd_op *, bool, const float *, float *, const double *, int,
                                 double *, int64_t *, hipStream_t);
 
+// The takes and releases of build_grouped replayed on host bookkeeping with
+// the largest sizes the layout can have (row blocks: at most two per chunk
+// plus one per 256 rows; groups: at most one per nonzero), for the
+// workspace-size query.
+void grouped_plan(WsAlloc &w, int64_t n, int64_t nnz) {
+    if (n == 0 || nnz <= 0 || nnz >= (int64_t(1) << 31)) return;
+    hipStream_t s0 = (hipStream_t)0;
+    std::vector<size_t> tmp;
+    auto get = [&](size_t b) { tmp.push_back(w.alloc(std::max<size_t>(b, 8))); };
+    size_t sb = 0, sb2 = 0, sb3 = 0, sb4 = 0;
+    (void)hipcub::DeviceScan::InclusiveSum(nullptr, sb, (const uint32_t *)nullptr,
+                                           (uint32_t *)nullptr, (int)n, s0);
+    get(n * 4);
+    get(n * 4);
+    get(sb);
+    get(8);
+    const int64_t nch = nnz / (kGroupedNnz / 2) + 1;   // chunk step >= kGroupedNnz / 2
+    get((nch + 1) * 8);
+    get((nch + 1) * 8);
+    get((nch + 1) * 8);
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, sb2, (const int64_t *)nullptr,
+                                           (int64_t *)nullptr, (int)(nch + 1), s0);
+    get(sb2);
+    const int64_t nb = 2 * nch + n / kGroupedRows + 2;
+    w.alloc((nb + 1) * 8);   // d_gbs (kept)
+    get(nnz * 8);
+    get(nnz * 8);
+    get(nnz * 4);
+    get(nnz * 4);
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sb3, (const uint64_t *)nullptr,
+                                             (uint64_t *)nullptr, (const uint32_t *)nullptr,
+                                             (uint32_t *)nullptr, (int)nnz, 0, 64, s0);
+    get(sb3);
+    get(nnz * 4);
+    get(nnz * 4);
+    (void)hipcub::DeviceScan::InclusiveSum(nullptr, sb4, (const uint32_t *)nullptr,
+                                           (uint32_t *)nullptr, (int)nnz, s0);
+    get(sb4);
+    get(sizeof(int));
+    w.alloc((nb + 1) * 8);                                         // d_goff
+    w.alloc((size_t)(std::min<int64_t>(nnz, nb * kGroupedMaxGroups) + 1) * 8);   // d_gtab
+    w.alloc(nnz * 4);                                              // d_gw
+    for (size_t o : tmp) w.release(o);
+}
+
 // ---------------------------------------------------------------------------
 // Build the layout from the packed CSR (rowptr, colw) and the sorted keys.
 int build_grouped(mcd_op *op, hipStream_t s) {
@@ -367,10 +412,16 @@ int build_grouped(mcd_op *op, hipStream_t s) {
     uint64_t *d_gtab = nullptr;
     uint32_t *d_gw = nullptr;
     auto fail_hip = [&](hipError_t e, const char *what) {
-        set_error("%s failed: %s", what, hipGetErrorString(e));
+        (void)hipStreamSynchronize(s);   // queued work may still read the pieces
         release();
         for (void *p : {(void *)d_gbs, (void *)d_goff, (void *)d_gtab, (void *)d_gw})
             if (p) (void)dfree(p, al);
+        if (e == hipErrorOutOfMemory) {   // no room in the workspace: no layout
+            std::lock_guard<std::mutex> lock(al.ws->mu);
+            al.ws->a.clear_need();
+            return MCD_OK;
+        }
+        set_error("%s failed: %s", what, hipGetErrorString(e));
         return MCD_E_HIP;
     };
 #define GK(expr)                                              \

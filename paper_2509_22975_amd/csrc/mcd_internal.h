@@ -11,7 +11,10 @@
 
 #include <string.h>
 
+#include <mutex>
+
 #include "mcd.h"
+#include "mcd_wsalloc.h"
 
 namespace mcd {
 
@@ -21,9 +24,14 @@ void set_error(const char *fmt, ...);
     do {                                                                               \
         hipError_t e_ = (expr);                                                        \
         if (e_ != hipSuccess) {                                                        \
-            ::mcd::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
-                             __FILE__, __LINE__);                                      \
-            return MCD_E_HIP;                                                          \
+            const int st_ = ::mcd::hip_status(e_);                                     \
+            if (st_ == MCD_E_WORKSPACE)                                                \
+                ::mcd::set_error("%s: workspace too small (%s:%d)", #expr, __FILE__,   \
+                                 __LINE__);                                            \
+            else                                                                       \
+                ::mcd::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),\
+                                 __FILE__, __LINE__);                                  \
+            return st_;                                                                \
         }                                                                              \
     } while (0)
 
@@ -93,72 +101,42 @@ struct DevModel {
     DevBond bonds[MCD_MAX_BONDS];
 };
 
-// Device buffers of the library.  Stream-ordered (async): memory comes from
-// the device's stream-ordered pool (hipMallocAsync) and goes back on the same
-// stream (hipFreeAsync), so solves running concurrently on different streams
-// never synchronise the whole device when they release memory; otherwise
-// hipMalloc / hipFree.
-// Process-wide cache of device memory chunks (mcd_common.hip).  A released
-// chunk keeps an event recorded on the releasing stream; the next stream to
-// take it waits on that event, so reuse is stream-ordered without a device
-// synchronisation.  Chunks are sized in multiples of 64 MB; at most
-// kChunkCacheBytes stay cached (beyond that a released chunk is freed).
-constexpr size_t kChunkCacheBytes = size_t(8) << 30;
-hipError_t chunk_acquire(size_t bytes, hipStream_t s, void **out, size_t *got);
-void chunk_release(void *p, size_t bytes, hipStream_t s);
+// Device memory.  The library allocates none of its own: every buffer is a
+// piece of a caller-owned workspace (mcd_ws, a device buffer the caller hands
+// over, e.g. a torch tensor), taken and released through Alloc.  Pieces are
+// 256-byte aligned.  Work that uses a workspace is enqueued on one stream (the
+// caller's), so a piece released on the host and taken again by a later call
+// is only touched by kernels enqueued after the earlier ones: reuse is ordered
+// by the stream, with no events and no device synchronisation.
+struct Alloc {
+    mcd_ws *ws = nullptr;
+};
+hipError_t dmalloc(void **p, size_t bytes, const Alloc &a);   // hipErrorOutOfMemory: ws full
+hipError_t dfree(void *p, const Alloc &a);                    // NULL is ignored
+// MCD status of a failed HIP call or allocation: MCD_E_WORKSPACE when the
+// workspace ran out (dmalloc's hipErrorOutOfMemory), else MCD_E_HIP.
+int hip_status(hipError_t e);
 
-// Bump allocator over cached chunks: every buffer of a short-lived solve (a
-// band run and its operator) comes from it and all go back together, with
-// no driver allocation or free per buffer (hipMallocAsync / hipFreeAsync
-// cost 0.1-1 ms of host time each here).  Pieces are 256-byte aligned;
-// freeing a piece does nothing.  One owner thread.
+// Pieces taken together and released together (reverse order of taking):
+// every buffer of a short-lived step (a band run and its operator) in one
+// place.  One owner thread.
 struct Arena {
-    hipStream_t s = nullptr;
-    std::vector<std::pair<char *, size_t>> chunks;
-    size_t used = 0;   // bytes taken from the last chunk
-    explicit Arena(hipStream_t st) : s(st) {}
+    Alloc al;
+    std::vector<void *> pieces;
+    explicit Arena(mcd_ws *ws) { al.ws = ws; }
     Arena(const Arena &) = delete;
     Arena &operator=(const Arena &) = delete;
     ~Arena() { release(); }
     hipError_t get(void **p, size_t bytes) {
-        bytes = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
-        if (chunks.empty() || used + bytes > chunks.back().second) {
-            void *c = nullptr;
-            size_t got = 0;
-            const hipError_t e = chunk_acquire(bytes, s, &c, &got);
-            if (e != hipSuccess) return e;
-            chunks.emplace_back((char *)c, got);
-            used = 0;
-        }
-        *p = chunks.back().first + used;
-        used += bytes;
-        return hipSuccess;
+        const hipError_t e = dmalloc(p, bytes, al);
+        if (e == hipSuccess) pieces.push_back(*p);
+        return e;
     }
     void release() {
-        for (auto &c : chunks) chunk_release(c.first, c.second, s);
-        chunks.clear();
-        used = 0;
+        for (auto it = pieces.rbegin(); it != pieces.rend(); ++it) (void)dfree(*it, al);
+        pieces.clear();
     }
 };
-struct Alloc {
-    hipStream_t s = nullptr;
-    bool async = false;
-    Arena *arena = nullptr;
-};
-inline hipError_t dmalloc(void **p, size_t bytes, const Alloc &a) {
-    if (a.arena) return a.arena->get(p, bytes);
-    return a.async ? hipMallocAsync(p, bytes, a.s) : hipMalloc(p, bytes);
-}
-inline hipError_t dfree(void *p, const Alloc &a) {
-    if (a.arena) return hipSuccess;
-    return a.async ? hipFreeAsync(p, a.s) : hipFree(p);
-}
-// Once per device: let the default stream-ordered memory pool keep up to
-// kPoolKeepBytes of freed memory instead of returning it to the driver at
-// every synchronisation, so the many short-lived buffers of the band runs
-// are reused without driver calls.
-constexpr uint64_t kPoolKeepBytes = uint64_t(8) << 30;
-void pool_keep_freed(int device);
 
 struct HashSlot {
     uint64_t key;
@@ -174,6 +152,15 @@ struct HostModel {
 int prepare_model(const mcd_model *m, HostModel *hm);
 
 }  // namespace mcd
+
+// A caller-owned workspace: the caller's device buffer [base, base + size)
+// and the host bookkeeping of the pieces taken from it.
+struct mcd_ws {
+    char *base;
+    mcd::WsAlloc a;
+    std::mutex mu;
+    mcd_ws(void *b, size_t bytes) : base((char *)b), a(bytes) {}
+};
 
 struct mcd_op {
     int device;
@@ -198,9 +185,6 @@ struct mcd_op {
     unsigned int *d_counter;   // last-block counters [8]
     double *d_scalars;         // [64]
     int64_t max_partials;
-    // grow-only solver workspace (Krylov store etc.), freed with the operator
-    void *ws;
-    size_t ws_bytes;
     // merge-path SpMV: chunk split points and carries
     int32_t kernel;            // KERNEL_STREAM or KERNEL_MERGE (one-vector CSR)
     int32_t merge_grid;        // persistent workgroups
@@ -216,7 +200,7 @@ struct mcd_op {
     int64_t *d_goff;                  // [g_nblocks + 1] first group of each block
     uint64_t *d_gtab;                 // [g_ngroups + 1] column | class << 32 | sign << 37
     uint32_t *d_gw;                   // [nnz] entry words in grouped order
-    mcd::Alloc alloc;                 // how the operator's buffers were allocated
+    mcd::Alloc alloc;                 // the workspace the operator's buffers come from
 };
 
 namespace mcd {
@@ -227,14 +211,16 @@ namespace mcd {
 // nullptr the scalar sum_r (sx x_r) y_r is written to *dot_out (device).
 int apply_f64_fused(const mcd_op *op, const double *x, double *y, const double *sx_dev,
                     int sx_mode, double *dot_out, hipStream_t s);
+// The same for a float32 or float64 vector (float accumulation for float32;
+// the scale and the dot are float64).
+template <typename T>
+int apply_fused(const mcd_op *op, const T *x, T *y, const double *sx_dev, int sx_mode,
+                double *dot_out, hipStream_t s);
 // y *= sx and optional dot as above (used after an on-the-fly apply).
-int scale_dot(const mcd_op *op, double *y, const double *x, const double *sx_dev, int sx_mode,
+template <typename T>
+int scale_dot(const mcd_op *op, T *y, const T *x, const double *sx_dev, int sx_mode,
               double *dot_out, hipStream_t s);
 int apply_any(const mcd_op *op, int dtype, int nvec, const void *x, void *y, hipStream_t s);
-
-// Solver workspace of at least `bytes` held by the operator (reallocated
-// only when it grows).  Not thread-safe per operator.
-int op_workspace(const mcd_op *op, size_t bytes, void **ptr);
 
 // Grouped one-vector layout (mcd_grouped.hip).  build_grouped leaves
 // g_nblocks = 0 when the basis does not fit the layout (short up-string
@@ -243,20 +229,20 @@ int op_workspace(const mcd_op *op, size_t bytes, void **ptr);
 // contract as the other one-vector kernels; partials per workgroup when
 // `partials` != nullptr, *grid = number of workgroups).
 int build_grouped(mcd_op *op, hipStream_t s);
+void grouped_plan(WsAlloc &w, int64_t n, int64_t nnz);
 template <typename T>
 int grouped_one(const mcd_op *op, bool xcd, const T *x, T *y, const double *sx_dev, int sx_mode,
                 double *partials, int64_t *grid, hipStream_t s);
 
 // Operator construction (mcd_op_create with tune = true); tune = false keeps
 // the default one-vector kernel (for operators used with block products).
-// async: buffers stream-ordered on `stream` (the operator must then only be
-// used on that stream; mcd_op_destroy releases them on it without a device
-// synchronisation).
-// arena: when given (async only), every buffer of the operator comes from it
-// and stays until the arena is released (after mcd_op_destroy).
+// Every buffer comes from `ws` and goes back to it in mcd_op_destroy.
 int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32_t storage,
-              int32_t validate, bool tune, void *stream, mcd_op **out, bool async = false,
-              Arena *arena = nullptr);
+              int32_t validate, bool tune, mcd_ws *ws, void *stream, mcd_op **out);
+// Workspace bytes op_create takes from an empty workspace (stages: 1 index,
+// 2 up to the nonzero count, 3 all but the grouped layout, 4 with the largest
+// grouped layout).
+size_t op_plan(int64_t n, bool csr, int64_t nnz, bool tune, bool validate, int stages);
 
 // Deterministic dot product a . b into *out_dev (mcd_lanczos.hip).
 int dev_dot(const mcd_op *op, const double *a, const double *b, int64_t n, double *out_dev,

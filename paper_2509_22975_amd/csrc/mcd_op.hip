@@ -7,8 +7,6 @@
 //   k_hash_insert   open-addressing hash key -> row (load <= 1/4)
 //   k_csr_count     kept hops per row (hop enumeration + lookup)
 //   k_csr_fill      packed words: column | class << col_bits | sign << 31
-//   k_csr_count_stage, k_csr_compact
-//                   the same CSR in one hash pass (words staged per row)
 //   k_block_max_all largest block nonzero count for every power-of-two block
 //   k_spmv_grouped  (mcd_grouped.hip) one vector, grouped entry order
 //   k_spmv_stream   one vector: a workgroup streams the nonzeros of a row
@@ -118,37 +116,6 @@ __global__ void k_csr_fill(int64_t n, const uint64_t *__restrict__ keys,
         const uint32_t neg = par ^ m->bonds[b].neg;
         colw[e++] = (uint32_t)c | (m->bonds[b].cls << m->col_bits) | (neg << 31);
     });
-}
-
-// Count and words in one hash pass (instead of k_csr_count + k_csr_fill):
-// word q of row r goes to stage[q * n + r] (stores coalesced across rows),
-// in the order k_csr_fill writes them; k_csr_compact moves them into place
-// once the row pointers are known.
-__global__ void k_csr_count_stage(int64_t n, const uint64_t *__restrict__ keys,
-                                  const DevModel *__restrict__ m, const HashSlot *__restrict__ h,
-                                  uint64_t hmask, int64_t *__restrict__ cnt,
-                                  uint32_t *__restrict__ stage) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r > n) return;
-    if (r == n) {
-        cnt[n] = 0;
-        return;
-    }
-    int64_t c = 0;
-    for_each_hop(keys[r], m, h, hmask, [&](int64_t col, int b, uint32_t par) {
-        const uint32_t neg = par ^ m->bonds[b].neg;
-        stage[c * n + r] = (uint32_t)col | (m->bonds[b].cls << m->col_bits) | (neg << 31);
-        c++;
-    });
-    cnt[r] = c;
-}
-
-__global__ void k_csr_compact(int64_t n, const uint32_t *__restrict__ stage,
-                              const int64_t *__restrict__ rowptr, uint32_t *__restrict__ colw) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    const int64_t e0 = rowptr[r], c = rowptr[r + 1] - e0;
-    for (int64_t q = 0; q < c; q++) colw[e0 + q] = stage[q * n + r];
 }
 
 // Largest nonzero count of a row block [b R, (b + 1) R) for every R = 2^k,
@@ -667,62 +634,71 @@ static double now_ms() {
         .count();
 }
 
-static int build_csr(mcd_op *op, hipStream_t s) {
+// Temporary bytes of the row-pointer scan (hipCUB) for n + 1 counts.
+static size_t scan_tmp_bytes(int64_t n) {
+    size_t b = 0;
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, b, (const int64_t *)nullptr,
+                                           (int64_t *)nullptr, n + 1, (hipStream_t)0);
+    return b;
+}
+
+static int64_t merge_chunks(int64_t n, int64_t nnz) {
+    return std::max<int64_t>(1, (kMergeRowCost * n + nnz + kMergeK - 1) / kMergeK);
+}
+
+// CSR stage 1: row pointers (kept) from per-row counts of the kept hops.
+static int csr_count(mcd_op *op, hipStream_t s) {
     const int64_t n = op->n;
     int64_t *cnt = nullptr;
-    MCD_HIP(dmalloc((void **)&op->d_rowptr, (n + 1) * sizeof(int64_t), op->alloc));
-    MCD_HIP(dmalloc((void **)&cnt, (n + 1) * sizeof(int64_t), op->alloc));
-    op->device_bytes += (n + 1) * sizeof(int64_t);
-    // One hash pass when the staging buffer (2 n_bonds words per row, the most
-    // a row can keep) is modest; else count, then fill.
-    const int64_t maxc = 2 * (int64_t)op->hm.dm.n_bonds;
-    size_t fr = 0, tot = 0;
-    MCD_HIP(hipMemGetInfo(&fr, &tot));
-    const double stage_bytes = (double)n * (double)maxc * sizeof(uint32_t);
-    uint32_t *stage = nullptr;
-    if (n > 0 && maxc > 0 && stage_bytes <= std::min(4e9, 0.25 * (double)fr))
-        MCD_HIP(dmalloc((void **)&stage, (size_t)stage_bytes, op->alloc));
-    if (stage)
-        hipLaunchKernelGGL(k_csr_count_stage, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, n,
-                           op->d_keys, op->d_model, op->d_hash, op->hash_mask, cnt, stage);
-    else
-        hipLaunchKernelGGL(k_csr_count, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, n,
-                           op->d_keys, op->d_model, op->d_hash, op->hash_mask, cnt);
-    MCD_HIP(hipGetLastError());
-    size_t tmp_bytes = 0;
-    MCD_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, op->d_rowptr, n + 1, s));
     void *tmp = nullptr;
-    MCD_HIP(dmalloc((void **)&tmp, tmp_bytes, op->alloc));
-    MCD_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, op->d_rowptr, n + 1, s));
+    MCD_HIP(dmalloc((void **)&op->d_rowptr, (n + 1) * sizeof(int64_t), op->alloc));
+    op->device_bytes += (n + 1) * sizeof(int64_t);
+    MCD_HIP(dmalloc((void **)&cnt, (n + 1) * sizeof(int64_t), op->alloc));
+    size_t tmp_bytes = scan_tmp_bytes(n);
+    const hipError_t et = dmalloc(&tmp, tmp_bytes, op->alloc);
+    if (et != hipSuccess) {
+        (void)dfree(cnt, op->alloc);
+        MCD_HIP(et);
+    }
+    hipLaunchKernelGGL(k_csr_count, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, n, op->d_keys,
+                       op->d_model, op->d_hash, op->hash_mask, cnt);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, op->d_rowptr, n + 1, s);
     int64_t nnz = 0;
-    MCD_HIP(hipMemcpyAsync(&nnz, op->d_rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    MCD_HIP(hipStreamSynchronize(s));
-    MCD_HIP(dfree(tmp, op->alloc));
-    MCD_HIP(dfree(cnt, op->alloc));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&nnz, op->d_rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)dfree(tmp, op->alloc);
+    (void)dfree(cnt, op->alloc);
+    MCD_HIP(e);
     op->nnz = nnz;
+    return MCD_OK;
+}
+
+// CSR stage 2: the packed words, the stream kernels' row blocks and the
+// merge-path split points.
+static int csr_fill(mcd_op *op, hipStream_t s) {
+    const int64_t n = op->n, nnz = op->nnz;
     MCD_HIP(dmalloc((void **)&op->d_colw, std::max<int64_t>(nnz, 1) * sizeof(uint32_t), op->alloc));
     op->device_bytes += nnz * sizeof(uint32_t);
-    if (stage) {
-        hipLaunchKernelGGL(k_csr_compact, dim3(grid_for(n, 256)), dim3(256), 0, s, n, stage,
-                           op->d_rowptr, op->d_colw);
-        MCD_HIP(hipGetLastError());
-        MCD_HIP(dfree(stage, op->alloc));
-    } else {
-        hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
-                           op->d_model, op->d_hash, op->hash_mask, op->d_rowptr, op->d_colw);
-        MCD_HIP(hipGetLastError());
-    }
+    hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
+                       op->d_model, op->d_hash, op->hash_mask, op->d_rowptr, op->d_colw);
+    MCD_HIP(hipGetLastError());
     // Largest power-of-two row block whose nonzeros fit the LDS product buffer
     // (one choice per buffer size of the stream kernels), all sizes in one pass.
     unsigned long long *d_max = nullptr;
     MCD_HIP(dmalloc((void **)&d_max, 9 * sizeof(unsigned long long), op->alloc));
-    MCD_HIP(hipMemsetAsync(d_max, 0, 9 * sizeof(unsigned long long), s));
-    hipLaunchKernelGGL(k_block_max_all, dim3(512), dim3(256), 0, s, n, op->d_rowptr, d_max);
-    MCD_HIP(hipGetLastError());
     unsigned long long mx[9] = {};
-    MCD_HIP(hipMemcpyAsync(mx, d_max, sizeof(mx), hipMemcpyDeviceToHost, s));
-    MCD_HIP(hipStreamSynchronize(s));
-    MCD_HIP(dfree(d_max, op->alloc));
+    hipError_t e = hipMemsetAsync(d_max, 0, 9 * sizeof(unsigned long long), s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_block_max_all, dim3(512), dim3(256), 0, s, n, op->d_rowptr, d_max);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(mx, d_max, sizeof(mx), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)dfree(d_max, op->alloc);
+    MCD_HIP(e);
     op->rows_per_block = 1;
     op->rows_per_block_s = 1;
     for (int k = 8; k >= 0; k--)
@@ -738,8 +714,7 @@ static int build_csr(mcd_op *op, hipStream_t s) {
     // row-parallel products: words per chunk from the mean row length
     op->group_chunk = (nnz < 4 * n) ? 4 : (nnz < 10 * n) ? 8 : 16;
     // merge-path split points
-    op->nchunks = (kMergeRowCost * n + nnz + kMergeK - 1) / kMergeK;
-    if (op->nchunks < 1) op->nchunks = 1;
+    op->nchunks = merge_chunks(n, nnz);
     MCD_HIP(dmalloc((void **)&op->d_split_i, (op->nchunks + 1) * sizeof(int64_t), op->alloc));
     MCD_HIP(dmalloc((void **)&op->d_split_j, (op->nchunks + 1) * sizeof(int64_t), op->alloc));
     MCD_HIP(dmalloc((void **)&op->d_carry, op->nchunks * sizeof(double), op->alloc));
@@ -849,11 +824,36 @@ static int tune_kernel(mcd_op *op, hipStream_t s) {
     if (op->n == 0) return MCD_OK;
     double *x = nullptr, *y = nullptr;
     MCD_HIP(dmalloc((void **)&x, op->n * sizeof(double), op->alloc));
-    MCD_HIP(dmalloc((void **)&y, op->n * sizeof(double), op->alloc));
-    MCD_HIP(hipMemcpyAsync(x, op->d_diag, op->n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    hipEvent_t a, b;
-    MCD_HIP(hipEventCreate(&a));
-    MCD_HIP(hipEventCreate(&b));
+    const hipError_t ey = dmalloc((void **)&y, op->n * sizeof(double), op->alloc);
+    if (ey != hipSuccess) {
+        (void)dfree(x, op->alloc);
+        MCD_HIP(ey);
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    auto done = [&](int rc) {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        (void)hipStreamSynchronize(s);   // the timed products read x and y
+        (void)dfree(x, op->alloc);
+        (void)dfree(y, op->alloc);
+        return rc;
+    };
+#define TK(expr)                                           \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) {                            \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_)); \
+            return done(MCD_E_HIP);                        \
+        }                                                  \
+    } while (0)
+#define TT(expr)                  \
+    do {                          \
+        int rc_ = (expr);         \
+        if (rc_ < 0) return done(rc_); \
+    } while (0)
+    TK(hipMemcpyAsync(x, op->d_diag, op->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    TK(hipEventCreate(&a));
+    TK(hipEventCreate(&b));
     double best = 1e300;
     int pick = KERNEL_STREAM;
     for (int k : {KERNEL_STREAM, KERNEL_STREAM_XCD, KERNEL_MERGE, KERNEL_ROWCHUNK,
@@ -861,20 +861,22 @@ static int tune_kernel(mcd_op *op, hipStream_t s) {
         op->tune_ms[k] = 0.0;
         if ((k == KERNEL_GROUPED || k == KERNEL_GROUPED_XCD) && op->g_nblocks == 0) continue;
         op->kernel = k;
-        MCD_TRY(csr_one<double>(op, x, y, nullptr, 0, nullptr, s));
-        MCD_HIP(hipEventRecord(a, s));
+        TT(csr_one<double>(op, x, y, nullptr, 0, nullptr, s));
+        TK(hipEventRecord(a, s));
         const int reps = 5;
-        for (int i = 0; i < reps; i++) MCD_TRY(csr_one<double>(op, x, y, nullptr, 0, nullptr, s));
-        MCD_HIP(hipEventRecord(b, s));
-        MCD_HIP(hipEventSynchronize(b));
+        for (int i = 0; i < reps; i++) TT(csr_one<double>(op, x, y, nullptr, 0, nullptr, s));
+        TK(hipEventRecord(b, s));
+        TK(hipEventSynchronize(b));
         float ms = 0.f;
-        MCD_HIP(hipEventElapsedTime(&ms, a, b));
+        TK(hipEventElapsedTime(&ms, a, b));
         op->tune_ms[k] = ms / reps;
         if (ms < best) {
             best = ms;
             pick = k;
         }
     }
+#undef TK
+#undef TT
     // Between the plain and the XCD-major order of the same kernel, keep the
     // XCD-major one unless the plain one is clearly faster: it moves less
     // data over the fabric (each L2 serves its own slice of x).
@@ -887,11 +889,7 @@ static int tune_kernel(mcd_op *op, hipStream_t s) {
         op->tune_ms[KERNEL_GROUPED_XCD] <= 1.03 * op->tune_ms[KERNEL_GROUPED])
         pick = KERNEL_GROUPED_XCD;
     op->kernel = pick;
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    MCD_HIP(dfree(x, op->alloc));
-    MCD_HIP(dfree(y, op->alloc));
-    return MCD_OK;
+    return done(MCD_OK);
 }
 
 // Block CSR product with 16-byte gathers (k_block_csr_v), when a row of the
@@ -976,19 +974,6 @@ static int launch_apply(const mcd_op *op, int nvec, const T *x, T *y, hipStream_
     return MCD_OK;
 }
 
-int op_workspace(const mcd_op *op_c, size_t bytes, void **ptr) {
-    mcd_op *op = const_cast<mcd_op *>(op_c);
-    if (op->ws_bytes < bytes) {
-        if (op->ws) MCD_HIP(dfree(op->ws, op->alloc));
-        op->ws = nullptr;
-        op->ws_bytes = 0;
-        MCD_HIP(dmalloc((void **)&op->ws, bytes, op->alloc));
-        op->ws_bytes = bytes;
-    }
-    *ptr = op->ws;
-    return MCD_OK;
-}
-
 int apply_any(const mcd_op *op, int dtype, int nvec, const void *x, void *y, hipStream_t s) {
     if (dtype == MCD_F64) return launch_apply<double>(op, nvec, (const double *)x, (double *)y, s);
     if (dtype == MCD_F32) return launch_apply<float>(op, nvec, (const float *)x, (float *)y, s);
@@ -996,33 +981,152 @@ int apply_any(const mcd_op *op, int dtype, int nvec, const void *x, void *y, hip
     return MCD_E_INVALID;
 }
 
+template <typename T>
+int apply_fused(const mcd_op *op, const T *x, T *y, const double *sx_dev, int sx_mode,
+                double *dot_out, hipStream_t s) {
+    if (op->storage == MCD_STORAGE_CSR) return csr_one<T>(op, x, y, sx_dev, sx_mode, dot_out, s);
+    // On-the-fly: product, then a separate fused scale + dot.
+    MCD_TRY(launch_apply<T>(op, 1, x, y, s));
+    if (sx_dev != nullptr || dot_out != nullptr)
+        MCD_TRY(scale_dot<T>(op, y, x, sx_dev, sx_mode, dot_out, s));
+    return MCD_OK;
+}
+template int apply_fused<double>(const mcd_op *, const double *, double *, const double *, int,
+                                 double *, hipStream_t);
+template int apply_fused<float>(const mcd_op *, const float *, float *, const double *, int,
+                                double *, hipStream_t);
+
 int apply_f64_fused(const mcd_op *op, const double *x, double *y, const double *sx_dev,
                     int sx_mode, double *dot_out, hipStream_t s) {
-    if (op->storage == MCD_STORAGE_CSR) return csr_one<double>(op, x, y, sx_dev, sx_mode, dot_out, s);
-    // On-the-fly: product, then a separate fused scale + dot.
-    MCD_TRY(launch_apply<double>(op, 1, x, y, s));
-    if (sx_dev != nullptr || dot_out != nullptr)
-        MCD_TRY(scale_dot(op, y, x, sx_dev, sx_mode, dot_out, s));
+    return apply_fused<double>(op, x, y, sx_dev, sx_mode, dot_out, s);
+}
+
+static uint64_t hash_capacity(int64_t n) {
+    const int64_t nn = std::max<int64_t>(n, 1);
+    uint64_t cap = 16;
+    while (cap < (uint64_t)(4 * nn)) cap <<= 1;   // load factor <= 1/4
+    return cap;
+}
+static int64_t partials_capacity(int64_t n) { return std::max<int64_t>(n + 1024, 4096); }
+
+// Stage "index": model, keys, diagonal, hash index (key -> row), reduction
+// scratch; keys validated on request.
+static int op_index(mcd_op *op, const uint64_t *keys_dev, int32_t validate, hipStream_t s) {
+    const int64_t n = op->n, nn = std::max<int64_t>(n, 1);
+    MCD_HIP(dmalloc((void **)&op->d_model, sizeof(DevModel), op->alloc));
+    MCD_HIP(hipMemcpyAsync(op->d_model, &op->hm.dm, sizeof(DevModel), hipMemcpyHostToDevice, s));
+    MCD_HIP(dmalloc((void **)&op->d_keys, nn * sizeof(uint64_t), op->alloc));
+    if (n)
+        MCD_HIP(hipMemcpyAsync(op->d_keys, keys_dev, n * sizeof(uint64_t), hipMemcpyDeviceToDevice,
+                               s));
+    MCD_HIP(dmalloc((void **)&op->d_diag, nn * sizeof(double), op->alloc));
+    op->device_bytes = sizeof(DevModel) + nn * 16;
+    if (validate && n) {
+        int *bad = nullptr, hbad = 0;
+        MCD_HIP(dmalloc((void **)&bad, sizeof(int), op->alloc));
+        hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_validate, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
+                               op->hm.dm.n_orb, bad);
+            e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)dfree(bad, op->alloc);
+        MCD_HIP(e);
+        MCD_REQUIRE(!hbad, MCD_E_SECTOR, "keys are not sorted/unique or exceed n_orb bits");
+    }
+    if (n) {
+        hipLaunchKernelGGL(k_diag, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
+                           op->d_model, op->d_diag);
+        MCD_HIP(hipGetLastError());
+    }
+    const uint64_t cap = hash_capacity(n);
+    op->hash_mask = cap - 1;
+    MCD_HIP(dmalloc((void **)&op->d_hash, cap * sizeof(HashSlot), op->alloc));
+    MCD_HIP(hipMemsetAsync(op->d_hash, 0xff, cap * sizeof(HashSlot), s));
+    op->device_bytes += cap * sizeof(HashSlot);
+    if (n) {
+        hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
+                           op->d_hash, op->hash_mask);
+        MCD_HIP(hipGetLastError());
+    }
+    op->max_partials = partials_capacity(n);
+    MCD_HIP(dmalloc((void **)&op->d_partials, op->max_partials * sizeof(double), op->alloc));
+    MCD_HIP(dmalloc((void **)&op->d_counter, 8 * sizeof(unsigned int), op->alloc));
+    MCD_HIP(hipMemsetAsync(op->d_counter, 0, 8 * sizeof(unsigned int), s));
+    MCD_HIP(dmalloc((void **)&op->d_scalars, 64 * sizeof(double), op->alloc));
+    op->device_bytes += op->max_partials * sizeof(double);
     return MCD_OK;
+}
+
+// The CSR pieces of stage "fill" (for the fallback of AUTO to on-the-fly).
+static void release_csr(mcd_op *op) {
+    for (void **p : {(void **)&op->d_rowptr, (void **)&op->d_colw, (void **)&op->d_split_i,
+                     (void **)&op->d_split_j, (void **)&op->d_carry, (void **)&op->d_carry_row}) {
+        (void)dfree(*p, op->alloc);
+        *p = nullptr;
+    }
+}
+
+// Bytes op_create takes from an empty workspace: its sequence of takes and
+// releases replayed on the host bookkeeping (stage 1: index only, 2: up to
+// the nonzero count, 3: everything but the optional grouped layout, 4: with
+// a grouped layout of the largest possible size).
+size_t op_plan(int64_t n, bool csr, int64_t nnz, bool tune, bool validate, int stages) {
+    WsAlloc w(size_t(1) << 62);
+    const int64_t nn = std::max<int64_t>(n, 1);
+    std::vector<size_t> keep;
+    auto take = [&](size_t b) { size_t o = w.alloc(b); keep.push_back(o); return o; };
+    auto temp = [&](size_t b) { return w.alloc(b); };
+    take(sizeof(DevModel));
+    take(nn * 8);
+    take(nn * 8);
+    if (validate && n) w.release(temp(sizeof(int)));
+    take(hash_capacity(n) * sizeof(HashSlot));
+    take(partials_capacity(n) * 8);
+    take(8 * sizeof(unsigned int));
+    take(64 * 8);
+    if (stages >= 2 && csr) {
+        take((n + 1) * 8);
+        const size_t c = temp((n + 1) * 8), t = temp(scan_tmp_bytes(n));
+        w.release(t);
+        w.release(c);
+    }
+    if (stages >= 3 && csr) {
+        take(std::max<int64_t>(nnz, 1) * 4);
+        w.release(temp(9 * 8));
+        const int64_t nch = merge_chunks(n, nnz);
+        take((nch + 1) * 8);
+        take((nch + 1) * 8);
+        take(nch * 8);
+        take(nch * 8);
+        if (stages >= 4 && tune) grouped_plan(w, n, nnz);
+        if (tune && n) {
+            const size_t x = temp(n * 8), y = temp(n * 8);
+            w.release(x);
+            w.release(y);
+        }
+    }
+    return w.extent();
 }
 
 // Operator construction; `tune` times the one-vector kernels on the matrix
 // (operators that only ever see block products skip it and keep the
-// XCD-major stream kernel for the rare one-vector product).
+// XCD-major stream kernel for the rare one-vector product) and builds the
+// grouped layout when the workspace has room for it.
 int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32_t storage,
-              int32_t validate, bool tune, void *stream, mcd_op **out, bool async, Arena *arena) {
+              int32_t validate, bool tune, mcd_ws *ws, void *stream, mcd_op **out) {
     MCD_REQUIRE(out != nullptr, MCD_E_INVALID, "out is NULL");
     *out = nullptr;
     MCD_REQUIRE(n >= 0 && (n == 0 || keys_dev != nullptr), MCD_E_INVALID, "bad keys/n");
     MCD_REQUIRE(storage >= MCD_STORAGE_AUTO && storage <= MCD_STORAGE_CSR, MCD_E_INVALID,
                 "storage %d unknown", storage);
+    MCD_REQUIRE(ws != nullptr, MCD_E_INVALID, "workspace is NULL");
     hipStream_t s = (hipStream_t)stream;
     const double t0 = now_ms();
     mcd_op *op = new mcd_op();
     memset(op, 0, sizeof(*op));
-    op->alloc.s = s;
-    op->alloc.async = async;
-    op->alloc.arena = async ? arena : nullptr;
+    op->alloc.ws = ws;
     auto fail = [&](int rc) {
         mcd_op_destroy(op);
         return rc;
@@ -1030,63 +1134,12 @@ int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32
     int rc = prepare_model(model, &op->hm);
     if (rc < 0) return fail(rc);
     if (hipGetDevice(&op->device) != hipSuccess) return fail(MCD_E_HIP);
-    if (async) pool_keep_freed(op->device);
     op->n = n;
     op->nnz = -1;
-#define CK(expr)                                                                             \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
-        if (e_ != hipSuccess) {                                                              \
-            set_error("%s failed: %s", #expr, hipGetErrorString(e_));                        \
-            return fail(MCD_E_HIP);                                                          \
-        }                                                                                    \
-    } while (0)
-    const int64_t nn = std::max<int64_t>(n, 1);
-    CK(dmalloc((void **)&op->d_model, sizeof(DevModel), op->alloc));
-    CK(hipMemcpyAsync(op->d_model, &op->hm.dm, sizeof(DevModel), hipMemcpyHostToDevice, s));
-    CK(dmalloc((void **)&op->d_keys, nn * sizeof(uint64_t), op->alloc));
-    if (n) CK(hipMemcpyAsync(op->d_keys, keys_dev, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-    CK(dmalloc((void **)&op->d_diag, nn * sizeof(double), op->alloc));
-    op->device_bytes = sizeof(DevModel) + nn * 16;
-    if (validate && n) {
-        int *bad = nullptr, hbad = 0;
-        CK(dmalloc((void **)&bad, sizeof(int), op->alloc));
-        CK(hipMemsetAsync(bad, 0, sizeof(int), s));
-        hipLaunchKernelGGL(k_validate, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
-                           op->hm.dm.n_orb, bad);
-        CK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
-        CK(hipStreamSynchronize(s));
-        CK(dfree(bad, op->alloc));
-        if (hbad) {
-            set_error("keys are not sorted/unique or exceed n_orb bits");
-            return fail(MCD_E_SECTOR);
-        }
-    }
-    if (n) {
-        hipLaunchKernelGGL(k_diag, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
-                           op->d_model, op->d_diag);
-        CK(hipGetLastError());
-    }
-    // Hash index, load factor <= 1/4.
-    uint64_t cap = 16;
-    while (cap < (uint64_t)(4 * nn)) cap <<= 1;
-    op->hash_mask = cap - 1;
-    CK(dmalloc((void **)&op->d_hash, cap * sizeof(HashSlot), op->alloc));
-    CK(hipMemsetAsync(op->d_hash, 0xff, cap * sizeof(HashSlot), s));
-    op->device_bytes += cap * sizeof(HashSlot);
-    if (n) {
-        hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
-                           op->d_hash, op->hash_mask);
-        CK(hipGetLastError());
-    }
-    // Reduction scratch.
-    op->max_partials = std::max<int64_t>(grid_for(n, 1) + 1024, 4096);
-    CK(dmalloc((void **)&op->d_partials, op->max_partials * sizeof(double), op->alloc));
-    CK(dmalloc((void **)&op->d_counter, 8 * sizeof(unsigned int), op->alloc));
-    CK(hipMemsetAsync(op->d_counter, 0, 8 * sizeof(unsigned int), s));
-    CK(dmalloc((void **)&op->d_scalars, 64 * sizeof(double), op->alloc));
-    op->device_bytes += op->max_partials * sizeof(double);
-    // Storage choice.
+    rc = op_index(op, keys_dev, validate, s);
+    if (rc < 0) return fail(rc);
+    // Storage choice: AUTO takes the CSR when the format fits and the
+    // workspace holds it, else recomputes the elements at every product.
     const bool fmt_ok = n <= (int64_t(1) << op->hm.dm.col_bits) && op->hm.ok_classes;
     int st = storage;
     if (st == MCD_STORAGE_CSR && !fmt_ok) {
@@ -1094,30 +1147,37 @@ int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32
                   "(n = %lld)", op->hm.dm.col_bits, op->hm.dm.n_classes, (long long)n);
         return fail(MCD_E_CAPACITY);
     }
-    if (st == MCD_STORAGE_AUTO) {
-        size_t fr = 0, tot = 0;
-        CK(hipMemGetInfo(&fr, &tot));
-        // Upper bound of the CSR: every candidate hop kept.
-        const double est = (double)n * (8.0 + 4.0 * 2.0 * op->hm.dm.n_bonds);
-        st = (fmt_ok && est < 0.5 * (double)fr) ? MCD_STORAGE_CSR : MCD_STORAGE_ON_THE_FLY;
-    }
-    op->storage = st;
+    if (st == MCD_STORAGE_AUTO) st = fmt_ok ? MCD_STORAGE_CSR : MCD_STORAGE_ON_THE_FLY;
     op->rows_per_block = 256;
     op->rows_per_block_s = 256;
     op->group_chunk = 16;
     op->kernel = KERNEL_STREAM_XCD;
     if (st == MCD_STORAGE_CSR) {
-        rc = build_csr(op, s);
-        if (rc < 0) return fail(rc);
-        if (tune) {
-            rc = build_grouped(op, s);
-            if (rc < 0) return fail(rc);
-            rc = tune_kernel(op, s);
-            if (rc < 0) return fail(rc);
+        rc = csr_count(op, s);
+        if (rc >= 0) rc = csr_fill(op, s);
+        if (rc == MCD_E_WORKSPACE && storage == MCD_STORAGE_AUTO) {
+            // no room for the CSR: elements on the fly instead
+            (void)hipStreamSynchronize(s);
+            release_csr(op);
+            op->nnz = -1;
+            op->device_bytes = sizeof(DevModel) + std::max<int64_t>(n, 1) * 16 +
+                               hash_capacity(n) * sizeof(HashSlot) + op->max_partials * 8;
+            {
+                std::lock_guard<std::mutex> lock(ws->mu);
+                ws->a.clear_need();
+            }
+            st = MCD_STORAGE_ON_THE_FLY;
+            rc = MCD_OK;
         }
+        if (rc < 0) return fail(rc);
     }
-    CK(hipStreamSynchronize(s));
-#undef CK
+    op->storage = st;
+    if (st == MCD_STORAGE_CSR && tune) {
+        rc = build_grouped(op, s);   // skipped when the workspace has no room
+        if (rc >= 0) rc = tune_kernel(op, s);
+        if (rc < 0) return fail(rc);
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(MCD_E_HIP);
     op->build_ms = now_ms() - t0;
     *out = op;
     return MCD_OK;
@@ -1128,26 +1188,67 @@ int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32
 using namespace mcd;
 
 extern "C" int mcd_op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
-                             int32_t storage, int32_t validate, void *stream, mcd_op **out) {
-    return op_create(model, keys_dev, n, storage, validate, true, stream, out);
+                             int32_t storage, int32_t validate, mcd_ws *ws, void *stream,
+                             mcd_op **out) {
+    return op_create(model, keys_dev, n, storage, validate, true, ws, stream, out);
+}
+
+extern "C" int mcd_op_workspace_size(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
+                                     int32_t storage, mcd_ws *ws, void *stream, size_t *bytes,
+                                     size_t *bytes_grouped) {
+    MCD_REQUIRE(bytes != nullptr, MCD_E_INVALID, "bytes is NULL");
+    MCD_REQUIRE(n >= 0 && (n == 0 || keys_dev != nullptr), MCD_E_INVALID, "bad keys/n");
+    MCD_REQUIRE(storage >= MCD_STORAGE_AUTO && storage <= MCD_STORAGE_CSR, MCD_E_INVALID,
+                "storage %d unknown", storage);
+    HostModel hm;
+    MCD_TRY(prepare_model(model, &hm));
+    const bool fmt_ok = n <= (int64_t(1) << hm.dm.col_bits) && hm.ok_classes;
+    MCD_REQUIRE(storage != MCD_STORAGE_CSR || fmt_ok, MCD_E_CAPACITY,
+                "packed CSR needs n <= 2^%u and <= 32 distinct |t|", hm.dm.col_bits);
+    if (storage == MCD_STORAGE_ON_THE_FLY || !fmt_ok) {
+        *bytes = op_plan(n, false, 0, false, true, 3);
+        if (bytes_grouped) *bytes_grouped = *bytes;
+        return MCD_OK;
+    }
+    // The CSR size needs the nonzero count: index and count in the caller's
+    // probe workspace (its size is the answer when ws is NULL or too small).
+    const size_t probe = op_plan(n, true, 0, false, true, 2);
+    if (ws == nullptr || ws->a.size() < probe) {
+        *bytes = probe;
+        if (bytes_grouped) *bytes_grouped = probe;
+        set_error("counting the nonzeros needs a probe workspace of %zu bytes", probe);
+        return MCD_E_WORKSPACE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    mcd_op *op = new mcd_op();
+    memset(op, 0, sizeof(*op));
+    op->alloc.ws = ws;
+    op->hm = hm;
+    op->n = n;
+    int rc = hipGetDevice(&op->device) == hipSuccess ? MCD_OK : MCD_E_HIP;
+    if (rc >= 0) rc = op_index(op, keys_dev, 0, s);
+    if (rc >= 0) rc = csr_count(op, s);
+    const int64_t nnz = op->nnz;
+    (void)hipStreamSynchronize(s);
+    mcd_op_destroy(op);
+    MCD_TRY(rc);
+    *bytes = op_plan(n, true, nnz, true, true, 3);
+    if (bytes_grouped) *bytes_grouped = std::max(*bytes, op_plan(n, true, nnz, true, true, 4));
+    return MCD_OK;
 }
 
 extern "C" void mcd_op_destroy(mcd_op *op) {
     if (!op) return;
-    int cur = 0;
-    (void)hipGetDevice(&cur);
-    (void)hipSetDevice(op->device);
-    // Stream-ordered buffers go back on their stream (after the work queued
-    // there); others wait for the device before hipFree.
-    if (!op->alloc.async) (void)hipDeviceSynchronize();
+    // Pieces go back to the caller's workspace; work still queued on the
+    // caller's stream that reads them runs before any later use of the
+    // workspace on that stream.
     for (void *p : {(void *)op->d_model, (void *)op->d_keys, (void *)op->d_diag,
                     (void *)op->d_hash, (void *)op->d_rowptr, (void *)op->d_colw,
                     (void *)op->d_partials, (void *)op->d_counter, (void *)op->d_scalars,
-                    op->ws, (void *)op->d_split_i, (void *)op->d_split_j, (void *)op->d_carry,
+                    (void *)op->d_split_i, (void *)op->d_split_j, (void *)op->d_carry,
                     (void *)op->d_carry_row, (void *)op->d_gbs, (void *)op->d_goff,
                     (void *)op->d_gtab, (void *)op->d_gw})
         if (p) (void)dfree(p, op->alloc);
-    (void)hipSetDevice(cur);
     delete op;
 }
 
@@ -1197,7 +1298,7 @@ extern "C" int mcd_hamiltonian_diagonal(const mcd_op *op, double *diag_dev, void
 extern "C" int mcd_hamiltonian_connectivity(const mcd_op *op, int64_t row0, int64_t row1,
                                             int64_t *rows_dev, int64_t *cols_dev,
                                             double *vals_dev, int64_t cap, int64_t *count_out,
-                                            void *stream) {
+                                            mcd_ws *ws, void *stream) {
     MCD_REQUIRE(op && count_out, MCD_E_INVALID, "op or count_out is NULL");
     MCD_REQUIRE(0 <= row0 && row0 <= row1 && row1 <= op->n, MCD_E_INVALID,
                 "row range [%lld, %lld) outside [0, %lld)", (long long)row0, (long long)row1,
@@ -1206,8 +1307,9 @@ extern "C" int mcd_hamiltonian_connectivity(const mcd_op *op, int64_t row0, int6
     const int64_t m = row1 - row0;
     *count_out = 0;
     if (m == 0) return MCD_OK;
+    const Alloc al{ws};
     int64_t *cnt = nullptr;
-    MCD_HIP(hipMalloc(&cnt, m * sizeof(int64_t)));
+    MCD_HIP(dmalloc((void **)&cnt, m * sizeof(int64_t), al));
     hipLaunchKernelGGL(k_conn_count, dim3(grid_for(m, 256)), dim3(256), 0, s, row0, row1,
                        op->d_keys, op->d_model, op->d_hash, op->hash_mask, cnt);
     std::vector<int64_t> h(m);
@@ -1221,17 +1323,21 @@ extern "C" int mcd_hamiltonian_connectivity(const mcd_op *op, int64_t row0, int6
     }
     *count_out = tot;
     if (tot > cap) {
-        (void)hipFree(cnt);
+        (void)dfree(cnt, al);
         set_error("connectivity needs %lld entries, cap is %lld", (long long)tot, (long long)cap);
         return MCD_E_CAPACITY;
     }
-    MCD_REQUIRE(tot == 0 || (rows_dev && cols_dev && vals_dev), MCD_E_INVALID, "outputs NULL");
+    if (tot > 0 && !(rows_dev && cols_dev && vals_dev)) {
+        (void)dfree(cnt, al);
+        set_error("outputs NULL");
+        return MCD_E_INVALID;
+    }
     MCD_HIP(hipMemcpyAsync(cnt, h.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_conn_fill, dim3(grid_for(m, 256)), dim3(256), 0, s, row0, row1,
                        op->d_keys, op->d_model, op->d_hash, op->hash_mask, cnt, rows_dev,
                        cols_dev, vals_dev);
     MCD_HIP(hipGetLastError());
     MCD_HIP(hipStreamSynchronize(s));
-    MCD_HIP(hipFree(cnt));
+    MCD_HIP(dfree(cnt, al));
     return MCD_OK;
 }

@@ -56,7 +56,7 @@ def test_batch_single_instance_and_step_cap():
 
 
 def test_batch_green_equals_single_and_oracle():
-    """mcd_batch_band_green on several instances (3 streams) returns exactly
+    """mcd_batch_band_green on several instances (all runs in lockstep) returns exactly
     what mcd_band_lanczos_green returns per instance; one instance is also
     checked against the oracle (same Krylov space, float64)."""
     torch, mcd = require_gpu()
@@ -76,7 +76,7 @@ def test_batch_green_equals_single_and_oracle():
         e0s.append(e0)
     for prec, reorth in (("f64", 2), ("f32", 0)):
         Gb, info = mcd.batch_band_green([m for m, _ in inst], kds, psis, e0s, orbs, spins, om,
-                                        n_streams=3, max_blocks=12, precision=prec,
+                                        max_blocks=12, precision=prec,
                                         reorth=reorth)
         assert info.krylov_dim > 0
         for i, (m, keys) in enumerate(inst):
@@ -93,4 +93,4 @@ def test_batch_green_equals_single_and_oracle():
     # an invalid selection for one instance is rejected before any work
     bad = [m for m, _ in inst]
     with pytest.raises(mcd.McdError):
-        mcd.batch_band_green(bad, kds, psis, e0s, [0, 40], [0, 0], om, n_streams=2)
+        mcd.batch_band_green(bad, kds, psis, e0s, [0, 40], [0, 0], om)
