@@ -303,6 +303,7 @@ int mcd_hamiltonian_contract(const mcd_op *op, const mcd_model *model, const dou
                              const double *b_dev, double *d_t, double *d_U, double *d_eps,
                              mcd_ws *ws, void *stream);
 
+
 /* ---------------------------------------------------------------------------
  * mcd_lanczos_ground -- lowest eigenpair of H~ by Lanczos (App. Lanczos,
  * Eqs. next_vector / an_bn; ground state rebuilt by Eq. change_basis).

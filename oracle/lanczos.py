@@ -58,11 +58,17 @@ def _lowest(alpha, beta):
 
 
 def lanczos_ground(H, phi0: np.ndarray, tol: float = 1e-12, max_iter: int = 400,
-                   reorth: bool = True, min_iter: int = 1):
+                   reorth: bool = True, min_iter: int = 1, keep_vectors: bool = True):
     """Lowest eigenpair of the symmetric operator H (matrix or callable).
 
-    Returns dict(e0, psi0, alpha, beta, iters, residual).
+    Returns dict(e0, psi0, alpha, beta, iters, residual).  keep_vectors=False
+    (no reorthogonalisation only) keeps just the last two Krylov vectors, the
+    recurrence unchanged, and returns psi0 = None (Eq. change_basis can then
+    be taken by ``recompute_ground_state``): for bases whose Krylov store
+    would not fit in host memory.
     """
+    if not keep_vectors and reorth:
+        raise ValueError("full reorthogonalisation needs the stored vectors")
     mv = H if callable(H) else (lambda x: H @ x)
     n = len(phi0)
     v = phi0 / np.linalg.norm(phi0)
@@ -90,10 +96,14 @@ def lanczos_ground(H, phi0: np.ndarray, tol: float = 1e-12, max_iter: int = 400,
             break
         beta.append(b)
         v_prev, v = v, w / b
-        V.append(v)
+        if keep_vectors:
+            V.append(v)
     K = len(alpha)
-    psi = np.array(V[:K]).T @ s
-    psi /= np.linalg.norm(psi)
+    if keep_vectors:
+        psi = np.array(V[:K]).T @ s
+        psi /= np.linalg.norm(psi)
+    else:
+        psi = None
     return dict(e0=e0, psi0=psi, alpha=np.array(alpha), beta=np.array(beta[:K - 1]),
                 iters=K, residual=resid)
 

@@ -44,6 +44,7 @@ def _make_function():
                 U=U.detach().cpu().numpy(), eps=eps.detach().cpu().numpy())
             op = Operator(m, keys, storage=storage)
             e0, psi, _, _, info = lanczos_ground(op, **lanczos_kw)
+            _require_converged(info, "ground state")
             dt, dU, de = op.contract(psi)
             op.close()
             ctx.save_for_backward(torch.as_tensor(dt, dtype=t.dtype, device=t.device),
@@ -63,6 +64,19 @@ _FN = None
 _GFN = None
 
 
+class NotConvergedError(RuntimeError):
+    """A solve behind a differentiable quantity stopped at its iteration cap:
+    the value (and Hellmann-Feynman or response gradients built on it) would
+    not belong to the converged state."""
+
+
+def _require_converged(info, what):
+    if not info.converged:
+        raise NotConvergedError(
+            f"{what} did not converge (iterations {info.iters}, residual {info.residual:.3e}); "
+            "raise max_iter / cg_max_iter or loosen the tolerance")
+
+
 def _make_green_function():
     torch = _torch()
 
@@ -74,8 +88,9 @@ def _make_green_function():
                 bonds=[(b[0], b[1], float(v)) for b, v in zip(model.bonds, t.detach().cpu().numpy())],
                 U=U.detach().cpu().numpy(), eps=eps.detach().cpu().numpy())
             op = Operator(m, keys, storage=storage)
-            e0, psi, _, _, _ = lanczos_ground(op, **lanczos_kw)
+            e0, psi, _, _, info = lanczos_ground(op, **lanczos_kw)
             op.close()
+            _require_converged(info, "ground state")
             # with a derivative ahead, keep the sector runs for it (no recomputation)
             ctx.keep = None
             if any(ctx.needs_input_grad[:3]) and not band_kw.get("per_column", False):
@@ -102,11 +117,12 @@ def _make_green_function():
             # second backward recomputes them: same result)
             kept, ctx.keep = ctx.keep, None
             try:
-                dt, dU, de, _ = band_green_vjp(ctx.m, ctx.keys, ctx.psi, ctx.e0, orbitals, spins,
-                                               omega, gb, e0_bar=eb, keep=kept, **kw)
+                dt, dU, de, vinfo = band_green_vjp(ctx.m, ctx.keys, ctx.psi, ctx.e0, orbitals,
+                                                   spins, omega, gb, e0_bar=eb, keep=kept, **kw)
             finally:
                 if kept is not None:
                     kept.close()
+            _require_converged(vinfo, "response solve of the Green-function derivative")
             t, U, eps = ctx.shapes
             as_t = lambda a, ref: torch.as_tensor(a, dtype=ref.dtype, device=ref.device)
             return (as_t(dt, t), as_t(dU, U), as_t(de, eps), None, None, None, None, None, None,

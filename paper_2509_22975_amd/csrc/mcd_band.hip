@@ -40,6 +40,7 @@
 #include "mcd_hash.h"
 #include "mcd_internal.h"
 #include "mcd_reduce.h"
+#include "mcd_spmm.h"
 
 namespace mcd {
 
@@ -214,18 +215,16 @@ __device__ __forceinline__ void halve_sum(double *v, int lane) {
 // dimension of 8 ceil(nch / 8) nm workgroups, handed out XCD-major: the nm
 // workgroups of one row chunk (one per block m) run on one XCD, so that the
 // chunk's X rows are fetched once into its L2 instead of once per block.
+// The work of one workgroup (block m, row chunk `chunk`); every thread of
+// the workgroup calls it.
 template <typename T, int P, int TPR>
-__global__ __launch_bounds__(256) void k_gram_rt(int64_t n, int64_t chunk_rows, int nch, int nm,
-                                                 const T *__restrict__ Q0, int64_t qstride,
-                                                 const T *__restrict__ X,
-                                                 double *__restrict__ part) {
+__device__ __forceinline__ void gram_rt_unit(int64_t n, int64_t chunk_rows, int nch,
+                                             const T *__restrict__ Q, const T *__restrict__ X,
+                                             double *__restrict__ part, int m, int chunk) {
     static_assert((P == 8 && (TPR == 1 || TPR == 2)) || (P == 16 && TPR == 4),
                   "register-tiled Gram for P = 8, 16");
     constexpr int PP = P * P, NA = P / TPR, NV = NA * P, RPB = 256 / TPR;
     __shared__ double red[4][PP];
-    const int k = blockIdx.x / 8, m = k % nm, chunk = (k / nm) * 8 + blockIdx.x % 8;
-    if (chunk >= nch) return;   // whole workgroup, before any barrier
-    const T *__restrict__ Q = Q0 + (int64_t)m * qstride;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int qq = t % TPR;
     const int64_t r0 = (int64_t)chunk * chunk_rows;
@@ -275,14 +274,20 @@ __global__ __launch_bounds__(256) void k_gram_rt(int64_t n, int64_t chunk_rows, 
         part[((int64_t)m * nch + chunk) * PP + e] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
 }
 
+template <typename T, int P, int TPR>
+__global__ __launch_bounds__(256) void k_gram_rt(int64_t n, int64_t chunk_rows, int nch, int nm,
+                                                 const T *__restrict__ Q0, int64_t qstride,
+                                                 const T *__restrict__ X,
+                                                 double *__restrict__ part) {
+    const int k = blockIdx.x / 8, m = k % nm, chunk = (k / nm) * 8 + blockIdx.x % 8;
+    if (chunk >= nch) return;   // whole workgroup, before any barrier
+    gram_rt_unit<T, P, TPR>(n, chunk_rows, nch, Q0 + (int64_t)m * qstride, X, part, m, chunk);
+}
+
 // out[m][e] = sum_c part[(m nch + c)][e]: one wavefront per output entry,
 // lanes stride over the chunks, fixed butterfly order.
-__global__ __launch_bounds__(256) void k_gram_reduce(int nm, int nch, int PP,
-                                                     const double *__restrict__ part,
-                                                     double *__restrict__ out) {
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (i >= nm * PP) return;          // whole wavefront exits together
+__device__ __forceinline__ void gram_reduce_wave(int nch, int PP, const double *__restrict__ part,
+                                                 double *__restrict__ out, int i, int lane) {
     const int m = i / PP, e = i % PP;
     const double *__restrict__ pm = part + (int64_t)m * nch * PP + e;
     double s = 0.0;
@@ -298,6 +303,15 @@ __global__ __launch_bounds__(256) void k_gram_reduce(int nm, int nch, int PP,
     for (; c < nch; c += 64) s += pm[(int64_t)c * PP];
     s = wave_sum(s);
     if (lane == 0) out[i] = s;
+}
+
+__global__ __launch_bounds__(256) void k_gram_reduce(int nm, int nch, int PP,
+                                                     const double *__restrict__ part,
+                                                     double *__restrict__ out) {
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= nm * PP) return;          // whole wavefront exits together
+    gram_reduce_wave(nch, PP, part, out, i, lane);
 }
 
 // W -= sum_{m < nm} Q_m C_m  (sub != 0)   or   W = Q_0 C_0  (sub == 0, nm == 1).
@@ -332,18 +346,14 @@ __global__ __launch_bounds__(BS) void k_block_apply(int64_t n, int nm, const T *
 // block come in 16-byte loads and are converted once, the P outputs are
 // accumulated in registers.  Each output receives the same terms in the same
 // (m, a) order as k_block_apply, so the results are bit-identical.
+// Row r of W (-)= sum_m Q_m C_m with the nm coefficient matrices in LDS (sC).
 template <typename T, int P>
-__global__ __launch_bounds__(BS) void k_block_apply_r(int64_t n, int nm, const T *__restrict__ Q0,
-                                                      int64_t qstride, const double *__restrict__ C,
-                                                      T *__restrict__ W, int sub) {
-    static_assert(P * sizeof(T) % 16 == 0, "row of P values must be whole 16-byte units");
+__device__ __forceinline__ void block_apply_row(int64_t r, int nm, const T *__restrict__ Q0,
+                                                int64_t qstride, const double *__restrict__ sC,
+                                                T *__restrict__ W, int sub) {
     constexpr int U = 16 / sizeof(T);
     using V16 = T __attribute__((ext_vector_type(16 / sizeof(T))));
-    extern __shared__ double sC[];
-    for (int e = threadIdx.x; e < nm * P * P; e += BS) sC[e] = C[e];
-    __syncthreads();
-    for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < n;
-         r += (int64_t)gridDim.x * BS) {
+    {
         double acc[P];
 #pragma unroll
         for (int b = 0; b < P; b++) acc[b] = 0.0;
@@ -375,6 +385,19 @@ __global__ __launch_bounds__(BS) void k_block_apply_r(int64_t n, int nm, const T
             w[u] = o;
         }
     }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(BS) void k_block_apply_r(int64_t n, int nm, const T *__restrict__ Q0,
+                                                      int64_t qstride, const double *__restrict__ C,
+                                                      T *__restrict__ W, int sub) {
+    static_assert(P * sizeof(T) % 16 == 0, "row of P values must be whole 16-byte units");
+    extern __shared__ double sC[];
+    for (int e = threadIdx.x; e < nm * P * P; e += BS) sC[e] = C[e];
+    __syncthreads();
+    for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * BS)
+        block_apply_row<T, P>(r, nm, Q0, qstride, sC, W, sub);
 }
 
 // W (-)= sum_m Q_m C_m for nm blocks (C on the device), one launch.
@@ -535,10 +558,10 @@ static void block_cf(const BandResult &br, cplx z, int p, cplx *out) {
 
 // Coefficients of W -= Q_{j-1} B_j^T + Q_j A_j in one pass over W:
 // A_j = sym(G) (also kept in dA), C2 = [B_j^T ; A_j] (B_j^T only when dB).
-__global__ __launch_bounds__(64) void k_sym_pair(int P, const double *__restrict__ G,
-                                                 double *__restrict__ dA,
-                                                 const double *__restrict__ dB,
-                                                 double *__restrict__ C2) {
+__device__ __forceinline__ void sym_pair_body(int P, const double *__restrict__ G,
+                                              double *__restrict__ dA,
+                                              const double *__restrict__ dB,
+                                              double *__restrict__ C2) {
     const int PP = P * P;
     for (int e = threadIdx.x; e < PP; e += 64) {
         const int a = e / P, b = e % P;
@@ -547,6 +570,13 @@ __global__ __launch_bounds__(64) void k_sym_pair(int P, const double *__restrict
         C2[PP + e] = v;
         if (dB != nullptr) C2[e] = dB[b * P + a];
     }
+}
+
+__global__ __launch_bounds__(64) void k_sym_pair(int P, const double *__restrict__ G,
+                                                 double *__restrict__ dA,
+                                                 const double *__restrict__ dB,
+                                                 double *__restrict__ C2) {
+    sym_pair_body(P, G, dA, dB, C2);
 }
 
 // QR factor of a block W from its Gram matrix M = W^T W by pivoted Cholesky
@@ -561,11 +591,10 @@ __global__ __launch_bounds__(64) void k_sym_pair(int P, const double *__restrict
 // chosen set is a register mask (the same in every lane), and M and Bacc are
 // loaded together at the start, so the steps are LDS round trips only.
 template <int P>
-__global__ __launch_bounds__(64) void k_pchol(const double *__restrict__ M, int mode,
-                                              double thr_abs, double *__restrict__ Xm,
-                                              double *__restrict__ Bm,
-                                              double *__restrict__ Bacc, int init,
-                                              int *__restrict__ rank_out) {
+__device__ __forceinline__ void pchol_body(const double *__restrict__ M, int mode,
+                                           double thr_abs, double *__restrict__ Xm,
+                                           double *__restrict__ Bm, double *__restrict__ Bacc,
+                                           int init, int *__restrict__ rank_out) {
     constexpr int PP = P * P;
     __shared__ double S[P][P], R[P][P], Ri[P][P], U[P][P], Bs[P][P];
     __shared__ int piv[P];
@@ -659,6 +688,15 @@ __global__ __launch_bounds__(64) void k_pchol(const double *__restrict__ M, int 
         Bacc[e] = acc;
     }
     if (t == 0) *rank_out = r;
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_pchol(const double *__restrict__ M, int mode,
+                                              double thr_abs, double *__restrict__ Xm,
+                                              double *__restrict__ Bm,
+                                              double *__restrict__ Bacc, int init,
+                                              int *__restrict__ rank_out) {
+    pchol_body<P>(M, mode, thr_abs, Xm, Bm, Bacc, init, rank_out);
 }
 
 // Frequency argument zeta of G: i w (Matsubara, eta <= 0) or w + i eta
@@ -1082,6 +1120,278 @@ struct BandRun {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Kernels over many runs at once (block widths P = 8 and 16, packed-CSR
+// operators): every kernel of a block step is one launch for all active
+// runs.  A workgroup finds its run by binary search over the runs' first
+// units (SpMM tiles, padded Gram chunks, apply row tiles) in a descriptor
+// table and does exactly the work the one-run kernel does for that unit, so
+// each run's numbers are bit for bit those of its own launches.
+struct MRun {
+    int64_t n;
+    const int64_t *rowptr;
+    const uint32_t *colw;
+    const double *diag;
+    const DevModel *model;
+    void *Qs, *W, *W2;
+    double *part, *dG, *dT;
+    int *rank;
+    int64_t chunk_rows;
+    int32_t nch, pad;
+    int64_t tile0, chunk0, row0;
+};
+
+// which: 0 tiles, 1 chunks, 2 apply row tiles; the last run whose first unit
+// is <= u (runs with no units are skipped over)
+__device__ __forceinline__ int mr_find(const MRun *__restrict__ R, int nrun, int64_t u,
+                                       int which) {
+    int lo = 0, hi = nrun - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t f = which == 0 ? R[mid].tile0 : which == 1 ? R[mid].chunk0 : R[mid].row0;
+        if (f <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// A run's block buffer: kind 0 = W, 1 = W2, 2 = stored block `slot`.
+template <typename T>
+__device__ __forceinline__ T *mr_buf(const MRun &r, int kind, int slot, int P) {
+    if (kind == 0) return (T *)r.W;
+    if (kind == 1) return (T *)r.W2;
+    return (T *)r.Qs + (int64_t)slot * r.n * P;
+}
+
+template <typename T, int NV, int CH>
+__global__ __launch_bounds__(256) void k_mr_spmm(const MRun *__restrict__ R, int nrun,
+                                                 int64_t total, int rpt, int slot) {
+    const int64_t per = (total + kNumXcd - 1) / kNumXcd;
+    const int64_t t = (int64_t)(blockIdx.x % kNumXcd) * per + blockIdx.x / kNumXcd;
+    if (t >= total) return;   // whole workgroup, before any barrier
+    const MRun &r = R[mr_find(R, nrun, t, 0)];
+    const int64_t rbeg = (t - r.tile0) * rpt;
+    block_csr_v_rows<T, NV, CH>(r.rowptr, r.colw, r.model, r.diag, mr_buf<T>(r, 2, slot, NV),
+                                (T *)r.W, rbeg, min(rbeg + (int64_t)rpt, r.n));
+}
+
+template <typename T, int P, int TPR>
+__global__ __launch_bounds__(256) void k_mr_gram(const MRun *__restrict__ R, int nrun, int nm,
+                                                 int qkind, int qslot, int xkind) {
+    const int64_t u = blockIdx.x;
+    const MRun &r = R[mr_find(R, nrun, u / nm, 1)];
+    const int64_t v = u - r.chunk0 * nm;
+    const int k = (int)(v / 8), m = k % nm, chunk = (k / nm) * 8 + (int)(v % 8);
+    if (chunk >= r.nch) return;   // whole workgroup, before any barrier
+    gram_rt_unit<T, P, TPR>(r.n, r.chunk_rows, r.nch, mr_buf<T>(r, qkind, qslot, P) +
+                            (int64_t)m * r.n * P, mr_buf<T>(r, xkind, 0, P), r.part, m, chunk);
+}
+
+__global__ __launch_bounds__(256) void k_mr_gram_reduce(const MRun *__restrict__ R, int nrun,
+                                                        int nm, int PP) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int per = nm * PP;
+    if (w >= (int64_t)nrun * per) return;   // whole wavefront
+    const MRun &r = R[w / per];
+    gram_reduce_wave(r.nch, PP, r.part, r.dG, (int)(w % per), threadIdx.x & 63);
+}
+
+__global__ __launch_bounds__(64) void k_mr_sym_pair(const MRun *__restrict__ R, int P, int mb,
+                                                    int j) {
+    const MRun &r = R[blockIdx.x];
+    const int PP = P * P;
+    sym_pair_body(P, r.dG, r.dT + (size_t)j * PP,
+                  j > 0 ? r.dT + (size_t)(mb + j) * PP : nullptr, r.dT + (size_t)(2 * mb + 5) * PP);
+}
+
+// dst (-)= sum_{m < nm} src_m C_m: src = buffer qkind (stored blocks from
+// qslot on), C = the run's dT (ckind 0) or dG (1) at offset coff.
+template <typename T, int P>
+__global__ __launch_bounds__(BS) void k_mr_apply(const MRun *__restrict__ R, int nrun, int nm,
+                                                 int qkind, int qslot, int ckind, int64_t coff,
+                                                 int dkind, int dslot, int sub) {
+    extern __shared__ double sC[];
+    const int64_t u = blockIdx.x;
+    const MRun &r = R[mr_find(R, nrun, u, 2)];
+    const double *__restrict__ C = (ckind == 0 ? r.dT : r.dG) + coff;
+    for (int e = threadIdx.x; e < nm * P * P; e += BS) sC[e] = C[e];
+    __syncthreads();
+    const int64_t row = (u - r.row0) * BS + threadIdx.x;
+    if (row < r.n)
+        block_apply_row<T, P>(row, nm, mr_buf<T>(r, qkind, qslot, P), r.n * P, sC,
+                              mr_buf<T>(r, dkind, dslot, P), sub);
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_mr_pchol(const MRun *__restrict__ R, int mb, int mode,
+                                                 double thr_abs, int init, int slot) {
+    const MRun &r = R[blockIdx.x];
+    constexpr int PP = P * P;
+    double *Xm = r.dT + (size_t)(2 * mb + 2) * PP;
+    pchol_body<P>(r.dG, mode, thr_abs, Xm, Xm + PP, Xm + 2 * PP, init, r.rank + slot);
+}
+
+// the QR factor (Bacc) of every run to its place in dT (offset dst_off)
+__global__ __launch_bounds__(64) void k_mr_copy_factor(const MRun *__restrict__ R, int PP, int mb,
+                                                       int64_t dst_off) {
+    const MRun &r = R[blockIdx.x];
+    const double *Bacc = r.dT + (size_t)(2 * mb + 4) * PP;
+    for (int e = threadIdx.x; e < PP; e += 64) r.dT[dst_off + e] = Bacc[e];
+}
+
+// The descriptor table of the active runs (rebuilt, after a synchronisation,
+// whenever the active set changes) and the fused step.
+template <typename T>
+struct MRTable {
+    std::vector<MRun> host;
+    MRun *dev = nullptr;       // workspace piece with room for every run
+    int nrun = 0, P = 0, mb = 0, nstore = 0;
+    int64_t tiles = 0, chunks = 0, rowt = 0;
+    int rpt = 0, ch = 16;
+    hipStream_t s = nullptr;
+
+    static bool usable(const std::vector<BandRun<T> *> &runs) {
+        for (auto *r : runs)
+            if (r->n > 0 && (r->op->storage != MCD_STORAGE_CSR || (r->P != 8 && r->P != 16)))
+                return false;
+        return true;
+    }
+    int slot(int j) const { return nstore == 3 ? j % 3 : j; }
+
+    int build(const std::vector<BandRun<T> *> &act) {
+        host.clear();
+        tiles = chunks = rowt = 0;
+        int64_t nnz = 0, rows = 0;
+        constexpr int VN = 16 / sizeof(T);
+        for (auto *r : act) {
+            P = r->P;
+            mb = r->mb;
+            nstore = r->nstore;
+            rpt = std::max(64, (256 / (r->P / VN)) / 2);   // as the one-run product
+            MRun d;
+            memset(&d, 0, sizeof(d));
+            d.n = r->n;
+            d.rowptr = r->op->d_rowptr;
+            d.colw = r->op->d_colw;
+            d.diag = r->op->d_diag;
+            d.model = r->op->d_model;
+            d.Qs = r->Qs;
+            d.W = r->W;
+            d.W2 = r->W2;
+            d.part = r->part;
+            d.dG = r->dG;
+            d.dT = r->dT;
+            d.rank = r->d_rank;
+            d.chunk_rows = r->chunk_rows;
+            d.nch = r->nch;
+            d.tile0 = tiles;
+            d.chunk0 = chunks;
+            d.row0 = rowt;
+            tiles += (r->n + rpt - 1) / rpt;
+            chunks += ((int64_t)r->nch + 7) / 8 * 8;
+            rowt += (r->n + BS - 1) / BS;
+            nnz += r->op->nnz;
+            rows += r->n;
+            host.push_back(d);
+        }
+        nrun = (int)host.size();
+        ch = (nnz < 4 * rows) ? 4 : (nnz < 10 * rows) ? 8 : 16;
+        if (nrun > 0)
+            MCD_HIP(hipMemcpyAsync(dev, host.data(), nrun * sizeof(MRun), hipMemcpyHostToDevice, s));
+        return MCD_OK;
+    }
+
+    int spmm(int j) {
+#define MRS(NV, CH)                                                                          \
+    hipLaunchKernelGGL((k_mr_spmm<T, NV, CH>), dim3((unsigned)((tiles + 7) / 8 * 8)),        \
+                       dim3(256), 0, s, dev, nrun, tiles, rpt, slot(j))
+        if (P == 8) {
+            if (ch == 4) MRS(8, 4); else if (ch == 8) MRS(8, 8); else MRS(8, 16);
+        } else {
+            if (ch == 4) MRS(16, 4); else if (ch == 8) MRS(16, 8); else MRS(16, 16);
+        }
+#undef MRS
+        MCD_HIP(hipGetLastError());
+        return MCD_OK;
+    }
+    int gram(int nm, int qkind, int qslot, int xkind) {
+        const unsigned g = (unsigned)(chunks * nm);
+        if (P == 8) {
+            if (sizeof(T) == 8)
+                hipLaunchKernelGGL((k_mr_gram<T, 8, 2>), dim3(g), dim3(256), 0, s, dev, nrun, nm,
+                                   qkind, qslot, xkind);
+            else
+                hipLaunchKernelGGL((k_mr_gram<T, 8, 1>), dim3(g), dim3(256), 0, s, dev, nrun, nm,
+                                   qkind, qslot, xkind);
+        } else {
+            hipLaunchKernelGGL((k_mr_gram<T, 16, 4>), dim3(g), dim3(256), 0, s, dev, nrun, nm,
+                               qkind, qslot, xkind);
+        }
+        MCD_HIP(hipGetLastError());
+        const int64_t waves = (int64_t)nrun * nm * P * P;
+        hipLaunchKernelGGL(k_mr_gram_reduce, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
+                           dev, nrun, nm, P * P);
+        MCD_HIP(hipGetLastError());
+        return MCD_OK;
+    }
+    int apply(int nm, int qkind, int qslot, int ckind, int64_t coff, int dkind, int dslot,
+              bool sub) {
+        const size_t lds = (size_t)nm * P * P * sizeof(double);
+        if (P == 8)
+            hipLaunchKernelGGL((k_mr_apply<T, 8>), dim3((unsigned)rowt), dim3(BS), lds, s, dev,
+                               nrun, nm, qkind, qslot, ckind, coff, dkind, dslot, sub ? 1 : 0);
+        else
+            hipLaunchKernelGGL((k_mr_apply<T, 16>), dim3((unsigned)rowt), dim3(BS), lds, s, dev,
+                               nrun, nm, qkind, qslot, ckind, coff, dkind, dslot, sub ? 1 : 0);
+        MCD_HIP(hipGetLastError());
+        return MCD_OK;
+    }
+    // QR of W into stored block `dslot`: two pivoted-Cholesky passes through
+    // W2, the factor to dT[dst_off], the rank to rank[rslot]
+    int qr(int dslot, int64_t dst_off, int rslot, double dtol_abs) {
+        const int PP = P * P;
+        const int64_t xm_off = (int64_t)(2 * mb + 2) * PP;
+        for (int pass = 0; pass < 2; pass++) {
+            MCD_TRY(gram(1, pass == 0 ? 0 : 1, 0, pass == 0 ? 0 : 1));
+            if (P == 8)
+                hipLaunchKernelGGL((k_mr_pchol<8>), dim3(nrun), dim3(64), 0, s, dev, mb, pass,
+                                   dtol_abs * dtol_abs, pass == 0 ? 1 : 0, rslot);
+            else
+                hipLaunchKernelGGL((k_mr_pchol<16>), dim3(nrun), dim3(64), 0, s, dev, mb, pass,
+                                   dtol_abs * dtol_abs, pass == 0 ? 1 : 0, rslot);
+            MCD_HIP(hipGetLastError());
+            MCD_TRY(apply(1, pass == 0 ? 0 : 1, 0, 0, xm_off, pass == 0 ? 1 : 2, dslot, false));
+        }
+        hipLaunchKernelGGL(k_mr_copy_factor, dim3(nrun), dim3(64), 0, s, dev, PP, mb, dst_off);
+        MCD_HIP(hipGetLastError());
+        return MCD_OK;
+    }
+    // block step j up to the new residual block in W (as BandRun::step_dev)
+    int step(int j, int reorth) {
+        const int PP = P * P;
+        MCD_TRY(spmm(j));
+        MCD_TRY(gram(1, 2, slot(j), 0));
+        hipLaunchKernelGGL(k_mr_sym_pair, dim3(nrun), dim3(64), 0, s, dev, P, mb, j);
+        MCD_HIP(hipGetLastError());
+        const int64_t c2 = (int64_t)(2 * mb + 5) * PP;
+        if (j > 0 && slot(j) == slot(j - 1) + 1) {
+            MCD_TRY(apply(2, 2, slot(j - 1), 0, c2, 0, 0, true));
+        } else {
+            MCD_TRY(apply(1, 2, slot(j), 0, c2 + PP, 0, 0, true));
+            if (j > 0) MCD_TRY(apply(1, 2, slot(j - 1), 0, c2, 0, 0, true));
+        }
+        const int group = std::max(1, (48 * 1024) / (PP * 8));
+        for (int pass = 0; pass < reorth; pass++) {
+            MCD_TRY(gram(j + 1, 2, 0, 0));
+            for (int g0 = 0; g0 <= j; g0 += group)
+                MCD_TRY(apply(std::min(group, j + 1 - g0), 2, g0, 1, (int64_t)g0 * PP, 0, 0, true));
+        }
+        return MCD_OK;
+    }
+};
+
 // Block Lanczos of every run in `runs` (device form) in lockstep: at block
 // step j every active run does its product, A_j, update,
 // reorthogonalisation and QR, each kernel enqueued for all runs before the
@@ -1094,39 +1404,82 @@ template <typename T>
 static int run_lockstep(std::vector<BandRun<T> *> &runs, double dtol_abs, int reorth,
                         hipStream_t s) {
     int mb = 0;
+    std::vector<BandRun<T> *> act;
     for (auto *r : runs) {
         r->m = 0;
         r->active = r->n > 0;
         r->gprev.clear();
-        if (r->active) {
-            MCD_TRY(r->qr_dev(r->W, r->blk(0), r->dR0(), 0, dtol_abs));
-            MCD_TRY(r->fetch_ranks(0));
-        }
         mb = std::max(mb, r->mb);
+        if (r->active) act.push_back(r);
     }
-    MCD_HIP(hipStreamSynchronize(s));
+    // fused launches over all runs when every operator is a packed CSR and
+    // P is 8 or 16; else each run's own launches
+    MRTable<T> tab;
+    tab.s = s;
+    const bool fused = !act.empty() && MRTable<T>::usable(act);
+    Alloc tal;
+    if (fused) {
+        tal = act[0]->al;
+        const hipError_t e = dmalloc((void **)&tab.dev, act.size() * sizeof(MRun), tal);
+        if (e != hipSuccess) {
+            set_error("band runs: workspace too small for the run table");
+            return hip_status(e);
+        }
+    }
+    auto done = [&](int rc) {
+        if (tab.dev) {
+            (void)hipStreamSynchronize(s);
+            (void)dfree(tab.dev, tal);
+        }
+        return rc;
+    };
+#define LTRY(expr)                     \
+    do {                               \
+        int rc_ = (expr);              \
+        if (rc_ < 0) return done(rc_); \
+    } while (0)
+    const int PP0 = act.empty() ? 0 : act[0]->PP();
+    if (fused) {
+        LTRY(tab.build(act));
+        LTRY(tab.qr(tab.slot(0), (int64_t)(2 * mb + 1) * PP0, 0, dtol_abs));
+    } else {
+        for (auto *r : act) LTRY(r->qr_dev(r->W, r->blk(0), r->dR0(), 0, dtol_abs));
+    }
+    for (auto *r : act) LTRY(r->fetch_ranks(0));
+    if (hipStreamSynchronize(s) != hipSuccess) return done(MCD_E_HIP);
     for (auto *r : runs)
         if (r->active && r->rank[0] <= 0) r->active = false;
-    std::vector<BandRun<T> *> act;
+    size_t built = act.size();
     for (int j = 0; j < mb; j++) {
         act.clear();
         for (auto *r : runs)
             if (r->active) act.push_back(r);
         if (act.empty()) break;
-        for (auto *r : act) MCD_TRY(r->step_dev(j, reorth));
+        if (fused && act.size() != built) {   // the set changed (after a synchronisation)
+            LTRY(tab.build(act));
+            built = act.size();
+        }
+        if (fused)
+            LTRY(tab.step(j, reorth));
+        else
+            for (auto *r : act) LTRY(r->step_dev(j, reorth));
         for (auto *r : act) r->m = j + 1;
         if (j + 1 == mb) break;
-        for (auto *r : act) MCD_TRY(r->qr_dev(r->W, r->blk(j + 1), r->dB(j + 1), j + 1, dtol_abs));
+        if (fused)
+            LTRY(tab.qr(tab.slot(j + 1), (int64_t)(mb + j + 1) * PP0, j + 1, dtol_abs));
+        else
+            for (auto *r : act)
+                LTRY(r->qr_dev(r->W, r->blk(j + 1), r->dB(j + 1), j + 1, dtol_abs));
         if ((j + 1) % 8 == 0) {
             bool gt = false;
             for (auto *r : act) {
-                MCD_TRY(r->fetch_ranks(j + 1));
+                LTRY(r->fetch_ranks(j + 1));
                 if (r->g_tol > 0.0) {
-                    MCD_TRY(r->fetch_T());
+                    LTRY(r->fetch_T());
                     gt = true;
                 }
             }
-            MCD_HIP(hipStreamSynchronize(s));
+            if (hipStreamSynchronize(s) != hipSuccess) return done(MCD_E_HIP);
             for (auto *r : act)
                 for (int z = 1; z <= j + 1; z++)
                     if (r->rank[z] == 0) {   // exhausted: blocks from z on are zero
@@ -1145,7 +1498,7 @@ static int run_lockstep(std::vector<BandRun<T> *> &runs, double dtol_abs, int re
                     if (rcs[i] == MCD_OK && chk[i]->g_converged(tmp)) stop[i] = 1;
                 });
                 for (size_t i = 0; i < chk.size(); i++) {
-                    MCD_TRY(rcs[i]);
+                    LTRY(rcs[i]);
                     if (stop[i]) chk[i]->active = false;
                 }
             }
@@ -1154,10 +1507,10 @@ static int run_lockstep(std::vector<BandRun<T> *> &runs, double dtol_abs, int re
     // final ranks and T of every run
     for (auto *r : runs)
         if (r->n > 0) {
-            MCD_TRY(r->fetch_ranks(std::max(r->m - 1, 0)));
-            MCD_TRY(r->fetch_T());
+            LTRY(r->fetch_ranks(std::max(r->m - 1, 0)));
+            LTRY(r->fetch_T());
         }
-    MCD_HIP(hipStreamSynchronize(s));
+    if (hipStreamSynchronize(s) != hipSuccess) return done(MCD_E_HIP);
     for (auto *r : runs) {
         r->active = false;
         if (r->n == 0) {
@@ -1171,9 +1524,10 @@ static int run_lockstep(std::vector<BandRun<T> *> &runs, double dtol_abs, int re
                 r->m = z;
                 break;
             }
-        MCD_TRY(r->make_T(r->m, r->br));
+        LTRY(r->make_T(r->m, r->br));
     }
-    return MCD_OK;
+#undef LTRY
+    return done(MCD_OK);
 }
 
 // F~+- of the kept states for the selection (images c+_mu x or c_mu x,
@@ -1320,13 +1674,16 @@ static size_t plan_runs(mcd_ws *ws, const std::vector<BandRun<T> *> &runs) {
         sim = ws->a;
     }
     sim.grow_to(size_t(1) << 62);   // the same live pieces, an unbounded range
+    size_t live = 0;
     for (auto *r : runs) {
         if (r->n == 0) continue;
         size_t sz[9];
         run_piece_sizes(*r, sz);
         for (int i = 0; i < 9; i++)
             if (sz[i]) (void)sim.alloc(sz[i]);
+        live++;
     }
+    if (live) (void)sim.alloc(live * sizeof(MRun));   // run_lockstep's table
     return sim.extent();
 }
 

@@ -101,8 +101,8 @@ static int contract_into(const mcd_op *op, const mcd_model *model, const double 
     hipLaunchKernelGGL(k_contract_reduce, dim3((unsigned)((np + 3) / 4)), dim3(256), 0, s, np,
                        (int64_t)nblk, part, out);
     MCD_HIP(hipGetLastError());
-    std::vector<double> h(np);
-    MCD_HIP(hipMemcpyAsync(h.data(), out, np * sizeof(double), hipMemcpyDeviceToHost, s));
+    double h[kMaxParams];   // np <= kMaxParams (merged bonds <= listed bonds)
+    MCD_HIP(hipMemcpyAsync(h, out, np * sizeof(double), hipMemcpyDeviceToHost, s));
     MCD_HIP(hipStreamSynchronize(s));
     // listed bond -> merged pair (bonds listed twice share the pair's derivative)
     if (d_t) {

@@ -22,6 +22,7 @@
 #include "mcd_hash.h"
 #include "mcd_internal.h"
 #include "mcd_reduce.h"
+#include "mcd_spmm.h"
 
 namespace mcd {
 
@@ -513,91 +514,22 @@ __global__ __launch_bounds__(256) void k_block_csr(
     }
 }
 
-// Vector types of one 16-byte gather.
-template <typename T>
-struct Vec16;
-template <>
-struct Vec16<float> {
-    using type = float4;
-    static constexpr int n = 4;
-};
-template <>
-struct Vec16<double> {
-    using type = double2;
-    static constexpr int n = 2;
-};
-__device__ __forceinline__ float4 vscale(float a, const float4 &x) {
-    return make_float4(a * x.x, a * x.y, a * x.z, a * x.w);
-}
-__device__ __forceinline__ double2 vscale(double a, const double2 &x) {
-    return make_double2(a * x.x, a * x.y);
-}
-__device__ __forceinline__ void vscale_add(float4 &acc, float a, const float4 &x) {
-    acc.x += a * x.x;
-    acc.y += a * x.y;
-    acc.z += a * x.z;
-    acc.w += a * x.w;
-}
-__device__ __forceinline__ void vscale_add(double2 &acc, double a, const double2 &x) {
-    acc.x += a * x.x;
-    acc.y += a * x.y;
-}
-
 // k_block_csr with 16-byte gathers: L = NV / (16 / sizeof(T)) lanes per row,
 // each lane 16 bytes of the gathered row (float4 / double2), so one gather
 // instruction covers 4 / L times more rows; the same terms are added in the
 // same order per column as in k_block_csr (bit-identical y).  X and Y
-// 16-byte aligned.
+// 16-byte aligned.  XCD-major row tiles.
 template <typename T, int NV, int CH>
 __global__ __launch_bounds__(256) void k_block_csr_v(
     int64_t n, const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ colw,
     const DevModel *__restrict__ m, const double *__restrict__ diag, const T *__restrict__ x,
     T *__restrict__ y, int64_t ntiles, int rows_per_tile) {
-    using V = typename Vec16<T>::type;
-    constexpr int L = NV / Vec16<T>::n;
-    static_assert(L >= 1 && L * Vec16<T>::n == NV, "NV must be a multiple of the vector width");
-    __shared__ T vtab[kMaxClasses];
-    if (threadIdx.x < kMaxClasses) vtab[threadIdx.x] = (T)m->vtab[threadIdx.x];
-    __syncthreads();
-    const uint32_t cmask = m->col_mask, cbits = m->col_bits;
-    constexpr int RPB = 256 / L;
-    constexpr int WPL = (CH + L - 1) / L;
     const int64_t per = (ntiles + kNumXcd - 1) / kNumXcd;
     const int64_t tile = (int64_t)(blockIdx.x % kNumXcd) * per + blockIdx.x / kNumXcd;
-    if (tile >= ntiles) return;
-    const int lane = threadIdx.x % L;
-    const V *__restrict__ xv4 = reinterpret_cast<const V *>(x);
-    V *__restrict__ yv4 = reinterpret_cast<V *>(y);
+    if (tile >= ntiles) return;   // whole workgroup, before any barrier
     const int64_t rbeg = tile * rows_per_tile;
-    const int64_t rend = min(rbeg + (int64_t)rows_per_tile, n);
-    for (int64_t r = rbeg + threadIdx.x / L; r < rend; r += RPB) {
-        const T d = (T)diag[r];
-        V acc = vscale(d, xv4[r * L + lane]);
-        const int64_t e1 = rowptr[r + 1];
-        for (int64_t base = rowptr[r]; base < e1; base += CH) {
-            uint32_t mw[WPL];
-#pragma unroll
-            for (int q = 0; q < WPL; q++) {
-                const int64_t e = base + q * L + lane;
-                mw[q] = (q * L + lane < CH && e < e1) ? colw[e] : 0u;
-            }
-            uint32_t wj[CH];
-            V xg[CH];
-#pragma unroll
-            for (int j = 0; j < CH; j++) {
-                wj[j] = (uint32_t)__shfl((int)mw[j / L], j % L, L);
-                xg[j] = (base + j < e1) ? xv4[(int64_t)(wj[j] & cmask) * L + lane] : V{};
-            }
-#pragma unroll
-            for (int j = 0; j < CH; j++) {
-                if (base + j < e1) {
-                    const T v = vtab[(wj[j] & 0x7fffffffu) >> cbits];
-                    vscale_add(acc, (wj[j] >> 31) ? -v : v, xg[j]);
-                }
-            }
-        }
-        yv4[r * L + lane] = acc;
-    }
+    block_csr_v_rows<T, NV, CH>(rowptr, colw, m, diag, x, y, rbeg,
+                                min(rbeg + (int64_t)rows_per_tile, n));
 }
 
 __global__ void k_conn_count(int64_t row0, int64_t row1, const uint64_t *__restrict__ keys,

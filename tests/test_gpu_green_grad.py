@@ -273,3 +273,44 @@ def test_green_vjp_wide_krylov_paths_agree():
         out[mb] = (G, np.concatenate(d[:3]))
     assert _rel(out[140][0], out[120][0]) < 1e-8
     assert _rel(out[140][1], out[120][1]) < 1e-6
+
+
+@pytest.mark.parametrize("nf", [80, 170])
+def test_green_vjp_c4_shape_vs_oracle(nf):
+    """The C4 configuration's shape on a basis the oracle can difference: the
+    2x2 + 8-bath impurity model (12 orbitals, U = 8), p = 8 (4 impurity sites
+    x 2 spins), 32 Matsubara frequencies, band runs to exhaustion, so the
+    Krylov dimension is several hundred (S = 384 / 768 adjoint columns: the
+    contraction's 6- and 12-value register forms and a multi-tile Z = Q M
+    product).  Every bond amplitude, U_i and eps_i derivative (the 33 model
+    parameters eps_b, V_ib, U are linear combinations of them) against the
+    oracle's central differences of its exact Lehmann sums: float64 to 1e-6
+    of max |dL|, float32 Krylov blocks to 1e-4."""
+    torch, mcd = require_gpu()
+    m = W.impurity_plaquette_bath(3)
+    keys, _ = sampler.chain_c(m, W.neel_start(m), 9, nf, 500, 10**7)
+    orbs, spins = [0, 1, 2, 3] * 2, [0] * 4 + [1] * 4
+    om = W.matsubara(32, 50.0)
+    rng = np.random.default_rng(nf)
+    Gb = rng.normal(size=(32, 8, 8)) + 1j * rng.normal(size=(32, 8, 8))
+    e0_bar = -0.6
+    kd = mcd.keys_from_numpy(keys)
+    e0, psi = _gpu_ground(mcd, m, kd)
+    log_case("green_vjp_c4_shape", n=len(keys))
+    r_t, r_U, r_e = dv.green_gradient(keys, m, orbs, spins, om, Gb, e0_bar=e0_bar)
+    ref = np.concatenate([r_t, r_U, r_e])
+    got = {}
+    for prec in ("f64", "f32"):
+        d_t, d_U, d_e, info = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb,
+                                                 e0_bar=e0_bar, max_blocks=400, reorth=2,
+                                                 precision=prec)
+        assert info.converged
+        print(f"[c4 shape] nf={nf} {prec} krylov_dim={info.krylov_dim} "
+              f"F+={info.n_plus} F-={info.n_minus}", flush=True)
+        got[prec] = np.concatenate([d_t, d_U, d_e])
+    kmax = max(info.n_plus, info.n_minus)
+    assert kmax >= 8 * 40     # hundreds of Krylov columns in the larger sector
+    err64, err32 = _rel(got["f64"], ref), _rel(got["f32"], ref)
+    print(f"[c4 shape] rel err f64 {err64:.2e} f32 {err32:.2e}", flush=True)
+    assert err64 < 1e-6
+    assert err32 < 1e-4

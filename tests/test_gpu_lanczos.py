@@ -66,6 +66,34 @@ def test_e0_and_ground_state(name, storage, store, kern):
     op.close()
 
 
+@pytest.mark.parametrize("name", ["c1_full", "c1_chain", "imp_chain"])
+@pytest.mark.parametrize("storage,store", [("csr", True), ("otf", False)])
+def test_float32_krylov_vectors_refined_e0(name, storage, store):
+    """Float32 Krylov vectors with float64 coefficients, then one float64
+    product for the Rayleigh quotient of the Ritz vector: E0 within 1e-9 of
+    the oracle (the quotient's error is second order in the float32-level
+    error of the vector), psi0 overlap to 1e-6, and the reported residual is
+    the true float64 residual ||H psi - E0 psi||."""
+    torch, mcd = require_gpu()
+    m, keys = CASES[name]
+    log_case("lanczos_f32", case=name, storage=storage, store=store, n=len(keys))
+    H, ro = _oracle(keys, m)
+    op = mcd.Operator(m, mcd.keys_from_numpy(keys), storage=storage)
+    e0, psi, a, b, info = mcd.lanczos_ground(op, max_iter=400, tol=1e-9, seed=11,
+                                              store_vectors=store, precision="f32")
+    p = psi.cpu().numpy()
+    print("[f32] E0 err", abs(e0 - ro["e0"]) / abs(ro["e0"]), "resid", info.residual, flush=True)
+    assert abs(e0 - ro["e0"]) <= 1e-9 * abs(ro["e0"])
+    assert abs(np.linalg.norm(p) - 1) < 1e-12
+    assert abs(abs(p @ ro["psi0"]) - 1.0) < 1e-6
+    assert abs(e0 - p @ (H @ p)) <= 1e-12 * abs(e0)
+    assert abs(info.residual - np.linalg.norm(H @ p - e0 * p)) <= 1e-6 * max(info.residual, 1e-9)
+    # the start vector is the float64 one rounded to float32
+    v0 = lz.start_vector(keys, 11).astype(np.float32).astype(np.float64)
+    assert abs(a[0] - (v0 @ (H @ v0)) / (v0 @ v0)) <= 1e-6 * max(1, abs(a[0]))
+    op.close()
+
+
 def test_paper_energies_on_gpu():
     """Full-ED energies printed in the paper's appendix tables (truncated to 4 decimals)."""
     torch, mcd = require_gpu()
@@ -122,4 +150,10 @@ def test_c2_full_size_e0():
     ec, psi, _, _, info = mcd.lanczos_ground(op, max_iter=1500, tol=1e-10, seed=11)
     print("[c2] E0(conv) gpu", ec, info.iters, "oracle", rc["e0"], rc["iters"], flush=True)
     assert abs(ec - rc["e0"]) <= 1e-10 * abs(rc["e0"])
+    # (c) float32 Krylov vectors + float64 Rayleigh-quotient refinement: 1e-8
+    e32, p32, _, _, i32 = mcd.lanczos_ground(op, max_iter=1500, tol=1e-9, seed=11,
+                                             precision="f32")
+    err = abs(e32 - rc["e0"]) / abs(rc["e0"])
+    print("[c2] E0 f32+refine", e32, i32.iters, "rel err", err, "resid", i32.residual, flush=True)
+    assert err <= 1e-8
     op.close()

@@ -121,3 +121,22 @@ def test_start_vector_is_key_determined():
     assert np.array_equal(lz.start_vector(sub, 5), v[::3])
     # first splitmix64 output of state 0 (published test value of the generator)
     assert int(lz.splitmix64_first(np.array([0], np.uint64))[0]) == 0xE220A8397B1DCDAF
+
+
+def test_lanczos_without_stored_vectors_same_recurrence():
+    """keep_vectors=False keeps the recurrence: the same a_n, b_n and Ritz
+    value as the stored form (no reorthogonalisation), and the ground state
+    from the second pass of Eq. change_basis."""
+    import workloads as W
+    from oracle import fock, hamiltonian as ham, lanczos as lz
+    m = W.config_c1()["model"]
+    keys = fock.sector_keys(8, 4, 4)
+    H = ham.build_csr(keys, m)
+    v0 = lz.start_vector(keys, 11)
+    a = lz.lanczos_ground(H, v0, tol=0.0, max_iter=60, reorth=False)
+    b = lz.lanczos_ground(H, v0, tol=0.0, max_iter=60, reorth=False, keep_vectors=False)
+    assert b["psi0"] is None
+    assert np.array_equal(a["alpha"], b["alpha"]) and np.array_equal(a["beta"], b["beta"])
+    assert a["e0"] == b["e0"]
+    e0, psi = lz.recompute_ground_state(H, v0, b["alpha"], b["beta"])
+    assert abs(abs(psi @ a["psi0"]) - 1.0) < 1e-10
