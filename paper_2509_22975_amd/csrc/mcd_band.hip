@@ -1901,6 +1901,10 @@ static int band_green_multi(std::vector<Instance<T> *> &inst, const SelOps &sel,
     mcd_solve_info agg;
     memset(&agg, 0, sizeof(agg));
     size_t need_max = 0;
+    {   // the size answers below measure this call alone
+        std::lock_guard<std::mutex> lock(ws->mu);
+        ws->a.restart_extent();
+    }
     int k0 = 0;
     while (k0 < K) {
         // prepare instances k0, k0 + 1, ... while their runs fit

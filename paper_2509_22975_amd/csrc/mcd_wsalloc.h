@@ -95,6 +95,13 @@ class WsAlloc {
     }
 
     void clear_need() { need_ = 0; }
+
+    // Restarts the extent at the end of the highest live piece, so that
+    // extent() measures one call from here on (a workspace reused by many
+    // calls keeps the largest end any of them reached otherwise).
+    void restart_extent() {
+        ext_ = used_.empty() ? 0 : used_.rbegin()->first + used_.rbegin()->second;
+    }
     void set_need(size_t b) { need_ = std::max(need_, b); }
 
     // Extends the range to `nsize` bytes (a copy used to replay takes

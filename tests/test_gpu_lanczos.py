@@ -157,3 +157,29 @@ def test_c2_full_size_e0():
     print("[c2] E0 f32+refine", e32, i32.iters, "rel err", err, "resid", i32.residual, flush=True)
     assert err <= 1e-8
     op.close()
+
+
+def test_c5_full_size_200_step_ritz_value():
+    """C5 at full size (4x8 t-t', 50M chain states): the GPU's Ritz value
+    after 200 steps from the seed-11 start vector against the oracle's
+    (tests/golden/c5_ritz200.json, written by tests/golden/make_c5_ritz.py
+    from the oracle alone: same Krylov space, float64, no
+    reorthogonalisation on either side), to 1e-10 relative; the first
+    coefficient a_0 to 1e-12."""
+    torch, mcd = require_gpu()
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c5_ritz200.json")))
+    c = W.config_c5()
+    m = c["model"]
+    log_case("lanczos_c5", n_f=c["n_f"])
+    kd, steps = mcd.basis_build(m, "chain", start_key=W.neel_start(m), seed=c["seed"],
+                                beta_s=c["beta_s"], burn_in=c["burn_in"],
+                                max_steps=c["max_steps"], n_f=c["n_f"])
+    assert kd.numel() == gold["n"] and steps == gold["chain_steps"]
+    op = mcd.Operator(m, kd, storage="csr")
+    e200, _, a, _, info = mcd.lanczos_ground(op, max_iter=200, tol=0.0, seed=11, min_iter=200,
+                                             want_psi=False, store_vectors=False)
+    print("[c5] E0(200) gpu", e200, "oracle", gold["e0_200"], flush=True)
+    assert info.iters == 200
+    assert abs(a[0] - gold["alpha_0"]) <= 1e-12 * abs(gold["alpha_0"])
+    assert abs(e200 - gold["e0_200"]) <= 1e-10 * abs(gold["e0_200"])
+    op.close()

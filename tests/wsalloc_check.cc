@@ -116,6 +116,18 @@ int main() {
             return fail("grow", (long)g.in_use(), (long)exact.in_use());
         if (g.alloc(exact.size()) == WsAlloc::kFail) return fail("grown range", 0, 0);
     }
+    // restart_extent: the extent of a second use of the same range
+    {
+        WsAlloc w(size_t(1) << 30);
+        const size_t a = w.alloc(1 << 20), b = w.alloc(8 << 20);
+        w.release(b);
+        if (w.extent() != (size_t)(9 << 20)) return fail("extent before", (long)w.extent(), 0);
+        w.restart_extent();
+        if (w.extent() != (size_t)(1 << 20)) return fail("restart", (long)w.extent(), 0);
+        w.alloc(4096);
+        if (w.extent() != (size_t)(1 << 20) + 4096) return fail("after restart", (long)w.extent(), 0);
+        (void)a;
+    }
     printf("ok\n");
     return 0;
 }
