@@ -303,6 +303,18 @@ int mcd_hamiltonian_contract(const mcd_op *op, const mcd_model *model, const dou
                              const double *b_dev, double *d_t, double *d_U, double *d_eps,
                              mcd_ws *ws, void *stream);
 
+/* mcd_hamiltonian_contract for callers that cannot allocate or hand over
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid it): the same contraction and results, with its workgroup
+ * partials in a fixed scratch array of the library in device memory (9.4 MB
+ * per device, held until the process ends; up to MCD_MAX_BONDS + 2
+ * MCD_MAX_ORB parameters, so every operator fits; MCD_E_CAPACITY otherwise).
+ * Calls that overlap on one device race on that array: serialise them (one
+ * stream, or wait for each call, which synchronises its stream).  Takes no
+ * workspace and allocates nothing.  Synchronises. */
+int mcd_hamiltonian_contract_noalloc(const mcd_op *op, const mcd_model *model,
+                                     const double *a_dev, const double *b_dev, double *d_t,
+                                     double *d_U, double *d_eps, void *stream);
 
 /* ---------------------------------------------------------------------------
  * mcd_lanczos_ground -- lowest eigenpair of H~ by Lanczos (App. Lanczos,

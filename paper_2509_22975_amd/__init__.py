@@ -113,6 +113,8 @@ def lib():
     L.mcd_lanczos_workspace_size.argtypes = [c_vp, P(McdLanczosCfg), P(c_sz)]
     L.mcd_hamiltonian_contract.argtypes = [c_vp, P(McdModel), c_vp, c_vp, P(c_dbl), P(c_dbl),
                                            P(c_dbl), c_vp, c_vp]
+    L.mcd_hamiltonian_contract_noalloc.argtypes = [c_vp, P(McdModel), c_vp, c_vp, P(c_dbl),
+                                                   P(c_dbl), P(c_dbl), c_vp]
     L.mcd_batch_lanczos_ground.argtypes = [P(c_vp), c_i32, P(McdLanczosCfg), P(c_dbl), P(c_vp),
                                            P(c_i32), P(McdSolveInfo), c_vp, c_vp]
     band = [P(McdModel), c_vp, c_i64, c_vp, c_dbl, c_i32, P(c_i32), P(c_i32), c_i32, P(c_dbl),
@@ -136,7 +138,8 @@ def lib():
                  "mcd_batch_lanczos_ground", "mcd_hamiltonian_contract", "mcd_band_green_vjp",
                  "mcd_batch_band_green", "mcd_band_lanczos_green_keep", "mcd_band_green_vjp_keep",
                  "mcd_ws_create", "mcd_ws_stats", "mcd_op_workspace_size",
-                 "mcd_lanczos_workspace_size", "mcd_band_workspace_size"):
+                 "mcd_lanczos_workspace_size", "mcd_band_workspace_size",
+                 "mcd_hamiltonian_contract_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -397,6 +400,20 @@ class Operator:
             self.handle, ctypes.byref(self._mb.s), c_vp(a.data_ptr()), c_vp(b.data_ptr()),
             dt.ctypes.data_as(P(c_dbl)), dU.ctypes.data_as(P(c_dbl)),
             de.ctypes.data_as(P(c_dbl)), ws, _stream()), "mcd_hamiltonian_contract")
+        return dt, dU, de
+
+    def contract_noalloc(self, a, b=None):
+        """contract() through mcd_hamiltonian_contract_noalloc (no workspace:
+        the library's fixed device scratch)."""
+        b = a if b is None else b
+        m = self.model
+        dt = np.zeros(len(m.bonds))
+        dU = np.zeros(m.n_orb)
+        de = np.zeros(m.n_orb)
+        _check(lib().mcd_hamiltonian_contract_noalloc(
+            self.handle, ctypes.byref(self._mb.s), c_vp(a.data_ptr()), c_vp(b.data_ptr()),
+            dt.ctypes.data_as(P(c_dbl)), dU.ctypes.data_as(P(c_dbl)),
+            de.ctypes.data_as(P(c_dbl)), _stream()), "mcd_hamiltonian_contract_noalloc")
         return dt, dU, de
 
     def close(self):

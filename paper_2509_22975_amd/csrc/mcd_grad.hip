@@ -8,6 +8,7 @@
 // One pass over the rows; each workgroup keeps one partial per parameter and
 // the partials are added in index order (deterministic).
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "mcd_hash.h"
@@ -128,6 +129,34 @@ static size_t contract_scratch_bytes(const mcd_op *op) {
     return ((size_t)np * contract_blocks(op->n) + np) * sizeof(double);
 }
 
+// Scratch of the allocation-free contraction: the workgroup partials of the
+// largest parameter count at the largest grid, and the reduced values
+// (9.4 MB per device, held until the process ends).  Host code never passes
+// `scratch` itself to a kernel: its address on a device is looked up once
+// per device (hipGetSymbolAddress, with that device current) and kept.
+constexpr size_t kNoAllocDoubles = (size_t)kMaxParams * kMaxContractBlocks + kMaxParams;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[64] = {};
+
+static int scratch_address(int dev, double **out) {
+    MCD_REQUIRE(dev >= 0 && dev < 64, MCD_E_INVALID, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr) {
+            set_error("hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                      hipGetErrorString(e));
+            return MCD_E_HIP;
+        }
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MCD_OK;
+}
+
 }  // namespace mcd
 
 using namespace mcd;
@@ -146,4 +175,23 @@ extern "C" int mcd_hamiltonian_contract(const mcd_op *op, const mcd_model *model
     (void)hipStreamSynchronize(s);
     (void)dfree(part, al);
     return rc;
+}
+
+extern "C" int mcd_hamiltonian_contract_noalloc(const mcd_op *op, const mcd_model *model,
+                                                const double *a_dev, const double *b_dev,
+                                                double *d_t, double *d_U, double *d_eps,
+                                                void *stream) {
+    MCD_REQUIRE(op && model && a_dev && b_dev, MCD_E_INVALID, "op, model, a, b required");
+    MCD_REQUIRE(model->n_orb == op->hm.dm.n_orb, MCD_E_INVALID,
+                "model has %d orbitals, operator %d", model->n_orb, op->hm.dm.n_orb);
+    MCD_REQUIRE(contract_scratch_bytes(op) <= kNoAllocDoubles * sizeof(double), MCD_E_CAPACITY,
+                "contraction needs %zu bytes of scratch, the fixed scratch holds %zu",
+                contract_scratch_bytes(op), kNoAllocDoubles * sizeof(double));
+    int dev = 0;
+    MCD_HIP(hipGetDevice(&dev));
+    double *part = nullptr;
+    MCD_TRY(scratch_address(dev, &part));
+    // every partial and output the reduction reads is written by this call's
+    // kernels first (k_contract writes all np x nblk partials)
+    return contract_into(op, model, a_dev, b_dev, part, d_t, d_U, d_eps, (hipStream_t)stream);
 }
