@@ -52,12 +52,14 @@ def _function_text(src: str, marker: str) -> str:
 
 def kernel_source_hash() -> str:
     """Hash of the one-vector kernels whose counters are kept (row-major stream
-    and grouped) and of the functions that launch them (launch shapes): the
-    counters in profiles/ stay valid while these are unchanged."""
+    and grouped), of the functions that launch them (launch shapes) and of the
+    hop enumeration (the CSR's entry order): the counters in profiles/ stay
+    valid while these are unchanged."""
     csrc = os.path.join(HERE, "paper_2509_22975_amd", "csrc")
     op_src = open(os.path.join(csrc, "mcd_op.hip")).read()
     g_src = open(os.path.join(csrc, "mcd_grouped.hip")).read()
-    text = (_function_text(op_src, "void k_spmv_stream(") + _function_text(op_src, "static int csr_one(")
+    text = (_function_text(op_src, "void for_each_hop(")
+            + _function_text(op_src, "void k_spmv_stream(") + _function_text(op_src, "static int csr_one(")
             + _function_text(g_src, "void k_spmv_grouped(") + _function_text(g_src, "int grouped_one("))
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
@@ -67,6 +69,43 @@ PROF_KERNEL = {"stream": "k_spmv_stream<double, 256, 4096>",
                "stream_xcd": "k_spmv_stream<double, 256, 4096>",
                "grouped": "k_spmv_grouped<double, 3072>",
                "grouped_xcd": "k_spmv_grouped<double, 3072>"}
+
+
+def block_source_hash() -> str:
+    """Hash of the block product (the device function shared by the
+    one-operator and many-run kernels, its launch shape, the one-operator
+    kernel and its launcher): the block counters in profiles/ stay valid while
+    these are unchanged."""
+    csrc = os.path.join(HERE, "paper_2509_22975_amd", "csrc")
+    h_src = open(os.path.join(csrc, "mcd_spmm.h")).read()
+    op_src = open(os.path.join(csrc, "mcd_op.hip")).read()
+    text = (_function_text(h_src, "void block_csr_v_rows(")
+            + _function_text(h_src, "int block_rows_per_tile(") + _function_text(h_src, "int block_chunk(")
+            + _function_text(op_src, "void k_block_csr_v(")
+            + _function_text(op_src, "static void launch_block_v("))
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+def block_launch_threads(n, nvec, elem_bytes):
+    """Grid (threads) of the 16-byte-gather block product for n rows and
+    nvec vectors: row tiles of 256 / lanes rows at <= 2 lanes per row, else
+    64 rows; XCD-major."""
+    lanes = nvec // (16 // elem_bytes)
+    rpt = 256 // lanes if lanes <= 2 else 64
+    ntiles = (n + rpt - 1) // rpt
+    return 256 * 8 * ((ntiles + 7) // 8)
+
+
+def block_traffic_from_profile(kname, grid_threads):
+    """HBM bytes per launch of a block product (rocprofv3 kernel name) from the
+    committed PMC summary, if taken on the current source; else None."""
+    p = os.path.join(HERE, "profiles", "block_spmm_c2_pmc.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_sha") != block_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch", {}).get(f"{kname}@{grid_threads}")
 
 
 def traffic_from_profile(kernel, grid_threads):
@@ -133,16 +172,21 @@ def pipeline_c3(mcd, W, torch, max_blocks=200):
     band run stopped when G has converged (g_tol: change between checks 8
     block steps apart, relative to max |G|).
 
-    plain:      float64 Lanczos, then float64 band Lanczos with one single-vector
-                product per block column and full (two-pass) reorthogonalisation,
-                g_tol 1e-9;
-    f64_block:  float64 block products, three-term block recurrence only, 1e-9;
-    chosen:     float32 block products (float64 Gram, recurrence, deflation and
-                resolvent), three-term block recurrence only, 1e-6 (float32
-                vectors hold G to ~1e-6).
-    Every form starts from a float64 ground state at a Ritz residual of 1e-9;
-    errors are against a 1e-12-residual ground state and a float64 band run
-    converged to 1e-10.
+    plain:      float64 Lanczos to a Ritz residual of 1e-9, then float64 band
+                Lanczos with one single-vector product per block column and full
+                (two-pass) reorthogonalisation, g_tol 1e-9;
+    f64_block:  the same ground state; float64 block products, three-term block
+                recurrence only, 1e-9;
+    chosen:     float32 Lanczos vectors (float64 coefficients) to a Ritz estimate
+                of 1e-7, E0 and psi0 refined in float64 (Rayleigh quotient of the
+                float64 Ritz vector); float32 block products (float64 Gram,
+                recurrence, deflation and resolvent), three-term block
+                recurrence only, 1e-6 (float32 vectors hold G to ~1e-6).
+    E0 errors are against the oracle's E0 of the same basis
+    (tests/golden/precision_refs.json) and a GPU float64 solve to 1e-12; G
+    errors against a float64 band run converged to 1e-10 from that solve (the
+    oracle's G at this size is out of the host's reach; precision_vs_oracle
+    states G errors against the oracle on a 20k-state instance).
     """
     import numpy as np
     c = W.config_c3()
@@ -156,17 +200,22 @@ def pipeline_c3(mcd, W, torch, max_blocks=200):
     e_ref, psi_ref, _, _, _ = mcd.lanczos_ground(op, max_iter=3000, tol=1e-12, seed=11)
     G_ref, gref = mcd.band_lanczos_green(m, keys, psi_ref, e_ref, orbs, spins, om,
                                          max_blocks=max_blocks, reorth=2, g_tol=1e-10)
+    gold = json.load(open(os.path.join(HERE, "tests", "golden", "precision_refs.json")))["c3"]
+    e_or = gold["e0"] if gold["n"] == keys.numel() else None
     out = {"workload": "2x2 plaquette + 8 baths, U=8, half filling, 0.5M chain states, p=8, "
                        "64 Matsubara frequencies (beta=50), band runs to convergence",
-           "n_states": int(keys.numel()), "reference_blocks": gref.iters}
-    for form, prec, percol, reo, gt in (("plain", "f64", True, 2, 1e-9),
-                                        ("f64_block", "f64", False, 0, 1e-9),
-                                        ("chosen", "f32", False, 0, 1e-6)):
+           "n_states": int(keys.numel()), "reference_blocks": gref.iters,
+           "e0_oracle": e_or, "e0_ref_gpu_rel_err_vs_oracle":
+               None if e_or is None else abs(e_ref - e_or) / abs(e_or)}
+    for form, lprec, ltol, prec, percol, reo, gt in (
+            ("plain", "f64", 1e-9, "f64", True, 2, 1e-9),
+            ("f64_block", "f64", 1e-9, "f64", False, 0, 1e-9),
+            ("chosen", "f32", 1e-7, "f32", False, 0, 1e-6)):
         for rep in range(2):          # second repetition is timed
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            e0, psi, _, _, si = mcd.lanczos_ground(op, max_iter=3000, tol=1e-9, seed=11,
-                                                   check_every=10)
+            e0, psi, _, _, si = mcd.lanczos_ground(op, max_iter=3000, tol=ltol, seed=11,
+                                                   check_every=10, precision=lprec)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             G, gi = mcd.band_lanczos_green(m, keys, psi, e0, orbs, spins, om,
@@ -176,7 +225,9 @@ def pipeline_c3(mcd, W, torch, max_blocks=200):
             t2 = time.perf_counter()
         out[form] = {"e0_s": round(t1 - t0, 4), "green_s": round(t2 - t1, 4),
                      "total_s": round(t2 - t0, 4), "lanczos_iters": si.iters,
+                     "lanczos_precision": lprec, "lanczos_tol": ltol,
                      "e0_rel_err": abs(e0 - e_ref) / abs(e_ref),
+                     "e0_rel_err_vs_oracle": None if e_or is None else abs(e0 - e_or) / abs(e_or),
                      "G_rel_err": float(np.max(np.abs(G - G_ref)) / np.max(np.abs(G_ref))),
                      "g_tol": gt, "block_steps": gi.iters, "reorth_passes": reo,
                      "n_plus": gi.n_plus, "n_minus": gi.n_minus, "krylov_dim": gi.krylov_dim}
@@ -184,6 +235,95 @@ def pipeline_c3(mcd, W, torch, max_blocks=200):
     out["speedup_green"] = round(out["plain"]["green_s"] / out["chosen"]["green_s"], 3)
     op.close()
     return out
+
+
+def precision_vs_oracle(mcd, W, torch):
+    """E0 and G(i w_n) of the plain and chosen forms against the oracle's
+    (tests/golden/precision_refs.json: 20k-state chain basis of the
+    plaquette + bath model, seed 5; 4 sites x 2 spins, 16 Matsubara
+    frequencies; the oracle's band Lanczos run to convergence)."""
+    import numpy as np
+    g = json.load(open(os.path.join(HERE, "tests", "golden", "precision_refs.json")))["g20k"]
+    m = W.impurity_plaquette_bath(g["model_seed"])
+    keys, _ = mcd.basis_build(m, "chain", start_key=W.neel_start(m), seed=g["chain_seed"],
+                              n_f=g["n_f"], burn_in=g["burn_in"], max_steps=g["max_steps"],
+                              beta_s=0.5)
+    if keys.numel() != g["n"]:
+        return {"skipped": f"basis has {keys.numel()} states, the reference {g['n']}"}
+    om = W.matsubara(g["n_freq"], g["beta_m"])
+    orbs = g["orbitals"] * 2
+    spins = [0] * 4 + [1] * 4
+    Go = np.zeros((len(om), 8, 8), complex)
+    for sp in (0, 1):
+        blk = np.array(g["G"][sp])
+        Go[:, 4 * sp:4 * sp + 4, 4 * sp:4 * sp + 4] = (blk[..., 0] + 1j * blk[..., 1]).reshape(
+            len(om), 4, 4)
+    op = mcd.Operator(m, keys, storage="csr")
+    out = {"workload": f"plaquette + 8 baths (seed {g['model_seed']}), {g['n']} chain states, "
+                       f"p=8, {len(om)} Matsubara frequencies (beta={g['beta_m']})",
+           "e0_oracle": g["e0"]}
+    for form, lprec, ltol, prec, reo, gt in (("plain", "f64", 1e-9, "f64", 2, 1e-9),
+                                             ("chosen", "f32", 1e-7, "f32", 0, 1e-6)):
+        e0, psi, _, _, si = mcd.lanczos_ground(op, max_iter=3000, tol=ltol, seed=11,
+                                               check_every=10, precision=lprec)
+        G, gi = mcd.band_lanczos_green(m, keys, psi, e0, orbs, spins, om, max_blocks=300,
+                                       precision=prec, reorth=reo, g_tol=gt)
+        out[form] = {"e0_rel_err": abs(e0 - g["e0"]) / abs(g["e0"]),
+                     "G_rel_err": float(np.max(np.abs(G - Go)) / np.max(np.abs(Go))),
+                     "lanczos_iters": si.iters, "block_steps": gi.iters}
+    op.close()
+    return out
+
+
+def large_nnz_16site(mcd, W, torch):
+    """The one-vector float64 product and the float32 x 8 block product on a
+    whole 16-site sector: 4x4 periodic square, U=8, (8,8), 165,636,900 states
+    (the paper's largest full-ED sector), every state kept (f = 1)."""
+    m = W.square(4, 4, t=1.0, U=8.0, mu=4.0, pbc=True)
+    t0 = time.perf_counter()
+    keys, _ = mcd.basis_build(m, "full")
+    op = mcd.Operator(m, keys, storage="csr", validate=False)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    del keys
+    info = op.info()
+    n, nnz = info["n"], info["nnz"]
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(21)
+    x = torch.rand(n, dtype=torch.float64, device=dev, generator=gen) * 2 - 1
+    y = torch.empty_like(x)
+    s = torch.cuda.current_stream()
+
+    def timed(xx, yy, reps):
+        for _ in range(2):
+            op.apply(xx, out=yy)
+        e_a, e_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e_a.record(s)
+        for _ in range(reps):
+            op.apply(xx, out=yy)
+        e_b.record(s)
+        e_b.synchronize()
+        return e_a.elapsed_time(e_b) / reps
+
+    ms1 = timed(x, y, 20)
+    b1 = 8.0 * (n + 1) + 4.0 * nnz + 24.0 * n
+    if info["kernel"] in ("grouped", "grouped_xcd"):
+        b1 += 16.0 * (info["grouped_blocks"] + 1) + 8.0 * (info["grouped_groups"] + 1)
+    del x, y
+    X = torch.rand((n, 8), dtype=torch.float32, device=dev, generator=gen) * 2 - 1
+    Y = torch.empty_like(X)
+    ms8 = timed(X, Y, 10)
+    b8 = 8.0 * (n + 1) + 4.0 * nnz + 8.0 * n + 2.0 * n * 8 * 4
+    del X, Y
+    op.close()
+    return {"workload": "4x4 periodic square, t=1, U=8, (8,8) full sector, f = 1",
+            "n_states": n, "nnz_offdiag": nnz, "build_s": round(build_s, 2),
+            "f64_one_vector": {"kernel": info["kernel"], "ms": round(ms1, 4),
+                               "bytes": b1, "GBs": round(b1 / ms1 / 1e6, 1),
+                               "frac": round(b1 / ms1 / 1e6 / HBM_PEAK_GBS, 4)},
+            "f32_block8": {"ms": round(ms8, 4), "bytes": b8, "GBs": round(b8 / ms8 / 1e6, 1),
+                           "frac": round(b8 / ms8 / 1e6 / HBM_PEAK_GBS, 4)}}
 
 
 def batch_c3(mcd, W, torch, n_inst=32):
@@ -485,6 +625,10 @@ def main():
                     help="skip the paper's 16-site ring end to end")
     ap.add_argument("--no-c5", action="store_true",
                     help="skip the 32-site, 50M-state cluster")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the plain / chosen forms against the oracle's stored values")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 16-site full-sector (165.6M states) products")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 32-instance batched ground-state comparison")
     ap.add_argument("--copy-probe", action="store_true",
@@ -586,8 +730,20 @@ def main():
             ms = e_a.elapsed_time(e_b) / 20
             byts = 8.0 * (n + 1) + 4.0 * nnz + 8.0 * n + 2.0 * n * b * X.element_size()
             spmm[f"{tname}_b{b}"] = {"ms": round(ms, 4), "ms_per_vector": round(ms / b, 5),
-                                     "GBs": round(byts / ms / 1e6, 1)}
+                                     "GBs": round(byts / ms / 1e6, 1), "bytes": byts,
+                                     "frac": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4)}
             del X, Y
+    # The chosen form's product: float32 blocks of 8 vectors (p = 8 band runs;
+    # the many-run band kernel runs the same device function per row tile).
+    ch = 4 if nnz < 4 * n else 8 if nnz < 10 * n else 16
+    bk = f"k_block_csr_v<float, 8, {ch}>"
+    b8 = spmm["f32_b8"]
+    gthreads = block_launch_threads(n, 8, 4)
+    roof_block = {"bound": "hbm", "achieved": b8["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": b8["frac"], "traffic": block_traffic_from_profile(bk, gthreads),
+                  "kernel": bk, "kernel_ms": b8["ms"], "algorithmic_bytes": b8["bytes"],
+                  "bytes_model": "8(n+1) row pointers + 4 nnz entry words + 8n diagonal "
+                                 "+ n*8*4 read X + n*8*4 write Y"}
     kernel_names = {"grouped": "k_spmv_grouped<double,3072>",
                     "grouped_xcd": "k_spmv_grouped<double,3072> (XCD-major order)",
                     "stream": "k_spmv_stream<double,256,4096>",
@@ -618,12 +774,15 @@ def main():
                      "ms_per_kernel_variant": per_kernel},
         "cpu_baseline": None,
         "block_spmm": spmm,
+        "roofline_block_spmm": roof_block,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(m, mcd.keys_to_numpy(keys), x.cpu().numpy(),
                                            nnz / n)
     if not args.no_pipeline:
         out["pipeline_e0_green"] = pipeline_c3(mcd, W, torch)
+    if not args.no_precision:
+        out["precision_vs_oracle"] = precision_vs_oracle(mcd, W, torch)
     if not args.no_batch:
         out["batch_ground_states"] = batch_c3(mcd, W, torch)
     if not args.no_sampler:
@@ -634,6 +793,8 @@ def main():
         out["gradients_c4"] = gradients_c4(mcd, W, torch)
     if not args.no_c5:
         out["c5_32_sites"] = c5_cluster(mcd, W, torch)
+    if not args.no_large:
+        out["large_nnz_16site"] = large_nnz_16site(mcd, W, torch)
     if args.copy_probe:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)

@@ -111,6 +111,18 @@ void mcd_ws_destroy(mcd_ws *ws);
 int mcd_ws_stats(const mcd_ws *ws, size_t *size, size_t *in_use, size_t *high_water,
                  size_t *need);
 
+/* Debugging aid.  With MCD_WS_POISON set, every floating-point piece the
+ * library takes from `ws` from then on (vectors, Krylov blocks, Gram
+ * partials, coefficient and recurrence stores, reduction scratch) is filled
+ * with all-ones bytes -- NaN in float32 and float64 -- by a kernel on the
+ * taking call's stream, so any result that depends on a read of such a piece
+ * before its first write comes out NaN (or differs from an unpoisoned call).
+ * Index, key and counter pieces are left as they are.  Results of correct
+ * code are bit for bit those without the flag; the fills cost time only.
+ * flags = 0 turns it off.  MCD_E_INVALID for a NULL handle or unknown bits. */
+#define MCD_WS_POISON 1
+int mcd_ws_set_debug(mcd_ws *ws, int32_t flags);
+
 /* ---------------------------------------------------------------------------
  * mcd_basis_build -- the truncated basis F~ (Sec. Subspace of the ground
  * state; Sec. Other sampling methods).
@@ -275,10 +287,11 @@ int mcd_hamiltonian_diagonal(const mcd_op *op, double *diag_dev, void *stream);
 /* ---------------------------------------------------------------------------
  * mcd_hamiltonian_connectivity -- the off-diagonal elements of rows
  * [row0, row1) as (row, col, value) triples, in the order the operator
- * enumerates them (bond order, up before down), for checking connectivity and
- * signs exactly.  rows_dev, cols_dev: int64 [cap]; vals_dev: double [cap].
- * count_out (host) = number of triples; MCD_E_CAPACITY if cap is too small.
- * ws: 8 (row1 - row0) bytes of scratch.  Synchronises.
+ * enumerates them (up-spin hops in bond order, then down-spin hops in bond
+ * order), for checking connectivity and signs exactly.  rows_dev, cols_dev:
+ * int64 [cap]; vals_dev: double [cap].  count_out (host) = number of
+ * triples; MCD_E_CAPACITY if cap is too small.  ws: 8 (row1 - row0) bytes of
+ * scratch.  Synchronises.
  * ------------------------------------------------------------------------- */
 int mcd_hamiltonian_connectivity(const mcd_op *op, int64_t row0, int64_t row1, int64_t *rows_dev,
                                  int64_t *cols_dev, double *vals_dev, int64_t cap,

@@ -95,6 +95,7 @@ def lib():
     L.mcd_ws_destroy.argtypes = [c_vp]
     L.mcd_ws_destroy.restype = None
     L.mcd_ws_stats.argtypes = [c_vp, P(c_sz), P(c_sz), P(c_sz), P(c_sz)]
+    L.mcd_ws_set_debug.argtypes = [c_vp, c_i32]
     L.mcd_basis_build.argtypes = [P(McdModel), P(McdBasisCfg), c_vp, c_i64, P(c_i64), P(c_i64),
                                   c_vp, c_vp]
     L.mcd_op_create.argtypes = [P(McdModel), c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, P(c_vp)]
@@ -137,7 +138,7 @@ def lib():
                  "mcd_hamiltonian_connectivity", "mcd_lanczos_ground", "mcd_band_lanczos_green",
                  "mcd_batch_lanczos_ground", "mcd_hamiltonian_contract", "mcd_band_green_vjp",
                  "mcd_batch_band_green", "mcd_band_lanczos_green_keep", "mcd_band_green_vjp_keep",
-                 "mcd_ws_create", "mcd_ws_stats", "mcd_op_workspace_size",
+                 "mcd_ws_create", "mcd_ws_stats", "mcd_ws_set_debug", "mcd_op_workspace_size",
                  "mcd_lanczos_workspace_size", "mcd_band_workspace_size",
                  "mcd_hamiltonian_contract_noalloc"):
         getattr(L, name).restype = ctypes.c_int
@@ -168,9 +169,14 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+WS_POISON = 1          # mcd_ws_set_debug: NaN-fill floating-point pieces on take
+_WS_DEBUG = 0
+
+
 class Workspace:
     """A caller-owned device buffer handed to the library (mcd_ws): a
-    torch.uint8 tensor of `nbytes` bytes on `device` and its handle."""
+    torch.uint8 tensor of `nbytes` bytes on `device` and its handle.  New
+    workspaces take the flags set by ``workspace_debug``."""
 
     def __init__(self, nbytes, device="cuda"):
         torch = _torch()
@@ -182,6 +188,11 @@ class Workspace:
         _check(lib().mcd_ws_create(c_vp(self.buf.data_ptr()), self.nbytes, ctypes.byref(h)),
                "mcd_ws_create")
         self._h = h
+        if _WS_DEBUG:
+            self.set_debug(_WS_DEBUG)
+
+    def set_debug(self, flags: int):
+        _check(lib().mcd_ws_set_debug(self._h, int(flags)), "mcd_ws_set_debug")
 
     @property
     def handle(self):
@@ -207,6 +218,16 @@ class Workspace:
 
 
 _SCRATCH = {}
+
+
+def workspace_debug(flags: int):
+    """Debug flags (WS_POISON or 0) for every workspace created from now on
+    and for the current scratch workspaces; returns the previous flags."""
+    global _WS_DEBUG
+    old, _WS_DEBUG = _WS_DEBUG, int(flags)
+    for ws in _SCRATCH.values():
+        ws.set_debug(_WS_DEBUG)
+    return old
 
 
 def _scratch_key():

@@ -1269,7 +1269,7 @@ struct MRTable {
             P = r->P;
             mb = r->mb;
             nstore = r->nstore;
-            rpt = std::max(64, (256 / (r->P / VN)) / 2);   // as the one-run product
+            rpt = block_rows_per_tile(r->P / VN);   // as the one-run product
             MRun d;
             memset(&d, 0, sizeof(d));
             d.n = r->n;
@@ -1297,7 +1297,7 @@ struct MRTable {
             host.push_back(d);
         }
         nrun = (int)host.size();
-        ch = (nnz < 4 * rows) ? 4 : (nnz < 10 * rows) ? 8 : 16;
+        ch = block_chunk(P / VN, (nnz < 4 * rows) ? 4 : (nnz < 10 * rows) ? 8 : 16);
         if (nrun > 0)
             MCD_HIP(hipMemcpyAsync(dev, host.data(), nrun * sizeof(MRun), hipMemcpyHostToDevice, s));
         return MCD_OK;
@@ -1649,6 +1649,7 @@ static int run_allocate(BandRun<T> &r) {
                       sz[i] / 1048576.0);
             return hip_status(e);
         }
+        if (i < 8) MCD_HIP(poison_fp(*dst[i], sz[i], r.al, r.s));   // all but d_rank
     }
     return MCD_OK;
 }
@@ -1753,12 +1754,16 @@ static int wt_cut(const uint64_t *keys_dev, int64_t n, const double *psi0_dev, d
     CK(dmalloc((void **)&idx, n * sizeof(uint32_t), A));
     CK(dmalloc((void **)&kept, n * sizeof(uint32_t), A));
     CK(dmalloc((void **)&scr, (4096 + 8) * sizeof(double), A));
+    CK(poison_fp(psi_t, n * sizeof(double), A, s));
+    CK(poison_fp(w, n * sizeof(double), A, s));
+    CK(poison_fp(scr, (4096 + 8) * sizeof(double), A, s));
     hipLaunchKernelGGL(k_weights, dim3(gridn(n, 256)), dim3(256), 0, s, n, psi0_dev, w, idx);
     CK(hipGetLastError());
     int64_t n_keep = n;
     if (w_t < 1.0) {
         CK(dmalloc((void **)&w2, n * sizeof(double), A));
         CK(dmalloc((void **)&idx2, n * sizeof(uint32_t), A));
+        CK(poison_fp(w2, n * sizeof(double), A, s));
         size_t b1 = 0;
         CK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, b1, w, w2, idx, idx2, (int)n, 0,
                                                         64, s));
@@ -2502,6 +2507,8 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     // reproduce the forward's recurrence (and stopping point) bit for bit
     CK(dmalloc((void **)&psi_n, n * sizeof(double), A));
     CK(dmalloc((void **)&scr, (4096 + 8) * sizeof(double), A));
+    CK(poison_fp(psi_n, n * sizeof(double), A, s));
+    CK(poison_fp(scr, (4096 + 8) * sizeof(double), A, s));
     CK(hipMemcpyAsync(psi_n, psi0_dev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     {
         const unsigned nbn = std::min<unsigned>(gridn(n, BS), 2048);
@@ -2515,10 +2522,14 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     CK(dmalloc((void **)&lam, n * sizeof(double), A));
     CK(dmalloc((void **)&acc, np * sizeof(double), A));
     CK(dmalloc((void **)&scal, 8 * sizeof(double), A));
+    CK(poison_fp(lam, n * sizeof(double), A, s));
+    CK(poison_fp(acc, np * sizeof(double), A, s));
+    CK(poison_fp(scal, 8 * sizeof(double), A, s));
     CK(hipMemsetAsync(lam, 0, n * sizeof(double), s));
     CK(hipMemsetAsync(acc, 0, np * sizeof(double), s));
     const int cblk = 16384;   // contraction workgroups at most (partials per parameter)
     CK(dmalloc((void **)&part, (size_t)np * cblk * sizeof(double), A));
+    CK(poison_fp(part, (size_t)np * cblk * sizeof(double), A, s));
 
     double trM = 0.0;   // sum over sectors of tr(M)
     int krylov = 0;
@@ -2602,8 +2613,8 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             int pl = 0;
             while ((1 << pl) < P) pl++;
             constexpr int kTail = 1024;   // zeroed values after the last row of Zt
-            // Zt, M and its factors from the chunk cache (an arena released at
-            // the end of the hook): repeated derivative calls reuse the memory
+            // Zt, M and its factors: workspace pieces released together at the
+            // end of the hook
             Arena zarena(ws);
             T *Zt = nullptr, *Md = nullptr;
             double *dA = nullptr, *dB = nullptr;
@@ -2615,6 +2626,12 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
                           (double)nx * S * sizeof(T) / 1e9);
                 rc = MCD_E_WORKSPACE;
             }
+            if (rc == MCD_OK &&
+                (poison_fp(Zt, ((size_t)nx * S + kTail) * sizeof(T), zarena.al, s) != hipSuccess ||
+                 poison_fp(Md, (size_t)S * S * sizeof(T), zarena.al, s) != hipSuccess ||
+                 poison_fp(dA, Am.size() * sizeof(double), zarena.al, s) != hipSuccess ||
+                 poison_fp(dB, Bm.size() * sizeof(double), zarena.al, s) != hipSuccess))
+                rc = MCD_E_HIP;
             if (rc == MCD_OK &&
                 (hipMemcpyAsync(dA, Am.data(), Am.size() * sizeof(double), hipMemcpyHostToDevice,
                                 s) != hipSuccess ||
@@ -2700,6 +2717,7 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     CK(dmalloc((void **)&dir, n * sizeof(double), A));
     CK(dmalloc((void **)&adir, n * sizeof(double), A));
     CK(dmalloc((void **)&zv, n * sizeof(double), A));
+    for (double *v : {xi, res, dir, adir, zv}) CK(poison_fp(v, n * sizeof(double), A, s));
     const unsigned gv = gridn(n, 256);
     const unsigned gp = std::min<unsigned>(gridn(n, BS), 2048);   // partial-sum kernels
     const double dfloor = 1e-6 * std::max(1.0, fabs(e0));

@@ -296,12 +296,17 @@ extern "C" int mcd_batch_lanczos_ground(mcd_op *const *ops, int32_t n_ops,
     CK(dmalloc((void **)&U, store_bytes, al));
     CK(dmalloc((void **)&Y, Ntot * sizeof(double), al));
     CK(dmalloc((void **)&sc, (size_t)2 * K * stride * sizeof(double), al));
+    CK(poison_fp(U, store_bytes, al, s));
+    CK(poison_fp(Y, Ntot * sizeof(double), al, s));
+    CK(poison_fp(sc, (size_t)2 * K * stride * sizeof(double), al, s));
     CK(hipMemsetAsync(sc, 0, (size_t)2 * K * stride * sizeof(double), s));
     CK(dmalloc((void **)&part, std::max(nb, ub) * sizeof(double), al));
+    CK(poison_fp(part, std::max(nb, ub) * sizeof(double), al, s));
     // psi coefficients of every instance, then the norm partials (at most
     // 2048 workgroups) and one squared norm per instance
     constexpr int kNormPart = 2048;
     CK(dmalloc((void **)&coef, ((size_t)K * stride + kNormPart + K) * sizeof(double), al));
+    CK(poison_fp(coef, ((size_t)K * stride + kNormPart + K) * sizeof(double), al, s));
     CK(dmalloc((void **)&iv, (K + 1) * sizeof(int), al));
     std::vector<int> hact(K + 1, 1);
     hact[K] = 0;   // step counter

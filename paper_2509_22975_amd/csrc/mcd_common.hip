@@ -36,6 +36,22 @@ hipError_t dfree(void *p, const Alloc &a) {
     return hipSuccess;
 }
 
+// All-ones 16-byte words over a piece (pieces are whole 256-byte units).
+__global__ __launch_bounds__(256) void k_poison(uint4 *p, int64_t words) {
+    const uint4 v = make_uint4(~0u, ~0u, ~0u, ~0u);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * 256)
+        p[i] = v;
+}
+
+hipError_t poison_fp(void *p, size_t bytes, const Alloc &a, hipStream_t s) {
+    if (p == nullptr || a.ws == nullptr || !(a.ws->debug & MCD_WS_POISON)) return hipSuccess;
+    const int64_t words = (int64_t)(WsAlloc::round(bytes) / 16);
+    const unsigned grid = (unsigned)std::min<int64_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_poison, dim3(grid), dim3(256), 0, s, (uint4 *)p, words);
+    return hipGetLastError();
+}
+
 void set_error(const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
@@ -139,6 +155,15 @@ extern "C" int mcd_ws_stats(const mcd_ws *ws, size_t *size, size_t *in_use, size
     if (in_use) *in_use = ws->a.in_use();
     if (high_water) *high_water = ws->a.high_water();
     if (need) *need = ws->a.need();
+    return MCD_OK;
+}
+
+extern "C" int mcd_ws_set_debug(mcd_ws *ws, int32_t flags) {
+    MCD_REQUIRE(ws != nullptr, MCD_E_INVALID, "ws is NULL");
+    MCD_REQUIRE((flags & ~MCD_WS_POISON) == 0, MCD_E_INVALID, "unknown workspace flags 0x%x",
+                (unsigned)flags);
+    std::lock_guard<std::mutex> lock(ws->mu);
+    ws->debug = flags;
     return MCD_OK;
 }
 extern "C" int mcd_version(void) { return 10000; }

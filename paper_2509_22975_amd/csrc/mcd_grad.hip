@@ -171,6 +171,11 @@ extern "C" int mcd_hamiltonian_contract(const mcd_op *op, const mcd_model *model
     const Alloc al{ws};
     double *part = nullptr;
     MCD_HIP(dmalloc((void **)&part, contract_scratch_bytes(op), al));
+    if (poison_fp(part, contract_scratch_bytes(op), al, s) != hipSuccess) {
+        (void)dfree(part, al);
+        set_error("contract: workspace fill failed");
+        return MCD_E_HIP;
+    }
     const int rc = contract_into(op, model, a_dev, b_dev, part, d_t, d_U, d_eps, s);
     (void)hipStreamSynchronize(s);
     (void)dfree(part, al);

@@ -116,6 +116,11 @@ hipError_t dfree(void *p, const Alloc &a);                    // NULL is ignored
 // MCD status of a failed HIP call or allocation: MCD_E_WORKSPACE when the
 // workspace ran out (dmalloc's hipErrorOutOfMemory), else MCD_E_HIP.
 int hip_status(hipError_t e);
+// Marks a piece of floating-point data just taken from a.ws: with the
+// workspace's MCD_WS_POISON flag it is filled with all-ones bytes (NaN) on
+// stream s, so reads before the first write show up in the results; a no-op
+// otherwise.
+hipError_t poison_fp(void *p, size_t bytes, const Alloc &a, hipStream_t s);
 
 // Pieces taken together and released together (reverse order of taking):
 // every buffer of a short-lived step (a band run and its operator) in one
@@ -159,6 +164,7 @@ struct mcd_ws {
     char *base;
     mcd::WsAlloc a;
     std::mutex mu;
+    int debug = 0;   // MCD_WS_POISON
     mcd_ws(void *b, size_t bytes) : base((char *)b), a(bytes) {}
 };
 

@@ -232,6 +232,11 @@ static int lanczos_run(const mcd_op *op, const mcd_lanczos_cfg *cfg, const doubl
     const Alloc al{ws};
     char *wsp = nullptr;
     MCD_HIP(dmalloc((void **)&wsp, L.total(), al));
+    if (poison_fp(wsp, L.total(), al, s) != hipSuccess) {
+        (void)dfree(wsp, al);
+        set_error("lanczos: workspace fill failed");
+        return MCD_E_HIP;
+    }
     T *U = (T *)wsp;
     T *y = (T *)(wsp + L.vec_bytes);
     double *y64 = (double *)(wsp + L.vec_bytes + L.y_bytes);

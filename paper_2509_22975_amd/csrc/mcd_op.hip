@@ -69,9 +69,14 @@ __global__ void k_hash_insert(int64_t n, const uint64_t *__restrict__ keys, Hash
     }
 }
 
-// Visit every kept hop of the state `key` in canonical order (bond order, up
-// spin before down).  f(col, bond) is called for each image found in the
-// basis; `neg` = element sign bit = JW parity XOR sign of t.
+// Visit every kept hop of the state `key` in canonical order: the up-spin
+// hops in bond order, then the down-spin hops in bond order.  Whether an up
+// hop exists depends on the up string alone, so the rows of one up-string
+// segment list their up hops first and alike: entry j of consecutive rows of
+// a segment (in a full sector) is the same bond, whose images are
+// consecutive rows of one target segment, and the row-parallel block
+// products gather them together.  f(col, bond) is called for each image
+// found in the basis; `neg` = element sign bit = JW parity XOR sign of t.
 template <typename F>
 __device__ __forceinline__ void for_each_hop(uint64_t key, const DevModel *__restrict__ m,
                                              const HashSlot *__restrict__ h, uint64_t hmask,
@@ -80,14 +85,16 @@ __device__ __forceinline__ void for_each_hop(uint64_t key, const DevModel *__res
     const int nb = m->n_bonds;
     for (int b = 0; b < nb; b++) {
         const uint32_t mask = m->bonds[b].mask;
-        const uint32_t between = m->bonds[b].between;
         if (__popc(up & mask) == 1) {
             const int64_t c = hash_find(h, hmask, key ^ ((uint64_t)mask << 32));
-            if (c >= 0) f(c, b, (uint32_t)(__popc(up & between) & 1));
+            if (c >= 0) f(c, b, (uint32_t)(__popc(up & m->bonds[b].between) & 1));
         }
+    }
+    for (int b = 0; b < nb; b++) {
+        const uint32_t mask = m->bonds[b].mask;
         if (__popc(dn & mask) == 1) {
             const int64_t c = hash_find(h, hmask, key ^ (uint64_t)mask);
-            if (c >= 0) f(c, b, (uint32_t)(__popc(dn & between) & 1));
+            if (c >= 0) f(c, b, (uint32_t)(__popc(dn & m->bonds[b].between) & 1));
         }
     }
 }
@@ -651,6 +658,7 @@ static int csr_fill(mcd_op *op, hipStream_t s) {
     MCD_HIP(dmalloc((void **)&op->d_split_j, (op->nchunks + 1) * sizeof(int64_t), op->alloc));
     MCD_HIP(dmalloc((void **)&op->d_carry, op->nchunks * sizeof(double), op->alloc));
     MCD_HIP(dmalloc((void **)&op->d_carry_row, op->nchunks * sizeof(int64_t), op->alloc));
+    MCD_HIP(poison_fp(op->d_carry, op->nchunks * sizeof(double), op->alloc, s));
     op->device_bytes += op->nchunks * 32;
     hipLaunchKernelGGL(k_merge_splits, dim3(grid_for(op->nchunks + 1, 256)), dim3(256), 0, s, n,
                        op->nchunks, op->d_rowptr, op->d_split_i, op->d_split_j);
@@ -761,6 +769,14 @@ static int tune_kernel(mcd_op *op, hipStream_t s) {
         (void)dfree(x, op->alloc);
         MCD_HIP(ey);
     }
+    if (poison_fp(x, op->n * sizeof(double), op->alloc, s) != hipSuccess ||
+        poison_fp(y, op->n * sizeof(double), op->alloc, s) != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        (void)dfree(x, op->alloc);
+        (void)dfree(y, op->alloc);
+        MCD_HIP(hipGetLastError());
+        return MCD_E_HIP;
+    }
     hipEvent_t a = nullptr, b = nullptr;
     auto done = [&](int rc) {
         if (a) (void)hipEventDestroy(a);
@@ -825,21 +841,22 @@ static int tune_kernel(mcd_op *op, hipStream_t s) {
 }
 
 // Block CSR product with 16-byte gathers (k_block_csr_v), when a row of the
-// block is a whole number of them: tiles of max(64, rows per pass / 2) rows
-// (measured best for float and double at 8 and 16 vectors).
+// block is a whole number of them; launch shape from block_rows_per_tile /
+// block_chunk.
 template <typename T, int NV>
 static void launch_block_v(const mcd_op *op, const T *x, T *y, hipStream_t s) {
     if constexpr (NV % Vec16<T>::n == 0) {
         constexpr int L = NV / Vec16<T>::n;
-        const int rpt = std::max(64, (256 / L) / 2);
+        const int rpt = block_rows_per_tile(L);
+        const int ch = block_chunk(L, op->group_chunk);
         const int64_t n = op->n;
         const int64_t ntiles = (n + rpt - 1) / rpt;
         const unsigned grid = (unsigned)(kNumXcd * ((ntiles + kNumXcd - 1) / kNumXcd));
-        if (op->group_chunk == 4)
+        if (ch == 4)
             hipLaunchKernelGGL((k_block_csr_v<T, NV, 4>), dim3(grid), dim3(256), 0, s, n,
                                op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x, y, ntiles,
                                rpt);
-        else if (op->group_chunk == 8)
+        else if (ch == 8)
             hipLaunchKernelGGL((k_block_csr_v<T, NV, 8>), dim3(grid), dim3(256), 0, s, n,
                                op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x, y, ntiles,
                                rpt);
@@ -952,6 +969,7 @@ static int op_index(mcd_op *op, const uint64_t *keys_dev, int32_t validate, hipS
         MCD_HIP(hipMemcpyAsync(op->d_keys, keys_dev, n * sizeof(uint64_t), hipMemcpyDeviceToDevice,
                                s));
     MCD_HIP(dmalloc((void **)&op->d_diag, nn * sizeof(double), op->alloc));
+    MCD_HIP(poison_fp(op->d_diag, nn * sizeof(double), op->alloc, s));
     op->device_bytes = sizeof(DevModel) + nn * 16;
     if (validate && n) {
         int *bad = nullptr, hbad = 0;
@@ -987,6 +1005,8 @@ static int op_index(mcd_op *op, const uint64_t *keys_dev, int32_t validate, hipS
     MCD_HIP(dmalloc((void **)&op->d_counter, 8 * sizeof(unsigned int), op->alloc));
     MCD_HIP(hipMemsetAsync(op->d_counter, 0, 8 * sizeof(unsigned int), s));
     MCD_HIP(dmalloc((void **)&op->d_scalars, 64 * sizeof(double), op->alloc));
+    MCD_HIP(poison_fp(op->d_partials, op->max_partials * sizeof(double), op->alloc, s));
+    MCD_HIP(poison_fp(op->d_scalars, 64 * sizeof(double), op->alloc, s));
     op->device_bytes += op->max_partials * sizeof(double);
     return MCD_OK;
 }

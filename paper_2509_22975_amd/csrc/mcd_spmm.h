@@ -40,6 +40,14 @@ __device__ __forceinline__ void vscale_add(double2 &acc, double a, const double2
     acc.y += a * x.y;
 }
 
+// Launch shape of the row-parallel block product with L lanes per row
+// (measured on gfx950, C2 basis, 8 and 16 vectors): row tiles that keep all
+// 256 threads busy at L <= 2 and 64-row tiles above; at most 8 gathers in
+// flight per lane at L >= 4 (ch: words per chunk from the mean row length).
+// Neither changes a row's sum (entry order either way).
+inline int block_rows_per_tile(int L) { return L <= 2 ? 256 / L : 64; }
+inline int block_chunk(int L, int ch) { return L >= 4 ? (ch < 8 ? ch : 8) : ch; }
+
 // Y[r] = d_r X[r] + sum over the row's entries of +-|t| X[col] for the rows
 // [rbeg, rend) of an n-row block of NV vectors (row-major, 16-byte aligned):
 // L = NV / (16 / sizeof T) lanes per row, each lane 16 bytes of the gathered
