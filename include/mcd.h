@@ -460,6 +460,11 @@ typedef struct mcd_band_cfg {
                                  axis and 7 evenly spaced) changes by <= g_tol
                                  max|G| between checks 8 block steps apart;
                                  0: run max_blocks steps (or to exhaustion) */
+    int32_t vjp_freq_batch;   /* derivative calls: frequencies per pass of the
+                                 contraction (0: all in one pass); each pass holds
+                                 two n x 2 batch p work matrices per sector */
+    int32_t vjp_chunk;        /* derivative calls: Krylov blocks per accumulation
+                                 (0: 16) */
 } mcd_band_cfg;
 
 int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int64_t n,

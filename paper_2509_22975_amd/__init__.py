@@ -73,7 +73,7 @@ class McdSolveInfo(ctypes.Structure):
 class McdBandCfg(ctypes.Structure):
     _fields_ = [("max_blocks", c_i32), ("precision", c_i32), ("w_t", c_dbl), ("dtol", c_dbl),
                 ("storage", c_i32), ("reorth", c_i32), ("per_column", c_i32), ("eta", c_dbl),
-                ("g_tol", c_dbl)]
+                ("g_tol", c_dbl), ("vjp_freq_batch", c_i32), ("vjp_chunk", c_i32)]
 
 
 _lib = None
@@ -562,10 +562,12 @@ def batch_lanczos_ground(ops, max_iter=400, tol=1e-12, seed=0, check_every=10, m
     return list(e0), psis, list(it), SolveInfo.of(info)
 
 
-def _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, per_column, eta, g_tol=0.0):
+def _band_cfg(max_blocks, precision, w_t, dtol, storage, reorth, per_column, eta, g_tol=0.0,
+              vjp_freq_batch=0, vjp_chunk=0):
     return McdBandCfg(int(max_blocks), DTYPE[precision], float(w_t), float(dtol),
                       STORAGE[storage], (2 if reorth is True else int(reorth)),
-                      1 if per_column else 0, float(eta), float(g_tol))
+                      1 if per_column else 0, float(eta), float(g_tol), int(vjp_freq_batch),
+                      int(vjp_chunk))
 
 
 class BandKeep:
@@ -662,11 +664,16 @@ def band_lanczos_green(model, keys, psi0, e0, orbitals, spins, omega, max_blocks
 
 def band_green_vjp(model, keys, psi0, e0, orbitals, spins, omega, G_bar, e0_bar=0.0,
                    max_blocks=50, precision="f64", dtol=1e-10, storage="auto", reorth=2, eta=0.0,
-                   cg_tol=1e-12, cg_max_iter=20000, g_tol=0.0, keep=None):
+                   cg_tol=1e-12, cg_max_iter=20000, g_tol=0.0, keep=None, vjp_freq_batch=0,
+                   vjp_chunk=0):
     """(d_t [n_bonds], d_U [n_orb], d_eps [n_orb], SolveInfo) = Re sum conj(G_bar) dG/dtheta
     + e0_bar dE0/dtheta via mcd_band_green_vjp (same arguments as band_lanczos_green), or
-    via mcd_band_green_vjp_keep on the runs of a BandKeep."""
-    cfg = _band_cfg(max_blocks, precision, 1.0, dtol, storage, reorth, False, eta, g_tol)
+    via mcd_band_green_vjp_keep on the runs of a BandKeep.  Without keep and with
+    reorth=0 the Krylov blocks are regenerated rather than stored; vjp_freq_batch
+    (frequencies per contraction pass, 0 = all) and vjp_chunk (blocks per
+    accumulation, 0 = 16) bound the work matrices."""
+    cfg = _band_cfg(max_blocks, precision, 1.0, dtol, storage, reorth, False, eta, g_tol,
+                    vjp_freq_batch, vjp_chunk)
     args, keepalive, ns, nf = _band_args(model, keys, psi0, e0, orbitals, spins, omega, cfg)
     gb = np.ascontiguousarray(np.asarray(G_bar, dtype=np.complex128).reshape(nf, ns, ns))
     dt = np.zeros(len(model.bonds))

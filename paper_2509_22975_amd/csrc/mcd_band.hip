@@ -400,19 +400,20 @@ __global__ __launch_bounds__(BS) void k_block_apply_r(int64_t n, int nm, const T
         block_apply_row<T, P>(r, nm, Q0, qstride, sC, W, sub);
 }
 
-// W (-)= sum_m Q_m C_m for nm blocks (C on the device), one launch.
+// W (-)= sum_m Q_m C_m for nm blocks (C on the device), one launch; block m
+// at Q0 + m qstride (elements; negative where a ring of blocks wraps).
 template <typename T, int P>
-static void launch_block_apply(int64_t n, int nm, const T *Q0, const double *C, T *W, bool sub,
-                               hipStream_t s) {
+static void launch_block_apply(int64_t n, int nm, const T *Q0, int64_t qstride, const double *C,
+                               T *W, bool sub, hipStream_t s) {
     const size_t lds = (size_t)nm * P * P * sizeof(double);
     if constexpr (P * sizeof(T) % 16 == 0) {
         const unsigned nb = (unsigned)std::min<int64_t>(gridn(n, BS), 8192);
         hipLaunchKernelGGL((k_block_apply_r<T, P>), dim3(nb), dim3(BS), lds, s, n, nm, Q0,
-                           (int64_t)n * P, C, W, sub ? 1 : 0);
+                           qstride, C, W, sub ? 1 : 0);
     } else {
         const unsigned nb = (unsigned)std::min<int64_t>(gridn(n, BS / P), 4096);
         hipLaunchKernelGGL((k_block_apply<T, P>), dim3(nb), dim3(BS), lds, s, n, nm, Q0,
-                           (int64_t)n * P, C, W, sub ? 1 : 0);
+                           qstride, C, W, sub ? 1 : 0);
     }
 }
 
@@ -726,6 +727,7 @@ struct BandRun {
     int64_t n = 0;
     hipStream_t s = nullptr;
     int mb = 0;                   // max block steps
+    int limit = 0;                // > 0: stop after this many block steps (a replay)
     int nstore = 0;               // stored blocks: mb + 1, or a ring of 3
     T *Qs = nullptr;              // [nstore][n][P]
     T *W = nullptr;               // [n][P]
@@ -874,18 +876,21 @@ struct BandRun {
         return MCD_OK;
     }
 
-    // W (-)= sum_m Q_m C_m with C already on the device ([nm][P][P]).
-    int block_apply_dev(const T *Q0, int nm, const double *C, T *Wout, bool sub) {
+    // W (-)= sum_m Q_m C_m with C already on the device ([nm][P][P]); block m
+    // at Q0 + m qstride (0: consecutive blocks of the store).
+    int block_apply_dev(const T *Q0, int nm, const double *C, T *Wout, bool sub,
+                        int64_t qstride = 0) {
         const int PP = P * P;
         const int group = std::max(1, (48 * 1024) / (PP * 8));
         MCD_REQUIRE(sub || nm <= group, MCD_E_INVALID, "assigning block product must use one group");
+        if (qstride == 0) qstride = (int64_t)n * P;
         for (int g0 = 0; g0 < nm; g0 += group) {
             const int g = std::min(group, nm - g0);
-            const T *q = Q0 + (int64_t)g0 * n * P;
+            const T *q = Q0 + (int64_t)g0 * qstride;
             const double *c = C + (size_t)g0 * PP;
 #define BAD(PV)                                                     \
     case PV:                                                        \
-        launch_block_apply<T, PV>(n, g, q, c, Wout, sub, s);        \
+        launch_block_apply<T, PV>(n, g, q, qstride, c, Wout, sub, s); \
         break;
             switch (P) {
                 BAD(1) BAD(2) BAD(4) BAD(8) BAD(16)
@@ -995,17 +1000,16 @@ struct BandRun {
     int step_dev(int j, int reorth) {
         MCD_TRY(apply_any(op, sizeof(T) == 8 ? MCD_F64 : MCD_F32, P, blk(j), W, s));
         MCD_TRY(gram_dev(blk(j), 1, W));
-        // W -= Q_{j-1} B_j^T + Q_j A_j: one pass when the two blocks are
-        // adjacent in the store
+        // W -= Q_{j-1} B_j^T + Q_j A_j in one pass, block j at its offset from
+        // block j - 1 (negative where the ring of three wraps), so a ring and
+        // a full store give the same W bit for bit
         hipLaunchKernelGGL(k_sym_pair, dim3(1), dim3(64), 0, s, P, dG, dA(j),
                            j > 0 ? dB(j) : nullptr, dC2());
         MCD_HIP(hipGetLastError());
-        if (j > 0 && blk(j) == blk(j - 1) + (int64_t)n * P) {
-            MCD_TRY(block_apply_dev(blk(j - 1), 2, dC2(), W, true));
-        } else {
-            MCD_TRY(block_apply_dev(blk(j), 1, dC2() + PP(), W, true));
-            if (j > 0) MCD_TRY(block_apply_dev(blk(j - 1), 1, dC2(), W, true));
-        }
+        if (j > 0)
+            MCD_TRY(block_apply_dev(blk(j - 1), 2, dC2(), W, true, (int64_t)(blk(j) - blk(j - 1))));
+        else
+            MCD_TRY(block_apply_dev(blk(0), 1, dC2() + PP(), W, true));
         for (int pass = 0; pass < reorth; pass++) {
             MCD_TRY(gram_dev(blk(0), j + 1, W));
             MCD_TRY(block_apply_dev(blk(0), j + 1, dG, W, true));
@@ -1207,11 +1211,12 @@ __global__ __launch_bounds__(64) void k_mr_sym_pair(const MRun *__restrict__ R, 
 }
 
 // dst (-)= sum_{m < nm} src_m C_m: src = buffer qkind (stored blocks from
-// qslot on), C = the run's dT (ckind 0) or dG (1) at offset coff.
+// qslot on, qstep slots apart: -2 where a ring of three wraps), C = the
+// run's dT (ckind 0) or dG (1) at offset coff.
 template <typename T, int P>
 __global__ __launch_bounds__(BS) void k_mr_apply(const MRun *__restrict__ R, int nrun, int nm,
-                                                 int qkind, int qslot, int ckind, int64_t coff,
-                                                 int dkind, int dslot, int sub) {
+                                                 int qkind, int qslot, int qstep, int ckind,
+                                                 int64_t coff, int dkind, int dslot, int sub) {
     extern __shared__ double sC[];
     const int64_t u = blockIdx.x;
     const MRun &r = R[mr_find(R, nrun, u, 2)];
@@ -1220,8 +1225,8 @@ __global__ __launch_bounds__(BS) void k_mr_apply(const MRun *__restrict__ R, int
     __syncthreads();
     const int64_t row = (u - r.row0) * BS + threadIdx.x;
     if (row < r.n)
-        block_apply_row<T, P>(row, nm, mr_buf<T>(r, qkind, qslot, P), r.n * P, sC,
-                              mr_buf<T>(r, dkind, dslot, P), sub);
+        block_apply_row<T, P>(row, nm, mr_buf<T>(r, qkind, qslot, P), (int64_t)qstep * r.n * P,
+                              sC, mr_buf<T>(r, dkind, dslot, P), sub);
 }
 
 template <int P>
@@ -1337,14 +1342,16 @@ struct MRTable {
         return MCD_OK;
     }
     int apply(int nm, int qkind, int qslot, int ckind, int64_t coff, int dkind, int dslot,
-              bool sub) {
+              bool sub, int qstep = 1) {
         const size_t lds = (size_t)nm * P * P * sizeof(double);
         if (P == 8)
             hipLaunchKernelGGL((k_mr_apply<T, 8>), dim3((unsigned)rowt), dim3(BS), lds, s, dev,
-                               nrun, nm, qkind, qslot, ckind, coff, dkind, dslot, sub ? 1 : 0);
+                               nrun, nm, qkind, qslot, qstep, ckind, coff, dkind, dslot,
+                               sub ? 1 : 0);
         else
             hipLaunchKernelGGL((k_mr_apply<T, 16>), dim3((unsigned)rowt), dim3(BS), lds, s, dev,
-                               nrun, nm, qkind, qslot, ckind, coff, dkind, dslot, sub ? 1 : 0);
+                               nrun, nm, qkind, qslot, qstep, ckind, coff, dkind, dslot,
+                               sub ? 1 : 0);
         MCD_HIP(hipGetLastError());
         return MCD_OK;
     }
@@ -1376,12 +1383,10 @@ struct MRTable {
         hipLaunchKernelGGL(k_mr_sym_pair, dim3(nrun), dim3(64), 0, s, dev, P, mb, j);
         MCD_HIP(hipGetLastError());
         const int64_t c2 = (int64_t)(2 * mb + 5) * PP;
-        if (j > 0 && slot(j) == slot(j - 1) + 1) {
-            MCD_TRY(apply(2, 2, slot(j - 1), 0, c2, 0, 0, true));
-        } else {
-            MCD_TRY(apply(1, 2, slot(j), 0, c2 + PP, 0, 0, true));
-            if (j > 0) MCD_TRY(apply(1, 2, slot(j - 1), 0, c2, 0, 0, true));
-        }
+        if (j > 0)   // one pass, block j at its (signed) slot offset from block j - 1
+            MCD_TRY(apply(2, 2, slot(j - 1), 0, c2, 0, 0, true, slot(j) - slot(j - 1)));
+        else
+            MCD_TRY(apply(1, 2, slot(0), 0, c2 + PP, 0, 0, true));
         const int group = std::max(1, (48 * 1024) / (PP * 8));
         for (int pass = 0; pass < reorth; pass++) {
             MCD_TRY(gram(j + 1, 2, 0, 0));
@@ -1401,8 +1406,14 @@ struct MRTable {
 // run's arithmetic depends on that run alone, so its result is the same in
 // any company.  Each run's start block is in its W.
 template <typename T>
+using BlockHook = std::function<int(BandRun<T> &, int)>;
+
+// on_block (optional) is called for each run and block j once Q_j is formed
+// (after its QR, before any later block overwrites a ring slot); it enqueues
+// its work on the stream.
+template <typename T>
 static int run_lockstep(std::vector<BandRun<T> *> &runs, double dtol_abs, int reorth,
-                        hipStream_t s) {
+                        hipStream_t s, const BlockHook<T> *on_block = nullptr) {
     int mb = 0;
     std::vector<BandRun<T> *> act;
     for (auto *r : runs) {
@@ -1449,13 +1460,16 @@ static int run_lockstep(std::vector<BandRun<T> *> &runs, double dtol_abs, int re
     if (hipStreamSynchronize(s) != hipSuccess) return done(MCD_E_HIP);
     for (auto *r : runs)
         if (r->active && r->rank[0] <= 0) r->active = false;
+    if (on_block)
+        for (auto *r : runs)
+            if (r->active) LTRY((*on_block)(*r, 0));
     size_t built = act.size();
     for (int j = 0; j < mb; j++) {
         act.clear();
         for (auto *r : runs)
             if (r->active) act.push_back(r);
         if (act.empty()) break;
-        if (fused && act.size() != built) {   // the set changed (after a synchronisation)
+        if (fused && act.size() != built) {   // the set changed
             LTRY(tab.build(act));
             built = act.size();
         }
@@ -1465,11 +1479,30 @@ static int run_lockstep(std::vector<BandRun<T> *> &runs, double dtol_abs, int re
             for (auto *r : act) LTRY(r->step_dev(j, reorth));
         for (auto *r : act) r->m = j + 1;
         if (j + 1 == mb) break;
+        // a replay stops at its limit (before the QR of the next block)
+        bool capped = false;
+        for (auto *r : act)
+            if (r->limit > 0 && r->m >= r->limit) {
+                r->active = false;
+                capped = true;
+            }
+        if (capped) {
+            act.clear();
+            for (auto *r : runs)
+                if (r->active) act.push_back(r);
+            if (act.empty()) break;
+            if (fused && act.size() != built) {
+                LTRY(tab.build(act));
+                built = act.size();
+            }
+        }
         if (fused)
             LTRY(tab.qr(tab.slot(j + 1), (int64_t)(mb + j + 1) * PP0, j + 1, dtol_abs));
         else
             for (auto *r : act)
                 LTRY(r->qr_dev(r->W, r->blk(j + 1), r->dB(j + 1), j + 1, dtol_abs));
+        if (on_block)
+            for (auto *r : act) LTRY((*on_block)(*r, j + 1));
         if ((j + 1) % 8 == 0) {
             bool gt = false;
             for (auto *r : act) {
@@ -2070,53 +2103,17 @@ __global__ void k_start_block_t(int64_t m, const uint64_t *__restrict__ keys, Se
     lam[r] += acc;
 }
 
-// The adjoint's weight matrix in symmetric form: Mp[i][j] = sg (A[i].B[j] +
-// A[j].B[i]) for i, j < KP and 0 elsewhere in the S x S output, with A and B
-// [KP][K2] row-major float64 (M = sg A B^T is the real part of the
-// frequency sum).  A 16 x 16 workgroup makes one 16 x 16 tile; the four row
-// panels it needs are staged through LDS 32 k at a time (zeros past KP and
-// K2), and each dot is one accumulator summed in k order, so the result does
-// not depend on the launch.
-template <typename T>
-__global__ __launch_bounds__(256) void k_sym_gram(int KP, int K2, int S, double sg,
-                                                 const double *__restrict__ A,
-                                                 const double *__restrict__ B,
-                                                 T *__restrict__ Mp) {
-    constexpr int TW = 16, KC = 32;
-    __shared__ double Ai[TW][KC + 1], Bj[TW][KC + 1], Aj[TW][KC + 1], Bi[TW][KC + 1];
-    const int tx = threadIdx.x, ty = threadIdx.y, t = ty * TW + tx;
-    const int i0 = blockIdx.y * TW, j0 = blockIdx.x * TW;
-    double s1 = 0.0, s2 = 0.0;
-    for (int k0 = 0; k0 < K2; k0 += KC) {
-        for (int e = t; e < TW * KC; e += TW * TW) {
-            const int rr = e / KC, kk = e % KC, k = k0 + kk;
-            const int ri = i0 + rr, rj = j0 + rr;
-            const bool kin = k < K2;
-            Ai[rr][kk] = kin && ri < KP ? A[(size_t)ri * K2 + k] : 0.0;
-            Bi[rr][kk] = kin && ri < KP ? B[(size_t)ri * K2 + k] : 0.0;
-            Aj[rr][kk] = kin && rj < KP ? A[(size_t)rj * K2 + k] : 0.0;
-            Bj[rr][kk] = kin && rj < KP ? B[(size_t)rj * K2 + k] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < KC; kk++) {
-            s1 = fma(Ai[ty][kk], Bj[tx][kk], s1);
-            s2 = fma(Aj[tx][kk], Bi[ty][kk], s2);
-        }
-        __syncthreads();
-    }
-    const int i = i0 + ty, j = j0 + tx;
-    if (i < S && j < S) Mp[(size_t)i * S + j] = (T)(sg * s1 + sg * s2);
-}
-
-// Zt = Q M for the adjoint: Q the Krylov store (blocks of n x P, P a power of
-// two; Q[r][k] = block k / P, row r, column k % P, k < KP), M [S][S] row-major
-// and Zt [n][S] row-major, S a multiple of 128 (M and Zt zero past KP).  A
+// Zt += Q M for the adjoint: Q consecutive Krylov blocks (n x P each, P a
+// power of two; Q[r][k] = block k / P, row r, column k % P, k < KP), M
+// row-major with S columns and Zt [n][S] row-major, S a multiple of 128.  A
 // workgroup of four wavefronts makes one 128 x 128 tile of Zt, each wavefront
 // a 64 x 64 quarter as 4 x 4 MFMA 16x16x4 products (float32 or float64 in,
 // same type accumulated), with both operands staged through LDS in steps of
 // 128 bytes of k.  Tiles are handed out XCD-major, so the S / 128 column tiles
-// of one row tile run on one XCD and share its L2 copy of the Q rows.
+// of one row tile run on one XCD and share its L2 copy of the Q rows.  M is
+// read for rows < KP rounded up to 8 x 16 bytes of k (finite there; the
+// products with rows past KP meet zero Q values).  Each element of Zt gets
+// its product over the KP terms, rounded, added once.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rows_times(int64_t n, int S, int KP, int pl,
                                                    const T *__restrict__ Q,
@@ -2142,7 +2139,7 @@ __global__ __launch_bounds__(256) void k_rows_times(int64_t n, int S, int KP, in
     for (int i = 0; i < 4; i++)
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[i][j] = (V4)(T)0;
-    const int kend = (KP + BK - 1) / BK * BK;   // rows of M past KP are zero
+    const int kend = (KP + BK - 1) / BK * BK;   // Q is zero past KP
     for (int k0 = 0; k0 < kend; k0 += BK) {
 #pragma unroll
         for (int q = 0; q < 4; q++) {   // A: 128 rows x 8 units of 16 bytes
@@ -2196,7 +2193,10 @@ __global__ __launch_bounds__(256) void k_rows_times(int64_t n, int S, int KP, in
             const int64_t r = r0 + wr + i * 16 + (sizeof(T) == 4 ? 4 * lk + v : lk + 4 * v);
             if (r >= n) continue;
 #pragma unroll
-            for (int j = 0; j < 4; j++) Zt[r * S + c0 + wc + j * 16 + li] = acc[i][j][v];
+            for (int j = 0; j < 4; j++) {
+                T *z = Zt + r * S + c0 + wc + j * 16 + li;
+                *z = *z + acc[i][j][v];
+            }
         }
 }
 
@@ -2205,37 +2205,31 @@ static constexpr int kMaxParams = MCD_MAX_BONDS + 2 * MCD_MAX_ORB;
 
 // part[p * gridDim.x + block] = sum over this workgroup's rows r of
 //   sum_a L[r][a] (dH/dtheta_p R)[r][a]
-// for the merged bonds p < nb, then U_i (p = nb + i) and eps_i (nb + no + i);
-// L is a block-major Krylov store (KP = nk P columns, column a = block a / P,
-// entry a % P), R is row-major (Rt: [n][S], zero past KP).  One wavefront per
-// row r.  The lanes look up all of the row's hop targets at once (lane
-// 2q + s: bond q, spin s), the row L[r] is loaded once into registers (NR
+// for the merged bonds p < nb, then U_i (p = nb + i) and eps_i (nb + no + i):
+// over all rows, tr(L^T dH_p R).  L and R are row-major [n][S] (columns
+// a < KP used; R zero past KP).  One wavefront per row r.  The lanes look up
+// all of the row's hop targets at once (lane 2q + s: bond q, spin s), the
+// row L[r] is loaded once into registers (NR
 // values per lane; NR = 0 re-reads it, any S), and the hops are then taken in
 // lane order (bond by bond, up spin first), each a gather of the contiguous
 // row Rt[col] with all NR loads issued together: loads past column S read the
 // next row (or a zeroed tail of at least 64 (NR - S / 64) values after the
 // last row) and meet zero weights.  Each wave keeps its own accumulators
-// (fixed order).  Symmetric form: with Rt = L (M + M^T) row-major, a hop pair
-// r <-> c (same bond, same sign both ways) adds L[r].Rt'[c] + L[c].Rt'[r] =
-// L[r].Rt[c] for Rt' = L M, so only hops with c > r are taken (half the
-// gathers), and the diagonal term is L[r].Rt[r] / 2.
+// (fixed order).
 template <typename T, int NR>
 __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
     int64_t n, const uint64_t *__restrict__ keys, const DevModel *__restrict__ m,
-    const HashSlot *__restrict__ h, uint64_t hmask, const T *__restrict__ L, int KP, int pl,
+    const HashSlot *__restrict__ h, uint64_t hmask, const T *__restrict__ L, int KP,
     const T *__restrict__ Rt, int S, double *__restrict__ part) {
     __shared__ double acc[kCWaves][kMaxParams];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nb = m->n_bonds, no = m->n_orb, np = nb + 2 * no;
-    const int P = 1 << pl;
     for (int i = lane; i < np; i += 64) acc[wid][i] = 0.0;
     for (int64_t r = (int64_t)blockIdx.x * kCWaves + wid; r < n;
          r += (int64_t)gridDim.x * kCWaves) {
         const uint64_t key = keys[r];
         const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
-        auto lval = [&](int a) -> T {
-            return a < KP ? L[(((int64_t)(a >> pl) * n + r) << pl) | (a & (P - 1))] : (T)0;
-        };
+        auto lval = [&](int a) -> T { return a < KP ? L[r * (int64_t)S + a] : (T)0; };
         T qv[NR > 0 ? NR : 1];
         if constexpr (NR > 0) {
 #pragma unroll
@@ -2266,7 +2260,6 @@ __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
                 if (__popc(sp & mask) == 1) {
                     col = hash_find(h, hmask, key ^ ((uint64_t)mask << ((hl & 1) ? 0 : 32)));
                     neg = __popc(sp & between) & 1;
-                    if (col <= r) col = -1;   // each pair once (from its lower row)
                 }
             }
             uint64_t live = __ballot(col >= 0);
@@ -2291,7 +2284,7 @@ __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
             }
             if (cur >= 0 && lane == 0) acc[wid][cur] += c;
         }
-        const double d = 0.5 * rowdot(r);
+        const double d = rowdot(r);
         if (lane == 0) {
             for (int i = 0; i < no; i++) {
                 const double nu = (double)((up >> i) & 1u), nd = (double)((dn >> i) & 1u);
@@ -2310,10 +2303,10 @@ __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
 
 template <typename T>
 static void launch_contract_rows(unsigned g, hipStream_t s, int64_t n, const mcd_op *op,
-                                 const T *L, int KP, int pl, const T *Rt, int S, double *part) {
+                                 const T *L, int KP, const T *Rt, int S, double *part) {
 #define CR(NRV)                                                                             \
     hipLaunchKernelGGL((k_contract_rows<T, NRV>), dim3(g), dim3(64 * kCWaves), 0, s, n,    \
-                       op->d_keys, op->d_model, op->d_hash, op->hash_mask, L, KP, pl, Rt, S, part)
+                       op->d_keys, op->d_model, op->d_hash, op->hash_mask, L, KP, Rt, S, part)
     const int nr = S / 64;
     if (nr <= 2) CR(2);
     else if (nr <= 4) CR(4);
@@ -2533,153 +2526,237 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
 
     double trM = 0.0;   // sum over sectors of tr(M)
     int krylov = 0;
-    // Per sector: the per-frequency solves, Omega and the two factors of M
-    // on the host; M + M^T, Z = Q (M + M^T) and W = Q Omega on the device,
-    // tr(Q^T dH Q M) into acc, lam += (start-block map)^T W.
-    auto hook = [&](BandRun<T> &run, bool create) -> int {
-        {
-            const mcd_op *op = run.op;
-            const BandResult &br = run.br;
-            const int m = br.m, KP = m * P;
-            const double sg = create ? 1.0 : -1.0;
-            std::vector<double> Om((size_t)KP * P, 0.0);
-            // Per frequency (in parallel): X_f = first block column of
-            // (z - T)^-1 R0, V_f = X_f conj(G_bar_f)^T.  Then M and Omega
-            // (in parallel over their rows a), each element summed over the
-            // frequencies in index order.
-            std::vector<std::vector<cplx>> Xs(n_freq), Vs(n_freq);
-            std::vector<std::vector<double>> Ws(n_freq);
-            parallel_for(n_freq, [&](int f) {
-                const cplx zeta = freq_arg(cfg, omega[f]);
-                block_solve_first(br, create ? e0 + zeta : e0 - zeta, p, Xs[f]);
-                const std::vector<cplx> &X = Xs[f];
-                std::vector<cplx> &V = Vs[f];
-                std::vector<double> &Wf = Ws[f];
-                V.assign((size_t)KP * p, cplx(0.0));
-                Wf.assign((size_t)KP * p, 0.0);
-                const cplx *Gb = (const cplx *)G_bar + (size_t)f * p * p;
-                for (int a = 0; a < KP; a++)
-                    for (int mu = 0; mu < p; mu++) {
-                        cplx v = 0.0, w = 0.0;
-                        for (int nu = 0; nu < p; nu++) {
-                            v += X[(size_t)a * p + nu] * std::conj(Gb[mu * p + nu]);
-                            w += X[(size_t)a * p + nu] * std::conj(Gb[nu * p + mu]);
-                        }
-                        V[(size_t)a * p + mu] = v;
-                        Wf[(size_t)a * p + mu] = (v + w).real();
+    const int reorth = std::max(0, std::min(2, (int)cfg->reorth));
+    const int chunk = cfg->vjp_chunk > 0 ? cfg->vjp_chunk : 16;
+    const int fb = cfg->vjp_freq_batch > 0 ? std::min<int>(cfg->vjp_freq_batch, n_freq) : n_freq;
+    // Without kept runs and without reorthogonalisation no Krylov block is
+    // stored: a second pass of the recurrence (the same kernels on the same
+    // data) regenerates Q_0, Q_1, ... one at a time.
+    const bool streaming = keep == nullptr && reorth == 0;
+    int pl = 0;
+    while ((1 << pl) < P) pl++;
+
+    // Per sector, on the host: the per-frequency solves give Omega and the
+    // two factors of M = sg A B^T (A, B: KP x K2, K2 = 2 n_freq p).
+    struct SectorPrep {
+        int m = 0, KP = 0;
+        double sg = 1.0;
+        std::vector<double> Om, Am, Bm;
+    };
+    auto prep = [&](const BandRun<T> &run, bool create, SectorPrep &sp) {
+        const BandResult &br = run.br;
+        const int m = br.m, KP = m * P;
+        const double sg = create ? 1.0 : -1.0;
+        sp.m = m;
+        sp.KP = KP;
+        sp.sg = sg;
+        std::vector<double> &Om = sp.Om;
+        Om.assign((size_t)KP * P, 0.0);
+        // Per frequency (in parallel): X_f = first block column of
+        // (z - T)^-1 R0, V_f = X_f conj(G_bar_f)^T.  Then M and Omega
+        // (in parallel over their rows a), each element summed over the
+        // frequencies in index order.
+        std::vector<std::vector<cplx>> Xs(n_freq), Vs(n_freq);
+        std::vector<std::vector<double>> Ws(n_freq);
+        parallel_for(n_freq, [&](int f) {
+            const cplx zeta = freq_arg(cfg, omega[f]);
+            block_solve_first(br, create ? e0 + zeta : e0 - zeta, p, Xs[f]);
+            const std::vector<cplx> &X = Xs[f];
+            std::vector<cplx> &V = Vs[f];
+            std::vector<double> &Wf = Ws[f];
+            V.assign((size_t)KP * p, cplx(0.0));
+            Wf.assign((size_t)KP * p, 0.0);
+            const cplx *Gb = (const cplx *)G_bar + (size_t)f * p * p;
+            for (int a = 0; a < KP; a++)
+                for (int mu = 0; mu < p; mu++) {
+                    cplx v = 0.0, w = 0.0;
+                    for (int nu = 0; nu < p; nu++) {
+                        v += X[(size_t)a * p + nu] * std::conj(Gb[mu * p + nu]);
+                        w += X[(size_t)a * p + nu] * std::conj(Gb[nu * p + mu]);
                     }
-            });
-            // M[a][b] = sg Re sum_f sum_mu V_f[a][mu] X_f[b][mu] as a real
-            // product A B^T over K2 = 2 n_freq p terms: A[a] = (Re V, -Im V),
-            // B[b] = (Re X, Im X), contiguous per row.  The product itself
-            // (in the symmetric form M + M^T) is made on the device below;
-            // the host keeps its trace.
-            const int K2 = 2 * n_freq * p;
-            std::vector<double> Am((size_t)KP * K2), Bm((size_t)KP * K2);
-            parallel_for(KP, [&](int a) {
-                double *Aa = Am.data() + (size_t)a * K2, *Ba = Bm.data() + (size_t)a * K2;
-                for (int f = 0; f < n_freq; f++)
-                    for (int mu = 0; mu < p; mu++) {
-                        const cplx v = Vs[f][(size_t)a * p + mu], x = Xs[f][(size_t)a * p + mu];
-                        const size_t k = 2 * ((size_t)f * p + mu);
-                        Aa[k] = v.real();
-                        Aa[k + 1] = -v.imag();
-                        Ba[k] = x.real();
-                        Ba[k + 1] = x.imag();
-                    }
-            });
-            std::vector<double> diag(KP);
-            parallel_for(KP, [&](int a) {
-                for (int f = 0; f < n_freq; f++)
-                    for (int mu = 0; mu < p; mu++)
-                        Om[(size_t)a * P + mu] += sg * Ws[f][(size_t)a * p + mu];
-                const double *Aa = Am.data() + (size_t)a * K2, *Ba = Bm.data() + (size_t)a * K2;
-                double t = 0.0;
-                for (int k = 0; k < K2; k++) t += Aa[k] * Ba[k];
-                diag[a] = sg * t;
-            });
-            for (int a = 0; a < KP; a++) trM += diag[a];
-            krylov += br.krylov;
-            const int64_t nx = run.n;
-            std::vector<double> C((size_t)m * P * P);
-            int rc = MCD_OK;
-            // about 16 rows per wavefront
-            const unsigned g =
-                (unsigned)std::min<int64_t>(cblk, (nx + 16 * kCWaves - 1) / (16 * kCWaves));
-            // Z = Q (M + M^T) as one product into a row-major Zt [nx][S] (the
-            // size of the Krylov store it is made from), then the contraction
-            // (symmetric form: each hop pair once)
-            const int S = (KP + 127) / 128 * 128;
-            int pl = 0;
-            while ((1 << pl) < P) pl++;
-            constexpr int kTail = 1024;   // zeroed values after the last row of Zt
-            // Zt, M and its factors: workspace pieces released together at the
-            // end of the hook
-            Arena zarena(ws);
-            T *Zt = nullptr, *Md = nullptr;
-            double *dA = nullptr, *dB = nullptr;
-            if (zarena.get((void **)&Zt, ((size_t)nx * S + kTail) * sizeof(T)) != hipSuccess ||
-                zarena.get((void **)&Md, (size_t)S * S * sizeof(T)) != hipSuccess ||
-                zarena.get((void **)&dA, Am.size() * sizeof(double)) != hipSuccess ||
-                zarena.get((void **)&dB, Bm.size() * sizeof(double)) != hipSuccess) {
-                set_error("green vjp: workspace too small for Z = Q M (%.1f GB)",
-                          (double)nx * S * sizeof(T) / 1e9);
+                    V[(size_t)a * p + mu] = v;
+                    Wf[(size_t)a * p + mu] = (v + w).real();
+                }
+        });
+        // M[a][b] = sg Re sum_f sum_mu V_f[a][mu] X_f[b][mu] as a real
+        // product A B^T over K2 = 2 n_freq p terms: A[a] = (Re V, -Im V),
+        // B[b] = (Re X, Im X), contiguous per row.  M itself is never
+        // formed: the device makes Q A and Q B below; the host keeps tr(M).
+        const int K2 = 2 * n_freq * p;
+        std::vector<double> &Am = sp.Am, &Bm = sp.Bm;
+        Am.assign((size_t)KP * K2, 0.0);
+        Bm.assign((size_t)KP * K2, 0.0);
+        parallel_for(KP, [&](int a) {
+            double *Aa = Am.data() + (size_t)a * K2, *Ba = Bm.data() + (size_t)a * K2;
+            for (int f = 0; f < n_freq; f++)
+                for (int mu = 0; mu < p; mu++) {
+                    const cplx v = Vs[f][(size_t)a * p + mu], x = Xs[f][(size_t)a * p + mu];
+                    const size_t k = 2 * ((size_t)f * p + mu);
+                    Aa[k] = v.real();
+                    Aa[k + 1] = -v.imag();
+                    Ba[k] = x.real();
+                    Ba[k + 1] = x.imag();
+                }
+        });
+        std::vector<double> diag(KP);
+        parallel_for(KP, [&](int a) {
+            for (int f = 0; f < n_freq; f++)
+                for (int mu = 0; mu < p; mu++)
+                    Om[(size_t)a * P + mu] += sg * Ws[f][(size_t)a * p + mu];
+            const double *Aa = Am.data() + (size_t)a * K2, *Ba = Bm.data() + (size_t)a * K2;
+            double t = 0.0;
+            for (int k = 0; k < K2; k++) t += Aa[k] * Ba[k];
+            diag[a] = sg * t;
+        });
+        for (int a = 0; a < KP; a++) trM += diag[a];
+        krylov += br.krylov;
+    };
+
+    // Per sector, on the device, for each batch of frequencies: over chunks
+    // of Krylov blocks Q_c (from the store, or regenerated),
+    //   U += Q_c (sg A_c),  V += Q_c B_c  (columns of the batch),
+    //   W += Q_c Omega_c                  (first batch),
+    // then tr(Q^T dH Q M) restricted to the batch = tr(U^T dH V) into acc
+    // (M = sg A B^T and dH symmetric); finally lam += (start-block map)^T W.
+    // Both sources give the same blocks, so the same sums bit for bit.
+    auto sector = [&](BandRun<T> &run, bool create, const SectorPrep &sp) -> int {
+        const mcd_op *op = run.op;
+        const int m = sp.m, KP = sp.KP;
+        const int64_t nx = run.n;
+        const int K2 = 2 * n_freq * p;
+        const int nbatch = (n_freq + fb - 1) / fb;
+        const int S2 = (2 * fb * p + 127) / 128 * 128;
+        const int KPr = KP + 64;   // coefficient rows (zero past KP; read up to 32 past a chunk)
+        constexpr int kTail = 1024;   // zeroed values after the last row of U and V
+        Arena za(ws);
+        T *U = nullptr, *V = nullptr, *Wo = nullptr, *dA = nullptr, *dB = nullptr, *Qc = nullptr;
+        double *dC = nullptr;
+        int rc = MCD_OK;
+        auto get = [&](void **ptr, size_t bytes) {
+            if (rc != MCD_OK) return;
+            if (za.get(ptr, bytes) != hipSuccess) {
+                set_error("green vjp: workspace too small for the contraction matrices "
+                          "(%.2f GB more; lower vjp_freq_batch)", bytes / 1e9);
                 rc = MCD_E_WORKSPACE;
-            }
-            if (rc == MCD_OK &&
-                (poison_fp(Zt, ((size_t)nx * S + kTail) * sizeof(T), zarena.al, s) != hipSuccess ||
-                 poison_fp(Md, (size_t)S * S * sizeof(T), zarena.al, s) != hipSuccess ||
-                 poison_fp(dA, Am.size() * sizeof(double), zarena.al, s) != hipSuccess ||
-                 poison_fp(dB, Bm.size() * sizeof(double), zarena.al, s) != hipSuccess))
+            } else if (poison_fp(*ptr, bytes, za.al, s) != hipSuccess) {
                 rc = MCD_E_HIP;
-            if (rc == MCD_OK &&
-                (hipMemcpyAsync(dA, Am.data(), Am.size() * sizeof(double), hipMemcpyHostToDevice,
-                                s) != hipSuccess ||
-                 hipMemcpyAsync(dB, Bm.data(), Bm.size() * sizeof(double), hipMemcpyHostToDevice,
-                                s) != hipSuccess ||
-                 hipMemsetAsync(Zt + (size_t)nx * S, 0, kTail * sizeof(T), s) != hipSuccess))
+            }
+        };
+        get((void **)&U, ((size_t)nx * S2 + kTail) * sizeof(T));
+        get((void **)&V, ((size_t)nx * S2 + kTail) * sizeof(T));
+        get((void **)&Wo, (size_t)nx * P * sizeof(T));
+        get((void **)&dA, (size_t)KPr * S2 * sizeof(T));
+        get((void **)&dB, (size_t)KPr * S2 * sizeof(T));
+        get((void **)&dC, (size_t)m * P * P * sizeof(double));
+        if (streaming) get((void **)&Qc, (size_t)chunk * nx * P * sizeof(T));
+        std::vector<double> C((size_t)m * P * P);
+        for (size_t e = 0; e < C.size(); e++) C[e] = -sp.Om[e];   // W -= Q (-Omega)
+        std::vector<T> hA((size_t)KPr * S2), hB((size_t)KPr * S2);
+        if (rc == MCD_OK &&
+            (hipMemcpyAsync(dC, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, s) !=
+                 hipSuccess ||
+             hipMemsetAsync(Wo, 0, (size_t)nx * P * sizeof(T), s) != hipSuccess))
+            rc = MCD_E_HIP;
+        const unsigned g =
+            (unsigned)std::min<int64_t>(cblk, (nx + 16 * kCWaves - 1) / (16 * kCWaves));
+        const int64_t tiles = (nx + 127) / 128 * (S2 / 128);
+        const unsigned gt = (unsigned)((tiles + 7) / 8 * 8);
+        for (int b = 0; b < nbatch && rc == MCD_OK; b++) {
+            const int f0 = b * fb, f1 = std::min(n_freq, f0 + fb);
+            const int K2b = 2 * (f1 - f0) * p;
+            std::fill(hA.begin(), hA.end(), (T)0);
+            std::fill(hB.begin(), hB.end(), (T)0);
+            parallel_for(KP, [&](int a) {
+                const double *Aa = sp.Am.data() + (size_t)a * K2 + 2 * (size_t)f0 * p;
+                const double *Ba = sp.Bm.data() + (size_t)a * K2 + 2 * (size_t)f0 * p;
+                for (int k = 0; k < K2b; k++) {
+                    hA[(size_t)a * S2 + k] = (T)(sp.sg * Aa[k]);
+                    hB[(size_t)a * S2 + k] = (T)Ba[k];
+                }
+            });
+            if (hipMemcpyAsync(dA, hA.data(), hA.size() * sizeof(T), hipMemcpyHostToDevice, s) !=
+                    hipSuccess ||
+                hipMemcpyAsync(dB, hB.data(), hB.size() * sizeof(T), hipMemcpyHostToDevice, s) !=
+                    hipSuccess ||
+                hipMemsetAsync(U, 0, ((size_t)nx * S2 + kTail) * sizeof(T), s) != hipSuccess ||
+                hipMemsetAsync(V, 0, ((size_t)nx * S2 + kTail) * sizeof(T), s) != hipSuccess) {
                 rc = MCD_E_HIP;
-            if (rc == MCD_OK) {
-                // M + M^T on the device (S x S, zero past KP)
-                hipLaunchKernelGGL((k_sym_gram<T>), dim3(S / 16, S / 16), dim3(16, 16), 0, s, KP,
-                                   K2, S, sg, dA, dB, Md);
-                const int64_t tiles = (nx + 127) / 128 * (S / 128);
-                hipLaunchKernelGGL((k_rows_times<T>), dim3((unsigned)((tiles + 7) / 8 * 8)),
-                                   dim3(256), 0, s, nx, S, KP, pl, run.blk(0), Md, Zt);
-                launch_contract_rows<T>(g, s, nx, op, run.blk(0), KP, pl, Zt, S, part);
+                break;
+            }
+            // the k blocks at Qp (consecutive) are blocks j0 .. j0 + k - 1
+            auto flush = [&](const T *Qp, int j0, int k) -> int {
+                hipLaunchKernelGGL((k_rows_times<T>), dim3(gt), dim3(256), 0, s, nx, S2, k * P, pl,
+                                   Qp, dA + (size_t)j0 * P * S2, U);
+                hipLaunchKernelGGL((k_rows_times<T>), dim3(gt), dim3(256), 0, s, nx, S2, k * P, pl,
+                                   Qp, dB + (size_t)j0 * P * S2, V);
+                MCD_HIP(hipGetLastError());
+                if (b == 0) MCD_TRY(run.block_apply_dev(Qp, k, dC + (size_t)j0 * P * P, Wo, true));
+                return MCD_OK;
+            };
+            if (!streaming) {
+                for (int j0 = 0; j0 < m && rc == MCD_OK; j0 += chunk)
+                    rc = flush(run.blk(j0), j0, std::min(chunk, m - j0));
+            } else {
+                // the cut, the start block and the recurrence again, capped at
+                // the first pass's m blocks; each new block is copied to the
+                // chunk buffer before the ring reuses its slot
+                uint64_t *kt = nullptr;
+                double *pt = nullptr;
+                int64_t nk = 0;
+                rc = wt_cut(keys_dev, n, psi0_dev, cfg->w_t, ws, s, &kt, &pt, &nk);
+                if (rc == MCD_OK) rc = run_start_block(run, kt, pt, nk, sel, create);
+                (void)dfree(pt, A);
+                (void)dfree(kt, A);
+                int cnt = 0, jn = 0;
+                BlockHook<T> hk = [&](BandRun<T> &r, int j) -> int {
+                    if (j >= m) return MCD_OK;
+                    MCD_HIP(hipMemcpyAsync(Qc + (size_t)cnt * nx * P, r.blk(j),
+                                           (size_t)nx * P * sizeof(T), hipMemcpyDeviceToDevice, s));
+                    cnt++;
+                    if (cnt == chunk || j == m - 1) {
+                        MCD_TRY(flush(Qc, jn, cnt));
+                        jn += cnt;
+                        cnt = 0;
+                    }
+                    return MCD_OK;
+                };
+                const double gtol = run.g_tol;
+                run.g_tol = 0.0;
+                run.limit = m;
+                std::vector<BandRun<T> *> one{&run};
+                if (rc == MCD_OK) rc = run_lockstep<T>(one, cfg->dtol, 0, s, &hk);
+                run.g_tol = gtol;
+                run.limit = 0;
+                if (rc == MCD_OK && (run.br.m != m || jn != m)) {
+                    set_error("green vjp: the regenerated Krylov blocks (%d) differ from the "
+                              "first pass (%d)", jn, m);
+                    rc = MCD_E_NUMERIC;
+                }
             }
             if (rc == MCD_OK) {
+                launch_contract_rows<T>(g, s, nx, op, U, K2b, V, S2, part);
                 hipLaunchKernelGGL(k_param_reduce, dim3((np + 3) / 4), dim3(256), 0, s, np, (int)g,
                                    part, acc, 1);
                 if (hipGetLastError() != hipSuccess) rc = MCD_E_HIP;
             }
-            // W = Q Omega (into run.W), then lam += map^T W
-            if (rc == MCD_OK) {
-                for (int j = 0; j < m; j++)
-                    for (int a = 0; a < P; a++)
-                        for (int b = 0; b < P; b++)
-                            C[((size_t)j * P + a) * P + b] = -Om[((size_t)j * P + a) * P + b];
-                if (hipMemsetAsync(run.W, 0, (size_t)nx * P * sizeof(T), s) != hipSuccess)
-                    rc = MCD_E_HIP;
-                if (rc == MCD_OK) rc = run.block_apply(run.blk(0), m, C, run.W, true);
-            }
-            if (rc == MCD_OK) {
-                hipLaunchKernelGGL((k_start_block_t<T>), dim3(gridn(n, 256)), dim3(256), 0, s, n,
-                                   keys_dev, sel, create ? 1 : 0, op->d_hash, op->hash_mask, P,
-                                   run.W, lam);
-                if (hipGetLastError() != hipSuccess) rc = MCD_E_HIP;
-            }
-            if (hipStreamSynchronize(s) != hipSuccess && rc == MCD_OK) rc = MCD_E_HIP;
-            zarena.release();   // after the synchronisation above
-            if (rc == MCD_E_HIP) set_error("green vjp: device step failed in a sector hook");
-            return rc;
         }
+        if (rc == MCD_OK) {
+            hipLaunchKernelGGL((k_start_block_t<T>), dim3(gridn(n, 256)), dim3(256), 0, s, n,
+                               keys_dev, sel, create ? 1 : 0, op->d_hash, op->hash_mask, P, Wo,
+                               lam);
+            if (hipGetLastError() != hipSuccess) rc = MCD_E_HIP;
+        }
+        if (hipStreamSynchronize(s) != hipSuccess && rc == MCD_OK) rc = MCD_E_HIP;
+        za.release();   // after the synchronisation above
+        if (rc == MCD_E_HIP) set_error("green vjp: device step failed in a sector");
+        return rc;
     };
+
     int64_t npl = 0, nmi = 0;
     {
-        // the forward call's sector runs, kept, or recomputed here with every
-        // Krylov block stored (from psi0 as given: the cut normalises it
-        // exactly as the forward call does, so the recurrence is the same)
+        // the forward call's sector runs, kept, or recomputed here (from psi0
+        // as given: the cut normalises it exactly as the forward call does, so
+        // the recurrence is the same), every block stored unless streaming
         Instance<T> *src = keep;
         if (!keep) {
             rec.model = model;
@@ -2688,8 +2765,8 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             rec.psi = psi0_dev;
             rec.e0 = e0;
             std::vector<Instance<T> *> one{&rec};
-            TRY(band_green_multi<T>(one, sel, n_freq, omega, cfg, ws, s, true, nullptr, true,
-                                    nullptr));
+            TRY(band_green_multi<T>(one, sel, n_freq, omega, cfg, ws, s, !streaming, nullptr,
+                                    true, nullptr));
             src = &rec;
         }
         npl = src->plus.n;
@@ -2697,9 +2774,11 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
         for (int side = 0; side < 2; side++) {
             BandRun<T> &r = side == 0 ? src->plus : src->minus;
             if (r.br.m > 0 && r.op) {
+                SectorPrep sp;
+                prep(r, side == 0, sp);
                 const hipStream_t s_prev = r.s;
                 r.s = s;
-                const int rc_h = hook(r, side == 0);
+                const int rc_h = sector(r, side == 0, sp);
                 r.s = s_prev;
                 TRY(rc_h);
             }

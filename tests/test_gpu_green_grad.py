@@ -171,11 +171,12 @@ def test_green_vjp_with_convergence_stop_replays_forward():
 def test_green_vjp_on_kept_runs_is_bit_identical(prec, reorth):
     """mcd_band_green_vjp_keep on the sector runs kept by the forward call gives
     exactly the derivative of mcd_band_green_vjp (which recomputes the same
-    runs, every block stored), twice in a row on one handle; the kept
-    forward's G equals the plain forward's (bit for bit with reorth = 1; with
-    reorth = 0 the plain forward keeps a ring of three blocks, whose
-    three-term update takes two passes where the ring wraps, so to rounding);
-    arguments that differ from the kept call are rejected."""
+    runs), twice in a row on one handle; the kept forward's G equals the
+    plain forward's bit for bit (with reorth = 0 the plain forward keeps a
+    ring of three blocks, the kept one every block: the three-term update
+    reads block j at its signed offset from block j - 1, so both take the
+    same single pass); arguments that differ from the kept call are
+    rejected."""
     torch, mcd = require_gpu()
     m = W.impurity_plaquette_bath(6)
     keys, _ = sampler.chain_c(m, W.neel_start(m), 2, 15000, 500, 10**7)
@@ -190,10 +191,7 @@ def test_green_vjp_on_kept_runs_is_bit_identical(prec, reorth):
     G0, info0 = mcd.band_lanczos_green(m, kd, psi, e0, orbs, spins, om, **kw)
     G1, info1, kept = mcd.band_lanczos_green(m, kd, psi, e0, orbs, spins, om, keep=True, **kw)
     try:
-        if reorth > 0:
-            assert np.array_equal(G0, G1) and info0.iters == info1.iters
-        else:
-            assert _rel(G1, G0) < (1e-5 if prec == "f32" else 1e-12)
+        assert np.array_equal(G0, G1) and info0.iters == info1.iters
         ref = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=0.3, **kw)
         for _ in range(2):
             got = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=0.3,
@@ -207,6 +205,40 @@ def test_green_vjp_on_kept_runs_is_bit_identical(prec, reorth):
         with pytest.raises(mcd.McdError):
             mcd.band_green_vjp(m, kd, psi, e0, [0, 1, 2, 3], [0, 0, 0, 0], om, Gb, keep=kept,
                                **kw)
+    finally:
+        kept.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_streaming_vjp_batches_and_chunks(prec):
+    """Without kept runs and without reorthogonalisation the derivative
+    regenerates the Krylov blocks in a second pass of the recurrence: with the
+    frequencies in batches and the blocks in chunks of other sizes it gives
+    the same derivative to rounding, and on kept (stored) runs with the same
+    batch and chunk sizes bit for bit."""
+    torch, mcd = require_gpu()
+    m = W.impurity_plaquette_bath(6)
+    keys, _ = sampler.chain_c(m, W.neel_start(m), 2, 15000, 500, 10**7)
+    kd = mcd.keys_from_numpy(keys)
+    om = W.matsubara(16, 50.0)
+    orbs, spins = [0, 1, 2, 3], [0, 0, 1, 1]
+    rng = np.random.default_rng(5)
+    Gb = rng.normal(size=(16, 4, 4)) + 1j * rng.normal(size=(16, 4, 4))
+    kw = dict(max_blocks=120, reorth=0, g_tol=1e-8, precision=prec)
+    log_case("green_vjp_streaming", n=len(keys), prec=prec)
+    e0, psi = _gpu_ground(mcd, m, kd)
+    ref = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=0.2, **kw)
+    bat = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=0.2, vjp_freq_batch=5,
+                             vjp_chunk=3, **kw)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    for a, b in zip(bat[:3], ref[:3]):
+        assert np.all(np.isfinite(a)) and _rel(a, b) <= tol
+    G, info, kept = mcd.band_lanczos_green(m, kd, psi, e0, orbs, spins, om, keep=True, **kw)
+    try:
+        got = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=0.2, keep=kept,
+                                 vjp_freq_batch=5, vjp_chunk=3, **kw)
+        for a, b in zip(got[:3], bat[:3]):
+            assert np.array_equal(a, b)
     finally:
         kept.close()
 
