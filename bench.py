@@ -659,11 +659,12 @@ def main():
     info = op.info()
     n, nnz = info["n"], info["nnz"]
     # compulsory bytes of one product: row pointers, entry words, diagonal,
-    # x and y; the grouped layout also reads its block row starts, group
-    # offsets and group table once per product
+    # x and y; the grouped layout also reads its block row starts, entry
+    # starts and group offsets (8 B each per block) and its group table (4 B
+    # per group) once per product
     alg_bytes = 8.0 * (n + 1) + 4.0 * nnz + 24.0 * n
     if info["kernel"] in ("grouped", "grouped_xcd"):
-        alg_bytes += 16.0 * (info["grouped_blocks"] + 1) + 8.0 * (info["grouped_groups"] + 1)
+        alg_bytes += 24.0 * (info["grouped_blocks"] + 1) + 4.0 * (info["grouped_groups"] + 1)
 
     def step():
         return mcd.lanczos_ground(op, max_iter=ITERS, tol=0.0, seed=11, check_every=50,

@@ -20,9 +20,12 @@
 //   one 32-bit word per entry, bits 0-11 = row-major slot in the block;
 //     down (bit 31 = 0): bits 12-26 column - r0 + 16384, 27-29 class, 30 sign
 //     up   (bit 31 = 1): bits 12-23 column - group base, 24-30 group in block
-//   group table (<= kGroupedMaxGroups per block): base column | class << 32 |
-//   sign << 37 (an up hop's |t| class and JW sign depend only on u and the
-//   bond, so they are the same for every entry of a group).
+//   group table (<= kGroupedMaxGroups per block), one 32-bit word per group:
+//   base column (bits 0-27) | class << 28 | sign << 31 (an up hop's |t|
+//   class and JW sign depend only on u and the bond, so they are the same
+//   for every entry of a group).  Bits 27-30 of a down word and 28-31 of a
+//   group word are both class | sign << 3: one signed-amplitude table of 16
+//   entries serves both kinds.
 // A basis whose segments are too short (many groups per block) or too long
 // (offsets out of range) does not get the layout; the other kernels serve it.
 //
@@ -34,6 +37,7 @@
 //   k_g_heads      segment head flags (up string changes)
 //   k_g_keys       sort key per entry: (block, up, source segment, column)
 //   k_g_starts     group start flags in sorted order
+//   k_g_entry_starts first entry of each block
 //   k_g_goff       first group of each block; groups per block checked
 //   k_g_tables     group table at each group start
 //   k_g_words      entry words; ranges and group uniformity checked
@@ -161,6 +165,14 @@ __global__ void k_g_starts(int64_t nnz, const uint64_t *__restrict__ skey,
     flag[p] = start ? 1u : 0u;
 }
 
+// gbe[b] = first entry of block b (its first row's row pointer).
+__global__ void k_g_entry_starts(int64_t nb, const int64_t *__restrict__ gbs,
+                                 const int64_t *__restrict__ rowptr, int64_t *__restrict__ gbe) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nb) return;
+    gbe[b] = rowptr[gbs[b]];
+}
+
 // goff[b] = groups in the entries before block b (inclusive scan `gid`).
 __global__ void k_g_goff(int64_t nb, const int64_t *__restrict__ gbs,
                          const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ gid,
@@ -180,17 +192,19 @@ __global__ void k_g_goff(int64_t nb, const int64_t *__restrict__ gbs,
 __global__ void k_g_tables(int64_t nnz, const uint32_t *__restrict__ sval,
                            const uint32_t *__restrict__ flag,
                            const uint32_t *__restrict__ gid, const uint32_t *__restrict__ colw,
-                           uint32_t col_mask, int col_bits, uint64_t *__restrict__ gtab) {
+                           uint32_t col_mask, int col_bits, uint32_t *__restrict__ gtab) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nnz || !flag[p]) return;
     const uint32_t w = colw[sval[p]];
-    const uint64_t cls = (uint64_t)((w & 0x7fffffffu) >> col_bits);
-    gtab[gid[p] - 1] = (uint64_t)(w & col_mask) | (cls << 32) | ((uint64_t)(w >> 31) << 37);
+    const uint32_t cls = (w & 0x7fffffffu) >> col_bits;
+    // (a column past 28 bits or a class past 3 is caught by k_g_words)
+    gtab[gid[p] - 1] = (w & col_mask & 0x0fffffffu) | ((uint32_t)(cls & 7u) << 28) |
+                       ((w >> 31) << 31);
 }
 
 __global__ void k_g_words(int64_t nnz, const uint64_t *__restrict__ skey,
                           const uint32_t *__restrict__ sval, const uint32_t *__restrict__ gid,
-                          const uint64_t *__restrict__ gtab, const int64_t *__restrict__ goff,
+                          const uint32_t *__restrict__ gtab, const int64_t *__restrict__ goff,
                           const int64_t *__restrict__ gbs, const int64_t *__restrict__ rowptr,
                           const uint32_t *__restrict__ colw, uint32_t col_mask, int col_bits,
                           int colbits, int segbits, uint32_t *__restrict__ gw,
@@ -214,11 +228,11 @@ __global__ void k_g_words(int64_t nnz, const uint64_t *__restrict__ skey,
         out = (sg << 30) | (cls << 27) | ((uint32_t)(off & 32767) << 12) | (uint32_t)(slot & 4095);
     } else {
         const int64_t g = (int64_t)gid[p] - 1;
-        const uint64_t t = gtab[g];
+        const uint32_t t = gtab[g];
         const int64_t gl = g - goff[b];
-        const int64_t off = col - (int64_t)(uint32_t)t;
-        ok = ok && gl >= 0 && gl < kGroupedMaxGroups && off >= 0 && off < 4096 &&
-             (uint32_t)((t >> 32) & 31u) == cls && (uint32_t)((t >> 37) & 1u) == sg;
+        const int64_t off = col - (int64_t)(t & 0x0fffffffu);
+        ok = ok && gl >= 0 && gl < kGroupedMaxGroups && off >= 0 && off < 4096 && cls < 8u &&
+             col < (int64_t(1) << 28) && ((t >> 28) & 7u) == cls && (t >> 31) == sg;
         out = 0x80000000u | ((uint32_t)(gl & 127) << 24) | ((uint32_t)(off & 4095) << 12) |
               (uint32_t)(slot & 4095);
     }
@@ -229,22 +243,59 @@ __global__ void k_g_words(int64_t nnz, const uint64_t *__restrict__ skey,
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Decoding of an entry word v (layout above): the column it gathers and the
+// index sc = class | sign << 3 of its signed amplitude.  ge = the block's
+// group-table word of the group field of v (read for every word; a down
+// word's bits 24-30 are its class, sign and high offset bits, so the read
+// stays inside the 128-entry table and its value is not used); r0m = the
+// block's first row - 16384, modulo 2^32.  Columns are < 2^28 (the layout is
+// only built for such bases), so 32-bit arithmetic is exact and the two
+// cases are selects, not branches.
+__device__ __forceinline__ uint32_t g_decode(uint32_t v, uint32_t ge, uint32_t r0m, uint32_t &sc) {
+    const bool up = (int32_t)v < 0;
+    const uint32_t cu = (ge & 0x0fffffffu) + ((v >> 12) & 4095u);
+    const uint32_t cd = r0m + ((v >> 12) & 32767u);
+    sc = up ? (ge >> 28) : ((v >> 27) & 15u);
+    return up ? cu : cd;
+}
+
+// x[col] for a column < 2^28 (a 32-bit byte offset from x).
+template <typename T>
+__device__ __forceinline__ T g_gather(const T *__restrict__ x, uint32_t col) {
+    return *(const T *)((const char *)x + (size_t)(col * (uint32_t)sizeof(T)));
+}
+
+// Signed amplitudes amp[class | sign << 3] = +-|t_class| (into LDS by the
+// first 16 threads).
+template <typename T>
+__device__ __forceinline__ void g_amp_table(const DevModel *__restrict__ m, T *amp) {
+    const int t = threadIdx.x;
+    if (t < 16) {
+        const T a = (T)m->vtab[t & 7];
+        amp[t] = (t & 8) ? -a : a;
+    }
+}
+
 // The product.  A workgroup owns one row block: it loads the block's group
 // table into LDS together with its rows' pointers, diagonal and x_r and its
-// entry words (all unconditional loads on clamped addresses), decodes the
-// columns, issues the gathers, writes each signed product to the entry's
-// row-major slot in LDS, and each row adds its run in entry order.
+// entry words (all unconditional loads on clamped addresses: the lanes past
+// the block's last entry repeat it and so write the same value to the same
+// slot), decodes the columns, issues the gathers, writes each signed product
+// to the entry's row-major slot in LDS, and each row adds its run in entry
+// order.  -(a x) and (-a) x are the same number, so y is bit-identical to
+// the row-major kernels.
 template <typename T, int NMAX>
 __global__ __launch_bounds__(BS) void k_spmv_grouped(
-    int64_t nblocks, const int64_t *__restrict__ gbs, const int64_t *__restrict__ goff,
-    const uint64_t *__restrict__ gtab, const int64_t *__restrict__ rowptr,
-    const uint32_t *__restrict__ gw, const DevModel *__restrict__ m,
-    const double *__restrict__ diag, const T *__restrict__ x, T *__restrict__ y,
-    const double *__restrict__ sx_dev, int sx_mode, double *__restrict__ partials, int xcd_major) {
+    int64_t nblocks, const int64_t *__restrict__ gbs, const int64_t *__restrict__ gbe,
+    const int64_t *__restrict__ goff, const uint32_t *__restrict__ gtab,
+    const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ gw,
+    const DevModel *__restrict__ m, const double *__restrict__ diag, const T *__restrict__ x,
+    T *__restrict__ y, const double *__restrict__ sx_dev, int sx_mode,
+    double *__restrict__ partials, int xcd_major) {
     constexpr int DEPTH = NMAX / BS;
     __shared__ T prod[NMAX];
-    __shared__ T vtab[kMaxClasses];
-    __shared__ uint64_t gt[kGroupedMaxGroups];
+    __shared__ T amp[16];
+    __shared__ uint32_t gt[kGroupedMaxGroups];
     const int tid = threadIdx.x;
     int64_t blk = blockIdx.x;
     if (xcd_major) {
@@ -258,52 +309,36 @@ __global__ __launch_bounds__(BS) void k_spmv_grouped(
     const int64_t r0 = gbs[blk], r1 = gbs[blk + 1];
     const int64_t g0 = goff[blk];
     const int ng = (int)(goff[blk + 1] - g0);
-    const uint64_t gme = gtab[g0 + min(tid, ng)];   // table has one spare entry at the end
+    const uint32_t gme = gtab[g0 + min(tid, ng)];   // table has one spare entry at the end
     const bool own = r0 + tid < r1;
     const int64_t r = min(r0 + (int64_t)tid, r1 - 1);
     const int64_t rs = rowptr[r], re = rowptr[r + 1];
     const double dr = diag[r];
     const T xr = x[r];
-    const int64_t e0 = rowptr[r0];
-    const int cnt = (int)(rowptr[r1] - e0);
+    const int64_t e0 = gbe[blk];
+    const int cnt = (int)(gbe[blk + 1] - e0);
     uint32_t w[DEPTH];
-    T xv[DEPTH];
 #pragma unroll
     for (int j = 0; j < DEPTH; j++) w[j] = 0u;
     if (cnt > 0) {   // uniform over the workgroup
         const uint32_t *__restrict__ cw = gw + e0;
 #pragma unroll
-        for (int j = 0; j < DEPTH; j++) w[j] = cw[min(tid + j * BS, cnt - 1)];
+        for (int j = 0; j < DEPTH; j++)
+            w[j] = *(const uint32_t *)((const char *)cw +
+                                       (size_t)(4u * (uint32_t)min(tid + j * BS, cnt - 1)));
     }
     if (tid < ng && tid < kGroupedMaxGroups) gt[tid] = gme;
-    if (tid < kMaxClasses) vtab[tid] = (T)m->vtab[tid];
+    g_amp_table<T>(m, amp);
     __syncthreads();
     if (cnt > 0) {
+        const uint32_t r0m = (uint32_t)(r0 - 16384);
+        T xv[DEPTH];
+        uint32_t sc[DEPTH];
 #pragma unroll
-        for (int j = 0; j < DEPTH; j++) {
-            const uint32_t v = w[j];
-            const int64_t col = (v >> 31)
-                                    ? (int64_t)(uint32_t)gt[(v >> 24) & 127u] + ((v >> 12) & 4095u)
-                                    : r0 - 16384 + (int64_t)((v >> 12) & 32767u);
-            xv[j] = x[col];
-        }
+        for (int j = 0; j < DEPTH; j++)
+            xv[j] = g_gather(x, g_decode(w[j], gt[(w[j] >> 24) & 127u], r0m, sc[j]));
 #pragma unroll
-        for (int j = 0; j < DEPTH; j++) {
-            if (tid + j * BS < cnt) {
-                const uint32_t v = w[j];
-                uint32_t cls, sg;
-                if (v >> 31) {
-                    const uint64_t g = gt[(v >> 24) & 127u];
-                    cls = (uint32_t)(g >> 32) & 31u;
-                    sg = (uint32_t)(g >> 37) & 1u;
-                } else {
-                    cls = (v >> 27) & 7u;
-                    sg = (v >> 30) & 1u;
-                }
-                const T a = vtab[cls];
-                prod[v & 4095u] = sg ? -(a * xv[j]) : a * xv[j];
-            }
-        }
+        for (int j = 0; j < DEPTH; j++) prod[w[j] & 4095u] = amp[sc[j]] * xv[j];
     }
     __syncthreads();
     const double sx = scale_from(sx_dev, sx_mode);
@@ -329,8 +364,8 @@ int grouped_one(const mcd_op *op, bool xcd, const T *x, T *y, const double *sx_d
     MCD_REQUIRE(partials == nullptr || g <= op->max_partials, MCD_E_CAPACITY,
                 "reduction scratch too small");
     hipLaunchKernelGGL((k_spmv_grouped<T, kGroupedNnz>), dim3((unsigned)g), dim3(BS), 0, s, nb,
-                       op->d_gbs, op->d_goff, op->d_gtab, op->d_rowptr, op->d_gw, op->d_model,
-                       op->d_diag, x, y, sx_dev, sx_mode, partials, xcd ? 1 : 0);
+                       op->d_gbs, op->d_gbe, op->d_goff, op->d_gtab, op->d_rowptr, op->d_gw,
+                       op->d_model, op->d_diag, x, y, sx_dev, sx_mode, partials, xcd ? 1 : 0);
     MCD_HIP(hipGetLastError());
     *grid = g;
     return MCD_OK;
@@ -381,7 +416,8 @@ void grouped_plan(WsAlloc &w, int64_t n, int64_t nnz) {
     get(sb4);
     get(sizeof(int));
     w.alloc((nb + 1) * 8);                                         // d_goff
-    w.alloc((size_t)(std::min<int64_t>(nnz, nb * kGroupedMaxGroups) + 1) * 8);   // d_gtab
+    w.alloc((nb + 1) * 8);                                         // d_gbe
+    w.alloc((size_t)(std::min<int64_t>(nnz, nb * kGroupedMaxGroups) + 1) * 4);   // d_gtab
     w.alloc(nnz * 4);                                              // d_gw
     for (size_t o : tmp) w.release(o);
 }
@@ -408,13 +444,13 @@ int build_grouped(mcd_op *op, hipStream_t s) {
         ntmp = 0;
     };
     int rc = MCD_OK;
-    int64_t *d_gbs = nullptr, *d_goff = nullptr;
-    uint64_t *d_gtab = nullptr;
+    int64_t *d_gbs = nullptr, *d_goff = nullptr, *d_gbe = nullptr;
+    uint32_t *d_gtab = nullptr;
     uint32_t *d_gw = nullptr;
     auto fail_hip = [&](hipError_t e, const char *what) {
         (void)hipStreamSynchronize(s);   // queued work may still read the pieces
         release();
-        for (void *p : {(void *)d_gbs, (void *)d_goff, (void *)d_gtab, (void *)d_gw})
+        for (void *p : {(void *)d_gbs, (void *)d_goff, (void *)d_gbe, (void *)d_gtab, (void *)d_gw})
             if (p) (void)dfree(p, al);
         if (e == hipErrorOutOfMemory) {   // no room in the workspace: no layout
             std::lock_guard<std::mutex> lock(al.ws->mu);
@@ -450,7 +486,8 @@ int build_grouped(mcd_op *op, hipStream_t s) {
     unsigned long long maxrow = 0;
     GK(hipMemcpyAsync(&maxrow, d_mx, sizeof(maxrow), hipMemcpyDeviceToHost, s));
     GK(hipStreamSynchronize(s));
-    if ((int64_t)nseg * 16 > n || maxrow >= (unsigned long long)(kGroupedNnz / 2)) {
+    if ((int64_t)nseg * 16 > n || maxrow >= (unsigned long long)(kGroupedNnz / 2) ||
+        n >= (int64_t(1) << 28)) {   // columns must fit 28 bits
         release();
         return MCD_OK;
     }
@@ -517,14 +554,18 @@ int build_grouped(mcd_op *op, hipStream_t s) {
     GK(get((void **)&bad, sizeof(int)));
     GK(hipMemsetAsync(bad, 0, sizeof(int), s));
     GK(dmalloc((void **)&d_goff, (nb + 1) * sizeof(int64_t), al));
+    GK(dmalloc((void **)&d_gbe, (nb + 1) * sizeof(int64_t), al));
+    hipLaunchKernelGGL(k_g_entry_starts, dim3(gridn(nb + 1)), dim3(BS), 0, s, nb, d_gbs,
+                       op->d_rowptr, d_gbe);
+    GK(hipGetLastError());
     hipLaunchKernelGGL(k_g_goff, dim3(gridn(nb + 1)), dim3(BS), 0, s, nb, d_gbs, op->d_rowptr, gid,
                        d_goff, bad);
     GK(hipGetLastError());
     uint32_t ngroups = 0;
     GK(hipMemcpyAsync(&ngroups, gid + (nnz - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     GK(hipStreamSynchronize(s));
-    GK(dmalloc((void **)&d_gtab, ((int64_t)ngroups + 1) * sizeof(uint64_t), al));
-    GK(hipMemsetAsync(d_gtab, 0, ((int64_t)ngroups + 1) * sizeof(uint64_t), s));
+    GK(dmalloc((void **)&d_gtab, ((int64_t)ngroups + 1) * sizeof(uint32_t), al));
+    GK(hipMemsetAsync(d_gtab, 0, ((int64_t)ngroups + 1) * sizeof(uint32_t), s));
     hipLaunchKernelGGL(k_g_tables, dim3(gridn(nnz)), dim3(BS), 0, s, nnz, v_out, flag, gid,
                        op->d_colw, dm.col_mask, (int)dm.col_bits, d_gtab);
     GK(hipGetLastError());
@@ -539,7 +580,7 @@ int build_grouped(mcd_op *op, hipStream_t s) {
     release();
 #undef GK
     if (hbad) {   // the basis does not fit the layout
-        for (void *p : {(void *)d_gbs, (void *)d_goff, (void *)d_gtab, (void *)d_gw})
+        for (void *p : {(void *)d_gbs, (void *)d_goff, (void *)d_gbe, (void *)d_gtab, (void *)d_gw})
             (void)dfree(p, al);
         return rc;
     }
@@ -547,9 +588,10 @@ int build_grouped(mcd_op *op, hipStream_t s) {
     op->g_ngroups = ngroups;
     op->d_gbs = d_gbs;
     op->d_goff = d_goff;
+    op->d_gbe = d_gbe;
     op->d_gtab = d_gtab;
     op->d_gw = d_gw;
-    op->device_bytes += (2 * (nb + 1) + ngroups + 1) * 8 + nnz * 4;
+    op->device_bytes += 3 * (nb + 1) * 8 + (ngroups + 1) * 4 + nnz * 4;
     return rc;
 }
 

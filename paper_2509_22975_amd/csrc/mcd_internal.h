@@ -204,7 +204,8 @@ struct mcd_op {
     int64_t g_ngroups;
     int64_t *d_gbs;                   // [g_nblocks + 1] first row of each block
     int64_t *d_goff;                  // [g_nblocks + 1] first group of each block
-    uint64_t *d_gtab;                 // [g_ngroups + 1] column | class << 32 | sign << 37
+    int64_t *d_gbe;                   // [g_nblocks + 1] first entry of each block
+    uint32_t *d_gtab;                 // [g_ngroups + 1] column | class << 28 | sign << 31
     uint32_t *d_gw;                   // [nnz] entry words in grouped order
     mcd::Alloc alloc;                 // the workspace the operator's buffers come from
 };
@@ -239,6 +240,7 @@ void grouped_plan(WsAlloc &w, int64_t n, int64_t nnz);
 template <typename T>
 int grouped_one(const mcd_op *op, bool xcd, const T *x, T *y, const double *sx_dev, int sx_mode,
                 double *partials, int64_t *grid, hipStream_t s);
+
 
 // Operator construction (mcd_op_create with tune = true); tune = false keeps
 // the default one-vector kernel (for operators used with block products).

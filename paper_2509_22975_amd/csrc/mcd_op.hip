@@ -1199,7 +1199,7 @@ extern "C" void mcd_op_destroy(mcd_op *op) {
                     (void *)op->d_partials, (void *)op->d_counter, (void *)op->d_scalars,
                     (void *)op->d_split_i, (void *)op->d_split_j, (void *)op->d_carry,
                     (void *)op->d_carry_row, (void *)op->d_gbs, (void *)op->d_goff,
-                    (void *)op->d_gtab, (void *)op->d_gw})
+                    (void *)op->d_gbe, (void *)op->d_gtab, (void *)op->d_gw})
         if (p) (void)dfree(p, op->alloc);
     delete op;
 }
