@@ -464,7 +464,9 @@ typedef struct mcd_band_cfg {
                                  contraction (0: all in one pass); each pass holds
                                  two n x 2 batch p work matrices per sector */
     int32_t vjp_chunk;        /* derivative calls: Krylov blocks per accumulation
-                                 (0: 16) */
+                                 (0: as many block columns as a work matrix
+                                 has columns, 2 batch p rounded up to 128,
+                                 at least 16 blocks) */
 } mcd_band_cfg;
 
 int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int64_t n,

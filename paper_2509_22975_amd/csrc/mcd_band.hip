@@ -2527,8 +2527,13 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
     double trM = 0.0;   // sum over sectors of tr(M)
     int krylov = 0;
     const int reorth = std::max(0, std::min(2, (int)cfg->reorth));
-    const int chunk = cfg->vjp_chunk > 0 ? cfg->vjp_chunk : 16;
     const int fb = cfg->vjp_freq_batch > 0 ? std::min<int>(cfg->vjp_freq_batch, n_freq) : n_freq;
+    // Default chunk: as many Krylov vectors as the work matrices U, V have
+    // columns (a chunk buffer no larger than U), at least 16 blocks; each
+    // flush reads and writes U and V once, so fewer flushes move less.
+    const int chunk = cfg->vjp_chunk > 0
+                          ? cfg->vjp_chunk
+                          : std::max(16, ((2 * fb * p + 127) / 128 * 128) / std::max(P, 1));
     // Without kept runs and without reorthogonalisation no Krylov block is
     // stored: a second pass of the recurrence (the same kernels on the same
     // data) regenerates Q_0, Q_1, ... one at a time.
