@@ -557,20 +557,27 @@ int mcd_batch_band_green(const mcd_model *const *models, const uint64_t *const *
  * G+(z) = B^T (z - H+)^-1 B with B = c+|psi0>, z = E0 + zeta (G- likewise
  * with minus signs), so dG/dtheta has three parts, all evaluated here:
  *   * the resolvent:  X^T (dH/dtheta - dE0/dtheta) X, X = (z - H)^-1 B,
- *     through the stored Krylov blocks Q (X = Q S, S from the block
- *     tridiagonal T): tr(Q^T dH/dtheta Q M) - tr(M) dE0/dtheta with M =
- *     Re sum_f S_f conj(G_bar_f)^T S_f^T, one contraction pass over F~+-;
+ *     through the Krylov blocks Q (X = Q S, S from the block tridiagonal
+ *     T): tr(Q^T dH/dtheta Q M) - tr(M) dE0/dtheta with M = Re sum_f S_f
+ *     conj(G_bar_f)^T S_f^T.  M = sg A B^T (A, B: m P x 2 n_freq p real), so
+ *     the trace is tr(U^T dH/dtheta V) with U = Q (sg A), V = Q B, which are
+ *     accumulated over chunks of Krylov blocks (MFMA products) and then
+ *     contracted in one pass over F~+- per batch of frequencies;
  *   * dE0/dtheta = <psi0| dH/dtheta |psi0> (Hellmann-Feynman);
  *   * the response of the start block through d psi0/dtheta =
  *     -(H - E0)^+ dH/dtheta psi0: one conjugate-gradient solve
  *     (H - E0) xi = P lambda on F~ (P projects out psi0, lambda collects the
  *     adjoint of the start blocks), then -<xi| dH/dtheta |psi0>.
  * The Krylov blocks are recomputed here (mcd_band_green_vjp_keep instead
- * takes them from a forward call that kept them).
+ * takes them from a forward call that kept them): with cfg->reorth > 0 the
+ * recomputed runs store every block (max_blocks + 1 blocks of n_x * P
+ * values per sector, as reorthogonalisation needs them anyway); with
+ * cfg->reorth = 0 no block is stored: a second pass of the same recurrence
+ * regenerates Q_0, Q_1, ... one at a time (three ring blocks and a chunk of
+ * cfg->vjp_chunk blocks in memory), with the same numbers bit for bit.
  *
  * psi0_dev: the normalised, non-degenerate ground state; cfg->w_t must be 1
- *   (a target-weight cut is not differentiable); every Krylov block is
- *   stored (max_blocks + 1 blocks of n_x * P values per sector).
+ *   (a target-weight cut is not differentiable).
  * G_bar: host complex128 [n_freq][n_sel][n_sel].
  * d_t [n_bonds] (listed bonds; a pair listed twice gets the pair's
  *   derivative in both entries), d_U [n_orb], d_eps [n_orb]: host outputs.
@@ -578,8 +585,9 @@ int mcd_batch_band_green(const mcd_model *const *models, const uint64_t *const *
  *   residual, krylov_dim, n_plus, n_minus, solve_ms.
  * cg_tol: relative residual of the solve (1e-12 is typical); cg_max_iter.
  * ws: the scratch of the call (ground-sector operator, solve vectors, the
- *   Z = Q M product, which has the size of one sector's Krylov store; without
- *   a kept forward also the two sector runs).
+ *   work matrices U and V, n_x x 2 batch p values each, rounded up to 128
+ *   columns, batch = cfg->vjp_freq_batch or n_freq; without a kept forward
+ *   also the two sector runs).
  * Returns MCD_NOCONV (outputs filled) if the solve stopped at cg_max_iter,
  * MCD_E_BREAKDOWN if it met <p, (H - E0) p> <= 0 (psi0 is not a
  * non-degenerate ground state of H~: the response is undefined).
