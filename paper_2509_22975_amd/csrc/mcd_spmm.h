@@ -78,12 +78,31 @@ __device__ __forceinline__ void block_csr_v_rows(const int64_t *__restrict__ row
         const T d = (T)diag[r];
         V acc = vscale(d, xv4[r * L + lane]);
         const int64_t e1 = rowptr[r + 1];
-        for (int64_t base = rowptr[r]; base < e1; base += CH) {
-            uint32_t mw[WPL];
+        // the words of the row's first two chunks are loaded at once (a row
+        // of up to 2 CH entries waits for one word load, not two)
+        uint32_t mw2[2 * WPL];
+        {
+            const int64_t b0 = rowptr[r];
 #pragma unroll
-            for (int q = 0; q < WPL; q++) {
-                const int64_t e = base + q * L + lane;
-                mw[q] = (q * L + lane < CH && e < e1) ? colw[e] : 0u;
+            for (int c = 0; c < 2; c++)
+#pragma unroll
+                for (int q = 0; q < WPL; q++) {
+                    const int64_t e = b0 + c * CH + q * L + lane;
+                    mw2[c * WPL + q] = (q * L + lane < CH && e < e1) ? colw[e] : 0u;
+                }
+        }
+        int chunk = 0;
+        for (int64_t base = rowptr[r]; base < e1; base += CH, chunk++) {
+            uint32_t mw[WPL];
+            if (chunk < 2) {
+#pragma unroll
+                for (int q = 0; q < WPL; q++) mw[q] = chunk == 0 ? mw2[q] : mw2[WPL + q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < WPL; q++) {
+                    const int64_t e = base + q * L + lane;
+                    mw[q] = (q * L + lane < CH && e < e1) ? colw[e] : 0u;
+                }
             }
             uint32_t wj[CH];
             V xg[CH];
