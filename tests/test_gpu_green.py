@@ -180,3 +180,43 @@ def test_green_stops_at_convergence():
     G3, i3 = mcd.band_lanczos_green(m, kd, pt, e0, orbs, spins, om, max_blocks=300, reorth=2,
                                     g_tol=1e-9)
     assert i3.iters == i1.iters and np.array_equal(G1, G3)
+
+
+def test_c5_full_size_e0_and_green():
+    """C5 at its full size (4x8 t-t', 50M chain states), end to end on the GPU
+    against the oracle's own run of the same pipeline
+    (tests/golden/c5_green.json, written by tests/golden/make_c5_green.py from
+    the oracle alone): float64 Lanczos from the seed-11 start vector to a
+    1e-10 Ritz residual, E0 to 1e-10 relative; the w_t = 0.999 cut and F~+-
+    (sizes equal); G of the up-spin orbitals 0..15 (band Lanczos to
+    exhaustion) at eight Matsubara frequencies to 1e-7 of max |G| (both
+    ground states carry a residual of ~1e-10 |E0|, which G sees linearly)."""
+    import json
+    import os
+    torch, mcd = require_gpu()
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c5_green.json")))
+    c = W.config_c5()
+    m = c["model"]
+    log_case("green_c5", n_f=c["n_f"])
+    kd, _ = mcd.basis_build(m, "chain", start_key=W.neel_start(m), seed=c["seed"],
+                            beta_s=c["beta_s"], burn_in=c["burn_in"], max_steps=c["max_steps"],
+                            n_f=c["n_f"])
+    assert kd.numel() == gold["n"]
+    op = mcd.Operator(m, kd, storage="csr")
+    e0, psi, _, _, info = mcd.lanczos_ground(op, max_iter=1000, tol=1e-10, seed=11,
+                                             store_vectors=False)
+    op.close()
+    print("[c5] E0 gpu", e0, "oracle", gold["e0"], "iters", info.iters, gold["lanczos_iters"],
+          flush=True)
+    assert info.converged
+    assert abs(e0 - gold["e0"]) <= 1e-10 * abs(gold["e0"])
+    om = W.matsubara(128, 50.0)
+    G, gi = mcd.band_lanczos_green(m, kd, psi, e0, list(range(16)), [0] * 16, om,
+                                   max_blocks=200, precision="f64", w_t=0.999, reorth=2)
+    assert (gi.n_truncated, gi.n_plus, gi.n_minus) == (gold["n_keep"], gold["n_plus"],
+                                                       gold["n_minus"])
+    ref = np.array(gold["G_re"]) + 1j * np.array(gold["G_im"])
+    got = G[gold["freq_index"]]
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    print("[c5] G max rel diff", err, flush=True)
+    assert err <= 1e-7
