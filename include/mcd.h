@@ -255,7 +255,8 @@ int mcd_op_info(const mcd_op *op, mcd_op_info_t *info);
  *       x; each entry keeps its row-major slot, so every row still adds its
  *       terms in entry order (y bit-identical to kernel 1).  Built at
  *       creation when the basis has up-string segments of >= 16 rows on
- *       average and every block fits 128 groups (mcd_op_info_t.grouped_blocks);
+ *       average, fewer than 2^28 rows, and every block fits 128 groups
+ *       (mcd_op_info_t.grouped_blocks);
  *   8 = 7 in XCD-major order.
  * All give the same result up to summation order: kernels 1, 3, 5, 6, 7
  * and 8 add each row's terms in the same order (bit-identical y); 2 and 4
