@@ -465,9 +465,10 @@ typedef struct mcd_band_cfg {
                                  contraction (0: all in one pass); each pass holds
                                  two n x 2 batch p work matrices per sector */
     int32_t vjp_chunk;        /* derivative calls: Krylov blocks per accumulation
-                                 (0: as many block columns as a work matrix
-                                 has columns, 2 batch p rounded up to 128,
-                                 at least 16 blocks) */
+                                 (0: S2 / P blocks, at least 16, where S2 = 2
+                                 batch p rounded up to 128 is the column count
+                                 of a work matrix: a chunk then holds as many
+                                 Krylov vectors as a work matrix has columns) */
 } mcd_band_cfg;
 
 int mcd_band_lanczos_green(const mcd_model *model, const uint64_t *keys_dev, int64_t n,
