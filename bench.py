@@ -184,9 +184,8 @@ def pipeline_c3(mcd, W, torch, max_blocks=200):
                 recurrence only, 1e-6 (float32 vectors hold G to ~1e-6).
     E0 errors are against the oracle's E0 of the same basis
     (tests/golden/precision_refs.json) and a GPU float64 solve to 1e-12; G
-    errors against a float64 band run converged to 1e-10 from that solve (the
-    oracle's G at this size is out of the host's reach; precision_vs_oracle
-    states G errors against the oracle on a 20k-state instance).
+    errors against the oracle's G of the same basis (tests/golden/c3_green.json)
+    and against a float64 band run converged to 1e-10 from that solve.
     """
     import numpy as np
     c = W.config_c3()
@@ -202,11 +201,26 @@ def pipeline_c3(mcd, W, torch, max_blocks=200):
                                          max_blocks=max_blocks, reorth=2, g_tol=1e-10)
     gold = json.load(open(os.path.join(HERE, "tests", "golden", "precision_refs.json")))["c3"]
     e_or = gold["e0"] if gold["n"] == keys.numel() else None
+    # the oracle's G of this instance (tests/golden/c3_green.json, written by
+    # tests/golden/make_c3_green.py from the oracle alone): block diagonal in
+    # spin, the two 4x4 blocks per frequency
+    G_or = None
+    pg = os.path.join(HERE, "tests", "golden", "c3_green.json")
+    if os.path.exists(pg):
+        go = json.load(open(pg))
+        if go["n"] == keys.numel() and go["n_freq"] == len(om):
+            G_or = np.zeros((len(om), 8, 8), dtype=np.complex128)
+            for sp in (0, 1):
+                b = np.array(go["G"][sp])                     # [freq][16][2]
+                G_or[:, 4 * sp:4 * sp + 4, 4 * sp:4 * sp + 4] = (
+                    b[:, :, 0] + 1j * b[:, :, 1]).reshape(len(om), 4, 4)
     out = {"workload": "2x2 plaquette + 8 baths, U=8, half filling, 0.5M chain states, p=8, "
                        "64 Matsubara frequencies (beta=50), band runs to convergence",
            "n_states": int(keys.numel()), "reference_blocks": gref.iters,
            "e0_oracle": e_or, "e0_ref_gpu_rel_err_vs_oracle":
-               None if e_or is None else abs(e_ref - e_or) / abs(e_or)}
+               None if e_or is None else abs(e_ref - e_or) / abs(e_or),
+           "G_ref_gpu_rel_err_vs_oracle":
+               None if G_or is None else float(np.max(np.abs(G_ref - G_or)) / np.max(np.abs(G_or)))}
     for form, lprec, ltol, prec, percol, reo, gt in (
             ("plain", "f64", 1e-9, "f64", True, 2, 1e-9),
             ("f64_block", "f64", 1e-9, "f64", False, 0, 1e-9),
@@ -229,6 +243,8 @@ def pipeline_c3(mcd, W, torch, max_blocks=200):
                      "e0_rel_err": abs(e0 - e_ref) / abs(e_ref),
                      "e0_rel_err_vs_oracle": None if e_or is None else abs(e0 - e_or) / abs(e_or),
                      "G_rel_err": float(np.max(np.abs(G - G_ref)) / np.max(np.abs(G_ref))),
+                     "G_rel_err_vs_oracle": None if G_or is None else
+                         float(np.max(np.abs(G - G_or)) / np.max(np.abs(G_or))),
                      "g_tol": gt, "block_steps": gi.iters, "reorth_passes": reo,
                      "n_plus": gi.n_plus, "n_minus": gi.n_minus, "krylov_dim": gi.krylov_dim}
     out["speedup_total"] = round(out["plain"]["total_s"] / out["chosen"]["total_s"], 3)

@@ -220,3 +220,42 @@ def test_c5_full_size_e0_and_green():
     err = float(np.abs(got - ref).max() / np.abs(ref).max())
     print("[c5] G max rel diff", err, flush=True)
     assert err <= 1e-7
+
+
+def test_c3_full_size_green_vs_oracle():
+    """C3 at its full size (2x2 plaquette + 8 baths, 0.5M chain states, sites
+    0..3 of both spins, 64 Matsubara frequencies) against the oracle's G of
+    the same basis (tests/golden/c3_green.json, written by
+    tests/golden/make_c3_green.py from the oracle alone; oracle ground state
+    at a 1e-12 residual, band Lanczos with full reorthogonalisation): the
+    float64 form (two reorthogonalisation passes, run until G settles to
+    1e-10) to 1e-9 of max |G| (6e-14 seen), the float32-block form to 1e-5
+    (2e-6 seen); G is block diagonal in spin."""
+    import json
+    import os
+    torch, mcd = require_gpu()
+    go = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c3_green.json")))
+    c = W.config_c3()
+    m = c["model"]
+    log_case("green_c3", n_f=c["n_f"])
+    kd, _ = mcd.basis_build(m, "chain", start_key=W.neel_start(m), seed=c["seed"],
+                            beta_s=c["beta_s"], burn_in=c["burn_in"], max_steps=c["max_steps"],
+                            n_f=c["n_f"])
+    assert kd.numel() == go["n"]
+    op = mcd.Operator(m, kd, storage="csr")
+    e0, psi, _, _, info = mcd.lanczos_ground(op, max_iter=3000, tol=1e-12, seed=11)
+    op.close()
+    assert info.converged and abs(e0 - go["e0"]) <= 1e-11 * abs(go["e0"])
+    om = W.matsubara(go["n_freq"], go["beta_m"])
+    ref = np.zeros((len(om), 8, 8), dtype=np.complex128)
+    for sp in (0, 1):
+        b = np.array(go["G"][sp])
+        ref[:, 4 * sp:4 * sp + 4, 4 * sp:4 * sp + 4] = (b[:, :, 0] + 1j * b[:, :, 1]).reshape(
+            len(om), 4, 4)
+    orbs, spins = [0, 1, 2, 3] * 2, [0] * 4 + [1] * 4
+    for prec, reorth, gt, tol in (("f64", 2, 1e-10, 1e-9), ("f32", 0, 1e-6, 1e-5)):
+        G, gi = mcd.band_lanczos_green(m, kd, psi, e0, orbs, spins, om, max_blocks=200,
+                                       precision=prec, reorth=reorth, g_tol=gt)
+        err = float(np.abs(G - ref).max() / np.abs(ref).max())
+        print(f"[c3] {prec}: {gi.iters} block steps, G max rel diff {err:.2e}", flush=True)
+        assert err <= tol, prec
