@@ -461,10 +461,12 @@ typedef struct mcd_band_cfg {
                                  axis and 7 evenly spaced) changes by <= g_tol
                                  max|G| between checks 8 block steps apart;
                                  0: run max_blocks steps (or to exhaustion) */
-    int32_t vjp_freq_batch;   /* derivative calls: frequencies per pass of the
-                                 contraction (0: all in one pass); each pass holds
-                                 two n x 2 batch p work matrices per sector */
-    int32_t vjp_chunk;        /* derivative calls: Krylov blocks per accumulation
+    int32_t vjp_freq_batch;   /* derivative calls with regenerated blocks:
+                                 frequencies per pass of the contraction (0: all
+                                 in one pass); each pass holds two n x 2 batch p
+                                 work matrices per sector */
+    int32_t vjp_chunk;        /* derivative calls with regenerated blocks: Krylov
+                                 blocks per accumulation
                                  (0: S2 / P blocks, at least 16, where S2 = 2
                                  batch p rounded up to 128 is the column count
                                  of a work matrix: a chunk then holds as many
@@ -561,10 +563,12 @@ int mcd_batch_band_green(const mcd_model *const *models, const uint64_t *const *
  *   * the resolvent:  X^T (dH/dtheta - dE0/dtheta) X, X = (z - H)^-1 B,
  *     through the Krylov blocks Q (X = Q S, S from the block tridiagonal
  *     T): tr(Q^T dH/dtheta Q M) - tr(M) dE0/dtheta with M = Re sum_f S_f
- *     conj(G_bar_f)^T S_f^T.  M = sg A B^T (A, B: m P x 2 n_freq p real), so
- *     the trace is tr(U^T dH/dtheta V) with U = Q (sg A), V = Q B, which are
- *     accumulated over chunks of Krylov blocks (MFMA products) and then
- *     contracted in one pass over F~+- per batch of frequencies;
+ *     conj(G_bar_f)^T S_f^T = sg A B^T (A, B: m P x 2 n_freq p real).  With
+ *     every block stored: Z = Q (M + M^T) (one MFMA product) and the trace
+ *     as the symmetric contraction of Q with Z, each hop pair once.  With
+ *     the blocks regenerated: tr(U^T dH/dtheta V), U = Q (sg A), V = Q B
+ *     accumulated over chunks of blocks (MFMA products) and contracted per
+ *     batch of frequencies.  The two forms agree to rounding;
  *   * dE0/dtheta = <psi0| dH/dtheta |psi0> (Hellmann-Feynman);
  *   * the response of the start block through d psi0/dtheta =
  *     -(H - E0)^+ dH/dtheta psi0: one conjugate-gradient solve
@@ -586,10 +590,11 @@ int mcd_batch_band_green(const mcd_model *const *models, const uint64_t *const *
  * info: iters = conjugate-gradient iterations, residual = its relative
  *   residual, krylov_dim, n_plus, n_minus, solve_ms.
  * cg_tol: relative residual of the solve (1e-12 is typical); cg_max_iter.
- * ws: the scratch of the call (ground-sector operator, solve vectors, the
- *   work matrices U and V, n_x x 2 batch p values each, rounded up to 128
- *   columns, batch = cfg->vjp_freq_batch or n_freq; without a kept forward
- *   also the two sector runs).
+ * ws: the scratch of the call (ground-sector operator, solve vectors; with
+ *   a store Z, n_x x m P values rounded up to 128 columns; with regenerated
+ *   blocks the work matrices U and V, n_x x 2 batch p values each, rounded
+ *   up to 128 columns, batch = cfg->vjp_freq_batch or n_freq, and a chunk of
+ *   blocks; without a kept forward also the two sector runs).
  * Returns MCD_NOCONV (outputs filled) if the solve stopped at cg_max_iter,
  * MCD_E_BREAKDOWN if it met <p, (H - E0) p> <= 0 (psi0 is not a
  * non-degenerate ground state of H~: the response is undefined).

@@ -2103,6 +2103,43 @@ __global__ void k_start_block_t(int64_t m, const uint64_t *__restrict__ keys, Se
     lam[r] += acc;
 }
 
+// The adjoint's weight matrix in symmetric form, for a store holding every
+// Krylov block: Mp[i][j] = sg (A[i].B[j] + A[j].B[i]) = (M + M^T)[i][j] with
+// M = sg A B^T (A, B: KP x K2 row-major float64), Mp [S][S] row-major in the
+// store's type, zero past KP.  16 x 16 tiles, the four row panels staged
+// through LDS in steps of 32 of k, one accumulator per dot summed in k order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sym_gram(int KP, int K2, int S, double sg,
+                                                 const double *__restrict__ A,
+                                                 const double *__restrict__ B,
+                                                 T *__restrict__ Mp) {
+    constexpr int TW = 16, KC = 32;
+    __shared__ double Ai[TW][KC + 1], Bj[TW][KC + 1], Aj[TW][KC + 1], Bi[TW][KC + 1];
+    const int tx = threadIdx.x, ty = threadIdx.y, t = ty * TW + tx;
+    const int i0 = blockIdx.y * TW, j0 = blockIdx.x * TW;
+    double s1 = 0.0, s2 = 0.0;
+    for (int k0 = 0; k0 < K2; k0 += KC) {
+        for (int e = t; e < TW * KC; e += TW * TW) {
+            const int rr = e / KC, kk = e % KC, k = k0 + kk;
+            const int ri = i0 + rr, rj = j0 + rr;
+            const bool kin = k < K2;
+            Ai[rr][kk] = kin && ri < KP ? A[(size_t)ri * K2 + k] : 0.0;
+            Bi[rr][kk] = kin && ri < KP ? B[(size_t)ri * K2 + k] : 0.0;
+            Aj[rr][kk] = kin && rj < KP ? A[(size_t)rj * K2 + k] : 0.0;
+            Bj[rr][kk] = kin && rj < KP ? B[(size_t)rj * K2 + k] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < KC; kk++) {
+            s1 = fma(Ai[ty][kk], Bj[tx][kk], s1);
+            s2 = fma(Aj[tx][kk], Bi[ty][kk], s2);
+        }
+        __syncthreads();
+    }
+    const int i = i0 + ty, j = j0 + tx;
+    if (i < S && j < S) Mp[(size_t)i * S + j] = (T)(sg * s1 + sg * s2);
+}
+
 // Zt += Q M for the adjoint: Q consecutive Krylov blocks (n x P each, P a
 // power of two; Q[r][k] = block k / P, row r, column k % P, k < KP), M
 // row-major with S columns and Zt [n][S] row-major, S a multiple of 128.  A
@@ -2215,11 +2252,16 @@ static constexpr int kMaxParams = MCD_MAX_BONDS + 2 * MCD_MAX_ORB;
 // row Rt[col] with all NR loads issued together: loads past column S read the
 // next row (or a zeroed tail of at least 64 (NR - S / 64) values after the
 // last row) and meet zero weights.  Each wave keeps its own accumulators
-// (fixed order).
-template <typename T, int NR>
+// (fixed order).  SYM: L is instead a block-major Krylov store (column a =
+// block a >> pl, entry a & (2^pl - 1)) and Rt = L (M + M^T) for the weight M:
+// a hop pair r <-> c (same bond, same sign both ways) contributes
+// L[r].(L M)[c] + L[c].(L M)[r] = L[r].Rt[c], so only hops with c > r are
+// taken (half the gathers) and the diagonal term is L[r].Rt[r] / 2; the sums
+// are then those of tr(L^T dH_p L M).
+template <typename T, int NR, bool SYM>
 __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
     int64_t n, const uint64_t *__restrict__ keys, const DevModel *__restrict__ m,
-    const HashSlot *__restrict__ h, uint64_t hmask, const T *__restrict__ L, int KP,
+    const HashSlot *__restrict__ h, uint64_t hmask, const T *__restrict__ L, int KP, int pl,
     const T *__restrict__ Rt, int S, double *__restrict__ part) {
     __shared__ double acc[kCWaves][kMaxParams];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -2229,7 +2271,12 @@ __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
          r += (int64_t)gridDim.x * kCWaves) {
         const uint64_t key = keys[r];
         const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
-        auto lval = [&](int a) -> T { return a < KP ? L[r * (int64_t)S + a] : (T)0; };
+        auto lval = [&](int a) -> T {
+            if (a >= KP) return (T)0;
+            if constexpr (SYM)   // block-major Krylov store
+                return L[(((int64_t)(a >> pl) * n + r) << pl) | (a & ((1 << pl) - 1))];
+            return L[r * (int64_t)S + a];
+        };
         T qv[NR > 0 ? NR : 1];
         if constexpr (NR > 0) {
 #pragma unroll
@@ -2260,6 +2307,7 @@ __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
                 if (__popc(sp & mask) == 1) {
                     col = hash_find(h, hmask, key ^ ((uint64_t)mask << ((hl & 1) ? 0 : 32)));
                     neg = __popc(sp & between) & 1;
+                    if (SYM && col <= r) col = -1;   // each pair once (from its lower row)
                 }
             }
             uint64_t live = __ballot(col >= 0);
@@ -2284,7 +2332,7 @@ __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
             }
             if (cur >= 0 && lane == 0) acc[wid][cur] += c;
         }
-        const double d = rowdot(r);
+        const double d = SYM ? 0.5 * rowdot(r) : rowdot(r);
         if (lane == 0) {
             for (int i = 0; i < no; i++) {
                 const double nu = (double)((up >> i) & 1u), nd = (double)((dn >> i) & 1u);
@@ -2301,12 +2349,14 @@ __global__ __launch_bounds__(64 * kCWaves) void k_contract_rows(
     }
 }
 
-template <typename T>
+template <typename T, bool SYM = false>
 static void launch_contract_rows(unsigned g, hipStream_t s, int64_t n, const mcd_op *op,
-                                 const T *L, int KP, const T *Rt, int S, double *part) {
+                                 const T *L, int KP, const T *Rt, int S, double *part,
+                                 int pl = 0) {
 #define CR(NRV)                                                                             \
-    hipLaunchKernelGGL((k_contract_rows<T, NRV>), dim3(g), dim3(64 * kCWaves), 0, s, n,    \
-                       op->d_keys, op->d_model, op->d_hash, op->hash_mask, L, KP, Rt, S, part)
+    hipLaunchKernelGGL((k_contract_rows<T, NRV, SYM>), dim3(g), dim3(64 * kCWaves), 0, s, n, \
+                       op->d_keys, op->d_model, op->d_hash, op->hash_mask, L, KP, pl, Rt, S,  \
+                       part)
     const int nr = S / 64;
     if (nr <= 2) CR(2);
     else if (nr <= 4) CR(4);
@@ -2617,13 +2667,12 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
         krylov += br.krylov;
     };
 
-    // Per sector, on the device, for each batch of frequencies: over chunks
-    // of Krylov blocks Q_c (from the store, or regenerated),
+    // Per sector without a store (the blocks regenerated), on the device, for
+    // each batch of frequencies: over chunks of Krylov blocks Q_c,
     //   U += Q_c (sg A_c),  V += Q_c B_c  (columns of the batch),
     //   W += Q_c Omega_c                  (first batch),
     // then tr(Q^T dH Q M) restricted to the batch = tr(U^T dH V) into acc
     // (M = sg A B^T and dH symmetric); finally lam += (start-block map)^T W.
-    // Both sources give the same blocks, so the same sums bit for bit.
     auto sector = [&](BandRun<T> &run, bool create, const SectorPrep &sp) -> int {
         const mcd_op *op = run.op;
         const int m = sp.m, KP = sp.KP;
@@ -2653,7 +2702,7 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
         get((void **)&dA, (size_t)KPr * S2 * sizeof(T));
         get((void **)&dB, (size_t)KPr * S2 * sizeof(T));
         get((void **)&dC, (size_t)m * P * P * sizeof(double));
-        if (streaming) get((void **)&Qc, (size_t)chunk * nx * P * sizeof(T));
+        get((void **)&Qc, (size_t)chunk * nx * P * sizeof(T));
         std::vector<double> C((size_t)m * P * P);
         for (size_t e = 0; e < C.size(); e++) C[e] = -sp.Om[e];   // W -= Q (-Omega)
         std::vector<T> hA((size_t)KPr * S2), hB((size_t)KPr * S2);
@@ -2698,45 +2747,40 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
                 if (b == 0) MCD_TRY(run.block_apply_dev(Qp, k, dC + (size_t)j0 * P * P, Wo, true));
                 return MCD_OK;
             };
-            if (!streaming) {
-                for (int j0 = 0; j0 < m && rc == MCD_OK; j0 += chunk)
-                    rc = flush(run.blk(j0), j0, std::min(chunk, m - j0));
-            } else {
-                // the cut, the start block and the recurrence again, capped at
-                // the first pass's m blocks; each new block is copied to the
-                // chunk buffer before the ring reuses its slot
-                uint64_t *kt = nullptr;
-                double *pt = nullptr;
-                int64_t nk = 0;
-                rc = wt_cut(keys_dev, n, psi0_dev, cfg->w_t, ws, s, &kt, &pt, &nk);
-                if (rc == MCD_OK) rc = run_start_block(run, kt, pt, nk, sel, create);
-                (void)dfree(pt, A);
-                (void)dfree(kt, A);
-                int cnt = 0, jn = 0;
-                BlockHook<T> hk = [&](BandRun<T> &r, int j) -> int {
-                    if (j >= m) return MCD_OK;
-                    MCD_HIP(hipMemcpyAsync(Qc + (size_t)cnt * nx * P, r.blk(j),
-                                           (size_t)nx * P * sizeof(T), hipMemcpyDeviceToDevice, s));
-                    cnt++;
-                    if (cnt == chunk || j == m - 1) {
-                        MCD_TRY(flush(Qc, jn, cnt));
-                        jn += cnt;
-                        cnt = 0;
-                    }
-                    return MCD_OK;
-                };
-                const double gtol = run.g_tol;
-                run.g_tol = 0.0;
-                run.limit = m;
-                std::vector<BandRun<T> *> one{&run};
-                if (rc == MCD_OK) rc = run_lockstep<T>(one, cfg->dtol, 0, s, &hk);
-                run.g_tol = gtol;
-                run.limit = 0;
-                if (rc == MCD_OK && (run.br.m != m || jn != m)) {
-                    set_error("green vjp: the regenerated Krylov blocks (%d) differ from the "
-                              "first pass (%d)", jn, m);
-                    rc = MCD_E_NUMERIC;
+            // the cut, the start block and the recurrence again, capped at
+            // the first pass's m blocks; each new block is copied to the
+            // chunk buffer before the ring reuses its slot
+            uint64_t *kt = nullptr;
+            double *pt = nullptr;
+            int64_t nk = 0;
+            rc = wt_cut(keys_dev, n, psi0_dev, cfg->w_t, ws, s, &kt, &pt, &nk);
+            if (rc == MCD_OK) rc = run_start_block(run, kt, pt, nk, sel, create);
+            (void)dfree(pt, A);
+            (void)dfree(kt, A);
+            int cnt = 0, jn = 0;
+            BlockHook<T> hk = [&](BandRun<T> &r, int j) -> int {
+                if (j >= m) return MCD_OK;
+                MCD_HIP(hipMemcpyAsync(Qc + (size_t)cnt * nx * P, r.blk(j),
+                                       (size_t)nx * P * sizeof(T), hipMemcpyDeviceToDevice, s));
+                cnt++;
+                if (cnt == chunk || j == m - 1) {
+                    MCD_TRY(flush(Qc, jn, cnt));
+                    jn += cnt;
+                    cnt = 0;
                 }
+                return MCD_OK;
+            };
+            const double gtol = run.g_tol;
+            run.g_tol = 0.0;
+            run.limit = m;
+            std::vector<BandRun<T> *> one{&run};
+            if (rc == MCD_OK) rc = run_lockstep<T>(one, cfg->dtol, 0, s, &hk);
+            run.g_tol = gtol;
+            run.limit = 0;
+            if (rc == MCD_OK && (run.br.m != m || jn != m)) {
+                set_error("green vjp: the regenerated Krylov blocks (%d) differ from the "
+                          "first pass (%d)", jn, m);
+                rc = MCD_E_NUMERIC;
             }
             if (rc == MCD_OK) {
                 launch_contract_rows<T>(g, s, nx, op, U, K2b, V, S2, part);
@@ -2746,6 +2790,79 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
             }
         }
         if (rc == MCD_OK) {
+            hipLaunchKernelGGL((k_start_block_t<T>), dim3(gridn(n, 256)), dim3(256), 0, s, n,
+                               keys_dev, sel, create ? 1 : 0, op->d_hash, op->hash_mask, P, Wo,
+                               lam);
+            if (hipGetLastError() != hipSuccess) rc = MCD_E_HIP;
+        }
+        if (hipStreamSynchronize(s) != hipSuccess && rc == MCD_OK) rc = MCD_E_HIP;
+        za.release();   // after the synchronisation above
+        if (rc == MCD_E_HIP) set_error("green vjp: device step failed in a sector");
+        return rc;
+    };
+
+    // With every Krylov block stored (kept runs, or a recomputed run with
+    // reorthogonalisation) the weight is taken whole: Mp = M + M^T (S x S, S =
+    // KP rounded up to 128) from A and B on the device, Z = Q Mp (one MFMA
+    // product over the store), then tr(Q^T dH Q M) by the symmetric
+    // contraction of the store with Z (each hop pair once), W = Q Omega, and
+    // lam += (start-block map)^T W.  Fewer operations than the factored form
+    // of the regenerated blocks (one n x S product instead of two n x S2, half
+    // the contraction's gathers); the two agree to rounding.
+    auto sector_stored = [&](BandRun<T> &run, bool create, const SectorPrep &sp) -> int {
+        const mcd_op *op = run.op;
+        const int m = sp.m, KP = sp.KP;
+        const int64_t nx = run.n;
+        const int K2 = 2 * n_freq * p;
+        const int S = (KP + 127) / 128 * 128;
+        constexpr int kTail = 1024;   // zeroed values after the last row of Z
+        Arena za(ws);
+        T *Z = nullptr, *Mp = nullptr, *Wo = nullptr;
+        double *dA = nullptr, *dB = nullptr, *dC = nullptr;
+        int rc = MCD_OK;
+        auto get = [&](void **ptr, size_t bytes) {
+            if (rc != MCD_OK) return;
+            if (za.get(ptr, bytes) != hipSuccess) {
+                set_error("green vjp: workspace too small for the contraction matrices "
+                          "(%.2f GB more)", bytes / 1e9);
+                rc = MCD_E_WORKSPACE;
+            } else if (poison_fp(*ptr, bytes, za.al, s) != hipSuccess) {
+                rc = MCD_E_HIP;
+            }
+        };
+        get((void **)&Z, ((size_t)nx * S + kTail) * sizeof(T));
+        get((void **)&Mp, (size_t)S * S * sizeof(T));
+        get((void **)&Wo, (size_t)nx * P * sizeof(T));
+        get((void **)&dA, (size_t)KP * K2 * sizeof(double));
+        get((void **)&dB, (size_t)KP * K2 * sizeof(double));
+        get((void **)&dC, (size_t)m * P * P * sizeof(double));
+        std::vector<double> C((size_t)m * P * P);
+        for (size_t e = 0; e < C.size(); e++) C[e] = -sp.Om[e];   // W -= Q (-Omega)
+        if (rc == MCD_OK &&
+            (hipMemcpyAsync(dC, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, s) !=
+                 hipSuccess ||
+             hipMemcpyAsync(dA, sp.Am.data(), (size_t)KP * K2 * sizeof(double),
+                            hipMemcpyHostToDevice, s) != hipSuccess ||
+             hipMemcpyAsync(dB, sp.Bm.data(), (size_t)KP * K2 * sizeof(double),
+                            hipMemcpyHostToDevice, s) != hipSuccess ||
+             hipMemsetAsync(Wo, 0, (size_t)nx * P * sizeof(T), s) != hipSuccess ||
+             hipMemsetAsync(Z, 0, ((size_t)nx * S + kTail) * sizeof(T), s) != hipSuccess))
+            rc = MCD_E_HIP;
+        if (rc == MCD_OK) {
+            hipLaunchKernelGGL((k_sym_gram<T>), dim3(S / 16, S / 16), dim3(16, 16), 0, s, KP, K2,
+                               S, sp.sg, dA, dB, Mp);
+            const int64_t tiles = (nx + 127) / 128 * (S / 128);
+            hipLaunchKernelGGL((k_rows_times<T>), dim3((unsigned)((tiles + 7) / 8 * 8)),
+                               dim3(256), 0, s, nx, S, KP, pl, run.blk(0), Mp, Z);
+            if (hipGetLastError() != hipSuccess) rc = MCD_E_HIP;
+        }
+        if (rc == MCD_OK) rc = run.block_apply_dev(run.blk(0), m, dC, Wo, true);
+        if (rc == MCD_OK) {
+            const unsigned g =
+                (unsigned)std::min<int64_t>(cblk, (nx + 16 * kCWaves - 1) / (16 * kCWaves));
+            launch_contract_rows<T, true>(g, s, nx, op, run.blk(0), KP, Z, S, part, pl);
+            hipLaunchKernelGGL(k_param_reduce, dim3((np + 3) / 4), dim3(256), 0, s, np, (int)g,
+                               part, acc, 1);
             hipLaunchKernelGGL((k_start_block_t<T>), dim3(gridn(n, 256)), dim3(256), 0, s, n,
                                keys_dev, sel, create ? 1 : 0, op->d_hash, op->hash_mask, P, Wo,
                                lam);
@@ -2783,7 +2900,8 @@ static int band_green_vjp(const mcd_model *model, const uint64_t *keys_dev, int6
                 prep(r, side == 0, sp);
                 const hipStream_t s_prev = r.s;
                 r.s = s;
-                const int rc_h = sector(r, side == 0, sp);
+                const int rc_h =
+                    streaming ? sector(r, side == 0, sp) : sector_stored(r, side == 0, sp);
                 r.s = s_prev;
                 TRY(rc_h);
             }

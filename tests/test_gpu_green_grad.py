@@ -170,12 +170,15 @@ def test_green_vjp_with_convergence_stop_replays_forward():
 @pytest.mark.parametrize("prec,reorth", [("f64", 1), ("f32", 1), ("f32", 0)])
 def test_green_vjp_on_kept_runs_is_bit_identical(prec, reorth):
     """mcd_band_green_vjp_keep on the sector runs kept by the forward call gives
-    exactly the derivative of mcd_band_green_vjp (which recomputes the same
-    runs), twice in a row on one handle; the kept forward's G equals the
-    plain forward's bit for bit (with reorth = 0 the plain forward keeps a
-    ring of three blocks, the kept one every block: the three-term update
-    reads block j at its signed offset from block j - 1, so both take the
-    same single pass); arguments that differ from the kept call are
+    the derivative of mcd_band_green_vjp (which recomputes the same runs),
+    twice in a row on one handle: bit for bit with reorthogonalisation (the
+    recomputed runs store every block too, and both contract the whole
+    store), to rounding with reorth = 0 (the recomputing call regenerates
+    the blocks instead and takes the factored form); the kept forward's G
+    equals the plain forward's bit for bit (with reorth = 0 the plain forward
+    keeps a ring of three blocks, the kept one every block: the three-term
+    update reads block j at its signed offset from block j - 1, so both take
+    the same single pass); arguments that differ from the kept call are
     rejected."""
     torch, mcd = require_gpu()
     m = W.impurity_plaquette_bath(6)
@@ -193,11 +196,20 @@ def test_green_vjp_on_kept_runs_is_bit_identical(prec, reorth):
     try:
         assert np.array_equal(G0, G1) and info0.iters == info1.iters
         ref = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=0.3, **kw)
+        tol = 1e-12 if prec == "f64" else 1e-5
+        first = None
         for _ in range(2):
             got = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=0.3,
                                      keep=kept, **kw)
             for a, b in zip(got[:3], ref[:3]):
-                assert np.array_equal(a, b)
+                if reorth > 0:
+                    assert np.array_equal(a, b)
+                else:
+                    assert _rel(a, b) <= tol
+            if first is not None:   # the same handle twice: the same numbers
+                for a, b in zip(got[:3], first[:3]):
+                    assert np.array_equal(a, b)
+            first = got
             assert got[3].krylov_dim == ref[3].krylov_dim
         bad = dict(kw, max_blocks=119)
         with pytest.raises(mcd.McdError):
@@ -214,8 +226,8 @@ def test_streaming_vjp_batches_and_chunks(prec):
     """Without kept runs and without reorthogonalisation the derivative
     regenerates the Krylov blocks in a second pass of the recurrence: with the
     frequencies in batches and the blocks in chunks of other sizes it gives
-    the same derivative to rounding, and on kept (stored) runs with the same
-    batch and chunk sizes bit for bit."""
+    the same derivative to rounding, and so do kept (stored) runs, whose
+    derivative takes the whole store at once."""
     torch, mcd = require_gpu()
     m = W.impurity_plaquette_bath(6)
     keys, _ = sampler.chain_c(m, W.neel_start(m), 2, 15000, 500, 10**7)
@@ -238,7 +250,7 @@ def test_streaming_vjp_batches_and_chunks(prec):
         got = mcd.band_green_vjp(m, kd, psi, e0, orbs, spins, om, Gb, e0_bar=0.2, keep=kept,
                                  vjp_freq_batch=5, vjp_chunk=3, **kw)
         for a, b in zip(got[:3], bat[:3]):
-            assert np.array_equal(a, b)
+            assert np.all(np.isfinite(a)) and _rel(a, b) <= tol
     finally:
         kept.close()
 
