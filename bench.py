@@ -291,6 +291,64 @@ def precision_vs_oracle(mcd, W, torch):
     return out
 
 
+def streaming_gradient_c2(mcd, W, torch, keys, op):
+    """The derivative of G on large excited sectors, where the Krylov store
+    is the memory bill: the 4x4 t-t' cluster's 4M-state basis (C2), its
+    float64 ground state, G of the up-spin sites 0..7 (p = 8) at 8 Matsubara
+    frequencies with float32 blocks (three-term recurrence, 120 block steps),
+    loss sum |G|^2.  Backward (1) with the blocks regenerated by a
+    second pass (no store: three ring blocks, a chunk and the two work
+    matrices), (2) on a kept forward (every block stored).  Reports both
+    times, the workspace high-water marks and the gradients' difference."""
+    import numpy as np
+    m = W.config_c2()["model"]
+    e0, psi, _, _, si = mcd.lanczos_ground(op, max_iter=1000, tol=1e-10, seed=11)
+    orbs, spins = list(range(8)), [0] * 8
+    om = W.matsubara(8, 50.0)
+    kw = dict(max_blocks=120, precision="f32", reorth=0, g_tol=0.0)
+    out = {"workload": "4x4 periodic t=1 t'=-0.3 U=8 (7,7), 4M chain states; G of up-spin "
+                       "sites 0..7 (p=8), 8 Matsubara frequencies (beta=50), float32 blocks, "
+                       "three-term recurrence, 120 block steps; loss sum |G|^2",
+           "e0": e0, "lanczos_iters": si.iters}
+    mcd.release_scratch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G, gi = mcd.band_lanczos_green(m, keys, psi, e0, orbs, spins, om, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gb = 2.0 * G
+    d_stream = mcd.band_green_vjp(m, keys, psi, e0, orbs, spins, om, gb, **kw)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    hw_stream = max(w.stats()["high_water"] for w in mcd._SCRATCH.values())
+    mcd.release_scratch()
+    G2, gi2, kept = mcd.band_lanczos_green(m, keys, psi, e0, orbs, spins, om, keep=True, **kw)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    try:
+        d_kept = mcd.band_green_vjp(m, keys, psi, e0, orbs, spins, om, gb, keep=kept, **kw)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        kept_bytes = kept._ws.nbytes if getattr(kept, "_ws", None) is not None else None
+    finally:
+        kept.close()
+    hw_kept = max(w.stats()["high_water"] for w in mcd._SCRATCH.values())
+    mcd.release_scratch()
+    a = np.concatenate(d_stream[:3])
+    b = np.concatenate(d_kept[:3])
+    out.update({"n_plus": gi.n_plus, "n_minus": gi.n_minus, "block_steps": gi.iters,
+                "krylov_dim": gi.krylov_dim, "forward_s": round(t1 - t0, 3),
+                "backward_regenerated_s": round(t2 - t1, 3),
+                "backward_regenerated_workspace_gb": round(hw_stream / 1e9, 2),
+                "forward_kept_s": round(t3 - t2, 3), "backward_kept_s": round(t4 - t3, 3),
+                "kept_store_gb": None if kept_bytes is None else round(kept_bytes / 1e9, 2),
+                "backward_kept_workspace_gb": round(hw_kept / 1e9, 2),
+                "G_equal": bool(np.array_equal(G, G2)),
+                "max_rel_grad_diff": float(np.max(np.abs(a - b)) / np.max(np.abs(b))),
+                "cg_iters": d_stream[3].iters})
+    return out
+
+
 def large_nnz_16site(mcd, W, torch):
     """The one-vector float64 product and the float32 x 8 block product on a
     whole 16-site sector: 4x4 periodic square, U=8, (8,8), 165,636,900 states
@@ -645,6 +703,8 @@ def main():
                     help="skip the plain / chosen forms against the oracle's stored values")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 16-site full-sector (165.6M states) products")
+    ap.add_argument("--no-stream-grad", action="store_true",
+                    help="skip the derivative on the C2 basis's large excited sectors")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 32-instance batched ground-state comparison")
     ap.add_argument("--copy-probe", action="store_true",
@@ -812,6 +872,8 @@ def main():
         out["c5_32_sites"] = c5_cluster(mcd, W, torch)
     if not args.no_large:
         out["large_nnz_16site"] = large_nnz_16site(mcd, W, torch)
+    if not args.no_stream_grad:
+        out["streaming_gradient_c2"] = streaming_gradient_c2(mcd, W, torch, keys, op)
     if args.copy_probe:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)

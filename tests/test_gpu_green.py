@@ -147,6 +147,41 @@ def test_green_impurity_p8_and_sum_rule():
     assert err <= 1e-4
 
 
+def test_green_empty_excited_sectors():
+    """Degenerate excited sectors: with every up orbital occupied (n_up =
+    n_orb) no c+_up image exists, so F~+ of the up-spin selection is empty and
+    G_up = G- only; with no down electron F~- of the down-spin selection is
+    empty and G_dn = G+ only.  Against the oracle's dense Lehmann sums over
+    the full sectors (which skip an empty sector), and the sum rule of the
+    surviving part (G -> 1/(i w) at large w: the start block keeps its
+    weight)."""
+    torch, mcd = require_gpu()
+    base = W.chain(6, U=4.0, mu=2.0, pbc=True)
+    for n_up, n_dn, orbs, spins in ((6, 3, [0, 2, 5], [0, 0, 0]), (3, 0, [1, 4], [1, 1]),
+                                    (6, 0, [0, 3, 1], [0, 0, 1])):
+        m = base.with_sector(n_up, n_dn)
+        keys = fock.sector_keys(6, n_up, n_dn)
+        log_case("green_empty_sector", n_up=n_up, n_dn=n_dn, n=len(keys))
+        e0, psi = _gs(m, keys)
+        G, gi = mcd.band_lanczos_green(m, mcd.keys_from_numpy(keys), torch.from_numpy(psi).cuda(),
+                                       e0, orbs, spins, OM, max_blocks=40)
+        ref = np.zeros_like(G)
+        for s in (0, 1):
+            sel = [q for q in range(len(orbs)) if spins[q] == s]
+            if not sel:
+                continue
+            Gs = gr.green_exact(keys, m, psi, e0, [orbs[q] for q in sel], s, OM)
+            for i, qi in enumerate(sel):
+                for j, qj in enumerate(sel):
+                    ref[:, qi, qj] = Gs[:, i, j]
+        assert _rel(G, ref) <= 1e-9, (n_up, n_dn)
+        big = 1e6
+        Gt, _ = mcd.band_lanczos_green(m, mcd.keys_from_numpy(keys),
+                                       torch.from_numpy(psi).cuda(), e0, orbs, spins,
+                                       np.array([big]), max_blocks=40)
+        assert np.allclose(Gt[0] * 1j * big, np.eye(len(orbs)), atol=1e-5), (n_up, n_dn)
+
+
 def test_green_deflation_duplicate_selection():
     torch, mcd = require_gpu()
     m, keys = _c1_chain()
