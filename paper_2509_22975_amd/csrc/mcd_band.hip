@@ -803,7 +803,8 @@ struct BandRun {
             c = std::min<int64_t>(gridn(n, 256), 2048);
         }
         c = std::max<int64_t>(1, c);
-        chunk_rows = (n + c - 1) / c;
+        // an empty sector (n = 0) has one empty chunk size and no chunks
+        chunk_rows = std::max<int64_t>(1, (n + c - 1) / c);
         nch = (int)((n + chunk_rows - 1) / chunk_rows);
     }
     // Gram partial capacity for up to mb + 1 blocks at once
