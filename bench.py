@@ -682,6 +682,30 @@ def c5_cluster(mcd, W, torch):
     return out
 
 
+def copy_reference(torch, dev, product_gbs):
+    """A plain 1 GiB device-to-device copy (torch's copy kernel) timed with
+    HIP events: the rate a streaming kernel reaches on this GPU, reported as
+    context beside the roofline (whose peak stays the published 8 TB/s), and
+    the product kernel's algorithmic rate as a fraction of it."""
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        b.copy_(a)
+    e_a, e_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e_a.record(s)
+    for _ in range(20):
+        b.copy_(a)
+    e_b.record(s)
+    e_b.synchronize()
+    ms = e_a.elapsed_time(e_b) / 20
+    gbs = 2.0 * a.numel() * 8 / ms / 1e6
+    del a, b
+    return {"bytes_read_and_written": 2 * (1 << 30), "ms": round(ms, 4), "GBs": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "product_frac_of_copy": round(product_gbs / gbs, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -852,6 +876,7 @@ def main():
         "cpu_baseline": None,
         "block_spmm": spmm,
         "roofline_block_spmm": roof_block,
+        "copy_reference": copy_reference(torch, dev, achieved),
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(m, mcd.keys_to_numpy(keys), x.cpu().numpy(),
