@@ -27,12 +27,16 @@
 #include <hipcub/hipcub.hpp>
 #include <math.h>
 
+#include <cmath>
+
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <complex>
+#include <condition_variable>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -460,52 +464,166 @@ static void jacobi_eig(int n, std::vector<double> A, std::vector<double> &w,
     for (int i = 0; i < n; i++) w[i] = A[i * n + i];
 }
 
-// fn(i) for i in [0, n) on up to 16 host threads (static round-robin); the
-// callers give every index its own output, so results do not depend on the
-// thread count.
+// Host worker pool for the small dense host work (block continued fractions,
+// per-frequency solves): up to 15 workers beside the calling thread, created
+// on first use and kept for the life of the process (the pool object is
+// never destroyed, so no worker is joined at exit; idle workers wait on a
+// condition variable).  One loop at a time: a call that finds the pool busy
+// (another host thread, or a call from inside a loop) runs in the calling
+// thread alone.
+class HostPool {
+  public:
+    static HostPool &get() {
+        static HostPool *p = new HostPool();
+        return *p;
+    }
+    int workers() const { return nworkers_; }
+    // fn(i) for every i in [0, n), the items handed out one at a time;
+    // false (nothing run) when the pool is busy
+    bool run(int n, const std::function<void(int)> &fn) {
+        std::unique_lock<std::mutex> busy(run_mu_, std::try_to_lock);
+        if (!busy.owns_lock()) return false;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            job_ = &fn;
+            total_ = n;
+            next_.store(0);
+            pending_ = nworkers_;
+            ++gen_;
+        }
+        cv_.notify_all();
+        work();
+        std::unique_lock<std::mutex> lk(mu_);
+        done_cv_.wait(lk, [&] { return pending_ == 0; });   // no worker still reads fn
+        job_ = nullptr;
+        return true;
+    }
+
+  private:
+    HostPool() {
+        const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+        nworkers_ = std::max(0, std::min(hw, 16) - 1);
+        for (int t = 0; t < nworkers_; t++) std::thread([this] { loop(); }).detach();
+    }
+    void work() {
+        for (int i = next_.fetch_add(1); i < total_; i = next_.fetch_add(1)) (*job_)(i);
+    }
+    void loop() {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return gen_ != seen; });
+                seen = gen_;
+            }
+            work();
+            std::lock_guard<std::mutex> lk(mu_);
+            if (--pending_ == 0) done_cv_.notify_one();
+        }
+    }
+    std::mutex run_mu_, mu_;
+    std::condition_variable cv_, done_cv_;
+    const std::function<void(int)> *job_ = nullptr;
+    int total_ = 0, nworkers_ = 0, pending_ = 0;
+    std::atomic<int> next_{0};
+    uint64_t gen_ = 0;
+};
+
+// fn(i) for i in [0, n) on the host pool (or in the calling thread); the
+// callers give every index its own output, so results do not depend on
+// which thread ran which index.
 template <typename F>
 static void parallel_for(int n, F &&fn) {
-    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
-    const int nt = std::max(1, std::min({n, hw, 16}));
-    if (nt <= 1) {
-        for (int i = 0; i < n; i++) fn(i);
-        return;
+    if (n <= 0) return;
+    if (n > 1 && HostPool::get().workers() > 0) {
+        const std::function<void(int)> f = [&](int i) { fn(i); };
+        if (HostPool::get().run(n, f)) return;
     }
-    std::vector<std::thread> th;
-    for (int t = 1; t < nt; t++)
-        th.emplace_back([&, t]() {
-            for (int i = t; i < n; i += nt) fn(i);
-        });
-    for (int i = 0; i < n; i += nt) fn(i);
-    for (auto &x : th) x.join();
+    for (int i = 0; i < n; i++) fn(i);
 }
 
-// Solve S X = B (S n x n, B n x k, complex, row-major) by Gaussian
-// elimination with partial pivoting; S and B are overwritten, X returned in B.
-static void csolve(int n, int k, std::vector<cplx> &S, std::vector<cplx> &B) {
+// Solve S X = B for complex S (n x n) and B (n x k), row-major, real and
+// imaginary parts in separate arrays, by Gaussian elimination with partial
+// pivoting (pivot: largest |S_rc|^2 in the column); S and B are overwritten,
+// X returned in B.  Complex products are written out and each pivot is
+// inverted once (scaled by its larger component), so no library complex
+// division or multiplication with its special-value handling is called.
+static void csolve_split(int n, int k, double *Sr, double *Si, double *Br, double *Bi) {
+    auto inv = [](double a, double b, double &ir, double &ii) {
+        const double sc = std::max(std::fabs(a), std::fabs(b));
+        const double as = a / sc, bs = b / sc;
+        const double den = sc * (as * as + bs * bs);
+        ir = as / den;
+        ii = -bs / den;
+    };
     for (int c = 0; c < n; c++) {
         int piv = c;
-        for (int r = c + 1; r < n; r++)
-            if (std::abs(S[r * n + c]) > std::abs(S[piv * n + c])) piv = r;
-        if (piv != c) {
-            for (int j = 0; j < n; j++) std::swap(S[c * n + j], S[piv * n + j]);
-            for (int j = 0; j < k; j++) std::swap(B[c * k + j], B[piv * k + j]);
-        }
-        const cplx d = S[c * n + c];
+        double best = Sr[c * n + c] * Sr[c * n + c] + Si[c * n + c] * Si[c * n + c];
         for (int r = c + 1; r < n; r++) {
-            const cplx f = S[r * n + c] / d;
-            if (f == cplx(0.0)) continue;
-            for (int j = c; j < n; j++) S[r * n + j] -= f * S[c * n + j];
-            for (int j = 0; j < k; j++) B[r * k + j] -= f * B[c * k + j];
+            const double v = Sr[r * n + c] * Sr[r * n + c] + Si[r * n + c] * Si[r * n + c];
+            if (v > best) {
+                best = v;
+                piv = r;
+            }
+        }
+        if (piv != c) {
+            for (int j = c; j < n; j++) {
+                std::swap(Sr[c * n + j], Sr[piv * n + j]);
+                std::swap(Si[c * n + j], Si[piv * n + j]);
+            }
+            for (int j = 0; j < k; j++) {
+                std::swap(Br[c * k + j], Br[piv * k + j]);
+                std::swap(Bi[c * k + j], Bi[piv * k + j]);
+            }
+        }
+        double dr, di;
+        inv(Sr[c * n + c], Si[c * n + c], dr, di);
+        for (int r = c + 1; r < n; r++) {
+            const double ar = Sr[r * n + c], ai = Si[r * n + c];
+            const double fr = ar * dr - ai * di, fi = ar * di + ai * dr;
+            if (fr == 0.0 && fi == 0.0) continue;
+            for (int j = c + 1; j < n; j++) {
+                const double ur = Sr[c * n + j], ui = Si[c * n + j];
+                Sr[r * n + j] -= fr * ur - fi * ui;
+                Si[r * n + j] -= fr * ui + fi * ur;
+            }
+            for (int j = 0; j < k; j++) {
+                const double ur = Br[c * k + j], ui = Bi[c * k + j];
+                Br[r * k + j] -= fr * ur - fi * ui;
+                Bi[r * k + j] -= fr * ui + fi * ur;
+            }
         }
     }
     for (int c = n - 1; c >= 0; c--) {
+        double dr, di;
+        inv(Sr[c * n + c], Si[c * n + c], dr, di);
         for (int j = 0; j < k; j++) {
-            cplx s = B[c * k + j];
-            for (int q = c + 1; q < n; q++) s -= S[c * n + q] * B[q * k + j];
-            B[c * k + j] = s / S[c * n + c];
+            double sr = Br[c * k + j], si = Bi[c * k + j];
+            for (int q = c + 1; q < n; q++) {
+                const double ar = Sr[c * n + q], ai = Si[c * n + q];
+                const double xr = Br[q * k + j], xi = Bi[q * k + j];
+                sr -= ar * xr - ai * xi;
+                si -= ar * xi + ai * xr;
+            }
+            Br[c * k + j] = sr * dr - si * di;
+            Bi[c * k + j] = sr * di + si * dr;
         }
     }
+}
+
+// The same solve on interleaved complex vectors.
+static void csolve(int n, int k, std::vector<cplx> &S, std::vector<cplx> &B) {
+    std::vector<double> Sr(n * n), Si(n * n), Br(n * k), Bi(n * k);
+    for (int e = 0; e < n * n; e++) {
+        Sr[e] = S[e].real();
+        Si[e] = S[e].imag();
+    }
+    for (int e = 0; e < n * k; e++) {
+        Br[e] = B[e].real();
+        Bi[e] = B[e].imag();
+    }
+    csolve_split(n, k, Sr.data(), Si.data(), Br.data(), Bi.data());
+    for (int e = 0; e < n * k; e++) B[e] = cplx(Br[e], Bi[e]);
 }
 
 struct BandResult {
@@ -518,37 +636,62 @@ struct BandResult {
 };
 
 // G_sub(z) = R0^T [(z - T)^-1]_00 R0 for one z; out p x p (first p columns).
+// The block continued fraction from the last block up: S_{m-1} = z - A_{m-1},
+// S_j = z - A_j - B_{j+1}^T S_{j+1}^-1 B_{j+1}; then R0^T S_0^-1 R0.  P <= 16;
+// no heap allocation (it runs at every convergence check).
 static void block_cf(const BandResult &br, cplx z, int p, cplx *out) {
-    const int P = br.P;
-    std::vector<cplx> S(P * P), X;
+    constexpr int kMax = 16;
+    const int P = br.P, m = br.m;
+    if (m <= 0 || P <= 0 || P > kMax) {
+        for (int e = 0; e < p * p; e++) out[e] = 0.0;
+        return;
+    }
+    double Sr[kMax * kMax], Si[kMax * kMax], Xr[kMax * kMax], Xi[kMax * kMax];
+    const double zr = z.real(), zi = z.imag();
     auto zA = [&](int j) {
+        const double *A = br.A[j].data();
         for (int a = 0; a < P; a++)
-            for (int b = 0; b < P; b++)
-                S[a * P + b] = (a == b ? z : cplx(0.0)) - br.A[j][a * P + b];
+            for (int b = 0; b < P; b++) {
+                Sr[a * P + b] = (a == b ? zr : 0.0) - A[a * P + b];
+                Si[a * P + b] = a == b ? zi : 0.0;
+            }
     };
-    zA(br.m - 1);
-    for (int j = br.m - 2; j >= 0; j--) {
+    zA(m - 1);
+    for (int j = m - 2; j >= 0; j--) {
         // X = S^-1 B_{j+1};  S_j = z - A_j - B_{j+1}^T X
-        X.assign(P * P, cplx(0.0));
-        for (int e = 0; e < P * P; e++) X[e] = br.B[j + 1][e];
-        std::vector<cplx> Sc = S;
-        csolve(P, P, Sc, X);
+        const double *Bj = br.B[j + 1].data();
+        for (int e = 0; e < P * P; e++) {
+            Xr[e] = Bj[e];
+            Xi[e] = 0.0;
+        }
+        csolve_split(P, P, Sr, Si, Xr, Xi);
         zA(j);
         for (int a = 0; a < P; a++)
             for (int b = 0; b < P; b++) {
-                cplx s = 0.0;
-                for (int q = 0; q < P; q++) s += br.B[j + 1][q * P + a] * X[q * P + b];
-                S[a * P + b] -= s;
+                double sr = 0.0, si = 0.0;
+                for (int q = 0; q < P; q++) {
+                    const double bq = Bj[q * P + a];
+                    sr += bq * Xr[q * P + b];
+                    si += bq * Xi[q * P + b];
+                }
+                Sr[a * P + b] -= sr;
+                Si[a * P + b] -= si;
             }
     }
-    std::vector<cplx> Y(P * P);
-    for (int e = 0; e < P * P; e++) Y[e] = br.R0[e];
-    csolve(P, P, S, Y);
+    const double *R0 = br.R0.data();
+    for (int e = 0; e < P * P; e++) {
+        Xr[e] = R0[e];
+        Xi[e] = 0.0;
+    }
+    csolve_split(P, P, Sr, Si, Xr, Xi);
     for (int a = 0; a < p; a++)
         for (int b = 0; b < p; b++) {
-            cplx s = 0.0;
-            for (int q = 0; q < P; q++) s += br.R0[q * P + a] * Y[q * P + b];
-            out[a * p + b] = s;
+            double sr = 0.0, si = 0.0;
+            for (int q = 0; q < P; q++) {
+                sr += R0[q * P + a] * Xr[q * P + b];
+                si += R0[q * P + a] * Xi[q * P + b];
+            }
+            out[a * p + b] = cplx(sr, si);
         }
 }
 
@@ -813,12 +956,12 @@ struct BandRun {
         return pad * (int64_t)(mb + 1) * PP();
     }
 
-    bool g_converged(const BandResult &b) {
-        if (g_tol <= 0.0 || zcheck.empty() || b.m == 0) return false;
-        std::vector<cplx> g((size_t)zcheck.size() * p_sel * p_sel);
-        parallel_for((int)zcheck.size(), [&](int f) {
-            block_cf(b, zcheck[f], p_sel, g.data() + (size_t)f * p_sel * p_sel);
-        });
+    // G at the check points is wanted for this T
+    bool g_wanted(const BandResult &b) const { return g_tol > 0.0 && !zcheck.empty() && b.m > 0; }
+    // G at the check points (zcheck.size() blocks of p_sel x p_sel, from
+    // block_cf) against the previous check's: settled when the largest change
+    // is within g_tol of the largest |G|; g becomes the previous values
+    bool g_settled(std::vector<cplx> &&g) {
         bool conv = false;
         if (gprev.size() == g.size()) {
             double dmax = 0.0, gmax = 0.0;
@@ -828,8 +971,16 @@ struct BandRun {
             }
             conv = dmax <= g_tol * gmax;
         }
-        gprev = g;
+        gprev = std::move(g);
         return conv;
+    }
+    bool g_converged(const BandResult &b) {
+        if (!g_wanted(b)) return false;
+        std::vector<cplx> g((size_t)zcheck.size() * p_sel * p_sel);
+        parallel_for((int)zcheck.size(), [&](int f) {
+            block_cf(b, zcheck[f], p_sel, g.data() + (size_t)f * p_sel * p_sel);
+        });
+        return g_settled(std::move(g));
     }
 
     int gram(const T *Q0, int nm, const T *X, std::vector<double> &out) {
@@ -1464,16 +1615,133 @@ static int run_lockstep(std::vector<BandRun<T> *> &runs, double dtol_abs, int re
     if (on_block)
         for (auto *r : runs)
             if (r->active) LTRY((*on_block)(*r, 0));
+    // The checks every 8 block steps read each run's ranks (and, with g_tol,
+    // T) back to the host.  Without a per-block hook or a replay limit the
+    // read-back goes to a pinned host buffer, asynchronously, and the host
+    // takes the check's decision only after the next block step and QR are
+    // enqueued, so the GPU works on them meanwhile; a run that stops at the
+    // check drops the extra step (its m goes back to the check's), so every
+    // run ends where a synchronous check would have ended it, with the same T.
+    bool spec = on_block == nullptr && !act.empty();
+    for (auto *r : runs)
+        if (r->limit > 0) spec = false;   // a replay's stop is checked synchronously
+    char *pin = nullptr;
+    hipEvent_t pev = nullptr;
+    std::vector<size_t> off_rank(runs.size(), 0), off_T(runs.size(), 0);
+    if (spec) {
+        size_t bytes = 0;
+        for (size_t i = 0; i < runs.size(); i++) {
+            if (runs[i]->n == 0) continue;
+            off_rank[i] = bytes;
+            bytes += ((size_t)(runs[i]->mb + 2) * sizeof(int) + 7) / 8 * 8;
+            off_T[i] = bytes;
+            bytes += runs[i]->nT() * sizeof(double);
+        }
+        if (hipHostMalloc((void **)&pin, std::max<size_t>(bytes, 8), 0) != hipSuccess) {
+            (void)hipGetLastError();
+            pin = nullptr;
+            spec = false;
+        } else if (hipEventCreateWithFlags(&pev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            pev = nullptr;
+            spec = false;
+        }
+    }
+    auto release_pin = [&]() {
+        if (pev || pin) (void)hipStreamSynchronize(s);
+        if (pev) (void)hipEventDestroy(pev);
+        if (pin) (void)hipHostFree(pin);
+        pev = nullptr;
+        pin = nullptr;
+    };
+#undef LTRY
+#define LTRY(expr)                     \
+    do {                               \
+        int rc_ = (expr);              \
+        if (rc_ < 0) {                 \
+            release_pin();             \
+            return done(rc_);          \
+        }                              \
+    } while (0)
+    auto index_of = [&](const BandRun<T> *r) {
+        return (size_t)(std::find(runs.begin(), runs.end(), r) - runs.begin());
+    };
+    // The check at block c of the runs `lst` (host copies of their ranks
+    // [0, c] and, with g_tol, of T): a run whose Krylov space is exhausted
+    // ends at its first zero rank; a run whose G at the check points has
+    // settled since its previous check ends at c.
+    auto check = [&](int c, const std::vector<BandRun<T> *> &lst) -> int {
+        for (auto *r : lst)
+            for (int z = 1; z <= c; z++)
+                if (r->rank[z] == 0) {   // exhausted: blocks from z on are zero
+                    r->m = z;
+                    r->active = false;
+                    break;
+                }
+        std::vector<BandRun<T> *> chk;
+        for (auto *r : lst)
+            if (r->active && r->g_tol > 0.0) chk.push_back(r);
+        if (chk.empty()) return MCD_OK;
+        // T of every checked run, then G at every (run, check point) pair in
+        // one parallel loop (one set of host threads per check, each pair
+        // its own output)
+        std::vector<int> rcs(chk.size(), MCD_OK);
+        std::vector<BandResult> tmp(chk.size());
+        for (size_t i = 0; i < chk.size(); i++) rcs[i] = chk[i]->make_T(c, tmp[i]);
+        std::vector<std::vector<cplx>> gz(chk.size());
+        std::vector<std::pair<int, int>> pairs;
+        for (size_t i = 0; i < chk.size(); i++) {
+            if (rcs[i] != MCD_OK || !chk[i]->g_wanted(tmp[i])) continue;
+            const size_t pp = (size_t)chk[i]->p_sel * chk[i]->p_sel;
+            gz[i].resize(chk[i]->zcheck.size() * pp);
+            for (int f = 0; f < (int)chk[i]->zcheck.size(); f++) pairs.emplace_back((int)i, f);
+        }
+        parallel_for((int)pairs.size(), [&](int w) {
+            const int i = pairs[w].first, f = pairs[w].second;
+            const int ps = chk[i]->p_sel;
+            block_cf(tmp[i], chk[i]->zcheck[f], ps, gz[i].data() + (size_t)f * ps * ps);
+        });
+        for (size_t i = 0; i < chk.size(); i++) {
+            MCD_TRY(rcs[i]);
+            if (!gz[i].empty() && chk[i]->g_settled(std::move(gz[i]))) {
+                chk[i]->active = false;
+                chk[i]->m = c;
+            }
+        }
+        return MCD_OK;
+    };
+    int pend_c = 0;                        // block of the check in flight (0: none)
+    std::vector<BandRun<T> *> pend;        // its runs
+    auto finish_pending = [&]() -> int {
+        if (pend_c == 0) return MCD_OK;
+        const int c = pend_c;
+        pend_c = 0;
+        if (hipEventSynchronize(pev) != hipSuccess) return MCD_E_HIP;
+        for (auto *r : pend) {
+            const size_t i = index_of(r);
+            r->rank.resize(r->mb + 2);
+            memcpy(r->rank.data(), pin + off_rank[i], (size_t)(c + 1) * sizeof(int));
+            if (r->g_tol > 0.0) {
+                r->hT.resize(r->nT());
+                memcpy(r->hT.data(), pin + off_T[i], r->nT() * sizeof(double));
+            }
+        }
+        return check(c, pend);
+    };
     size_t built = act.size();
-    for (int j = 0; j < mb; j++) {
+    auto refresh = [&]() -> int {   // the active set, and the fused table for it
         act.clear();
         for (auto *r : runs)
             if (r->active) act.push_back(r);
-        if (act.empty()) break;
-        if (fused && act.size() != built) {   // the set changed
-            LTRY(tab.build(act));
+        if (fused && !act.empty() && act.size() != built) {   // the set changed
+            MCD_TRY(tab.build(act));
             built = act.size();
         }
+        return MCD_OK;
+    };
+    for (int j = 0; j < mb; j++) {
+        LTRY(refresh());
+        if (act.empty()) break;
         if (fused)
             LTRY(tab.step(j, reorth));
         else
@@ -1481,22 +1749,10 @@ static int run_lockstep(std::vector<BandRun<T> *> &runs, double dtol_abs, int re
         for (auto *r : act) r->m = j + 1;
         if (j + 1 == mb) break;
         // a replay stops at its limit (before the QR of the next block)
-        bool capped = false;
-        for (auto *r : act)
-            if (r->limit > 0 && r->m >= r->limit) {
-                r->active = false;
-                capped = true;
-            }
-        if (capped) {
-            act.clear();
-            for (auto *r : runs)
-                if (r->active) act.push_back(r);
-            if (act.empty()) break;
-            if (fused && act.size() != built) {
-                LTRY(tab.build(act));
-                built = act.size();
-            }
-        }
+        for (auto *r : runs)
+            if (r->active && r->limit > 0 && r->m >= r->limit) r->active = false;
+        LTRY(refresh());
+        if (act.empty()) break;
         if (fused)
             LTRY(tab.qr(tab.slot(j + 1), (int64_t)(mb + j + 1) * PP0, j + 1, dtol_abs));
         else
@@ -1504,40 +1760,50 @@ static int run_lockstep(std::vector<BandRun<T> *> &runs, double dtol_abs, int re
                 LTRY(r->qr_dev(r->W, r->blk(j + 1), r->dB(j + 1), j + 1, dtol_abs));
         if (on_block)
             for (auto *r : act) LTRY((*on_block)(*r, j + 1));
+        // the check at block j (if one is in flight), decided while block
+        // step j and the QR of block j + 1 run
+        LTRY(finish_pending());
         if ((j + 1) % 8 == 0) {
-            bool gt = false;
-            for (auto *r : act) {
-                LTRY(r->fetch_ranks(j + 1));
-                if (r->g_tol > 0.0) {
-                    LTRY(r->fetch_T());
-                    gt = true;
-                }
-            }
-            if (hipStreamSynchronize(s) != hipSuccess) return done(MCD_E_HIP);
-            for (auto *r : act)
-                for (int z = 1; z <= j + 1; z++)
-                    if (r->rank[z] == 0) {   // exhausted: blocks from z on are zero
-                        r->m = z;
-                        r->active = false;
-                        break;
+            if (spec) {
+                for (auto *r : act) {
+                    const size_t i = index_of(r);
+                    if (hipMemcpyAsync(pin + off_rank[i], r->d_rank,
+                                       (size_t)(j + 2) * sizeof(int), hipMemcpyDeviceToHost,
+                                       s) != hipSuccess ||
+                        (r->g_tol > 0.0 &&
+                         hipMemcpyAsync(pin + off_T[i], r->dT, r->nT() * sizeof(double),
+                                        hipMemcpyDeviceToHost, s) != hipSuccess)) {
+                        release_pin();
+                        return done(MCD_E_HIP);
                     }
-            if (gt) {
-                std::vector<BandRun<T> *> chk;
-                for (auto *r : act)
-                    if (r->active && r->g_tol > 0.0) chk.push_back(r);
-                std::vector<int> rcs(chk.size(), MCD_OK), stop(chk.size(), 0);
-                parallel_for((int)chk.size(), [&](int i) {
-                    BandResult tmp;
-                    rcs[i] = chk[i]->make_T(chk[i]->m, tmp);
-                    if (rcs[i] == MCD_OK && chk[i]->g_converged(tmp)) stop[i] = 1;
-                });
-                for (size_t i = 0; i < chk.size(); i++) {
-                    LTRY(rcs[i]);
-                    if (stop[i]) chk[i]->active = false;
                 }
+                if (hipEventRecord(pev, s) != hipSuccess) {
+                    release_pin();
+                    return done(MCD_E_HIP);
+                }
+                pend = act;
+                pend_c = j + 1;
+            } else {
+                for (auto *r : act) {
+                    LTRY(r->fetch_ranks(j + 1));
+                    if (r->g_tol > 0.0) LTRY(r->fetch_T());
+                }
+                if (hipStreamSynchronize(s) != hipSuccess) {
+                    release_pin();
+                    return done(MCD_E_HIP);
+                }
+                LTRY(check(j + 1, act));
             }
         }
     }
+    LTRY(finish_pending());
+    release_pin();
+#undef LTRY
+#define LTRY(expr)                     \
+    do {                               \
+        int rc_ = (expr);              \
+        if (rc_ < 0) return done(rc_); \
+    } while (0)
     // final ranks and T of every run
     for (auto *r : runs)
         if (r->n > 0) {
