@@ -40,7 +40,12 @@
  *   buffer to it and call again).
  * Streams.  `stream` is a hipStream_t (NULL = default stream).  Work is
  *   enqueued on it and nowhere else: the library creates no streams and no
- *   host threads that touch the GPU.  Calls that return host values
+ *   host threads that touch the GPU (the band calls' host-side dense work --
+ *   continued fractions, per-frequency solves -- runs on a process-wide pool
+ *   of up to 15 worker threads, created on first use, that never call HIP;
+ *   and a band call pins a small host buffer, the ranks and T of its runs,
+ *   for its asynchronous read-backs, freed before it returns).  Calls that
+ *   return host values
  *   synchronise it first and say so.  All calls that use one workspace must
  *   be ordered on one stream (a released piece is reused by later work on
  *   that stream); calls on one operator from several host threads or streams
