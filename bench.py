@@ -79,19 +79,21 @@ def block_source_hash() -> str:
     csrc = os.path.join(HERE, "paper_2509_22975_amd", "csrc")
     h_src = open(os.path.join(csrc, "mcd_spmm.h")).read()
     op_src = open(os.path.join(csrc, "mcd_op.hip")).read()
-    text = (_function_text(h_src, "void block_csr_v_rows(")
-            + _function_text(h_src, "int block_rows_per_tile(") + _function_text(h_src, "int block_chunk(")
+    text = (_function_text(h_src, "void block_csr_v_tile(") + _function_text(h_src, "int block_chunk(")
+            + _function_text(h_src, "BlockTile block_tile(")
             + _function_text(op_src, "void k_block_csr_v(")
             + _function_text(op_src, "static void launch_block_v("))
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
-def block_launch_threads(n, nvec, elem_bytes):
+def block_launch_threads(n, nvec, elem_bytes, rows_per_block, rows_per_block_l):
     """Grid (threads) of the 16-byte-gather block product for n rows and
-    nvec vectors: row tiles of 256 / lanes rows at <= 2 lanes per row, else
-    64 rows; XCD-major."""
+    nvec vectors: one-pass row tiles of 256 / lanes rows when the operator's
+    stream row block is that long, else of its 8192-word row block (at most
+    256 / lanes); XCD-major."""
     lanes = nvec // (16 // elem_bytes)
-    rpt = 256 // lanes if lanes <= 2 else 64
+    full = 256 // lanes
+    rpt = full if rows_per_block >= full else max(1, min(full, rows_per_block_l))
     ntiles = (n + rpt - 1) // rpt
     return 256 * 8 * ((ntiles + 7) // 8)
 
@@ -839,7 +841,7 @@ def main():
     ch = 4 if nnz < 4 * n else 8 if nnz < 10 * n else 16
     bk = f"k_block_csr_v<float, 8, {ch}>"
     b8 = spmm["f32_b8"]
-    gthreads = block_launch_threads(n, 8, 4)
+    gthreads = block_launch_threads(n, 8, 4, info["rows_per_block"], info["rows_per_block_l"])
     roof_block = {"bound": "hbm", "achieved": b8["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": b8["frac"], "traffic": block_traffic_from_profile(bk, gthreads),
                   "kernel": bk, "kernel_ms": b8["ms"], "algorithmic_bytes": b8["bytes"],

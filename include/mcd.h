@@ -237,6 +237,9 @@ typedef struct mcd_op_info_t {
                                  built (on-the-fly operator, operator made for block
                                  products only, or a basis that does not fit the layout) */
     int64_t grouped_groups;   /* up-hop groups of the grouped layout (table entries) */
+    int32_t rows_per_block_l; /* CSR: rows per block with <= 8192 nonzeros (tiles of the
+                                 block products when the stream row block is shorter) */
+    int32_t reserved;         /* 0 */
 } mcd_op_info_t;
 
 int mcd_op_info(const mcd_op *op, mcd_op_info_t *info);

@@ -55,7 +55,7 @@ class McdOpInfo(ctypes.Structure):
     _fields_ = [("n", c_i64), ("nnz", c_i64), ("storage", c_i32), ("n_classes", c_i32),
                 ("rows_per_block", c_i32), ("kernel", c_i32), ("device_bytes", c_i64),
                 ("build_ms", c_dbl), ("grouped_blocks", c_i64),
-                ("grouped_groups", c_i64)]
+                ("grouped_groups", c_i64), ("rows_per_block_l", c_i32), ("reserved", c_i32)]
 
 
 class McdLanczosCfg(ctypes.Structure):
@@ -351,7 +351,8 @@ class Operator:
         return dict(n=i.n, nnz=i.nnz, storage=STORAGE_NAME[i.storage], n_classes=i.n_classes,
                     rows_per_block=i.rows_per_block, kernel=KERNEL_NAME.get(i.kernel, "none"),
                     device_bytes=i.device_bytes, build_ms=i.build_ms,
-                    grouped_blocks=i.grouped_blocks, grouped_groups=i.grouped_groups)
+                    grouped_blocks=i.grouped_blocks, grouped_groups=i.grouped_groups,
+                    rows_per_block_l=i.rows_per_block_l)
 
     def kernels(self) -> list:
         """One-vector CSR kernels this operator can run (grouped ones only when

@@ -1321,7 +1321,7 @@ __device__ __forceinline__ T *mr_buf(const MRun &r, int kind, int slot, int P) {
     return (T *)r.Qs + (int64_t)slot * r.n * P;
 }
 
-template <typename T, int NV, int CH>
+template <typename T, int NV, int CH, int WMAX>
 __global__ __launch_bounds__(256) void k_mr_spmm(const MRun *__restrict__ R, int nrun,
                                                  int64_t total, int rpt, int slot) {
     const int64_t per = (total + kNumXcd - 1) / kNumXcd;
@@ -1329,8 +1329,8 @@ __global__ __launch_bounds__(256) void k_mr_spmm(const MRun *__restrict__ R, int
     if (t >= total) return;   // whole workgroup, before any barrier
     const MRun &r = R[mr_find(R, nrun, t, 0)];
     const int64_t rbeg = (t - r.tile0) * rpt;
-    block_csr_v_rows<T, NV, CH>(r.rowptr, r.colw, r.model, r.diag, mr_buf<T>(r, 2, slot, NV),
-                                (T *)r.W, rbeg, min(rbeg + (int64_t)rpt, r.n));
+    block_csr_v_tile<T, NV, CH, WMAX>(r.rowptr, r.colw, r.model, r.diag, mr_buf<T>(r, 2, slot, NV),
+                                      (T *)r.W, rbeg, min(rbeg + (int64_t)rpt, r.n));
 }
 
 template <typename T, int P, int TPR>
@@ -1407,6 +1407,7 @@ struct MRTable {
     int nrun = 0, P = 0, mb = 0, nstore = 0;
     int64_t tiles = 0, chunks = 0, rowt = 0;
     int rpt = 0, ch = 16;
+    bool large = false;   // tiles with room for kBlockWordsLarge words
     hipStream_t s = nullptr;
 
     static bool usable(const std::vector<BandRun<T> *> &runs) {
@@ -1422,11 +1423,22 @@ struct MRTable {
         tiles = chunks = rowt = 0;
         int64_t nnz = 0, rows = 0;
         constexpr int VN = 16 / sizeof(T);
+        // one-pass tiles (block_tile) that fit every run's row blocks
+        {
+            const int L = act.empty() ? 1 : std::max(1, act[0]->P / VN);
+            int rpb = 256, rpb_l = 256;
+            for (auto *r : act) {
+                rpb = std::min(rpb, r->op->rows_per_block);
+                rpb_l = std::min(rpb_l, r->op->rows_per_block_l);
+            }
+            const BlockTile bt = block_tile(L, rpb, rpb_l);
+            rpt = bt.rows;
+            large = bt.large;
+        }
         for (auto *r : act) {
             P = r->P;
             mb = r->mb;
             nstore = r->nstore;
-            rpt = block_rows_per_tile(r->P / VN);   // as the one-run product
             MRun d;
             memset(&d, 0, sizeof(d));
             d.n = r->n;
@@ -1461,14 +1473,19 @@ struct MRTable {
     }
 
     int spmm(int j) {
-#define MRS(NV, CH)                                                                          \
-    hipLaunchKernelGGL((k_mr_spmm<T, NV, CH>), dim3((unsigned)((tiles + 7) / 8 * 8)),        \
+#define MRS(NV, CH, WM)                                                                      \
+    hipLaunchKernelGGL((k_mr_spmm<T, NV, CH, WM>), dim3((unsigned)((tiles + 7) / 8 * 8)),    \
                        dim3(256), 0, s, dev, nrun, tiles, rpt, slot(j))
+#define MRW(NV, CH) \
+    do {                                                                                     \
+        if (large) MRS(NV, CH, kBlockWordsLarge); else MRS(NV, CH, kStreamNnzMax);           \
+    } while (0)
         if (P == 8) {
-            if (ch == 4) MRS(8, 4); else if (ch == 8) MRS(8, 8); else MRS(8, 16);
+            if (ch == 4) MRW(8, 4); else if (ch == 8) MRW(8, 8); else MRW(8, 16);
         } else {
-            if (ch == 4) MRS(16, 4); else if (ch == 8) MRS(16, 8); else MRS(16, 16);
+            if (ch == 4) MRW(16, 4); else if (ch == 8) MRW(16, 8); else MRW(16, 16);
         }
+#undef MRW
 #undef MRS
         MCD_HIP(hipGetLastError());
         return MCD_OK;

@@ -56,6 +56,7 @@ constexpr uint64_t kEmpty = ~0ull;           // hash sentinel, never a valid key
 constexpr int kMaxClasses = 32;              // packed CSR: distinct |t| values
 constexpr int kStreamNnzMax = 4096;          // LDS products per stream block
 constexpr int kStreamNnzSmall = 1024;        // ... of the small-block stream variant
+constexpr int kBlockWordsLarge = 8192;      // column words of a large one-pass block-product tile
 constexpr int kMergeBS = 256;                // merge-path SpMV: threads per workgroup
 constexpr int kMergeDepth = 8;               // nonzeros per thread per chunk
 constexpr int kMergeK = kMergeBS * kMergeDepth;  // path items (nonzeros + 9 per row) per chunk
@@ -174,6 +175,7 @@ struct mcd_op {
     int32_t storage;
     int32_t rows_per_block;    // stream kernel: rows per block (<= kStreamNnzMax nonzeros)
     int32_t rows_per_block_s;  // small-block stream kernel (<= kStreamNnzSmall nonzeros)
+    int32_t rows_per_block_l;  // rows per block with <= kBlockWordsLarge nonzeros
     int32_t group_chunk;       // row-parallel products: packed words per chunk (4, 8 or 16)
     int64_t nnz;
     int64_t device_bytes;

@@ -526,7 +526,7 @@ __global__ __launch_bounds__(256) void k_block_csr(
 // instruction covers 4 / L times more rows; the same terms are added in the
 // same order per column as in k_block_csr (bit-identical y).  X and Y
 // 16-byte aligned.  XCD-major row tiles.
-template <typename T, int NV, int CH>
+template <typename T, int NV, int CH, int WMAX>
 __global__ __launch_bounds__(256) void k_block_csr_v(
     int64_t n, const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ colw,
     const DevModel *__restrict__ m, const double *__restrict__ diag, const T *__restrict__ x,
@@ -535,8 +535,8 @@ __global__ __launch_bounds__(256) void k_block_csr_v(
     const int64_t tile = (int64_t)(blockIdx.x % kNumXcd) * per + blockIdx.x / kNumXcd;
     if (tile >= ntiles) return;   // whole workgroup, before any barrier
     const int64_t rbeg = tile * rows_per_tile;
-    block_csr_v_rows<T, NV, CH>(rowptr, colw, m, diag, x, y, rbeg,
-                                min(rbeg + (int64_t)rows_per_tile, n));
+    block_csr_v_tile<T, NV, CH, WMAX>(rowptr, colw, m, diag, x, y, rbeg,
+                                      min(rbeg + (int64_t)rows_per_tile, n));
 }
 
 __global__ void k_conn_count(int64_t row0, int64_t row1, const uint64_t *__restrict__ keys,
@@ -640,6 +640,7 @@ static int csr_fill(mcd_op *op, hipStream_t s) {
     MCD_HIP(e);
     op->rows_per_block = 1;
     op->rows_per_block_s = 1;
+    op->rows_per_block_l = 1;
     for (int k = 8; k >= 0; k--)
         if (mx[k] <= (unsigned long long)kStreamNnzMax) {
             op->rows_per_block = 1 << k;
@@ -648,6 +649,11 @@ static int csr_fill(mcd_op *op, hipStream_t s) {
     for (int k = 8; k >= 0; k--)
         if (mx[k] <= (unsigned long long)kStreamNnzSmall) {
             op->rows_per_block_s = 1 << k;
+            break;
+        }
+    for (int k = 8; k >= 0; k--)
+        if (mx[k] <= (unsigned long long)kBlockWordsLarge) {
+            op->rows_per_block_l = 1 << k;
             break;
         }
     // row-parallel products: words per chunk from the mean row length
@@ -841,29 +847,31 @@ static int tune_kernel(mcd_op *op, hipStream_t s) {
 }
 
 // Block CSR product with 16-byte gathers (k_block_csr_v), when a row of the
-// block is a whole number of them; launch shape from block_rows_per_tile /
-// block_chunk.
+// block is a whole number of them; one-pass tiles (block_csr_v_tile), words
+// per chunk from block_chunk.
 template <typename T, int NV>
 static void launch_block_v(const mcd_op *op, const T *x, T *y, hipStream_t s) {
     if constexpr (NV % Vec16<T>::n == 0) {
         constexpr int L = NV / Vec16<T>::n;
-        const int rpt = block_rows_per_tile(L);
+        const BlockTile bt = block_tile(L, op->rows_per_block, op->rows_per_block_l);
+        const int rpt = bt.rows;
         const int ch = block_chunk(L, op->group_chunk);
         const int64_t n = op->n;
         const int64_t ntiles = (n + rpt - 1) / rpt;
         const unsigned grid = (unsigned)(kNumXcd * ((ntiles + kNumXcd - 1) / kNumXcd));
-        if (ch == 4)
-            hipLaunchKernelGGL((k_block_csr_v<T, NV, 4>), dim3(grid), dim3(256), 0, s, n,
-                               op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x, y, ntiles,
-                               rpt);
-        else if (ch == 8)
-            hipLaunchKernelGGL((k_block_csr_v<T, NV, 8>), dim3(grid), dim3(256), 0, s, n,
-                               op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x, y, ntiles,
-                               rpt);
-        else
-            hipLaunchKernelGGL((k_block_csr_v<T, NV, 16>), dim3(grid), dim3(256), 0, s, n,
-                               op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x, y, ntiles,
-                               rpt);
+#define LBV(CH, WM)                                                                      \
+    hipLaunchKernelGGL((k_block_csr_v<T, NV, CH, WM>), dim3(grid), dim3(256), 0, s, n,     \
+                       op->d_rowptr, op->d_colw, op->d_model, op->d_diag, x, y, ntiles, rpt)
+        if (!bt.large) {
+            if (ch == 4) LBV(4, kStreamNnzMax);
+            else if (ch == 8) LBV(8, kStreamNnzMax);
+            else LBV(16, kStreamNnzMax);
+        } else {
+            if (ch == 4) LBV(4, kBlockWordsLarge);
+            else if (ch == 8) LBV(8, kBlockWordsLarge);
+            else LBV(16, kBlockWordsLarge);
+        }
+#undef LBV
     }
 }
 
@@ -1102,6 +1110,7 @@ int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32
     if (st == MCD_STORAGE_AUTO) st = fmt_ok ? MCD_STORAGE_CSR : MCD_STORAGE_ON_THE_FLY;
     op->rows_per_block = 256;
     op->rows_per_block_s = 256;
+    op->rows_per_block_l = 256;
     op->group_chunk = 16;
     op->kernel = KERNEL_STREAM_XCD;
     if (st == MCD_STORAGE_CSR) {
@@ -1211,11 +1220,13 @@ extern "C" int mcd_op_info(const mcd_op *op, mcd_op_info_t *info) {
     info->storage = op->storage;
     info->n_classes = op->hm.dm.n_classes;
     info->rows_per_block = op->rows_per_block;
+    info->rows_per_block_l = op->rows_per_block_l;
     info->kernel = op->kernel;
     info->device_bytes = op->device_bytes;
     info->build_ms = op->build_ms;
     info->grouped_blocks = op->g_nblocks;
     info->grouped_groups = op->g_nblocks > 0 ? op->g_ngroups : 0;
+    info->reserved = 0;
     return MCD_OK;
 }
 

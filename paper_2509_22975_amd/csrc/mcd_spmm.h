@@ -40,23 +40,42 @@ __device__ __forceinline__ void vscale_add(double2 &acc, double a, const double2
     acc.y += a * x.y;
 }
 
-// Launch shape of the row-parallel block product with L lanes per row
-// (measured on gfx950, C2 basis, 8 and 16 vectors): row tiles that keep all
-// 256 threads busy at L <= 2 and 64-row tiles above; at most 8 gathers in
-// flight per lane at L >= 4 (ch: words per chunk from the mean row length).
-// Neither changes a row's sum (entry order either way).
-inline int block_rows_per_tile(int L) { return L <= 2 ? 256 / L : 64; }
+// Words per chunk of the block product with L lanes per row (measured on
+// gfx950, C2 basis, 8 and 16 vectors): at most 8 gathers in flight per lane
+// at L >= 4 (ch: words per chunk from the mean row length).  It does not
+// change a row's sum (entry order either way).
 inline int block_chunk(int L, int ch) { return L >= 4 ? (ch < 8 ? ch : 8) : ch; }
 
-// Y[r] = d_r X[r] + sum over the row's entries of +-|t| X[col] for the rows
-// [rbeg, rend) of an n-row block of NV vectors (row-major, 16-byte aligned):
-// L = NV / (16 / sizeof T) lanes per row, each lane 16 bytes of the gathered
-// row (float4 / double2); the row's words loaded CH at a time (one coalesced
-// access) and broadcast by lane shuffles, CH gathers in flight; sum in entry
-// order.  Every thread of the workgroup must call it (the amplitude table
-// goes through LDS behind a barrier).
-template <typename T, int NV, int CH>
-__device__ __forceinline__ void block_csr_v_rows(const int64_t *__restrict__ rowptr,
+// Tile of the one-pass block product with L lanes per row: 256 / L rows with
+// room for kStreamNnzMax column words when every block of that many rows has
+// no more nonzeros (rpb: the operator's row block for kStreamNnzMax), else
+// room for kBlockWordsLarge words and as many rows as that allows (rpb_l),
+// at most 256 / L.  Both row counts are powers of two, so a tile is an
+// aligned part of a block that fits.
+struct BlockTile {
+    int rows;
+    bool large;
+};
+inline BlockTile block_tile(int L, int rpb, int rpb_l) {
+    const int full = 256 / L;
+    if (rpb >= full) return {full, false};
+    return {rpb_l < full ? (rpb_l > 1 ? rpb_l : 1) : full, true};
+}
+
+// Y[r] = d_r X[r] + sum over the row's entries of +-|t| X[col] for one tile
+// of rows [rbeg, rend) of an n-row block of NV vectors (row-major, 16-byte
+// aligned) in a single pass: rend - rbeg <= 256 / L with L = NV / (16 /
+// sizeof T) lanes per row, each lane 16 bytes of the gathered row (float4 /
+// double2), and the tile's entries <= WMAX.  Every thread first issues its
+// loads -- its row's pointers, diagonal and own X row, the tile's first and
+// last pointers, the amplitude table -- then the tile's column words are
+// loaded together (coalesced, unconditional loads on clamped addresses) into
+// LDS, and after one barrier each row reads its words from LDS, CH at a
+// time, and issues their gathers; sum in entry order.  Two dependent global
+// round trips before the gathers.  Every thread of the workgroup must call
+// it (barrier).
+template <typename T, int NV, int CH, int WMAX>
+__device__ __forceinline__ void block_csr_v_tile(const int64_t *__restrict__ rowptr,
                                                  const uint32_t *__restrict__ colw,
                                                  const DevModel *__restrict__ m,
                                                  const double *__restrict__ diag,
@@ -65,62 +84,52 @@ __device__ __forceinline__ void block_csr_v_rows(const int64_t *__restrict__ row
     using V = typename Vec16<T>::type;
     constexpr int L = NV / Vec16<T>::n;
     static_assert(L >= 1 && L * Vec16<T>::n == NV, "NV must be a multiple of the vector width");
+    constexpr int DEPTH = WMAX / 256;
+    static_assert(DEPTH * 256 == WMAX, "whole words per thread");
     __shared__ T vtab[kMaxClasses];
-    if (threadIdx.x < kMaxClasses) vtab[threadIdx.x] = (T)m->vtab[threadIdx.x];
-    __syncthreads();
-    const uint32_t cmask = m->col_mask, cbits = m->col_bits;
-    constexpr int RPB = 256 / L;
-    constexpr int WPL = (CH + L - 1) / L;
-    const int lane = threadIdx.x % L;
+    __shared__ uint32_t wl[WMAX];
+    const int t = threadIdx.x, lane = t % L;
     const V *__restrict__ xv4 = reinterpret_cast<const V *>(x);
     V *__restrict__ yv4 = reinterpret_cast<V *>(y);
-    for (int64_t r = rbeg + threadIdx.x / L; r < rend; r += RPB) {
-        const T d = (T)diag[r];
-        V acc = vscale(d, xv4[r * L + lane]);
-        const int64_t e1 = rowptr[r + 1];
-        // the words of the row's first two chunks are loaded at once (a row
-        // of up to 2 CH entries waits for one word load, not two)
-        uint32_t mw2[2 * WPL];
-        {
-            const int64_t b0 = rowptr[r];
+    const int64_t r = rbeg + t / L;
+    const bool own = r < rend;
+    const int64_t rr = own ? r : rend - 1;
+    const int64_t e0 = rowptr[rbeg], eT = rowptr[rend];
+    const int64_t b0 = rowptr[rr], e1 = rowptr[rr + 1];
+    const T d = (T)diag[rr];
+    const V xr = xv4[rr * L + lane];
+    if (t < kMaxClasses) vtab[t] = (T)m->vtab[t];
+    const uint32_t cmask = m->col_mask, cbits = m->col_bits;
+    const int cnt = (int)(eT - e0);
+    if (cnt > 0) {   // uniform over the workgroup
+        uint32_t w[DEPTH];
 #pragma unroll
-            for (int c = 0; c < 2; c++)
+        for (int j = 0; j < DEPTH; j++) w[j] = colw[e0 + min(t + j * 256, cnt - 1)];
 #pragma unroll
-                for (int q = 0; q < WPL; q++) {
-                    const int64_t e = b0 + c * CH + q * L + lane;
-                    mw2[c * WPL + q] = (q * L + lane < CH && e < e1) ? colw[e] : 0u;
-                }
-        }
-        int chunk = 0;
-        for (int64_t base = rowptr[r]; base < e1; base += CH, chunk++) {
-            uint32_t mw[WPL];
-            if (chunk < 2) {
-#pragma unroll
-                for (int q = 0; q < WPL; q++) mw[q] = chunk == 0 ? mw2[q] : mw2[WPL + q];
-            } else {
-#pragma unroll
-                for (int q = 0; q < WPL; q++) {
-                    const int64_t e = base + q * L + lane;
-                    mw[q] = (q * L + lane < CH && e < e1) ? colw[e] : 0u;
-                }
-            }
-            uint32_t wj[CH];
-            V xg[CH];
-#pragma unroll
-            for (int j = 0; j < CH; j++) {
-                wj[j] = (uint32_t)__shfl((int)mw[j / L], j % L, L);
-                xg[j] = (base + j < e1) ? xv4[(int64_t)(wj[j] & cmask) * L + lane] : V{};
-            }
-#pragma unroll
-            for (int j = 0; j < CH; j++) {
-                if (base + j < e1) {
-                    const T v = vtab[(wj[j] & 0x7fffffffu) >> cbits];
-                    vscale_add(acc, (wj[j] >> 31) ? -v : v, xg[j]);
-                }
-            }
-        }
-        yv4[r * L + lane] = acc;
+        for (int j = 0; j < DEPTH; j++)
+            if (t + j * 256 < cnt) wl[t + j * 256] = w[j];
     }
+    __syncthreads();
+    if (!own) return;
+    V acc = vscale(d, xr);
+    const int s1 = (int)(e1 - e0);
+    for (int base = (int)(b0 - e0); base < s1; base += CH) {
+        uint32_t wj[CH];
+        V xg[CH];
+#pragma unroll
+        for (int j = 0; j < CH; j++) wj[j] = base + j < s1 ? wl[base + j] : 0u;
+#pragma unroll
+        for (int j = 0; j < CH; j++)
+            xg[j] = (base + j < s1) ? xv4[(int64_t)(wj[j] & cmask) * L + lane] : V{};
+#pragma unroll
+        for (int j = 0; j < CH; j++) {
+            if (base + j < s1) {
+                const T v = vtab[(wj[j] & 0x7fffffffu) >> cbits];
+                vscale_add(acc, (wj[j] >> 31) ? -v : v, xg[j]);
+            }
+        }
+    }
+    yv4[r * L + lane] = acc;
 }
 
 }  // namespace mcd
