@@ -839,7 +839,8 @@ def main():
     # The chosen form's product: float32 blocks of 8 vectors (p = 8 band runs;
     # the many-run band kernel runs the same device function per row tile).
     ch = 4 if nnz < 4 * n else 8 if nnz < 10 * n else 16
-    bk = f"k_block_csr_v<float, 8, {ch}>"
+    wmax = 4096 if info["rows_per_block"] >= 128 else 8192   # tile words (2 lanes per row)
+    bk = f"k_block_csr_v<float, 8, {ch}, {wmax}>"
     b8 = spmm["f32_b8"]
     gthreads = block_launch_threads(n, 8, 4, info["rows_per_block"], info["rows_per_block_l"])
     roof_block = {"bound": "hbm", "achieved": b8["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
