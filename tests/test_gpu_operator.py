@@ -162,6 +162,44 @@ def test_merge_path_long_and_empty_rows():
         op.close()
 
 
+def test_block_product_tiles():
+    """Block products in one-pass row tiles: rows of ~48 nonzeros (the first
+    40,000 states of a fully connected 12-orbital model's sector) give
+    64-row blocks of <= 4096 and 128-row blocks of <= 8192 nonzeros, so one
+    or two lanes per row (float32 x 4 / x 8, float64 x 2 / x 4) take the
+    large 128-row tiles and four or eight lanes the 4096-word ones; a sparse
+    chain subset takes full tiles.  Against the whole-matrix product, and
+    the shared columns of different block widths bit for bit (the
+    per-column sum is the same whatever the tile)."""
+    torch, mcd = require_gpu()
+    rng = np.random.default_rng(5)
+    amps = [-1.0, -0.5, 0.3, 0.7]
+    bonds = [(i, j, float(rng.choice(amps))) for i in range(12) for j in range(i + 1, 12)]
+    dense = W.Model(12, bonds, rng.uniform(0, 4, 12), rng.uniform(-1, 1, 12), 6, 6, "dense")
+    full = fock.sector_keys(12, 6, 6)
+    cases = {"dense": (dense, full[:40000], (64, 128)),
+             "chain": (W.chain(12, U=8.0, mu=4.0), np.sort(rng.choice(full, 30000, replace=False)), None)}
+    for name, (m, keys, rpb) in cases.items():
+        H = ham.build_csr(keys, m)
+        op = mcd.Operator(m, mcd.keys_from_numpy(keys), storage="csr")
+        info = op.info()
+        log_case("block_tiles", case=name, n=len(keys), rows_per_block=info["rows_per_block"],
+                 rows_per_block_l=info["rows_per_block_l"])
+        if rpb is not None:
+            assert (info["rows_per_block"], info["rows_per_block_l"]) == rpb
+        for dt, tdt, tol in ((np.float64, torch.float64, 1e-12), (np.float32, torch.float32, 2e-6)):
+            X = W.random_vector(len(keys), 9, 16).astype(dt)
+            Xd = torch.from_numpy(X).cuda()
+            Y = {}
+            for nv in (2, 4, 8, 16):
+                Y[nv] = op.apply(Xd[:, :nv].contiguous()).cpu().numpy()
+                ref = H @ X[:, :nv].astype(np.float64)
+                assert _rel(Y[nv].astype(np.float64), ref) <= tol, (name, dt, nv)
+            for nv in (2, 4, 8):
+                assert np.array_equal(Y[16][:, :nv], Y[nv]), (name, dt, nv)
+        op.close()
+
+
 @pytest.mark.parametrize("storage", ["csr", "otf"])
 @pytest.mark.parametrize("nvec", [1, 8, 16])
 def test_apply_f32(storage, nvec):
