@@ -1,7 +1,7 @@
 // Block product of the packed CSR with 16-byte gathers, as a device
-// function over a range of rows, shared by the one-operator kernel
+// function over one tile of rows, shared by the one-operator kernel
 // (mcd_op.hip) and the kernel that serves many band runs in one launch
-// (mcd_band.hip).
+// (mcd_band.hip), and the rule that sizes its tiles.
 #pragma once
 
 #include <hip/hip_runtime.h>
