@@ -252,7 +252,8 @@ int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32
 // Workspace bytes op_create takes from an empty workspace (stages: 1 index,
 // 2 up to the nonzero count, 3 all but the grouped layout, 4 with the largest
 // grouped layout).
-size_t op_plan(int64_t n, bool csr, int64_t nnz, bool tune, bool validate, int stages);
+size_t op_plan(int64_t n, bool csr, int64_t nnz, bool tune, bool validate, int stages,
+               int n_bonds);
 
 // Deterministic dot product a . b into *out_dev (mcd_lanczos.hip).
 int dev_dot(const mcd_op *op, const double *a, const double *b, int64_t n, double *out_dev,

@@ -99,31 +99,109 @@ __device__ __forceinline__ void for_each_hop(uint64_t key, const DevModel *__res
     }
 }
 
+// Candidate hops of a row, in for_each_hop's order (up-spin bonds, then
+// down-spin bonds; a bond is a candidate when exactly one of its ends is
+// occupied in that spin's string): at most 2 n_bonds, so up to 256 fit the
+// four 64-bit words of a row's found mask.
+constexpr int kFoundWords = 4;
+inline int found_words(int n_bonds) {
+    const int w = (2 * n_bonds + 63) / 64;
+    return w <= kFoundWords ? std::max(w, 1) : 0;   // 0: no mask (every candidate probed twice)
+}
+
+// Kept hops per row; with `found` (nw words per row, word w of row r at
+// found[w n + r]) also which candidates were found in the basis, so the fill
+// probes only those.
 __global__ void k_csr_count(int64_t n, const uint64_t *__restrict__ keys,
                             const DevModel *__restrict__ m, const HashSlot *__restrict__ h,
-                            uint64_t hmask, int64_t *__restrict__ cnt) {
+                            uint64_t hmask, int64_t *__restrict__ cnt,
+                            uint64_t *__restrict__ found, int nw) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r > n) return;
     if (r == n) {
         cnt[n] = 0;
         return;
     }
+    if (found == nullptr) {
+        int64_t c = 0;
+        for_each_hop(keys[r], m, h, hmask, [&](int64_t, int, uint32_t) { c++; });
+        cnt[r] = c;
+        return;
+    }
+    const uint64_t key = keys[r];
+    const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
+    uint64_t f[kFoundWords] = {0, 0, 0, 0};
+    int cand = 0;
     int64_t c = 0;
-    for_each_hop(keys[r], m, h, hmask, [&](int64_t, int, uint32_t) { c++; });
+    const int nb = m->n_bonds;
+    for (int spin = 0; spin < 2; spin++) {
+        const uint32_t str = spin == 0 ? up : dn;
+        for (int b = 0; b < nb; b++) {
+            const uint32_t mask = m->bonds[b].mask;
+            if (__popc(str & mask) != 1) continue;
+            const uint64_t t = spin == 0 ? key ^ ((uint64_t)mask << 32) : key ^ (uint64_t)mask;
+            if (hash_find(h, hmask, t) >= 0) {
+                const uint64_t bit = 1ull << (cand & 63);
+#pragma unroll
+                for (int w = 0; w < kFoundWords; w++)
+                    if ((cand >> 6) == w) f[w] |= bit;
+                c++;
+            }
+            cand++;
+        }
+    }
     cnt[r] = c;
+#pragma unroll
+    for (int w = 0; w < kFoundWords; w++)
+        if (w < nw) found[(int64_t)w * n + r] = f[w];
 }
 
+// Packed words of a row in for_each_hop's order; with `found`, only the
+// candidates the count found are looked up (each lookup then hits).
 __global__ void k_csr_fill(int64_t n, const uint64_t *__restrict__ keys,
                            const DevModel *__restrict__ m, const HashSlot *__restrict__ h,
                            uint64_t hmask, const int64_t *__restrict__ rowptr,
-                           uint32_t *__restrict__ colw) {
+                           uint32_t *__restrict__ colw, const uint64_t *__restrict__ found,
+                           int nw) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     int64_t e = rowptr[r];
-    for_each_hop(keys[r], m, h, hmask, [&](int64_t c, int b, uint32_t par) {
-        const uint32_t neg = par ^ m->bonds[b].neg;
-        colw[e++] = (uint32_t)c | (m->bonds[b].cls << m->col_bits) | (neg << 31);
-    });
+    if (found == nullptr) {
+        for_each_hop(keys[r], m, h, hmask, [&](int64_t c, int b, uint32_t par) {
+            const uint32_t neg = par ^ m->bonds[b].neg;
+            colw[e++] = (uint32_t)c | (m->bonds[b].cls << m->col_bits) | (neg << 31);
+        });
+        return;
+    }
+    uint64_t f[kFoundWords] = {0, 0, 0, 0};
+#pragma unroll
+    for (int w = 0; w < kFoundWords; w++)
+        if (w < nw) f[w] = found[(int64_t)w * n + r];
+    const uint64_t key = keys[r];
+    const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
+    int cand = 0;
+    const int nb = m->n_bonds;
+    for (int spin = 0; spin < 2; spin++) {
+        const uint32_t str = spin == 0 ? up : dn;
+        for (int b = 0; b < nb; b++) {
+            const uint32_t mask = m->bonds[b].mask;
+            if (__popc(str & mask) != 1) continue;
+            uint64_t word = 0;
+#pragma unroll
+            for (int w = 0; w < kFoundWords; w++)
+                if ((cand >> 6) == w) word = f[w];
+            if ((word >> (cand & 63)) & 1ull) {
+                const uint64_t t = spin == 0 ? key ^ ((uint64_t)mask << 32) : key ^ (uint64_t)mask;
+                const int64_t c = hash_find(h, hmask, t);
+                if (c >= 0) {
+                    const uint32_t par = (uint32_t)(__popc(str & m->bonds[b].between) & 1);
+                    const uint32_t neg = par ^ m->bonds[b].neg;
+                    colw[e++] = (uint32_t)c | (m->bonds[b].cls << m->col_bits) | (neg << 31);
+                }
+            }
+            cand++;
+        }
+    }
 }
 
 // Largest nonzero count of a row block [b R, (b + 1) R) for every R = 2^k,
@@ -586,21 +664,39 @@ static int64_t merge_chunks(int64_t n, int64_t nnz) {
 }
 
 // CSR stage 1: row pointers (kept) from per-row counts of the kept hops.
-static int csr_count(mcd_op *op, hipStream_t s) {
+// With `found` (op_create) the count also leaves each row's found-candidate
+// mask in a workspace piece taken before the count's temporaries, for
+// csr_fill, which releases it; without (the size query's probe) it counts
+// only.
+static int csr_count(mcd_op *op, hipStream_t s, uint64_t **found) {
     const int64_t n = op->n;
     int64_t *cnt = nullptr;
     void *tmp = nullptr;
+    uint64_t *fm = nullptr;
+    const int nw = found_words(op->hm.dm.n_bonds);
     MCD_HIP(dmalloc((void **)&op->d_rowptr, (n + 1) * sizeof(int64_t), op->alloc));
     op->device_bytes += (n + 1) * sizeof(int64_t);
-    MCD_HIP(dmalloc((void **)&cnt, (n + 1) * sizeof(int64_t), op->alloc));
+    if (found && nw > 0) MCD_HIP(dmalloc((void **)&fm, (size_t)n * nw * sizeof(uint64_t), op->alloc));
+    auto drop_mask = [&]() {
+        if (fm) (void)dfree(fm, op->alloc);
+        fm = nullptr;
+    };
+    {
+        const hipError_t ec = dmalloc((void **)&cnt, (n + 1) * sizeof(int64_t), op->alloc);
+        if (ec != hipSuccess) {
+            drop_mask();
+            MCD_HIP(ec);
+        }
+    }
     size_t tmp_bytes = scan_tmp_bytes(n);
     const hipError_t et = dmalloc(&tmp, tmp_bytes, op->alloc);
     if (et != hipSuccess) {
         (void)dfree(cnt, op->alloc);
+        drop_mask();
         MCD_HIP(et);
     }
     hipLaunchKernelGGL(k_csr_count, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, n, op->d_keys,
-                       op->d_model, op->d_hash, op->hash_mask, cnt);
+                       op->d_model, op->d_hash, op->hash_mask, cnt, fm, nw);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
         e = hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, op->d_rowptr, n + 1, s);
@@ -610,19 +706,30 @@ static int csr_count(mcd_op *op, hipStream_t s) {
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)dfree(tmp, op->alloc);
     (void)dfree(cnt, op->alloc);
+    if (e != hipSuccess) drop_mask();
     MCD_HIP(e);
     op->nnz = nnz;
+    if (found) *found = fm;
     return MCD_OK;
 }
 
 // CSR stage 2: the packed words, the stream kernels' row blocks and the
 // merge-path split points.
-static int csr_fill(mcd_op *op, hipStream_t s) {
+static int csr_fill(mcd_op *op, hipStream_t s, uint64_t *found) {
     const int64_t n = op->n, nnz = op->nnz;
-    MCD_HIP(dmalloc((void **)&op->d_colw, std::max<int64_t>(nnz, 1) * sizeof(uint32_t), op->alloc));
+    {
+        const hipError_t ea = dmalloc((void **)&op->d_colw,
+                                      std::max<int64_t>(nnz, 1) * sizeof(uint32_t), op->alloc);
+        if (ea != hipSuccess) {
+            if (found) (void)dfree(found, op->alloc);
+            MCD_HIP(ea);
+        }
+    }
     op->device_bytes += nnz * sizeof(uint32_t);
     hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, n, op->d_keys,
-                       op->d_model, op->d_hash, op->hash_mask, op->d_rowptr, op->d_colw);
+                       op->d_model, op->d_hash, op->hash_mask, op->d_rowptr, op->d_colw, found,
+                       found_words(op->hm.dm.n_bonds));
+    if (found) (void)dfree(found, op->alloc);   // stream order: later work runs after the fill
     MCD_HIP(hipGetLastError());
     // Largest power-of-two row block whose nonzeros fit the LDS product buffer
     // (one choice per buffer size of the stream kernels), all sizes in one pass.
@@ -1032,7 +1139,8 @@ static void release_csr(mcd_op *op) {
 // releases replayed on the host bookkeeping (stage 1: index only, 2: up to
 // the nonzero count, 3: everything but the optional grouped layout, 4: with
 // a grouped layout of the largest possible size).
-size_t op_plan(int64_t n, bool csr, int64_t nnz, bool tune, bool validate, int stages) {
+size_t op_plan(int64_t n, bool csr, int64_t nnz, bool tune, bool validate, int stages,
+               int n_bonds) {
     WsAlloc w(size_t(1) << 62);
     const int64_t nn = std::max<int64_t>(n, 1);
     std::vector<size_t> keep;
@@ -1046,14 +1154,21 @@ size_t op_plan(int64_t n, bool csr, int64_t nnz, bool tune, bool validate, int s
     take(partials_capacity(n) * 8);
     take(8 * sizeof(unsigned int));
     take(64 * 8);
+    // the found-candidate mask is taken by op_create's count (stage 3 plans),
+    // not by the size query's probe (stage 2 alone)
+    const int nw = found_words(n_bonds);
+    const bool mask = stages >= 3 && csr && nw > 0 && n > 0;
+    size_t fm = 0;
     if (stages >= 2 && csr) {
         take((n + 1) * 8);
+        if (mask) fm = temp((size_t)n * nw * 8);
         const size_t c = temp((n + 1) * 8), t = temp(scan_tmp_bytes(n));
         w.release(t);
         w.release(c);
     }
     if (stages >= 3 && csr) {
         take(std::max<int64_t>(nnz, 1) * 4);
+        if (mask) w.release(fm);
         w.release(temp(9 * 8));
         const int64_t nch = merge_chunks(n, nnz);
         take((nch + 1) * 8);
@@ -1114,8 +1229,9 @@ int op_create(const mcd_model *model, const uint64_t *keys_dev, int64_t n, int32
     op->group_chunk = 16;
     op->kernel = KERNEL_STREAM_XCD;
     if (st == MCD_STORAGE_CSR) {
-        rc = csr_count(op, s);
-        if (rc >= 0) rc = csr_fill(op, s);
+        uint64_t *found = nullptr;
+        rc = csr_count(op, s, &found);
+        if (rc >= 0) rc = csr_fill(op, s, found);
         if (rc == MCD_E_WORKSPACE && storage == MCD_STORAGE_AUTO) {
             // no room for the CSR: elements on the fly instead
             (void)hipStreamSynchronize(s);
@@ -1167,13 +1283,13 @@ extern "C" int mcd_op_workspace_size(const mcd_model *model, const uint64_t *key
     MCD_REQUIRE(storage != MCD_STORAGE_CSR || fmt_ok, MCD_E_CAPACITY,
                 "packed CSR needs n <= 2^%u and <= 32 distinct |t|", hm.dm.col_bits);
     if (storage == MCD_STORAGE_ON_THE_FLY || !fmt_ok) {
-        *bytes = op_plan(n, false, 0, false, true, 3);
+        *bytes = op_plan(n, false, 0, false, true, 3, hm.dm.n_bonds);
         if (bytes_grouped) *bytes_grouped = *bytes;
         return MCD_OK;
     }
     // The CSR size needs the nonzero count: index and count in the caller's
     // probe workspace (its size is the answer when ws is NULL or too small).
-    const size_t probe = op_plan(n, true, 0, false, true, 2);
+    const size_t probe = op_plan(n, true, 0, false, true, 2, hm.dm.n_bonds);
     if (ws == nullptr || ws->a.size() < probe) {
         *bytes = probe;
         if (bytes_grouped) *bytes_grouped = probe;
@@ -1188,13 +1304,14 @@ extern "C" int mcd_op_workspace_size(const mcd_model *model, const uint64_t *key
     op->n = n;
     int rc = hipGetDevice(&op->device) == hipSuccess ? MCD_OK : MCD_E_HIP;
     if (rc >= 0) rc = op_index(op, keys_dev, 0, s);
-    if (rc >= 0) rc = csr_count(op, s);
+    if (rc >= 0) rc = csr_count(op, s, nullptr);
     const int64_t nnz = op->nnz;
     (void)hipStreamSynchronize(s);
     mcd_op_destroy(op);
     MCD_TRY(rc);
-    *bytes = op_plan(n, true, nnz, true, true, 3);
-    if (bytes_grouped) *bytes_grouped = std::max(*bytes, op_plan(n, true, nnz, true, true, 4));
+    *bytes = op_plan(n, true, nnz, true, true, 3, hm.dm.n_bonds);
+    if (bytes_grouped)
+        *bytes_grouped = std::max(*bytes, op_plan(n, true, nnz, true, true, 4, hm.dm.n_bonds));
     return MCD_OK;
 }
 
