@@ -69,7 +69,11 @@ __global__ void k_g_rowmax(int64_t n, const int64_t *__restrict__ rowptr,
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
          r += (int64_t)gridDim.x * blockDim.x)
         best = max(best, (unsigned long long)(rowptr[r + 1] - rowptr[r]));
-    atomicMax(out, best);
+    for (int off = 32; off > 0; off >>= 1) best = max(best, __shfl_xor(best, off, 64));
+    // one atomic per wavefront, and only where it can raise the maximum
+    if ((threadIdx.x & 63) == 0 &&
+        best > __hip_atomic_load(out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(out, best);
 }
 
 __global__ void k_g_chunks(int64_t n, int64_t nch, int64_t step, const int64_t *__restrict__ rowptr,

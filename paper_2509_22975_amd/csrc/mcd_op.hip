@@ -224,7 +224,11 @@ __global__ void k_block_max_all(int64_t n, const int64_t *__restrict__ rowptr,
     for (int k = 0; k < 9; k++) {
         unsigned long long v = best[k];
         for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
-        if ((threadIdx.x & 63) == 0) atomicMax(&out[k], v);
+        // the atomic only where it can raise the maximum: the wavefronts
+        // would otherwise all queue on the same nine words
+        if ((threadIdx.x & 63) == 0 &&
+            v > __hip_atomic_load(&out[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&out[k], v);
     }
 }
 
