@@ -157,50 +157,75 @@ __global__ void k_csr_count(int64_t n, const uint64_t *__restrict__ keys,
 }
 
 // Packed words of a row in for_each_hop's order; with `found`, only the
-// candidates the count found are looked up (each lookup then hits).
-__global__ void k_csr_fill(int64_t n, const uint64_t *__restrict__ keys,
-                           const DevModel *__restrict__ m, const HashSlot *__restrict__ h,
-                           uint64_t hmask, const int64_t *__restrict__ rowptr,
-                           uint32_t *__restrict__ colw, const uint64_t *__restrict__ found,
-                           int nw) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    int64_t e = rowptr[r];
-    if (found == nullptr) {
-        for_each_hop(keys[r], m, h, hmask, [&](int64_t c, int b, uint32_t par) {
-            const uint32_t neg = par ^ m->bonds[b].neg;
-            colw[e++] = (uint32_t)c | (m->bonds[b].cls << m->col_bits) | (neg << 31);
-        });
-        return;
-    }
-    uint64_t f[kFoundWords] = {0, 0, 0, 0};
-#pragma unroll
-    for (int w = 0; w < kFoundWords; w++)
-        if (w < nw) f[w] = found[(int64_t)w * n + r];
-    const uint64_t key = keys[r];
-    const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
-    int cand = 0;
-    const int nb = m->n_bonds;
-    for (int spin = 0; spin < 2; spin++) {
-        const uint32_t str = spin == 0 ? up : dn;
-        for (int b = 0; b < nb; b++) {
-            const uint32_t mask = m->bonds[b].mask;
-            if (__popc(str & mask) != 1) continue;
-            uint64_t word = 0;
+// candidates the count found are looked up (each lookup then hits).  The
+// workgroup's rows own one contiguous range of words: when it fits
+// kFillStage words, each thread writes its row's words into LDS and the
+// workgroup then stores the range coalesced; otherwise straight to memory.
+constexpr int kFillStage = 8192;
+__global__ __launch_bounds__(256) void k_csr_fill(int64_t n, const uint64_t *__restrict__ keys,
+                                                  const DevModel *__restrict__ m,
+                                                  const HashSlot *__restrict__ h, uint64_t hmask,
+                                                  const int64_t *__restrict__ rowptr,
+                                                  uint32_t *__restrict__ colw,
+                                                  const uint64_t *__restrict__ found, int nw) {
+    __shared__ uint32_t stage[kFillStage];
+    const int64_t r0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t r = r0 + threadIdx.x;
+    const int64_t r1 = min(r0 + (int64_t)blockDim.x, n);   // r0 < n for every workgroup
+    const int64_t w0 = rowptr[r0], w1 = rowptr[r1];
+    const bool staged = w1 - w0 <= kFillStage;               // uniform over the workgroup
+    const bool own = r < n;
+    int64_t e = own ? rowptr[r] : 0;
+    auto put = [&](uint32_t word) {
+        if (staged)
+            stage[e - w0] = word;
+        else
+            colw[e] = word;
+        e++;
+    };
+    if (own) {
+        if (found == nullptr) {
+            for_each_hop(keys[r], m, h, hmask, [&](int64_t c, int b, uint32_t par) {
+                const uint32_t neg = par ^ m->bonds[b].neg;
+                put((uint32_t)c | (m->bonds[b].cls << m->col_bits) | (neg << 31));
+            });
+        } else {
+            uint64_t f[kFoundWords] = {0, 0, 0, 0};
 #pragma unroll
             for (int w = 0; w < kFoundWords; w++)
-                if ((cand >> 6) == w) word = f[w];
-            if ((word >> (cand & 63)) & 1ull) {
-                const uint64_t t = spin == 0 ? key ^ ((uint64_t)mask << 32) : key ^ (uint64_t)mask;
-                const int64_t c = hash_find(h, hmask, t);
-                if (c >= 0) {
-                    const uint32_t par = (uint32_t)(__popc(str & m->bonds[b].between) & 1);
-                    const uint32_t neg = par ^ m->bonds[b].neg;
-                    colw[e++] = (uint32_t)c | (m->bonds[b].cls << m->col_bits) | (neg << 31);
+                if (w < nw) f[w] = found[(int64_t)w * n + r];
+            const uint64_t key = keys[r];
+            const uint32_t up = (uint32_t)(key >> 32), dn = (uint32_t)key;
+            int cand = 0;
+            const int nb = m->n_bonds;
+            for (int spin = 0; spin < 2; spin++) {
+                const uint32_t str = spin == 0 ? up : dn;
+                for (int b = 0; b < nb; b++) {
+                    const uint32_t mask = m->bonds[b].mask;
+                    if (__popc(str & mask) != 1) continue;
+                    uint64_t word = 0;
+#pragma unroll
+                    for (int w = 0; w < kFoundWords; w++)
+                        if ((cand >> 6) == w) word = f[w];
+                    if ((word >> (cand & 63)) & 1ull) {
+                        const uint64_t t =
+                            spin == 0 ? key ^ ((uint64_t)mask << 32) : key ^ (uint64_t)mask;
+                        const int64_t c = hash_find(h, hmask, t);
+                        if (c >= 0) {
+                            const uint32_t par =
+                                (uint32_t)(__popc(str & m->bonds[b].between) & 1);
+                            const uint32_t neg = par ^ m->bonds[b].neg;
+                            put((uint32_t)c | (m->bonds[b].cls << m->col_bits) | (neg << 31));
+                        }
+                    }
+                    cand++;
                 }
             }
-            cand++;
         }
+    }
+    if (staged) {
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < w1 - w0; i += blockDim.x) colw[w0 + i] = stage[i];
     }
 }
 
