@@ -346,48 +346,57 @@ __global__ __launch_bounds__(BS) void k_block_apply(int64_t n, int nm, const T *
     }
 }
 
-// k_block_apply with one thread per row (P >= 4): the row's P values of each
-// block come in 16-byte loads and are converted once, the P outputs are
-// accumulated in registers.  Each output receives the same terms in the same
-// (m, a) order as k_block_apply, so the results are bit-identical.
-// Row r of W (-)= sum_m Q_m C_m with the nm coefficient matrices in LDS (sC).
+// k_block_apply with one thread per row (P >= 4): row r of W (-)= sum_m
+// Q_m C_m.  The row's P values of each block come in 16-byte loads and are
+// converted once, the P outputs are accumulated in registers; each output
+// receives the same terms in the same (m, a) order as k_block_apply, so the
+// results are bit-identical.  The blocks are read as global memory (generic
+// pointers, as taken from a run table, would otherwise make flat loads that
+// wait together with everything else), and the coefficients C (read-only,
+// the same for the whole workgroup) through the constant address space, so
+// they arrive by scalar loads and feed the multiply-adds from scalar
+// registers (no LDS copy, no per-lane loads).
+template <typename T>
+using GPtr = __attribute__((address_space(1))) T *;
 template <typename T, int P>
-__device__ __forceinline__ void block_apply_row(int64_t r, int nm, const T *__restrict__ Q0,
-                                                int64_t qstride, const double *__restrict__ sC,
-                                                T *__restrict__ W, int sub) {
+__device__ __forceinline__ void block_apply_row(int64_t r, int nm, const T *Q0p, int64_t qstride,
+                                                const double *__restrict__ C, T *Wp, int sub) {
     constexpr int U = 16 / sizeof(T);
     using V16 = T __attribute__((ext_vector_type(16 / sizeof(T))));
-    {
-        double acc[P];
+    const GPtr<const T> Q0 = (GPtr<const T>)Q0p;
+    const GPtr<T> W = (GPtr<T>)Wp;
+    double acc[P];
 #pragma unroll
-        for (int b = 0; b < P; b++) acc[b] = 0.0;
-        for (int m = 0; m < nm; m++) {
-            const V16 *__restrict__ q = (const V16 *)(Q0 + (int64_t)m * qstride + r * P);
-            V16 qv[P / U];
+    for (int b = 0; b < P; b++) acc[b] = 0.0;
+    for (int m = 0; m < nm; m++) {
+        const GPtr<const V16> q = (GPtr<const V16>)(Q0 + (int64_t)m * qstride + r * P);
+        V16 qv[P / U];
 #pragma unroll
-            for (int u = 0; u < P / U; u++) qv[u] = q[u];
-            const double *__restrict__ c = sC + m * P * P;
+        for (int u = 0; u < P / U; u++) qv[u] = q[u];
+        // read-only for the kernel and the same for the whole workgroup:
+        // through the constant address space, so they come by scalar loads
+        const __attribute__((address_space(4))) double *c =
+            (const __attribute__((address_space(4))) double *)(C + m * P * P);
 #pragma unroll
-            for (int a = 0; a < P; a++) {
-                const double qa = (double)qv[a / U][a % U];
+        for (int a = 0; a < P; a++) {
+            const double qa = (double)qv[a / U][a % U];
 #pragma unroll
-                for (int b = 0; b < P; b++) acc[b] += qa * c[a * P + b];
-            }
+            for (int b = 0; b < P; b++) acc[b] += qa * c[a * P + b];
         }
-        V16 *__restrict__ w = (V16 *)(W + r * P);
+    }
+    const GPtr<V16> w = (GPtr<V16>)(W + r * P);
 #pragma unroll
-        for (int u = 0; u < P / U; u++) {
-            V16 o;
-            if (sub) {
-                const V16 wv = w[u];
+    for (int u = 0; u < P / U; u++) {
+        V16 o;
+        if (sub) {
+            const V16 wv = w[u];
 #pragma unroll
-                for (int e = 0; e < U; e++) o[e] = (T)((double)wv[e] - acc[u * U + e]);
-            } else {
+            for (int e = 0; e < U; e++) o[e] = (T)((double)wv[e] - acc[u * U + e]);
+        } else {
 #pragma unroll
-                for (int e = 0; e < U; e++) o[e] = (T)acc[u * U + e];
-            }
-            w[u] = o;
+            for (int e = 0; e < U; e++) o[e] = (T)acc[u * U + e];
         }
+        w[u] = o;
     }
 }
 
@@ -396,12 +405,9 @@ __global__ __launch_bounds__(BS) void k_block_apply_r(int64_t n, int nm, const T
                                                       int64_t qstride, const double *__restrict__ C,
                                                       T *__restrict__ W, int sub) {
     static_assert(P * sizeof(T) % 16 == 0, "row of P values must be whole 16-byte units");
-    extern __shared__ double sC[];
-    for (int e = threadIdx.x; e < nm * P * P; e += BS) sC[e] = C[e];
-    __syncthreads();
     for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < n;
          r += (int64_t)gridDim.x * BS)
-        block_apply_row<T, P>(r, nm, Q0, qstride, sC, W, sub);
+        block_apply_row<T, P>(r, nm, Q0, qstride, C, W, sub);
 }
 
 // W (-)= sum_m Q_m C_m for nm blocks (C on the device), one launch; block m
@@ -412,8 +418,8 @@ static void launch_block_apply(int64_t n, int nm, const T *Q0, int64_t qstride, 
     const size_t lds = (size_t)nm * P * P * sizeof(double);
     if constexpr (P * sizeof(T) % 16 == 0) {
         const unsigned nb = (unsigned)std::min<int64_t>(gridn(n, BS), 8192);
-        hipLaunchKernelGGL((k_block_apply_r<T, P>), dim3(nb), dim3(BS), lds, s, n, nm, Q0,
-                           qstride, C, W, sub ? 1 : 0);
+        hipLaunchKernelGGL((k_block_apply_r<T, P>), dim3(nb), dim3(BS), 0, s, n, nm, Q0, qstride,
+                           C, W, sub ? 1 : 0);
     } else {
         const unsigned nb = (unsigned)std::min<int64_t>(gridn(n, BS / P), 4096);
         hipLaunchKernelGGL((k_block_apply<T, P>), dim3(nb), dim3(BS), lds, s, n, nm, Q0,
@@ -1369,16 +1375,13 @@ template <typename T, int P>
 __global__ __launch_bounds__(BS) void k_mr_apply(const MRun *__restrict__ R, int nrun, int nm,
                                                  int qkind, int qslot, int qstep, int ckind,
                                                  int64_t coff, int dkind, int dslot, int sub) {
-    extern __shared__ double sC[];
     const int64_t u = blockIdx.x;
     const MRun &r = R[mr_find(R, nrun, u, 2)];
     const double *__restrict__ C = (ckind == 0 ? r.dT : r.dG) + coff;
-    for (int e = threadIdx.x; e < nm * P * P; e += BS) sC[e] = C[e];
-    __syncthreads();
     const int64_t row = (u - r.row0) * BS + threadIdx.x;
     if (row < r.n)
-        block_apply_row<T, P>(row, nm, mr_buf<T>(r, qkind, qslot, P), (int64_t)qstep * r.n * P,
-                              sC, mr_buf<T>(r, dkind, dslot, P), sub);
+        block_apply_row<T, P>(row, nm, mr_buf<T>(r, qkind, qslot, P), (int64_t)qstep * r.n * P, C,
+                              mr_buf<T>(r, dkind, dslot, P), sub);
 }
 
 template <int P>
@@ -1512,15 +1515,12 @@ struct MRTable {
     }
     int apply(int nm, int qkind, int qslot, int ckind, int64_t coff, int dkind, int dslot,
               bool sub, int qstep = 1) {
-        const size_t lds = (size_t)nm * P * P * sizeof(double);
         if (P == 8)
-            hipLaunchKernelGGL((k_mr_apply<T, 8>), dim3((unsigned)rowt), dim3(BS), lds, s, dev,
-                               nrun, nm, qkind, qslot, qstep, ckind, coff, dkind, dslot,
-                               sub ? 1 : 0);
+            hipLaunchKernelGGL((k_mr_apply<T, 8>), dim3((unsigned)rowt), dim3(BS), 0, s, dev, nrun,
+                               nm, qkind, qslot, qstep, ckind, coff, dkind, dslot, sub ? 1 : 0);
         else
-            hipLaunchKernelGGL((k_mr_apply<T, 16>), dim3((unsigned)rowt), dim3(BS), lds, s, dev,
-                               nrun, nm, qkind, qslot, qstep, ckind, coff, dkind, dslot,
-                               sub ? 1 : 0);
+            hipLaunchKernelGGL((k_mr_apply<T, 16>), dim3((unsigned)rowt), dim3(BS), 0, s, dev, nrun,
+                               nm, qkind, qslot, qstep, ckind, coff, dkind, dslot, sub ? 1 : 0);
         MCD_HIP(hipGetLastError());
         return MCD_OK;
     }
