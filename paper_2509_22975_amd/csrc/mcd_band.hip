@@ -233,6 +233,7 @@ __device__ __forceinline__ void gram_rt_unit(int64_t n, int64_t chunk_rows, int 
     const int qq = t % TPR;
     const int64_t r0 = (int64_t)chunk * chunk_rows;
     const int64_t r1 = min(r0 + chunk_rows, n);
+    const GPtr<const T> Qg = (GPtr<const T>)Q, Xg = (GPtr<const T>)X;
     double v[NV];
 #pragma unroll
     for (int i = 0; i < NV; i++) v[i] = 0.0;
@@ -240,9 +241,9 @@ __device__ __forceinline__ void gram_rt_unit(int64_t n, int64_t chunk_rows, int 
     for (int64_t r = r0 + t / TPR; r < r1; r += RPB) {
         T qa[NA], xb[P];
 #pragma unroll
-        for (int i = 0; i < NA; i++) qa[i] = Q[r * P + qq * NA + i];
+        for (int i = 0; i < NA; i++) qa[i] = Qg[r * P + qq * NA + i];
 #pragma unroll
-        for (int b = 0; b < P; b++) xb[b] = X[r * P + b];
+        for (int b = 0; b < P; b++) xb[b] = Xg[r * P + b];
 #pragma unroll
         for (int i = 0; i < NA; i++)
 #pragma unroll
@@ -274,8 +275,9 @@ __device__ __forceinline__ void gram_rt_unit(int64_t n, int64_t chunk_rows, int 
         for (int j = 0; j < 4; j++) red[w][64 * (lane & 3) + (lane & ~3) + j] = v[j];
     }
     __syncthreads();
+    const GPtr<double> pg = (GPtr<double>)part;
     for (int e = t; e < PP; e += 256)
-        part[((int64_t)m * nch + chunk) * PP + e] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+        pg[((int64_t)m * nch + chunk) * PP + e] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
 }
 
 template <typename T, int P, int TPR>
@@ -356,8 +358,6 @@ __global__ __launch_bounds__(BS) void k_block_apply(int64_t n, int nm, const T *
 // the same for the whole workgroup) through the constant address space, so
 // they arrive by scalar loads and feed the multiply-adds from scalar
 // registers (no LDS copy, no per-lane loads).
-template <typename T>
-using GPtr = __attribute__((address_space(1))) T *;
 template <typename T, int P>
 __device__ __forceinline__ void block_apply_row(int64_t r, int nm, const T *Q0p, int64_t qstride,
                                                 const double *__restrict__ C, T *Wp, int sub) {

@@ -80,6 +80,12 @@ constexpr int kGroupedRows = 256;
 constexpr int kGroupedMaxGroups = 128;
 constexpr int kNumXcd = 8;                   // gfx950: workgroups are dealt round-robin to 8 XCDs
 
+// A pointer into global memory as such: loads and stores through it are
+// global ones even where the pointer came from memory (a run table) and the
+// compiler would otherwise use flat accesses, which wait together with LDS.
+template <typename T>
+using GPtr = __attribute__((address_space(1))) T *;
+
 // One hopping bond with i < j, prepared for bit arithmetic.
 struct DevBond {
     uint32_t mask;      // (1 << i) | (1 << j)

@@ -23,22 +23,6 @@ struct Vec16<double> {
     using type = double2;
     static constexpr int n = 2;
 };
-__device__ __forceinline__ float4 vscale(float a, const float4 &x) {
-    return make_float4(a * x.x, a * x.y, a * x.z, a * x.w);
-}
-__device__ __forceinline__ double2 vscale(double a, const double2 &x) {
-    return make_double2(a * x.x, a * x.y);
-}
-__device__ __forceinline__ void vscale_add(float4 &acc, float a, const float4 &x) {
-    acc.x += a * x.x;
-    acc.y += a * x.y;
-    acc.z += a * x.z;
-    acc.w += a * x.w;
-}
-__device__ __forceinline__ void vscale_add(double2 &acc, double a, const double2 &x) {
-    acc.x += a * x.x;
-    acc.y += a * x.y;
-}
 
 // Words per chunk of the block product with L lanes per row (measured on
 // gfx950, C2 basis, 8 and 16 vectors): at most 8 gathers in flight per lane
@@ -81,7 +65,9 @@ __device__ __forceinline__ void block_csr_v_tile(const int64_t *__restrict__ row
                                                  const double *__restrict__ diag,
                                                  const T *__restrict__ x, T *__restrict__ y,
                                                  int64_t rbeg, int64_t rend) {
-    using V = typename Vec16<T>::type;
+    // 16 bytes of a row as a clang vector (loads and stores through global
+    // pointers; element-wise arithmetic)
+    using V = T __attribute__((ext_vector_type(Vec16<T>::n)));
     constexpr int L = NV / Vec16<T>::n;
     static_assert(L >= 1 && L * Vec16<T>::n == NV, "NV must be a multiple of the vector width");
     constexpr int DEPTH = WMAX / 256;
@@ -89,29 +75,35 @@ __device__ __forceinline__ void block_csr_v_tile(const int64_t *__restrict__ row
     __shared__ T vtab[kMaxClasses];
     __shared__ uint32_t wl[WMAX];
     const int t = threadIdx.x, lane = t % L;
-    const V *__restrict__ xv4 = reinterpret_cast<const V *>(x);
-    V *__restrict__ yv4 = reinterpret_cast<V *>(y);
+    // every load and store as a global one (the many-run kernel passes
+    // pointers read from its run table)
+    const GPtr<const V> xv4 = (GPtr<const V>)x;
+    const GPtr<V> yv4 = (GPtr<V>)y;
+    const GPtr<const int64_t> rp = (GPtr<const int64_t>)rowptr;
+    const GPtr<const uint32_t> cw = (GPtr<const uint32_t>)colw;
+    const GPtr<const double> dg = (GPtr<const double>)diag;
+    const GPtr<const DevModel> mg = (GPtr<const DevModel>)m;
     const int64_t r = rbeg + t / L;
     const bool own = r < rend;
     const int64_t rr = own ? r : rend - 1;
-    const int64_t e0 = rowptr[rbeg], eT = rowptr[rend];
-    const int64_t b0 = rowptr[rr], e1 = rowptr[rr + 1];
-    const T d = (T)diag[rr];
+    const int64_t e0 = rp[rbeg], eT = rp[rend];
+    const int64_t b0 = rp[rr], e1 = rp[rr + 1];
+    const T d = (T)dg[rr];
     const V xr = xv4[rr * L + lane];
-    if (t < kMaxClasses) vtab[t] = (T)m->vtab[t];
-    const uint32_t cmask = m->col_mask, cbits = m->col_bits;
+    if (t < kMaxClasses) vtab[t] = (T)mg->vtab[t];
+    const uint32_t cmask = mg->col_mask, cbits = mg->col_bits;
     const int cnt = (int)(eT - e0);
     if (cnt > 0) {   // uniform over the workgroup
         uint32_t w[DEPTH];
 #pragma unroll
-        for (int j = 0; j < DEPTH; j++) w[j] = colw[e0 + min(t + j * 256, cnt - 1)];
+        for (int j = 0; j < DEPTH; j++) w[j] = cw[e0 + min(t + j * 256, cnt - 1)];
 #pragma unroll
         for (int j = 0; j < DEPTH; j++)
             if (t + j * 256 < cnt) wl[t + j * 256] = w[j];
     }
     __syncthreads();
     if (!own) return;
-    V acc = vscale(d, xr);
+    V acc = d * xr;
     const int s1 = (int)(e1 - e0);
     for (int base = (int)(b0 - e0); base < s1; base += CH) {
         uint32_t wj[CH];
@@ -119,13 +111,15 @@ __device__ __forceinline__ void block_csr_v_tile(const int64_t *__restrict__ row
 #pragma unroll
         for (int j = 0; j < CH; j++) wj[j] = base + j < s1 ? wl[base + j] : 0u;
 #pragma unroll
-        for (int j = 0; j < CH; j++)
-            xg[j] = (base + j < s1) ? xv4[(int64_t)(wj[j] & cmask) * L + lane] : V{};
+        for (int j = 0; j < CH; j++) {
+            xg[j] = V(0);
+            if (base + j < s1) xg[j] = xv4[(int64_t)(wj[j] & cmask) * L + lane];
+        }
 #pragma unroll
         for (int j = 0; j < CH; j++) {
             if (base + j < s1) {
                 const T v = vtab[(wj[j] & 0x7fffffffu) >> cbits];
-                vscale_add(acc, (wj[j] >> 31) ? -v : v, xg[j]);
+                acc += ((wj[j] >> 31) ? -v : v) * xg[j];
             }
         }
     }
