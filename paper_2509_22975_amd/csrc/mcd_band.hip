@@ -207,11 +207,58 @@ __device__ __forceinline__ void halve_sum(double *v, int lane) {
     }
 }
 
-// Partial Gram matrices for P = 8 and 16, register-tiled: TPR threads share
-// a row and each owns P^2 / TPR of its products (rows a in [NA qq, NA qq +
-// NA), NA = P / TPR, all b): P = 8 in float32, TPR = 1 (64 products); P = 8
-// in float64, TPR = 2 (32 products: half the registers, twice the waves of
-// the one-thread form); P = 16, TPR = 4 (64).  A thread reads its rows
+// P = 16: the chunk's partial Gram matrix on the float64 matrix cores.  One
+// v_mfma_f64_16x16x4f64 adds the products of four rows: lane l supplies
+// A[i][k] = Q[g + k][i] and B[k][j] = X[g + k][j] with i = j = l % 16, k =
+// l / 16 (so a wavefront's two operand loads are the four rows' contiguous
+// values of Q and of X), and holds D[l / 16 + 4 e][l % 16], e < 4, of the
+// running 16 x 16 sum (this result layout checked on gfx950).  Wavefront w takes the row groups g = r0 + 4 w + 16 i
+// of the chunk, U groups' loads in flight before their U products (rows
+// past the chunk's end enter as zeros); the four wavefronts' sums are added
+// in LDS in a fixed order.  Float64 accumulation (inputs converted exactly),
+// deterministic; 16 accumulators per lane instead of the 64 a register tile
+// of 64 products per thread needs, so eight wavefronts per SIMD instead of
+// two.
+template <typename T>
+__device__ __forceinline__ void gram16_mfma_unit(int64_t n, int64_t chunk_rows, int nch,
+                                                 const T *__restrict__ Q, const T *__restrict__ X,
+                                                 double *__restrict__ part, int m, int chunk) {
+    using D4 = double __attribute__((ext_vector_type(4)));
+    constexpr int U = 8;
+    __shared__ double red[4][256];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int col = lane & 15, k = lane >> 4;
+    const int64_t r0 = (int64_t)chunk * chunk_rows;
+    const int64_t r1 = min(r0 + chunk_rows, n);
+    const GPtr<const T> Qg = (GPtr<const T>)Q, Xg = (GPtr<const T>)X;
+    D4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t g = r0 + 4 * w; g < r1; g += 16 * U) {   // uniform over the wavefront
+        double a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t r = g + 16 * u + k;
+            const int64_t rc = min(r, r1 - 1);
+            const T qv = Qg[rc * 16 + col], xv = Xg[rc * 16 + col];
+            a[u] = r < r1 ? (double)qv : 0.0;
+            b[u] = r < r1 ? (double)xv : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; e++) red[w][(k + 4 * e) * 16 + col] = acc[e];
+    __syncthreads();
+    const GPtr<double> pg = (GPtr<double>)part;
+    pg[((int64_t)m * nch + chunk) * 256 + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+}
+
+// Partial Gram matrices for P = 8 and 16.  P = 8 is register-tiled: TPR
+// threads share a row and each owns P^2 / TPR of its products (rows a in
+// [NA qq, NA qq + NA), NA = P / TPR, all b): float32, TPR = 1 (64 products);
+// float64, TPR = 2 (32 products: half the registers, twice the waves of the
+// one-thread form).  P = 16 (TPR = 4: 64 rows per pass in the chunk sizing)
+// takes the matrix-core form above.  A thread reads its rows
 // straight from memory (coalesced, no LDS staging, no barriers in the row
 // loop) and accumulates in float64; the sums are reduced over the lanes of
 // equal qq by recursive halving and over the four wavefronts in LDS, in a
@@ -222,11 +269,10 @@ __device__ __forceinline__ void halve_sum(double *v, int lane) {
 // The work of one workgroup (block m, row chunk `chunk`); every thread of
 // the workgroup calls it.
 template <typename T, int P, int TPR>
-__device__ __forceinline__ void gram_rt_unit(int64_t n, int64_t chunk_rows, int nch,
-                                             const T *__restrict__ Q, const T *__restrict__ X,
-                                             double *__restrict__ part, int m, int chunk) {
-    static_assert((P == 8 && (TPR == 1 || TPR == 2)) || (P == 16 && TPR == 4),
-                  "register-tiled Gram for P = 8, 16");
+__device__ __forceinline__ void gram8_rt_unit(int64_t n, int64_t chunk_rows, int nch,
+                                              const T *__restrict__ Q, const T *__restrict__ X,
+                                              double *__restrict__ part, int m, int chunk) {
+    static_assert(P == 8 && (TPR == 1 || TPR == 2), "register-tiled Gram for P = 8");
     constexpr int PP = P * P, NA = P / TPR, NV = NA * P, RPB = 256 / TPR;
     __shared__ double red[4][PP];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -265,19 +311,23 @@ __device__ __forceinline__ void gram_rt_unit(int64_t n, int64_t chunk_rows, int 
         halve_sum<1, 2>(v, lane);
         // lane l holds value (l >> 1) of its half qq = l & 1
         red[w][32 * (lane & 1) + (lane >> 1)] = v[0];
-    } else {
-        halve_sum<32, 32>(v, lane);
-        halve_sum<16, 16>(v, lane);
-        halve_sum<8, 8>(v, lane);
-        halve_sum<4, 4>(v, lane);
-        // lane l holds values (l & ~3) + j of its quarter qq = l & 3
-#pragma unroll
-        for (int j = 0; j < 4; j++) red[w][64 * (lane & 3) + (lane & ~3) + j] = v[j];
     }
     __syncthreads();
     const GPtr<double> pg = (GPtr<double>)part;
     for (int e = t; e < PP; e += 256)
         pg[((int64_t)m * nch + chunk) * PP + e] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+}
+
+template <typename T, int P, int TPR>
+__device__ __forceinline__ void gram_rt_unit(int64_t n, int64_t chunk_rows, int nch,
+                                             const T *__restrict__ Q, const T *__restrict__ X,
+                                             double *__restrict__ part, int m, int chunk) {
+    static_assert((P == 8 && (TPR == 1 || TPR == 2)) || (P == 16 && TPR == 4),
+                  "partial Gram for P = 8, 16");
+    if constexpr (P == 16)
+        gram16_mfma_unit<T>(n, chunk_rows, nch, Q, X, part, m, chunk);
+    else
+        gram8_rt_unit<T, P, TPR>(n, chunk_rows, nch, Q, X, part, m, chunk);
 }
 
 template <typename T, int P, int TPR>
