@@ -191,22 +191,6 @@ __global__ __launch_bounds__(BS) void k_gram(int64_t n, int64_t chunk_rows, int 
     }
 }
 
-// One step of a recursive-halving sum over the lanes of a wavefront: lanes
-// with bit O set keep the upper H of their values, the others the lower H,
-// each adds its partner's copy of the half it keeps.  After the steps
-// O = 32, 16, ..., lane l holds the wavefront sums of the values whose index
-// bits match its lane bits (a reduce-scatter in 63 shuffles for 64 values).
-template <int H, int O>
-__device__ __forceinline__ void halve_sum(double *v, int lane) {
-    const bool up = (lane & O) != 0;
-#pragma unroll
-    for (int i = 0; i < H; i++) {
-        const double mine = up ? v[i + H] : v[i];
-        const double other = up ? v[i] : v[i + H];
-        v[i] = mine + __shfl_xor(other, O, 64);
-    }
-}
-
 // P = 16: the chunk's partial Gram matrix on the float64 matrix cores.  One
 // v_mfma_f64_16x16x4f64 adds the products of four rows: lane l supplies
 // A[i][k] = Q[g + k][i] and B[k][j] = X[g + k][j] with i = j = l % 16, k =
@@ -253,91 +237,81 @@ __device__ __forceinline__ void gram16_mfma_unit(int64_t n, int64_t chunk_rows, 
     pg[((int64_t)m * nch + chunk) * 256 + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
 }
 
-// Partial Gram matrices for P = 8 and 16.  P = 8 is register-tiled: TPR
-// threads share a row and each owns P^2 / TPR of its products (rows a in
-// [NA qq, NA qq + NA), NA = P / TPR, all b): float32, TPR = 1 (64 products);
-// float64, TPR = 2 (32 products: half the registers, twice the waves of the
-// one-thread form).  P = 16 (TPR = 4: 64 rows per pass in the chunk sizing)
-// takes the matrix-core form above.  A thread reads its rows
-// straight from memory (coalesced, no LDS staging, no barriers in the row
-// loop) and accumulates in float64; the sums are reduced over the lanes of
-// equal qq by recursive halving and over the four wavefronts in LDS, in a
-// fixed order.  partial[(m * nch + chunk)][a][b] as for k_gram.  One
+// P = 8 on the same instruction, two rows per row of its operands: lane l
+// supplies A[i][k] = Q[g + 2 k + h][i % 8] and B[k][j] = X[g + 2 k + h'][j %
+// 8] with h = i / 8, h' = j / 8 (i = j = l % 16, k = l / 16), which is Q[g +
+// l / 8][l % 8]: a wavefront's operand loads are eight whole rows.  The two
+// diagonal 8 x 8 blocks of D (h = h') are the sums over the even and the
+// odd rows of the group; the others mix rows and are dropped.  Wavefront w
+// takes the row groups g = r0 + 8 w + 32 i; the halves and the four
+// wavefronts are added in LDS in a fixed order.
+template <typename T>
+__device__ __forceinline__ void gram8_mfma_unit(int64_t n, int64_t chunk_rows, int nch,
+                                                const T *__restrict__ Q, const T *__restrict__ X,
+                                                double *__restrict__ part, int m, int chunk) {
+    using D4 = double __attribute__((ext_vector_type(4)));
+    constexpr int U = 8;
+    __shared__ double red[4][2][64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t r0 = (int64_t)chunk * chunk_rows;
+    const int64_t r1 = min(r0 + chunk_rows, n);
+    const GPtr<const T> Qg = (GPtr<const T>)Q, Xg = (GPtr<const T>)X;
+    D4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t g = r0 + 8 * w; g < r1; g += 32 * U) {   // uniform over the wavefront
+        double a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t r = g + 32 * u + (lane >> 3);
+            const int64_t rc = min(r, r1 - 1);
+            const T qv = Qg[rc * 8 + (lane & 7)], xv = Xg[rc * 8 + (lane & 7)];
+            a[u] = r < r1 ? (double)qv : 0.0;
+            b[u] = r < r1 ? (double)xv : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+    }
+    // lane l holds D[l / 16 + 4 e][l % 16]: rows < 8 for e < 2, so columns
+    // < 8 keep e = 0, 1 (even rows) and columns >= 8 keep e = 2, 3 (odd rows)
+    const int j = lane & 15, hh = j >> 3, b8 = j & 7;
+#pragma unroll
+    for (int e = 0; e < 2; e++)
+        red[w][hh][((lane >> 4) + 4 * e) * 8 + b8] = acc[2 * hh + e];
+    __syncthreads();
+    if (t < 64) {
+        const GPtr<double> pg = (GPtr<double>)part;
+        pg[((int64_t)m * nch + chunk) * 64 + t] =
+            ((red[0][0][t] + red[0][1][t]) + (red[1][0][t] + red[1][1][t])) +
+            ((red[2][0][t] + red[2][1][t]) + (red[3][0][t] + red[3][1][t]));
+    }
+}
+
+// Partial Gram matrices Q_m^T X for P = 8 and 16 on the matrix cores (the
+// two forms above): partial[(m * nch + chunk)][a][b] as for k_gram.  One
 // dimension of 8 ceil(nch / 8) nm workgroups, handed out XCD-major: the nm
 // workgroups of one row chunk (one per block m) run on one XCD, so that the
 // chunk's X rows are fetched once into its L2 instead of once per block.
 // The work of one workgroup (block m, row chunk `chunk`); every thread of
 // the workgroup calls it.
-template <typename T, int P, int TPR>
-__device__ __forceinline__ void gram8_rt_unit(int64_t n, int64_t chunk_rows, int nch,
-                                              const T *__restrict__ Q, const T *__restrict__ X,
-                                              double *__restrict__ part, int m, int chunk) {
-    static_assert(P == 8 && (TPR == 1 || TPR == 2), "register-tiled Gram for P = 8");
-    constexpr int PP = P * P, NA = P / TPR, NV = NA * P, RPB = 256 / TPR;
-    __shared__ double red[4][PP];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int qq = t % TPR;
-    const int64_t r0 = (int64_t)chunk * chunk_rows;
-    const int64_t r1 = min(r0 + chunk_rows, n);
-    const GPtr<const T> Qg = (GPtr<const T>)Q, Xg = (GPtr<const T>)X;
-    double v[NV];
-#pragma unroll
-    for (int i = 0; i < NV; i++) v[i] = 0.0;
-#pragma unroll 2
-    for (int64_t r = r0 + t / TPR; r < r1; r += RPB) {
-        T qa[NA], xb[P];
-#pragma unroll
-        for (int i = 0; i < NA; i++) qa[i] = Qg[r * P + qq * NA + i];
-#pragma unroll
-        for (int b = 0; b < P; b++) xb[b] = Xg[r * P + b];
-#pragma unroll
-        for (int i = 0; i < NA; i++)
-#pragma unroll
-            for (int b = 0; b < P; b++) v[i * P + b] += (double)qa[i] * (double)xb[b];
-    }
-    if constexpr (TPR == 1) {
-        halve_sum<32, 32>(v, lane);
-        halve_sum<16, 16>(v, lane);
-        halve_sum<8, 8>(v, lane);
-        halve_sum<4, 4>(v, lane);
-        halve_sum<2, 2>(v, lane);
-        halve_sum<1, 1>(v, lane);
-        red[w][lane] = v[0];   // value index = lane
-    } else if constexpr (TPR == 2) {
-        halve_sum<16, 32>(v, lane);
-        halve_sum<8, 16>(v, lane);
-        halve_sum<4, 8>(v, lane);
-        halve_sum<2, 4>(v, lane);
-        halve_sum<1, 2>(v, lane);
-        // lane l holds value (l >> 1) of its half qq = l & 1
-        red[w][32 * (lane & 1) + (lane >> 1)] = v[0];
-    }
-    __syncthreads();
-    const GPtr<double> pg = (GPtr<double>)part;
-    for (int e = t; e < PP; e += 256)
-        pg[((int64_t)m * nch + chunk) * PP + e] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
-}
-
-template <typename T, int P, int TPR>
+template <typename T, int P>
 __device__ __forceinline__ void gram_rt_unit(int64_t n, int64_t chunk_rows, int nch,
                                              const T *__restrict__ Q, const T *__restrict__ X,
                                              double *__restrict__ part, int m, int chunk) {
-    static_assert((P == 8 && (TPR == 1 || TPR == 2)) || (P == 16 && TPR == 4),
-                  "partial Gram for P = 8, 16");
+    static_assert(P == 8 || P == 16, "partial Gram for P = 8, 16");
     if constexpr (P == 16)
         gram16_mfma_unit<T>(n, chunk_rows, nch, Q, X, part, m, chunk);
     else
-        gram8_rt_unit<T, P, TPR>(n, chunk_rows, nch, Q, X, part, m, chunk);
+        gram8_mfma_unit<T>(n, chunk_rows, nch, Q, X, part, m, chunk);
 }
 
-template <typename T, int P, int TPR>
+template <typename T, int P>
 __global__ __launch_bounds__(256) void k_gram_rt(int64_t n, int64_t chunk_rows, int nch, int nm,
                                                  const T *__restrict__ Q0, int64_t qstride,
                                                  const T *__restrict__ X,
                                                  double *__restrict__ part) {
     const int k = blockIdx.x / 8, m = k % nm, chunk = (k / nm) * 8 + blockIdx.x % 8;
     if (chunk >= nch) return;   // whole workgroup, before any barrier
-    gram_rt_unit<T, P, TPR>(n, chunk_rows, nch, Q0 + (int64_t)m * qstride, X, part, m, chunk);
+    gram_rt_unit<T, P>(n, chunk_rows, nch, Q0 + (int64_t)m * qstride, X, part, m, chunk);
 }
 
 // out[m][e] = sum_c part[(m nch + c)][e]: one wavefront per output entry,
@@ -989,9 +963,10 @@ struct BandRun {
     }
 
     // Gram row chunks of the run: a function of (n, P, T) only, so a run
-    // gives the same sums whichever runs share its launches.  Register-tiled
-    // kernel (P >= 8): >= 8 rows per thread slot and at most 1024 chunks; LDS
-    // kernel (P < 8): at least 256 rows per chunk, at most 2048 chunks.
+    // gives the same sums whichever runs share its launches.  Matrix-core
+    // kernels (P >= 8): at least 8 rpb rows per chunk (rpb = 256, 128 or 64
+    // for float32 P = 8, float64 P = 8 and P = 16) and at most 1024 chunks;
+    // LDS kernel (P < 8): at least 256 rows per chunk, at most 2048 chunks.
     void set_chunks() {
         int64_t c;
         if (P >= 8) {
@@ -1060,20 +1035,14 @@ struct BandRun {
         hipLaunchKernelGGL((k_gram<T, PV>), grid, dim3(BS), 0, s, n, chunk_rows, nch, Q0, \
                            (int64_t)n * P, X, part);                                     \
         break;
-#define GRT(PV, TV)                                                                          \
-    hipLaunchKernelGGL((k_gram_rt<T, PV, TV>), dim3((unsigned)((nch + 7) / 8 * 8 * nm)),      \
-                       dim3(256), 0, s, n, chunk_rows, nch, nm, Q0, (int64_t)n * P, X, part)
+#define GRT(PV)                                                                              \
+    case PV:                                                                                 \
+        hipLaunchKernelGGL((k_gram_rt<T, PV>), dim3((unsigned)((nch + 7) / 8 * 8 * nm)),      \
+                           dim3(256), 0, s, n, chunk_rows, nch, nm, Q0, (int64_t)n * P, X,   \
+                           part);                                                            \
+        break;
         switch (P) {
-            GR(1) GR(2) GR(4)
-        case 8:
-            if (sizeof(T) == 8)
-                GRT(8, 2);
-            else
-                GRT(8, 1);
-            break;
-        case 16:
-            GRT(16, 4);
-            break;
+            GR(1) GR(2) GR(4) GRT(8) GRT(16)
         }
 #undef GR
 #undef GRT
@@ -1389,7 +1358,7 @@ __global__ __launch_bounds__(256) void k_mr_spmm(const MRun *__restrict__ R, int
                                       (T *)r.W, rbeg, min(rbeg + (int64_t)rpt, r.n));
 }
 
-template <typename T, int P, int TPR>
+template <typename T, int P>
 __global__ __launch_bounds__(256) void k_mr_gram(const MRun *__restrict__ R, int nrun, int nm,
                                                  int qkind, int qslot, int xkind) {
     const int64_t u = blockIdx.x;
@@ -1397,7 +1366,7 @@ __global__ __launch_bounds__(256) void k_mr_gram(const MRun *__restrict__ R, int
     const int64_t v = u - r.chunk0 * nm;
     const int k = (int)(v / 8), m = k % nm, chunk = (k / nm) * 8 + (int)(v % 8);
     if (chunk >= r.nch) return;   // whole workgroup, before any barrier
-    gram_rt_unit<T, P, TPR>(r.n, r.chunk_rows, r.nch, mr_buf<T>(r, qkind, qslot, P) +
+    gram_rt_unit<T, P>(r.n, r.chunk_rows, r.nch, mr_buf<T>(r, qkind, qslot, P) +
                             (int64_t)m * r.n * P, mr_buf<T>(r, xkind, 0, P), r.part, m, chunk);
 }
 
@@ -1545,17 +1514,12 @@ struct MRTable {
     }
     int gram(int nm, int qkind, int qslot, int xkind) {
         const unsigned g = (unsigned)(chunks * nm);
-        if (P == 8) {
-            if (sizeof(T) == 8)
-                hipLaunchKernelGGL((k_mr_gram<T, 8, 2>), dim3(g), dim3(256), 0, s, dev, nrun, nm,
-                                   qkind, qslot, xkind);
-            else
-                hipLaunchKernelGGL((k_mr_gram<T, 8, 1>), dim3(g), dim3(256), 0, s, dev, nrun, nm,
-                                   qkind, qslot, xkind);
-        } else {
-            hipLaunchKernelGGL((k_mr_gram<T, 16, 4>), dim3(g), dim3(256), 0, s, dev, nrun, nm,
-                               qkind, qslot, xkind);
-        }
+        if (P == 8)
+            hipLaunchKernelGGL((k_mr_gram<T, 8>), dim3(g), dim3(256), 0, s, dev, nrun, nm, qkind,
+                               qslot, xkind);
+        else
+            hipLaunchKernelGGL((k_mr_gram<T, 16>), dim3(g), dim3(256), 0, s, dev, nrun, nm, qkind,
+                               qslot, xkind);
         MCD_HIP(hipGetLastError());
         const int64_t waves = (int64_t)nrun * nm * P * P;
         hipLaunchKernelGGL(k_mr_gram_reduce, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
