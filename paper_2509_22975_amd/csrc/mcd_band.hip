@@ -191,127 +191,123 @@ __global__ __launch_bounds__(BS) void k_gram(int64_t n, int64_t chunk_rows, int 
     }
 }
 
-// P = 16: the chunk's partial Gram matrix on the float64 matrix cores.  One
-// v_mfma_f64_16x16x4f64 adds the products of four rows: lane l supplies
-// A[i][k] = Q[g + k][i] and B[k][j] = X[g + k][j] with i = j = l % 16, k =
-// l / 16 (so a wavefront's two operand loads are the four rows' contiguous
-// values of Q and of X), and holds D[l / 16 + 4 e][l % 16], e < 4, of the
-// running 16 x 16 sum (this result layout checked on gfx950).  Wavefront w takes the row groups g = r0 + 4 w + 16 i
-// of the chunk, U groups' loads in flight before their U products (rows
-// past the chunk's end enter as zeros); the four wavefronts' sums are added
-// in LDS in a fixed order.  Float64 accumulation (inputs converted exactly),
-// deterministic; 16 accumulators per lane instead of the 64 a register tile
-// of 64 products per thread needs, so eight wavefronts per SIMD instead of
-// two.
+// Partial Gram matrices Q_m^T X (P = 8, 16) of one row chunk for the blocks
+// m in [m0, m0 + mc), mc <= gram_blocks<T>(), on the float64 matrix cores.  One
+// v_mfma_f64_16x16x4f64 takes A (16 x 4) and B (4 x 16) from one double per
+// lane -- lane l gives A[l % 16][l / 16] and B[l / 16][l % 16] -- and lane l
+// holds D[l / 16 + 4 e][l % 16], e < 4, of the running 16 x 16 sum (this
+// result layout checked on gfx950).  Lane l loads value l of 64 consecutive
+// values of Q_m and of X, i.e. row g + l / P, column l % P, of the 64 / P
+// rows from g on:
+//   P = 16: A[i][k] = Q[g + k][i], B[k][j] = X[g + k][j]: D = the four
+//   rows' Q^T X;
+//   P = 8: two rows per operand row, A[8 h + a][k] = Q[g + 2 k + h][a] and
+//   likewise B: the diagonal 8 x 8 blocks of D (h = h') are the sums over
+//   the group's even and odd rows, the rest mixes rows and is dropped.
+// Wavefront w takes the row groups g = r0 + (64 / P) (w + 4 i), U groups at a
+// time: the X rows are loaded once for all mc blocks, then each block's Q
+// rows, then the products (rows past the chunk's end enter as zeros).  Each
+// block's sums are added over the wavefronts (and the two halves at P = 8)
+// in LDS in a fixed order and stored at partial[(m * nch + chunk)][a][b] as
+// for k_gram.  Float64 accumulation (inputs converted exactly), in the same
+// order whatever mc and U are, so deterministic and independent of how blocks
+// are grouped.  Blocks per workgroup: 4 for float64 blocks (X loaded once for
+// four blocks, U = 4: C3 Grams with two reorthogonalisation passes 1.03 ->
+// 0.93 s), 1 for float32 (U = 8: 42-52 VGPRs and 8 wavefronts per SIMD; four
+// blocks at 110 VGPRs were 3% slower there).
 template <typename T>
-__device__ __forceinline__ void gram16_mfma_unit(int64_t n, int64_t chunk_rows, int nch,
-                                                 const T *__restrict__ Q, const T *__restrict__ X,
-                                                 double *__restrict__ part, int m, int chunk) {
+__host__ __device__ constexpr int gram_blocks() {
+    return sizeof(T) == 8 ? 4 : 1;
+}
+
+template <typename T, int P>
+__device__ __forceinline__ void gram_mfma_unit(int64_t n, int64_t chunk_rows, int nch,
+                                               const T *__restrict__ Q0, int64_t qstride, int m0,
+                                               int mc, const T *__restrict__ X,
+                                               double *__restrict__ part, int chunk) {
+    static_assert(P == 8 || P == 16, "matrix-core Gram for P = 8, 16");
     using D4 = double __attribute__((ext_vector_type(4)));
-    constexpr int U = 8;
+    constexpr int MB = gram_blocks<T>(), U = MB == 1 ? 8 : 4, RG = 64 / P, PP = P * P;
     __shared__ double red[4][256];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int col = lane & 15, k = lane >> 4;
+    const int lr = lane / P, lc = lane % P;
     const int64_t r0 = (int64_t)chunk * chunk_rows;
     const int64_t r1 = min(r0 + chunk_rows, n);
-    const GPtr<const T> Qg = (GPtr<const T>)Q, Xg = (GPtr<const T>)X;
-    D4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t g = r0 + 4 * w; g < r1; g += 16 * U) {   // uniform over the wavefront
-        double a[U], b[U];
+    const GPtr<const T> Qg = (GPtr<const T>)Q0, Xg = (GPtr<const T>)X;
+    D4 acc[MB];
+#pragma unroll
+    for (int i = 0; i < MB; i++) acc[i] = D4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t g = r0 + RG * w; g < r1; g += 4 * RG * U) {   // uniform over the wavefront
+        double b[U], a[MB][U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const int64_t r = g + 16 * u + k;
-            const int64_t rc = min(r, r1 - 1);
-            const T qv = Qg[rc * 16 + col], xv = Xg[rc * 16 + col];
-            a[u] = r < r1 ? (double)qv : 0.0;
+            const int64_t r = g + 4 * RG * u + lr;
+            const T xv = Xg[min(r, r1 - 1) * P + lc];
             b[u] = r < r1 ? (double)xv : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < U; u++)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
-    }
+        for (int i = 0; i < MB; i++) {
+            if (i < mc) {   // uniform over the workgroup
+                const int64_t qo = (int64_t)(m0 + i) * qstride;
 #pragma unroll
-    for (int e = 0; e < 4; e++) red[w][(k + 4 * e) * 16 + col] = acc[e];
-    __syncthreads();
+                for (int u = 0; u < U; u++) {
+                    const int64_t r = g + 4 * RG * u + lr;
+                    const T qv = Qg[qo + min(r, r1 - 1) * P + lc];
+                    a[i][u] = r < r1 ? (double)qv : 0.0;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < MB; i++)
+            if (i < mc)
+#pragma unroll
+                for (int u = 0; u < U; u++)
+                    acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][u], b[u], acc[i], 0, 0, 0);
+    }
     const GPtr<double> pg = (GPtr<double>)part;
-    pg[((int64_t)m * nch + chunk) * 256 + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
-}
-
-// P = 8 on the same instruction, two rows per row of its operands: lane l
-// supplies A[i][k] = Q[g + 2 k + h][i % 8] and B[k][j] = X[g + 2 k + h'][j %
-// 8] with h = i / 8, h' = j / 8 (i = j = l % 16, k = l / 16), which is Q[g +
-// l / 8][l % 8]: a wavefront's operand loads are eight whole rows.  The two
-// diagonal 8 x 8 blocks of D (h = h') are the sums over the even and the
-// odd rows of the group; the others mix rows and are dropped.  Wavefront w
-// takes the row groups g = r0 + 8 w + 32 i; the halves and the four
-// wavefronts are added in LDS in a fixed order.
-template <typename T>
-__device__ __forceinline__ void gram8_mfma_unit(int64_t n, int64_t chunk_rows, int nch,
-                                                const T *__restrict__ Q, const T *__restrict__ X,
-                                                double *__restrict__ part, int m, int chunk) {
-    using D4 = double __attribute__((ext_vector_type(4)));
-    constexpr int U = 8;
-    __shared__ double red[4][2][64];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int64_t r0 = (int64_t)chunk * chunk_rows;
-    const int64_t r1 = min(r0 + chunk_rows, n);
-    const GPtr<const T> Qg = (GPtr<const T>)Q, Xg = (GPtr<const T>)X;
-    D4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t g = r0 + 8 * w; g < r1; g += 32 * U) {   // uniform over the wavefront
-        double a[U], b[U];
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int64_t r = g + 32 * u + (lane >> 3);
-            const int64_t rc = min(r, r1 - 1);
-            const T qv = Qg[rc * 8 + (lane & 7)], xv = Xg[rc * 8 + (lane & 7)];
-            a[u] = r < r1 ? (double)qv : 0.0;
-            b[u] = r < r1 ? (double)xv : 0.0;
+    for (int i = 0; i < MB; i++) {
+        if (i >= mc) break;   // uniform
+        if constexpr (P == 16) {
+#pragma unroll
+            for (int e = 0; e < 4; e++) red[w][((lane >> 4) + 4 * e) * 16 + (lane & 15)] = acc[i][e];
+        } else {
+            // rows < 8 for e < 2: columns < 8 keep e = 0, 1 (even rows),
+            // columns >= 8 keep e = 2, 3 (odd rows)
+            const int j = lane & 15, hh = j >> 3;
+#pragma unroll
+            for (int e = 0; e < 2; e++)
+                red[w][64 * hh + ((lane >> 4) + 4 * e) * 8 + (j & 7)] = acc[i][2 * hh + e];
         }
-#pragma unroll
-        for (int u = 0; u < U; u++)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
-    }
-    // lane l holds D[l / 16 + 4 e][l % 16]: rows < 8 for e < 2, so columns
-    // < 8 keep e = 0, 1 (even rows) and columns >= 8 keep e = 2, 3 (odd rows)
-    const int j = lane & 15, hh = j >> 3, b8 = j & 7;
-#pragma unroll
-    for (int e = 0; e < 2; e++)
-        red[w][hh][((lane >> 4) + 4 * e) * 8 + b8] = acc[2 * hh + e];
-    __syncthreads();
-    if (t < 64) {
-        const GPtr<double> pg = (GPtr<double>)part;
-        pg[((int64_t)m * nch + chunk) * 64 + t] =
-            ((red[0][0][t] + red[0][1][t]) + (red[1][0][t] + red[1][1][t])) +
-            ((red[2][0][t] + red[2][1][t]) + (red[3][0][t] + red[3][1][t]));
+        __syncthreads();
+        if (t < PP) {
+            double v;
+            if constexpr (P == 16)
+                v = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+            else
+                v = ((red[0][t] + red[0][64 + t]) + (red[1][t] + red[1][64 + t])) +
+                    ((red[2][t] + red[2][64 + t]) + (red[3][t] + red[3][64 + t]));
+            pg[((int64_t)(m0 + i) * nch + chunk) * PP + t] = v;
+        }
+        __syncthreads();
     }
 }
 
-// Partial Gram matrices Q_m^T X for P = 8 and 16 on the matrix cores (the
-// two forms above): partial[(m * nch + chunk)][a][b] as for k_gram.  One
-// dimension of 8 ceil(nch / 8) nm workgroups, handed out XCD-major: the nm
-// workgroups of one row chunk (one per block m) run on one XCD, so that the
-// chunk's X rows are fetched once into its L2 instead of once per block.
-// The work of one workgroup (block m, row chunk `chunk`); every thread of
-// the workgroup calls it.
-template <typename T, int P>
-__device__ __forceinline__ void gram_rt_unit(int64_t n, int64_t chunk_rows, int nch,
-                                             const T *__restrict__ Q, const T *__restrict__ X,
-                                             double *__restrict__ part, int m, int chunk) {
-    static_assert(P == 8 || P == 16, "partial Gram for P = 8, 16");
-    if constexpr (P == 16)
-        gram16_mfma_unit<T>(n, chunk_rows, nch, Q, X, part, m, chunk);
-    else
-        gram8_mfma_unit<T>(n, chunk_rows, nch, Q, X, part, m, chunk);
-}
-
+// Partial Gram matrices Q_m^T X, m < nm, P = 8, 16: one dimension of 8
+// ceil(nch / 8) ceil(nm / gram_blocks) workgroups, handed out XCD-major: the
+// workgroups of one row chunk run on one XCD, so that the chunk's X rows are
+// fetched once into its L2, and each loads them once for its blocks.
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_gram_rt(int64_t n, int64_t chunk_rows, int nch, int nm,
                                                  const T *__restrict__ Q0, int64_t qstride,
                                                  const T *__restrict__ X,
                                                  double *__restrict__ part) {
-    const int k = blockIdx.x / 8, m = k % nm, chunk = (k / nm) * 8 + blockIdx.x % 8;
+    constexpr int MB = gram_blocks<T>();
+    const int nmg = (nm + MB - 1) / MB;
+    const int k = blockIdx.x / 8, mg = k % nmg, chunk = (k / nmg) * 8 + blockIdx.x % 8;
     if (chunk >= nch) return;   // whole workgroup, before any barrier
-    gram_rt_unit<T, P>(n, chunk_rows, nch, Q0 + (int64_t)m * qstride, X, part, m, chunk);
+    const int m0 = mg * MB;
+    gram_mfma_unit<T, P>(n, chunk_rows, nch, Q0, qstride, m0, min(MB, nm - m0), X, part, chunk);
 }
 
 // out[m][e] = sum_c part[(m nch + c)][e]: one wavefront per output entry,
@@ -1037,7 +1033,9 @@ struct BandRun {
         break;
 #define GRT(PV)                                                                              \
     case PV:                                                                                 \
-        hipLaunchKernelGGL((k_gram_rt<T, PV>), dim3((unsigned)((nch + 7) / 8 * 8 * nm)),      \
+        hipLaunchKernelGGL((k_gram_rt<T, PV>),                                                 \
+                           dim3((unsigned)((nch + 7) / 8 * 8 *                               \
+                                           ((nm + gram_blocks<T>() - 1) / gram_blocks<T>()))), \
                            dim3(256), 0, s, n, chunk_rows, nch, nm, Q0, (int64_t)n * P, X,   \
                            part);                                                            \
         break;
@@ -1361,13 +1359,16 @@ __global__ __launch_bounds__(256) void k_mr_spmm(const MRun *__restrict__ R, int
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_mr_gram(const MRun *__restrict__ R, int nrun, int nm,
                                                  int qkind, int qslot, int xkind) {
+    constexpr int MB = gram_blocks<T>();
+    const int nmg = (nm + MB - 1) / MB;
     const int64_t u = blockIdx.x;
-    const MRun &r = R[mr_find(R, nrun, u / nm, 1)];
-    const int64_t v = u - r.chunk0 * nm;
-    const int k = (int)(v / 8), m = k % nm, chunk = (k / nm) * 8 + (int)(v % 8);
+    const MRun &r = R[mr_find(R, nrun, u / nmg, 1)];
+    const int64_t v = u - r.chunk0 * nmg;
+    const int k = (int)(v / 8), mg = k % nmg, chunk = (k / nmg) * 8 + (int)(v % 8);
     if (chunk >= r.nch) return;   // whole workgroup, before any barrier
-    gram_rt_unit<T, P>(r.n, r.chunk_rows, r.nch, mr_buf<T>(r, qkind, qslot, P) +
-                            (int64_t)m * r.n * P, mr_buf<T>(r, xkind, 0, P), r.part, m, chunk);
+    const int m0 = mg * MB;
+    gram_mfma_unit<T, P>(r.n, r.chunk_rows, r.nch, mr_buf<T>(r, qkind, qslot, P), r.n * P, m0,
+                         min(MB, nm - m0), mr_buf<T>(r, xkind, 0, P), r.part, chunk);
 }
 
 __global__ __launch_bounds__(256) void k_mr_gram_reduce(const MRun *__restrict__ R, int nrun,
@@ -1513,7 +1514,7 @@ struct MRTable {
         return MCD_OK;
     }
     int gram(int nm, int qkind, int qslot, int xkind) {
-        const unsigned g = (unsigned)(chunks * nm);
+        const unsigned g = (unsigned)(chunks * ((nm + gram_blocks<T>() - 1) / gram_blocks<T>()));
         if (P == 8)
             hipLaunchKernelGGL((k_mr_gram<T, 8>), dim3(g), dim3(256), 0, s, dev, nrun, nm, qkind,
                                qslot, xkind);
