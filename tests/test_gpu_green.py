@@ -77,6 +77,33 @@ def test_green_c1_chain_vs_oracle(sel):
     assert err0 <= 1e-7
 
 
+def test_green_p16_one_sector_vs_oracle():
+    """p = 16 in one spin sector -- the 16 up orbitals of a 16-site ring (U = 8,
+    mu = 4, half filling) on a 5,000-state chain basis -- against the
+    oracle's band Lanczos G on the same basis: float64 blocks with two
+    reorthogonalisation passes to 1e-9 of max |G|, float32 blocks with one
+    pass to 1e-4.  This reaches the P = 16 partial Gram matrices (matrix-core
+    form) of both block precisions on excited sectors whose row counts end
+    inside a row group."""
+    torch, mcd = require_gpu()
+    m = W.chain(16, t=1.0, U=8.0, mu=4.0, pbc=True)
+    keys, _ = sampler.chain_c(m, W.neel_start(m), 7, 5000, 1000, 10**8)
+    log_case("green_p16", n=len(keys))
+    e0, psi = _gs(m, keys)
+    orbs, spins = list(range(16)), [0] * 16
+    blocks = 8
+    Go = _oracle_G(keys, m, psi, e0, orbs, spins, blocks)
+    for prec, reorth, tol in (("f64", 2, 1e-9), ("f32", 1, 1e-4)):
+        G, info = mcd.band_lanczos_green(m, mcd.keys_from_numpy(keys),
+                                         torch.from_numpy(psi).cuda(), e0, orbs, spins, OM,
+                                         max_blocks=blocks, precision=prec, reorth=reorth)
+        err = _rel(G, Go)
+        print(f"[green p16] {prec} reorth={reorth} rel err {err:.2e} "
+              f"(n+ {info.n_plus}, n- {info.n_minus})", flush=True)
+        assert info.n_plus % 16 != 0 or info.n_minus % 16 != 0
+        assert err <= tol
+
+
 def test_green_exhausted_equals_dense_definition():
     """Small space run to exhaustion: G equals the dense Lehmann sum over the
     truncated H~+- (the definition, Eqs. green_plus / green_minus)."""
